@@ -1,0 +1,229 @@
+/*
+ * nlelast.h -- C ABI of the MI355X (gfx950) nonlinear-elasticity solver library.
+ *
+ * The library solves the quasi-static hyperelastic balance of the paper
+ * (Sec. 2, eq. "momentum strong" without inertia) on P1 tetrahedral meshes,
+ * matrix-free, with the nonlinear solvers of Sec. 3: Newton-Krylov (NK),
+ * inexact Newton-Krylov with Eisenstat-Walker forcing (iNK) and limited-memory
+ * BFGS with an initial inverse Hessian taken from the tangent at the first
+ * iterate (BFGS-preonly and inexact BFGS); solver options follow App. A.
+ *
+ * Conventions (all calls):
+ *  - Displacement-like vectors interleave components per node:
+ *    dof = 3 * node + component, length 3 * n_nodes.
+ *  - The residual is r(u) = f_int(u) - s * f_ext, the gradient of the
+ *    potential Pi(u) = sum_e V_e Psi(F_e) - s f_ext . u (Sec. 3, eq.
+ *    "minimization"); this is the paper's R = f - div P up to sign (same
+ *    root).  r is zero on Dirichlet dofs; the tangent J = dr/du has identity
+ *    rows and columns there (strong imposition; u holds the prescribed
+ *    values, increments vanish).
+ *  - Host pointers are borrowed for the duration of a call and never kept.
+ *    Device pointers are caller-owned (e.g. torch tensors on the context's
+ *    device) and must stay valid until the work queued on the context's
+ *    stream has finished.  The library never frees caller memory.
+ *  - Calls are asynchronous on the context's stream unless they return host
+ *    scalars (residual norm, solve report), which synchronise that stream.
+ *  - A context is bound to one device and one stream and is not thread-safe.
+ *  - Return values: 0 = NLE_OK; > 0 a solver outcome (the call ran, the
+ *    solve did not converge); < 0 a usage or system error, with a message
+ *    from nle_last_error().  No C++ exception crosses this interface.
+ *  - Results are deterministic: every sum (element scatter, dot product,
+ *    norm) is taken in a fixed order without floating-point atomics, so a
+ *    repeated call on the same inputs is bitwise identical.
+ */
+#ifndef NLELAST_H
+#define NLELAST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+typedef int32_t nle_status;
+#define NLE_OK 0
+#define NLE_DIVERGED_MAXIT 1    /* nonlinear iteration limit reached          */
+#define NLE_DIVERGED_NAN 2      /* residual norm became NaN or Inf            */
+#define NLE_DIVERGED_INVERTED 3 /* some element has det F <= 0               */
+#define NLE_DIVERGED_LINEAR 4   /* Krylov breakdown (e.g. CG p.Ap <= 0)       */
+#define NLE_BFGS_BREAKDOWN 5    /* L-BFGS direction unusable                  */
+#define NLE_E_INVAL (-1)        /* bad argument                               */
+#define NLE_E_BADMESH (-2)      /* index out of range / repeated / V_e <= 0   */
+#define NLE_E_STATE (-3)        /* call order violated (e.g. jv before linearize) */
+#define NLE_E_OOM (-4)          /* device allocation failed                  */
+#define NLE_E_HIP (-5)          /* HIP runtime error                          */
+#define NLE_E_UNSUPPORTED (-6)  /* option not implemented                     */
+
+/* ---- enumerations ---------------------------------------------------- */
+#define NLE_FP64 0 /* kernel arithmetic / vector storage in double */
+#define NLE_FP32 1 /* kernel arithmetic / vector storage in float  */
+
+/* Materials (Sec. 2, Sec. 4 "Cook test"); params in parentheses.
+ * M1 compressible neo-Hookean (mu, lambda):
+ *      Psi = mu/2 (I1 - 3) - mu ln J + lambda/2 (ln J)^2
+ * M2 the paper's Cook law with the isochoric / volumetric split
+ *    (mu, lambda, c_vol), kappa = lambda + 2 mu / 3:
+ *      Psi = mu/2 (J^(-2/3) I1 - 3) + c_vol kappa (J^2 - 1 - 2 ln J)
+ *    The printed law has c_vol = 1; c_vol = 1/4 gives bulk modulus kappa in
+ *    the small-strain limit.  n_params = 2 takes c_vol = 1/4. */
+#define NLE_MAT_M1 1
+#define NLE_MAT_M2 2
+
+#define NLE_NK 0   /* Newton-Krylov, fixed linear tolerance (App. A)        */
+#define NLE_INK 1  /* inexact NK, Eisenstat-Walker forcing (Sec. 3, App. A) */
+#define NLE_BFGS 2 /* limited-memory BFGS (Sec. 3, App. A)                  */
+
+#define NLE_KSP_GMRES 0 /* right-preconditioned GMRES(restart)             */
+#define NLE_KSP_CG 1    /* preconditioned conjugate gradients (SPD tangent) */
+
+#define NLE_ORTH_MGS 0  /* modified Gram-Schmidt (the paper's choice)       */
+#define NLE_ORTH_CGS2 1 /* classical Gram-Schmidt, two passes               */
+
+#define NLE_PC_NONE 0
+#define NLE_PC_JACOBI 1 /* point Jacobi: inverse of the tangent diagonal     */
+
+#define NLE_H0_PREONLY 0 /* BFGS-preonly: H0 = one preconditioner application */
+#define NLE_H0_KSP 1     /* inexact BFGS: H0 = Krylov solve on J(u0)          */
+
+#define NLE_PREC_FP64 0  /* every vector and kernel in double                */
+#define NLE_PREC_MIXED 1 /* FP32 tangent, preconditioner, Krylov and L-BFGS
+                            vectors; FP64 residual, norms, state and update */
+
+typedef struct nle_ctx nle_ctx;
+
+/* Optional device allocator (e.g. a framework's caching allocator).  alloc
+ * returns device memory on the context's device or NULL; free releases it.
+ * With a NULL allocator the library uses hipMalloc / hipFree. */
+typedef struct {
+  void *(*alloc)(size_t bytes, void *user);
+  void (*free)(void *ptr, void *user);
+  void *user;
+} nle_allocator;
+
+/* Solver options: the PETSc options of App. A as fields. */
+typedef struct {
+  int32_t precision;  /* NLE_PREC_FP64 / NLE_PREC_MIXED                      */
+  int32_t ksp_type;   /* NLE_KSP_GMRES / NLE_KSP_CG                           */
+  int32_t orth;       /* GMRES orthogonalisation                              */
+  int32_t pc;         /* NLE_PC_JACOBI / NLE_PC_NONE                          */
+  int32_t restart;    /* GMRES restart length; <= 0 means ksp_max_it          */
+  int32_t ksp_max_it; /* Krylov iteration limit per linear solve              */
+  int32_t snes_max_it;/* nonlinear iteration limit                            */
+  int32_t ew_version; /* Eisenstat-Walker variant 1 or 2                      */
+  int32_t qn_m;       /* L-BFGS memory (App. A uses 50)                       */
+  int32_t h0;         /* NLE_H0_PREONLY / NLE_H0_KSP                          */
+  int32_t check_every;/* Krylov iterations queued between host checks        */
+  int32_t reserved;
+  double ksp_rtol, ksp_atol;        /* NK: 1e-6, 1e-10                    */
+  double ew_rtol0, ew_rtolmax;      /* iNK: 0.1, 0.1                      */
+  double ew_rtolmin;                /* lower clip of eta (0: none)        */
+  double ew_gamma, ew_alpha, ew_alpha2, ew_threshold; /* 1, phi, phi, 0.1 */
+  double ink_ksp_atol;              /* iNK absolute tolerance: 1e-14      */
+  double snes_rtol, snes_atol;      /* ||r_k|| <= max(rtol ||r_0||, atol) */
+  double h0_rtol, h0_atol;          /* inexact BFGS H0 solve: 1e-2, 1e-14 */
+  double curvature_eps;             /* skip pair if s.y <= eps |s||y|     */
+} nle_solver_opts;
+
+/* Solve report.  Histories are written to caller buffers of hist_cap
+ * entries (any may be NULL); entry k belongs to nonlinear iteration k. */
+typedef struct {
+  int32_t status;       /* same code as the solve's return value            */
+  int32_t nit;          /* nonlinear iterations                             */
+  int64_t lit_total;    /* Krylov iterations, summed                        */
+  int64_t n_jv;         /* Jacobian actions                                 */
+  int64_t n_residual;   /* residual evaluations                             */
+  int32_t bfgs_skipped; /* L-BFGS pairs rejected by the curvature test      */
+  int32_t hist_cap;
+  double rnorm0;        /* ||r|| at the start of the step (after the lift)  */
+  double rnorm_final;
+  double t_ms;          /* wall time of the solve on the stream (HIP events) */
+  double *rnorm_hist;   /* [hist_cap] ||r_k||, k = 0..nit                   */
+  double *eta_hist;     /* [hist_cap] linear relative tolerance used        */
+  int32_t *lit_hist;    /* [hist_cap] Krylov iterations per step            */
+} nle_report;
+
+/* ---- context ---------------------------------------------------------- */
+/* Create a context on `device`, queueing work on `hip_stream` (a
+ * hipStream_t; NULL = the null stream).  `alloc` may be NULL. */
+nle_status nle_create(nle_ctx **out, int32_t device, void *hip_stream, const nle_allocator *alloc);
+/* Release every device buffer the library allocated.  NULL is a no-op. */
+void nle_destroy(nle_ctx *ctx);
+const char *nle_last_error(const nle_ctx *ctx);
+const char *nle_version(void);
+
+/* Elements per block of the element partition (fixed-order scatter unit);
+ * takes effect at the next nle_upload_mesh.  Range 64..4096, default 512. */
+nle_status nle_set_block_size(nle_ctx *ctx, int32_t elems_per_block);
+
+/* ---- problem data ----------------------------------------------------- */
+/* Upload a P1 tetrahedral mesh (Sec. 4 geometries; host arrays).
+ *   X    [n_nodes][3] reference coordinates (double).
+ *   conn [n_elems][4] node indices (int32), positively oriented:
+ *        det[X1-X0, X2-X0, X3-X0] > 0.
+ * Validates indices (0 <= i < n_nodes, no repeats within an element) and
+ * volumes; on failure returns NLE_E_BADMESH and names the first bad element.
+ * Precomputes shape-function gradients and volumes in FP64 (and an FP32
+ * copy) and the element partition.  Resets Dirichlet data, loads and the
+ * linearization.  n_nodes < 2^28. */
+nle_status nle_upload_mesh(nle_ctx *ctx, int64_t n_nodes, const double *X, int64_t n_elems,
+                           int32_t nodes_per_elem, const int32_t *conn);
+/* Material law and parameters (see NLE_MAT_*). */
+nle_status nle_set_material(nle_ctx *ctx, int32_t kind, const double *params, int32_t n_params);
+/* Dirichlet dofs and their prescribed displacement (host arrays of n
+ * entries; dofs unique, in [0, 3 n_nodes)).  Replaces previous data. */
+nle_status nle_set_dirichlet(nle_ctx *ctx, int64_t n, const int64_t *dofs, const double *values);
+/* Dead traction t (per unit reference area, 3 doubles) on n_faces
+ * triangles tri[n_faces][3]; consistent nodal load t A / 3 per vertex.
+ * Replaces the traction part of f_ext. */
+nle_status nle_set_traction(nle_ctx *ctx, int64_t n_faces, const int32_t *tri, const double *t);
+/* Uniform body force f (3 doubles, per unit reference volume): f V_e / 4 per
+ * vertex.  Replaces the body-force part of f_ext. */
+nle_status nle_set_body_force(nle_ctx *ctx, const double *f);
+/* Load factor s multiplying f_ext in the residual (default 1). */
+nle_status nle_set_load_scale(nle_ctx *ctx, double s);
+
+/* ---- kernels (device vectors of 3 n_nodes entries) ---------------------- */
+/* Write the prescribed Dirichlet values into u (double, device). */
+nle_status nle_lift(nle_ctx *ctx, double *u_dev);
+/* r = f_int(u) - s f_ext with r = 0 on Dirichlet dofs (double, device).
+ * If rnorm_host != NULL the stream is synchronised and ||r||_2 stored.
+ * Returns NLE_DIVERGED_INVERTED when some element has det F <= 0 (this
+ * check synchronises; it is made only when rnorm_host != NULL). */
+nle_status nle_residual(nle_ctx *ctx, const double *u_dev, double *r_dev, double *rnorm_host);
+/* Fix the linearization point u (double, device): the tangent used by
+ * nle_jv is J(u) until the next nle_linearize.  prec selects which copies
+ * (NLE_FP64 or NLE_FP32) are prepared; both are kept if called twice. */
+nle_status nle_linearize(nle_ctx *ctx, const double *u_dev, int32_t prec);
+/* y = J(u_lin) v (Sec. 3, eq. "newton" left-hand side), matrix-free, in
+ * precision prec (v and y are double* for NLE_FP64, float* for NLE_FP32).
+ * NLE_E_STATE without a linearization in that precision. */
+nle_status nle_jv(nle_ctx *ctx, const void *v_dev, void *y_dev, int32_t prec);
+/* Jacobi data of the current linearization: d = diag J (1 on Dirichlet
+ * dofs), double, device. */
+nle_status nle_diag(nle_ctx *ctx, double *d_dev);
+/* Potential Pi(u) = sum_e V_e Psi(F_e) - s f_ext . u (synchronises). */
+nle_status nle_energy(nle_ctx *ctx, const double *u_dev, double *pi_host);
+
+/* ---- solvers ------------------------------------------------------------- */
+/* Defaults of App. A for the method (NK, iNK or BFGS); ksp_type CG. */
+void nle_default_opts(int32_t method, nle_solver_opts *opts);
+/* Solve r(u) = 0 at the current load scale, starting from u (double,
+ * device, overwritten with the result; Dirichlet values are lifted first).
+ * Convergence: ||r_k||_2 <= max(snes_rtol ||r_0||_2, snes_atol) with r_0
+ * the residual after the lift.  `report` may be NULL. */
+nle_status nle_solve_nk(nle_ctx *ctx, double *u_dev, const nle_solver_opts *opts, nle_report *report);
+nle_status nle_solve_ink(nle_ctx *ctx, double *u_dev, const nle_solver_opts *opts, nle_report *report);
+nle_status nle_solve_bfgs(nle_ctx *ctx, double *u_dev, const nle_solver_opts *opts, nle_report *report);
+
+/* ---- mesh partition inspection (for tests and tuning) --------------------- */
+/* info[0..7] = n_blocks, max elems per block, max nodes per block,
+ * block-node slots, shared nodes, merge slots, LDS bytes (FP64 Jv),
+ * LDS bytes (FP32 Jv). */
+nle_status nle_partition_info(const nle_ctx *ctx, int64_t *info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NLELAST_H */

@@ -1,0 +1,433 @@
+// C-ABI entry points: context, problem data and single-operator calls.
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <new>
+
+#include "nle_internal.hpp"
+
+namespace nle {
+
+nle_status fail(Ctx *c, nle_status code, const std::string &msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+void *dalloc(Ctx *c, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (c->custom_alloc) return c->al.alloc(bytes, c->al.user);
+  void *p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void dfree(Ctx *c, void *p) {
+  if (!p) return;
+  if (c->custom_alloc)
+    c->al.free(p, c->al.user);
+  else
+    (void)hipFree(p);
+}
+
+namespace {
+
+nle_status need_mesh(Ctx *c) {
+  if (!c) return NLE_E_INVAL;
+  if (!c->has_mesh) return fail(c, NLE_E_STATE, "no mesh uploaded");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, NLE_E_HIP, "hipSetDevice failed");
+  return NLE_OK;
+}
+
+nle_status rebuild_fext(Ctx *c) {
+  const int64_t n = 3 * c->m.n_nodes;
+  std::vector<double> f(n);
+  for (int64_t i = 0; i < n; ++i) f[i] = c->h_ftrac[i] + c->h_fbody[i];
+  NLE_HIP(c, hipMemcpyAsync(c->fext, f.data(), n * 8, hipMemcpyHostToDevice, c->stream));
+  NLE_HIP(c, hipStreamSynchronize(c->stream));
+  return NLE_OK;
+}
+
+template <typename F>
+nle_status guarded(Ctx *c, F &&f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc &) {
+    return fail(c, NLE_E_OOM, "host allocation failed");
+  } catch (const std::exception &e) {
+    return fail(c, NLE_E_INVAL, e.what());
+  } catch (...) {
+    return fail(c, NLE_E_INVAL, "unknown error");
+  }
+}
+
+}  // namespace
+
+// ---- readback helper used by the solvers --------------------------------
+nle_status read_scalars(Ctx *c, const void *dev, size_t bytes) {
+  NLE_HIP(c, hipMemcpyAsync(c->hpin, dev, bytes, hipMemcpyDeviceToHost, c->stream));
+  NLE_HIP(c, hipStreamSynchronize(c->stream));
+  return NLE_OK;
+}
+
+// r = R(u), ||r|| -> *rn (synchronising); inverted -> *inv
+nle_status residual_norm(Ctx *c, const double *u, double *r, double *rn, bool *inv) {
+  NLE_HIP(c, hipMemsetAsync(c->dflag, 0, sizeof(int32_t), c->stream));
+  hipError_t e;
+  int np = elem_apply(c, OP_RES, NLE_FP64, u, nullptr, r, c->red, &e);
+  if (e != hipSuccess) return fail(c, NLE_E_HIP, std::string("residual: ") + hipGetErrorString(e));
+  NLE_HIP(c, reduce_scalar(c, c->red, np, c->dscal + 63));
+  NLE_HIP(c, hipMemcpyAsync(c->hpin, c->dscal + 63, 8, hipMemcpyDeviceToHost, c->stream));
+  NLE_HIP(c, hipMemcpyAsync(c->hpin + 1, c->dflag, 4, hipMemcpyDeviceToHost, c->stream));
+  NLE_HIP(c, hipStreamSynchronize(c->stream));
+  *rn = std::sqrt(c->hpin[0]);
+  int32_t f;
+  std::memcpy(&f, c->hpin + 1, 4);
+  *inv = f != 0;
+  return NLE_OK;
+}
+
+nle_status linearize(Ctx *c, const double *u, int prec) {
+  const int64_t n = 3 * c->m.n_nodes;
+  if (u != c->ulin64)
+    NLE_HIP(c, hipMemcpyAsync(c->ulin64, u, n * 8, hipMemcpyDeviceToDevice, c->stream));
+  hipError_t e;
+  elem_apply(c, OP_DIAG, NLE_FP64, c->ulin64, nullptr, c->diag64, nullptr, &e);
+  if (e != hipSuccess) return fail(c, NLE_E_HIP, std::string("diag: ") + hipGetErrorString(e));
+  NLE_HIP(c, vec_recip(c, c->diag64, c->dinv64, n));
+  c->lin64 = true;
+  c->lin32 = false;
+  if (prec == NLE_FP32) {
+    NLE_HIP(c, vec_cast_scale(c, NLE_FP64, c->ulin64, NLE_FP32, c->ulin32, 1.0, n));
+    NLE_HIP(c, vec_cast_scale(c, NLE_FP64, c->dinv64, NLE_FP32, c->dinv32, 1.0, n));
+    c->lin32 = true;
+  }
+  return NLE_OK;
+}
+
+nle_status jv(Ctx *c, const void *v, void *y, int prec) {
+  hipError_t e;
+  const void *ul = prec == NLE_FP32 ? static_cast<const void *>(c->ulin32)
+                                    : static_cast<const void *>(c->ulin64);
+  elem_apply(c, OP_JV, prec, ul, v, y, nullptr, &e);
+  if (e != hipSuccess) return fail(c, NLE_E_HIP, std::string("jv: ") + hipGetErrorString(e));
+  return NLE_OK;
+}
+
+}  // namespace nle
+
+using namespace nle;
+
+extern "C" {
+
+const char *nle_version(void) { return "nlelast 0.1.0 (gfx950)"; }
+
+const char *nle_last_error(const nle_ctx *ctx) {
+  if (!ctx) return "null context";
+  return reinterpret_cast<const Ctx *>(ctx)->err.c_str();
+}
+
+nle_status nle_create(nle_ctx **out, int32_t device, void *stream, const nle_allocator *alloc) {
+  if (!out) return NLE_E_INVAL;
+  *out = nullptr;
+  Ctx *c = new (std::nothrow) Ctx();
+  if (!c) return NLE_E_OOM;
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(stream);
+  if (alloc && alloc->alloc && alloc->free) {
+    c->al = *alloc;
+    c->custom_alloc = true;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    delete c;
+    return NLE_E_HIP;
+  }
+  if (hipSetDevice(device) != hipSuccess) {
+    delete c;
+    return NLE_E_HIP;
+  }
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess &&
+      lds > 0)
+    c->lds_limit = size_t(lds);
+  c->dscal = static_cast<double *>(dalloc(c, 64 * 8));
+  c->dflag = static_cast<int32_t *>(dalloc(c, 64 * 4));
+  if (!c->dscal || !c->dflag || hipHostMalloc(&c->hpin, 4096) != hipSuccess) {
+    dfree(c, c->dscal);
+    dfree(c, c->dflag);
+    delete c;
+    return NLE_E_OOM;
+  }
+  if (hipMemsetAsync(c->dflag, 0, 64 * 4, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    dfree(c, c->dscal);
+    dfree(c, c->dflag);
+    (void)hipHostFree(c->hpin);
+    delete c;
+    return NLE_E_HIP;
+  }
+  *out = reinterpret_cast<nle_ctx *>(c);
+  return NLE_OK;
+}
+
+void nle_destroy(nle_ctx *ctx) {
+  if (!ctx) return;
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  for (void *p : c->mesh_allocs) dfree(c, p);
+  for (void *p : c->ws_allocs) dfree(c, p);
+  dfree(c, c->red);
+  dfree(c, c->dscal);
+  dfree(c, c->dflag);
+  dfree(c, c->dir_dofs);
+  dfree(c, c->dir_vals);
+  if (c->hpin) (void)hipHostFree(c->hpin);
+  delete c;
+}
+
+nle_status nle_set_block_size(nle_ctx *ctx, int32_t be) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  if (!c) return NLE_E_INVAL;
+  if (be < 64 || be > 4096) return fail(c, NLE_E_INVAL, "block size must be in [64, 4096]");
+  c->be_req = be;
+  return NLE_OK;
+}
+
+nle_status nle_upload_mesh(nle_ctx *ctx, int64_t n_nodes, const double *X, int64_t n_elems,
+                           int32_t npe, const int32_t *conn) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  if (!c) return NLE_E_INVAL;
+  return guarded(c, [&]() -> nle_status {
+    if (npe != 4) return fail(c, NLE_E_UNSUPPORTED, "only 4-node (P1) tetrahedra are supported");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, NLE_E_HIP, "hipSetDevice failed");
+    c->has_mesh = false;
+    nle_status s = build_mesh(c, n_nodes, X, n_elems, conn);
+    if (s != NLE_OK) return s;
+    dfree(c, c->dir_dofs);
+    dfree(c, c->dir_vals);
+    c->dir_dofs = nullptr;
+    c->dir_vals = nullptr;
+    return upload_node_masks(c);
+  });
+}
+
+nle_status nle_set_material(nle_ctx *ctx, int32_t kind, const double *p, int32_t np) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  if (!c) return NLE_E_INVAL;
+  if (!p) return fail(c, NLE_E_INVAL, "null parameter array");
+  MatParams m{};
+  if (kind == NLE_MAT_M1) {
+    if (np != 2) return fail(c, NLE_E_INVAL, "M1 takes (mu, lambda)");
+    m.kind = kind;
+    m.mu = p[0];
+    m.lam = p[1];
+    m.cvol = 0.25;
+  } else if (kind == NLE_MAT_M2) {
+    if (np != 2 && np != 3) return fail(c, NLE_E_INVAL, "M2 takes (mu, lambda[, c_vol])");
+    m.kind = kind;
+    m.mu = p[0];
+    m.lam = p[1];
+    m.cvol = np == 3 ? p[2] : 0.25;
+  } else {
+    return fail(c, NLE_E_UNSUPPORTED, "unknown material kind");
+  }
+  if (!(m.mu > 0.0) || !std::isfinite(m.lam) || !std::isfinite(m.cvol))
+    return fail(c, NLE_E_INVAL, "material parameters must be finite with mu > 0");
+  m.kappa = m.lam + 2.0 * m.mu / 3.0;
+  c->mat = m;
+  c->has_mat = true;
+  c->lin64 = c->lin32 = false;
+  return NLE_OK;
+}
+
+nle_status nle_set_dirichlet(nle_ctx *ctx, int64_t n, const int64_t *dofs, const double *vals) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  nle_status s = need_mesh(c);
+  if (s != NLE_OK) return s;
+  return guarded(c, [&]() -> nle_status {
+    if (n < 0 || (n > 0 && (!dofs || !vals))) return fail(c, NLE_E_INVAL, "bad Dirichlet arrays");
+    const int64_t ndof = 3 * c->m.n_nodes;
+    std::vector<uint8_t> mask(c->m.n_nodes, 0);
+    for (int64_t k = 0; k < n; ++k) {
+      const int64_t d = dofs[k];
+      if (d < 0 || d >= ndof) return fail(c, NLE_E_INVAL, "Dirichlet dof out of range");
+      const uint8_t bit = uint8_t(1u << (d % 3));
+      if (mask[d / 3] & bit) return fail(c, NLE_E_INVAL, "repeated Dirichlet dof");
+      if (!std::isfinite(vals[k])) return fail(c, NLE_E_INVAL, "non-finite Dirichlet value");
+      mask[d / 3] |= bit;
+    }
+    dfree(c, c->dir_dofs);
+    dfree(c, c->dir_vals);
+    c->dir_dofs = nullptr;
+    c->dir_vals = nullptr;
+    c->n_dir = n;
+    if (n > 0) {
+      c->dir_dofs = static_cast<int64_t *>(dalloc(c, n * 8));
+      c->dir_vals = static_cast<double *>(dalloc(c, n * 8));
+      if (!c->dir_dofs || !c->dir_vals) return fail(c, NLE_E_OOM, "device allocation failed");
+      NLE_HIP(c, hipMemcpyAsync(c->dir_dofs, dofs, n * 8, hipMemcpyHostToDevice, c->stream));
+      NLE_HIP(c, hipMemcpyAsync(c->dir_vals, vals, n * 8, hipMemcpyHostToDevice, c->stream));
+    }
+    const bool changed = mask != c->h_mask;
+    c->h_mask = mask;
+    if (changed) {
+      c->lin64 = c->lin32 = false;
+      return upload_node_masks(c);
+    }
+    NLE_HIP(c, hipStreamSynchronize(c->stream));
+    return NLE_OK;
+  });
+}
+
+nle_status nle_set_traction(nle_ctx *ctx, int64_t nf, const int32_t *tri, const double *t) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  nle_status s = need_mesh(c);
+  if (s != NLE_OK) return s;
+  return guarded(c, [&]() -> nle_status {
+    if (nf < 0 || (nf > 0 && (!tri || !t))) return fail(c, NLE_E_INVAL, "bad traction arrays");
+    std::vector<double> f(3 * c->m.n_nodes, 0.0);
+    const double *X = c->m.h_X.data();
+    for (int64_t k = 0; k < nf; ++k) {
+      const int32_t *v = tri + 3 * k;
+      for (int a = 0; a < 3; ++a)
+        if (v[a] < 0 || v[a] >= c->m.n_nodes) return fail(c, NLE_E_INVAL, "face node out of range");
+      double e1[3], e2[3];
+      for (int i = 0; i < 3; ++i) {
+        e1[i] = X[3 * v[1] + i] - X[3 * v[0] + i];
+        e2[i] = X[3 * v[2] + i] - X[3 * v[0] + i];
+      }
+      const double cx = e1[1] * e2[2] - e1[2] * e2[1];
+      const double cy = e1[2] * e2[0] - e1[0] * e2[2];
+      const double cz = e1[0] * e2[1] - e1[1] * e2[0];
+      const double area = 0.5 * std::sqrt(cx * cx + cy * cy + cz * cz);
+      for (int a = 0; a < 3; ++a)
+        for (int i = 0; i < 3; ++i) f[3 * int64_t(v[a]) + i] += t[i] * area / 3.0;
+    }
+    c->h_ftrac = f;
+    return rebuild_fext(c);
+  });
+}
+
+nle_status nle_set_body_force(nle_ctx *ctx, const double *fb) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  nle_status s = need_mesh(c);
+  if (s != NLE_OK) return s;
+  if (!fb) return fail(c, NLE_E_INVAL, "null body force");
+  return guarded(c, [&]() -> nle_status {
+    std::vector<double> f(3 * c->m.n_nodes, 0.0);
+    for (int64_t e = 0; e < c->m.n_elems; ++e)
+      for (int a = 0; a < 4; ++a)
+        for (int i = 0; i < 3; ++i)
+          f[3 * int64_t(c->m.h_conn[4 * e + a]) + i] += fb[i] * c->m.h_V[e] / 4.0;
+    c->h_fbody = f;
+    return rebuild_fext(c);
+  });
+}
+
+nle_status nle_set_load_scale(nle_ctx *ctx, double s) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  if (!c) return NLE_E_INVAL;
+  if (!std::isfinite(s)) return fail(c, NLE_E_INVAL, "non-finite load scale");
+  c->load_scale = s;
+  return NLE_OK;
+}
+
+nle_status nle_lift(nle_ctx *ctx, double *u) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  nle_status s = need_mesh(c);
+  if (s != NLE_OK) return s;
+  if (!u) return fail(c, NLE_E_INVAL, "null vector");
+  NLE_HIP(c, vec_lift(c, u));
+  return NLE_OK;
+}
+
+nle_status nle_residual(nle_ctx *ctx, const double *u, double *r, double *rn) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  nle_status s = need_mesh(c);
+  if (s != NLE_OK) return s;
+  if (!c->has_mat) return fail(c, NLE_E_STATE, "no material set");
+  if (!u || !r) return fail(c, NLE_E_INVAL, "null vector");
+  if (rn) {
+    bool inv = false;
+    s = residual_norm(c, u, r, rn, &inv);
+    if (s != NLE_OK) return s;
+    return inv ? fail(c, NLE_DIVERGED_INVERTED, "element with det F <= 0") : NLE_OK;
+  }
+  hipError_t e;
+  elem_apply(c, OP_RES, NLE_FP64, u, nullptr, r, c->red, &e);
+  if (e != hipSuccess) return fail(c, NLE_E_HIP, std::string("residual: ") + hipGetErrorString(e));
+  return NLE_OK;
+}
+
+nle_status nle_linearize(nle_ctx *ctx, const double *u, int32_t prec) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  nle_status s = need_mesh(c);
+  if (s != NLE_OK) return s;
+  if (!c->has_mat) return fail(c, NLE_E_STATE, "no material set");
+  if (!u) return fail(c, NLE_E_INVAL, "null vector");
+  if (prec != NLE_FP64 && prec != NLE_FP32) return fail(c, NLE_E_INVAL, "bad precision");
+  return linearize(c, u, prec);
+}
+
+nle_status nle_jv(nle_ctx *ctx, const void *v, void *y, int32_t prec) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  nle_status s = need_mesh(c);
+  if (s != NLE_OK) return s;
+  if (!v || !y) return fail(c, NLE_E_INVAL, "null vector");
+  if (prec != NLE_FP64 && prec != NLE_FP32) return fail(c, NLE_E_INVAL, "bad precision");
+  if ((prec == NLE_FP64 && !c->lin64) || (prec == NLE_FP32 && !c->lin32))
+    return fail(c, NLE_E_STATE, "nle_jv needs nle_linearize in this precision first");
+  return jv(c, v, y, prec);
+}
+
+nle_status nle_diag(nle_ctx *ctx, double *d) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  nle_status s = need_mesh(c);
+  if (s != NLE_OK) return s;
+  if (!d) return fail(c, NLE_E_INVAL, "null vector");
+  if (!c->lin64) return fail(c, NLE_E_STATE, "nle_diag needs nle_linearize first");
+  NLE_HIP(c, hipMemcpyAsync(d, c->diag64, 3 * c->m.n_nodes * 8, hipMemcpyDeviceToDevice, c->stream));
+  return NLE_OK;
+}
+
+nle_status nle_energy(nle_ctx *ctx, const double *u, double *pi) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  nle_status s = need_mesh(c);
+  if (s != NLE_OK) return s;
+  if (!c->has_mat) return fail(c, NLE_E_STATE, "no material set");
+  if (!u || !pi) return fail(c, NLE_E_INVAL, "null argument");
+  hipError_t e;
+  const int np = elem_apply(c, OP_ENERGY, NLE_FP64, u, nullptr, nullptr, c->red, &e);
+  if (e != hipSuccess) return fail(c, NLE_E_HIP, std::string("energy: ") + hipGetErrorString(e));
+  NLE_HIP(c, reduce_scalar(c, c->red, np, c->dscal + 60));
+  double *red2 = c->red + np;
+  const int np2 = vec_dot_partials(c, NLE_FP64, c->fext, u, 3 * c->m.n_nodes, red2, &e);
+  if (e != hipSuccess) return fail(c, NLE_E_HIP, "energy dot");
+  NLE_HIP(c, reduce_scalar(c, red2, np2, c->dscal + 61));
+  s = read_scalars(c, c->dscal + 60, 16);
+  if (s != NLE_OK) return s;
+  *pi = c->hpin[0] - c->load_scale * c->hpin[1];
+  return NLE_OK;
+}
+
+nle_status nle_partition_info(const nle_ctx *ctx, int64_t *info) {
+  const Ctx *c = reinterpret_cast<const Ctx *>(ctx);
+  if (!c || !info) return NLE_E_INVAL;
+  if (!c->has_mesh) return NLE_E_STATE;
+  const Mesh &M = c->m;
+  info[0] = M.nblk;
+  info[1] = M.be_max;
+  info[2] = M.nl_max;
+  info[3] = M.n_slots;
+  info[4] = M.n_shared;
+  info[5] = M.n_fx;
+  info[6] = int64_t(6 * M.nl_max + 12 * M.be_max) * 8;
+  info[7] = int64_t(6 * M.nl_max + 12 * M.be_max) * 4;
+  return NLE_OK;
+}
+
+}  // extern "C"

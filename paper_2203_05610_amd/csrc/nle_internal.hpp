@@ -1,0 +1,201 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "nlelast.h"
+
+namespace nle {
+
+constexpr int NT = 256;            // threads per workgroup (four wave64)
+constexpr int VGRID_MAX = 1024;    // workgroups of the streaming vector kernels
+constexpr uint32_t NODE_MASK = 0x0FFFFFFFu;  // node id bits of a block-node word
+
+// Element kernel operations.
+enum ElemOp : int { OP_RES = 0, OP_JV = 1, OP_DIAG = 2, OP_ENERGY = 3 };
+
+struct MatParams {
+  int32_t kind;   // NLE_MAT_M1 / NLE_MAT_M2
+  double mu, lam, cvol, kappa;
+};
+
+// Element partition and geometry on the device.  Elements are renumbered
+// into blocks (contiguous ranges); every block owns a sorted list of the
+// nodes it touches ("slots"), a block-local connectivity, and a block-local
+// CSR listing, for each slot, the (element, vertex) contributions to sum.
+struct Mesh {
+  int64_t n_nodes = 0, n_elems = 0;
+  int32_t nblk = 0, be_max = 0, nl_max = 0;
+  int64_t n_slots = 0, n_shared = 0, n_fx = 0;
+  double *G64 = nullptr; float *G32 = nullptr;  // [9][n_elems] grad N_1..3 rows
+  double *V64 = nullptr; float *V32 = nullptr;  // [n_elems]
+  uint16_t *lconn = nullptr;                    // [4][n_elems] slot-local vertex ids
+  uint16_t *csr_idx = nullptr;                  // [4 n_elems] 4*elem_local + vertex
+  uint16_t *csr_end = nullptr;                  // [n_slots] end offset within block
+  uint32_t *nodes = nullptr;                    // [n_slots] id | mask<<28 | shared<<31
+  int32_t *blk_elem = nullptr, *blk_node = nullptr;  // [nblk+1]
+  uint32_t *fx_node = nullptr;                  // [n_shared] id | mask<<28
+  int32_t *fx_ptr = nullptr, *fx_slot = nullptr;     // merge CSR over slots
+  // host mirrors needed later
+  std::vector<uint32_t> h_nodes, h_fx_node;     // ids and shared bit, no mask
+  std::vector<int32_t> h_conn;                  // user connectivity (user order)
+  std::vector<double> h_V;                      // volumes (user order)
+  std::vector<double> h_X;
+};
+
+struct Ctx;
+
+// Device memory through the optional caller allocator.
+void *dalloc(Ctx *c, size_t bytes);
+void dfree(Ctx *c, void *p);
+
+struct Ctx {
+  int32_t device = 0;
+  hipStream_t stream = nullptr;
+  nle_allocator al{};
+  bool custom_alloc = false;
+  std::string err;
+  int32_t be_req = 512;
+  int32_t xcd_remap = 1;
+  size_t lds_limit = 65536;
+
+  Mesh m;
+  bool has_mesh = false;
+  std::vector<void *> mesh_allocs;  // freed on re-upload
+
+  MatParams mat{NLE_MAT_M1, 1.0, 1.0, 0.25, 1.0 + 2.0 / 3.0};
+  bool has_mat = false;
+
+  // Dirichlet data
+  int64_t n_dir = 0;
+  int64_t *dir_dofs = nullptr;
+  double *dir_vals = nullptr;
+  std::vector<uint8_t> h_mask;  // per node, bit i = component i prescribed
+
+  // loads
+  std::vector<double> h_ftrac, h_fbody;
+  double *fext = nullptr;
+  double load_scale = 1.0;
+
+  // linearization
+  bool lin64 = false, lin32 = false;
+  double *ulin64 = nullptr;
+  float *ulin32 = nullptr;
+  double *diag64 = nullptr;
+  double *dinv64 = nullptr;
+  float *dinv32 = nullptr;
+
+  // scratch
+  void *partial = nullptr;   // [n_slots][3] doubles (shared-slot partial sums)
+  double *red = nullptr;     // reduction partials, RED_CAP doubles
+  int64_t red_cap = 0;
+  double *dscal = nullptr;   // device scalars
+  int32_t *dflag = nullptr;  // device flags: [0] inverted element
+  const int32_t *elem_skip = nullptr;  // Krylov done flag seen by element kernels
+  double *hpin = nullptr;    // pinned host scalars
+  std::vector<void *> ctx_allocs;
+
+  // solver workspace (grown on demand)
+  std::vector<void *> ws_allocs;
+  size_t ws_bytes = 0;
+  void *ws = nullptr;
+};
+
+nle_status fail(Ctx *c, nle_status code, const std::string &msg);
+#define NLE_HIP(c, call)                                                        \
+  do {                                                                          \
+    hipError_t e_ = (call);                                                     \
+    if (e_ != hipSuccess)                                                       \
+      return ::nle::fail((c), NLE_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// mesh preparation (host)
+nle_status build_mesh(Ctx *c, int64_t n_nodes, const double *X, int64_t n_elems, const int32_t *conn);
+nle_status upload_node_masks(Ctx *c);
+
+// ---- element kernels (nle_elem.hip) ---------------------------------------
+// Launch the block and merge kernels of `op` in precision prec.
+//  OP_RES: u = double state, out = r, red gets per-workgroup sum r.r
+//  OP_JV : u = linearization state (prec), v = direction, out = J v
+//  OP_DIAG: u = ulin64, out = diag (double)
+//  OP_ENERGY: u = double state, red gets per-workgroup sum V Psi
+// Returns the number of reduction partials written to red (0 if none).
+int elem_apply(Ctx *c, int op, int prec, const void *u, const void *v, void *out, double *red,
+               hipError_t *err);
+int elem_red_capacity(const Ctx *c);
+
+// ---- vector kernels (nle_vec.hip) ------------------------------------------
+int vgrid(int64_t n);
+hipError_t vec_fill(Ctx *c, int prec, void *x, double val, int64_t n);
+hipError_t vec_cast_scale(Ctx *c, int px, const void *x, int py, void *y, double scale, int64_t n);
+// y = y + a * x   (x in precision px, y in precision py); a taken from a
+// device scalar *a_dev times a_host (a_dev may be null).
+hipError_t vec_axpy(Ctx *c, int px, const void *x, int py, void *y, double a_host,
+                    const double *a_dev, int64_t n);
+hipError_t vec_lift(Ctx *c, double *u);
+// partials of sum_i a_i b_i (and sum b_i^2 if sq != 0) -> red; returns count
+int vec_dot_partials(Ctx *c, int prec, const void *a, const void *b, int64_t n, double *red,
+                     hipError_t *err);
+// single-workgroup fixed-order sum of red[0..np) (stride 1) -> out[0]
+hipError_t reduce_scalar(Ctx *c, const double *red, int np, double *out);
+hipError_t reduce_scalars(Ctx *c, const double *red, int np, int count, double *out);
+hipError_t vec_mul(Ctx *c, int prec, const void *a, const void *b, void *y, int64_t n);
+hipError_t vec_recip(Ctx *c, const double *d, double *dinv, int64_t n);
+
+// CG kernels
+struct CgArgs {
+  int prec;
+  int64_t n;
+  void *x, *r, *z, *p, *Ap;
+  const void *dinv;   // may be null (no preconditioner)
+  double *red_a;      // partials of p.Ap
+  int np_a;
+  double *red_b;      // partials of (r.z, r.r), 2 x VGRID_MAX
+  double *scal;       // device scalars
+  int32_t *flag;      // [0] done (1 conv, 2 breakdown), [1] iterations
+};
+hipError_t cg_start(Ctx *c, const CgArgs &a, const void *b, double rtol, double atol);
+hipError_t cg_update(Ctx *c, const CgArgs &a, int it);
+hipError_t cg_direction(Ctx *c, const CgArgs &a, int it);
+
+// GMRES kernels
+struct GmresArgs {
+  int prec;
+  int64_t n;
+  int m;             // basis capacity (restart)
+  void *V;           // [m+1][n]
+  void *w;           // [n] work
+  void *z;           // [n] work (preconditioned)
+  void *x;           // [n] solution
+  const void *dinv;  // may be null
+  double *red;       // partials [(m+2) x VGRID_MAX]
+  double *H;         // device Hessenberg [(m+1) x m] column-major, + rotations
+  double *scal;
+  int32_t *flag;
+};
+hipError_t gmres_multidot(Ctx *c, const GmresArgs &a, int j);           // h_i = V_i . w, i<=j
+hipError_t gmres_subtract(Ctx *c, const GmresArgs &a, int j, int pass, int want_dots);
+hipError_t gmres_mgs_step(Ctx *c, const GmresArgs &a, int i, int j);    // fused MGS step
+hipError_t gmres_finish_col(Ctx *c, const GmresArgs &a, int j, int mgs);// norm, Givens, test
+hipError_t gmres_update_x(Ctx *c, const GmresArgs &a);                  // x += M^-1 V y
+hipError_t gmres_start(Ctx *c, const GmresArgs &a, const void *r0, double rtol, double atol,
+                       int first);
+
+// L-BFGS two-loop kernels
+hipError_t lbfgs_dot(Ctx *c, int prec, const void *s, const void *q, int64_t n, double *red,
+                     int *np);
+// q -= alpha * y with alpha = rho * sum(red) (stored to alpha_out[0]);
+// optionally accumulates partials of s_next . q_new into red_next
+hipError_t lbfgs_axpy_dot(Ctx *c, int prec, void *q, const void *y, const double *red, int np,
+                          double rho, double *alpha_out, const void *s_next, double *red_next,
+                          int64_t n);
+// z += (alpha - rho * sum(red)) * s ; optionally partials of y_next . z_new
+hipError_t lbfgs_axpy2_dot(Ctx *c, int prec, void *z, const void *s, const double *red, int np,
+                           double rho, const double *alpha, const void *y_next, double *red_next,
+                           int64_t n);
+
+}  // namespace nle

@@ -1,0 +1,653 @@
+// Nonlinear and Krylov solver control (host side; every vector operation runs
+// in the library's kernels, scalars stay on the device between host checks).
+//
+// Paper, Sec. 3 and App. A:
+//  NK   : Newton with a Krylov solve of J du = -r to rtol 1e-6 / atol 1e-10,
+//         full step (line search "basic").
+//  iNK  : the same with the Eisenstat-Walker relative tolerance
+//         (eta_0 = 0.1, eta_max = 0.1) and atol 1e-14.
+//  BFGS : limited-memory inverse update (two-loop recursion); H0 from the
+//         tangent at the first iterate of the step, as one preconditioner
+//         application (BFGS-preonly) or a Krylov solve with rtol 1e-2
+//         (inexact BFGS); no scalar scaling of H0; full step.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <deque>
+
+#include "nle_internal.hpp"
+
+namespace nle {
+
+nle_status read_scalars(Ctx *c, const void *dev, size_t bytes);
+nle_status residual_norm(Ctx *c, const double *u, double *r, double *rn, bool *inv);
+nle_status linearize(Ctx *c, const double *u, int prec);
+nle_status jv(Ctx *c, const void *v, void *y, int prec);
+
+namespace {
+
+constexpr double GOLDEN = 1.6180339887498949;
+
+// Workspace: one device allocation grown on demand, carved sequentially.
+struct Carver {
+  char *base;
+  size_t off = 0;
+  void *take(size_t bytes) {
+    void *p = base + off;
+    off += (bytes + 255) & ~size_t(255);
+    return p;
+  }
+};
+
+nle_status ensure_ws(Ctx *c, size_t bytes) {
+  if (c->ws_bytes >= bytes) return NLE_OK;
+  NLE_HIP(c, hipStreamSynchronize(c->stream));
+  for (void *p : c->ws_allocs) dfree(c, p);
+  c->ws_allocs.clear();
+  c->ws = dalloc(c, bytes);
+  if (!c->ws) {
+    c->ws_bytes = 0;
+    return fail(c, NLE_E_OOM, "solver workspace allocation failed");
+  }
+  c->ws_allocs.push_back(c->ws);
+  c->ws_bytes = bytes;
+  return NLE_OK;
+}
+
+struct KspOpts {
+  int type, orth, pc, restart, max_it, check_every;
+  double rtol, atol;
+};
+
+struct KspResult {
+  int its = 0;
+  int flag = 0;  // 1 converged, 0 max_it, 2 indefinite, 3 NaN
+};
+
+inline size_t esz(int prec) { return prec == NLE_FP32 ? 4 : 8; }
+
+size_t ksp_bytes(const KspOpts &o, int64_t n, int prec) {
+  const size_t v = (size_t(n) * esz(prec) + 255) & ~size_t(255);
+  if (o.type == NLE_KSP_CG) return 4 * v + 4096;
+  const int m = o.restart > 0 ? std::min(o.restart, o.max_it) : o.max_it;
+  return size_t(m + 3) * v + size_t((m + 1) * m + 4 * m + 8) * 8 +
+         size_t(m + 3) * VGRID_MAX * 8 + size_t(8 + 2 * (m + 1)) * 8 + 8 * 256;
+}
+
+// Solve J x = b (J = tangent at the current linearization, precision prec)
+// from x = 0.  Converged when ||b - J x|| <= max(rtol ||b||, atol).
+nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x, Carver &W,
+                     KspResult *R, int64_t *n_jv) {
+  const int64_t n = 3 * c->m.n_nodes;
+  const size_t vb = size_t(n) * esz(prec);
+  const void *dinv = nullptr;
+  if (o.pc == NLE_PC_JACOBI)
+    dinv = prec == NLE_FP32 ? static_cast<const void *>(c->dinv32)
+                            : static_cast<const void *>(c->dinv64);
+  int32_t *flag = c->dflag + 8;
+  const int check = std::max(1, o.check_every);
+  R->its = 0;
+  R->flag = 0;
+  if (o.type == NLE_KSP_CG) {
+    CgArgs a;
+    a.prec = prec;
+    a.n = n;
+    a.x = x;
+    a.r = W.take(vb);
+    a.z = W.take(vb);
+    a.p = W.take(vb);
+    a.Ap = W.take(vb);
+    a.dinv = dinv;
+    a.red_a = c->red;
+    a.red_b = c->red + VGRID_MAX;
+    a.scal = c->dscal;
+    a.flag = flag;
+    a.np_a = vgrid(n);
+    NLE_HIP(c, cg_start(c, a, b, o.rtol, o.atol));
+    c->elem_skip = flag;
+    int it = 0;
+    for (; it < o.max_it; ++it) {
+      hipError_t e;
+      elem_apply(c, OP_JV, prec, prec == NLE_FP32 ? (const void *)c->ulin32 : (const void *)c->ulin64,
+                 a.p, a.Ap, nullptr, &e);
+      if (e == hipSuccess) vec_dot_partials(c, prec, a.p, a.Ap, n, a.red_a, &e);
+      if (e == hipSuccess) e = cg_update(c, a, it);
+      if (e == hipSuccess) e = cg_direction(c, a, it);
+      if (e != hipSuccess) {
+        c->elem_skip = nullptr;
+        return fail(c, NLE_E_HIP, std::string("cg: ") + hipGetErrorString(e));
+      }
+      if ((it + 1) % check == 0 || it + 1 == o.max_it) {
+        nle_status s = read_scalars(c, flag, 8);
+        if (s != NLE_OK) {
+          c->elem_skip = nullptr;
+          return s;
+        }
+        int32_t f[2];
+        std::memcpy(f, c->hpin, 8);
+        if (f[0] != 0) break;
+      }
+    }
+    c->elem_skip = nullptr;
+    nle_status s = read_scalars(c, flag, 8);
+    if (s != NLE_OK) return s;
+    int32_t f[2];
+    std::memcpy(f, c->hpin, 8);
+    R->its = f[1];
+    R->flag = f[0];
+    *n_jv += f[1] + (f[0] == 2 ? 1 : 0);
+    return NLE_OK;
+  }
+  // ---- GMRES (right preconditioned) -----------------------------------------
+  const int m = o.restart > 0 ? std::min(o.restart, o.max_it) : o.max_it;
+  GmresArgs a;
+  a.prec = prec;
+  a.n = n;
+  a.m = m;
+  a.V = W.take(size_t(m + 1) * vb);
+  a.w = W.take(vb);
+  a.z = W.take(vb);
+  a.x = x;
+  a.dinv = dinv;
+  a.H = static_cast<double *>(W.take(size_t((m + 1) * m + 4 * m + 8) * 8));
+  a.red = static_cast<double *>(W.take(size_t(m + 3) * VGRID_MAX * 8));
+  a.scal = static_cast<double *>(W.take(size_t(8 + 2 * (m + 1)) * 8));
+  a.flag = flag;
+  const int mgs = o.orth == NLE_ORTH_MGS;
+  NLE_HIP(c, vec_fill(c, prec, x, 0.0, n));
+  NLE_HIP(c, gmres_start(c, a, b, o.rtol, o.atol, 1));
+  int total = 0;
+  int32_t f[2] = {0, 0};
+  c->elem_skip = flag;
+  while (true) {
+    int queued = 0;
+    for (int j = 0; j < m && total + queued < o.max_it; ++j) {
+      const void *vj = static_cast<const char *>(a.V) + size_t(j) * vb;
+      hipError_t e = hipSuccess;
+      if (dinv)
+        e = vec_mul(c, prec, dinv, vj, a.z, n);
+      else
+        e = hipMemcpyAsync(a.z, vj, vb, hipMemcpyDeviceToDevice, c->stream);
+      if (e == hipSuccess)
+        elem_apply(c, OP_JV, prec,
+                   prec == NLE_FP32 ? (const void *)c->ulin32 : (const void *)c->ulin64, a.z, a.w,
+                   nullptr, &e);
+      if (e == hipSuccess) {
+        if (mgs) {
+          for (int i = 0; i <= j && e == hipSuccess; ++i) e = gmres_mgs_step(c, a, i, j);
+        } else {
+          e = gmres_multidot(c, a, j);
+          if (e == hipSuccess) e = gmres_subtract(c, a, j, 0, 0);
+          if (e == hipSuccess) e = gmres_multidot(c, a, j);
+          if (e == hipSuccess) e = gmres_subtract(c, a, j, 1, 1);
+        }
+      }
+      if (e == hipSuccess) e = gmres_finish_col(c, a, j, mgs);
+      if (e != hipSuccess) {
+        c->elem_skip = nullptr;
+        return fail(c, NLE_E_HIP, std::string("gmres: ") + hipGetErrorString(e));
+      }
+      ++queued;
+      if (queued % check == 0) {
+        nle_status s = read_scalars(c, flag, 8);
+        if (s != NLE_OK) {
+          c->elem_skip = nullptr;
+          return s;
+        }
+        std::memcpy(f, c->hpin, 8);
+        if (f[0] != 0) break;
+      }
+    }
+    c->elem_skip = nullptr;
+    NLE_HIP(c, gmres_update_x(c, a));
+    nle_status s = read_scalars(c, flag, 8);
+    if (s != NLE_OK) return s;
+    std::memcpy(f, c->hpin, 8);
+    total += f[1];
+    *n_jv += f[1];
+    if (f[0] == 1 || f[0] == 3 || total >= o.max_it || f[1] == 0) break;
+    // restart: r = b - J x
+    NLE_HIP(c, hipMemcpyAsync(a.w, b, vb, hipMemcpyDeviceToDevice, c->stream));
+    s = jv(c, x, a.z, prec);
+    if (s != NLE_OK) return s;
+    *n_jv += 1;
+    NLE_HIP(c, vec_axpy(c, prec, a.z, prec, a.w, -1.0, nullptr, n));
+    NLE_HIP(c, gmres_start(c, a, a.w, o.rtol, o.atol, 0));
+    c->elem_skip = flag;
+  }
+  R->its = total;
+  R->flag = (f[0] == 1) ? 1 : (f[0] == 3 ? 3 : 0);
+  return NLE_OK;
+}
+
+double ew_eta(const nle_solver_opts &o, int k, double rn, double rn_prev, double linres_prev,
+              double eta_prev) {
+  if (k == 0) return std::min(o.ew_rtol0, o.ew_rtolmax);
+  double eta, stol;
+  if (o.ew_version == 2) {
+    eta = o.ew_gamma * std::pow(rn / rn_prev, o.ew_alpha);
+    stol = o.ew_gamma * std::pow(eta_prev, o.ew_alpha);
+  } else {
+    eta = std::fabs(rn - linres_prev) / rn_prev;
+    stol = std::pow(eta_prev, o.ew_alpha2);
+  }
+  if (stol > o.ew_threshold) eta = std::max(eta, stol);
+  eta = std::min(eta, o.ew_rtolmax);
+  return std::max(eta, o.ew_rtolmin);
+}
+
+struct Timer {
+  hipEvent_t a = nullptr, b = nullptr;
+  Ctx *c;
+  explicit Timer(Ctx *cc) : c(cc) {
+    if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+      (void)hipEventRecord(a, c->stream);
+  }
+  double stop() {
+    float ms = 0.f;
+    if (a && b && hipEventRecord(b, c->stream) == hipSuccess &&
+        hipEventSynchronize(b) == hipSuccess)
+      (void)hipEventElapsedTime(&ms, a, b);
+    return double(ms);
+  }
+  ~Timer() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+struct Report {
+  nle_report *r;
+  explicit Report(nle_report *rr) : r(rr) {
+    if (r) {
+      r->status = 0;
+      r->nit = 0;
+      r->lit_total = 0;
+      r->n_jv = 0;
+      r->n_residual = 0;
+      r->bfgs_skipped = 0;
+      r->rnorm0 = 0;
+      r->rnorm_final = 0;
+      r->t_ms = 0;
+    }
+  }
+  void hist(int k, double rn, double eta, int lit) {
+    if (!r || k < 0 || k >= r->hist_cap) return;
+    if (r->rnorm_hist) r->rnorm_hist[k] = rn;
+    if (r->eta_hist) r->eta_hist[k] = eta;
+    if (r->lit_hist) r->lit_hist[k] = lit;
+  }
+};
+
+nle_status check_ready(Ctx *c, double *u, const nle_solver_opts *o) {
+  if (!c) return NLE_E_INVAL;
+  if (!c->has_mesh) return fail(c, NLE_E_STATE, "no mesh uploaded");
+  if (!c->has_mat) return fail(c, NLE_E_STATE, "no material set");
+  if (!u || !o) return fail(c, NLE_E_INVAL, "null argument");
+  if (o->precision != NLE_PREC_FP64 && o->precision != NLE_PREC_MIXED)
+    return fail(c, NLE_E_INVAL, "bad precision");
+  if (o->ksp_type != NLE_KSP_CG && o->ksp_type != NLE_KSP_GMRES)
+    return fail(c, NLE_E_INVAL, "bad ksp_type");
+  if (o->pc != NLE_PC_JACOBI && o->pc != NLE_PC_NONE) return fail(c, NLE_E_INVAL, "bad pc");
+  if (o->ksp_max_it < 1 || o->snes_max_it < 0) return fail(c, NLE_E_INVAL, "bad iteration limits");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, NLE_E_HIP, "hipSetDevice failed");
+  return NLE_OK;
+}
+
+nle_status finish(Ctx *c, Report &rep, nle_status st, int nit, double rn0, double rn, Timer &t) {
+  const double ms = t.stop();
+  if (rep.r) {
+    rep.r->status = st;
+    rep.r->nit = nit;
+    rep.r->rnorm0 = rn0;
+    rep.r->rnorm_final = rn;
+    rep.r->t_ms = ms;
+  }
+  if (st > 0 && c->err.empty()) c->err = "solver did not converge";
+  return st;
+}
+
+nle_status newton(Ctx *c, double *u, const nle_solver_opts &o, nle_report *report, bool inexact) {
+  Timer timer(c);
+  Report rep(report);
+  c->err.clear();
+  const int prec = o.precision == NLE_PREC_MIXED ? NLE_FP32 : NLE_FP64;
+  const int64_t n = 3 * c->m.n_nodes;
+  KspOpts ko{o.ksp_type, o.orth, o.pc, o.restart, o.ksp_max_it, std::max(1, o.check_every),
+             o.ksp_rtol, o.ksp_atol};
+  const size_t vb64 = (size_t(n) * 8 + 255) & ~size_t(255);
+  const size_t vbp = (size_t(n) * esz(prec) + 255) & ~size_t(255);
+  nle_status s = ensure_ws(c, vb64 + 3 * vbp + ksp_bytes(ko, n, prec));
+  if (s != NLE_OK) return s;
+  Carver W{static_cast<char *>(c->ws)};
+  double *r = static_cast<double *>(W.take(vb64));
+  void *b = W.take(vbp);
+  void *dx = W.take(vbp);
+  void *tmp = W.take(vbp);
+  const size_t ksp_off = W.off;
+  int64_t n_jv = 0, n_res = 0, lit_total = 0;
+
+  NLE_HIP(c, vec_lift(c, u));
+  double rn = 0.0;
+  bool inv = false;
+  s = residual_norm(c, u, r, &rn, &inv);
+  if (s != NLE_OK) return s;
+  ++n_res;
+  const double rn0 = rn;
+  const double tol = std::max(o.snes_rtol * rn0, o.snes_atol);
+  double rn_prev = 0.0, linres_prev = 0.0, eta_prev = 0.0;
+  int k = 0;
+  nle_status st = NLE_DIVERGED_MAXIT;
+  auto fill_rep = [&]() {
+    if (report) {
+      report->lit_total = lit_total;
+      report->n_jv = n_jv;
+      report->n_residual = n_res;
+    }
+  };
+  for (;; ++k) {
+    if (inv) {
+      st = fail(c, NLE_DIVERGED_INVERTED, "element with det F <= 0");
+      break;
+    }
+    if (!std::isfinite(rn)) {
+      st = fail(c, NLE_DIVERGED_NAN, "residual norm is not finite");
+      break;
+    }
+    if (rn <= tol) {
+      st = NLE_OK;
+      rep.hist(k, rn, 0.0, 0);
+      break;
+    }
+    if (k >= o.snes_max_it) {
+      rep.hist(k, rn, 0.0, 0);
+      break;
+    }
+    s = linearize(c, u, prec);
+    if (s != NLE_OK) return s;
+    double eta = o.ksp_rtol, atol = o.ksp_atol;
+    if (inexact) {
+      eta = ew_eta(o, k, rn, rn_prev, linres_prev, eta_prev);
+      atol = o.ink_ksp_atol;
+    }
+    // b = -r / ||r||: the solve is scaled to a unit right-hand side
+    NLE_HIP(c, vec_cast_scale(c, NLE_FP64, r, prec, b, -1.0 / rn, n));
+    KspOpts kk = ko;
+    kk.rtol = eta;
+    kk.atol = atol / rn;
+    KspResult kr;
+    W.off = ksp_off;
+    s = ksp_solve(c, kk, prec, b, dx, W, &kr, &n_jv);
+    if (s != NLE_OK) return s;
+    lit_total += kr.its;
+    rep.hist(k, rn, eta, kr.its);
+    if (kr.flag == 3) {
+      st = fail(c, NLE_DIVERGED_LINEAR, "Krylov solve produced NaN");
+      break;
+    }
+    if (inexact) {  // ||r + J du|| = ||r|| ||J dx - b||, recomputed explicitly
+      s = jv(c, dx, tmp, prec);
+      if (s != NLE_OK) return s;
+      ++n_jv;
+      NLE_HIP(c, vec_axpy(c, prec, b, prec, tmp, -1.0, nullptr, n));
+      hipError_t e;
+      const int np = vec_dot_partials(c, prec, tmp, tmp, n, c->red, &e);
+      if (e != hipSuccess) return fail(c, NLE_E_HIP, "linear residual");
+      NLE_HIP(c, reduce_scalar(c, c->red, np, c->dscal + 62));
+      s = read_scalars(c, c->dscal + 62, 8);
+      if (s != NLE_OK) return s;
+      linres_prev = rn * std::sqrt(c->hpin[0]);
+      eta_prev = eta;
+    }
+    NLE_HIP(c, vec_axpy(c, prec, dx, NLE_FP64, u, rn, nullptr, n));
+    rn_prev = rn;
+    s = residual_norm(c, u, r, &rn, &inv);
+    if (s != NLE_OK) return s;
+    ++n_res;
+  }
+  fill_rep();
+  return finish(c, rep, st, k, rn0, rn, timer);
+}
+
+nle_status bfgs(Ctx *c, double *u, const nle_solver_opts &o, nle_report *report) {
+  Timer timer(c);
+  Report rep(report);
+  c->err.clear();
+  const int prec = o.precision == NLE_PREC_MIXED ? NLE_FP32 : NLE_FP64;
+  const int64_t n = 3 * c->m.n_nodes;
+  const int m = std::max(1, o.qn_m);
+  KspOpts ko{o.ksp_type, o.orth, o.pc, o.restart, o.ksp_max_it, std::max(1, o.check_every),
+             o.h0_rtol, o.h0_atol};
+  const size_t vb64 = (size_t(n) * 8 + 255) & ~size_t(255);
+  const size_t vbp = (size_t(n) * esz(prec) + 255) & ~size_t(255);
+  size_t need = 3 * vb64 + size_t(2 * m + 5) * vbp + 8 * size_t(m + 8) + 4096;
+  if (o.h0 == NLE_H0_KSP) need += ksp_bytes(ko, n, prec);
+  nle_status s = ensure_ws(c, need);
+  if (s != NLE_OK) return s;
+  Carver W{static_cast<char *>(c->ws)};
+  double *g = static_cast<double *>(W.take(vb64));
+  double *gn = static_cast<double *>(W.take(vb64));
+  double *y64 = static_cast<double *>(W.take(vb64));
+  void *q = W.take(vbp);
+  void *z = W.take(vbp);
+  void *b = W.take(vbp);
+  // m + 1 slots: the candidate pair of an iteration always has a free slot
+  std::vector<void *> S(m + 1), Y(m + 1);
+  for (int i = 0; i <= m; ++i) {
+    S[i] = W.take(vbp);
+    Y[i] = W.take(vbp);
+  }
+  double *alpha = static_cast<double *>(W.take(8 * size_t(m + 8)));
+  const size_t ksp_off = W.off;
+  int64_t n_jv = 0, n_res = 0, lit_total = 0;
+  int skipped = 0;
+  std::vector<double> rho(m + 1, 0.0);
+  std::deque<int> pairs;      // slot ids of stored pairs, oldest first
+  std::vector<int> free_slots;
+  for (int i = m; i >= 0; --i) free_slots.push_back(i);
+
+  NLE_HIP(c, vec_lift(c, u));
+  double rn = 0.0;
+  bool inv = false;
+  s = residual_norm(c, u, g, &rn, &inv);
+  if (s != NLE_OK) return s;
+  ++n_res;
+  const double rn0 = rn;
+  const double tol = std::max(o.snes_rtol * rn0, o.snes_atol);
+  if (rn > tol && std::isfinite(rn) && !inv) {
+    s = linearize(c, u, prec);  // the single linearization of the step
+    if (s != NLE_OK) return s;
+  }
+  const void *dinv = prec == NLE_FP32 ? static_cast<const void *>(c->dinv32)
+                                      : static_cast<const void *>(c->dinv64);
+  double *redA = c->red, *redB = c->red + VGRID_MAX;
+  int k = 0;
+  nle_status st = NLE_DIVERGED_MAXIT;
+  for (;; ++k) {
+    if (inv) {
+      st = fail(c, NLE_DIVERGED_INVERTED, "element with det F <= 0");
+      break;
+    }
+    if (!std::isfinite(rn)) {
+      st = fail(c, NLE_DIVERGED_NAN, "residual norm is not finite");
+      break;
+    }
+    if (rn <= tol) {
+      st = NLE_OK;
+      rep.hist(k, rn, 0.0, 0);
+      break;
+    }
+    if (k >= o.snes_max_it) {
+      rep.hist(k, rn, 0.0, 0);
+      break;
+    }
+    // q = g / ||g||
+    NLE_HIP(c, vec_cast_scale(c, NLE_FP64, g, prec, q, 1.0 / rn, n));
+    const int np_pairs = int(pairs.size());
+    // first loop, newest to oldest: alpha_i = rho_i s_i.q ; q -= alpha_i y_i
+    int np = 0;
+    if (np_pairs > 0) NLE_HIP(c, lbfgs_dot(c, prec, S[pairs.back()], q, n, redA, &np));
+    for (int t = np_pairs - 1; t >= 0; --t) {
+      const int i = pairs[t];
+      const void *snext = t > 0 ? S[pairs[t - 1]] : nullptr;
+      NLE_HIP(c, lbfgs_axpy_dot(c, prec, q, Y[i], redA, np, rho[i], alpha + i, snext,
+                                snext ? redB : nullptr, n));
+      std::swap(redA, redB);
+    }
+    // z = H0 q
+    int lit = 0;
+    if (o.h0 == NLE_H0_KSP) {
+      KspResult kr;
+      W.off = ksp_off;
+      s = ksp_solve(c, ko, prec, q, z, W, &kr, &n_jv);
+      if (s != NLE_OK) return s;
+      lit = kr.its;
+      lit_total += kr.its;
+      if (kr.flag == 3) {
+        st = fail(c, NLE_DIVERGED_LINEAR, "H0 Krylov solve produced NaN");
+        break;
+      }
+    } else if (o.pc == NLE_PC_JACOBI) {
+      NLE_HIP(c, vec_mul(c, prec, dinv, q, z, n));
+    } else {
+      NLE_HIP(c, hipMemcpyAsync(z, q, size_t(n) * esz(prec), hipMemcpyDeviceToDevice, c->stream));
+    }
+    // second loop, oldest to newest: beta = rho_i y_i.z ; z += (alpha_i - beta) s_i
+    if (np_pairs > 0) NLE_HIP(c, lbfgs_dot(c, prec, Y[pairs.front()], z, n, redA, &np));
+    for (int t = 0; t < np_pairs; ++t) {
+      const int i = pairs[t];
+      const void *ynext = t + 1 < np_pairs ? Y[pairs[t + 1]] : nullptr;
+      NLE_HIP(c, lbfgs_axpy2_dot(c, prec, z, S[i], redA, np, rho[i], alpha + i, ynext,
+                                 ynext ? redB : nullptr, n));
+      std::swap(redA, redB);
+    }
+    rep.hist(k, rn, o.h0 == NLE_H0_KSP ? o.h0_rtol : 0.0, lit);
+    // step p = -||g|| z ; u += p ; s = p
+    const int slot = free_slots.back();
+    free_slots.pop_back();
+    NLE_HIP(c, vec_cast_scale(c, prec, z, prec, S[slot], -rn, n));
+    NLE_HIP(c, vec_axpy(c, prec, z, NLE_FP64, u, -rn, nullptr, n));
+    // new gradient, y = g_new - g
+    const double rn_old = rn;
+    hipError_t e;
+    NLE_HIP(c, hipMemsetAsync(c->dflag, 0, 4, c->stream));
+    const int npr = elem_apply(c, OP_RES, NLE_FP64, u, nullptr, gn, c->red + 4 * VGRID_MAX, &e);
+    if (e != hipSuccess) return fail(c, NLE_E_HIP, "residual");
+    ++n_res;
+    NLE_HIP(c, reduce_scalar(c, c->red + 4 * VGRID_MAX, npr, c->dscal + 40));
+    NLE_HIP(c, vec_cast_scale(c, NLE_FP64, gn, NLE_FP64, y64, 1.0, n));
+    NLE_HIP(c, vec_axpy(c, NLE_FP64, g, NLE_FP64, y64, -1.0, nullptr, n));
+    NLE_HIP(c, vec_cast_scale(c, NLE_FP64, y64, prec, Y[slot], 1.0, n));
+    int n1 = vec_dot_partials(c, prec, S[slot], Y[slot], n, c->red, &e);
+    vec_dot_partials(c, prec, S[slot], S[slot], n, c->red + VGRID_MAX, &e);
+    vec_dot_partials(c, prec, Y[slot], Y[slot], n, c->red + 2 * VGRID_MAX, &e);
+    if (e != hipSuccess) return fail(c, NLE_E_HIP, "curvature dots");
+    NLE_HIP(c, reduce_scalars(c, c->red, n1, 3, c->dscal + 41));
+    NLE_HIP(c, hipMemcpyAsync(c->hpin, c->dscal + 40, 32, hipMemcpyDeviceToHost, c->stream));
+    NLE_HIP(c, hipMemcpyAsync(c->hpin + 4, c->dflag, 4, hipMemcpyDeviceToHost, c->stream));
+    NLE_HIP(c, hipStreamSynchronize(c->stream));
+    rn = std::sqrt(c->hpin[0]);
+    const double sy = c->hpin[1], ss = c->hpin[2], yy = c->hpin[3];
+    int32_t fl;
+    std::memcpy(&fl, c->hpin + 4, 4);
+    inv = fl != 0;
+    (void)rn_old;
+    if (sy > o.curvature_eps * std::sqrt(ss * yy) && std::isfinite(sy)) {
+      rho[slot] = 1.0 / sy;
+      pairs.push_back(slot);
+      if (int(pairs.size()) > m) {
+        free_slots.push_back(pairs.front());
+        pairs.pop_front();
+      }
+    } else {
+      ++skipped;
+      free_slots.push_back(slot);
+    }
+    std::swap(g, gn);
+  }
+  if (report) {
+    report->lit_total = lit_total;
+    report->n_jv = n_jv;
+    report->n_residual = n_res;
+    report->bfgs_skipped = skipped;
+  }
+  return finish(c, rep, st, k, rn0, rn, timer);
+}
+
+}  // namespace
+
+}  // namespace nle
+
+using namespace nle;
+
+extern "C" {
+
+void nle_default_opts(int32_t method, nle_solver_opts *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = NLE_PREC_FP64;
+  o->ksp_type = NLE_KSP_CG;
+  o->orth = NLE_ORTH_CGS2;
+  o->pc = NLE_PC_JACOBI;
+  o->restart = 0;
+  o->ksp_max_it = 100000;
+  o->snes_max_it = 50;
+  o->ew_version = 1;
+  o->qn_m = 50;
+  o->h0 = NLE_H0_KSP;
+  o->check_every = 32;
+  o->ksp_rtol = 1e-6;
+  o->ksp_atol = 1e-10;
+  o->ew_rtol0 = 0.1;
+  o->ew_rtolmax = 0.1;
+  o->ew_rtolmin = 0.0;
+  o->ew_gamma = 1.0;
+  o->ew_alpha = GOLDEN;
+  o->ew_alpha2 = GOLDEN;
+  o->ew_threshold = 0.1;
+  o->ink_ksp_atol = 1e-14;
+  o->snes_rtol = 1e-8;
+  o->snes_atol = 0.0;
+  o->h0_rtol = 1e-2;
+  o->h0_atol = 1e-14;
+  o->curvature_eps = 1e-12;
+  if (method == NLE_BFGS) o->snes_max_it = 1000;
+}
+
+nle_status nle_solve_nk(nle_ctx *ctx, double *u, const nle_solver_opts *o, nle_report *rep) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  nle_status s = check_ready(c, u, o);
+  if (s != NLE_OK) return s;
+  try {
+    return newton(c, u, *o, rep, false);
+  } catch (...) {
+    c->elem_skip = nullptr;
+    return fail(c, NLE_E_OOM, "host exception in solver");
+  }
+}
+
+nle_status nle_solve_ink(nle_ctx *ctx, double *u, const nle_solver_opts *o, nle_report *rep) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  nle_status s = check_ready(c, u, o);
+  if (s != NLE_OK) return s;
+  try {
+    return newton(c, u, *o, rep, true);
+  } catch (...) {
+    c->elem_skip = nullptr;
+    return fail(c, NLE_E_OOM, "host exception in solver");
+  }
+}
+
+nle_status nle_solve_bfgs(nle_ctx *ctx, double *u, const nle_solver_opts *o, nle_report *rep) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  nle_status s = check_ready(c, u, o);
+  if (s != NLE_OK) return s;
+  try {
+    return bfgs(c, u, *o, rep);
+  } catch (...) {
+    c->elem_skip = nullptr;
+    return fail(c, NLE_E_OOM, "host exception in solver");
+  }
+}
+
+}  // extern "C"

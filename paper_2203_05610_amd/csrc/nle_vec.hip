@@ -1,0 +1,660 @@
+// Streaming vector kernels for the Krylov and L-BFGS loops.
+//
+// Reductions are deterministic: each workgroup of a fixed-size grid (a
+// function of the vector length only) sums its grid-stride share in a fixed
+// order and writes one partial; the consumer (a later kernel) sums the
+// partials in index order.  When several workgroups of the consumer need the
+// same scalar, each of them repeats that identical sum, so every workgroup
+// sees the same bits without another launch.
+#include <hip/hip_runtime.h>
+
+#include "nle_internal.hpp"
+
+namespace nle {
+
+namespace {
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Fixed-order workgroup sum, result broadcast to all threads.
+template <typename T>
+__device__ __forceinline__ T block_sum_all(T v, T *sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  T r = sh[0];
+  for (int k = 1; k < NT / 64; ++k) r += sh[k];
+  return r;
+}
+
+// Sum of red[0..np) in a fixed order, identical in every workgroup.
+__device__ __forceinline__ double sum_partials(const double *red, int np, double *sh) {
+  double v = 0.0;
+  for (int k = threadIdx.x; k < np; k += NT) v += red[k];
+  return block_sum_all(v, sh);
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_fill(T *x, T val, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT)
+    x[i] = val;
+}
+
+template <typename S, typename D>
+__global__ __launch_bounds__(NT) void k_cast_scale(const S *x, D *y, double s, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT)
+    y[i] = D(s * double(x[i]));
+}
+
+template <typename S, typename D>
+__global__ __launch_bounds__(NT) void k_axpy(const S *x, D *y, double a, const double *ad,
+                                             int64_t n) {
+  const double alpha = ad ? a * ad[0] : a;
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT)
+    y[i] = D(double(y[i]) + alpha * double(x[i]));
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_mul(const T *a, const T *b, T *y, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT)
+    y[i] = a[i] * b[i];
+}
+
+__global__ __launch_bounds__(NT) void k_recip(const double *d, double *di, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT)
+    di[i] = 1.0 / d[i];
+}
+
+__global__ __launch_bounds__(NT) void k_lift(double *u, const int64_t *dofs, const double *vals,
+                                             int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT)
+    u[dofs[i]] = vals[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_dot(const T *a, const T *b, int64_t n, double *red) {
+  __shared__ T sh[NT / 64];
+  T acc = T(0);
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT)
+    acc += a[i] * b[i];
+  acc = block_sum_all(acc, sh);
+  if (threadIdx.x == 0) red[blockIdx.x] = double(acc);
+}
+
+// out[c] = sum_k red[c * stride + k], k < np, one workgroup per c.
+__global__ __launch_bounds__(NT) void k_reduce(const double *red, int np, int stride, double *out) {
+  __shared__ double sh[NT / 64];
+  const double s = sum_partials(red + int64_t(blockIdx.x) * stride, np, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+// ------------------------------------------------------------------ CG
+enum { S_RZ = 0, S_TOL2 = 2, S_RR = 3, S_B2 = 4, S_ALPHA = 5 };
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_cg_start(const T *b, T *x, T *r, T *z, T *p, const T *dinv,
+                                                 int64_t n, double *red) {
+  __shared__ T sh[NT / 64];
+  T arz = T(0), arr = T(0);
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT) {
+    const T bi = b[i];
+    const T zi = dinv ? dinv[i] * bi : bi;
+    x[i] = T(0);
+    r[i] = bi;
+    z[i] = zi;
+    p[i] = zi;
+    arz += bi * zi;
+    arr += bi * bi;
+  }
+  arz = block_sum_all(arz, sh);
+  arr = block_sum_all(arr, sh);
+  if (threadIdx.x == 0) {
+    red[blockIdx.x] = double(arz);
+    red[VGRID_MAX + blockIdx.x] = double(arr);
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_cg_start2(const double *red, int np, double *scal,
+                                                  int32_t *flag, double rtol, double atol) {
+  __shared__ double sh[NT / 64];
+  const double rz = sum_partials(red, np, sh);
+  const double rr = sum_partials(red + VGRID_MAX, np, sh);
+  if (threadIdx.x == 0) {
+    const double tol2 = fmax(rtol * rtol * rr, atol * atol);
+    scal[S_RZ] = rz;
+    scal[S_TOL2] = tol2;
+    scal[S_RR] = rr;
+    scal[S_B2] = rr;
+    flag[1] = 0;
+    flag[0] = (rr <= tol2) ? 1 : ((rr == rr) ? 0 : 3);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_cg_update(T *x, T *r, T *z, const T *p, const T *Ap,
+                                                  const T *dinv, int64_t n, const double *red_a,
+                                                  int np_a, double *red_b, double *scal,
+                                                  int32_t *flag, int it) {
+  __shared__ double shd[NT / 64];
+  __shared__ T sh[NT / 64];
+  if (flag[0] != 0) return;
+  const double pAp = sum_partials(red_a, np_a, shd);
+  if (!(pAp > 0.0)) {  // not positive definite (or NaN): stop, keep x
+    if (blockIdx.x == 0 && threadIdx.x == 0) flag[0] = 2;
+    return;
+  }
+  const double alpha = scal[S_RZ + (it & 1)] / pAp;
+  const T a = T(alpha);
+  T arz = T(0), arr = T(0);
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT) {
+    const T ri = r[i] - a * Ap[i];
+    const T zi = dinv ? dinv[i] * ri : ri;
+    x[i] += a * p[i];
+    r[i] = ri;
+    z[i] = zi;
+    arz += ri * zi;
+    arr += ri * ri;
+  }
+  arz = block_sum_all(arz, sh);
+  arr = block_sum_all(arr, sh);
+  if (threadIdx.x == 0) {
+    red_b[blockIdx.x] = double(arz);
+    red_b[VGRID_MAX + blockIdx.x] = double(arr);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_cg_direction(T *p, const T *z, int64_t n,
+                                                     const double *red_b, int np, double *scal,
+                                                     int32_t *flag, int it) {
+  __shared__ double sh[NT / 64];
+  if (flag[0] != 0) return;
+  const double rz = sum_partials(red_b, np, sh);
+  const double rr = sum_partials(red_b + VGRID_MAX, np, sh);
+  const double beta = rz / scal[S_RZ + (it & 1)];
+  const T bt = T(beta);
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT)
+    p[i] = z[i] + bt * p[i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    scal[S_RZ + ((it + 1) & 1)] = rz;
+    scal[S_RR] = rr;
+    flag[1] = it + 1;
+    if (!(rr == rr))
+      flag[0] = 3;
+    else if (rr <= scal[S_TOL2])
+      flag[0] = 1;
+  }
+}
+
+// ------------------------------------------------------------------ GMRES
+// Device layout of GmresArgs::H (doubles, m = capacity):
+//   H[(m+1) * m] column-major Hessenberg, then cs[m], sn[m], g[m+1], y[m].
+// scal: [0] beta (norm of r0), [1] tolerance, [2] 1 / h(j+1, j), [3] current
+// residual estimate; flag: [0] done (1 converged, 3 breakdown), [1] columns
+// in the current cycle.
+__device__ __forceinline__ double *gm_cs(double *H, int m) { return H + (m + 1) * m; }
+__device__ __forceinline__ double *gm_sn(double *H, int m) { return H + (m + 1) * m + m; }
+__device__ __forceinline__ double *gm_g(double *H, int m) { return H + (m + 1) * m + 2 * m; }
+__device__ __forceinline__ double *gm_y(double *H, int m) { return H + (m + 1) * m + 3 * m + 1; }
+
+// partials of V_i . w for i = blockIdx.y
+template <typename T>
+__global__ __launch_bounds__(NT) void k_gm_dots(const T *V, const T *w, int64_t n, double *red,
+                                                const int32_t *flag) {
+  __shared__ T sh[NT / 64];
+  if (flag[0] != 0) return;
+  const T *vi = V + int64_t(blockIdx.y) * n;
+  T acc = T(0);
+  for (int64_t k = int64_t(blockIdx.x) * NT + threadIdx.x; k < n; k += int64_t(gridDim.x) * NT)
+    acc += vi[k] * w[k];
+  acc = block_sum_all(acc, sh);
+  if (threadIdx.x == 0) red[int64_t(blockIdx.y) * VGRID_MAX + blockIdx.x] = double(acc);
+}
+
+// hc[i] (+)= sum of partials of dot i, one workgroup per i
+__global__ __launch_bounds__(NT) void k_gm_reduce(const double *red, int np, double *hc, int add,
+                                                  const int32_t *flag) {
+  __shared__ double sh[NT / 64];
+  if (flag[0] != 0) return;
+  const double s = sum_partials(red + int64_t(blockIdx.x) * VGRID_MAX, np, sh);
+  if (threadIdx.x == 0) hc[blockIdx.x] = add ? hc[blockIdx.x] + s : s;
+}
+
+// w -= sum_{i<=j} h_i V_i, with h the second argument (pass-specific copy);
+// if want_sq, partials of w.w
+template <typename T>
+__global__ __launch_bounds__(NT) void k_gm_sub(const T *V, T *w, int64_t n, const double *h, int j1,
+                                               double *red_sq, const int32_t *flag) {
+  __shared__ T sh[NT / 64];
+  __shared__ double hs[256];
+  if (flag[0] != 0) return;
+  for (int i = threadIdx.x; i < j1 && i < 256; i += NT) hs[i] = h[i];
+  __syncthreads();
+  T acc = T(0);
+  for (int64_t k = int64_t(blockIdx.x) * NT + threadIdx.x; k < n; k += int64_t(gridDim.x) * NT) {
+    double wk = double(w[k]);
+    for (int i = 0; i < j1; ++i) wk -= (i < 256 ? hs[i] : h[i]) * double(V[int64_t(i) * n + k]);
+    const T t = T(wk);
+    w[k] = t;
+    acc += t * t;
+  }
+  if (red_sq) {
+    acc = block_sum_all(acc, sh);
+    if (threadIdx.x == 0) red_sq[blockIdx.x] = double(acc);
+  }
+}
+
+// Finish column j: h(j+1,j) = ||w||, Givens rotations, residual test.
+__global__ void k_gm_col(double *H, int m, int j, const double *red_sq, int np, const double *hc1,
+                         const double *hc2, double *scal, int32_t *flag, int max_cols) {
+  __shared__ double sh[NT / 64];
+  if (flag[0] != 0) return;
+  const double ww = sum_partials(red_sq, np, sh);
+  if (threadIdx.x != 0) return;
+  double *col = H + int64_t(m + 1) * j;
+  for (int i = 0; i <= j; ++i) col[i] = hc1[i] + (hc2 ? hc2[i] : 0.0);
+  const double hn = sqrt(ww);
+  col[j + 1] = hn;
+  double *cs = gm_cs(H, m), *sn = gm_sn(H, m), *g = gm_g(H, m);
+  for (int i = 0; i < j; ++i) {
+    const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+    col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+    col[i] = t;
+  }
+  const double den = hypot(col[j], col[j + 1]);
+  double c = 1.0, s = 0.0;
+  if (den > 0.0) {
+    c = col[j] / den;
+    s = col[j + 1] / den;
+  }
+  cs[j] = c;
+  sn[j] = s;
+  col[j] = c * col[j] + s * col[j + 1];
+  col[j + 1] = 0.0;
+  g[j + 1] = -s * g[j];
+  g[j] = c * g[j];
+  const double res = fabs(g[j + 1]);
+  scal[3] = res;
+  scal[2] = hn > 0.0 ? 1.0 / hn : 0.0;
+  flag[1] = j + 1;
+  if (!(res == res))
+    flag[0] = 3;
+  else if (res <= scal[1] || hn == 0.0)
+    flag[0] = 1;
+  else if (j + 1 >= max_cols)
+    flag[0] = 4;  // cycle full (host restarts or stops)
+}
+
+// V_{j+1} = w * scal[2]
+template <typename T>
+__global__ __launch_bounds__(NT) void k_gm_next(const T *w, T *vn, int64_t n, const double *scal,
+                                                const int32_t *flag) {
+  if (flag[0] != 0) return;
+  const T s = T(scal[2]);
+  for (int64_t k = int64_t(blockIdx.x) * NT + threadIdx.x; k < n; k += int64_t(gridDim.x) * NT)
+    vn[k] = w[k] * s;
+}
+
+// Back substitution H(0:k,0:k) y = g(0:k), k = flag[1].
+__global__ void k_gm_solve(double *H, int m, const int32_t *flag) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int k = flag[1];
+  double *g = gm_g(H, m), *y = gm_y(H, m);
+  for (int i = k - 1; i >= 0; --i) {
+    double s = g[i];
+    for (int l = i + 1; l < k; ++l) s -= H[int64_t(m + 1) * l + i] * y[l];
+    const double d = H[int64_t(m + 1) * i + i];
+    y[i] = d != 0.0 ? s / d : 0.0;
+  }
+}
+
+// x += M^-1 (sum_i y_i V_i)
+template <typename T>
+__global__ __launch_bounds__(NT) void k_gm_update(const T *V, T *x, const T *dinv, int64_t n,
+                                                  const double *H, int m, const int32_t *flag) {
+  __shared__ double ys[256];
+  const int k = flag[1];
+  const double *y = H + (m + 1) * m + 3 * m + 1;
+  for (int i = threadIdx.x; i < k && i < 256; i += NT) ys[i] = y[i];
+  __syncthreads();
+  for (int64_t q = int64_t(blockIdx.x) * NT + threadIdx.x; q < n; q += int64_t(gridDim.x) * NT) {
+    double s = 0.0;
+    for (int i = 0; i < k; ++i) s += (i < 256 ? ys[i] : y[i]) * double(V[int64_t(i) * n + q]);
+    const double d = dinv ? double(dinv[q]) : 1.0;
+    x[q] = T(double(x[q]) + d * s);
+  }
+}
+
+// Start of a cycle: V_0 = r0 / ||r0|| given partials of r0.r0; initialise g.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_gm_start(const T *r0, T *V0, int64_t n, const double *red,
+                                                 int np, double *H, int m, double *scal,
+                                                 int32_t *flag, double rtol, double atol,
+                                                 int first) {
+  __shared__ double sh[NT / 64];
+  const double rr = sum_partials(red, np, sh);
+  const double beta = sqrt(rr);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (first) scal[1] = fmax(rtol * beta, atol);
+    scal[0] = beta;
+    scal[3] = beta;
+    double *g = gm_g(H, m);
+    for (int i = 0; i <= m; ++i) g[i] = 0.0;
+    g[0] = beta;
+    flag[1] = 0;
+    flag[0] = !(beta == beta) ? 3 : (beta <= scal[1] ? 1 : 0);
+  }
+  const T s = T(beta > 0.0 ? 1.0 / beta : 0.0);
+  for (int64_t k = int64_t(blockIdx.x) * NT + threadIdx.x; k < n; k += int64_t(gridDim.x) * NT)
+    V0[k] = r0[k] * s;
+}
+
+// ------------------------------------------------------------------ L-BFGS
+template <typename T>
+__global__ __launch_bounds__(NT) void k_lb_axpy_dot(T *q, const T *y, const double *red, int np,
+                                                    double rho, double *alpha_out,
+                                                    const T *s_next, double *red_next, int64_t n) {
+  __shared__ double shd[NT / 64];
+  __shared__ T sh[NT / 64];
+  const double alpha = rho * sum_partials(red, np, shd);
+  if (blockIdx.x == 0 && threadIdx.x == 0) alpha_out[0] = alpha;
+  const T a = T(alpha);
+  T acc = T(0);
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT) {
+    const T qi = q[i] - a * y[i];
+    q[i] = qi;
+    if (s_next) acc += s_next[i] * qi;
+  }
+  if (red_next) {
+    acc = block_sum_all(acc, sh);
+    if (threadIdx.x == 0) red_next[blockIdx.x] = double(acc);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_lb_axpy2_dot(T *z, const T *s, const double *red, int np,
+                                                     double rho, const double *alpha,
+                                                     const T *y_next, double *red_next,
+                                                     int64_t n) {
+  __shared__ double shd[NT / 64];
+  __shared__ T sh[NT / 64];
+  const double beta = rho * sum_partials(red, np, shd);
+  const T cc = T(alpha[0] - beta);
+  T acc = T(0);
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT) {
+    const T zi = z[i] + cc * s[i];
+    z[i] = zi;
+    if (y_next) acc += y_next[i] * zi;
+  }
+  if (red_next) {
+    acc = block_sum_all(acc, sh);
+    if (threadIdx.x == 0) red_next[blockIdx.x] = double(acc);
+  }
+}
+
+}  // namespace
+
+int vgrid(int64_t n) {
+  int64_t g = (n + NT * 4 - 1) / (NT * 4);
+  if (g < 1) g = 1;
+  if (g > VGRID_MAX) g = VGRID_MAX;
+  return int(g);
+}
+
+#define LAUNCH(kern, grid, ...) hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), 0, c->stream, __VA_ARGS__)
+
+hipError_t vec_fill(Ctx *c, int prec, void *x, double val, int64_t n) {
+  if (prec == NLE_FP32)
+    LAUNCH(k_fill<float>, vgrid(n), static_cast<float *>(x), float(val), n);
+  else
+    LAUNCH(k_fill<double>, vgrid(n), static_cast<double *>(x), val, n);
+  return hipGetLastError();
+}
+
+hipError_t vec_cast_scale(Ctx *c, int px, const void *x, int py, void *y, double s, int64_t n) {
+  const int g = vgrid(n);
+  if (px == NLE_FP64 && py == NLE_FP64)
+    LAUNCH((k_cast_scale<double, double>), g, static_cast<const double *>(x), static_cast<double *>(y), s, n);
+  else if (px == NLE_FP64)
+    LAUNCH((k_cast_scale<double, float>), g, static_cast<const double *>(x), static_cast<float *>(y), s, n);
+  else if (py == NLE_FP64)
+    LAUNCH((k_cast_scale<float, double>), g, static_cast<const float *>(x), static_cast<double *>(y), s, n);
+  else
+    LAUNCH((k_cast_scale<float, float>), g, static_cast<const float *>(x), static_cast<float *>(y), s, n);
+  return hipGetLastError();
+}
+
+hipError_t vec_axpy(Ctx *c, int px, const void *x, int py, void *y, double a, const double *ad,
+                    int64_t n) {
+  const int g = vgrid(n);
+  if (px == NLE_FP64 && py == NLE_FP64)
+    LAUNCH((k_axpy<double, double>), g, static_cast<const double *>(x), static_cast<double *>(y), a, ad, n);
+  else if (px == NLE_FP32 && py == NLE_FP64)
+    LAUNCH((k_axpy<float, double>), g, static_cast<const float *>(x), static_cast<double *>(y), a, ad, n);
+  else if (px == NLE_FP64)
+    LAUNCH((k_axpy<double, float>), g, static_cast<const double *>(x), static_cast<float *>(y), a, ad, n);
+  else
+    LAUNCH((k_axpy<float, float>), g, static_cast<const float *>(x), static_cast<float *>(y), a, ad, n);
+  return hipGetLastError();
+}
+
+hipError_t vec_mul(Ctx *c, int prec, const void *a, const void *b, void *y, int64_t n) {
+  if (prec == NLE_FP32)
+    LAUNCH(k_mul<float>, vgrid(n), static_cast<const float *>(a), static_cast<const float *>(b),
+           static_cast<float *>(y), n);
+  else
+    LAUNCH(k_mul<double>, vgrid(n), static_cast<const double *>(a), static_cast<const double *>(b),
+           static_cast<double *>(y), n);
+  return hipGetLastError();
+}
+
+hipError_t vec_recip(Ctx *c, const double *d, double *di, int64_t n) {
+  LAUNCH(k_recip, vgrid(n), d, di, n);
+  return hipGetLastError();
+}
+
+hipError_t vec_lift(Ctx *c, double *u) {
+  if (c->n_dir == 0) return hipSuccess;
+  LAUNCH(k_lift, vgrid(c->n_dir), u, c->dir_dofs, c->dir_vals, c->n_dir);
+  return hipGetLastError();
+}
+
+int vec_dot_partials(Ctx *c, int prec, const void *a, const void *b, int64_t n, double *red,
+                     hipError_t *err) {
+  const int g = vgrid(n);
+  if (prec == NLE_FP32)
+    LAUNCH(k_dot<float>, g, static_cast<const float *>(a), static_cast<const float *>(b), n, red);
+  else
+    LAUNCH(k_dot<double>, g, static_cast<const double *>(a), static_cast<const double *>(b), n, red);
+  *err = hipGetLastError();
+  return g;
+}
+
+hipError_t reduce_scalar(Ctx *c, const double *red, int np, double *out) {
+  LAUNCH(k_reduce, 1, red, np, 0, out);
+  return hipGetLastError();
+}
+
+hipError_t reduce_scalars(Ctx *c, const double *red, int np, int count, double *out) {
+  LAUNCH(k_reduce, count, red, np, VGRID_MAX, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ CG
+hipError_t cg_start(Ctx *c, const CgArgs &a, const void *b, double rtol, double atol) {
+  const int g = vgrid(a.n);
+  if (a.prec == NLE_FP32)
+    LAUNCH(k_cg_start<float>, g, static_cast<const float *>(b), static_cast<float *>(a.x),
+           static_cast<float *>(a.r), static_cast<float *>(a.z), static_cast<float *>(a.p),
+           static_cast<const float *>(a.dinv), a.n, a.red_b);
+  else
+    LAUNCH(k_cg_start<double>, g, static_cast<const double *>(b), static_cast<double *>(a.x),
+           static_cast<double *>(a.r), static_cast<double *>(a.z), static_cast<double *>(a.p),
+           static_cast<const double *>(a.dinv), a.n, a.red_b);
+  LAUNCH(k_cg_start2, 1, a.red_b, g, a.scal, a.flag, rtol, atol);
+  return hipGetLastError();
+}
+
+hipError_t cg_update(Ctx *c, const CgArgs &a, int it) {
+  const int g = vgrid(a.n);
+  if (a.prec == NLE_FP32)
+    LAUNCH(k_cg_update<float>, g, static_cast<float *>(a.x), static_cast<float *>(a.r),
+           static_cast<float *>(a.z), static_cast<const float *>(a.p),
+           static_cast<const float *>(a.Ap), static_cast<const float *>(a.dinv), a.n, a.red_a,
+           a.np_a, a.red_b, a.scal, a.flag, it);
+  else
+    LAUNCH(k_cg_update<double>, g, static_cast<double *>(a.x), static_cast<double *>(a.r),
+           static_cast<double *>(a.z), static_cast<const double *>(a.p),
+           static_cast<const double *>(a.Ap), static_cast<const double *>(a.dinv), a.n, a.red_a,
+           a.np_a, a.red_b, a.scal, a.flag, it);
+  return hipGetLastError();
+}
+
+hipError_t cg_direction(Ctx *c, const CgArgs &a, int it) {
+  const int g = vgrid(a.n);
+  if (a.prec == NLE_FP32)
+    LAUNCH(k_cg_direction<float>, g, static_cast<float *>(a.p), static_cast<const float *>(a.z),
+           a.n, a.red_b, g, a.scal, a.flag, it);
+  else
+    LAUNCH(k_cg_direction<double>, g, static_cast<double *>(a.p), static_cast<const double *>(a.z),
+           a.n, a.red_b, g, a.scal, a.flag, it);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ GMRES
+hipError_t gmres_start(Ctx *c, const GmresArgs &a, const void *r0, double rtol, double atol,
+                       int first) {
+  const int g = vgrid(a.n);
+  hipError_t e;
+  vec_dot_partials(c, a.prec, r0, r0, a.n, a.red, &e);
+  if (e != hipSuccess) return e;
+  if (a.prec == NLE_FP32)
+    LAUNCH(k_gm_start<float>, g, static_cast<const float *>(r0), static_cast<float *>(a.V), a.n,
+           a.red, g, a.H, a.m, a.scal, a.flag, rtol, atol, first);
+  else
+    LAUNCH(k_gm_start<double>, g, static_cast<const double *>(r0), static_cast<double *>(a.V), a.n,
+           a.red, g, a.H, a.m, a.scal, a.flag, rtol, atol, first);
+  return hipGetLastError();
+}
+
+// h = V_{0..j}^T w into hc (pass 0: scal area A, pass 1: area B)
+hipError_t gmres_multidot(Ctx *c, const GmresArgs &a, int j) {
+  const int g = vgrid(a.n);
+  if (a.prec == NLE_FP32)
+    hipLaunchKernelGGL(k_gm_dots<float>, dim3(g, j + 1), dim3(NT), 0, c->stream,
+                       static_cast<const float *>(a.V), static_cast<const float *>(a.w), a.n, a.red, a.flag);
+  else
+    hipLaunchKernelGGL(k_gm_dots<double>, dim3(g, j + 1), dim3(NT), 0, c->stream,
+                       static_cast<const double *>(a.V), static_cast<const double *>(a.w), a.n, a.red, a.flag);
+  return hipGetLastError();
+}
+
+// pass p: reduce the j+1 dots into hc_p, subtract; the last pass also
+// produces partials of w.w (in the partial row j+1 of a.red).
+hipError_t gmres_subtract(Ctx *c, const GmresArgs &a, int j, int pass, int want_sq) {
+  const int g = vgrid(a.n);
+  double *hc = a.scal + 8 + pass * (a.m + 1);
+  hipLaunchKernelGGL(k_gm_reduce, dim3(j + 1), dim3(NT), 0, c->stream, a.red, g, hc, 0, a.flag);
+  double *red_sq = want_sq ? a.red + int64_t(a.m + 1) * VGRID_MAX : nullptr;
+  if (a.prec == NLE_FP32)
+    LAUNCH(k_gm_sub<float>, g, static_cast<const float *>(a.V), static_cast<float *>(a.w), a.n,
+           hc, j + 1, red_sq, a.flag);
+  else
+    LAUNCH(k_gm_sub<double>, g, static_cast<const double *>(a.V), static_cast<double *>(a.w), a.n,
+           hc, j + 1, red_sq, a.flag);
+  return hipGetLastError();
+}
+
+// Modified Gram-Schmidt step i: h_i = V_i . w (reduced), w -= h_i V_i.  The
+// coefficient is accumulated into the pass-0 column area.
+hipError_t gmres_mgs_step(Ctx *c, const GmresArgs &a, int i, int j) {
+  const int g = vgrid(a.n);
+  hipError_t e;
+  const int64_t n = a.n;
+  const size_t es = a.prec == NLE_FP32 ? 4 : 8;
+  const void *vi = static_cast<const char *>(a.V) + size_t(i) * n * es;
+  vec_dot_partials(c, a.prec, vi, a.w, n, a.red, &e);
+  if (e != hipSuccess) return e;
+  double *hc = a.scal + 8;
+  hipLaunchKernelGGL(k_gm_reduce, dim3(1), dim3(NT), 0, c->stream, a.red, g, hc + i, 0, a.flag);
+  const bool last = (i == j);
+  double *red_sq = last ? a.red + int64_t(a.m + 1) * VGRID_MAX : nullptr;
+  if (a.prec == NLE_FP32)
+    LAUNCH(k_gm_sub<float>, g, static_cast<const float *>(vi), static_cast<float *>(a.w), n,
+           hc + i, 1, red_sq, a.flag);
+  else
+    LAUNCH(k_gm_sub<double>, g, static_cast<const double *>(vi), static_cast<double *>(a.w), n,
+           hc + i, 1, red_sq, a.flag);
+  return hipGetLastError();
+}
+
+hipError_t gmres_finish_col(Ctx *c, const GmresArgs &a, int j, int mgs) {
+  const int g = vgrid(a.n);
+  const double *hc1 = a.scal + 8;
+  const double *hc2 = mgs ? nullptr : a.scal + 8 + (a.m + 1);
+  hipLaunchKernelGGL(k_gm_col, dim3(1), dim3(NT), 0, c->stream, a.H, a.m, j,
+                     a.red + int64_t(a.m + 1) * VGRID_MAX, g, hc1, hc2, a.scal, a.flag, a.m);
+  const size_t es = a.prec == NLE_FP32 ? 4 : 8;
+  void *vn = static_cast<char *>(a.V) + size_t(j + 1) * a.n * es;
+  if (a.prec == NLE_FP32)
+    LAUNCH(k_gm_next<float>, g, static_cast<const float *>(a.w), static_cast<float *>(vn), a.n,
+           a.scal, a.flag);
+  else
+    LAUNCH(k_gm_next<double>, g, static_cast<const double *>(a.w), static_cast<double *>(vn), a.n,
+           a.scal, a.flag);
+  return hipGetLastError();
+}
+
+hipError_t gmres_update_x(Ctx *c, const GmresArgs &a) {
+  hipLaunchKernelGGL(k_gm_solve, dim3(1), dim3(64), 0, c->stream, a.H, a.m, a.flag);
+  const int g = vgrid(a.n);
+  if (a.prec == NLE_FP32)
+    LAUNCH(k_gm_update<float>, g, static_cast<const float *>(a.V), static_cast<float *>(a.x),
+           static_cast<const float *>(a.dinv), a.n, a.H, a.m, a.flag);
+  else
+    LAUNCH(k_gm_update<double>, g, static_cast<const double *>(a.V), static_cast<double *>(a.x),
+           static_cast<const double *>(a.dinv), a.n, a.H, a.m, a.flag);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ L-BFGS
+hipError_t lbfgs_dot(Ctx *c, int prec, const void *s, const void *q, int64_t n, double *red,
+                     int *np) {
+  hipError_t e;
+  *np = vec_dot_partials(c, prec, s, q, n, red, &e);
+  return e;
+}
+
+hipError_t lbfgs_axpy_dot(Ctx *c, int prec, void *q, const void *y, const double *red, int np,
+                          double rho, double *alpha_out, const void *s_next, double *red_next,
+                          int64_t n) {
+  const int g = vgrid(n);
+  if (prec == NLE_FP32)
+    LAUNCH(k_lb_axpy_dot<float>, g, static_cast<float *>(q), static_cast<const float *>(y), red, np,
+           rho, alpha_out, static_cast<const float *>(s_next), red_next, n);
+  else
+    LAUNCH(k_lb_axpy_dot<double>, g, static_cast<double *>(q), static_cast<const double *>(y), red,
+           np, rho, alpha_out, static_cast<const double *>(s_next), red_next, n);
+  return hipGetLastError();
+}
+
+hipError_t lbfgs_axpy2_dot(Ctx *c, int prec, void *z, const void *s, const double *red, int np,
+                           double rho, const double *alpha, const void *y_next, double *red_next,
+                           int64_t n) {
+  const int g = vgrid(n);
+  if (prec == NLE_FP32)
+    LAUNCH(k_lb_axpy2_dot<float>, g, static_cast<float *>(z), static_cast<const float *>(s), red, np,
+           rho, alpha, static_cast<const float *>(y_next), red_next, n);
+  else
+    LAUNCH(k_lb_axpy2_dot<double>, g, static_cast<double *>(z), static_cast<const double *>(s), red,
+           np, rho, alpha, static_cast<const double *>(y_next), red_next, n);
+  return hipGetLastError();
+}
+
+}  // namespace nle

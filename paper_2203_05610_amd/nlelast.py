@@ -1,0 +1,338 @@
+"""Thin ctypes binding of libnlelast.so (the C ABI declared in include/nlelast.h).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels.  Device vectors are torch tensors on the context's device (float64,
+or float32 for FP32 Jacobian actions); device memory for the library's own
+buffers comes from torch's caching allocator through the nle_allocator
+callbacks, and work is queued on torch's current stream.  There is no CPU
+fallback: without the built library every call raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnlelast.so")
+
+NLE_OK = 0
+NLE_DIVERGED_MAXIT, NLE_DIVERGED_NAN, NLE_DIVERGED_INVERTED = 1, 2, 3
+NLE_DIVERGED_LINEAR, NLE_BFGS_BREAKDOWN = 4, 5
+NLE_E_INVAL, NLE_E_BADMESH, NLE_E_STATE = -1, -2, -3
+NLE_E_OOM, NLE_E_HIP, NLE_E_UNSUPPORTED = -4, -5, -6
+NLE_FP64, NLE_FP32 = 0, 1
+NLE_MAT_M1, NLE_MAT_M2 = 1, 2
+NLE_NK, NLE_INK, NLE_BFGS = 0, 1, 2
+NLE_KSP_GMRES, NLE_KSP_CG = 0, 1
+NLE_ORTH_MGS, NLE_ORTH_CGS2 = 0, 1
+NLE_PC_NONE, NLE_PC_JACOBI = 0, 1
+NLE_H0_PREONLY, NLE_H0_KSP = 0, 1
+NLE_PREC_FP64, NLE_PREC_MIXED = 0, 1
+
+STATUS_NAMES = {
+    0: "OK", 1: "DIVERGED_MAXIT", 2: "DIVERGED_NAN", 3: "DIVERGED_INVERTED",
+    4: "DIVERGED_LINEAR", 5: "BFGS_BREAKDOWN", -1: "E_INVAL", -2: "E_BADMESH",
+    -3: "E_STATE", -4: "E_OOM", -5: "E_HIP", -6: "E_UNSUPPORTED",
+}
+
+# every symbol the header declares (checked by the CPU test suite)
+EXPORTS = [
+    "nle_create", "nle_destroy", "nle_last_error", "nle_version", "nle_set_block_size",
+    "nle_upload_mesh", "nle_set_material", "nle_set_dirichlet", "nle_set_traction",
+    "nle_set_body_force", "nle_set_load_scale", "nle_lift", "nle_residual", "nle_linearize",
+    "nle_jv", "nle_diag", "nle_energy", "nle_default_opts", "nle_solve_nk", "nle_solve_ink",
+    "nle_solve_bfgs", "nle_partition_info",
+]
+
+
+class NleError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class nle_allocator(ctypes.Structure):
+    _fields_ = [("alloc", ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)),
+                ("free", ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)),
+                ("user", ctypes.c_void_p)]
+
+
+class nle_solver_opts(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in (
+        "precision", "ksp_type", "orth", "pc", "restart", "ksp_max_it", "snes_max_it",
+        "ew_version", "qn_m", "h0", "check_every", "reserved")] + [
+        (n, ctypes.c_double) for n in (
+            "ksp_rtol", "ksp_atol", "ew_rtol0", "ew_rtolmax", "ew_rtolmin", "ew_gamma",
+            "ew_alpha", "ew_alpha2", "ew_threshold", "ink_ksp_atol", "snes_rtol", "snes_atol",
+            "h0_rtol", "h0_atol", "curvature_eps")]
+
+
+class nle_report(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("nit", ctypes.c_int32),
+                ("lit_total", ctypes.c_int64), ("n_jv", ctypes.c_int64),
+                ("n_residual", ctypes.c_int64), ("bfgs_skipped", ctypes.c_int32),
+                ("hist_cap", ctypes.c_int32), ("rnorm0", ctypes.c_double),
+                ("rnorm_final", ctypes.c_double), ("t_ms", ctypes.c_double),
+                ("rnorm_hist", ctypes.POINTER(ctypes.c_double)),
+                ("eta_hist", ctypes.POINTER(ctypes.c_double)),
+                ("lit_hist", ctypes.POINTER(ctypes.c_int32))]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libnlelast.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "nle_create": (I32, [ctypes.POINTER(P), I32, P, ctypes.POINTER(nle_allocator)]),
+        "nle_destroy": (None, [P]),
+        "nle_last_error": (ctypes.c_char_p, [P]),
+        "nle_version": (ctypes.c_char_p, []),
+        "nle_set_block_size": (I32, [P, I32]),
+        "nle_upload_mesh": (I32, [P, I64, P, I64, I32, P]),
+        "nle_set_material": (I32, [P, I32, P, I32]),
+        "nle_set_dirichlet": (I32, [P, I64, P, P]),
+        "nle_set_traction": (I32, [P, I64, P, P]),
+        "nle_set_body_force": (I32, [P, P]),
+        "nle_set_load_scale": (I32, [P, D]),
+        "nle_lift": (I32, [P, P]),
+        "nle_residual": (I32, [P, P, P, ctypes.POINTER(D)]),
+        "nle_linearize": (I32, [P, P, I32]),
+        "nle_jv": (I32, [P, P, P, I32]),
+        "nle_diag": (I32, [P, P]),
+        "nle_energy": (I32, [P, P, ctypes.POINTER(D)]),
+        "nle_default_opts": (None, [I32, ctypes.POINTER(nle_solver_opts)]),
+        "nle_solve_nk": (I32, [P, P, ctypes.POINTER(nle_solver_opts), ctypes.POINTER(nle_report)]),
+        "nle_solve_ink": (I32, [P, P, ctypes.POINTER(nle_solver_opts), ctypes.POINTER(nle_report)]),
+        "nle_solve_bfgs": (I32, [P, P, ctypes.POINTER(nle_solver_opts), ctypes.POINTER(nle_report)]),
+        "nle_partition_info": (I32, [P, ctypes.POINTER(I64)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+class Context:
+    """An nle_ctx bound to one device and torch's current stream on it."""
+
+    def __init__(self, device: int = 0, use_torch_allocator: bool = True):
+        import torch
+
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        L = lib()
+        self._keep = []
+        alloc_p = None
+        if use_torch_allocator:
+            dev = device
+
+            @ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+            def _alloc(nbytes, user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), dev)
+                except Exception:  # noqa: BLE001 - the C side reports OOM
+                    return None
+
+            @ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+            def _free(ptr, user):
+                if ptr:
+                    torch.cuda.caching_allocator_delete(ptr)
+
+            al = nle_allocator(_alloc, _free, None)
+            self._keep += [_alloc, _free, al]
+            alloc_p = ctypes.pointer(al)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        st = L.nle_create(ctypes.byref(h), device, ctypes.c_void_p(self.stream.cuda_stream), alloc_p)
+        if st != NLE_OK:
+            raise NleError(st, "nle_create failed")
+        self.handle = h
+        self.n_nodes = 0
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().nle_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+    def check(self, st: int) -> int:
+        if st < 0:
+            msg = lib().nle_last_error(self.handle)
+            raise NleError(st, msg.decode() if msg else "")
+        return st
+
+    def vec(self, t, dtype=None, n=None):
+        torch = self.torch
+        if not isinstance(t, torch.Tensor) or t.device != self.device or not t.is_contiguous():
+            raise ValueError("expected a contiguous tensor on the context's device")
+        if dtype is not None and t.dtype != dtype:
+            raise ValueError(f"expected dtype {dtype}, got {t.dtype}")
+        n = 3 * self.n_nodes if n is None else n
+        if t.numel() != n:
+            raise ValueError(f"expected {n} entries, got {t.numel()}")
+        return ctypes.c_void_p(t.data_ptr())
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ---- C-ABI mirror (same names) ------------------------------------------------
+def nle_version() -> str:
+    return lib().nle_version().decode()
+
+
+def nle_create(device: int = 0, use_torch_allocator: bool = True) -> Context:
+    return Context(device, use_torch_allocator)
+
+
+def nle_destroy(ctx: Context) -> None:
+    ctx.close()
+
+
+def nle_last_error(ctx: Context) -> str:
+    return lib().nle_last_error(ctx.handle).decode()
+
+
+def nle_set_block_size(ctx: Context, elems_per_block: int) -> None:
+    ctx.check(lib().nle_set_block_size(ctx.handle, int(elems_per_block)))
+
+
+def nle_upload_mesh(ctx: Context, X, conn) -> None:
+    X, px = _host(X, np.float64)
+    conn, pc = _host(conn, np.int32)
+    if X.ndim != 2 or X.shape[1] != 3 or conn.ndim != 2:
+        raise ValueError("X must be (n, 3) and conn (n_e, k)")
+    ctx.check(lib().nle_upload_mesh(ctx.handle, X.shape[0], px, conn.shape[0], conn.shape[1], pc))
+    ctx.n_nodes = X.shape[0]
+
+
+def nle_set_material(ctx: Context, kind: int, params) -> None:
+    p, pp = _host(params, np.float64)
+    ctx.check(lib().nle_set_material(ctx.handle, int(kind), pp, p.size))
+
+
+def nle_set_dirichlet(ctx: Context, dofs, values) -> None:
+    d, pd = _host(dofs, np.int64)
+    v, pv = _host(values, np.float64)
+    if d.shape != v.shape:
+        raise ValueError("dofs and values differ in length")
+    ctx.check(lib().nle_set_dirichlet(ctx.handle, d.size, pd, pv))
+
+
+def nle_set_traction(ctx: Context, tri, t) -> None:
+    f, pf = _host(tri, np.int32)
+    tt, pt = _host(t, np.float64)
+    ctx.check(lib().nle_set_traction(ctx.handle, f.shape[0] if f.size else 0, pf, pt))
+
+
+def nle_set_body_force(ctx: Context, f) -> None:
+    ff, pf = _host(f, np.float64)
+    ctx.check(lib().nle_set_body_force(ctx.handle, pf))
+
+
+def nle_set_load_scale(ctx: Context, s: float) -> None:
+    ctx.check(lib().nle_set_load_scale(ctx.handle, float(s)))
+
+
+def nle_lift(ctx: Context, u) -> None:
+    ctx.check(lib().nle_lift(ctx.handle, ctx.vec(u, ctx.torch.float64)))
+
+
+def nle_residual(ctx: Context, u, r, norm: bool = True) -> Optional[float]:
+    """r = f_int(u) - s f_ext; returns ||r|| (synchronising) when norm=True.
+    Raises NleError on usage errors; an inverted element raises too."""
+    T = ctx.torch.float64
+    if norm:
+        rn = ctypes.c_double()
+        st = lib().nle_residual(ctx.handle, ctx.vec(u, T), ctx.vec(r, T), ctypes.byref(rn))
+        if st == NLE_DIVERGED_INVERTED:
+            raise NleError(st, nle_last_error(ctx))
+        ctx.check(st)
+        return rn.value
+    ctx.check(lib().nle_residual(ctx.handle, ctx.vec(u, T), ctx.vec(r, T), None))
+    return None
+
+
+def nle_linearize(ctx: Context, u, prec: int = NLE_FP64) -> None:
+    ctx.check(lib().nle_linearize(ctx.handle, ctx.vec(u, ctx.torch.float64), int(prec)))
+
+
+def nle_jv(ctx: Context, v, y, prec: int = NLE_FP64) -> None:
+    T = ctx.torch.float32 if prec == NLE_FP32 else ctx.torch.float64
+    ctx.check(lib().nle_jv(ctx.handle, ctx.vec(v, T), ctx.vec(y, T), int(prec)))
+
+
+def nle_diag(ctx: Context, d) -> None:
+    ctx.check(lib().nle_diag(ctx.handle, ctx.vec(d, ctx.torch.float64)))
+
+
+def nle_energy(ctx: Context, u) -> float:
+    out = ctypes.c_double()
+    ctx.check(lib().nle_energy(ctx.handle, ctx.vec(u, ctx.torch.float64), ctypes.byref(out)))
+    return out.value
+
+
+def nle_default_opts(method: int) -> nle_solver_opts:
+    o = nle_solver_opts()
+    lib().nle_default_opts(int(method), ctypes.byref(o))
+    return o
+
+
+def _solve(fn, ctx: Context, u, opts: nle_solver_opts, hist_cap: int):
+    rep = nle_report()
+    rh = (ctypes.c_double * hist_cap)()
+    eh = (ctypes.c_double * hist_cap)()
+    lh = (ctypes.c_int32 * hist_cap)()
+    rep.hist_cap = hist_cap
+    rep.rnorm_hist = rh
+    rep.eta_hist = eh
+    rep.lit_hist = lh
+    st = fn(ctx.handle, ctx.vec(u, ctx.torch.float64), ctypes.byref(opts), ctypes.byref(rep))
+    ctx.check(st)
+    k = min(rep.nit + 1, hist_cap)
+    return st, dict(status=st, status_name=STATUS_NAMES.get(st, str(st)), nit=rep.nit,
+                    lit_total=rep.lit_total, n_jv=rep.n_jv, n_residual=rep.n_residual,
+                    bfgs_skipped=rep.bfgs_skipped, rnorm0=rep.rnorm0,
+                    rnorm_final=rep.rnorm_final, t_ms=rep.t_ms,
+                    rnorm_hist=list(rh[:k]), eta_hist=list(eh[:k]), lit_hist=list(lh[:k]))
+
+
+def nle_solve_nk(ctx: Context, u, opts: nle_solver_opts, hist_cap: int = 2048):
+    return _solve(lib().nle_solve_nk, ctx, u, opts, hist_cap)
+
+
+def nle_solve_ink(ctx: Context, u, opts: nle_solver_opts, hist_cap: int = 2048):
+    return _solve(lib().nle_solve_ink, ctx, u, opts, hist_cap)
+
+
+def nle_solve_bfgs(ctx: Context, u, opts: nle_solver_opts, hist_cap: int = 2048):
+    return _solve(lib().nle_solve_bfgs, ctx, u, opts, hist_cap)
+
+
+def nle_partition_info(ctx: Context) -> dict:
+    info = (ctypes.c_int64 * 8)()
+    ctx.check(lib().nle_partition_info(ctx.handle, info))
+    keys = ["n_blocks", "max_elems_per_block", "max_nodes_per_block", "block_node_slots",
+            "shared_nodes", "merge_slots", "lds_bytes_fp64_jv", "lds_bytes_fp32_jv"]
+    return dict(zip(keys, list(info)))

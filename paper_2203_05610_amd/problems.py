@@ -1,0 +1,64 @@
+"""Set up the Cook's-membrane workloads on a library context (marshalling only).
+
+Cook test (Sec. 4): clamp on x = 0, dead shear traction (0, tau, 0) per unit
+reference area on x = 48, compressible neo-Hookean (M1) or the paper's split
+law (M2).  The mesh object needs X, conn, faces['load'] and a
+dirichlet_dofs('clamp') method (the synthetic generator's Mesh).
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from . import nlelast as nl
+
+
+def setup_cook(ctx: nl.Context, mesh, mu: float, lam: float, tau: float = 1.0,
+               material: int = nl.NLE_MAT_M1, c_vol=None, block_size=None) -> None:
+    if block_size is not None:
+        nl.nle_set_block_size(ctx, block_size)
+    nl.nle_upload_mesh(ctx, mesh.X, mesh.conn)
+    params = [mu, lam] if material == nl.NLE_MAT_M1 or c_vol is None else [mu, lam, c_vol]
+    nl.nle_set_material(ctx, material, params)
+    dofs = mesh.dirichlet_dofs("clamp")
+    nl.nle_set_dirichlet(ctx, dofs, np.zeros(dofs.size))
+    nl.nle_set_traction(ctx, mesh.faces["load"], [0.0, tau, 0.0])
+    nl.nle_set_load_scale(ctx, 1.0)
+
+
+SOLVERS = {"nk": nl.nle_solve_nk, "ink": nl.nle_solve_ink, "bfgs": nl.nle_solve_bfgs}
+METHOD_IDS = {"nk": nl.NLE_NK, "ink": nl.NLE_INK, "bfgs": nl.NLE_BFGS}
+
+
+def make_opts(method: str, precision: str = "fp64", **over) -> nl.nle_solver_opts:
+    """Options of App. A for `method` ('nk', 'ink', 'bfgs'), plus overrides.
+
+    For 'bfgs', h0='preonly' (BFGS-preonly) or 'ksp' (inexact BFGS).
+    """
+    o = nl.nle_default_opts(METHOD_IDS[method])
+    o.precision = nl.NLE_PREC_MIXED if precision == "mixed" else nl.NLE_PREC_FP64
+    h0 = over.pop("h0", None)
+    if h0 is not None:
+        o.h0 = nl.NLE_H0_KSP if h0 == "ksp" else nl.NLE_H0_PREONLY
+    ksp = over.pop("ksp", None)
+    if ksp is not None:
+        o.ksp_type = nl.NLE_KSP_CG if ksp == "cg" else nl.NLE_KSP_GMRES
+    orth = over.pop("orth", None)
+    if orth is not None:
+        o.orth = nl.NLE_ORTH_MGS if orth == "mgs" else nl.NLE_ORTH_CGS2
+    for k, v in over.items():
+        setattr(o, k, v)
+    return o
+
+
+def solve_schedule(ctx: nl.Context, u, method: str, opts, scales, hist_cap: int = 4096):
+    """Solve at each load scale in turn, warm-started; returns the reports."""
+    reps = []
+    for s in scales:
+        nl.nle_set_load_scale(ctx, s)
+        st, rep = SOLVERS[method](ctx, u, opts, hist_cap)
+        rep["load_scale"] = s
+        reps.append(rep)
+        if st != nl.NLE_OK:
+            break
+    return reps

@@ -1,0 +1,195 @@
+"""GPU parity of the element kernels against the FP64 oracle (through the C ABI).
+
+Residual, Jacobian action (FP64 and FP32), tangent diagonal and potential at
+seeded states, on meshes that span several element blocks with a ragged last
+block, at the full 64x64x4 Cook size in the launch configuration the
+benchmark uses, and on degenerate cases.  Tolerances: FP64 <= 1e-12 relative
+(max-norm against the largest entry), FP32 Jacobian action <= 1e-5 relative
+(2-norm).
+"""
+
+import numpy as np
+import pytest
+
+import synthetic as syn
+from oracle import fem, materials
+from tests.gpu_common import MU, relmax, relnorm, smooth_state
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2203_05610_amd import nlelast as nl  # noqa: E402
+from paper_2203_05610_amd import problems  # noqa: E402
+
+CASES = [
+    # (nx, ny, nz, lambda/mu, block size, material)
+    (8, 8, 1, 5.0, 512, "M1"),     # the 384-tet Cook mesh, one block
+    (8, 8, 1, 5.0, 64, "M1"),      # same mesh, six blocks
+    (12, 10, 3, 50.0, 100, "M1"),  # 2160 tets, ragged last block
+    (12, 10, 3, 5000.0, 256, "M2"),
+    (7, 5, 2, 20.0, 64, "M2"),
+]
+
+
+def _setup(nx, ny, nz, ratio, be, mat, tau=1.0):
+    mesh = syn.cook_mesh(nx, ny, nz)
+    kind = materials.M1 if mat == "M1" else materials.M2
+    P = fem.cook_problem(mesh, mu=MU, lam=ratio * MU, tau=tau, material=kind)
+    ctx = nl.Context(0)
+    problems.setup_cook(ctx, mesh, MU, ratio * MU, tau,
+                        material=nl.NLE_MAT_M1 if mat == "M1" else nl.NLE_MAT_M2, block_size=be)
+    return mesh, P, ctx
+
+
+def _t(x, dtype=torch.float64):
+    return torch.tensor(np.asarray(x), dtype=dtype, device="cuda")
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_residual_parity(case):
+    mesh, P, ctx = _setup(*case)
+    u_h = P.lift(smooth_state(mesh, P.n_dofs, seed=3))
+    for s in (0.0, 1.0, 2.5):
+        nl.nle_set_load_scale(ctx, s)
+        r = torch.empty(P.n_dofs, dtype=torch.float64, device="cuda")
+        rn = nl.nle_residual(ctx, _t(u_h), r)
+        ref = P.residual(u_h, s)
+        assert relmax(r.cpu().numpy(), ref) < 1e-12
+        assert abs(rn - np.linalg.norm(ref)) <= 1e-12 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_jacobian_action_parity(case):
+    mesh, P, ctx = _setup(*case)
+    u_h = P.lift(smooth_state(mesh, P.n_dofs, seed=4))
+    v_h = syn.random_field(P.n_dofs, 1.0, seed=5)
+    ref = P.jv(u_h, v_h)
+    nl.nle_linearize(ctx, _t(u_h), nl.NLE_FP32)
+    y = torch.empty(P.n_dofs, dtype=torch.float64, device="cuda")
+    nl.nle_jv(ctx, _t(v_h), y, nl.NLE_FP64)
+    assert relmax(y.cpu().numpy(), ref) < 1e-12
+    y32 = torch.empty(P.n_dofs, dtype=torch.float32, device="cuda")
+    nl.nle_jv(ctx, _t(v_h, torch.float32), y32, nl.NLE_FP32)
+    assert relnorm(y32.double().cpu().numpy(), ref) < 1e-5
+
+
+@pytest.mark.parametrize("case", CASES[1:3])
+def test_diagonal_and_energy_parity(case):
+    mesh, P, ctx = _setup(*case)
+    u_h = P.lift(smooth_state(mesh, P.n_dofs, seed=6))
+    nl.nle_linearize(ctx, _t(u_h), nl.NLE_FP64)
+    d = torch.empty(P.n_dofs, dtype=torch.float64, device="cuda")
+    nl.nle_diag(ctx, d)
+    assert relmax(d.cpu().numpy(), P.diagonal(u_h)) < 1e-12
+    for s in (0.0, 1.7):
+        nl.nle_set_load_scale(ctx, s)
+        e = nl.nle_energy(ctx, _t(u_h))
+        ref = P.energy(u_h, s)
+        assert abs(e - ref) <= 1e-11 * abs(ref)
+
+
+def test_bitwise_repeatable():
+    mesh, P, ctx = _setup(12, 10, 3, 50.0, 100, "M1")
+    u = _t(P.lift(smooth_state(mesh, P.n_dofs, seed=7)))
+    v = _t(syn.random_field(P.n_dofs, 1.0, seed=8))
+    nl.nle_linearize(ctx, u, nl.NLE_FP32)
+    outs = []
+    for _ in range(3):
+        r = torch.empty_like(u)
+        nl.nle_residual(ctx, u, r, norm=False)
+        y = torch.empty_like(u)
+        nl.nle_jv(ctx, v, y, nl.NLE_FP64)
+        y32 = torch.empty(P.n_dofs, dtype=torch.float32, device="cuda")
+        nl.nle_jv(ctx, v.float(), y32, nl.NLE_FP32)
+        outs.append((r.clone(), y.clone(), y32.clone()))
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            assert torch.equal(a, b)
+
+
+def test_full_size_cook_parity_in_bench_configuration():
+    # 64x64x4 (98,304 tets), lambda/mu = 5000, default block size (bench launch)
+    mesh = syn.cook_mesh(64, 64, 4)
+    P = fem.cook_problem(mesh, mu=MU, lam=5000 * MU, tau=1.0)
+    ctx = nl.Context(0)
+    problems.setup_cook(ctx, mesh, MU, 5000 * MU, 1.0)
+    info = nl.nle_partition_info(ctx)
+    assert info["n_blocks"] == (mesh.n_elems + 511) // 512
+    u_h = P.lift(smooth_state(mesh, P.n_dofs, seed=9, amp=0.005))
+    v_h = syn.random_field(P.n_dofs, 1.0, seed=10)
+    r = torch.empty(P.n_dofs, dtype=torch.float64, device="cuda")
+    nl.nle_residual(ctx, _t(u_h), r)
+    assert relmax(r.cpu().numpy(), P.residual(u_h)) < 1e-12
+    nl.nle_linearize(ctx, _t(u_h), nl.NLE_FP32)
+    ref = P.jv(u_h, v_h)
+    y = torch.empty_like(r)
+    nl.nle_jv(ctx, _t(v_h), y, nl.NLE_FP64)
+    assert relmax(y.cpu().numpy(), ref) < 1e-12
+    y32 = torch.empty(P.n_dofs, dtype=torch.float32, device="cuda")
+    nl.nle_jv(ctx, _t(v_h, torch.float32), y32, nl.NLE_FP32)
+    assert relnorm(y32.double().cpu().numpy(), ref) < 1e-5
+
+
+def test_single_element_and_fully_constrained():
+    X = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], float)
+    conn = np.array([[0, 1, 2, 3]], np.int32)
+    ctx = nl.Context(0)
+    nl.nle_upload_mesh(ctx, X, conn)
+    nl.nle_set_material(ctx, nl.NLE_MAT_M1, [MU, 3 * MU])
+    P = fem.Problem(X, conn, materials.M1, (MU, 3 * MU), np.zeros(12), np.array([0, 1, 2]),
+                    np.zeros(3))
+    nl.nle_set_dirichlet(ctx, [0, 1, 2], [0, 0, 0])
+    u_h = P.lift(0.05 * syn.random_field(12, 1.0, seed=11))
+    r = torch.empty(12, dtype=torch.float64, device="cuda")
+    nl.nle_residual(ctx, _t(u_h), r)
+    assert relmax(r.cpu().numpy(), P.residual(u_h)) < 1e-12
+    # every dof prescribed: r = 0 and J v = v
+    nl.nle_set_dirichlet(ctx, np.arange(12), np.zeros(12))
+    assert nl.nle_residual(ctx, _t(u_h), r) == 0.0
+    nl.nle_linearize(ctx, _t(u_h), nl.NLE_FP64)
+    v = _t(syn.random_field(12, 1.0, seed=12))
+    y = torch.empty_like(v)
+    nl.nle_jv(ctx, v, y, nl.NLE_FP64)
+    assert torch.equal(y, v)
+
+
+def test_usage_errors():
+    ctx = nl.Context(0)
+    with pytest.raises(nl.NleError) as e:
+        nl.nle_upload_mesh(ctx, np.zeros((0, 3)), np.zeros((0, 4), np.int32))
+    assert e.value.status == nl.NLE_E_INVAL
+    X = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], float)
+    with pytest.raises(nl.NleError) as e:
+        nl.nle_upload_mesh(ctx, X, np.array([[0, 1, 2, 4]], np.int32))
+    assert e.value.status == nl.NLE_E_BADMESH
+    with pytest.raises(nl.NleError) as e:  # inverted element
+        nl.nle_upload_mesh(ctx, X, np.array([[0, 2, 1, 3]], np.int32))
+    assert e.value.status == nl.NLE_E_BADMESH and "element 0" in str(e.value)
+    with pytest.raises(nl.NleError) as e:  # repeated node
+        nl.nle_upload_mesh(ctx, X, np.array([[0, 1, 1, 3]], np.int32))
+    assert e.value.status == nl.NLE_E_BADMESH
+    nl.nle_upload_mesh(ctx, X, np.array([[0, 1, 2, 3]], np.int32))
+    with pytest.raises(nl.NleError) as e:  # no material yet
+        nl.nle_residual(ctx, torch.zeros(12, dtype=torch.float64, device="cuda"),
+                        torch.zeros(12, dtype=torch.float64, device="cuda"))
+    assert e.value.status == nl.NLE_E_STATE
+    nl.nle_set_material(ctx, nl.NLE_MAT_M1, [MU, MU])
+    with pytest.raises(nl.NleError) as e:  # Jv before linearize
+        nl.nle_jv(ctx, torch.zeros(12, dtype=torch.float64, device="cuda"),
+                  torch.zeros(12, dtype=torch.float64, device="cuda"))
+    assert e.value.status == nl.NLE_E_STATE
+    with pytest.raises(nl.NleError) as e:
+        nl.nle_set_dirichlet(ctx, [0, 0], [0.0, 0.0])
+    assert e.value.status == nl.NLE_E_INVAL
+    with pytest.raises(nl.NleError):
+        nl.nle_set_material(ctx, 99, [1.0, 1.0])
+
+
+def test_inverted_state_is_reported():
+    mesh, P, ctx = _setup(4, 4, 1, 5.0, 64, "M1")
+    u_h = np.zeros(P.n_dofs)
+    u_h[0::3] = -2.0 * mesh.X[:, 0]  # mirror x -> det F < 0 everywhere
+    r = torch.empty(P.n_dofs, dtype=torch.float64, device="cuda")
+    with pytest.raises(nl.NleError) as e:
+        nl.nle_residual(ctx, _t(u_h), r)
+    assert e.value.status == nl.NLE_DIVERGED_INVERTED
