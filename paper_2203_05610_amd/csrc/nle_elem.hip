@@ -23,8 +23,7 @@ template <typename T>
 struct ElemArgs {
   const T *G;
   const T *V;
-  const uint16_t *lconn;
-  const uint16_t *csr_idx;
+  const uint4 *lcp;   // per element: 4 slot-local vertex ids, 4 contribution positions (u16)
   const uint16_t *csr_end;
   const uint32_t *nodes;
   const int32_t *blk_elem;
@@ -85,7 +84,39 @@ __device__ __forceinline__ T block_sum(T v, T *sh) {
   return r;
 }
 
-// Element kinematics: F = I + H, J - 1 without cancellation, ln J, F^-T.
+// x / d in double from the hardware reciprocal estimate refined by two
+// Newton-Raphson corrections (reciprocal, then quotient).
+__device__ __forceinline__ double div_d(double x, double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(fma(-d, r, 1.0), r, r);
+  double q = x * r;
+  return fma(fma(-d, q, x), r, q);
+}
+
+// ln(1 + x) in double.  For |x| < 1/4 the series of 2 atanh(t), t = x/(2+x)
+// (terms t^(2k+1)/(2k+1), truncated where t^2^k < 1e-17) is cheaper than the
+// general routine; larger |x| falls back to log1p.
+__device__ __forceinline__ double log1p_d(double x) {
+  if (fabs(x) < 0.25) {
+    const double t = div_d(x, 2.0 + x);
+    const double t2 = t * t;
+    double p = 1.0 / 21.0;
+    p = fma(p, t2, 1.0 / 19.0);
+    p = fma(p, t2, 1.0 / 17.0);
+    p = fma(p, t2, 1.0 / 15.0);
+    p = fma(p, t2, 1.0 / 13.0);
+    p = fma(p, t2, 1.0 / 11.0);
+    p = fma(p, t2, 1.0 / 9.0);
+    p = fma(p, t2, 1.0 / 7.0);
+    p = fma(p, t2, 1.0 / 5.0);
+    p = fma(p, t2, 1.0 / 3.0);
+    p = fma(p, t2, 1.0);
+    return 2.0 * t * p;
+  }
+  return log1p(x);
+}
+
+// Element kinematics: F = I + H, J - 1, ln J (double), F^-T.
 template <typename T>
 struct Kin {
   T F[3][3];
@@ -96,34 +127,49 @@ struct Kin {
 
 template <typename T>
 __device__ __forceinline__ void kinematics(const T H[3][3], Kin<T> &k) {
-  // det(I + H) - 1 = tr H + ((tr H)^2 - tr(H^2)) / 2 + det H, in double so the
-  // volumetric terms keep their accuracy when J is close to one.
-  double h[3][3];
+  double jm1;
+  if (sizeof(T) == 8) {
+    // det(I + H) - 1 = tr H + ((tr H)^2 - tr(H^2)) / 2 + det H: no cancellation
+    // when J is near one, which keeps the FP64 residual's volumetric term exact
+    double h[3][3];
 #pragma unroll
-  for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) h[i][j] = double(H[i][j]);
-  const double tr = h[0][0] + h[1][1] + h[2][2];
-  double tr2 = 0.0;
+      for (int j = 0; j < 3; ++j) h[i][j] = double(H[i][j]);
+    const double tr = h[0][0] + h[1][1] + h[2][2];
+    const double tr2 = h[0][0] * h[0][0] + h[1][1] * h[1][1] + h[2][2] * h[2][2] +
+                       2.0 * (h[0][1] * h[1][0] + h[0][2] * h[2][0] + h[1][2] * h[2][1]);
+    const double deth = h[0][0] * (h[1][1] * h[2][2] - h[1][2] * h[2][1]) -
+                        h[0][1] * (h[1][0] * h[2][2] - h[1][2] * h[2][0]) +
+                        h[0][2] * (h[1][0] * h[2][1] - h[1][1] * h[2][0]);
+    jm1 = tr + 0.5 * (tr * tr - tr2) + deth;
+  } else {
+    // FP32 state: I + H is exact in double, and det(I + H) - 1 in double keeps
+    // ~12 significant digits of J - 1 (more than the FP32 inputs carry)
+    double f[3][3];
 #pragma unroll
-  for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) tr2 += h[i][j] * h[j][i];
-  const double deth = h[0][0] * (h[1][1] * h[2][2] - h[1][2] * h[2][1]) -
-                      h[0][1] * (h[1][0] * h[2][2] - h[1][2] * h[2][0]) +
-                      h[0][2] * (h[1][0] * h[2][1] - h[1][1] * h[2][0]);
-  double jm1 = tr + 0.5 * (tr * tr - tr2) + deth;
+      for (int j = 0; j < 3; ++j) f[i][j] = double(H[i][j]) + (i == j ? 1.0 : 0.0);
+    jm1 = f[0][0] * (f[1][1] * f[2][2] - f[1][2] * f[2][1]) -
+          f[0][1] * (f[1][0] * f[2][2] - f[1][2] * f[2][0]) +
+          f[0][2] * (f[1][0] * f[2][1] - f[1][1] * f[2][0]) - 1.0;
+  }
   k.bad = !(jm1 > -1.0);
   if (k.bad) jm1 = 0.0;
   k.jm1 = jm1;
   k.J = 1.0 + jm1;
-  k.lnJ = log1p(jm1);
+  k.lnJ = log1p_d(jm1);
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) k.F[i][j] = H[i][j] + (i == j ? T(1) : T(0));
   const T(&F)[3][3] = k.F;
-  const T ij = T(1.0 / k.J);
+  T ij;
+  if (sizeof(T) == 8)
+    ij = T(1.0 / k.J);
+  else
+    ij = T(__builtin_amdgcn_rcpf(float(k.J)));
   // cof F / J
   k.FiT[0][0] = (F[1][1] * F[2][2] - F[1][2] * F[2][1]) * ij;
   k.FiT[0][1] = (F[1][2] * F[2][0] - F[1][0] * F[2][2]) * ij;
@@ -143,10 +189,10 @@ struct Coef {
   double a, cF, cT, cM, cX, pT;
 };
 
-template <typename T>
+template <int MAT, typename T>
 __device__ __forceinline__ Coef coefficients(const Kin<T> &k, const MatParams &mp) {
   Coef c;
-  if (mp.kind == NLE_MAT_M2) {
+  if (MAT == NLE_MAT_M2) {
     // Psi = mu/2 (J^-2/3 I1 - 3) + cvol kappa (J^2 - 1 - 2 ln J)
     double I1 = 0.0;
 #pragma unroll
@@ -174,7 +220,7 @@ __device__ __forceinline__ Coef coefficients(const Kin<T> &k, const MatParams &m
   return c;
 }
 
-template <typename T>
+template <int MAT, typename T>
 __device__ __forceinline__ double energy_density(const Kin<T> &k, const T H[3][3],
                                                  const MatParams &mp) {
   // I1 - 3 = 2 tr H + H:H (no cancellation)
@@ -186,7 +232,7 @@ __device__ __forceinline__ double energy_density(const Kin<T> &k, const T H[3][3
     for (int j = 0; j < 3; ++j) hh += double(H[i][j]) * double(H[i][j]);
   }
   const double i1m3 = 2.0 * trH + hh;
-  if (mp.kind == NLE_MAT_M2) {
+  if (MAT == NLE_MAT_M2) {
     const double j23 = exp(-2.0 / 3.0 * k.lnJ);
     const double j2m1 = k.jm1 * (k.jm1 + 2.0);
     return 0.5 * mp.mu * (j23 * (i1m3 + 3.0) - 3.0) + mp.cvol * mp.kappa * (j2m1 - 2.0 * k.lnJ);
@@ -216,7 +262,148 @@ __device__ __forceinline__ void finalize_node(uint32_t g, uint32_t mk, const T a
   }
 }
 
-template <typename T, int OP>
+// Per-element input read from the element-contiguous arrays.
+template <typename T>
+struct ElemIn {
+  uint4 lcp;   // 8 x u16: slot-local vertex ids, then contribution positions
+  T g[3][3];   // grad N_1..3
+  T vol;
+};
+
+__device__ __forceinline__ int lo16(uint32_t w) { return int(w & 0xFFFFu); }
+__device__ __forceinline__ int hi16(uint32_t w) { return int(w >> 16); }
+
+// Component k of the gradients lives at G + k n_e: with a 32-bit element
+// index and uniform per-component base pointers every load is a scalar base
+// plus one shared 32-bit lane offset.
+template <typename T>
+__device__ __forceinline__ void load_elem(const ElemArgs<T> &A, uint32_t ge, ElemIn<T> &d) {
+  d.lcp = A.lcp[ge];
+  const uint32_t ne = uint32_t(A.n_e);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const T *Gk = A.G + size_t(3 * a + j) * ne;
+      d.g[a][j] = Gk[ge];
+    }
+  d.vol = A.V[ge];
+}
+
+// Element force vector (12 values, vertex-major) of one element.
+template <typename T, int OP, int MAT>
+__device__ __forceinline__ void element_forces(const ElemIn<T> &d, const T *uS, const T *vS,
+                                               int NL, const MatParams &mp, T out[4][3],
+                                               bool &bad, double &eacc) {
+  const int la[4] = {lo16(d.lcp.x), hi16(d.lcp.x), lo16(d.lcp.y), hi16(d.lcp.y)};
+  T g[4][3];
+#pragma unroll
+  for (int a = 1; a < 4; ++a)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) g[a][j] = d.g[a - 1][j];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) g[0][j] = -(g[1][j] + g[2][j] + g[3][j]);
+  T H[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) H[i][j] = T(0);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const T ua = uS[i * NL + la[a]];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) H[i][j] += ua * g[a][j];
+    }
+  Kin<T> k;
+  kinematics(H, k);
+  bad |= k.bad;
+  const double V = double(d.vol);
+  if (OP == OP_ENERGY) {
+    eacc += V * energy_density<MAT>(k, H, mp);
+    return;
+  }
+  const Coef cf = coefficients<MAT>(k, mp);
+  if (OP == OP_RES) {
+    const T ca = T(V * cf.a), cp = T(V * cf.pT);
+    T P[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) P[i][j] = ca * k.F[i][j] + cp * k.FiT[i][j];
+#pragma unroll
+    for (int a = 1; a < 4; ++a)
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        out[a][i] = P[i][0] * g[a][0] + P[i][1] * g[a][1] + P[i][2] * g[a][2];
+  } else if (OP == OP_JV) {
+    T dF[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) dF[i][j] = T(0);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const T va = vS[i * NL + la[a]];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) dF[i][j] += va * g[a][j];
+      }
+    T L = T(0), FdF = T(0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        L += k.FiT[i][j] * dF[i][j];
+        if (MAT == NLE_MAT_M2) FdF += k.F[i][j] * dF[i][j];
+      }
+    // X = F^-T dF^T F^-T = F^-T M with M = dF^T F^-T
+    T M[3][3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        M[p][j] = dF[0][p] * k.FiT[0][j] + dF[1][p] * k.FiT[1][j] + dF[2][p] * k.FiT[2][j];
+    const T ca = T(V * cf.a), cX = T(V * cf.cX);
+    const T sT = T(V * cf.cT) * L + (MAT == NLE_MAT_M2 ? T(V * cf.cM) * FdF : T(0));
+    const T sF = MAT == NLE_MAT_M2 ? T(V * cf.cF) * L : T(0);
+    T dP[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const T X = k.FiT[i][0] * M[0][j] + k.FiT[i][1] * M[1][j] + k.FiT[i][2] * M[2][j];
+        T t = ca * dF[i][j] + sT * k.FiT[i][j] + cX * X;
+        if (MAT == NLE_MAT_M2) t += sF * k.F[i][j];
+        dP[i][j] = t;
+      }
+#pragma unroll
+    for (int a = 1; a < 4; ++a)
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        out[a][i] = dP[i][0] * g[a][0] + dP[i][1] * g[a][1] + dP[i][2] * g[a][2];
+  } else {  // OP_DIAG: dF = e_i (x) g_a, one column at a time
+    const double ca = V * cf.a, c1 = V * (cf.cF + cf.cM), c2 = V * (cf.cT + cf.cX);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const T gg = g[a][0] * g[a][0] + g[a][1] * g[a][1] + g[a][2] * g[a][2];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const T w = k.FiT[i][0] * g[a][0] + k.FiT[i][1] * g[a][1] + k.FiT[i][2] * g[a][2];
+        const T z = k.F[i][0] * g[a][0] + k.F[i][1] * g[a][1] + k.F[i][2] * g[a][2];
+        out[a][i] = T(ca) * gg + T(c1) * w * z + T(c2) * w * w;
+      }
+    }
+    return;
+  }
+  // vertex 0: grad N_0 = -(grad N_1 + grad N_2 + grad N_3)
+#pragma unroll
+  for (int i = 0; i < 3; ++i) out[0][i] = -(out[1][i] + out[2][i] + out[3][i]);
+}
+
+template <typename T, int OP, int MAT>
 __global__ __launch_bounds__(NT) void k_elem_block(ElemArgs<T> A) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T *lds = reinterpret_cast<T *>(lds_raw);
@@ -229,11 +416,17 @@ __global__ __launch_bounds__(NT) void k_elem_block(ElemArgs<T> A) {
   const int tid = threadIdx.x;
   const int e0 = A.blk_elem[b], ne = A.blk_elem[b + 1] - e0;
   const int p0 = A.blk_node[b], nl = A.blk_node[b + 1] - p0;
-  const int NL = A.nl_max, BE = A.be_max;
+  const int NL = A.nl_max, C4 = 4 * A.be_max;
   T *uS = lds;                 // [3][NL]
   T *vS = lds + 3 * NL;        // [3][NL]      (Jv only)
-  T *cS = lds + 6 * NL;        // [12][BE]
+  T *cS = lds + 6 * NL;        // [3][4 BE]    contributions in slot-sorted order
   double *rs = reinterpret_cast<double *>(lds);  // reduction scratch (reused)
+
+  // The inputs of this thread's first two elements are requested before the
+  // node gather so all of these loads are in flight together.
+  ElemIn<T> ea, eb;
+  if (tid < ne) load_elem(A, uint32_t(e0 + tid), ea);
+  if (tid + NT < ne) load_elem(A, uint32_t(e0 + tid + NT), eb);
 
   // Phase 1: gather nodal state (and direction) of the block.
   for (int l = tid; l < nl; l += NT) {
@@ -248,117 +441,25 @@ __global__ __launch_bounds__(NT) void k_elem_block(ElemArgs<T> A) {
   }
   __syncthreads();
 
-  // Phase 2: one element per thread.
+  // Phase 2: one element per thread at a time.
   bool bad = false;
   double eacc = 0.0;
-  for (int e = tid; e < ne; e += NT) {
-    const int64_t ge = e0 + e;
-    int la[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) la[a] = A.lconn[a * A.n_e + ge];
-    T g[4][3];
-#pragma unroll
-    for (int a = 1; a < 4; ++a)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) g[a][j] = A.G[(3 * (a - 1) + j) * A.n_e + ge];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) g[0][j] = -(g[1][j] + g[2][j] + g[3][j]);
-    const T vol = A.V[ge];
-    T H[3][3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) H[i][j] = T(0);
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const T ua = uS[i * NL + la[a]];
-#pragma unroll
-        for (int j = 0; j < 3; ++j) H[i][j] += ua * g[a][j];
-      }
-    Kin<T> k;
-    kinematics(H, k);
-    bad |= k.bad;
-    if (OP == OP_ENERGY) {
-      eacc += double(vol) * energy_density(k, H, A.mp);
-      continue;
-    }
-    const Coef cf = coefficients(k, A.mp);
+  auto run = [&](const ElemIn<T> &d) {
     T out[4][3];
-    if (OP == OP_RES) {
-      const T ca = T(cf.a), cp = T(cf.pT);
-      T P[3][3];
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) P[i][j] = ca * k.F[i][j] + cp * k.FiT[i][j];
+    element_forces<T, OP, MAT>(d, uS, vS, NL, A.mp, out, bad, eacc);
+    if (OP != OP_ENERGY) {
+      const int cp[4] = {lo16(d.lcp.z), hi16(d.lcp.z), lo16(d.lcp.w), hi16(d.lcp.w)};
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
-          out[a][i] = vol * (P[i][0] * g[a][0] + P[i][1] * g[a][1] + P[i][2] * g[a][2]);
-    } else if (OP == OP_JV) {
-      T dF[3][3];
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) dF[i][j] = T(0);
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          const T va = vS[i * NL + la[a]];
-#pragma unroll
-          for (int j = 0; j < 3; ++j) dF[i][j] += va * g[a][j];
-        }
-      T L = T(0), FdF = T(0);
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          L += k.FiT[i][j] * dF[i][j];
-          FdF += k.F[i][j] * dF[i][j];
-        }
-      // X = F^-T dF^T F^-T = F^-T M with M = dF^T F^-T
-      T M[3][3];
-#pragma unroll
-      for (int p = 0; p < 3; ++p)
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-          M[p][j] = dF[0][p] * k.FiT[0][j] + dF[1][p] * k.FiT[1][j] + dF[2][p] * k.FiT[2][j];
-      const T ca = T(cf.a), cX = T(cf.cX);
-      const T sF = T(cf.cF) * L, sT = T(cf.cT) * L + T(cf.cM) * FdF;
-      T dP[3][3];
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          const T X = k.FiT[i][0] * M[0][j] + k.FiT[i][1] * M[1][j] + k.FiT[i][2] * M[2][j];
-          dP[i][j] = ca * dF[i][j] + sF * k.F[i][j] + sT * k.FiT[i][j] + cX * X;
-        }
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-          out[a][i] = vol * (dP[i][0] * g[a][0] + dP[i][1] * g[a][1] + dP[i][2] * g[a][2]);
-    } else {  // OP_DIAG: dF = e_i (x) g_a, one column at a time
-      const double ca = cf.a, c1 = cf.cF + cf.cM, c2 = cf.cT + cf.cX;
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const T gg = g[a][0] * g[a][0] + g[a][1] * g[a][1] + g[a][2] * g[a][2];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          const T w = k.FiT[i][0] * g[a][0] + k.FiT[i][1] * g[a][1] + k.FiT[i][2] * g[a][2];
-          const T z = k.F[i][0] * g[a][0] + k.F[i][1] * g[a][1] + k.F[i][2] * g[a][2];
-          out[a][i] = vol * (T(ca) * gg + T(c1) * w * z + T(c2) * w * w);
-        }
-      }
+        for (int i = 0; i < 3; ++i) cS[i * C4 + cp[a]] = out[a][i];
     }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int i = 0; i < 3; ++i) cS[(3 * a + i) * BE + e] = out[a][i];
+  };
+  if (tid < ne) run(ea);
+  if (tid + NT < ne) run(eb);
+  for (int e = tid + 2 * NT; e < ne; e += NT) {
+    load_elem(A, uint32_t(e0 + e), ea);
+    run(ea);
   }
   if (bad && A.flag) A.flag[0] = 1;
 
@@ -369,18 +470,15 @@ __global__ __launch_bounds__(NT) void k_elem_block(ElemArgs<T> A) {
   }
   __syncthreads();
 
-  // Phase 3: fixed-order node sums.
+  // Phase 3: node sums over contiguous ranges, in (element, vertex) order.
   double nrm = 0.0;
-  const uint16_t *ci = A.csr_idx + 4 * int64_t(e0);
   for (int l = tid; l < nl; l += NT) {
     const int beg = l == 0 ? 0 : int(A.csr_end[p0 + l - 1]);
     const int end = A.csr_end[p0 + l];
     T acc[3] = {T(0), T(0), T(0)};
     for (int q = beg; q < end; ++q) {
-      const int id = ci[q];
-      const int el = id >> 2, a = id & 3;
 #pragma unroll
-      for (int i = 0; i < 3; ++i) acc[i] += cS[(3 * a + i) * BE + el];
+      for (int i = 0; i < 3; ++i) acc[i] += cS[i * C4 + q];
     }
     const uint32_t w = A.nodes[p0 + l];
     if (w & 0x80000000u) {
@@ -406,12 +504,25 @@ __global__ __launch_bounds__(NT) void k_elem_merge(MergeArgs<T> A) {
   double nrm = 0.0;
   if (k < A.n_sh) {
     T acc[3] = {T(0), T(0), T(0)};
-    const int q1 = A.fx_ptr[k + 1];
-    for (int q = A.fx_ptr[k]; q < q1; ++q) {
-      const T *pp = A.partial + 3 * int64_t(A.fx_slot[q]);
-      acc[0] += pp[0];
-      acc[1] += pp[1];
-      acc[2] += pp[2];
+    const int q0 = A.fx_ptr[k], q1 = A.fx_ptr[k + 1];
+    // slots in groups of four: the four gathers are issued before the sums,
+    // which are still taken in slot order
+    for (int q = q0; q < q1; q += 4) {
+      int sl[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) sl[t] = q + t < q1 ? A.fx_slot[q + t] : -1;
+      T pv[4][3];
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) pv[t][i] = sl[t] >= 0 ? A.partial[3 * int64_t(sl[t]) + i] : T(0);
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (sl[t] >= 0) {
+          acc[0] += pv[t][0];
+          acc[1] += pv[t][1];
+          acc[2] += pv[t][2];
+        }
     }
     const uint32_t w = A.fx_node[k];
     finalize_node<T, OP>(w & NODE_MASK, (w >> 28) & 7u, acc, A.v, A.out, A.fext, A.s, nrm);
@@ -429,8 +540,7 @@ int launch(Ctx *c, int op, const T *G, const T *V, const T *u, const T *v, T *ou
   ElemArgs<T> A;
   A.G = G;
   A.V = V;
-  A.lconn = M.lconn;
-  A.csr_idx = M.csr_idx;
+  A.lcp = M.lcp;
   A.csr_end = M.csr_end;
   A.nodes = M.nodes;
   A.blk_elem = M.blk_elem;
@@ -453,20 +563,27 @@ int launch(Ctx *c, int op, const T *G, const T *V, const T *u, const T *v, T *ou
   const int grid = A.per_xcd > 0 ? 8 * A.per_xcd : M.nblk;
   size_t lds = size_t(6 * M.nl_max + 12 * M.be_max) * sizeof(T);
   lds = std::max(lds, size_t(NT / 64) * sizeof(double));
+  const bool m2 = c->mat.kind == NLE_MAT_M2;
+#define NLE_LAUNCH_BLOCK(OPV)                                                                 \
+  if (m2)                                                                                     \
+    hipLaunchKernelGGL((k_elem_block<T, OPV, NLE_MAT_M2>), dim3(grid), dim3(NT), lds, c->stream, A); \
+  else                                                                                        \
+    hipLaunchKernelGGL((k_elem_block<T, OPV, NLE_MAT_M1>), dim3(grid), dim3(NT), lds, c->stream, A);
   switch (op) {
     case OP_RES:
-      hipLaunchKernelGGL((k_elem_block<T, OP_RES>), dim3(grid), dim3(NT), lds, c->stream, A);
+      NLE_LAUNCH_BLOCK(OP_RES);
       break;
     case OP_JV:
-      hipLaunchKernelGGL((k_elem_block<T, OP_JV>), dim3(grid), dim3(NT), lds, c->stream, A);
+      NLE_LAUNCH_BLOCK(OP_JV);
       break;
     case OP_DIAG:
-      hipLaunchKernelGGL((k_elem_block<T, OP_DIAG>), dim3(grid), dim3(NT), lds, c->stream, A);
+      NLE_LAUNCH_BLOCK(OP_DIAG);
       break;
     default:
-      hipLaunchKernelGGL((k_elem_block<T, OP_ENERGY>), dim3(grid), dim3(NT), lds, c->stream, A);
+      NLE_LAUNCH_BLOCK(OP_ENERGY);
       break;
   }
+#undef NLE_LAUNCH_BLOCK
   *err = hipGetLastError();
   if (*err != hipSuccess) return 0;
   if (op == OP_ENERGY) return grid;

@@ -25,17 +25,18 @@ struct MatParams {
 
 // Element partition and geometry on the device.  Elements are renumbered
 // into blocks (contiguous ranges); every block owns a sorted list of the
-// nodes it touches ("slots"), a block-local connectivity, and a block-local
-// CSR listing, for each slot, the (element, vertex) contributions to sum.
+// nodes it touches ("slots") and a block-local connectivity.  Each
+// (element, vertex) contribution has a position in the block's slot-sorted
+// order (stored with the local ids), so the contributions of slot l occupy the contiguous range
+// [csr_end[l-1], csr_end[l]) of the block's contribution array.
 struct Mesh {
   int64_t n_nodes = 0, n_elems = 0;
   int32_t nblk = 0, be_max = 0, nl_max = 0;
   int64_t n_slots = 0, n_shared = 0, n_fx = 0;
   double *G64 = nullptr; float *G32 = nullptr;  // [9][n_elems] grad N_1..3 rows
   double *V64 = nullptr; float *V32 = nullptr;  // [n_elems]
-  uint16_t *lconn = nullptr;                    // [4][n_elems] slot-local vertex ids
-  uint16_t *csr_idx = nullptr;                  // [4 n_elems] 4*elem_local + vertex
-  uint16_t *csr_end = nullptr;                  // [n_slots] end offset within block
+  uint4 *lcp = nullptr;   // [n_elems] 4 slot-local vertex ids, 4 slot-sorted positions (u16)
+  uint16_t *csr_end = nullptr;                  // [n_slots] end of the slot's range
   uint32_t *nodes = nullptr;                    // [n_slots] id | mask<<28 | shared<<31
   int32_t *blk_elem = nullptr, *blk_node = nullptr;  // [nblk+1]
   uint32_t *fx_node = nullptr;                  // [n_shared] id | mask<<28

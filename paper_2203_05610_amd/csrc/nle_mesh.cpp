@@ -127,7 +127,7 @@ nle_status build_mesh(Ctx *c, int64_t nn, const double *X, int64_t ne, const int
   std::vector<int32_t> blk_node(nblk + 1, 0);
   std::vector<uint32_t> nodes;
   nodes.reserve(size_t(ne));
-  std::vector<uint16_t> lconn(4 * ne), csr_idx(4 * ne), csr_end;
+  std::vector<uint16_t> lcp(8 * ne), csr_end;
   std::vector<int32_t> loc(nn, -1), touch(nn, 0);
   std::vector<int32_t> cnt;
   int32_t be_max = 0, nl_max = 0;
@@ -151,16 +151,18 @@ nle_status build_mesh(Ctx *c, int64_t nn, const double *X, int64_t ne, const int
     for (int64_t k = e0; k < e1; ++k)
       for (int a = 0; a < 4; ++a) {
         int32_t l = loc[conn[4 * perm[k] + a]];
-        lconn[a * ne + k] = uint16_t(l);
+        lcp[8 * k + a] = uint16_t(l);
         cnt[l + 1] += 1;
       }
     for (int32_t l = 0; l < nl; ++l) cnt[l + 1] += cnt[l];
     for (int32_t l = 0; l < nl; ++l) csr_end.push_back(uint16_t(cnt[l + 1]));
+    // position of contribution (element, vertex) in the block's slot-sorted
+    // order; within a slot, increasing (element, vertex) order
     std::vector<int32_t> fillp(cnt.begin(), cnt.end() - 1);
-    for (int64_t k = e0; k < e1; ++k)  // increasing (element, vertex) order
+    for (int64_t k = e0; k < e1; ++k)
       for (int a = 0; a < 4; ++a) {
         int32_t l = loc[conn[4 * perm[k] + a]];
-        csr_idx[4 * e0 + fillp[l]++] = uint16_t(4 * (k - e0) + a);
+        lcp[8 * k + 4 + a] = uint16_t(fillp[l]++);
       }
     for (int32_t l = 0; l < nl; ++l) loc[bn[l]] = -1;
     be_max = std::max<int32_t>(be_max, int32_t(e1 - e0));
@@ -200,7 +202,7 @@ nle_status build_mesh(Ctx *c, int64_t nn, const double *X, int64_t ne, const int
       return fail(c, NLE_E_BADMESH, "node " + std::to_string(g) + " belongs to no element");
 
   // ---- LDS budget ---------------------------------------------------------------
-  const size_t lds64 = size_t(6 * nl_max + 12 * be_max) * 8;
+  const size_t lds64 = size_t(6 * nl_max + 12 * be_max) * 8;  // see the element kernel
   if (lds64 > c->lds_limit)
     return fail(c, NLE_E_UNSUPPORTED,
                 "element block needs " + std::to_string(lds64) + " B of LDS (limit " +
@@ -235,8 +237,7 @@ nle_status build_mesh(Ctx *c, int64_t nn, const double *X, int64_t ne, const int
   M.G32 = upload(c, G32, &herr);
   M.V64 = upload(c, Vp, &herr);
   M.V32 = upload(c, V32, &herr);
-  M.lconn = upload(c, lconn, &herr);
-  M.csr_idx = upload(c, csr_idx, &herr);
+  M.lcp = reinterpret_cast<uint4 *>(upload(c, lcp, &herr));
   M.csr_end = upload(c, csr_end, &herr);
   M.nodes = upload(c, nodes, &herr);
   M.blk_elem = upload(c, blk_elem, &herr);
