@@ -1,0 +1,333 @@
+#!/usr/bin/env python
+"""Benchmark: time-to-solve on the 64x64x4 Cook's membrane, and the Jacobian
+action's HBM roofline on the 256x256x16 Cook mesh (6.29M tetrahedra).
+
+One step = one full solve of the Cook workload over its load schedule with the
+chosen method (mesh upload, partition and material setup are done once,
+outside the timed region; every load step's linearizations are inside).
+Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--method ink_mixed]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+MU = 80.194
+RATIO = 5000.0
+GRID = (64, 64, 4)
+XL_GRID = (256, 256, 16)
+HBM_PEAK_GBS = 8000.0
+
+# method name -> (solver, precision, option overrides)
+METHODS = {
+    "nk_fp64": ("nk", "fp64", {}),
+    "nk_mixed": ("nk", "mixed", {}),
+    "ink_fp64": ("ink", "fp64", {}),
+    "ink_mixed": ("ink", "mixed", {}),
+    "bfgs_ib_fp64": ("bfgs", "fp64", {"h0": "ksp", "qn_m": 10}),
+    "bfgs_ib_mixed": ("bfgs", "mixed", {"h0": "ksp", "qn_m": 10}),
+    "bfgs_b_mixed": ("bfgs", "mixed", {"h0": "preonly", "qn_m": 10}),
+}
+
+
+def load_schedule():
+    from synthetic import fields
+
+    return fields.cook_load_schedule(16.0)
+
+
+def run_solve(ctx, u, method, schedule):
+    from paper_2203_05610_amd import problems
+
+    solver, prec, kw = METHODS[method]
+    opts = problems.make_opts(solver, prec, **dict(kw))
+    u.zero_()
+    reps = problems.solve_schedule(ctx, u, solver, opts, schedule)
+    return problems.schedule_ok(reps, schedule), reps
+
+
+def summarize(reps):
+    from paper_2203_05610_amd import problems
+
+    return {
+        "ok": problems.schedule_ok(reps, load_schedule()),
+        "steps": [f"{r['load_scale']:g}:{r['status_name']}" for r in reps],
+        "nit": [r["nit"] for r in reps],
+        "lit": [int(r["lit_total"]) for r in reps],
+        "n_jv": int(sum(r["n_jv"] for r in reps)),
+        "t_ms": [round(r["t_ms"], 2) for r in reps],
+    }
+
+
+def jv_roofline(nl, torch, reps: int):
+    """FP32 and FP64 Jacobian action on the 6.29M-tet Cook mesh; HIP events
+    around `reps` back-to-back calls on the context's stream."""
+    import numpy as np
+
+    import synthetic as syn
+
+    mesh = syn.cook_mesh(*XL_GRID, with_faces=False)
+    ctx = nl.Context(0)
+    nl.nle_upload_mesh(ctx, mesh.X, mesh.conn)
+    nl.nle_set_material(ctx, nl.NLE_MAT_M1, [MU, RATIO * MU])
+    d = mesh.dirichlet_dofs("clamp")
+    nl.nle_set_dirichlet(ctx, d, np.zeros(d.size))
+    n = 3 * mesh.n_nodes
+    g = torch.Generator(device="cuda").manual_seed(1234)
+    u = (torch.tensor(mesh.X, device="cuda") * 1e-3).reshape(-1).contiguous()
+    nl.nle_linearize(ctx, u, nl.NLE_FP32)
+    out = {}
+    for prec, dt, s in ((nl.NLE_FP32, torch.float32, 4), (nl.NLE_FP64, torch.float64, 8)):
+        v = torch.randn(n, dtype=dt, device="cuda", generator=g)
+        y = torch.empty_like(v)
+        for _ in range(10):
+            nl.nle_jv(ctx, v, y, prec)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        ctx.stream.synchronize()
+        e0.record(ctx.stream)
+        for _ in range(reps):
+            nl.nle_jv(ctx, v, y, prec)
+        e1.record(ctx.stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        balg = mesh.n_elems * (16 + 10 * s) + mesh.n_nodes * 9 * s
+        out["fp32" if s == 4 else "fp64"] = {
+            "ms": ms, "bytes": balg, "gbs": balg / ms / 1e6,
+            "n_elems": mesh.n_elems, "n_nodes": mesh.n_nodes,
+        }
+    out["partition"] = nl.nle_partition_info(ctx)
+    ctx.close()
+    return out
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("nle_elem.hip",):
+        with open(os.path.join(ROOT, "paper_2203_05610_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(ms_bytes):
+    """HBM bytes per Jv from the committed rocprofv3 counter summary, if it was
+    taken on the current element-kernel source; otherwise None."""
+    path = os.path.join(ROOT, "profiles", "jv_cookxl_fp32_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return t.get("hbm_bytes_per_jv")
+
+
+CPU_SNIPPET = r"""
+import os, sys, time, json
+sys.path.insert(0, {root!r})
+import numpy as np
+import synthetic as syn
+from oracle import fem
+import scipy.sparse.linalg as spla
+m = syn.cook_mesh({nx}, {ny}, {nz})
+P = fem.cook_problem(m, mu={mu}, lam={lam}, tau=1.0)
+u = P.lift(np.zeros(P.n_dofs))
+t0 = time.perf_counter()
+its = 0
+r = P.residual(u, 1.0)
+while its < {its}:
+    K = P.stiffness(u)
+    du = spla.splu(K.tocsc()).solve(-r)
+    u = u + du
+    r = P.residual(u, 1.0)
+    its += 1
+dt = time.perf_counter() - t0
+print(json.dumps(dict(seconds=dt, iterations=its)))
+"""
+
+
+def cpu_baseline(newton_iterations: int, sample_its: int = 1):
+    """The oracle's exact Newton (assembled complex-step tangent + sparse LU)
+    on the same 64x64x4 mesh, one thread; a bounded sample of `sample_its`
+    Newton iterations at the first load step, scaled to the whole schedule by
+    the NK iteration count of the GPU run."""
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    code = CPU_SNIPPET.format(root=ROOT, nx=GRID[0], ny=GRID[1], nz=GRID[2], mu=MU,
+                              lam=RATIO * MU, its=sample_its)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                       timeout=600)
+    if r.returncode != 0:
+        return {"error": r.stderr[-400:]}
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    per_it = d["seconds"] / d["iterations"]
+    return {
+        "value": per_it * newton_iterations,
+        "unit": "s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"{d['iterations']} exact-Newton iterations (assembly + splu) on the "
+                   f"64x64x4 mesh at tau=1, {per_it:.2f} s each, scaled by the "
+                   f"{newton_iterations} Newton iterations of the GPU NK-FP64 schedule"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--method", default="ink_mixed", choices=sorted(METHODS))
+    ap.add_argument("--baseline", default="nk_fp64", choices=sorted(METHODS))
+    ap.add_argument("--compare", default="", help="comma-separated extra methods, run once each")
+    ap.add_argument("--jv-reps", type=int, default=200)
+    ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-baseline", action="store_true")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only the Jv roofline phase (plus a 256 MB copy kernel used to "
+                         "calibrate HBM byte counters); for profiling runs")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "path is a design in DESIGN.md, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synthetic as syn
+    from paper_2203_05610_amd import nlelast as nl
+    from paper_2203_05610_amd import problems
+
+    if args.roofline_only:
+        jv = jv_roofline(nl, torch, args.jv_reps)
+        x = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        z = torch.empty_like(x)
+        for _ in range(5):
+            torch.neg(x, out=z)  # plain copy kernel: 256 MiB read + 256 MiB written
+        torch.cuda.synchronize()
+        print(json.dumps({"roofline_only": True, "jv": jv}))
+        return
+
+    schedule = load_schedule()
+    t_setup = time.perf_counter()
+    mesh = syn.cook_mesh(*GRID)
+    ctx = nl.Context(0)
+    problems.setup_cook(ctx, mesh, MU, RATIO * MU, 1.0)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    u = torch.zeros(3 * mesh.n_nodes, dtype=torch.float64, device="cuda")
+
+    print(f"[bench] setup {t_setup:.2f}s; warmup {args.warmup} x {args.method}", file=sys.stderr,
+          flush=True)
+    for _ in range(args.warmup):
+        run_solve(ctx, u, args.method, schedule)
+    torch.cuda.synchronize()
+    runs = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ok, reps = run_solve(ctx, u, args.method, schedule)
+        runs.append(summarize(reps))
+        print(f"[bench] step {k}: ok={ok} nit={runs[-1]['nit']}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1000.0 / max(args.steps, 1)
+    all_ok = all(r["ok"] for r in runs)
+
+    extra = {}
+    base = None
+    if not args.no_baseline and args.baseline != args.method:
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        ok, reps = run_solve(ctx, u, args.baseline, schedule)
+        torch.cuda.synchronize()
+        base = {"method": args.baseline, "seconds": time.perf_counter() - tb, **summarize(reps)}
+        print(f"[bench] baseline {args.baseline}: {base['seconds']:.2f}s ok={base['ok']}",
+              file=sys.stderr, flush=True)
+    for m in [x for x in args.compare.split(",") if x]:
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        ok, reps = run_solve(ctx, u, m, schedule)
+        torch.cuda.synchronize()
+        extra[m] = {"seconds": time.perf_counter() - tb, **summarize(reps)}
+        print(f"[bench] compare {m}: {extra[m]['seconds']:.2f}s ok={extra[m]['ok']}",
+              file=sys.stderr, flush=True)
+    ctx.close()
+
+    roof = None
+    jv = None
+    if not args.no_roofline:
+        jv = jv_roofline(nl, torch, args.jv_reps)
+        f = jv["fp32"]
+        traffic = measured_traffic(f["bytes"])
+        roof = {
+            "bound": "hbm",
+            "achieved": round(f["gbs"], 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(f["gbs"] / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": "nle_jv FP32 (k_elem_block<float,JV> + k_elem_merge<float,JV>)",
+            "workload": "Cook 256x256x16, 6,291,456 P1 tets, 1,122,833 nodes",
+            "bytes_per_launch": f["bytes"],
+            "ms_per_launch": round(f["ms"], 5),
+            "fp64": {"achieved": round(jv["fp64"]["gbs"], 1), "ms_per_launch":
+                     round(jv["fp64"]["ms"], 5), "bytes_per_launch": jv["fp64"]["bytes"],
+                     "frac": round(jv["fp64"]["gbs"] / HBM_PEAK_GBS, 4)},
+        }
+        print(f"[bench] Jv roofline fp32 {f['gbs']:.0f} GB/s", file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu:
+        nit_nk = sum(base["nit"]) if base else sum(runs[0]["nit"])
+        cpu = cpu_baseline(max(nit_nk, 1))
+
+    value = ms_per_step / 1000.0
+    line = {
+        "metric": "time-to-solve at rel. residual 1e-8 (NK-FP64 vs iNK/BFGS mixed); Jv HBM GB/s",
+        "value": round(value, 4),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if METHODS[args.method][1] == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "Cook's membrane 64x64x4 hexes -> 98,304 P1 tets, 63,375 dofs, "
+                        "lambda/mu=5000, traction schedule " + ",".join(f"{s:g}" for s in schedule),
+            "method": args.method,
+            "precision": "FP32 inner (tangent, Jacobi, Krylov, L-BFGS vectors), FP64 residual/state"
+            if METHODS[args.method][1] == "mixed" else "FP64",
+            "preconditioner": "Jacobi",
+            "parallelism": "1 GPU",
+        },
+        "solved": all_ok,
+        "runs": runs,
+        "setup_s": round(t_setup, 3),
+        "gpu_baseline": base,
+        "speedup_vs_gpu_baseline": (round(base["seconds"] / value, 3)
+                                    if base and base["ok"] and all_ok else None),
+        "compare": extra or None,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -51,14 +51,42 @@ def make_opts(method: str, precision: str = "fp64", **over) -> nl.nle_solver_opt
     return o
 
 
-def solve_schedule(ctx: nl.Context, u, method: str, opts, scales, hist_cap: int = 4096):
-    """Solve at each load scale in turn, warm-started; returns the reports."""
+def solve_schedule(ctx: nl.Context, u, method: str, opts, scales, hist_cap: int = 4096,
+                   max_cuts: int = 8, start_scale: float = 0.0):
+    """Solve at each load scale in turn, warm-started from the previous step.
+
+    If a step does not converge (an element inverts, NaN, or the iteration
+    limit), the state is restored to the last converged step and the load
+    increment is halved (at most `max_cuts` times in total); the failed
+    attempts stay in the returned reports (their time is part of the solve).
+    Each report carries 'load_scale' and 'accepted'.
+    """
     reps = []
-    for s in scales:
+    targets = [float(x) for x in scales]
+    backup = u.clone()
+    s_prev = float(start_scale)
+    cuts = 0
+    i = 0
+    while i < len(targets):
+        s = targets[i]
         nl.nle_set_load_scale(ctx, s)
         st, rep = SOLVERS[method](ctx, u, opts, hist_cap)
         rep["load_scale"] = s
+        rep["accepted"] = st == nl.NLE_OK
         reps.append(rep)
-        if st != nl.NLE_OK:
+        if st == nl.NLE_OK:
+            backup.copy_(u)
+            s_prev = s
+            i += 1
+            continue
+        u.copy_(backup)
+        if cuts >= max_cuts:
             break
+        cuts += 1
+        targets.insert(i, 0.5 * (s_prev + s))
     return reps
+
+
+def schedule_ok(reps, scales) -> bool:
+    acc = [r["load_scale"] for r in reps if r["accepted"]]
+    return bool(acc) and abs(acc[-1] - float(scales[-1])) == 0.0
