@@ -75,8 +75,10 @@ typedef int32_t nle_status;
 #define NLE_INK 1  /* inexact NK, Eisenstat-Walker forcing (Sec. 3, App. A) */
 #define NLE_BFGS 2 /* limited-memory BFGS (Sec. 3, App. A)                  */
 
-#define NLE_KSP_GMRES 0 /* right-preconditioned GMRES(restart)             */
-#define NLE_KSP_CG 1    /* preconditioned conjugate gradients (SPD tangent) */
+#define NLE_KSP_GMRES 0  /* right-preconditioned GMRES(restart)             */
+#define NLE_KSP_CG 1     /* preconditioned conjugate gradients (SPD tangent) */
+#define NLE_KSP_MINRES 2 /* preconditioned MINRES (symmetric, possibly
+                            indefinite tangent; SPD preconditioner)        */
 
 #define NLE_ORTH_MGS 0  /* modified Gram-Schmidt (the paper's choice)       */
 #define NLE_ORTH_CGS2 1 /* classical Gram-Schmidt, two passes               */
@@ -105,7 +107,7 @@ typedef struct {
 /* Solver options: the PETSc options of App. A as fields. */
 typedef struct {
   int32_t precision;  /* NLE_PREC_FP64 / NLE_PREC_MIXED                      */
-  int32_t ksp_type;   /* NLE_KSP_GMRES / NLE_KSP_CG                           */
+  int32_t ksp_type;   /* NLE_KSP_GMRES / NLE_KSP_CG / NLE_KSP_MINRES          */
   int32_t orth;       /* GMRES orthogonalisation                              */
   int32_t pc;         /* NLE_PC_JACOBI / NLE_PC_NONE                          */
   int32_t restart;    /* GMRES restart length; <= 0 means ksp_max_it          */

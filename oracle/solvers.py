@@ -132,6 +132,62 @@ def cg(matvec: Callable, b: np.ndarray, precond: Optional[Callable] = None,
     return x, k, hist, hist[-1] <= ttol
 
 
+def minres(matvec: Callable, b: np.ndarray, precond: Optional[Callable] = None,
+           rtol: float = 1e-6, atol: float = 1e-10, max_it: int = 10000):
+    """Preconditioned MINRES (Paige & Saunders) for symmetric, possibly
+    indefinite A with an SPD preconditioner M, from a zero initial guess.
+
+    The k-th iterate minimises ||b - A x||_{M^-1} over the Krylov space
+    K_k(M^-1 A, M^-1 b).  The stopping test uses the true residual
+    ||b - A x||_2 <= max(rtol ||b||, atol), evaluated explicitly here.
+    Returns (x, iterations, residual-norm history, converged flag).
+    """
+    M = precond if precond is not None else (lambda v: v)
+    n = b.size
+    x = np.zeros(n)
+    bnorm = float(np.linalg.norm(b))
+    ttol = max(rtol * bnorm, atol)
+    hist = [bnorm]
+    if bnorm <= ttol:
+        return x, 0, hist, True
+    r1 = b.copy()
+    y = M(r1)
+    beta1 = float(np.sqrt(np.dot(r1, y)))
+    oldb, beta, dbar, epsln, phibar = 0.0, beta1, 0.0, 0.0, beta1
+    cs, sn = -1.0, 0.0
+    w = np.zeros(n)
+    w2 = np.zeros(n)
+    r2 = r1.copy()
+    k = 0
+    while k < max_it:
+        k += 1
+        v = y / beta
+        y = matvec(v)
+        if k >= 2:
+            y = y - (beta / oldb) * r1
+        alfa = float(np.dot(v, y))
+        y = y - (alfa / beta) * r2
+        r1, r2 = r2, y
+        y = M(r2)
+        oldb, beta = beta, float(np.sqrt(np.dot(r2, y)))
+        oldeps = epsln
+        delta = cs * dbar + sn * alfa
+        gbar = sn * dbar - cs * alfa
+        epsln = sn * beta
+        dbar = -cs * beta
+        gamma = max(float(np.hypot(gbar, beta)), 1e-300)
+        cs, sn = gbar / gamma, beta / gamma
+        phi = cs * phibar
+        phibar = sn * phibar
+        w1, w2 = w2, w
+        w = (v - oldeps * w1 - delta * w2) / gamma
+        x = x + phi * w
+        hist.append(float(np.linalg.norm(b - matvec(x))))
+        if hist[-1] <= ttol or beta == 0.0:
+            break
+    return x, k, hist, hist[-1] <= ttol
+
+
 # ---------------------------------------------------------------- EW
 def ew_forcing(k: int, rnorm: float, rnorm_prev: float, linres_prev: float, eta_prev: float,
                version: int = 1, rtol0: float = 0.1, rtolmax: float = 0.1,
@@ -218,7 +274,7 @@ def newton_krylov(residual: Callable, linearize: Callable, u0: np.ndarray, *,
             lrtol, latol = eta, 1e-14
         else:
             eta, lrtol, latol = ksp_rtol, ksp_rtol, ksp_atol
-        solver = gmres if ksp == "gmres" else cg
+        solver = {"gmres": gmres, "cg": cg, "minres": minres}[ksp]
         kw = dict(restart=restart) if ksp == "gmres" else {}
         du, its, _, _ = solver(matvec, -r, prec, rtol=lrtol, atol=latol, max_it=ksp_max_it, **kw)
         linres_prev = float(np.linalg.norm(r + matvec(du)))

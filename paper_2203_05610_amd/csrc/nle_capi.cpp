@@ -153,6 +153,12 @@ nle_status nle_create(nle_ctx **out, int32_t device, void *stream, const nle_all
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess &&
       lds > 0)
     c->lds_limit = size_t(lds);
+  if (hipStreamCreateWithFlags(&c->kstream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_a, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_b, hipEventDisableTiming) != hipSuccess) {
+    delete c;
+    return NLE_E_HIP;
+  }
   c->dscal = static_cast<double *>(dalloc(c, 64 * 8));
   c->dflag = static_cast<int32_t *>(dalloc(c, 64 * 4));
   if (!c->dscal || !c->dflag || hipHostMalloc(&c->hpin, 4096) != hipSuccess) {
@@ -178,6 +184,8 @@ void nle_destroy(nle_ctx *ctx) {
   Ctx *c = reinterpret_cast<Ctx *>(ctx);
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
+  if (c->kstream) (void)hipStreamSynchronize(c->kstream);
+  drop_graph(c);
   for (void *p : c->mesh_allocs) dfree(c, p);
   for (void *p : c->ws_allocs) dfree(c, p);
   dfree(c, c->red);
@@ -186,6 +194,12 @@ void nle_destroy(nle_ctx *ctx) {
   dfree(c, c->dir_dofs);
   dfree(c, c->dir_vals);
   if (c->hpin) (void)hipHostFree(c->hpin);
+  if (c->ev_a) (void)hipEventDestroy(c->ev_a);
+  if (c->ev_b) (void)hipEventDestroy(c->ev_b);
+  if (c->kstream) {
+    (void)hipStreamSynchronize(c->kstream);
+    (void)hipStreamDestroy(c->kstream);
+  }
   delete c;
 }
 
@@ -205,6 +219,7 @@ nle_status nle_upload_mesh(nle_ctx *ctx, int64_t n_nodes, const double *X, int64
     if (npe != 4) return fail(c, NLE_E_UNSUPPORTED, "only 4-node (P1) tetrahedra are supported");
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, NLE_E_HIP, "hipSetDevice failed");
     c->has_mesh = false;
+    drop_graph(c);
     nle_status s = build_mesh(c, n_nodes, X, n_elems, conn);
     if (s != NLE_OK) return s;
     dfree(c, c->dir_dofs);
@@ -238,6 +253,7 @@ nle_status nle_set_material(nle_ctx *ctx, int32_t kind, const double *p, int32_t
   if (!(m.mu > 0.0) || !std::isfinite(m.lam) || !std::isfinite(m.cvol))
     return fail(c, NLE_E_INVAL, "material parameters must be finite with mu > 0");
   m.kappa = m.lam + 2.0 * m.mu / 3.0;
+  drop_graph(c);
   c->mat = m;
   c->has_mat = true;
   c->lin64 = c->lin32 = false;

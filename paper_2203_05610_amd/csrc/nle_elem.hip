@@ -39,6 +39,11 @@ struct ElemArgs {
   double *red;        // per-workgroup partial sums (residual norm^2 / energy)
   int32_t *flag;      // set to 1 when some det F <= 0
   const int32_t *skip;// if non-null and *skip != 0 the launch does nothing
+  // Jv epilogue (optional): out = J v - c w with c = *ep_coef, and partial sums
+  // of v.out written to ep_red (one per workgroup of each kernel)
+  const T *ep_w;
+  const double *ep_coef;
+  double *ep_red;
   MatParams mp;
 };
 
@@ -55,6 +60,9 @@ struct MergeArgs {
   double s;
   double *red;
   const int32_t *skip;
+  const T *ep_w;
+  const double *ep_coef;
+  double *ep_red;
 };
 
 __device__ __forceinline__ int block_id(int nblk, int per_xcd) {
@@ -245,7 +253,7 @@ __device__ __forceinline__ double energy_density(const Kin<T> &k, const T H[3][3
 template <typename T, int OP>
 __device__ __forceinline__ void finalize_node(uint32_t g, uint32_t mk, const T acc[3], const T *v,
                                               T *out, const double *fext, double s,
-                                              double &nrm) {
+                                              double &nrm, const T *epw, T epc) {
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     const int64_t d = 3 * int64_t(g) + i;
@@ -255,7 +263,11 @@ __device__ __forceinline__ void finalize_node(uint32_t g, uint32_t mk, const T a
       out[d] = T(r);
       nrm += r * r;
     } else if (OP == OP_JV) {
-      out[d] = fixed ? v[d] : acc[i];
+      const T vd = v[d];
+      T y = fixed ? vd : acc[i];
+      if (epw) y -= epc * epw[d];
+      out[d] = y;
+      nrm += double(vd * y);
     } else if (OP == OP_DIAG) {
       out[d] = fixed ? T(1) : acc[i];
     }
@@ -410,6 +422,7 @@ __global__ __launch_bounds__(NT) void k_elem_block(ElemArgs<T> A) {
   const int b = block_id(A.nblk, A.per_xcd);
   if (b >= A.nblk) {  // padding workgroup of the XCD remap: contributes nothing
     if ((OP == OP_RES || OP == OP_ENERGY) && threadIdx.x == 0) A.red[blockIdx.x] = 0.0;
+    if (OP == OP_JV && A.ep_red && threadIdx.x == 0) A.ep_red[blockIdx.x] = 0.0;
     return;
   }
   if (A.skip && A.skip[0] != 0) return;
@@ -472,6 +485,7 @@ __global__ __launch_bounds__(NT) void k_elem_block(ElemArgs<T> A) {
 
   // Phase 3: node sums over contiguous ranges, in (element, vertex) order.
   double nrm = 0.0;
+  const T epc = A.ep_coef ? T(A.ep_coef[0]) : T(0);
   for (int l = tid; l < nl; l += NT) {
     const int beg = l == 0 ? 0 : int(A.csr_end[p0 + l - 1]);
     const int end = A.csr_end[p0 + l];
@@ -487,12 +501,13 @@ __global__ __launch_bounds__(NT) void k_elem_block(ElemArgs<T> A) {
       pp[1] = acc[1];
       pp[2] = acc[2];
     } else {
-      finalize_node<T, OP>(w & NODE_MASK, (w >> 28) & 7u, acc, A.v, A.out, A.fext, A.s, nrm);
+      finalize_node<T, OP>(w & NODE_MASK, (w >> 28) & 7u, acc, A.v, A.out, A.fext, A.s, nrm,
+                           A.ep_w, epc);
     }
   }
-  if (OP == OP_RES) {
+  if (OP == OP_RES || (OP == OP_JV && A.ep_red)) {
     const double s = block_sum(nrm, rs);
-    if (tid == 0) A.red[blockIdx.x] = s;
+    if (tid == 0) (OP == OP_RES ? A.red : A.ep_red)[blockIdx.x] = s;
   }
 }
 
@@ -525,11 +540,12 @@ __global__ __launch_bounds__(NT) void k_elem_merge(MergeArgs<T> A) {
         }
     }
     const uint32_t w = A.fx_node[k];
-    finalize_node<T, OP>(w & NODE_MASK, (w >> 28) & 7u, acc, A.v, A.out, A.fext, A.s, nrm);
+    finalize_node<T, OP>(w & NODE_MASK, (w >> 28) & 7u, acc, A.v, A.out, A.fext, A.s, nrm,
+                         A.ep_w, A.ep_coef ? T(A.ep_coef[0]) : T(0));
   }
-  if (OP == OP_RES) {
+  if (OP == OP_RES || (OP == OP_JV && A.ep_red)) {
     const double s = block_sum(nrm, rs);
-    if (threadIdx.x == 0) A.red[blockIdx.x] = s;
+    if (threadIdx.x == 0) (OP == OP_RES ? A.red : A.ep_red)[blockIdx.x] = s;
   }
 }
 
@@ -559,6 +575,9 @@ int launch(Ctx *c, int op, const T *G, const T *V, const T *u, const T *v, T *ou
   A.red = red;
   A.flag = c->dflag;
   A.skip = c->elem_skip;
+  A.ep_w = static_cast<const T *>(c->ep.w);
+  A.ep_coef = c->ep.coef;
+  A.ep_red = op == OP_JV ? c->ep.red : nullptr;
   A.mp = c->mat;
   const int grid = A.per_xcd > 0 ? 8 * A.per_xcd : M.nblk;
   size_t lds = size_t(6 * M.nl_max + 12 * M.be_max) * sizeof(T);
@@ -587,7 +606,7 @@ int launch(Ctx *c, int op, const T *G, const T *V, const T *u, const T *v, T *ou
   *err = hipGetLastError();
   if (*err != hipSuccess) return 0;
   if (op == OP_ENERGY) return grid;
-  int nred = (op == OP_RES) ? grid : 0;
+  int nred = (op == OP_RES || (op == OP_JV && c->ep.red)) ? grid : 0;
   if (M.n_shared > 0) {
     MergeArgs<T> B;
     B.fx_node = M.fx_node;
@@ -601,6 +620,9 @@ int launch(Ctx *c, int op, const T *G, const T *V, const T *u, const T *v, T *ou
     B.s = c->load_scale;
     B.red = red ? red + grid : nullptr;
     B.skip = c->elem_skip;
+    B.ep_w = static_cast<const T *>(c->ep.w);
+    B.ep_coef = c->ep.coef;
+    B.ep_red = (op == OP_JV && c->ep.red) ? c->ep.red + grid : nullptr;
     const int g2 = int((M.n_shared + NT - 1) / NT);
     switch (op) {
       case OP_RES:
@@ -609,6 +631,7 @@ int launch(Ctx *c, int op, const T *G, const T *V, const T *u, const T *v, T *ou
         break;
       case OP_JV:
         hipLaunchKernelGGL((k_elem_merge<T, OP_JV>), dim3(g2), dim3(NT), 0, c->stream, B);
+        if (c->ep.red) nred += g2;
         break;
       default:
         hipLaunchKernelGGL((k_elem_merge<T, OP_DIAG>), dim3(g2), dim3(NT), 0, c->stream, B);

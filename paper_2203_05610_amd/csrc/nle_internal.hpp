@@ -56,7 +56,9 @@ void dfree(Ctx *c, void *p);
 
 struct Ctx {
   int32_t device = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;   // the caller's stream (current launch stream)
+  hipStream_t kstream = nullptr;  // library stream for captured Krylov loops
+  hipEvent_t ev_a = nullptr, ev_b = nullptr;
   nle_allocator al{};
   bool custom_alloc = false;
   std::string err;
@@ -97,8 +99,20 @@ struct Ctx {
   double *dscal = nullptr;   // device scalars
   int32_t *dflag = nullptr;  // device flags: [0] inverted element
   const int32_t *elem_skip = nullptr;  // Krylov done flag seen by element kernels
+  // Jv epilogue used by the Krylov loops: out = J v - (*coef) w; partial sums
+  // of v.out to red (block partials, then merge partials)
+  struct {
+    const void *w = nullptr;
+    const double *coef = nullptr;
+    double *red = nullptr;
+  } ep;
   double *hpin = nullptr;    // pinned host scalars
   std::vector<void *> ctx_allocs;
+
+  // captured Krylov chunk (see drop_graph)
+  std::vector<uint64_t> gkey;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
 
   // solver workspace (grown on demand)
   std::vector<void *> ws_allocs;
@@ -107,6 +121,7 @@ struct Ctx {
 };
 
 nle_status fail(Ctx *c, nle_status code, const std::string &msg);
+void drop_graph(Ctx *c);
 #define NLE_HIP(c, call)                                                        \
   do {                                                                          \
     hipError_t e_ = (call);                                                     \
@@ -124,7 +139,8 @@ nle_status upload_node_masks(Ctx *c);
 //  OP_JV : u = linearization state (prec), v = direction, out = J v
 //  OP_DIAG: u = ulin64, out = diag (double)
 //  OP_ENERGY: u = double state, red gets per-workgroup sum V Psi
-// Returns the number of reduction partials written to red (0 if none).
+// Returns the number of reduction partials written to red (0 if none); for
+// OP_JV with c->ep.red set, the number of v.(Jv) partials written there.
 int elem_apply(Ctx *c, int op, int prec, const void *u, const void *v, void *out, double *red,
                hipError_t *err);
 int elem_red_capacity(const Ctx *c);
@@ -147,21 +163,39 @@ hipError_t reduce_scalars(Ctx *c, const double *red, int np, int count, double *
 hipError_t vec_mul(Ctx *c, int prec, const void *a, const void *b, void *y, int64_t n);
 hipError_t vec_recip(Ctx *c, const double *d, double *dinv, int64_t n);
 
-// CG kernels
+// CG kernels (no per-iteration host arguments: a chunk of iterations can be
+// captured as a graph)
 struct CgArgs {
   int prec;
   int64_t n;
   void *x, *r, *z, *p, *Ap;
   const void *dinv;   // may be null (no preconditioner)
-  double *red_a;      // partials of p.Ap
+  double *red_a;      // partials of p.Ap (from the Jacobian-action epilogue)
   int np_a;
   double *red_b;      // partials of (r.z, r.r), 2 x VGRID_MAX
   double *scal;       // device scalars
-  int32_t *flag;      // [0] done (1 conv, 2 breakdown), [1] iterations
+  int32_t *flag;      // [0] state (1 converged, 2 breakdown, 3 NaN, 5 limit), [1] its
 };
-hipError_t cg_start(Ctx *c, const CgArgs &a, const void *b, double rtol, double atol);
-hipError_t cg_update(Ctx *c, const CgArgs &a, int it);
-hipError_t cg_direction(Ctx *c, const CgArgs &a, int it);
+hipError_t cg_start(Ctx *c, const CgArgs &a, const void *b, double rtol, double atol, int max_it);
+hipError_t cg_update(Ctx *c, const CgArgs &a);
+hipError_t cg_direction(Ctx *c, const CgArgs &a);
+
+// MINRES kernels
+struct MinresArgs {
+  int prec;
+  int64_t n;
+  void *x, *r1, *r2, *y, *v, *av, *wa, *wb, *za, *zb, *r;
+  const void *dinv;
+  double *red_a;  // partials of v.(A v - coef r1) from the Jacobian-action epilogue
+  int np_a;
+  double *red_b;  // partials of t.(M^-1 t)
+  double *red_r;  // partials of r.r
+  double *scal;
+  int32_t *flag;
+};
+hipError_t mr_start(Ctx *c, const MinresArgs &a, const void *b, double rtol, double atol,
+                    int max_it);
+hipError_t mr_iterate(Ctx *c, const MinresArgs &a);
 
 // GMRES kernels
 struct GmresArgs {

@@ -24,6 +24,16 @@ nle_status residual_norm(Ctx *c, const double *u, double *r, double *rn, bool *i
 nle_status linearize(Ctx *c, const double *u, int prec);
 nle_status jv(Ctx *c, const void *v, void *y, int prec);
 
+// The captured Krylov chunk bakes in kernel arguments (pointers, sizes and
+// material parameters); it is dropped whenever any of them may change.
+void drop_graph(Ctx *c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+  c->gkey.clear();
+}
+
 namespace {
 
 constexpr double GOLDEN = 1.6180339887498949;
@@ -42,6 +52,7 @@ struct Carver {
 nle_status ensure_ws(Ctx *c, size_t bytes) {
   if (c->ws_bytes >= bytes) return NLE_OK;
   NLE_HIP(c, hipStreamSynchronize(c->stream));
+  drop_graph(c);
   for (void *p : c->ws_allocs) dfree(c, p);
   c->ws_allocs.clear();
   c->ws = dalloc(c, bytes);
@@ -69,9 +80,49 @@ inline size_t esz(int prec) { return prec == NLE_FP32 ? 4 : 8; }
 size_t ksp_bytes(const KspOpts &o, int64_t n, int prec) {
   const size_t v = (size_t(n) * esz(prec) + 255) & ~size_t(255);
   if (o.type == NLE_KSP_CG) return 4 * v + 4096;
+  if (o.type == NLE_KSP_MINRES) return 11 * v + 4096;
   const int m = o.restart > 0 ? std::min(o.restart, o.max_it) : o.max_it;
   return size_t(m + 3) * v + size_t((m + 1) * m + 4 * m + 8) * 8 +
          size_t(m + 3) * VGRID_MAX * 8 + size_t(8 + 2 * (m + 1)) * 8 + 8 * 256;
+}
+
+// Run `iteration` (which queues one Krylov iteration on c->stream) until the
+// device flag leaves 0: chunks of `chunk` iterations are captured once as a
+// graph and replayed; the flag is read after each replay.
+template <typename F>
+nle_status run_chunks(Ctx *c, const std::vector<uint64_t> &key, int chunk, int max_it,
+                      int32_t *flag, F &&iteration) {
+  if (c->gkey != key) {
+    drop_graph(c);
+    NLE_HIP(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < chunk && e == hipSuccess; ++i) e = iteration();
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(c, NLE_E_HIP, std::string("graph capture: ") +
+                                    hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return fail(c, NLE_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    c->graph = g;
+    c->gexec = ex;
+    c->gkey = key;
+  }
+  for (int done = 0; done < max_it; done += chunk) {
+    NLE_HIP(c, hipGraphLaunch(c->gexec, c->stream));
+    nle_status s = read_scalars(c, flag, 8);
+    if (s != NLE_OK) return s;
+    int32_t f;
+    std::memcpy(&f, c->hpin, 4);
+    if (f != 0) break;
+  }
+  return NLE_OK;
 }
 
 // Solve J x = b (J = tangent at the current linearization, precision prec)
@@ -84,58 +135,117 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
   if (o.pc == NLE_PC_JACOBI)
     dinv = prec == NLE_FP32 ? static_cast<const void *>(c->dinv32)
                             : static_cast<const void *>(c->dinv64);
+  const void *ulin = prec == NLE_FP32 ? static_cast<const void *>(c->ulin32)
+                                      : static_cast<const void *>(c->ulin64);
   int32_t *flag = c->dflag + 8;
   const int check = std::max(1, o.check_every);
   R->its = 0;
   R->flag = 0;
-  if (o.type == NLE_KSP_CG) {
-    CgArgs a;
-    a.prec = prec;
-    a.n = n;
-    a.x = x;
-    a.r = W.take(vb);
-    a.z = W.take(vb);
-    a.p = W.take(vb);
-    a.Ap = W.take(vb);
-    a.dinv = dinv;
-    a.red_a = c->red;
-    a.red_b = c->red + VGRID_MAX;
-    a.scal = c->dscal;
-    a.flag = flag;
-    a.np_a = vgrid(n);
-    NLE_HIP(c, cg_start(c, a, b, o.rtol, o.atol));
-    c->elem_skip = flag;
-    int it = 0;
-    for (; it < o.max_it; ++it) {
-      hipError_t e;
-      elem_apply(c, OP_JV, prec, prec == NLE_FP32 ? (const void *)c->ulin32 : (const void *)c->ulin64,
-                 a.p, a.Ap, nullptr, &e);
-      if (e == hipSuccess) vec_dot_partials(c, prec, a.p, a.Ap, n, a.red_a, &e);
-      if (e == hipSuccess) e = cg_update(c, a, it);
-      if (e == hipSuccess) e = cg_direction(c, a, it);
-      if (e != hipSuccess) {
+  const int cap = elem_red_capacity(c);
+  double *red_a = c->red, *red_b = c->red + cap, *red_r = c->red + cap + 2 * VGRID_MAX;
+  if (o.type == NLE_KSP_CG || o.type == NLE_KSP_MINRES) {
+    // the loop runs on the library's own stream (graph capture needs a
+    // non-default stream), ordered after and before the caller's stream
+    hipStream_t user = c->stream;
+    NLE_HIP(c, hipEventRecord(c->ev_a, user));
+    NLE_HIP(c, hipStreamWaitEvent(c->kstream, c->ev_a, 0));
+    c->stream = c->kstream;
+    struct Restore {
+      Ctx *c;
+      hipStream_t user;
+      ~Restore() {
         c->elem_skip = nullptr;
-        return fail(c, NLE_E_HIP, std::string("cg: ") + hipGetErrorString(e));
+        c->ep.w = nullptr;
+        c->ep.coef = nullptr;
+        c->ep.red = nullptr;
+        c->stream = user;
       }
-      if ((it + 1) % check == 0 || it + 1 == o.max_it) {
-        nle_status s = read_scalars(c, flag, 8);
-        if (s != NLE_OK) {
-          c->elem_skip = nullptr;
-          return s;
-        }
-        int32_t f[2];
-        std::memcpy(f, c->hpin, 8);
-        if (f[0] != 0) break;
-      }
+    } restore{c, user};
+    nle_status st = NLE_OK;
+    hipError_t e = hipSuccess;
+    if (o.type == NLE_KSP_CG) {
+      CgArgs a;
+      a.prec = prec;
+      a.n = n;
+      a.x = x;
+      a.r = W.take(vb);
+      a.z = W.take(vb);
+      a.p = W.take(vb);
+      a.Ap = W.take(vb);
+      a.dinv = dinv;
+      a.red_a = red_a;
+      a.red_b = red_b;
+      a.scal = c->dscal;
+      a.flag = flag;
+      a.np_a = 0;
+      NLE_HIP(c, cg_start(c, a, b, o.rtol, o.atol, o.max_it));
+      c->elem_skip = flag;
+      c->ep.red = red_a;
+      auto iter = [&]() -> hipError_t {
+        hipError_t err;
+        a.np_a = elem_apply(c, OP_JV, prec, ulin, a.p, a.Ap, nullptr, &err);
+        if (err != hipSuccess) return err;
+        err = cg_update(c, a);
+        if (err != hipSuccess) return err;
+        return cg_direction(c, a);
+      };
+      std::vector<uint64_t> key = {1, uint64_t(prec), uint64_t(n), uint64_t(check),
+                                   uint64_t(uintptr_t(x)), uint64_t(uintptr_t(a.r)),
+                                   uint64_t(uintptr_t(dinv)), uint64_t(uintptr_t(ulin)),
+                                   uint64_t(uintptr_t(c->red)), uint64_t(uintptr_t(c->m.G32)),
+                                   uint64_t(uintptr_t(c->m.nodes)), uint64_t(c->mat.kind)};
+      st = run_chunks(c, key, check, o.max_it, flag, iter);
+    } else {
+      MinresArgs a;
+      a.prec = prec;
+      a.n = n;
+      a.x = x;
+      a.r1 = W.take(vb);
+      a.r2 = W.take(vb);
+      a.y = W.take(vb);
+      a.v = W.take(vb);
+      a.av = W.take(vb);
+      a.wa = W.take(vb);
+      a.wb = W.take(vb);
+      a.za = W.take(vb);
+      a.zb = W.take(vb);
+      a.r = W.take(vb);
+      a.dinv = dinv;
+      a.red_a = red_a;
+      a.red_b = red_b;
+      a.red_r = red_r;
+      a.scal = c->dscal;
+      a.flag = flag;
+      a.np_a = 0;
+      NLE_HIP(c, mr_start(c, a, b, o.rtol, o.atol, o.max_it));
+      c->elem_skip = flag;
+      c->ep.w = a.r1;
+      c->ep.coef = c->dscal + 20;  // M_COEF
+      c->ep.red = red_a;
+      auto iter = [&]() -> hipError_t {
+        hipError_t err;
+        a.np_a = elem_apply(c, OP_JV, prec, ulin, a.v, a.y, nullptr, &err);
+        if (err != hipSuccess) return err;
+        return mr_iterate(c, a);
+      };
+      std::vector<uint64_t> key = {2, uint64_t(prec), uint64_t(n), uint64_t(check),
+                                   uint64_t(uintptr_t(x)), uint64_t(uintptr_t(a.r1)),
+                                   uint64_t(uintptr_t(dinv)), uint64_t(uintptr_t(ulin)),
+                                   uint64_t(uintptr_t(c->red)), uint64_t(uintptr_t(c->m.G32)),
+                                   uint64_t(uintptr_t(c->m.nodes)), uint64_t(c->mat.kind)};
+      st = run_chunks(c, key, check, o.max_it, flag, iter);
     }
-    c->elem_skip = nullptr;
-    nle_status s = read_scalars(c, flag, 8);
-    if (s != NLE_OK) return s;
+    if (st != NLE_OK) return st;
+    (void)e;
+    st = read_scalars(c, flag, 8);
+    if (st != NLE_OK) return st;
     int32_t f[2];
     std::memcpy(f, c->hpin, 8);
     R->its = f[1];
-    R->flag = f[0];
-    *n_jv += f[1] + (f[0] == 2 ? 1 : 0);
+    R->flag = f[0] == 5 ? 0 : f[0];
+    *n_jv += f[1];
+    NLE_HIP(c, hipEventRecord(c->ev_b, c->kstream));
+    NLE_HIP(c, hipStreamWaitEvent(user, c->ev_b, 0));
     return NLE_OK;
   }
   // ---- GMRES (right preconditioned) -----------------------------------------
@@ -286,7 +396,8 @@ nle_status check_ready(Ctx *c, double *u, const nle_solver_opts *o) {
   if (!u || !o) return fail(c, NLE_E_INVAL, "null argument");
   if (o->precision != NLE_PREC_FP64 && o->precision != NLE_PREC_MIXED)
     return fail(c, NLE_E_INVAL, "bad precision");
-  if (o->ksp_type != NLE_KSP_CG && o->ksp_type != NLE_KSP_GMRES)
+  if (o->ksp_type != NLE_KSP_CG && o->ksp_type != NLE_KSP_GMRES &&
+      o->ksp_type != NLE_KSP_MINRES)
     return fail(c, NLE_E_INVAL, "bad ksp_type");
   if (o->pc != NLE_PC_JACOBI && o->pc != NLE_PC_NONE) return fail(c, NLE_E_INVAL, "bad pc");
   if (o->ksp_max_it < 1 || o->snes_max_it < 0) return fail(c, NLE_E_INVAL, "bad iteration limits");

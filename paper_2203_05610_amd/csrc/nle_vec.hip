@@ -95,7 +95,19 @@ __global__ __launch_bounds__(NT) void k_reduce(const double *red, int np, int st
 }
 
 // ------------------------------------------------------------------ CG
-enum { S_RZ = 0, S_TOL2 = 2, S_RR = 3, S_B2 = 4, S_ALPHA = 5 };
+// Device scalars (scal[]) and flags (flag[]) shared by the CG and MINRES
+// loops.  Every iteration is a fixed sequence of launches with no per-
+// iteration host argument, so a chunk of iterations can be replayed as one
+// graph.  A scalar written by one workgroup is only read by later kernels.
+//   flag[0]: 0 running, 1 converged, 2 breakdown, 3 NaN, 5 iteration limit
+//   flag[1]: completed iterations
+enum {
+  S_RZ = 0, S_RZOLD = 1, S_TOL2 = 2, S_RR = 3, S_B2 = 4, S_MAXIT = 5,
+  // MINRES
+  M_BETA = 8, M_OLDB = 9, M_ALFA = 10, M_CS = 11, M_SN = 12, M_DBAR = 13, M_EPS = 14,
+  M_OLDEPS = 15, M_DELTA = 16, M_PHI = 17, M_PHIBAR = 18, M_DENOM = 19, M_COEF = 20,
+  M_INVBETA = 21
+};
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_cg_start(const T *b, T *x, T *r, T *z, T *p, const T *dinv,
@@ -121,7 +133,8 @@ __global__ __launch_bounds__(NT) void k_cg_start(const T *b, T *x, T *r, T *z, T
 }
 
 __global__ __launch_bounds__(NT) void k_cg_start2(const double *red, int np, double *scal,
-                                                  int32_t *flag, double rtol, double atol) {
+                                                  int32_t *flag, double rtol, double atol,
+                                                  int max_it) {
   __shared__ double sh[NT / 64];
   const double rz = sum_partials(red, np, sh);
   const double rr = sum_partials(red + VGRID_MAX, np, sh);
@@ -131,25 +144,30 @@ __global__ __launch_bounds__(NT) void k_cg_start2(const double *red, int np, dou
     scal[S_TOL2] = tol2;
     scal[S_RR] = rr;
     scal[S_B2] = rr;
+    scal[S_MAXIT] = double(max_it);
     flag[1] = 0;
     flag[0] = (rr <= tol2) ? 1 : ((rr == rr) ? 0 : 3);
   }
 }
 
+// alpha = rz / p.Ap;  x += alpha p;  r -= alpha Ap;  z = M^-1 r; partials of
+// r.z and r.r.  p.Ap partials come from the Jacobian-action epilogue.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_cg_update(T *x, T *r, T *z, const T *p, const T *Ap,
                                                   const T *dinv, int64_t n, const double *red_a,
                                                   int np_a, double *red_b, double *scal,
-                                                  int32_t *flag, int it) {
+                                                  int32_t *flag) {
   __shared__ double shd[NT / 64];
   __shared__ T sh[NT / 64];
   if (flag[0] != 0) return;
   const double pAp = sum_partials(red_a, np_a, shd);
   if (!(pAp > 0.0)) {  // not positive definite (or NaN): stop, keep x
-    if (blockIdx.x == 0 && threadIdx.x == 0) flag[0] = 2;
+    if (blockIdx.x == 0 && threadIdx.x == 0) flag[0] = (pAp == pAp) ? 2 : 3;
     return;
   }
-  const double alpha = scal[S_RZ + (it & 1)] / pAp;
+  const double rz = scal[S_RZ];
+  const double alpha = rz / pAp;
+  if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_RZOLD] = rz;
   const T a = T(alpha);
   T arz = T(0), arr = T(0);
   for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT) {
@@ -169,27 +187,220 @@ __global__ __launch_bounds__(NT) void k_cg_update(T *x, T *r, T *z, const T *p, 
   }
 }
 
+// beta = rz_new / rz_old;  p = z + beta p;  convergence test on r.r.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_cg_direction(T *p, const T *z, int64_t n,
                                                      const double *red_b, int np, double *scal,
-                                                     int32_t *flag, int it) {
+                                                     int32_t *flag) {
   __shared__ double sh[NT / 64];
   if (flag[0] != 0) return;
   const double rz = sum_partials(red_b, np, sh);
   const double rr = sum_partials(red_b + VGRID_MAX, np, sh);
-  const double beta = rz / scal[S_RZ + (it & 1)];
+  const double beta = rz / scal[S_RZOLD];
   const T bt = T(beta);
   for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT)
     p[i] = z[i] + bt * p[i];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    scal[S_RZ + ((it + 1) & 1)] = rz;
+    scal[S_RZ] = rz;
     scal[S_RR] = rr;
-    flag[1] = it + 1;
+    const int its = flag[1] + 1;
+    flag[1] = its;
     if (!(rr == rr))
       flag[0] = 3;
     else if (rr <= scal[S_TOL2])
       flag[0] = 1;
+    else if (double(its) >= scal[S_MAXIT])
+      flag[0] = 5;
   }
+}
+
+// ------------------------------------------------------------------ MINRES
+// Preconditioned MINRES (Paige & Saunders 1975; the Lanczos / Givens form).
+// Besides the solution it carries z = A w and the true residual r = b - A x,
+// so the stopping test is on ||b - A x||_2 like the other Krylov methods.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_mr_start(const T *b, T *x, T *r1, T *r2, T *y, T *r,
+                                                 T *wa, T *wb, T *za, T *zb, const T *dinv,
+                                                 int64_t n, double *red) {
+  __shared__ T sh[NT / 64];
+  T aby = T(0), abb = T(0);
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT) {
+    const T bi = b[i];
+    const T yi = dinv ? dinv[i] * bi : bi;
+    x[i] = T(0);
+    r1[i] = bi;
+    r2[i] = bi;
+    r[i] = bi;
+    y[i] = yi;
+    wa[i] = T(0);
+    wb[i] = T(0);
+    za[i] = T(0);
+    zb[i] = T(0);
+    aby += bi * yi;
+    abb += bi * bi;
+  }
+  aby = block_sum_all(aby, sh);
+  abb = block_sum_all(abb, sh);
+  if (threadIdx.x == 0) {
+    red[blockIdx.x] = double(aby);
+    red[VGRID_MAX + blockIdx.x] = double(abb);
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_mr_start2(const double *red, int np, double *scal,
+                                                  int32_t *flag, double rtol, double atol,
+                                                  int max_it) {
+  __shared__ double sh[NT / 64];
+  const double by = sum_partials(red, np, sh);
+  const double bb = sum_partials(red + VGRID_MAX, np, sh);
+  if (threadIdx.x == 0) {
+    const double tol2 = fmax(rtol * rtol * bb, atol * atol);
+    const double beta1 = sqrt(fmax(by, 0.0));
+    scal[S_TOL2] = tol2;
+    scal[S_RR] = bb;
+    scal[S_B2] = bb;
+    scal[S_MAXIT] = double(max_it);
+    scal[M_BETA] = beta1;
+    scal[M_OLDB] = 0.0;
+    scal[M_CS] = -1.0;
+    scal[M_SN] = 0.0;
+    scal[M_DBAR] = 0.0;
+    scal[M_EPS] = 0.0;
+    scal[M_PHIBAR] = beta1;
+    scal[M_COEF] = 0.0;
+    scal[M_INVBETA] = beta1 > 0.0 ? 1.0 / beta1 : 0.0;
+    flag[1] = 0;
+    if (!(bb == bb) || !(by == by))
+      flag[0] = 3;
+    else if (bb <= tol2)
+      flag[0] = 1;
+    else if (!(by > 0.0))
+      flag[0] = 2;  // preconditioner not positive definite
+    else
+      flag[0] = 0;
+  }
+}
+
+// v = y / beta (first iteration only; later iterations form v in k_mr_e)
+template <typename T>
+__global__ __launch_bounds__(NT) void k_mr_v(const T *y, T *v, int64_t n, const double *scal,
+                                             const int32_t *flag) {
+  if (flag[0] != 0) return;
+  const T s = T(scal[M_INVBETA]);
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT)
+    v[i] = y[i] * s;
+}
+
+// After the Jacobian action (with epilogue) y = A v - coef r1 and partials of
+// alfa = v.y:  av = A v;  t = y - (alfa / beta) r2;  r1 = r2;  r2 = t;
+// y = M^-1 t;  partials of t.y.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_mr_c(T *y, T *r1, T *r2, T *av, const T *dinv, int64_t n,
+                                             const double *red_a, int np_a, double *red_b,
+                                             double *scal, const int32_t *flag) {
+  __shared__ double shd[NT / 64];
+  __shared__ T sh[NT / 64];
+  if (flag[0] != 0) return;
+  const double alfa = sum_partials(red_a, np_a, shd);
+  if (blockIdx.x == 0 && threadIdx.x == 0) scal[M_ALFA] = alfa;
+  const T c = T(scal[M_COEF]);
+  const T ab = T(alfa * scal[M_INVBETA]);
+  T acc = T(0);
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT) {
+    const T yi = y[i];
+    const T r1i = r1[i], r2i = r2[i];
+    av[i] = yi + c * r1i;
+    const T t = yi - ab * r2i;
+    r1[i] = r2i;
+    r2[i] = t;
+    const T yn = dinv ? dinv[i] * t : t;
+    y[i] = yn;
+    acc += t * yn;
+  }
+  acc = block_sum_all(acc, sh);
+  if (threadIdx.x == 0) red_b[blockIdx.x] = double(acc);
+}
+
+// Scalar recurrence (one workgroup): new beta, Givens rotation, step phi;
+// also the convergence test on the previous iteration's ||r||^2.
+__global__ __launch_bounds__(NT) void k_mr_d(const double *red_b, int np, const double *red_r,
+                                             int np_r, double *scal, int32_t *flag) {
+  __shared__ double sh[NT / 64];
+  if (flag[0] != 0) return;
+  const double bb = sum_partials(red_b, np, sh);
+  const double rr = flag[1] > 0 ? sum_partials(red_r, np_r, sh) : scal[S_RR];
+  if (threadIdx.x != 0) return;
+  scal[S_RR] = rr;
+  if (!(rr == rr) || !(bb == bb)) {
+    flag[0] = 3;
+    return;
+  }
+  if (flag[1] > 0 && rr <= scal[S_TOL2]) {
+    flag[0] = 1;
+    return;
+  }
+  if (double(flag[1]) >= scal[S_MAXIT]) {
+    flag[0] = 5;
+    return;
+  }
+  const double alfa = scal[M_ALFA];
+  const double beta_old = scal[M_BETA];
+  const double beta = sqrt(fmax(bb, 0.0));
+  const double cs = scal[M_CS], sn = scal[M_SN], dbar = scal[M_DBAR];
+  const double oldeps = scal[M_EPS];
+  const double delta = cs * dbar + sn * alfa;
+  const double gbar = sn * dbar - cs * alfa;
+  const double epsln = sn * beta;
+  const double dbar_n = -cs * beta;
+  double gamma = sqrt(gbar * gbar + beta * beta);
+  gamma = fmax(gamma, 1e-300);
+  const double cs_n = gbar / gamma, sn_n = beta / gamma;
+  const double phibar = scal[M_PHIBAR];
+  scal[M_OLDB] = beta_old;
+  scal[M_BETA] = beta;
+  scal[M_OLDEPS] = oldeps;
+  scal[M_DELTA] = delta;
+  scal[M_EPS] = epsln;
+  scal[M_DBAR] = dbar_n;
+  scal[M_CS] = cs_n;
+  scal[M_SN] = sn_n;
+  scal[M_PHI] = cs_n * phibar;
+  scal[M_PHIBAR] = sn_n * phibar;
+  scal[M_DENOM] = 1.0 / gamma;
+  scal[M_COEF] = beta_old > 0.0 ? beta / beta_old : 0.0;
+  scal[M_INVBETA] = beta > 0.0 ? 1.0 / beta : 0.0;
+  flag[1] = flag[1] + 1;
+}
+
+// w = (v - oldeps w_{k-2} - delta w_{k-1}) / gamma;  x += phi w;
+// z = (A v - oldeps z_{k-2} - delta z_{k-1}) / gamma;  r -= phi z;  partials
+// of r.r;  next v = y / beta.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_mr_e(T *x, T *v, const T *y, const T *av, T *wa, T *wb,
+                                             T *za, T *zb, T *r, int64_t n, double *red_r,
+                                             const double *scal, const int32_t *flag) {
+  __shared__ T sh[NT / 64];
+  if (flag[0] != 0) return;
+  const T oe = T(scal[M_OLDEPS]), de = T(scal[M_DELTA]), dn = T(scal[M_DENOM]);
+  const T ph = T(scal[M_PHI]), ib = T(scal[M_INVBETA]);
+  T acc = T(0);
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT) {
+    const T w1 = wa[i], w2 = wb[i];  // w_{k-1}, w_{k-2}
+    const T w = (v[i] - oe * w2 - de * w1) * dn;
+    wb[i] = w1;
+    wa[i] = w;
+    x[i] += ph * w;
+    const T z1 = za[i], z2 = zb[i];
+    const T zz = (av[i] - oe * z2 - de * z1) * dn;
+    zb[i] = z1;
+    za[i] = zz;
+    const T ri = r[i] - ph * zz;
+    r[i] = ri;
+    acc += ri * ri;
+    v[i] = y[i] * ib;
+  }
+  acc = block_sum_all(acc, sh);
+  if (threadIdx.x == 0) red_r[blockIdx.x] = double(acc);
 }
 
 // ------------------------------------------------------------------ GMRES
@@ -487,7 +698,7 @@ hipError_t reduce_scalars(Ctx *c, const double *red, int np, int count, double *
 }
 
 // ------------------------------------------------------------------ CG
-hipError_t cg_start(Ctx *c, const CgArgs &a, const void *b, double rtol, double atol) {
+hipError_t cg_start(Ctx *c, const CgArgs &a, const void *b, double rtol, double atol, int max_it) {
   const int g = vgrid(a.n);
   if (a.prec == NLE_FP32)
     LAUNCH(k_cg_start<float>, g, static_cast<const float *>(b), static_cast<float *>(a.x),
@@ -497,33 +708,81 @@ hipError_t cg_start(Ctx *c, const CgArgs &a, const void *b, double rtol, double 
     LAUNCH(k_cg_start<double>, g, static_cast<const double *>(b), static_cast<double *>(a.x),
            static_cast<double *>(a.r), static_cast<double *>(a.z), static_cast<double *>(a.p),
            static_cast<const double *>(a.dinv), a.n, a.red_b);
-  LAUNCH(k_cg_start2, 1, a.red_b, g, a.scal, a.flag, rtol, atol);
+  LAUNCH(k_cg_start2, 1, a.red_b, g, a.scal, a.flag, rtol, atol, max_it);
   return hipGetLastError();
 }
 
-hipError_t cg_update(Ctx *c, const CgArgs &a, int it) {
+hipError_t cg_update(Ctx *c, const CgArgs &a) {
   const int g = vgrid(a.n);
   if (a.prec == NLE_FP32)
     LAUNCH(k_cg_update<float>, g, static_cast<float *>(a.x), static_cast<float *>(a.r),
            static_cast<float *>(a.z), static_cast<const float *>(a.p),
            static_cast<const float *>(a.Ap), static_cast<const float *>(a.dinv), a.n, a.red_a,
-           a.np_a, a.red_b, a.scal, a.flag, it);
+           a.np_a, a.red_b, a.scal, a.flag);
   else
     LAUNCH(k_cg_update<double>, g, static_cast<double *>(a.x), static_cast<double *>(a.r),
            static_cast<double *>(a.z), static_cast<const double *>(a.p),
            static_cast<const double *>(a.Ap), static_cast<const double *>(a.dinv), a.n, a.red_a,
-           a.np_a, a.red_b, a.scal, a.flag, it);
+           a.np_a, a.red_b, a.scal, a.flag);
   return hipGetLastError();
 }
 
-hipError_t cg_direction(Ctx *c, const CgArgs &a, int it) {
+hipError_t cg_direction(Ctx *c, const CgArgs &a) {
   const int g = vgrid(a.n);
   if (a.prec == NLE_FP32)
     LAUNCH(k_cg_direction<float>, g, static_cast<float *>(a.p), static_cast<const float *>(a.z),
-           a.n, a.red_b, g, a.scal, a.flag, it);
+           a.n, a.red_b, g, a.scal, a.flag);
   else
     LAUNCH(k_cg_direction<double>, g, static_cast<double *>(a.p), static_cast<const double *>(a.z),
-           a.n, a.red_b, g, a.scal, a.flag, it);
+           a.n, a.red_b, g, a.scal, a.flag);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ MINRES
+#define MR_PTRS(T)                                                                              \
+  static_cast<T *>(a.x), static_cast<T *>(a.r1), static_cast<T *>(a.r2), static_cast<T *>(a.y), \
+      static_cast<T *>(a.r), static_cast<T *>(a.wa), static_cast<T *>(a.wb),                      \
+      static_cast<T *>(a.za), static_cast<T *>(a.zb), static_cast<const T *>(a.dinv)
+
+hipError_t mr_start(Ctx *c, const MinresArgs &a, const void *b, double rtol, double atol,
+                    int max_it) {
+  const int g = vgrid(a.n);
+  if (a.prec == NLE_FP32)
+    LAUNCH(k_mr_start<float>, g, static_cast<const float *>(b), MR_PTRS(float), a.n, a.red_b);
+  else
+    LAUNCH(k_mr_start<double>, g, static_cast<const double *>(b), MR_PTRS(double), a.n, a.red_b);
+  LAUNCH(k_mr_start2, 1, a.red_b, g, a.scal, a.flag, rtol, atol, max_it);
+  if (a.prec == NLE_FP32)
+    LAUNCH(k_mr_v<float>, g, static_cast<const float *>(a.y), static_cast<float *>(a.v), a.n,
+           a.scal, a.flag);
+  else
+    LAUNCH(k_mr_v<double>, g, static_cast<const double *>(a.y), static_cast<double *>(a.v), a.n,
+           a.scal, a.flag);
+  return hipGetLastError();
+}
+
+// the three vector / scalar steps after the Jacobian action of one iteration
+hipError_t mr_iterate(Ctx *c, const MinresArgs &a) {
+  const int g = vgrid(a.n);
+  if (a.prec == NLE_FP32)
+    LAUNCH(k_mr_c<float>, g, static_cast<float *>(a.y), static_cast<float *>(a.r1),
+           static_cast<float *>(a.r2), static_cast<float *>(a.av), static_cast<const float *>(a.dinv),
+           a.n, a.red_a, a.np_a, a.red_b, a.scal, a.flag);
+  else
+    LAUNCH(k_mr_c<double>, g, static_cast<double *>(a.y), static_cast<double *>(a.r1),
+           static_cast<double *>(a.r2), static_cast<double *>(a.av),
+           static_cast<const double *>(a.dinv), a.n, a.red_a, a.np_a, a.red_b, a.scal, a.flag);
+  LAUNCH(k_mr_d, 1, a.red_b, g, a.red_r, g, a.scal, a.flag);
+  if (a.prec == NLE_FP32)
+    LAUNCH(k_mr_e<float>, g, static_cast<float *>(a.x), static_cast<float *>(a.v),
+           static_cast<const float *>(a.y), static_cast<const float *>(a.av),
+           static_cast<float *>(a.wa), static_cast<float *>(a.wb), static_cast<float *>(a.za),
+           static_cast<float *>(a.zb), static_cast<float *>(a.r), a.n, a.red_r, a.scal, a.flag);
+  else
+    LAUNCH(k_mr_e<double>, g, static_cast<double *>(a.x), static_cast<double *>(a.v),
+           static_cast<const double *>(a.y), static_cast<const double *>(a.av),
+           static_cast<double *>(a.wa), static_cast<double *>(a.wb), static_cast<double *>(a.za),
+           static_cast<double *>(a.zb), static_cast<double *>(a.r), a.n, a.red_r, a.scal, a.flag);
   return hipGetLastError();
 }
 

@@ -27,7 +27,7 @@ NLE_E_OOM, NLE_E_HIP, NLE_E_UNSUPPORTED = -4, -5, -6
 NLE_FP64, NLE_FP32 = 0, 1
 NLE_MAT_M1, NLE_MAT_M2 = 1, 2
 NLE_NK, NLE_INK, NLE_BFGS = 0, 1, 2
-NLE_KSP_GMRES, NLE_KSP_CG = 0, 1
+NLE_KSP_GMRES, NLE_KSP_CG, NLE_KSP_MINRES = 0, 1, 2
 NLE_ORTH_MGS, NLE_ORTH_CGS2 = 0, 1
 NLE_PC_NONE, NLE_PC_JACOBI = 0, 1
 NLE_H0_PREONLY, NLE_H0_KSP = 0, 1

@@ -42,7 +42,8 @@ def make_opts(method: str, precision: str = "fp64", **over) -> nl.nle_solver_opt
         o.h0 = nl.NLE_H0_KSP if h0 == "ksp" else nl.NLE_H0_PREONLY
     ksp = over.pop("ksp", None)
     if ksp is not None:
-        o.ksp_type = nl.NLE_KSP_CG if ksp == "cg" else nl.NLE_KSP_GMRES
+        o.ksp_type = {"cg": nl.NLE_KSP_CG, "gmres": nl.NLE_KSP_GMRES,
+                      "minres": nl.NLE_KSP_MINRES}[ksp]
     orth = over.pop("orth", None)
     if orth is not None:
         o.orth = nl.NLE_ORTH_MGS if orth == "mgs" else nl.NLE_ORTH_CGS2

@@ -43,6 +43,9 @@ C1 = (8, 8, 1, 5.0)
 
 METHODS = [
     ("nk", {}),
+    ("nk", {"ksp": "minres"}),
+    ("ink", {"ksp": "minres"}),
+    ("bfgs", {"h0": "ksp", "qn_m": 10, "ksp": "minres"}),
     ("nk", {"ksp": "gmres", "orth": "mgs"}),
     ("nk", {"ksp": "gmres", "orth": "cgs2", "restart": 30}),
     ("ink", {}),
@@ -101,6 +104,32 @@ def test_nk_iterates_follow_oracle_reference_loop():
     for a, b in zip(rep["rnorm_hist"][:3], ref["rnorm"][:3]):
         assert abs(a - b) <= 1e-6 * b
     assert all(abs(a - b) <= 2 for a, b in zip(rep["lit_hist"], ref["lits"]))
+
+
+@pytest.mark.parametrize("ksp", ["cg", "minres"])
+def test_krylov_iteration_counts_follow_oracle(ksp):
+    # NK with CG or MINRES (Jacobi) against the same algorithm on the assembled tangent
+    mesh, P, ctx = _cook(*C1, be=64)
+
+    def lin(u):
+        K = P.stiffness(u)
+        d = K.diagonal()
+        return (lambda v: K @ v), (lambda v: v / d)
+
+    ref = solvers.newton_krylov(lambda u: P.residual(u), lin, np.zeros(P.n_dofs), ksp=ksp)
+    u = torch.zeros(P.n_dofs, dtype=torch.float64, device="cuda")
+    o = problems.make_opts("nk", ksp=ksp)
+    o.check_every = 8
+    st, rep = nl.nle_solve_nk(ctx, u, o)
+    assert st == nl.NLE_OK
+    assert abs(rep["nit"] - ref["nit"]) <= 1
+    # ||r_0|| is exact; later norms depend on where each inexact solve crossed
+    # its 1e-6 tolerance, so they agree to that tolerance times ||r_0||
+    assert abs(rep["rnorm_hist"][0] - ref["rnorm"][0]) <= 1e-12 * ref["rnorm"][0]
+    for a, b in zip(rep["rnorm_hist"][1:3], ref["rnorm"][1:3]):
+        assert abs(a - b) <= 1e-3 * b + 1e-6 * ref["rnorm"][0]
+    for a, b in zip(rep["lit_hist"], ref["lits"]):
+        assert abs(a - b) <= max(2, 0.02 * b)
 
 
 def test_ink_forcing_terms_follow_oracle():

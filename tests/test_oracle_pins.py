@@ -339,6 +339,39 @@ def test_gmres_restarted_and_cg_solve_spd():
     assert np.allclose(x1, xs, rtol=1e-9) and np.allclose(x2, xs, rtol=1e-9)
 
 
+def _krylov_minimizer_weighted(A, Minv, b, k):
+    """Brute force: argmin ||b - A x||_{M^-1} over x in K_k(M^-1 A, M^-1 b)."""
+    MA = Minv @ A
+    basis = [Minv @ b]
+    for _ in range(k - 1):
+        basis.append(MA @ basis[-1])
+    Kb = np.array(basis).T
+    L = np.linalg.cholesky(Minv)  # ||e||_{M^-1} = ||L^T e||
+    c, *_ = np.linalg.lstsq(L.T @ A @ Kb, L.T @ b, rcond=None)
+    return Kb @ c
+
+
+def test_minres_iterate_is_weighted_krylov_minimizer_on_indefinite_matrix():
+    n = 10
+    rng = np.random.default_rng(21)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = Q @ np.diag(np.concatenate([np.linspace(-5, -1, 4), np.linspace(1, 9, 6)])) @ Q.T
+    d = np.abs(np.diag(A)) + 1.0  # SPD Jacobi-like preconditioner
+    b = rng.standard_normal(n)
+    for k in (1, 2, 4, 6):
+        x, its, _, _ = solvers.minres(lambda v: A @ v, b, lambda v: v / d, rtol=0, atol=0, max_it=k)
+        assert its == k
+        assert np.allclose(x, _krylov_minimizer_weighted(A, np.diag(1 / d), b, k), rtol=1e-8,
+                           atol=1e-10)
+    x, its, hist, conv = solvers.minres(lambda v: A @ v, b, lambda v: v / d, rtol=1e-12, atol=0,
+                                        max_it=200)
+    assert conv and np.allclose(A @ x, b, atol=1e-10)
+    # unpreconditioned MINRES on a symmetric matrix coincides with GMRES
+    xm, *_ = solvers.minres(lambda v: A @ v, b, None, rtol=0, atol=0, max_it=5)
+    xg, *_ = solvers.gmres(lambda v: A @ v, b, None, rtol=0, atol=0, max_it=5)
+    assert np.allclose(xm, xg, rtol=1e-8, atol=1e-10)
+
+
 def test_eisenstat_walker_closed_form():
     f = solvers.ew_forcing
     assert f(0, 1.0, 0.0, 0.0, 0.0) == 0.1
