@@ -219,6 +219,44 @@ nle_status nle_solve_nk(nle_ctx *ctx, double *u_dev, const nle_solver_opts *opts
 nle_status nle_solve_ink(nle_ctx *ctx, double *u_dev, const nle_solver_opts *opts, nle_report *report);
 nle_status nle_solve_bfgs(nle_ctx *ctx, double *u_dev, const nle_solver_opts *opts, nle_report *report);
 
+/* ---- batched solves ---------------------------------------------------------
+ * Many independent problems (uneven meshes, material parameters, loads and
+ * load schedules; the sweeps over size and data magnitude of Sec. 6) solved
+ * together: every launch covers all instances, every decision (convergence,
+ * Krylov tolerance, step, load-step cutback) is per instance.  Instances of a
+ * batch share the material law (kind), not its parameters. */
+typedef struct nle_batch nle_batch;
+nle_status nle_batch_create(nle_batch **out, int32_t device, void *hip_stream,
+                            const nle_allocator *alloc);
+void nle_batch_destroy(nle_batch *b);
+const char *nle_batch_last_error(const nle_batch *b);
+/* Add one instance (host arrays, copied): P1 mesh (as nle_upload_mesh),
+ * material (as nle_set_material), Dirichlet dofs / values (instance-local
+ * dof numbers), dead traction t on n_faces triangles, and the load scales of
+ * its schedule (positive, strictly increasing; solved in order, warm-started).
+ * *id receives its index.  NLE_E_INVAL / NLE_E_BADMESH on bad arrays,
+ * NLE_E_STATE once the batch is finalized. */
+nle_status nle_batch_add(nle_batch *b, int64_t n_nodes, const double *X, int64_t n_elems,
+                         const int32_t *conn, int32_t mat_kind, const double *params,
+                         int32_t n_params, int64_t n_dir, const int64_t *dofs,
+                         const double *values, int64_t n_faces, const int32_t *tri,
+                         const double *traction, int32_t n_scales, const double *scales,
+                         int32_t *id);
+/* Upload the disjoint union of all instances (partition, geometry). */
+nle_status nle_batch_finalize(nle_batch *b);
+/* node_offsets[n_inst + 1]: instance i owns nodes [off[i], off[i+1]) of the
+ * concatenated vector (dof = 3 * node + component). */
+nle_status nle_batch_layout(const nle_batch *b, int64_t *node_offsets);
+/* Solve every instance over its schedule with NK or iNK (CG + Jacobi inner
+ * solves), starting from u (device, concatenated, overwritten).  A load step
+ * that diverges is retried from the last converged state with half the
+ * increment (at most 8 times per instance).  reports[n_inst] (nullable)
+ * receive per-instance outcomes (bfgs_skipped holds the number of cutbacks);
+ * *t_ms the wall time of the whole batch on the stream.  Returns NLE_OK when
+ * every instance finished its schedule, else the last failing status. */
+nle_status nle_batch_solve(nle_batch *b, int32_t method, const nle_solver_opts *opts, double *u_dev,
+                           nle_report *reports, double *t_ms);
+
 /* ---- mesh partition inspection (for tests and tuning) --------------------- */
 /* info[0..7] = n_blocks, max elems per block, max nodes per block,
  * block-node slots, shared nodes, merge slots, LDS bytes (FP64 Jv),

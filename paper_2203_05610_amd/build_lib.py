@@ -20,7 +20,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libnlelast.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["nle_mesh.cpp", "nle_capi.cpp", "nle_solvers.cpp", "nle_elem.hip", "nle_vec.hip"]
+SOURCES = ["nle_mesh.cpp", "nle_capi.cpp", "nle_solvers.cpp", "nle_batch.cpp", "nle_elem.hip",
+           "nle_vec.hip", "nle_batchk.hip"]
 
 ARCH = os.environ.get("NLE_OFFLOAD_ARCH", "gfx950")
 

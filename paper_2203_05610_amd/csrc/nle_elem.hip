@@ -45,6 +45,12 @@ struct ElemArgs {
   const double *ep_coef;
   double *ep_red;
   MatParams mp;
+  // batched mode (all null for a single problem): instance of each block,
+  // per-instance load scale, material (mu, lam, cvol, kappa) and done mask
+  const int32_t *blk_inst;
+  const double *inst_s;
+  const double *inst_mat;
+  const int32_t *inst_done;
 };
 
 template <typename T>
@@ -63,6 +69,9 @@ struct MergeArgs {
   const T *ep_w;
   const double *ep_coef;
   double *ep_red;
+  const int32_t *mwg_inst;  // batched mode: instance of each merge workgroup
+  const double *inst_s;
+  const int32_t *inst_done;
 };
 
 __device__ __forceinline__ int block_id(int nblk, int per_xcd) {
@@ -419,13 +428,22 @@ template <typename T, int OP, int MAT>
 __global__ __launch_bounds__(NT) void k_elem_block(ElemArgs<T> A) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T *lds = reinterpret_cast<T *>(lds_raw);
+  // Reduction partials are stored at the block's index b (consumers sum the
+  // blocks of one problem instance, which are contiguous).
   const int b = block_id(A.nblk, A.per_xcd);
-  if (b >= A.nblk) {  // padding workgroup of the XCD remap: contributes nothing
-    if ((OP == OP_RES || OP == OP_ENERGY) && threadIdx.x == 0) A.red[blockIdx.x] = 0.0;
-    if (OP == OP_JV && A.ep_red && threadIdx.x == 0) A.ep_red[blockIdx.x] = 0.0;
-    return;
-  }
+  if (b >= A.nblk) return;  // padding workgroup of the XCD remap
   if (A.skip && A.skip[0] != 0) return;
+  const int inst = A.blk_inst ? A.blk_inst[b] : 0;
+  if (A.inst_done && A.inst_done[inst]) return;
+  MatParams mp = A.mp;
+  double lscale = A.s;
+  if (A.inst_mat) {
+    mp.mu = A.inst_mat[4 * inst];
+    mp.lam = A.inst_mat[4 * inst + 1];
+    mp.cvol = A.inst_mat[4 * inst + 2];
+    mp.kappa = A.inst_mat[4 * inst + 3];
+  }
+  if (A.inst_s) lscale = A.inst_s[inst];
   const int tid = threadIdx.x;
   const int e0 = A.blk_elem[b], ne = A.blk_elem[b + 1] - e0;
   const int p0 = A.blk_node[b], nl = A.blk_node[b + 1] - p0;
@@ -459,7 +477,7 @@ __global__ __launch_bounds__(NT) void k_elem_block(ElemArgs<T> A) {
   double eacc = 0.0;
   auto run = [&](const ElemIn<T> &d) {
     T out[4][3];
-    element_forces<T, OP, MAT>(d, uS, vS, NL, A.mp, out, bad, eacc);
+    element_forces<T, OP, MAT>(d, uS, vS, NL, mp, out, bad, eacc);
     if (OP != OP_ENERGY) {
       const int cp[4] = {lo16(d.lcp.z), hi16(d.lcp.z), lo16(d.lcp.w), hi16(d.lcp.w)};
 #pragma unroll
@@ -474,11 +492,11 @@ __global__ __launch_bounds__(NT) void k_elem_block(ElemArgs<T> A) {
     load_elem(A, uint32_t(e0 + e), ea);
     run(ea);
   }
-  if (bad && A.flag) A.flag[0] = 1;
+  if (bad && A.flag) A.flag[inst] = 1;
 
   if (OP == OP_ENERGY) {
     const double s = block_sum(eacc, rs);
-    if (tid == 0) A.red[blockIdx.x] = s;
+    if (tid == 0) A.red[b] = s;
     return;
   }
   __syncthreads();
@@ -501,13 +519,13 @@ __global__ __launch_bounds__(NT) void k_elem_block(ElemArgs<T> A) {
       pp[1] = acc[1];
       pp[2] = acc[2];
     } else {
-      finalize_node<T, OP>(w & NODE_MASK, (w >> 28) & 7u, acc, A.v, A.out, A.fext, A.s, nrm,
+      finalize_node<T, OP>(w & NODE_MASK, (w >> 28) & 7u, acc, A.v, A.out, A.fext, lscale, nrm,
                            A.ep_w, epc);
     }
   }
   if (OP == OP_RES || (OP == OP_JV && A.ep_red)) {
     const double s = block_sum(nrm, rs);
-    if (tid == 0) (OP == OP_RES ? A.red : A.ep_red)[blockIdx.x] = s;
+    if (tid == 0) (OP == OP_RES ? A.red : A.ep_red)[b] = s;
   }
 }
 
@@ -515,9 +533,14 @@ template <typename T, int OP>
 __global__ __launch_bounds__(NT) void k_elem_merge(MergeArgs<T> A) {
   __shared__ double rs[NT / 64];
   if (A.skip && A.skip[0] != 0) return;
+  const int inst = A.mwg_inst ? A.mwg_inst[blockIdx.x] : 0;
+  if (A.inst_done && A.inst_done[inst]) return;
+  const double lscale = A.inst_s ? A.inst_s[inst] : A.s;
   const int64_t k = int64_t(blockIdx.x) * NT + threadIdx.x;
   double nrm = 0.0;
-  if (k < A.n_sh) {
+  // padding entries (batched mode aligns each instance to whole workgroups)
+  // have an empty slot range and the id 0xFFFFFFFF
+  if (k < A.n_sh && A.fx_node[k] != 0xFFFFFFFFu) {
     T acc[3] = {T(0), T(0), T(0)};
     const int q0 = A.fx_ptr[k], q1 = A.fx_ptr[k + 1];
     // slots in groups of four: the four gathers are issued before the sums,
@@ -540,7 +563,7 @@ __global__ __launch_bounds__(NT) void k_elem_merge(MergeArgs<T> A) {
         }
     }
     const uint32_t w = A.fx_node[k];
-    finalize_node<T, OP>(w & NODE_MASK, (w >> 28) & 7u, acc, A.v, A.out, A.fext, A.s, nrm,
+    finalize_node<T, OP>(w & NODE_MASK, (w >> 28) & 7u, acc, A.v, A.out, A.fext, lscale, nrm,
                          A.ep_w, A.ep_coef ? T(A.ep_coef[0]) : T(0));
   }
   if (OP == OP_RES || (OP == OP_JV && A.ep_red)) {
@@ -573,12 +596,16 @@ int launch(Ctx *c, int op, const T *G, const T *V, const T *u, const T *v, T *ou
   A.fext = c->fext;
   A.s = c->load_scale;
   A.red = red;
-  A.flag = c->dflag;
+  A.flag = c->inst_inv ? c->inst_inv : c->dflag;
   A.skip = c->elem_skip;
   A.ep_w = static_cast<const T *>(c->ep.w);
   A.ep_coef = c->ep.coef;
   A.ep_red = op == OP_JV ? c->ep.red : nullptr;
   A.mp = c->mat;
+  A.blk_inst = M.blk_inst;
+  A.inst_s = c->inst_s;
+  A.inst_mat = c->inst_mat;
+  A.inst_done = c->inst_done;
   const int grid = A.per_xcd > 0 ? 8 * A.per_xcd : M.nblk;
   size_t lds = size_t(6 * M.nl_max + 12 * M.be_max) * sizeof(T);
   lds = std::max(lds, size_t(NT / 64) * sizeof(double));
@@ -605,8 +632,8 @@ int launch(Ctx *c, int op, const T *G, const T *V, const T *u, const T *v, T *ou
 #undef NLE_LAUNCH_BLOCK
   *err = hipGetLastError();
   if (*err != hipSuccess) return 0;
-  if (op == OP_ENERGY) return grid;
-  int nred = (op == OP_RES || (op == OP_JV && c->ep.red)) ? grid : 0;
+  if (op == OP_ENERGY) return M.nblk;
+  int nred = (op == OP_RES || (op == OP_JV && c->ep.red)) ? M.nblk : 0;
   if (M.n_shared > 0) {
     MergeArgs<T> B;
     B.fx_node = M.fx_node;
@@ -618,11 +645,14 @@ int launch(Ctx *c, int op, const T *G, const T *V, const T *u, const T *v, T *ou
     B.out = out;
     B.fext = c->fext;
     B.s = c->load_scale;
-    B.red = red ? red + grid : nullptr;
+    B.red = red ? red + M.nblk : nullptr;
+    B.mwg_inst = M.mwg_inst;
+    B.inst_s = c->inst_s;
+    B.inst_done = c->inst_done;
     B.skip = c->elem_skip;
     B.ep_w = static_cast<const T *>(c->ep.w);
     B.ep_coef = c->ep.coef;
-    B.ep_red = (op == OP_JV && c->ep.red) ? c->ep.red + grid : nullptr;
+    B.ep_red = (op == OP_JV && c->ep.red) ? c->ep.red + M.nblk : nullptr;
     const int g2 = int((M.n_shared + NT - 1) / NT);
     switch (op) {
       case OP_RES:

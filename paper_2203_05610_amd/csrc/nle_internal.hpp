@@ -39,6 +39,13 @@ struct Mesh {
   uint16_t *csr_end = nullptr;                  // [n_slots] end of the slot's range
   uint32_t *nodes = nullptr;                    // [n_slots] id | mask<<28 | shared<<31
   int32_t *blk_elem = nullptr, *blk_node = nullptr;  // [nblk+1]
+  // batched meshes (disjoint union of instances): instance of each block and
+  // of each merge workgroup (each instance's shared nodes start on a whole
+  // merge workgroup), and per-instance ranges
+  int32_t *blk_inst = nullptr, *mwg_inst = nullptr;
+  int32_t n_inst = 1, n_mwg = 0;
+  std::vector<int64_t> h_inst_node, h_inst_elem;   // [n_inst+1] offsets
+  std::vector<int32_t> h_inst_blk, h_inst_mwg;     // [n_inst+1] block / merge-WG offsets
   uint32_t *fx_node = nullptr;                  // [n_shared] id | mask<<28
   int32_t *fx_ptr = nullptr, *fx_slot = nullptr;     // merge CSR over slots
   // host mirrors needed later
@@ -83,6 +90,13 @@ struct Ctx {
   std::vector<double> h_ftrac, h_fbody;
   double *fext = nullptr;
   double load_scale = 1.0;
+
+  // batched mode: per-instance load scale, material (mu, lam, cvol, kappa)
+  // and done mask on the device (null for a single problem)
+  double *inst_s = nullptr;
+  double *inst_mat = nullptr;
+  int32_t *inst_done = nullptr;
+  int32_t *inst_inv = nullptr;  // per-instance "some det F <= 0" flags
 
   // linearization
   bool lin64 = false, lin32 = false;
@@ -130,7 +144,11 @@ void drop_graph(Ctx *c);
   } while (0)
 
 // mesh preparation (host)
-nle_status build_mesh(Ctx *c, int64_t n_nodes, const double *X, int64_t n_elems, const int32_t *conn);
+// inst_elem / inst_node: instance offsets (size n_inst + 1) of a disjoint
+// union of meshes (element and node ranges); null for a single mesh.
+nle_status build_mesh(Ctx *c, int64_t n_nodes, const double *X, int64_t n_elems, const int32_t *conn,
+                      const std::vector<int64_t> *inst_elem = nullptr,
+                      const std::vector<int64_t> *inst_node = nullptr);
 nle_status upload_node_masks(Ctx *c);
 
 // ---- element kernels (nle_elem.hip) ---------------------------------------

@@ -59,7 +59,11 @@ T *upload(Ctx *c, const std::vector<T> &h, hipError_t *e) {
 
 }  // namespace
 
-nle_status build_mesh(Ctx *c, int64_t nn, const double *X, int64_t ne, const int32_t *conn) {
+nle_status build_mesh(Ctx *c, int64_t nn, const double *X, int64_t ne, const int32_t *conn,
+                      const std::vector<int64_t> *inst_elem, const std::vector<int64_t> *inst_node) {
+  std::vector<int64_t> ie = inst_elem ? *inst_elem : std::vector<int64_t>{0, ne};
+  std::vector<int64_t> in = inst_node ? *inst_node : std::vector<int64_t>{0, nn};
+  const int32_t n_inst = int32_t(ie.size()) - 1;
   if (nn <= 0 || ne <= 0) return fail(c, NLE_E_INVAL, "mesh needs n_nodes > 0 and n_elems > 0");
   if (nn >= (int64_t(1) << 28)) return fail(c, NLE_E_UNSUPPORTED, "n_nodes must be < 2^28");
   if (!X || !conn) return fail(c, NLE_E_INVAL, "null mesh array");
@@ -114,12 +118,19 @@ nle_status build_mesh(Ctx *c, int64_t nn, const double *X, int64_t ne, const int
   std::vector<int64_t> perm(ne);
   std::iota(perm.begin(), perm.end(), int64_t(0));
   std::vector<int64_t> starts;
-  rcb(perm, 0, ne, cen, be, starts);
-  std::sort(starts.begin(), starts.end());
+  std::vector<int32_t> inst_blk(n_inst + 1, 0);
+  for (int32_t i = 0; i < n_inst; ++i) {  // blocks never span two instances
+    const size_t s0 = starts.size();
+    rcb(perm, ie[i], ie[i + 1], cen, be, starts);
+    std::sort(starts.begin() + s0, starts.end());
+    inst_blk[i + 1] = int32_t(starts.size());
+  }
   const int32_t nblk = int32_t(starts.size());
-  std::vector<int32_t> blk_elem(nblk + 1);
+  std::vector<int32_t> blk_elem(nblk + 1), blk_inst(nblk);
   for (int32_t b = 0; b < nblk; ++b) blk_elem[b] = int32_t(starts[b]);
   blk_elem[nblk] = int32_t(ne);
+  for (int32_t i = 0; i < n_inst; ++i)
+    for (int32_t b = inst_blk[i]; b < inst_blk[i + 1]; ++b) blk_inst[b] = i;
   for (int32_t b = 0; b < nblk; ++b)  // elements of a block in user order
     std::sort(perm.begin() + blk_elem[b], perm.begin() + blk_elem[b + 1]);
 
@@ -172,14 +183,25 @@ nle_status build_mesh(Ctx *c, int64_t nn, const double *X, int64_t ne, const int
   const int64_t n_slots = int64_t(nodes.size());
 
   // ---- shared nodes and their merge lists (slots in block order) -------------
+  // With several instances each instance's shared nodes start on a whole
+  // merge workgroup (padding entries: id 0xFFFFFFFF, empty slot range).
   std::vector<int32_t> fx_id(nn, -1);
   std::vector<uint32_t> fx_node;
-  for (int64_t g = 0; g < nn; ++g)
-    if (touch[g] >= 2) {
-      fx_id[g] = int32_t(fx_node.size());
-      fx_node.push_back(uint32_t(g));
-    }
+  std::vector<int32_t> inst_mwg(n_inst + 1, 0);
+  for (int32_t i = 0; i < n_inst; ++i) {
+    for (int64_t g = in[i]; g < in[i + 1]; ++g)
+      if (touch[g] >= 2) {
+        fx_id[g] = int32_t(fx_node.size());
+        fx_node.push_back(uint32_t(g));
+      }
+    if (n_inst > 1)
+      while (fx_node.size() % NT != 0) fx_node.push_back(0xFFFFFFFFu);
+    inst_mwg[i + 1] = int32_t((fx_node.size() + NT - 1) / NT);
+  }
   const int64_t n_sh = int64_t(fx_node.size());
+  std::vector<int32_t> mwg_inst(inst_mwg[n_inst]);
+  for (int32_t i = 0; i < n_inst; ++i)
+    for (int32_t w = inst_mwg[i]; w < inst_mwg[i + 1]; ++w) mwg_inst[w] = i;
   std::vector<int32_t> fx_ptr(n_sh + 1, 0), fx_slot;
   for (int64_t p = 0; p < n_slots; ++p) {
     int32_t f = fx_id[nodes[p]];
@@ -242,6 +264,16 @@ nle_status build_mesh(Ctx *c, int64_t nn, const double *X, int64_t ne, const int
   M.nodes = upload(c, nodes, &herr);
   M.blk_elem = upload(c, blk_elem, &herr);
   M.blk_node = upload(c, blk_node, &herr);
+  M.n_inst = n_inst;
+  M.n_mwg = inst_mwg[n_inst];
+  M.h_inst_elem = ie;
+  M.h_inst_node = in;
+  M.h_inst_blk = inst_blk;
+  M.h_inst_mwg = inst_mwg;
+  if (n_inst > 1) {
+    M.blk_inst = upload(c, blk_inst, &herr);
+    if (!mwg_inst.empty()) M.mwg_inst = upload(c, mwg_inst, &herr);
+  }
   if (n_sh > 0) {
     M.fx_node = upload(c, fx_node, &herr);
     M.fx_ptr = upload(c, fx_ptr, &herr);
@@ -299,7 +331,8 @@ nle_status upload_node_masks(Ctx *c) {
   Mesh &M = c->m;
   std::vector<uint32_t> nodes(M.h_nodes), fx(M.h_fx_node);
   for (auto &w : nodes) w |= uint32_t(c->h_mask[w & NODE_MASK] & 7u) << 28;
-  for (auto &w : fx) w |= uint32_t(c->h_mask[w] & 7u) << 28;
+  for (auto &w : fx)
+    if (w != 0xFFFFFFFFu) w |= uint32_t(c->h_mask[w] & 7u) << 28;
   NLE_HIP(c, hipMemcpyAsync(M.nodes, nodes.data(), nodes.size() * 4, hipMemcpyHostToDevice, c->stream));
   if (!fx.empty())
     NLE_HIP(c, hipMemcpyAsync(M.fx_node, fx.data(), fx.size() * 4, hipMemcpyHostToDevice, c->stream));

@@ -45,7 +45,9 @@ EXPORTS = [
     "nle_upload_mesh", "nle_set_material", "nle_set_dirichlet", "nle_set_traction",
     "nle_set_body_force", "nle_set_load_scale", "nle_lift", "nle_residual", "nle_linearize",
     "nle_jv", "nle_diag", "nle_energy", "nle_default_opts", "nle_solve_nk", "nle_solve_ink",
-    "nle_solve_bfgs", "nle_partition_info",
+    "nle_solve_bfgs", "nle_partition_info", "nle_batch_create", "nle_batch_destroy",
+    "nle_batch_last_error", "nle_batch_add", "nle_batch_finalize", "nle_batch_layout",
+    "nle_batch_solve",
 ]
 
 
@@ -117,6 +119,15 @@ def lib() -> ctypes.CDLL:
         "nle_solve_ink": (I32, [P, P, ctypes.POINTER(nle_solver_opts), ctypes.POINTER(nle_report)]),
         "nle_solve_bfgs": (I32, [P, P, ctypes.POINTER(nle_solver_opts), ctypes.POINTER(nle_report)]),
         "nle_partition_info": (I32, [P, ctypes.POINTER(I64)]),
+        "nle_batch_create": (I32, [ctypes.POINTER(P), I32, P, ctypes.POINTER(nle_allocator)]),
+        "nle_batch_destroy": (None, [P]),
+        "nle_batch_last_error": (ctypes.c_char_p, [P]),
+        "nle_batch_add": (I32, [P, I64, P, I64, P, I32, P, I32, I64, P, P, I64, P, P, I32, P,
+                                ctypes.POINTER(I32)]),
+        "nle_batch_finalize": (I32, [P]),
+        "nle_batch_layout": (I32, [P, ctypes.POINTER(I64)]),
+        "nle_batch_solve": (I32, [P, I32, ctypes.POINTER(nle_solver_opts), P,
+                                  ctypes.POINTER(nle_report), ctypes.POINTER(D)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -336,3 +347,121 @@ def nle_partition_info(ctx: Context) -> dict:
     keys = ["n_blocks", "max_elems_per_block", "max_nodes_per_block", "block_node_slots",
             "shared_nodes", "merge_slots", "lds_bytes_fp64_jv", "lds_bytes_fp32_jv"]
     return dict(zip(keys, list(info)))
+
+
+# ---- batched solves -------------------------------------------------------------
+class Batch:
+    """An nle_batch: many independent problems solved together on one device."""
+
+    def __init__(self, device: int = 0, use_torch_allocator: bool = True):
+        import torch
+
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        L = lib()
+        self._keep = []
+        alloc_p = None
+        if use_torch_allocator:
+            dev = device
+
+            @ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+            def _alloc(nbytes, user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), dev)
+                except Exception:  # noqa: BLE001 - the C side reports OOM
+                    return None
+
+            @ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+            def _free(ptr, user):
+                if ptr:
+                    torch.cuda.caching_allocator_delete(ptr)
+
+            al = nle_allocator(_alloc, _free, None)
+            self._keep += [_alloc, _free, al]
+            alloc_p = ctypes.pointer(al)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        st = L.nle_batch_create(ctypes.byref(h), device, ctypes.c_void_p(self.stream.cuda_stream),
+                                alloc_p)
+        if st != NLE_OK:
+            raise NleError(st, "nle_batch_create failed")
+        self.handle = h
+        self.n_inst = 0
+        self.offsets = None
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().nle_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+    def check(self, st: int) -> int:
+        if st < 0:
+            msg = lib().nle_batch_last_error(self.handle)
+            raise NleError(st, msg.decode() if msg else "")
+        return st
+
+
+def nle_batch_create(device: int = 0, use_torch_allocator: bool = True) -> Batch:
+    return Batch(device, use_torch_allocator)
+
+
+def nle_batch_destroy(b: Batch) -> None:
+    b.close()
+
+
+def nle_batch_last_error(b: Batch) -> str:
+    return lib().nle_batch_last_error(b.handle).decode()
+
+
+def nle_batch_add(b: Batch, X, conn, kind: int, params, dofs, values, tri, traction,
+                  scales) -> int:
+    X, px = _host(X, np.float64)
+    conn, pc = _host(conn, np.int32)
+    p, pp = _host(params, np.float64)
+    d, pd = _host(dofs, np.int64)
+    v, pv = _host(values, np.float64)
+    f, pf = _host(tri, np.int32)
+    t, pt = _host(traction, np.float64)
+    s, ps = _host(scales, np.float64)
+    out = ctypes.c_int32()
+    b.check(lib().nle_batch_add(b.handle, X.shape[0], px, conn.shape[0], pc, int(kind), pp,
+                                p.size, d.size, pd, pv, f.shape[0] if f.size else 0, pf, pt,
+                                s.size, ps, ctypes.byref(out)))
+    b.n_inst = out.value + 1
+    return out.value
+
+
+def nle_batch_finalize(b: Batch) -> None:
+    b.check(lib().nle_batch_finalize(b.handle))
+    off = (ctypes.c_int64 * (b.n_inst + 1))()
+    b.check(lib().nle_batch_layout(b.handle, off))
+    b.offsets = np.array(off[:], dtype=np.int64)
+
+
+def nle_batch_layout(b: Batch):
+    return b.offsets
+
+
+def nle_batch_solve(b: Batch, method: int, opts: nle_solver_opts, u):
+    """Solve all instances; u is the concatenated float64 device vector.
+    Returns (status, list of per-instance report dicts, t_ms)."""
+    torch = b.torch
+    n = int(3 * b.offsets[-1])
+    if (not isinstance(u, torch.Tensor) or u.device != b.device or u.dtype != torch.float64
+            or not u.is_contiguous() or u.numel() != n):
+        raise ValueError(f"expected a contiguous float64 tensor of {n} entries on the device")
+    reps = (nle_report * b.n_inst)()
+    tms = ctypes.c_double()
+    st = b.check(lib().nle_batch_solve(b.handle, int(method), ctypes.byref(opts),
+                                       ctypes.c_void_p(u.data_ptr()), reps, ctypes.byref(tms)))
+    out = [dict(status=r.status, status_name=STATUS_NAMES.get(r.status, str(r.status)),
+                nit=r.nit, lit_total=r.lit_total, n_jv=r.n_jv, n_residual=r.n_residual,
+                cutbacks=r.bfgs_skipped, rnorm0=r.rnorm0, rnorm_final=r.rnorm_final)
+           for r in reps]
+    return st, out, tms.value

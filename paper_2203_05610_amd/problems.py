@@ -91,3 +91,11 @@ def solve_schedule(ctx: nl.Context, u, method: str, opts, scales, hist_cap: int 
 def schedule_ok(reps, scales) -> bool:
     acc = [r["load_scale"] for r in reps if r["accepted"]]
     return bool(acc) and abs(acc[-1] - float(scales[-1])) == 0.0
+
+
+def add_cook_instance(batch: nl.Batch, mesh, mu: float, lam: float, tau: float, scales,
+                      material: int = nl.NLE_MAT_M1) -> int:
+    """One Cook's-membrane instance: traction (0, tau, 0) times each load scale."""
+    dofs = mesh.dirichlet_dofs("clamp")
+    return nl.nle_batch_add(batch, mesh.X, mesh.conn, material, [mu, lam], dofs,
+                            np.zeros(dofs.size), mesh.faces["load"], [0.0, tau, 0.0], scales)
