@@ -179,6 +179,84 @@ def cpu_baseline(n_load_steps: int):
     }
 
 
+def batch_c4(nl, torch, count: int, serial_stride: int, steps: int):
+    """Batched solves: `count` sampled Cook instances (uneven size, lambda/mu and
+    traction; doubling load schedules ending at each tau) solved in one batch
+    with mixed iNK, against serial FP64 NK solves of every `serial_stride`-th
+    instance on the same GPU (the serial time is that sample times the stride)."""
+    import numpy as np
+
+    import synthetic as syn
+    from paper_2203_05610_amd import problems
+
+    recipe = syn.batch_recipe(count)
+    t = time.perf_counter()
+    B = nl.Batch(0)
+    meshes, n_elems = [], 0
+    for r in recipe:
+        m = syn.cook_mesh(r["nx"], r["ny"], r["nz"])
+        problems.add_cook_instance(B, m, r["mu"], r["lam"], 1.0, syn.cook_load_schedule(r["tau"]))
+        meshes.append(m)
+        n_elems += m.conn.shape[0]
+    nl.nle_batch_finalize(B)
+    off = nl.nle_batch_layout(B)
+    u = torch.zeros(int(3 * off[-1]), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t
+    print(f"[bench] batch of {count}: {n_elems} tets, {int(off[-1])} nodes, setup {t_setup:.1f}s",
+          file=sys.stderr, flush=True)
+    opts = problems.make_opts("ink", "mixed", ksp="cg")
+    times, oks = [], []
+    for k in range(steps):
+        u.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st, reps, _ = nl.nle_batch_solve(B, nl.NLE_INK, opts, u)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+        oks.append(sum(r["status"] == nl.NLE_OK for r in reps))
+        print(f"[bench] batch solve {k}: {times[-1]:.2f}s, {oks[-1]}/{count} solved, "
+              f"max nit {max(r['nit'] for r in reps)}, max lit {max(r['lit_total'] for r in reps)}",
+              file=sys.stderr, flush=True)
+    B.close()
+    t_batch = float(np.median(times))
+    serial = None
+    if serial_stride > 0:
+        ctx = nl.Context(0)
+        tot, n_ok, ids = 0.0, 0, list(range(0, count, serial_stride))
+        for i in ids:
+            r, m = recipe[i], meshes[i]
+            problems.setup_cook(ctx, m, r["mu"], r["lam"], 1.0)
+            v = torch.zeros(3 * m.n_nodes, dtype=torch.float64, device="cuda")
+            sched = syn.cook_load_schedule(r["tau"])
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            reps = problems.solve_schedule(ctx, v, "nk", problems.make_opts("nk", "fp64", ksp="minres"),
+                                           sched)
+            torch.cuda.synchronize()
+            tot += time.perf_counter() - t
+            n_ok += problems.schedule_ok(reps, sched)
+            print(f"[bench] serial NK fp64 instance {i} ({m.conn.shape[0]} tets): "
+                  f"{time.perf_counter() - t:.2f}s", file=sys.stderr, flush=True)
+        ctx.close()
+        est = tot * count / len(ids)
+        serial = {"method": "nk_fp64 (MINRES + Jacobi), one instance at a time",
+                  "sample": f"instances {ids[0]}, {ids[0] + serial_stride}, ... ({len(ids)} of {count})",
+                  "sample_seconds": round(tot, 3), "solved": f"{n_ok}/{len(ids)}",
+                  "estimated_seconds_all": round(est, 2),
+                  "instances_per_s": round(count / est, 3)}
+    return {
+        "workload": f"{count} Cook instances (n x n x nz, n in 8..48, nz in 1..3, "
+                    "lambda/mu log-uniform 10..1e4, tau 2^U(0,5)), seed 0",
+        "tets": n_elems, "nodes": int(off[-1]), "setup_s": round(t_setup, 2),
+        "method": "iNK mixed, CG + Jacobi, all instances per launch",
+        "seconds": [round(x, 3) for x in times], "solved": f"{min(oks)}/{count}",
+        "instances_per_s": round(count / t_batch, 3),
+        "serial_fp64_nk": serial,
+        "speedup_vs_serial": round(serial["estimated_seconds_all"] / t_batch, 2) if serial else None,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -191,6 +269,11 @@ def main():
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-baseline", action="store_true")
+    ap.add_argument("--batch", type=int, default=256,
+                    help="instances of the batched-solve leg (0 skips it)")
+    ap.add_argument("--batch-serial-stride", type=int, default=64,
+                    help="serial FP64 NK baseline on every k-th batch instance (0 skips it)")
+    ap.add_argument("--batch-only", action="store_true", help="only the batched-solve leg")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the Jv roofline phase (plus a 256 MB copy kernel used to "
                          "calibrate HBM byte counters); for profiling runs")
@@ -214,6 +297,12 @@ def main():
             torch.neg(x, out=z)  # plain copy kernel: 256 MiB read + 256 MiB written
         torch.cuda.synchronize()
         print(json.dumps({"roofline_only": True, "jv": jv}))
+        return
+
+    if args.batch_only:
+        print(json.dumps({"batch_only": True,
+                          "batch": batch_c4(nl, torch, args.batch, args.batch_serial_stride,
+                                            max(args.steps, 1))}))
         return
 
     schedule = load_schedule()
@@ -284,6 +373,10 @@ def main():
         }
         print(f"[bench] Jv roofline fp32 {f['gbs']:.0f} GB/s", file=sys.stderr, flush=True)
 
+    batch = None
+    if args.batch > 0:
+        batch = batch_c4(nl, torch, args.batch, args.batch_serial_stride, 1)
+
     cpu = None
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle, 1 thread)", file=sys.stderr, flush=True)
@@ -320,6 +413,7 @@ def main():
         "speedup_vs_gpu_baseline": (round(base["seconds"] / value, 3)
                                     if base and base["ok"] and all_ok else None),
         "compare": extra or None,
+        "batch": batch,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
