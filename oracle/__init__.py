@@ -11,14 +11,19 @@ What it computes (paper sections cited per function):
 * materials  -- strain energies Psi(F) and first Piola stresses P = dPsi/dF
                 for the compressible neo-Hookean law (M1) and the paper's
                 Cook law with an isochoric / volumetric split (M2) (Sec. 2,
-                Sec. 4 "Cook test").
+                Sec. 4 "Cook test"), and the cardiac-like law M4
+                (exponential isotropic and fibre terms, volumetric penalty,
+                the active stress of Sec. 4 "Heartbeat test").
 * fem        -- P1 tetrahedral geometry, internal forces, the residual
                 r(u) = f_int(u) - f_ext (the quasi-static balance of Sec. 2
                 written as the gradient of the potential of Sec. 3, eq.
-                "minimization"), the potential itself, dead tractions, and
+                "minimization"), the potential itself, dead tractions, the
+                follower endocardial pressure and elastic Robin springs of
+                the heartbeat test, and
                 the tangent stiffness assembled as a sparse matrix from
                 complex-step derivatives of P.
-* newton     -- exact Newton (eq. "newton" with a direct sparse solve).
+* newton     -- exact Newton (eq. "newton" with a direct sparse solve), over
+                load schedules and the heartbeat's time steps.
 * solvers    -- plain GMRES (right preconditioned, modified Gram-Schmidt),
                 CG, the Eisenstat-Walker forcing term, L-BFGS two-loop
                 recursion and the dense BFGS inverse update of Sec. 3, and

@@ -80,6 +80,69 @@ def dead_traction(X: np.ndarray, tri: np.ndarray, t: Sequence[float]) -> np.ndar
     return out.reshape(-1)
 
 
+def follower_pressure(X: np.ndarray, u: np.ndarray, tri: np.ndarray, p: float) -> np.ndarray:
+    """Nodal residual contribution of a follower pressure p on triangles tri.
+
+    The pressure acts on the current surface (x = X + u) against the body's
+    outward normal; on a flat linear triangle with current area vector
+    a = (x1 - x0) x (x2 - x0) / 2 the consistent load is -p a / 3 per vertex
+    (exact), so r gains +p a / 3 at each vertex.  Valid for complex u.
+    """
+    x = np.asarray(X)[tri] + np.asarray(u).reshape(-1, 3)[tri]  # (f, 3, 3)
+    a2 = np.cross(x[:, 1] - x[:, 0], x[:, 2] - x[:, 0])
+    out = np.zeros((X.shape[0], 3), dtype=a2.dtype)
+    for i in range(3):
+        w = np.repeat(p * a2[:, i] / 6.0, 3)
+        idx = tri.reshape(-1)
+        if np.iscomplexobj(w):
+            out[:, i] = (np.bincount(idx, weights=w.real, minlength=X.shape[0])
+                         + 1j * np.bincount(idx, weights=w.imag, minlength=X.shape[0]))
+        else:
+            out[:, i] = np.bincount(idx, weights=w, minlength=X.shape[0])
+    return out.reshape(-1)
+
+
+def follower_pressure_jacobian(X: np.ndarray, u: np.ndarray, tri: np.ndarray, p: float,
+                               h: float = 1e-30) -> sp.csr_matrix:
+    """d(follower_pressure)/du, assembled from per-face complex-step blocks
+    (9 x 9 per triangle).  Not symmetric in general."""
+    X = np.asarray(X, dtype=np.float64)
+    x = X[tri] + np.asarray(u, dtype=np.float64).reshape(-1, 3)[tri]
+    nf = tri.shape[0]
+    Kf = np.empty((nf, 3, 3, 3, 3))  # [f, a, i, b, k]
+    for b in range(3):
+        for k in range(3):
+            xc = x.astype(np.complex128)
+            xc[:, b, k] += 1j * h
+            d = np.cross(xc[:, 1] - xc[:, 0], xc[:, 2] - xc[:, 0]).imag / h  # (f, 3)
+            Kf[:, :, :, b, k] = (p / 6.0) * d[:, None, :]
+    dofs = (3 * tri[:, :, None] + np.arange(3)[None, None, :]).reshape(nf, 9)
+    rows = np.repeat(dofs, 9, axis=1).reshape(-1)
+    cols = np.tile(dofs, (1, 9)).reshape(-1)
+    n = 3 * X.shape[0]
+    return sp.coo_matrix((Kf.reshape(-1), (rows, cols)), shape=(n, n)).tocsr()
+
+
+def robin_matrix(X: np.ndarray, tri: np.ndarray, k_perp: float, k_par: float) -> sp.csr_matrix:
+    """Elastic Robin condition of Sec. 4 ("Heartbeat test", epicardium, without
+    its damping terms): traction -[k_perp N (x) N + k_par (I - N (x) N)] u with
+    the reference unit normal N.  Its residual contribution is R u with
+    R_(a,b) = M_ab K, M_ab = A (1 + delta_ab) / 12 (exact P1 face mass)."""
+    X = np.asarray(X, dtype=np.float64)
+    a2 = np.cross(X[tri[:, 1]] - X[tri[:, 0]], X[tri[:, 2]] - X[tri[:, 0]])
+    A = 0.5 * np.linalg.norm(a2, axis=1)
+    N = a2 / (2.0 * A)[:, None]
+    K = k_par * np.eye(3)[None] + (k_perp - k_par) * np.einsum("fi,fj->fij", N, N)
+    M = (np.ones((3, 3)) + np.eye(3)) / 12.0
+    Kf = np.einsum("f,ab,fik->faibk", A, M, K)
+    nf = tri.shape[0]
+    dofs = (3 * tri[:, :, None] + np.arange(3)[None, None, :]).reshape(nf, 9)
+    rows = np.repeat(dofs, 9, axis=1).reshape(-1)
+    cols = np.tile(dofs, (1, 9)).reshape(-1)
+    n = 3 * X.shape[0]
+    return sp.coo_matrix((Kf.reshape(-1), (rows, cols)), shape=(n, n)).tocsr()
+
+
 @dataclass
 class Problem:
     """A P1 quasi-static problem: mesh, law, loads and Dirichlet data.
@@ -95,6 +158,13 @@ class Problem:
     f_ext: np.ndarray
     ddofs: np.ndarray
     dvals: np.ndarray
+    # optional surface loads: follower pressure (scaled by the load scale)
+    # and elastic Robin springs
+    pressure_tri: Optional[np.ndarray] = None
+    pressure: float = 0.0
+    robin_tri: Optional[np.ndarray] = None
+    k_perp: float = 0.0
+    k_par: float = 0.0
 
     def __post_init__(self):
         self.conn = np.asarray(self.conn)[:, :4].astype(np.int64)
@@ -106,6 +176,18 @@ class Problem:
         self.fixed = np.zeros(self.n_dofs, dtype=bool)
         self.fixed[np.asarray(self.ddofs, dtype=np.int64)] = True
         self.free = ~self.fixed
+        self.R = (robin_matrix(self.X, np.asarray(self.robin_tri), self.k_perp, self.k_par)
+                  if self.robin_tri is not None else None)
+
+    def surface_force(self, u: np.ndarray, load_scale: float = 1.0) -> np.ndarray:
+        """Residual contribution of the follower pressure and the springs."""
+        out = np.zeros(self.n_dofs)
+        if self.pressure_tri is not None:
+            out += follower_pressure(self.X, u, np.asarray(self.pressure_tri),
+                                     load_scale * self.pressure)
+        if self.R is not None:
+            out += self.R @ u
+        return out
 
     # -- evaluation -------------------------------------------------------
     def lift(self, u: np.ndarray) -> np.ndarray:
@@ -120,7 +202,7 @@ class Problem:
         return scatter_nodal(self.n_nodes, self.conn, fe)
 
     def residual(self, u: np.ndarray, load_scale: float = 1.0) -> np.ndarray:
-        r = self.internal_force(u) - load_scale * self.f_ext
+        r = self.internal_force(u) - load_scale * self.f_ext + self.surface_force(u, load_scale)
         r[self.fixed] = 0.0
         return r
 
@@ -129,8 +211,11 @@ class Problem:
 
     def energy(self, u: np.ndarray, load_scale: float = 1.0) -> float:
         F = deformation_gradient(u, self.conn, self.G)
+        if self.pressure_tri is not None:
+            raise ValueError("a follower pressure has no potential")
         psi = materials.energy(self.material, F, self.params)
-        return float(np.sum(self.V * psi) - load_scale * np.dot(self.f_ext, u))
+        springs = 0.5 * float(u @ (self.R @ u)) if self.R is not None else 0.0
+        return float(np.sum(self.V * psi) - load_scale * np.dot(self.f_ext, u)) + springs
 
     # -- tangent ----------------------------------------------------------
     def element_stiffness(self, u: np.ndarray) -> np.ndarray:
@@ -140,25 +225,31 @@ class Problem:
         Ke = np.einsum("e,eiJkL,eaJ,ebL->eaibk", self.V, A, self.G, self.G, optimize=True)
         return Ke.reshape(-1, 12, 12)
 
-    def stiffness(self, u: np.ndarray, dirichlet: bool = True) -> sp.csr_matrix:
+    def stiffness(self, u: np.ndarray, dirichlet: bool = True,
+                  load_scale: float = 1.0) -> sp.csr_matrix:
         """Assembled tangent dr/du (CSR); identity rows/cols on Dirichlet dofs."""
         Ke = self.element_stiffness(u)
         dofs = (3 * self.conn[:, :, None] + np.arange(3)[None, None, :]).reshape(-1, 12)
         rows = np.repeat(dofs, 12, axis=1).reshape(-1)
         cols = np.tile(dofs, (1, 12)).reshape(-1)
         K = sp.coo_matrix((Ke.reshape(-1), (rows, cols)), shape=(self.n_dofs, self.n_dofs)).tocsr()
+        if self.pressure_tri is not None:
+            K = K + follower_pressure_jacobian(self.X, u, np.asarray(self.pressure_tri),
+                                               load_scale * self.pressure)
+        if self.R is not None:
+            K = K + self.R
         if dirichlet:
             Dfree = sp.diags(self.free.astype(np.float64))
             K = (Dfree @ K @ Dfree + sp.diags(self.fixed.astype(np.float64))).tocsr()
         return K
 
-    def jv(self, u: np.ndarray, v: np.ndarray) -> np.ndarray:
+    def jv(self, u: np.ndarray, v: np.ndarray, load_scale: float = 1.0) -> np.ndarray:
         """Jacobian action J(u) v with identity rows/cols on Dirichlet dofs."""
-        return self.stiffness(u) @ v
+        return self.stiffness(u, load_scale=load_scale) @ v
 
-    def diagonal(self, u: np.ndarray) -> np.ndarray:
+    def diagonal(self, u: np.ndarray, load_scale: float = 1.0) -> np.ndarray:
         """Diagonal of the tangent (1 on Dirichlet dofs)."""
-        return self.stiffness(u).diagonal()
+        return self.stiffness(u, load_scale=load_scale).diagonal()
 
 
 def cook_problem(mesh, mu: float = 80.194, lam: float = 400.9, tau: float = 1.0,
@@ -171,3 +262,25 @@ def cook_problem(mesh, mu: float = 80.194, lam: float = 400.9, tau: float = 1.0,
     f_ext = dead_traction(mesh.X, mesh.faces["load"], (0.0, tau, 0.0))
     ddofs = mesh.dirichlet_dofs("clamp")
     return Problem(mesh.X, mesh.conn, material, params, f_ext, ddofs, np.zeros(ddofs.size))
+
+
+def cardiac_problem(mesh, consts: dict, gamma: float = 0.0) -> Problem:
+    """Cardiac-like shell (Sec. 4, "Heartbeat test", quasi-static): law M4 with
+    the mesh's per-element fibres and active tension gamma, follower pressure
+    p_max on the endocardium (times the load scale), elastic Robin springs on
+    the epicardium, base plane held in z plus three circumferential pins."""
+    from synthetic import shell_dirichlet
+
+    c = consts
+    params = (c["a"], c["b"], c["af"], c["bf"], c["kappa"], gamma, mesh.elem_fibre)
+    ddofs = shell_dirichlet(mesh)
+    return Problem(mesh.X, mesh.conn, materials.M4, params, np.zeros(3 * mesh.n_nodes), ddofs,
+                   np.zeros(ddofs.size), pressure_tri=mesh.faces["endo"], pressure=c["p_max"],
+                   robin_tri=mesh.faces["epi"], k_perp=c["k_perp"], k_par=c["k_par"])
+
+
+def set_active_tension(problem: Problem, gamma: float) -> None:
+    """Replace the active tension gamma of an M4 problem."""
+    p = list(problem.params)
+    p[5] = gamma
+    problem.params = tuple(p)

@@ -17,6 +17,17 @@ M2  the paper's Cook law (Sec. 4, "Cook test"), C1 = mu/2, kappa = lambda + 2 mu
     The printed law has c_vol = 1; we use c_vol = 1/4 by default, the value
     for which the small-strain limit has bulk modulus kappa (Lame lambda
     recovered exactly).  c_vol is the third parameter.
+M4  the cardiac-like law: an exponential isotropic term of Holzapfel-Ogden
+    type, an exponential fibre term active in fibre tension only, a volumetric
+    penalty, and the active stress of Sec. 4 ("Heartbeat test": P_act =
+    gamma (F f) (x) f / |F f|), which is the gradient of gamma |F f|:
+      Psi = a/(2b) (exp(b (J^(-2/3) I1 - 3)) - 1)
+            + af/(2bf) (exp(bf (I4 - 1)^2) - 1) [I4 > 1]
+            + kappa/2 (J - 1)^2 + gamma sqrt(I4),        I4 = |F f|^2
+    params = (a, b, af, bf, kappa, gamma, fib) with fib the unit fibre
+    direction(s), shape (..., 3) broadcasting against F.  The paper's own
+    Guccione law needs constants it does not print; this law and its
+    constants are a stated substitute.
 """
 
 from __future__ import annotations
@@ -25,6 +36,7 @@ import numpy as np
 
 M1 = "M1"
 M2 = "M2"
+M4 = "M4"
 
 
 def _det(F):
@@ -57,8 +69,24 @@ def inv_transpose(F):
     return _cofactor(F) / _det(F)[..., None, None]
 
 
+def _fibre_terms(F, params):
+    """Ff = F f, I4 = |F f|^2 and the fibre direction (M4)."""
+    f = np.asarray(params[6], dtype=np.float64)
+    Ff = np.einsum("...ij,...j->...i", F, f)
+    I4 = np.einsum("...i,...i->...", Ff, Ff)
+    return f, Ff, I4
+
+
 def energy(kind: str, F, params):
     """Strain energy density Psi(F)."""
+    if kind == M4:
+        a, b, af, bf, kappa, gamma = (float(x) for x in params[:6])
+        J = _det(F)
+        I1 = np.einsum("...ij,...ij->...", F, F)
+        _, _, I4 = _fibre_terms(F, params)
+        iso = a / (2.0 * b) * (np.exp(b * (J ** (-2.0 / 3.0) * I1 - 3.0)) - 1.0)
+        fib = np.where(np.real(I4) > 1.0, af / (2.0 * bf) * (np.exp(bf * (I4 - 1.0) ** 2) - 1.0), 0.0)
+        return iso + fib + 0.5 * kappa * (J - 1.0) ** 2 + gamma * np.sqrt(I4)
     J = _det(F)
     I1 = np.einsum("...ij,...ij->...", F, F)
     lnJ = np.log(J)
@@ -77,6 +105,20 @@ def piola(kind: str, F, params):
     """First Piola-Kirchhoff stress P(F) = dPsi/dF."""
     J = _det(F)
     FiT = inv_transpose(F)
+    if kind == M4:
+        # d(J^-2/3 I1)/dF = J^-2/3 (2F - 2/3 I1 F^-T), dI4/dF = 2 (Ff) (x) f,
+        # dJ/dF = J F^-T, d sqrt(I4)/dF = (Ff) (x) f / sqrt(I4)
+        a, b, af, bf, kappa, gamma = (float(x) for x in params[:6])
+        I1 = np.einsum("...ij,...ij->...", F, F)
+        f, Ff, I4 = _fibre_terms(F, params)
+        j23 = J ** (-2.0 / 3.0)
+        iso = (a * np.exp(b * (j23 * I1 - 3.0)) * j23)[..., None, None] * (
+            F - (I1 / 3.0)[..., None, None] * FiT)
+        gf = np.where(np.real(I4) > 1.0, 2.0 * af * (I4 - 1.0) * np.exp(bf * (I4 - 1.0) ** 2), 0.0)
+        hf = gf + gamma / np.sqrt(I4)
+        fibre = hf[..., None, None] * np.einsum("...i,...j->...ij", Ff, np.broadcast_to(f, Ff.shape))
+        vol = (kappa * (J - 1.0) * J)[..., None, None] * FiT
+        return iso + fibre + vol
     if kind == M1:
         mu, lam = params[0], params[1]
         lnJ = np.log(J)

@@ -38,7 +38,7 @@ def newton_exact(problem, u0: np.ndarray, load_scale: float = 1.0, rtol: float =
     for _ in range(max_it):
         if hist[-1] <= rtol * r0:
             return u, hist
-        K = problem.stiffness(u)
+        K = problem.stiffness(u, load_scale=load_scale)
         du = spla.splu(K.tocsc()).solve(-r)
         u_new = u + du
         if problem.min_jacobian(u_new) <= 0.0:
@@ -60,5 +60,20 @@ def solve_schedule(problem, scales, u0=None, **kw):
     hists = []
     for s in scales:
         u, h = newton_exact(problem, u, s, **kw)
+        hists.append(h)
+    return u, hists
+
+
+def solve_heartbeat(problem, schedule, gamma_max: float, u0=None, **kw):
+    """Quasi-static heartbeat (Sec. 4): for each time step (t, shape) set the
+    active tension gamma_max * shape and the pressure load scale shape, then
+    exact Newton warm-started from the previous step."""
+    from .fem import set_active_tension
+
+    u = np.zeros(problem.n_dofs) if u0 is None else np.array(u0, dtype=np.float64)
+    hists = []
+    for _, shape in schedule:
+        set_active_tension(problem, gamma_max * shape)
+        u, h = newton_exact(problem, u, shape, **kw)
         hists.append(h)
     return u, hists

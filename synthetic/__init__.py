@@ -28,4 +28,7 @@ from .fields import (  # noqa: F401
     cook_load_schedule,
     twist_dirichlet,
     twist_angles,
+    CARDIAC,
+    heartbeat_schedule,
+    shell_dirichlet,
 )

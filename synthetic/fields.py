@@ -76,3 +76,37 @@ def twist_dirichlet(X: np.ndarray, bottom: np.ndarray, top: np.ndarray, theta: f
     vals = np.concatenate([np.zeros(3 * b.size), ux, uy])
     order = np.argsort(dofs, kind="stable")
     return dofs[order], vals[order]
+
+
+# Cardiac-like workload (heartbeat test of Sec. 4 with a substitute law; units
+# mm, N, MPa).  Builder-chosen constants: passive a, b (isotropic exponential),
+# af = 2a, bf (fibre exponential), kappa = 1000 a (volumetric penalty); peak
+# active tension 60 kPa and endocardial pressure 2 kPa; epicardial springs
+# K_perp, K_par per unit reference area.  The passive stiffness a = 0.1 MPa is
+# the softest tried (0.01, 0.05, 0.1) for which every one of the 20 steps
+# converges with full Newton steps from the previous step.
+CARDIAC = dict(a=0.1, b=5.0, af=0.2, bf=5.0, kappa=100.0, gamma_max=0.06, p_max=0.002,
+               k_perp=2e-4, k_par=2e-5, period=0.8, dt=0.02, n_steps=20)
+
+
+def heartbeat_schedule(n_steps: int = 20, dt: float = 0.02, period: float = 0.8) -> list:
+    """Time steps t_n = n dt (n = 1..n_steps) and the activation shape
+    max(sin(2 pi t_n / period), 0) of Sec. 4 ("Heartbeat test"); the active
+    tension and the endocardial pressure both follow this shape."""
+    return [(n * dt, max(math.sin(2.0 * math.pi * n * dt / period), 0.0))
+            for n in range(1, n_steps + 1)]
+
+
+def shell_dirichlet(mesh) -> np.ndarray:
+    """Constrained dofs of the ventricle shell: u_z = 0 on the base plane,
+    plus three circumferential pins on the endocardial base ring (at its
+    +x, +y and -x extremes: u_y, u_x and u_y) against rigid rotation about
+    z and in-plane translation.  Returns sorted dof numbers (values zero)."""
+    base = np.nonzero(mesh.sets["base"])[0]
+    ring = base[mesh.sets["endo"][base]]
+    X = mesh.X
+    px = ring[np.argmax(X[ring, 0])]
+    py = ring[np.argmax(X[ring, 1])]
+    mx = ring[np.argmin(X[ring, 0])]
+    dofs = np.concatenate([3 * base + 2, [3 * px + 1, 3 * py + 0, 3 * mx + 1]])
+    return np.sort(dofs.astype(np.int64))
