@@ -70,6 +70,7 @@ typedef int32_t nle_status;
  *    the small-strain limit.  n_params = 2 takes c_vol = 1/4. */
 #define NLE_MAT_M1 1
 #define NLE_MAT_M2 2
+#define NLE_MAT_M4 4
 
 #define NLE_NK 0   /* Newton-Krylov, fixed linear tolerance (App. A)        */
 #define NLE_INK 1  /* inexact NK, Eisenstat-Walker forcing (Sec. 3, App. A) */
@@ -171,7 +172,14 @@ nle_status nle_set_block_size(nle_ctx *ctx, int32_t elems_per_block);
  * linearization.  n_nodes < 2^28. */
 nle_status nle_upload_mesh(nle_ctx *ctx, int64_t n_nodes, const double *X, int64_t n_elems,
                            int32_t nodes_per_elem, const int32_t *conn);
-/* Material law and parameters (see NLE_MAT_*). */
+/* Material law and parameters (see NLE_MAT_*).  NLE_MAT_M4 (cardiac-like,
+ * Sec. 4 "Heartbeat test" with a stated substitute for its Guccione law):
+ *   Psi = a/(2b) (exp(b (J^-2/3 I1 - 3)) - 1)
+ *         + a_f/(2 b_f) (exp(b_f (I4 - 1)^2) - 1) [I4 > 1]
+ *         + kappa/2 (J - 1)^2 + gamma sqrt(I4),       I4 = |F f|^2,
+ * params = (a, b, a_f, b_f, kappa); the last term is the paper's active
+ * stress gamma (F f) (x) f / |F f| (gamma from nle_set_active_tension, f per
+ * element from nle_set_fibres, both required state for M4). */
 nle_status nle_set_material(nle_ctx *ctx, int32_t kind, const double *params, int32_t n_params);
 /* Dirichlet dofs and their prescribed displacement (host arrays of n
  * entries; dofs unique, in [0, 3 n_nodes)).  Replaces previous data. */
@@ -183,8 +191,29 @@ nle_status nle_set_traction(nle_ctx *ctx, int64_t n_faces, const int32_t *tri, c
 /* Uniform body force f (3 doubles, per unit reference volume): f V_e / 4 per
  * vertex.  Replaces the body-force part of f_ext. */
 nle_status nle_set_body_force(nle_ctx *ctx, const double *f);
-/* Load factor s multiplying f_ext in the residual (default 1). */
+/* Load factor s multiplying f_ext and the follower pressure (default 1). */
 nle_status nle_set_load_scale(nle_ctx *ctx, double s);
+/* Unit fibre direction per element for law M4: fib[n_elems][3] (host, user
+ * element order, copied); NLE_E_INVAL unless every |f| = 1 to 1e-6. */
+nle_status nle_set_fibres(nle_ctx *ctx, const double *fib);
+/* Active tension gamma of law M4 (Sec. 4, the activation function's value at
+ * the current time step; default 0). */
+nle_status nle_set_active_tension(nle_ctx *ctx, double gamma);
+/* Follower pressure p (times the load scale) on n_faces triangles tri[][3]
+ * whose (x1 - x0) x (x2 - x0) points out of the body: it acts on the current
+ * surface, against the outward normal (an endocardial cavity pressure, Sec. 4
+ * "Heartbeat test").  The residual gains p (x1-x0) x (x2-x0) / 6 per vertex
+ * (x = X + u); its Jacobian is not symmetric, so use GMRES.  The Jacobian
+ * action uses the pressure at the time of nle_linearize.  Replaces previous
+ * pressure faces; n_faces = 0 removes them.  With a pressure set, nle_energy
+ * returns NLE_E_UNSUPPORTED (no potential). */
+nle_status nle_set_pressure(nle_ctx *ctx, int64_t n_faces, const int32_t *tri, double p);
+/* Elastic Robin springs on n_faces triangles (the epicardial condition of
+ * Sec. 4 without its damping terms): traction -(k_perp N (x) N + k_par
+ * (I - N (x) N)) u with the reference unit normal N, integrated exactly
+ * (consistent P1 face mass).  Replaces previous spring faces. */
+nle_status nle_set_robin(nle_ctx *ctx, int64_t n_faces, const int32_t *tri, double k_perp,
+                         double k_par);
 
 /* ---- kernels (device vectors of 3 n_nodes entries) ---------------------- */
 /* Write the prescribed Dirichlet values into u (double, device). */
@@ -205,7 +234,9 @@ nle_status nle_jv(nle_ctx *ctx, const void *v_dev, void *y_dev, int32_t prec);
 /* Jacobi data of the current linearization: d = diag J (1 on Dirichlet
  * dofs), double, device. */
 nle_status nle_diag(nle_ctx *ctx, double *d_dev);
-/* Potential Pi(u) = sum_e V_e Psi(F_e) - s f_ext . u (synchronises). */
+/* Potential Pi(u) = sum_e V_e Psi(F_e) - s f_ext . u + u.R u / 2 with R
+ * the spring matrix (synchronises).  NLE_E_UNSUPPORTED with a follower
+ * pressure set. */
 nle_status nle_energy(nle_ctx *ctx, const double *u_dev, double *pi_host);
 
 /* ---- solvers ------------------------------------------------------------- */

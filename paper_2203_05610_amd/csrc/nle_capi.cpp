@@ -91,6 +91,7 @@ nle_status residual_norm(Ctx *c, const double *u, double *r, double *rn, bool *i
 
 nle_status linearize(Ctx *c, const double *u, int prec) {
   const int64_t n = 3 * c->m.n_nodes;
+  NLE_HIP(c, surf_set_linear_pressure(c));
   if (u != c->ulin64)
     NLE_HIP(c, hipMemcpyAsync(c->ulin64, u, n * 8, hipMemcpyDeviceToDevice, c->stream));
   hipError_t e;
@@ -193,6 +194,8 @@ void nle_destroy(nle_ctx *ctx) {
   dfree(c, c->dflag);
   dfree(c, c->dir_dofs);
   dfree(c, c->dir_vals);
+  for (void *p : c->fib_allocs) dfree(c, p);
+  free_surface(c);
   if (c->hpin) (void)hipHostFree(c->hpin);
   if (c->ev_a) (void)hipEventDestroy(c->ev_a);
   if (c->ev_b) (void)hipEventDestroy(c->ev_b);
@@ -222,6 +225,14 @@ nle_status nle_upload_mesh(nle_ctx *ctx, int64_t n_nodes, const double *X, int64
     drop_graph(c);
     nle_status s = build_mesh(c, n_nodes, X, n_elems, conn);
     if (s != NLE_OK) return s;
+    // per-element and per-face data of the previous mesh no longer apply
+    for (void *p : c->fib_allocs) dfree(c, p);
+    c->fib_allocs.clear();
+    c->fib64 = nullptr;
+    c->fib32 = nullptr;
+    free_surface(c);
+    c->surf.h_ptri.clear();
+    c->surf.h_rtri.clear();
     dfree(c, c->dir_dofs);
     dfree(c, c->dir_vals);
     c->dir_dofs = nullptr;
@@ -247,12 +258,34 @@ nle_status nle_set_material(nle_ctx *ctx, int32_t kind, const double *p, int32_t
     m.mu = p[0];
     m.lam = p[1];
     m.cvol = np == 3 ? p[2] : 0.25;
+  } else if (kind == NLE_MAT_M4) {
+    if (np != 5) return fail(c, NLE_E_INVAL, "M4 takes (a, b, a_f, b_f, kappa)");
+    for (int i = 0; i < 5; ++i)
+      if (!std::isfinite(p[i])) return fail(c, NLE_E_INVAL, "non-finite material parameter");
+    if (!(p[0] > 0.0) || !(p[1] > 0.0) || !(p[2] >= 0.0) || !(p[3] > 0.0) || !(p[4] > 0.0))
+      return fail(c, NLE_E_INVAL, "M4 needs a, b, b_f, kappa > 0 and a_f >= 0");
+    m.kind = kind;
+    m.a_iso = p[0];
+    m.b_iso = p[1];
+    m.a_f = p[2];
+    m.b_f = p[3];
+    m.kappa = p[4];
+    m.gamma = c->mat.gamma;
+    m.mu = p[0];  // small-strain shear modulus (used only for reporting)
+    m.lam = p[4] - 2.0 * p[0] / 3.0;
+    m.cvol = 0.25;
+    drop_graph(c);
+    c->mat = m;
+    c->has_mat = true;
+    c->lin64 = c->lin32 = false;
+    return NLE_OK;
   } else {
     return fail(c, NLE_E_UNSUPPORTED, "unknown material kind");
   }
   if (!(m.mu > 0.0) || !std::isfinite(m.lam) || !std::isfinite(m.cvol))
     return fail(c, NLE_E_INVAL, "material parameters must be finite with mu > 0");
   m.kappa = m.lam + 2.0 * m.mu / 3.0;
+  m.gamma = c->mat.gamma;
   drop_graph(c);
   c->mat = m;
   c->has_mat = true;
@@ -352,6 +385,101 @@ nle_status nle_set_load_scale(nle_ctx *ctx, double s) {
   return NLE_OK;
 }
 
+nle_status nle_set_fibres(nle_ctx *ctx, const double *fib) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  nle_status s = need_mesh(c);
+  if (s != NLE_OK) return s;
+  if (!fib) return fail(c, NLE_E_INVAL, "null fibre array");
+  return guarded(c, [&]() -> nle_status {
+    const int64_t ne = c->m.n_elems;
+    std::vector<double> f64(3 * ne);
+    std::vector<float> f32(3 * ne);
+    for (int64_t k = 0; k < ne; ++k) {
+      const int64_t e = c->m.h_perm[k];
+      const double *f = fib + 3 * e;
+      const double l2 = f[0] * f[0] + f[1] * f[1] + f[2] * f[2];
+      if (!std::isfinite(l2) || !(std::fabs(l2 - 1.0) <= 1e-6))
+        return fail(c, NLE_E_INVAL, "fibres must be finite unit vectors");
+      for (int j = 0; j < 3; ++j) {
+        f64[j * ne + k] = f[j];
+        f32[j * ne + k] = float(f[j]);
+      }
+    }
+    drop_graph(c);
+    NLE_HIP(c, hipStreamSynchronize(c->stream));
+    for (void *p : c->fib_allocs) dfree(c, p);
+    c->fib_allocs.clear();
+    c->fib64 = static_cast<double *>(dalloc(c, size_t(3 * ne) * 8));
+    c->fib32 = static_cast<float *>(dalloc(c, size_t(3 * ne) * 4));
+    c->fib_allocs = {c->fib64, c->fib32};
+    if (!c->fib64 || !c->fib32) return fail(c, NLE_E_OOM, "device allocation failed");
+    NLE_HIP(c, hipMemcpyAsync(c->fib64, f64.data(), f64.size() * 8, hipMemcpyHostToDevice, c->stream));
+    NLE_HIP(c, hipMemcpyAsync(c->fib32, f32.data(), f32.size() * 4, hipMemcpyHostToDevice, c->stream));
+    NLE_HIP(c, hipStreamSynchronize(c->stream));
+    c->lin64 = c->lin32 = false;
+    return NLE_OK;
+  });
+}
+
+nle_status nle_set_active_tension(nle_ctx *ctx, double gamma) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  if (!c) return NLE_E_INVAL;
+  if (!std::isfinite(gamma)) return fail(c, NLE_E_INVAL, "non-finite active tension");
+  if (gamma != c->mat.gamma) {
+    drop_graph(c);
+    c->mat.gamma = gamma;
+    c->lin64 = c->lin32 = false;
+  }
+  return NLE_OK;
+}
+
+namespace {
+nle_status check_tri(Ctx *c, int64_t nf, const int32_t *tri, std::vector<int32_t> *out) {
+  if (nf < 0 || (nf > 0 && !tri)) return fail(c, NLE_E_INVAL, "bad face arrays");
+  out->assign(tri, tri + 3 * nf);
+  for (int32_t v : *out)
+    if (v < 0 || v >= c->m.n_nodes) return fail(c, NLE_E_INVAL, "face node out of range");
+  return NLE_OK;
+}
+}  // namespace
+
+nle_status nle_set_pressure(nle_ctx *ctx, int64_t nf, const int32_t *tri, double p) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  nle_status s = need_mesh(c);
+  if (s != NLE_OK) return s;
+  if (!std::isfinite(p)) return fail(c, NLE_E_INVAL, "non-finite pressure");
+  return guarded(c, [&]() -> nle_status {
+    std::vector<int32_t> t;
+    nle_status st = check_tri(c, nf, tri, &t);
+    if (st != NLE_OK) return st;
+    c->surf.p = p;
+    c->lin64 = c->lin32 = false;
+    if (t == c->surf.h_ptri) return NLE_OK;
+    c->surf.h_ptri = t;
+    return build_surface(c);
+  });
+}
+
+nle_status nle_set_robin(nle_ctx *ctx, int64_t nf, const int32_t *tri, double k_perp, double k_par) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  nle_status s = need_mesh(c);
+  if (s != NLE_OK) return s;
+  if (!std::isfinite(k_perp) || !std::isfinite(k_par))
+    return fail(c, NLE_E_INVAL, "non-finite spring constants");
+  return guarded(c, [&]() -> nle_status {
+    std::vector<int32_t> t;
+    nle_status st = check_tri(c, nf, tri, &t);
+    if (st != NLE_OK) return st;
+    if (k_perp != c->surf.kperp || k_par != c->surf.kpar) drop_graph(c);
+    c->surf.kperp = k_perp;
+    c->surf.kpar = k_par;
+    c->lin64 = c->lin32 = false;
+    if (t == c->surf.h_rtri) return NLE_OK;
+    c->surf.h_rtri = t;
+    return build_surface(c);
+  });
+}
+
 nle_status nle_lift(nle_ctx *ctx, double *u) {
   Ctx *c = reinterpret_cast<Ctx *>(ctx);
   nle_status s = need_mesh(c);
@@ -367,6 +495,8 @@ nle_status nle_residual(nle_ctx *ctx, const double *u, double *r, double *rn) {
   if (s != NLE_OK) return s;
   if (!c->has_mat) return fail(c, NLE_E_STATE, "no material set");
   if (!u || !r) return fail(c, NLE_E_INVAL, "null vector");
+  s = need_fibres(c);
+  if (s != NLE_OK) return s;
   if (rn) {
     bool inv = false;
     s = residual_norm(c, u, r, rn, &inv);
@@ -386,6 +516,8 @@ nle_status nle_linearize(nle_ctx *ctx, const double *u, int32_t prec) {
   if (!c->has_mat) return fail(c, NLE_E_STATE, "no material set");
   if (!u) return fail(c, NLE_E_INVAL, "null vector");
   if (prec != NLE_FP64 && prec != NLE_FP32) return fail(c, NLE_E_INVAL, "bad precision");
+  s = need_fibres(c);
+  if (s != NLE_OK) return s;
   return linearize(c, u, prec);
 }
 
@@ -416,6 +548,9 @@ nle_status nle_energy(nle_ctx *ctx, const double *u, double *pi) {
   if (s != NLE_OK) return s;
   if (!c->has_mat) return fail(c, NLE_E_STATE, "no material set");
   if (!u || !pi) return fail(c, NLE_E_INVAL, "null argument");
+  if (c->surf.npf > 0) return fail(c, NLE_E_UNSUPPORTED, "a follower pressure has no potential");
+  s = need_fibres(c);
+  if (s != NLE_OK) return s;
   hipError_t e;
   const int np = elem_apply(c, OP_ENERGY, NLE_FP64, u, nullptr, nullptr, c->red, &e);
   if (e != hipSuccess) return fail(c, NLE_E_HIP, std::string("energy: ") + hipGetErrorString(e));
@@ -424,9 +559,20 @@ nle_status nle_energy(nle_ctx *ctx, const double *u, double *pi) {
   const int np2 = vec_dot_partials(c, NLE_FP64, c->fext, u, 3 * c->m.n_nodes, red2, &e);
   if (e != hipSuccess) return fail(c, NLE_E_HIP, "energy dot");
   NLE_HIP(c, reduce_scalar(c, red2, np2, c->dscal + 61));
-  s = read_scalars(c, c->dscal + 60, 16);
+  int np3 = 0;
+  double *red3 = red2 + np2;
+  const int64_t nsg = (c->surf.nsn + NT - 1) / NT;
+  if (np + np2 + nsg > c->red_cap) return fail(c, NLE_E_UNSUPPORTED, "too many face nodes");
+  surf_apply(c, OP_ENERGY, NLE_FP64, u, nullptr, &np3, &e, red3);
+  if (e != hipSuccess) return fail(c, NLE_E_HIP, "spring energy");
+  if (np3 > 0) {
+    NLE_HIP(c, reduce_scalar(c, red3, np3, c->dscal + 62));
+  } else {
+    NLE_HIP(c, hipMemsetAsync(c->dscal + 62, 0, 8, c->stream));
+  }
+  s = read_scalars(c, c->dscal + 60, 24);
   if (s != NLE_OK) return s;
-  *pi = c->hpin[0] - c->load_scale * c->hpin[1];
+  *pi = c->hpin[0] - c->load_scale * c->hpin[1] + c->hpin[2];
   return NLE_OK;
 }
 

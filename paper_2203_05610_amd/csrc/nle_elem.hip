@@ -45,6 +45,8 @@ struct ElemArgs {
   const double *ep_coef;
   double *ep_red;
   MatParams mp;
+  const T *fib;       // law M4: unit fibre per element, [3][n_e]
+  const T *fs;        // surface-load contributions per dof (null without surface loads)
   // batched mode (all null for a single problem): instance of each block,
   // per-instance load scale, material (mu, lam, cvol, kappa) and done mask
   const int32_t *blk_inst;
@@ -69,6 +71,7 @@ struct MergeArgs {
   const T *ep_w;
   const double *ep_coef;
   double *ep_red;
+  const T *fs;
   const int32_t *mwg_inst;  // batched mode: instance of each merge workgroup
   const double *inst_s;
   const int32_t *inst_done;
@@ -200,16 +203,79 @@ __device__ __forceinline__ void kinematics(const T H[3][3], Kin<T> &k) {
 }
 
 // Coefficients of the tangent in the form
-//   dP = a dF + cF L F + (cT L + cM (F:dF)) F^-T + cX F^-T dF^T F^-T,
-// L = F^-T : dF = tr(F^-1 dF).  Also the stress P = a F + pT F^-T.
+//   dP = a dF + (cF L + cFF (F:dF)) F + (cT L + cM (F:dF)) F^-T + cX F^-T dF^T F^-T
+//        + h1 (dF f) (x) f + h2 ((F f).(dF f)) (F f) (x) f,
+// L = F^-T : dF = tr(F^-1 dF); the fibre terms belong to law M4 only.  The
+// stress is P = a F + pT F^-T + h1 (F f) (x) f.
 struct Coef {
-  double a, cF, cT, cM, cX, pT;
+  double a, cF, cT, cM, cX, pT, cFF, h1, h2;
 };
 
+// Fibre kinematics of law M4: F f and I4 - 1 = 2 f.(H f) + |H f|^2 (unit f).
+struct FibreKin {
+  double Ff[3];
+  double e4;
+};
+
+template <typename T>
+__device__ __forceinline__ FibreKin fibre_kinematics(const T H[3][3], const T f[3]) {
+  FibreKin q;
+  double Hf[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    Hf[i] = double(H[i][0]) * double(f[0]) + double(H[i][1]) * double(f[1]) +
+            double(H[i][2]) * double(f[2]);
+  q.e4 = 2.0 * (double(f[0]) * Hf[0] + double(f[1]) * Hf[1] + double(f[2]) * Hf[2]) +
+         Hf[0] * Hf[0] + Hf[1] * Hf[1] + Hf[2] * Hf[2];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) q.Ff[i] = double(f[i]) + Hf[i];
+  return q;
+}
+
 template <int MAT, typename T>
-__device__ __forceinline__ Coef coefficients(const Kin<T> &k, const MatParams &mp) {
+__device__ __forceinline__ Coef coefficients(const Kin<T> &k, const T H[3][3], const FibreKin &fk,
+                                             const MatParams &mp) {
   Coef c;
-  if (MAT == NLE_MAT_M2) {
+  c.cFF = 0.0;
+  c.h1 = 0.0;
+  c.h2 = 0.0;
+  if (MAT == NLE_MAT_M4) {
+    // Psi = a/2b (exp(b (Ib1 - 3)) - 1) + af/2bf (exp(bf e4^2) - 1) [e4 > 0]
+    //       + kappa/2 (J - 1)^2 + gamma sqrt(I4),  Ib1 = J^-2/3 I1, e4 = I4 - 1
+    double I1 = 0.0, trH = 0.0, hh = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      trH += double(H[i][i]);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        I1 += double(k.F[i][j]) * double(k.F[i][j]);
+        hh += double(H[i][j]) * double(H[i][j]);
+      }
+    }
+    const double j23m1 = expm1(-2.0 / 3.0 * k.lnJ);
+    const double j23 = 1.0 + j23m1;
+    const double ib3 = 2.0 * trH + hh + j23m1 * I1;  // J^-2/3 I1 - 3 without cancellation
+    const double A = mp.a_iso * exp(mp.b_iso * ib3) * j23;
+    const double be = A * mp.b_iso * j23;
+    const double vk = mp.kappa * k.J;
+    c.a = A;
+    c.pT = vk * k.jm1 - A * I1 / 3.0;
+    c.cF = -2.0 / 3.0 * (A + be * I1);
+    c.cM = c.cF;
+    c.cFF = 2.0 * be;
+    c.cT = 2.0 / 9.0 * (A * I1 + be * I1 * I1) + vk * (2.0 * k.J - 1.0);
+    c.cX = A * I1 / 3.0 - vk * k.jm1;
+    const double e4 = fk.e4, I4 = 1.0 + e4;
+    double G = 0.0, Gp = 0.0;
+    if (e4 > 0.0) {
+      const double ex = exp(mp.b_f * e4 * e4);
+      G = 2.0 * mp.a_f * e4 * ex;
+      Gp = 2.0 * mp.a_f * ex * (1.0 + 2.0 * mp.b_f * e4 * e4);
+    }
+    const double rs = rsqrt(I4);
+    c.h1 = G + mp.gamma * rs;
+    c.h2 = 2.0 * Gp - mp.gamma * rs / I4;
+  } else if (MAT == NLE_MAT_M2) {
     // Psi = mu/2 (J^-2/3 I1 - 3) + cvol kappa (J^2 - 1 - 2 ln J)
     double I1 = 0.0;
 #pragma unroll
@@ -239,7 +305,7 @@ __device__ __forceinline__ Coef coefficients(const Kin<T> &k, const MatParams &m
 
 template <int MAT, typename T>
 __device__ __forceinline__ double energy_density(const Kin<T> &k, const T H[3][3],
-                                                 const MatParams &mp) {
+                                                 const FibreKin &fk, const MatParams &mp) {
   // I1 - 3 = 2 tr H + H:H (no cancellation)
   double trH = 0.0, hh = 0.0;
 #pragma unroll
@@ -249,6 +315,16 @@ __device__ __forceinline__ double energy_density(const Kin<T> &k, const T H[3][3
     for (int j = 0; j < 3; ++j) hh += double(H[i][j]) * double(H[i][j]);
   }
   const double i1m3 = 2.0 * trH + hh;
+  if (MAT == NLE_MAT_M4) {
+    double I1 = i1m3 + 3.0;
+    const double j23m1 = expm1(-2.0 / 3.0 * k.lnJ);
+    const double ib3 = i1m3 + j23m1 * I1;
+    const double e4 = fk.e4;
+    double psi = mp.a_iso / (2.0 * mp.b_iso) * expm1(mp.b_iso * ib3) +
+                 0.5 * mp.kappa * k.jm1 * k.jm1 + mp.gamma * sqrt(1.0 + e4);
+    if (e4 > 0.0) psi += mp.a_f / (2.0 * mp.b_f) * expm1(mp.b_f * e4 * e4);
+    return psi;
+  }
   if (MAT == NLE_MAT_M2) {
     const double j23 = exp(-2.0 / 3.0 * k.lnJ);
     const double j2m1 = k.jm1 * (k.jm1 + 2.0);
@@ -259,26 +335,28 @@ __device__ __forceinline__ double energy_density(const Kin<T> &k, const T H[3][3
 
 // Final value of one node (all three components) from its summed element
 // contributions.  mk = Dirichlet bits of the node.
+// fs (nullable) holds the surface-load contributions of the same operation.
 template <typename T, int OP>
 __device__ __forceinline__ void finalize_node(uint32_t g, uint32_t mk, const T acc[3], const T *v,
                                               T *out, const double *fext, double s,
-                                              double &nrm, const T *epw, T epc) {
+                                              double &nrm, const T *epw, T epc, const T *fs) {
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     const int64_t d = 3 * int64_t(g) + i;
     const bool fixed = (mk >> i) & 1u;
+    const T a = fs ? acc[i] + fs[d] : acc[i];
     if (OP == OP_RES) {
-      const double r = fixed ? 0.0 : double(acc[i]) - s * fext[d];
+      const double r = fixed ? 0.0 : double(a) - s * fext[d];
       out[d] = T(r);
       nrm += r * r;
     } else if (OP == OP_JV) {
       const T vd = v[d];
-      T y = fixed ? vd : acc[i];
+      T y = fixed ? vd : a;
       if (epw) y -= epc * epw[d];
       out[d] = y;
       nrm += double(vd * y);
     } else if (OP == OP_DIAG) {
-      out[d] = fixed ? T(1) : acc[i];
+      out[d] = fixed ? T(1) : a;
     }
   }
 }
@@ -289,6 +367,7 @@ struct ElemIn {
   uint4 lcp;   // 8 x u16: slot-local vertex ids, then contribution positions
   T g[3][3];   // grad N_1..3
   T vol;
+  T f[3];      // fibre direction (law M4)
 };
 
 __device__ __forceinline__ int lo16(uint32_t w) { return int(w & 0xFFFFu); }
@@ -297,7 +376,7 @@ __device__ __forceinline__ int hi16(uint32_t w) { return int(w >> 16); }
 // Component k of the gradients lives at G + k n_e: with a 32-bit element
 // index and uniform per-component base pointers every load is a scalar base
 // plus one shared 32-bit lane offset.
-template <typename T>
+template <int MAT, typename T>
 __device__ __forceinline__ void load_elem(const ElemArgs<T> &A, uint32_t ge, ElemIn<T> &d) {
   d.lcp = A.lcp[ge];
   const uint32_t ne = uint32_t(A.n_e);
@@ -309,6 +388,10 @@ __device__ __forceinline__ void load_elem(const ElemArgs<T> &A, uint32_t ge, Ele
       d.g[a][j] = Gk[ge];
     }
   d.vol = A.V[ge];
+  if (MAT == NLE_MAT_M4) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) d.f[j] = A.fib[size_t(j) * ne + ge];
+  }
 }
 
 // Element force vector (12 values, vertex-major) of one element.
@@ -341,11 +424,21 @@ __device__ __forceinline__ void element_forces(const ElemIn<T> &d, const T *uS, 
   kinematics(H, k);
   bad |= k.bad;
   const double V = double(d.vol);
+  FibreKin fk;
+  if (MAT == NLE_MAT_M4) fk = fibre_kinematics(H, d.f);
   if (OP == OP_ENERGY) {
-    eacc += V * energy_density<MAT>(k, H, mp);
+    eacc += V * energy_density<MAT>(k, H, fk, mp);
     return;
   }
-  const Coef cf = coefficients<MAT>(k, mp);
+  const Coef cf = coefficients<MAT>(k, H, fk, mp);
+  T Ff[3], f[3];
+  if (MAT == NLE_MAT_M4) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      Ff[i] = T(fk.Ff[i]);
+      f[i] = d.f[i];
+    }
+  }
   if (OP == OP_RES) {
     const T ca = T(V * cf.a), cp = T(V * cf.pT);
     T P[3][3];
@@ -353,6 +446,13 @@ __device__ __forceinline__ void element_forces(const ElemIn<T> &d, const T *uS, 
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j) P[i][j] = ca * k.F[i][j] + cp * k.FiT[i][j];
+    if (MAT == NLE_MAT_M4) {
+      const T ch = T(V * cf.h1);
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) P[i][j] += ch * Ff[i] * f[j];
+    }
 #pragma unroll
     for (int a = 1; a < 4; ++a)
 #pragma unroll
@@ -378,7 +478,7 @@ __device__ __forceinline__ void element_forces(const ElemIn<T> &d, const T *uS, 
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
         L += k.FiT[i][j] * dF[i][j];
-        if (MAT == NLE_MAT_M2) FdF += k.F[i][j] * dF[i][j];
+        if (MAT != NLE_MAT_M1) FdF += k.F[i][j] * dF[i][j];
       }
     // X = F^-T dF^T F^-T = F^-T M with M = dF^T F^-T
     T M[3][3];
@@ -388,8 +488,19 @@ __device__ __forceinline__ void element_forces(const ElemIn<T> &d, const T *uS, 
       for (int j = 0; j < 3; ++j)
         M[p][j] = dF[0][p] * k.FiT[0][j] + dF[1][p] * k.FiT[1][j] + dF[2][p] * k.FiT[2][j];
     const T ca = T(V * cf.a), cX = T(V * cf.cX);
-    const T sT = T(V * cf.cT) * L + (MAT == NLE_MAT_M2 ? T(V * cf.cM) * FdF : T(0));
-    const T sF = MAT == NLE_MAT_M2 ? T(V * cf.cF) * L : T(0);
+    const T sT = T(V * cf.cT) * L + (MAT != NLE_MAT_M1 ? T(V * cf.cM) * FdF : T(0));
+    T sF = MAT != NLE_MAT_M1 ? T(V * cf.cF) * L : T(0);
+    if (MAT == NLE_MAT_M4) sF += T(V * cf.cFF) * FdF;
+    // fibre terms (M4): h1 (dF f) (x) f + h2 ((F f).(dF f)) (F f) (x) f
+    T dFf[3] = {T(0), T(0), T(0)}, s2 = T(0);
+    if (MAT == NLE_MAT_M4) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) dFf[i] = dF[i][0] * f[0] + dF[i][1] * f[1] + dF[i][2] * f[2];
+      s2 = T(V * cf.h2) * (Ff[0] * dFf[0] + Ff[1] * dFf[1] + Ff[2] * dFf[2]);
+      const T c1 = T(V * cf.h1);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) dFf[i] *= c1;
+    }
     T dP[3][3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -397,7 +508,8 @@ __device__ __forceinline__ void element_forces(const ElemIn<T> &d, const T *uS, 
       for (int j = 0; j < 3; ++j) {
         const T X = k.FiT[i][0] * M[0][j] + k.FiT[i][1] * M[1][j] + k.FiT[i][2] * M[2][j];
         T t = ca * dF[i][j] + sT * k.FiT[i][j] + cX * X;
-        if (MAT == NLE_MAT_M2) t += sF * k.F[i][j];
+        if (MAT != NLE_MAT_M1) t += sF * k.F[i][j];
+        if (MAT == NLE_MAT_M4) t += (dFf[i] + s2 * Ff[i]) * f[j];
         dP[i][j] = t;
       }
 #pragma unroll
@@ -414,7 +526,12 @@ __device__ __forceinline__ void element_forces(const ElemIn<T> &d, const T *uS, 
       for (int i = 0; i < 3; ++i) {
         const T w = k.FiT[i][0] * g[a][0] + k.FiT[i][1] * g[a][1] + k.FiT[i][2] * g[a][2];
         const T z = k.F[i][0] * g[a][0] + k.F[i][1] * g[a][1] + k.F[i][2] * g[a][2];
-        out[a][i] = T(ca) * gg + T(c1) * w * z + T(c2) * w * w;
+        T dg = T(ca) * gg + T(c1) * w * z + T(c2) * w * w;
+        if (MAT == NLE_MAT_M4) {
+          const T gf = g[a][0] * f[0] + g[a][1] * f[1] + g[a][2] * f[2];
+          dg += T(V * cf.cFF) * z * z + (T(V * cf.h1) + T(V * cf.h2) * Ff[i] * Ff[i]) * gf * gf;
+        }
+        out[a][i] = dg;
       }
     }
     return;
@@ -456,8 +573,8 @@ __global__ __launch_bounds__(NT) void k_elem_block(ElemArgs<T> A) {
   // The inputs of this thread's first two elements are requested before the
   // node gather so all of these loads are in flight together.
   ElemIn<T> ea, eb;
-  if (tid < ne) load_elem(A, uint32_t(e0 + tid), ea);
-  if (tid + NT < ne) load_elem(A, uint32_t(e0 + tid + NT), eb);
+  if (tid < ne) load_elem<MAT>(A, uint32_t(e0 + tid), ea);
+  if (tid + NT < ne) load_elem<MAT>(A, uint32_t(e0 + tid + NT), eb);
 
   // Phase 1: gather nodal state (and direction) of the block.
   for (int l = tid; l < nl; l += NT) {
@@ -489,7 +606,7 @@ __global__ __launch_bounds__(NT) void k_elem_block(ElemArgs<T> A) {
   if (tid < ne) run(ea);
   if (tid + NT < ne) run(eb);
   for (int e = tid + 2 * NT; e < ne; e += NT) {
-    load_elem(A, uint32_t(e0 + e), ea);
+    load_elem<MAT>(A, uint32_t(e0 + e), ea);
     run(ea);
   }
   if (bad && A.flag) A.flag[inst] = 1;
@@ -520,7 +637,7 @@ __global__ __launch_bounds__(NT) void k_elem_block(ElemArgs<T> A) {
       pp[2] = acc[2];
     } else {
       finalize_node<T, OP>(w & NODE_MASK, (w >> 28) & 7u, acc, A.v, A.out, A.fext, lscale, nrm,
-                           A.ep_w, epc);
+                           A.ep_w, epc, A.fs);
     }
   }
   if (OP == OP_RES || (OP == OP_JV && A.ep_red)) {
@@ -564,7 +681,7 @@ __global__ __launch_bounds__(NT) void k_elem_merge(MergeArgs<T> A) {
     }
     const uint32_t w = A.fx_node[k];
     finalize_node<T, OP>(w & NODE_MASK, (w >> 28) & 7u, acc, A.v, A.out, A.fext, lscale, nrm,
-                         A.ep_w, A.ep_coef ? T(A.ep_coef[0]) : T(0));
+                         A.ep_w, A.ep_coef ? T(A.ep_coef[0]) : T(0), A.fs);
   }
   if (OP == OP_RES || (OP == OP_JV && A.ep_red)) {
     const double s = block_sum(nrm, rs);
@@ -576,6 +693,13 @@ template <typename T>
 int launch(Ctx *c, int op, const T *G, const T *V, const T *u, const T *v, T *out, double *red,
            hipError_t *err) {
   const Mesh &M = c->m;
+  // surface loads (follower pressure, springs): their nodal contributions are
+  // computed first and added when each node is finalized
+  void *fs = nullptr;
+  if (c->surf.nsn > 0 && op != OP_ENERGY) {
+    fs = surf_apply(c, op, sizeof(T) == 8 ? NLE_FP64 : NLE_FP32, u, v, nullptr, err);
+    if (*err != hipSuccess) return 0;
+  }
   ElemArgs<T> A;
   A.G = G;
   A.V = V;
@@ -602,6 +726,9 @@ int launch(Ctx *c, int op, const T *G, const T *V, const T *u, const T *v, T *ou
   A.ep_coef = c->ep.coef;
   A.ep_red = op == OP_JV ? c->ep.red : nullptr;
   A.mp = c->mat;
+  A.fib = static_cast<const T *>(sizeof(T) == 8 ? static_cast<const void *>(c->fib64)
+                                                : static_cast<const void *>(c->fib32));
+  A.fs = op == OP_ENERGY ? nullptr : static_cast<T *>(fs);
   A.blk_inst = M.blk_inst;
   A.inst_s = c->inst_s;
   A.inst_mat = c->inst_mat;
@@ -609,10 +736,12 @@ int launch(Ctx *c, int op, const T *G, const T *V, const T *u, const T *v, T *ou
   const int grid = A.per_xcd > 0 ? 8 * A.per_xcd : M.nblk;
   size_t lds = size_t(6 * M.nl_max + 12 * M.be_max) * sizeof(T);
   lds = std::max(lds, size_t(NT / 64) * sizeof(double));
-  const bool m2 = c->mat.kind == NLE_MAT_M2;
+  const int kind = c->mat.kind;
 #define NLE_LAUNCH_BLOCK(OPV)                                                                 \
-  if (m2)                                                                                     \
+  if (kind == NLE_MAT_M2)                                                                     \
     hipLaunchKernelGGL((k_elem_block<T, OPV, NLE_MAT_M2>), dim3(grid), dim3(NT), lds, c->stream, A); \
+  else if (kind == NLE_MAT_M4)                                                                \
+    hipLaunchKernelGGL((k_elem_block<T, OPV, NLE_MAT_M4>), dim3(grid), dim3(NT), lds, c->stream, A); \
   else                                                                                        \
     hipLaunchKernelGGL((k_elem_block<T, OPV, NLE_MAT_M1>), dim3(grid), dim3(NT), lds, c->stream, A);
   switch (op) {
@@ -653,6 +782,7 @@ int launch(Ctx *c, int op, const T *G, const T *V, const T *u, const T *v, T *ou
     B.ep_w = static_cast<const T *>(c->ep.w);
     B.ep_coef = c->ep.coef;
     B.ep_red = (op == OP_JV && c->ep.red) ? c->ep.red + M.nblk : nullptr;
+    B.fs = A.fs;
     const int g2 = int((M.n_shared + NT - 1) / NT);
     switch (op) {
       case OP_RES:

@@ -19,8 +19,9 @@ constexpr uint32_t NODE_MASK = 0x0FFFFFFFu;  // node id bits of a block-node wor
 enum ElemOp : int { OP_RES = 0, OP_JV = 1, OP_DIAG = 2, OP_ENERGY = 3 };
 
 struct MatParams {
-  int32_t kind;   // NLE_MAT_M1 / NLE_MAT_M2
+  int32_t kind;   // NLE_MAT_M1 / NLE_MAT_M2 / NLE_MAT_M4
   double mu, lam, cvol, kappa;
+  double a_iso, b_iso, a_f, b_f, gamma;  // law M4 (kappa shared)
 };
 
 // Element partition and geometry on the device.  Elements are renumbered
@@ -52,6 +53,7 @@ struct Mesh {
   std::vector<uint32_t> h_nodes, h_fx_node;     // ids and shared bit, no mask
   std::vector<int32_t> h_conn;                  // user connectivity (user order)
   std::vector<double> h_V;                      // volumes (user order)
+  std::vector<int64_t> h_perm;                  // user element of each renumbered element
   std::vector<double> h_X;
 };
 
@@ -90,6 +92,33 @@ struct Ctx {
   std::vector<double> h_ftrac, h_fbody;
   double *fext = nullptr;
   double load_scale = 1.0;
+
+  // law M4: unit fibre per element, [3][n_elems] in the renumbered order
+  double *fib64 = nullptr;
+  float *fib32 = nullptr;
+  std::vector<void *> fib_allocs;
+
+  // surface loads: follower pressure (scaled by the load scale) and elastic
+  // springs, evaluated node by node over the incident faces
+  struct Surf {
+    int64_t nsn = 0;             // face nodes
+    int32_t npf = 0, nrf = 0;    // pressure faces, spring faces (faces numbered in that order)
+    int32_t *node = nullptr;     // [nsn] node ids
+    int32_t *ptr = nullptr;      // [nsn+1] incident-face ranges
+    int32_t *ent = nullptr;      // incident faces, increasing
+    int32_t *tri = nullptr;      // [npf+nrf][3]
+    uint32_t *fmask = nullptr;   // [npf+nrf] Dirichlet bits of the 3 vertices (3 each)
+    double *pgeo64 = nullptr;    // [npf][9] reference vertex coordinates
+    float *pgeo32 = nullptr;
+    double *rgeo64 = nullptr;    // [nrf][4] reference unit normal, area
+    float *rgeo32 = nullptr;
+    double *plin = nullptr;      // device: effective pressure at the linearization
+    double *fs64 = nullptr;      // [3 n_nodes] contributions (zero off the face nodes)
+    float *fs32 = nullptr;
+    double p = 0.0, kperp = 0.0, kpar = 0.0;
+    std::vector<int32_t> h_ptri, h_rtri, h_tri;
+    std::vector<void *> allocs;
+  } surf;
 
   // batched mode: per-instance load scale, material (mu, lam, cvol, kappa)
   // and done mask on the device (null for a single problem)
@@ -135,6 +164,11 @@ struct Ctx {
 };
 
 nle_status fail(Ctx *c, nle_status code, const std::string &msg);
+inline nle_status need_fibres(Ctx *c) {
+  if (c->mat.kind == NLE_MAT_M4 && !c->fib64)
+    return fail(c, NLE_E_STATE, "law M4 needs nle_set_fibres");
+  return NLE_OK;
+}
 void drop_graph(Ctx *c);
 #define NLE_HIP(c, call)                                                        \
   do {                                                                          \
@@ -150,6 +184,21 @@ nle_status build_mesh(Ctx *c, int64_t n_nodes, const double *X, int64_t n_elems,
                       const std::vector<int64_t> *inst_elem = nullptr,
                       const std::vector<int64_t> *inst_node = nullptr);
 nle_status upload_node_masks(Ctx *c);
+
+// ---- surface loads (nle_surf.hip) ------------------------------------------
+// (Re)build the face-node structure from surf.h_ptri / h_rtri and the mesh.
+nle_status build_surface(Ctx *c);
+// Re-write the per-face Dirichlet bits after the Dirichlet set changed.
+nle_status upload_surface_masks(Ctx *c);
+void free_surface(Ctx *c);
+// Evaluate the surface contributions of op (OP_RES at u, OP_JV of v at the
+// linearization state u, OP_DIAG at u) into surf.fs64 / fs32 and return that
+// buffer; OP_ENERGY writes per-workgroup partials of the spring energy to red
+// and returns their count through *n_red.
+void *surf_apply(Ctx *c, int op, int prec, const void *u, const void *v, int *n_red,
+                 hipError_t *err, double *red = nullptr);
+// Store s * p as the pressure seen by the Jacobian action.
+hipError_t surf_set_linear_pressure(Ctx *c);
 
 // ---- element kernels (nle_elem.hip) ---------------------------------------
 // Launch the block and merge kernels of `op` in precision prec.

@@ -314,6 +314,7 @@ nle_status build_mesh(Ctx *c, int64_t nn, const double *X, int64_t ne, const int
   M.h_fx_node = fx_node;
   M.h_conn.assign(conn, conn + 4 * ne);
   M.h_V = V;
+  M.h_perm = perm;
   M.h_X.assign(X, X + 3 * nn);
   c->h_mask.assign(nn, 0);
   c->h_ftrac.assign(3 * nn, 0.0);
@@ -337,7 +338,7 @@ nle_status upload_node_masks(Ctx *c) {
   if (!fx.empty())
     NLE_HIP(c, hipMemcpyAsync(M.fx_node, fx.data(), fx.size() * 4, hipMemcpyHostToDevice, c->stream));
   NLE_HIP(c, hipStreamSynchronize(c->stream));
-  return NLE_OK;
+  return upload_surface_masks(c);
 }
 
 }  // namespace nle

@@ -393,6 +393,7 @@ nle_status check_ready(Ctx *c, double *u, const nle_solver_opts *o) {
   if (!c) return NLE_E_INVAL;
   if (!c->has_mesh) return fail(c, NLE_E_STATE, "no mesh uploaded");
   if (!c->has_mat) return fail(c, NLE_E_STATE, "no material set");
+  if (need_fibres(c) != NLE_OK) return NLE_E_STATE;
   if (!u || !o) return fail(c, NLE_E_INVAL, "null argument");
   if (o->precision != NLE_PREC_FP64 && o->precision != NLE_PREC_MIXED)
     return fail(c, NLE_E_INVAL, "bad precision");

@@ -1,0 +1,354 @@
+// Surface loads of the heartbeat test (Sec. 4): a follower pressure on the
+// endocardium and elastic Robin springs on the epicardium.
+//
+// One thread per face node sums the contributions of its incident faces in
+// increasing face order and writes the node's three values to a dense
+// per-dof buffer (zero off the face nodes); the element kernels add that
+// buffer when they finalize each node.  No atomics: the result is bitwise
+// reproducible.
+//
+// Pressure p (times the load scale) on a flat triangle with current vertices
+// x0, x1, x2 (outward from the body): each vertex gets p (x1-x0) x (x2-x0) / 6
+// in the residual, and p [(v1-v0) x (x2-x0) + (x1-x0) x (v2-v0)] / 6 in the
+// Jacobian action (not symmetric).  Springs with reference unit normal N and
+// area A: the residual gains M K u with M_ab = A (1 + delta_ab) / 12 and
+// K = k_par I + (k_perp - k_par) N (x) N (symmetric, constant).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "nle_internal.hpp"
+
+namespace nle {
+
+namespace {
+
+template <typename T>
+struct SurfArgs {
+  int64_t nsn;
+  int32_t npf;
+  const int32_t *node, *ptr, *ent, *tri;
+  const uint32_t *fmask;  // per face: Dirichlet bits of vertex a at bits 3a..3a+2
+  const T *pgeo, *rgeo;
+  double p;             // effective pressure (residual)
+  const double *plin;   // effective pressure at the linearization (Jacobian action)
+  double kperp, kpar;
+  const T *u, *v;
+  T *fs;
+  double *red;          // energy partials (one per workgroup)
+  const int32_t *skip;
+};
+
+template <typename T>
+__device__ __forceinline__ void cross_acc(const T a[3], const T b[3], T s, T acc[3]) {
+  acc[0] += s * (a[1] * b[2] - a[2] * b[1]);
+  acc[1] += s * (a[2] * b[0] - a[0] * b[2]);
+  acc[2] += s * (a[0] * b[1] - a[1] * b[0]);
+}
+
+template <typename T, int OP>
+__global__ __launch_bounds__(NT) void k_surface(SurfArgs<T> A) {
+  __shared__ double sh[NT / 64];
+  if (A.skip && A.skip[0] != 0) return;
+  const int64_t k = int64_t(blockIdx.x) * NT + threadIdx.x;
+  double e = 0.0;
+  if (k < A.nsn) {
+    const int32_t g = A.node[k];
+    T acc[3] = {T(0), T(0), T(0)};
+    const T pe = OP == OP_JV ? T(A.plin[0]) : T(A.p);
+    for (int q = A.ptr[k]; q < A.ptr[k + 1]; ++q) {
+      const int32_t f = A.ent[q];
+      const int32_t n[3] = {A.tri[3 * f], A.tri[3 * f + 1], A.tri[3 * f + 2]};
+      if (f < A.npf) {
+        if (OP == OP_RES || OP == OP_JV) {
+          const T *Xf = A.pgeo + 9 * int64_t(f);
+          T x[3][3];
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) x[a][i] = Xf[3 * a + i] + A.u[3 * int64_t(n[a]) + i];
+          T e1[3], e2[3];
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            e1[i] = x[1][i] - x[0][i];
+            e2[i] = x[2][i] - x[0][i];
+          }
+          const T s = pe / T(6);
+          if (OP == OP_RES) {
+            cross_acc(e1, e2, s, acc);
+          } else {
+            // the tangent has identity rows and columns on Dirichlet dofs:
+            // v's prescribed components do not enter the coupling
+            const uint32_t fm = A.fmask[f];
+            T d1[3], d2[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+              const T v0 = ((fm >> i) & 1u) ? T(0) : A.v[3 * int64_t(n[0]) + i];
+              const T v1 = ((fm >> (3 + i)) & 1u) ? T(0) : A.v[3 * int64_t(n[1]) + i];
+              const T v2 = ((fm >> (6 + i)) & 1u) ? T(0) : A.v[3 * int64_t(n[2]) + i];
+              d1[i] = v1 - v0;
+              d2[i] = v2 - v0;
+            }
+            cross_acc(d1, e2, s, acc);
+            cross_acc(e1, d2, s, acc);
+          }
+        }
+      } else {
+        const T *R = A.rgeo + 4 * int64_t(f - A.npf);
+        const T N[3] = {R[0], R[1], R[2]};
+        const T area = R[3];
+        const T kpar = T(A.kpar), dk = T(A.kperp - A.kpar);
+        if (OP == OP_DIAG) {
+#pragma unroll
+          for (int i = 0; i < 3; ++i) acc[i] += area / T(6) * (kpar + dk * N[i] * N[i]);
+        } else {
+          const T *w = OP == OP_JV ? A.v : A.u;
+          const uint32_t fm = OP == OP_JV ? A.fmask[f] : 0u;
+#pragma unroll
+          for (int b = 0; b < 3; ++b) {
+            const T m = area / T(12) * (n[b] == g ? T(2) : T(1));
+            T wb[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+              wb[i] = ((fm >> (3 * b + i)) & 1u) ? T(0) : w[3 * int64_t(n[b]) + i];
+            const T nw = N[0] * wb[0] + N[1] * wb[1] + N[2] * wb[2];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) acc[i] += m * (kpar * wb[i] + dk * nw * N[i]);
+          }
+        }
+      }
+    }
+    if (OP == OP_ENERGY) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) e += 0.5 * double(A.u[3 * int64_t(g) + i]) * double(acc[i]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) A.fs[3 * int64_t(g) + i] = acc[i];
+    }
+  }
+  if (OP == OP_ENERGY) {
+    double v = e;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double r = 0.0;
+      for (int w = 0; w < NT / 64; ++w) r += sh[w];
+      A.red[blockIdx.x] = r;
+    }
+  }
+}
+
+__global__ void k_set_scalar(double *dst, double v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) dst[0] = v;
+}
+
+template <typename T>
+void launch_surface(Ctx *c, int op, const T *u, const T *v, T *fs, double *red, const T *pgeo,
+                    const T *rgeo) {
+  const Ctx::Surf &S = c->surf;
+  SurfArgs<T> A;
+  A.nsn = S.nsn;
+  A.npf = S.npf;
+  A.node = S.node;
+  A.ptr = S.ptr;
+  A.ent = S.ent;
+  A.tri = S.tri;
+  A.fmask = S.fmask;
+  A.pgeo = pgeo;
+  A.rgeo = rgeo;
+  A.p = c->load_scale * S.p;
+  A.plin = S.plin;
+  A.kperp = S.kperp;
+  A.kpar = S.kpar;
+  A.u = u;
+  A.v = v;
+  A.fs = fs;
+  A.red = red;
+  A.skip = c->elem_skip;
+  const int grid = int((S.nsn + NT - 1) / NT);
+  switch (op) {
+    case OP_RES:
+      hipLaunchKernelGGL((k_surface<T, OP_RES>), dim3(grid), dim3(NT), 0, c->stream, A);
+      break;
+    case OP_JV:
+      hipLaunchKernelGGL((k_surface<T, OP_JV>), dim3(grid), dim3(NT), 0, c->stream, A);
+      break;
+    case OP_DIAG:
+      hipLaunchKernelGGL((k_surface<T, OP_DIAG>), dim3(grid), dim3(NT), 0, c->stream, A);
+      break;
+    default:
+      hipLaunchKernelGGL((k_surface<T, OP_ENERGY>), dim3(grid), dim3(NT), 0, c->stream, A);
+      break;
+  }
+}
+
+template <typename T>
+T *bupload(Ctx *c, const std::vector<T> &h, hipError_t *e) {
+  T *d = static_cast<T *>(dalloc(c, std::max<size_t>(h.size(), 1) * sizeof(T)));
+  if (!d) {
+    *e = hipErrorOutOfMemory;
+    return nullptr;
+  }
+  c->surf.allocs.push_back(d);
+  if (!h.empty()) {
+    const hipError_t r =
+        hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, c->stream);
+    if (r != hipSuccess) *e = r;
+  }
+  return d;
+}
+
+}  // namespace
+
+void free_surface(Ctx *c) {
+  Ctx::Surf &S = c->surf;
+  for (void *p : S.allocs) dfree(c, p);
+  S.allocs.clear();
+  S.nsn = 0;
+  S.npf = S.nrf = 0;
+  S.node = S.ptr = S.ent = S.tri = nullptr;
+  S.fmask = nullptr;
+  S.pgeo64 = S.rgeo64 = S.plin = S.fs64 = nullptr;
+  S.pgeo32 = S.rgeo32 = S.fs32 = nullptr;
+}
+
+nle_status build_surface(Ctx *c) {
+  Ctx::Surf &S = c->surf;
+  drop_graph(c);
+  NLE_HIP(c, hipStreamSynchronize(c->stream));
+  free_surface(c);
+  const int64_t npf = int64_t(S.h_ptri.size() / 3), nrf = int64_t(S.h_rtri.size() / 3);
+  if (npf + nrf == 0) return NLE_OK;
+  if (npf + nrf >= (int64_t(1) << 31) / 3) return fail(c, NLE_E_UNSUPPORTED, "too many faces");
+  const int64_t nn = c->m.n_nodes;
+  const double *X = c->m.h_X.data();
+  std::vector<int32_t> tri(S.h_ptri);
+  tri.insert(tri.end(), S.h_rtri.begin(), S.h_rtri.end());
+  // incident faces of each node (CSR over nodes, faces in increasing order)
+  std::vector<int32_t> cnt(nn + 1, 0);
+  for (int32_t v : tri) cnt[v + 1] += 1;
+  std::vector<int32_t> fnode, fptr(1, 0), fent;
+  std::vector<int64_t> start(nn + 1, 0);
+  for (int64_t g = 0; g < nn; ++g) start[g + 1] = start[g] + cnt[g + 1];
+  std::vector<int32_t> all(start[nn]);
+  std::vector<int64_t> pos(start.begin(), start.end() - 1);
+  const int64_t nf = npf + nrf;
+  for (int64_t f = 0; f < nf; ++f)
+    for (int a = 0; a < 3; ++a) {
+      const int32_t v = tri[3 * f + a];
+      // a face listing a node twice would add it twice: rejected
+      for (int b = 0; b < a; ++b)
+        if (tri[3 * f + b] == v) return fail(c, NLE_E_BADMESH, "degenerate surface triangle");
+      all[pos[v]++] = int32_t(f);
+    }
+  for (int64_t g = 0; g < nn; ++g) {
+    if (start[g + 1] == start[g]) continue;
+    fnode.push_back(int32_t(g));
+    for (int64_t q = start[g]; q < start[g + 1]; ++q) fent.push_back(all[q]);
+    fptr.push_back(int32_t(fent.size()));
+  }
+  std::vector<double> pg(9 * npf), rg(4 * nrf);
+  for (int64_t f = 0; f < npf; ++f)
+    for (int a = 0; a < 3; ++a)
+      for (int i = 0; i < 3; ++i) pg[9 * f + 3 * a + i] = X[3 * int64_t(tri[3 * f + a]) + i];
+  for (int64_t r = 0; r < nrf; ++r) {
+    const int32_t *t = &tri[3 * (npf + r)];
+    double e1[3], e2[3];
+    for (int i = 0; i < 3; ++i) {
+      e1[i] = X[3 * int64_t(t[1]) + i] - X[3 * int64_t(t[0]) + i];
+      e2[i] = X[3 * int64_t(t[2]) + i] - X[3 * int64_t(t[0]) + i];
+    }
+    const double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                         e1[0] * e2[1] - e1[1] * e2[0]};
+    const double l = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    if (!(l > 0.0)) return fail(c, NLE_E_BADMESH, "zero-area spring triangle");
+    for (int i = 0; i < 3; ++i) rg[4 * r + i] = n[i] / l;
+    rg[4 * r + 3] = 0.5 * l;
+  }
+  std::vector<float> pg32(pg.begin(), pg.end()), rg32(rg.begin(), rg.end());
+  hipError_t e = hipSuccess;
+  S.npf = int32_t(npf);
+  S.nrf = int32_t(nrf);
+  S.nsn = int64_t(fnode.size());
+  S.node = bupload(c, fnode, &e);
+  S.ptr = bupload(c, fptr, &e);
+  S.ent = bupload(c, fent, &e);
+  S.tri = bupload(c, tri, &e);
+  const std::vector<uint32_t> fm0(nf, 0u);
+  S.fmask = bupload(c, fm0, &e);
+  S.pgeo64 = bupload(c, pg, &e);
+  S.pgeo32 = bupload(c, pg32, &e);
+  S.rgeo64 = bupload(c, rg, &e);
+  S.rgeo32 = bupload(c, rg32, &e);
+  S.plin = static_cast<double *>(dalloc(c, 256));
+  S.fs64 = static_cast<double *>(dalloc(c, size_t(3 * nn) * 8));
+  S.fs32 = static_cast<float *>(dalloc(c, size_t(3 * nn) * 4));
+  for (void *p : {(void *)S.plin, (void *)S.fs64, (void *)S.fs32}) {
+    if (!p) e = hipErrorOutOfMemory;
+    S.allocs.push_back(p);
+  }
+  if (e == hipErrorOutOfMemory) {
+    free_surface(c);
+    return fail(c, NLE_E_OOM, "device allocation failed");
+  }
+  if (e != hipSuccess) {
+    free_surface(c);
+    return fail(c, NLE_E_HIP, std::string("surface upload: ") + hipGetErrorString(e));
+  }
+  // entries off the face nodes stay zero for good
+  NLE_HIP(c, hipMemsetAsync(S.fs64, 0, size_t(3 * nn) * 8, c->stream));
+  NLE_HIP(c, hipMemsetAsync(S.fs32, 0, size_t(3 * nn) * 4, c->stream));
+  NLE_HIP(c, hipMemsetAsync(S.plin, 0, 8, c->stream));
+  S.h_tri = tri;
+  c->lin64 = c->lin32 = false;
+  return upload_surface_masks(c);
+}
+
+nle_status upload_surface_masks(Ctx *c) {
+  Ctx::Surf &S = c->surf;
+  if (S.nsn == 0) return NLE_OK;
+  const int64_t nf = int64_t(S.h_tri.size() / 3);
+  std::vector<uint32_t> fm(nf, 0u);
+  for (int64_t f = 0; f < nf; ++f)
+    for (int a = 0; a < 3; ++a)
+      fm[f] |= uint32_t(c->h_mask[S.h_tri[3 * f + a]] & 7u) << (3 * a);
+  NLE_HIP(c, hipMemcpyAsync(S.fmask, fm.data(), fm.size() * 4, hipMemcpyHostToDevice, c->stream));
+  NLE_HIP(c, hipStreamSynchronize(c->stream));
+  return NLE_OK;
+}
+
+hipError_t surf_set_linear_pressure(Ctx *c) {
+  if (c->surf.nsn == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(64), 0, c->stream, c->surf.plin,
+                     c->load_scale * c->surf.p);
+  return hipGetLastError();
+}
+
+void *surf_apply(Ctx *c, int op, int prec, const void *u, const void *v, int *n_red,
+                 hipError_t *err, double *red) {
+  const Ctx::Surf &S = c->surf;
+  *err = hipSuccess;
+  if (S.nsn == 0) {
+    if (n_red) *n_red = 0;
+    return nullptr;
+  }
+  const int grid = int((S.nsn + NT - 1) / NT);
+  if (n_red) *n_red = op == OP_ENERGY ? grid : 0;
+  void *fs;
+  if (prec == NLE_FP32) {
+    fs = S.fs32;
+    launch_surface<float>(c, op, static_cast<const float *>(u), static_cast<const float *>(v),
+                          S.fs32, red, S.pgeo32, S.rgeo32);
+  } else {
+    fs = S.fs64;
+    launch_surface<double>(c, op, static_cast<const double *>(u), static_cast<const double *>(v),
+                           S.fs64, red, S.pgeo64, S.rgeo64);
+  }
+  *err = hipGetLastError();
+  return fs;
+}
+
+}  // namespace nle

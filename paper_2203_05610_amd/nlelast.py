@@ -25,7 +25,7 @@ NLE_DIVERGED_LINEAR, NLE_BFGS_BREAKDOWN = 4, 5
 NLE_E_INVAL, NLE_E_BADMESH, NLE_E_STATE = -1, -2, -3
 NLE_E_OOM, NLE_E_HIP, NLE_E_UNSUPPORTED = -4, -5, -6
 NLE_FP64, NLE_FP32 = 0, 1
-NLE_MAT_M1, NLE_MAT_M2 = 1, 2
+NLE_MAT_M1, NLE_MAT_M2, NLE_MAT_M4 = 1, 2, 4
 NLE_NK, NLE_INK, NLE_BFGS = 0, 1, 2
 NLE_KSP_GMRES, NLE_KSP_CG, NLE_KSP_MINRES = 0, 1, 2
 NLE_ORTH_MGS, NLE_ORTH_CGS2 = 0, 1
@@ -47,7 +47,8 @@ EXPORTS = [
     "nle_jv", "nle_diag", "nle_energy", "nle_default_opts", "nle_solve_nk", "nle_solve_ink",
     "nle_solve_bfgs", "nle_partition_info", "nle_batch_create", "nle_batch_destroy",
     "nle_batch_last_error", "nle_batch_add", "nle_batch_finalize", "nle_batch_layout",
-    "nle_batch_solve",
+    "nle_batch_solve", "nle_set_fibres", "nle_set_active_tension", "nle_set_pressure",
+    "nle_set_robin",
 ]
 
 
@@ -108,6 +109,10 @@ def lib() -> ctypes.CDLL:
         "nle_set_traction": (I32, [P, I64, P, P]),
         "nle_set_body_force": (I32, [P, P]),
         "nle_set_load_scale": (I32, [P, D]),
+        "nle_set_fibres": (I32, [P, P]),
+        "nle_set_active_tension": (I32, [P, D]),
+        "nle_set_pressure": (I32, [P, I64, P, D]),
+        "nle_set_robin": (I32, [P, I64, P, D, D]),
         "nle_lift": (I32, [P, P]),
         "nle_residual": (I32, [P, P, P, ctypes.POINTER(D)]),
         "nle_linearize": (I32, [P, P, I32]),
@@ -173,6 +178,7 @@ class Context:
             raise NleError(st, "nle_create failed")
         self.handle = h
         self.n_nodes = 0
+        self.n_elems = 0
 
     def close(self):
         if getattr(self, "handle", None):
@@ -236,6 +242,7 @@ def nle_upload_mesh(ctx: Context, X, conn) -> None:
         raise ValueError("X must be (n, 3) and conn (n_e, k)")
     ctx.check(lib().nle_upload_mesh(ctx.handle, X.shape[0], px, conn.shape[0], conn.shape[1], pc))
     ctx.n_nodes = X.shape[0]
+    ctx.n_elems = conn.shape[0]
 
 
 def nle_set_material(ctx: Context, kind: int, params) -> None:
@@ -255,6 +262,28 @@ def nle_set_traction(ctx: Context, tri, t) -> None:
     f, pf = _host(tri, np.int32)
     tt, pt = _host(t, np.float64)
     ctx.check(lib().nle_set_traction(ctx.handle, f.shape[0] if f.size else 0, pf, pt))
+
+
+def nle_set_fibres(ctx: Context, fib) -> None:
+    f, pf = _host(fib, np.float64)
+    if f.shape != (ctx.n_elems, 3):
+        raise ValueError(f"expected fibres of shape ({ctx.n_elems}, 3)")
+    ctx.check(lib().nle_set_fibres(ctx.handle, pf))
+
+
+def nle_set_active_tension(ctx: Context, gamma: float) -> None:
+    ctx.check(lib().nle_set_active_tension(ctx.handle, float(gamma)))
+
+
+def nle_set_pressure(ctx: Context, tri, p: float) -> None:
+    f, pf = _host(tri, np.int32)
+    ctx.check(lib().nle_set_pressure(ctx.handle, f.shape[0] if f.size else 0, pf, float(p)))
+
+
+def nle_set_robin(ctx: Context, tri, k_perp: float, k_par: float) -> None:
+    f, pf = _host(tri, np.int32)
+    ctx.check(lib().nle_set_robin(ctx.handle, f.shape[0] if f.size else 0, pf, float(k_perp),
+                                  float(k_par)))
 
 
 def nle_set_body_force(ctx: Context, f) -> None:

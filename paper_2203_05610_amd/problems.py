@@ -1,4 +1,4 @@
-"""Set up the Cook's-membrane workloads on a library context (marshalling only).
+"""Set up the workloads on a library context (marshalling only).
 
 Cook test (Sec. 4): clamp on x = 0, dead shear traction (0, tau, 0) per unit
 reference area on x = 48, compressible neo-Hookean (M1) or the paper's split
@@ -99,3 +99,61 @@ def add_cook_instance(batch: nl.Batch, mesh, mu: float, lam: float, tau: float, 
     dofs = mesh.dirichlet_dofs("clamp")
     return nl.nle_batch_add(batch, mesh.X, mesh.conn, material, [mu, lam], dofs,
                             np.zeros(dofs.size), mesh.faces["load"], [0.0, tau, 0.0], scales)
+
+
+def setup_cardiac(ctx: nl.Context, mesh, consts: dict, dofs, block_size=None) -> None:
+    """Cardiac-like shell (Sec. 4, "Heartbeat test", quasi-static): law M4 with
+    the mesh's per-element fibres, follower pressure consts['p_max'] on the
+    'endo' faces (times the load scale), springs on the 'epi' faces, the given
+    constrained dofs held at zero.  Load scale and active tension start at 0."""
+    c = consts
+    if block_size is not None:
+        nl.nle_set_block_size(ctx, block_size)
+    nl.nle_upload_mesh(ctx, mesh.X, mesh.conn)
+    nl.nle_set_material(ctx, nl.NLE_MAT_M4, [c["a"], c["b"], c["af"], c["bf"], c["kappa"]])
+    nl.nle_set_fibres(ctx, mesh.elem_fibre)
+    dofs = np.asarray(dofs, dtype=np.int64)
+    nl.nle_set_dirichlet(ctx, dofs, np.zeros(dofs.size))
+    nl.nle_set_pressure(ctx, mesh.faces["endo"], c["p_max"])
+    nl.nle_set_robin(ctx, mesh.faces["epi"], c["k_perp"], c["k_par"])
+    nl.nle_set_load_scale(ctx, 0.0)
+    nl.nle_set_active_tension(ctx, 0.0)
+
+
+def solve_heartbeat(ctx: nl.Context, u, method: str, opts, schedule, gamma_max: float,
+                    hist_cap: int = 4096, max_cuts: int = 8, start=(0.0, 0.0)):
+    """Quasi-static heartbeat: for each time step (t, shape) set the active
+    tension gamma_max * shape and the pressure load scale shape, then solve,
+    warm-started.  A step that fails is retried from the last converged state
+    at the midpoint (in t and shape) of the failed increment (at most
+    `max_cuts` times in total); `start` is the (t, shape) that u solves.
+    Reports carry 't', 'shape' and 'accepted'."""
+    reps = []
+    targets = [(float(t), float(sh)) for t, sh in schedule]
+    backup = u.clone()
+    prev = (float(start[0]), float(start[1]))
+    cuts = 0
+    i = 0
+    while i < len(targets):
+        t, sh = targets[i]
+        nl.nle_set_active_tension(ctx, gamma_max * sh)
+        nl.nle_set_load_scale(ctx, sh)
+        st, rep = SOLVERS[method](ctx, u, opts, hist_cap)
+        rep.update(t=t, shape=sh, accepted=st == nl.NLE_OK)
+        reps.append(rep)
+        if st == nl.NLE_OK:
+            backup.copy_(u)
+            prev = (t, sh)
+            i += 1
+            continue
+        u.copy_(backup)
+        if cuts >= max_cuts:
+            break
+        cuts += 1
+        targets.insert(i, (0.5 * (prev[0] + t), 0.5 * (prev[1] + sh)))
+    return reps
+
+
+def heartbeat_ok(reps, schedule) -> bool:
+    acc = [r["t"] for r in reps if r["accepted"]]
+    return bool(acc) and acc[-1] == float(schedule[-1][0])
