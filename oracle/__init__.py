@@ -28,7 +28,11 @@ What it computes (paper sections cited per function):
                 CG, the Eisenstat-Walker forcing term, L-BFGS two-loop
                 recursion and the dense BFGS inverse update of Sec. 3, and
                 the NK / iNK / BFGS outer loops (Sec. 3, App. A options).
-* linear     -- textbook small-strain linear elasticity (B-matrix / Voigt),
+* mixed      -- the twist test's quadratic displacement / linear pressure
+                form with the incompressible neo-Hookean law (M3), 4-point
+                degree-2 rule, complex-step tangent (Sec. 4 "Twist test").
+* linear     -- textbook small-strain linear elasticity (B-matrix / Voigt;
+                linear and quadratic tetrahedra, the divergence block),
                 independent of everything above, used as a pin.
 
 Parity pins live in tests/test_oracle_*.py (closed forms, invariants,
