@@ -70,6 +70,7 @@ typedef int32_t nle_status;
  *    the small-strain limit.  n_params = 2 takes c_vol = 1/4. */
 #define NLE_MAT_M1 1
 #define NLE_MAT_M2 2
+#define NLE_MAT_M3 3
 #define NLE_MAT_M4 4
 
 #define NLE_NK 0   /* Newton-Krylov, fixed linear tolerance (App. A)        */
@@ -172,6 +173,23 @@ nle_status nle_set_block_size(nle_ctx *ctx, int32_t elems_per_block);
  * linearization.  n_nodes < 2^28. */
 nle_status nle_upload_mesh(nle_ctx *ctx, int64_t n_nodes, const double *X, int64_t n_elems,
                            int32_t nodes_per_elem, const int32_t *conn);
+/* Mixed quadratic-displacement / linear-pressure mesh (Sec. 4 "Twist test"
+ * with the P2-P1 pair): n_nodes displacement nodes X[n_nodes][3], conn
+ * [n_elems][10] (four vertices, positively oriented, then the midpoints of
+ * edges (0,1), (1,2), (0,2), (0,3), (1,3), (2,3); straight-sided), and
+ * n_pnodes pressure nodes with pconn[n_elems][4] (the pressure at the four
+ * vertices).  Host arrays, copied.  The unknown vector then has 3 n_nodes +
+ * n_pnodes entries: [u (node-interleaved) | p].  Only law NLE_MAT_M3 applies:
+ *   L(u, p) = int mu/2 (I1 - 3) - mu ln J - p (J - 1)   (params = (mu)),
+ * integrated by the 4-point degree-2 rule; the tangent is symmetric and
+ * indefinite (use MINRES or GMRES).  The Jacobi data (nle_diag) are the
+ * displacement-block diagonal and, on pressure rows, the lumped pressure mass
+ * over mu, so NLE_PC_JACOBI is a block-diagonal SPD preconditioner.  Dirichlet
+ * dofs index displacement dofs.  Fibres, follower pressure, springs and body
+ * forces are NLE_E_UNSUPPORTED on mixed meshes.  NLE_E_BADMESH on bad indices
+ * or a non-positive vertex volume. */
+nle_status nle_upload_mesh_mixed(nle_ctx *ctx, int64_t n_nodes, const double *X, int64_t n_elems,
+                                 const int32_t *conn, int64_t n_pnodes, const int32_t *pconn);
 /* Material law and parameters (see NLE_MAT_*).  NLE_MAT_M4 (cardiac-like,
  * Sec. 4 "Heartbeat test" with a stated substitute for its Guccione law):
  *   Psi = a/(2b) (exp(b (J^-2/3 I1 - 3)) - 1)

@@ -90,7 +90,7 @@ nle_status residual_norm(Ctx *c, const double *u, double *r, double *rn, bool *i
 }
 
 nle_status linearize(Ctx *c, const double *u, int prec) {
-  const int64_t n = 3 * c->m.n_nodes;
+  const int64_t n = ndof(c);
   NLE_HIP(c, surf_set_linear_pressure(c));
   if (u != c->ulin64)
     NLE_HIP(c, hipMemcpyAsync(c->ulin64, u, n * 8, hipMemcpyDeviceToDevice, c->stream));
@@ -241,12 +241,51 @@ nle_status nle_upload_mesh(nle_ctx *ctx, int64_t n_nodes, const double *X, int64
   });
 }
 
+nle_status nle_upload_mesh_mixed(nle_ctx *ctx, int64_t n_nodes, const double *X, int64_t n_elems,
+                                 const int32_t *conn, int64_t n_pnodes, const int32_t *pconn) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  if (!c) return NLE_E_INVAL;
+  return guarded(c, [&]() -> nle_status {
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, NLE_E_HIP, "hipSetDevice failed");
+    c->has_mesh = false;
+    drop_graph(c);
+    NLE_HIP(c, hipStreamSynchronize(c->stream));
+    for (void *p : c->fib_allocs) dfree(c, p);
+    c->fib_allocs.clear();
+    c->fib64 = nullptr;
+    c->fib32 = nullptr;
+    free_surface(c);
+    c->surf.h_ptri.clear();
+    c->surf.h_rtri.clear();
+    nle_status s = build_mixed_mesh(c, n_nodes, X, n_elems, conn, n_pnodes, pconn);
+    if (s != NLE_OK) return s;
+    dfree(c, c->dir_dofs);
+    dfree(c, c->dir_vals);
+    c->dir_dofs = nullptr;
+    c->dir_vals = nullptr;
+    return NLE_OK;
+  });
+}
+
 nle_status nle_set_material(nle_ctx *ctx, int32_t kind, const double *p, int32_t np) {
   Ctx *c = reinterpret_cast<Ctx *>(ctx);
   if (!c) return NLE_E_INVAL;
   if (!p) return fail(c, NLE_E_INVAL, "null parameter array");
   MatParams m{};
-  if (kind == NLE_MAT_M1) {
+  if (kind == NLE_MAT_M3) {
+    if (np != 1) return fail(c, NLE_E_INVAL, "M3 takes (mu)");
+    if (!(p[0] > 0.0) || !std::isfinite(p[0])) return fail(c, NLE_E_INVAL, "M3 needs mu > 0");
+    m.kind = kind;
+    m.mu = p[0];
+    m.lam = 0.0;
+    m.cvol = 0.25;
+    m.kappa = 0.0;
+    drop_graph(c);
+    c->mat = m;
+    c->has_mat = true;
+    c->lin64 = c->lin32 = false;
+    return NLE_OK;
+  } else if (kind == NLE_MAT_M1) {
     if (np != 2) return fail(c, NLE_E_INVAL, "M1 takes (mu, lambda)");
     m.kind = kind;
     m.mu = p[0];
@@ -365,6 +404,7 @@ nle_status nle_set_body_force(nle_ctx *ctx, const double *fb) {
   Ctx *c = reinterpret_cast<Ctx *>(ctx);
   nle_status s = need_mesh(c);
   if (s != NLE_OK) return s;
+  if (c->mixed) return fail(c, NLE_E_UNSUPPORTED, "not available on mixed meshes");
   if (!fb) return fail(c, NLE_E_INVAL, "null body force");
   return guarded(c, [&]() -> nle_status {
     std::vector<double> f(3 * c->m.n_nodes, 0.0);
@@ -389,6 +429,7 @@ nle_status nle_set_fibres(nle_ctx *ctx, const double *fib) {
   Ctx *c = reinterpret_cast<Ctx *>(ctx);
   nle_status s = need_mesh(c);
   if (s != NLE_OK) return s;
+  if (c->mixed) return fail(c, NLE_E_UNSUPPORTED, "not available on mixed meshes");
   if (!fib) return fail(c, NLE_E_INVAL, "null fibre array");
   return guarded(c, [&]() -> nle_status {
     const int64_t ne = c->m.n_elems;
@@ -447,6 +488,7 @@ nle_status nle_set_pressure(nle_ctx *ctx, int64_t nf, const int32_t *tri, double
   Ctx *c = reinterpret_cast<Ctx *>(ctx);
   nle_status s = need_mesh(c);
   if (s != NLE_OK) return s;
+  if (c->mixed) return fail(c, NLE_E_UNSUPPORTED, "not available on mixed meshes");
   if (!std::isfinite(p)) return fail(c, NLE_E_INVAL, "non-finite pressure");
   return guarded(c, [&]() -> nle_status {
     std::vector<int32_t> t;
@@ -464,6 +506,7 @@ nle_status nle_set_robin(nle_ctx *ctx, int64_t nf, const int32_t *tri, double k_
   Ctx *c = reinterpret_cast<Ctx *>(ctx);
   nle_status s = need_mesh(c);
   if (s != NLE_OK) return s;
+  if (c->mixed) return fail(c, NLE_E_UNSUPPORTED, "not available on mixed meshes");
   if (!std::isfinite(k_perp) || !std::isfinite(k_par))
     return fail(c, NLE_E_INVAL, "non-finite spring constants");
   return guarded(c, [&]() -> nle_status {
@@ -538,7 +581,7 @@ nle_status nle_diag(nle_ctx *ctx, double *d) {
   if (s != NLE_OK) return s;
   if (!d) return fail(c, NLE_E_INVAL, "null vector");
   if (!c->lin64) return fail(c, NLE_E_STATE, "nle_diag needs nle_linearize first");
-  NLE_HIP(c, hipMemcpyAsync(d, c->diag64, 3 * c->m.n_nodes * 8, hipMemcpyDeviceToDevice, c->stream));
+  NLE_HIP(c, hipMemcpyAsync(d, c->diag64, ndof(c) * 8, hipMemcpyDeviceToDevice, c->stream));
   return NLE_OK;
 }
 
@@ -580,6 +623,7 @@ nle_status nle_partition_info(const nle_ctx *ctx, int64_t *info) {
   const Ctx *c = reinterpret_cast<const Ctx *>(ctx);
   if (!c || !info) return NLE_E_INVAL;
   if (!c->has_mesh) return NLE_E_STATE;
+  if (c->mixed) return NLE_E_UNSUPPORTED;
   const Mesh &M = c->m;
   info[0] = M.nblk;
   info[1] = M.be_max;

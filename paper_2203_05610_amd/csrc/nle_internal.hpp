@@ -19,7 +19,7 @@ constexpr uint32_t NODE_MASK = 0x0FFFFFFFu;  // node id bits of a block-node wor
 enum ElemOp : int { OP_RES = 0, OP_JV = 1, OP_DIAG = 2, OP_ENERGY = 3 };
 
 struct MatParams {
-  int32_t kind;   // NLE_MAT_M1 / NLE_MAT_M2 / NLE_MAT_M4
+  int32_t kind;   // NLE_MAT_M1 / NLE_MAT_M2 / NLE_MAT_M3 / NLE_MAT_M4
   double mu, lam, cvol, kappa;
   double a_iso, b_iso, a_f, b_f, gamma;  // law M4 (kappa shared)
 };
@@ -57,6 +57,24 @@ struct Mesh {
   std::vector<double> h_X;
 };
 
+// Mixed quadratic-displacement / linear-pressure mesh (twist test): element
+// data in user element order, node-centred gather lists.
+struct MixedMesh {
+  int64_t n_u = 0, n_p = 0, n_e = 0;
+  int32_t *conn = nullptr;    // [10][n_e] displacement nodes
+  int32_t *pconn = nullptr;   // [4][n_e] pressure nodes
+  double *G64 = nullptr;      // [9][n_e] grad lambda_1..3
+  float *G32 = nullptr;
+  double *V64 = nullptr;      // [n_e]
+  float *V32 = nullptr;
+  int32_t *u_ptr = nullptr, *u_ent = nullptr;  // per u node: entries e*10 + a
+  int32_t *p_ptr = nullptr, *p_ent = nullptr;  // per p node: entries e*4 + b
+  uint8_t *umask = nullptr;   // [n_u] Dirichlet bits
+  double *mlump = nullptr;    // [n_p] lumped pressure mass
+  void *cu = nullptr;         // [n_e*10][4] element contributions (double or float)
+  void *cp = nullptr;         // [n_e*4]
+};
+
 struct Ctx;
 
 // Device memory through the optional caller allocator.
@@ -77,6 +95,8 @@ struct Ctx {
 
   Mesh m;
   bool has_mesh = false;
+  bool mixed = false;        // quadratic / linear mixed mesh (law M3)
+  MixedMesh mx;
   std::vector<void *> mesh_allocs;  // freed on re-upload
 
   MatParams mat{NLE_MAT_M1, 1.0, 1.0, 0.25, 1.0 + 2.0 / 3.0};
@@ -164,7 +184,12 @@ struct Ctx {
 };
 
 nle_status fail(Ctx *c, nle_status code, const std::string &msg);
+// Length of the unknown vector: 3 per node, plus one per pressure node.
+inline int64_t ndof(const Ctx *c) { return 3 * c->m.n_nodes + (c->mixed ? c->mx.n_p : 0); }
+// The material must suit the mesh (M3 on mixed meshes only), and M4 needs fibres.
 inline nle_status need_fibres(Ctx *c) {
+  if ((c->mat.kind == NLE_MAT_M3) != c->mixed)
+    return fail(c, NLE_E_STATE, "law M3 goes with a mixed mesh, the other laws with P1 meshes");
   if (c->mat.kind == NLE_MAT_M4 && !c->fib64)
     return fail(c, NLE_E_STATE, "law M4 needs nle_set_fibres");
   return NLE_OK;
@@ -199,6 +224,14 @@ void *surf_apply(Ctx *c, int op, int prec, const void *u, const void *v, int *n_
                  hipError_t *err, double *red = nullptr);
 // Store s * p as the pressure seen by the Jacobian action.
 hipError_t surf_set_linear_pressure(Ctx *c);
+
+// ---- mixed quadratic / linear elements (nle_mixed.hip) --------------------
+nle_status build_mixed_mesh(Ctx *c, int64_t n_u, const double *X, int64_t n_e, const int32_t *conn,
+                            int64_t n_p, const int32_t *pconn);
+nle_status upload_mixed_masks(Ctx *c);
+int mixed_apply(Ctx *c, int op, int prec, const void *x, const void *v, void *out, double *red,
+                hipError_t *err);
+int mixed_red_capacity(const Ctx *c);
 
 // ---- element kernels (nle_elem.hip) ---------------------------------------
 // Launch the block and merge kernels of `op` in precision prec.

@@ -323,12 +323,14 @@ nle_status build_mesh(Ctx *c, int64_t nn, const double *X, int64_t ne, const int
   c->lin64 = c->lin32 = false;
   c->load_scale = 1.0;
   NLE_HIP(c, hipStreamSynchronize(c->stream));
+  c->mixed = false;
   c->has_mesh = true;
   return NLE_OK;
 }
 
 // Re-write the Dirichlet mask bits of the block-node and merge-node words.
 nle_status upload_node_masks(Ctx *c) {
+  if (c->mixed) return upload_mixed_masks(c);
   Mesh &M = c->m;
   std::vector<uint32_t> nodes(M.h_nodes), fx(M.h_fx_node);
   for (auto &w : nodes) w |= uint32_t(c->h_mask[w & NODE_MASK] & 7u) << 28;

@@ -129,7 +129,7 @@ nle_status run_chunks(Ctx *c, const std::vector<uint64_t> &key, int chunk, int m
 // from x = 0.  Converged when ||b - J x|| <= max(rtol ||b||, atol).
 nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x, Carver &W,
                      KspResult *R, int64_t *n_jv) {
-  const int64_t n = 3 * c->m.n_nodes;
+  const int64_t n = ndof(c);
   const size_t vb = size_t(n) * esz(prec);
   const void *dinv = nullptr;
   if (o.pc == NLE_PC_JACOBI)
@@ -424,7 +424,7 @@ nle_status newton(Ctx *c, double *u, const nle_solver_opts &o, nle_report *repor
   Report rep(report);
   c->err.clear();
   const int prec = o.precision == NLE_PREC_MIXED ? NLE_FP32 : NLE_FP64;
-  const int64_t n = 3 * c->m.n_nodes;
+  const int64_t n = ndof(c);
   KspOpts ko{o.ksp_type, o.orth, o.pc, o.restart, o.ksp_max_it, std::max(1, o.check_every),
              o.ksp_rtol, o.ksp_atol};
   const size_t vb64 = (size_t(n) * 8 + 255) & ~size_t(255);
@@ -526,7 +526,7 @@ nle_status bfgs(Ctx *c, double *u, const nle_solver_opts &o, nle_report *report)
   Report rep(report);
   c->err.clear();
   const int prec = o.precision == NLE_PREC_MIXED ? NLE_FP32 : NLE_FP64;
-  const int64_t n = 3 * c->m.n_nodes;
+  const int64_t n = ndof(c);
   const int m = std::max(1, o.qn_m);
   KspOpts ko{o.ksp_type, o.orth, o.pc, o.restart, o.ksp_max_it, std::max(1, o.check_every),
              o.h0_rtol, o.h0_atol};

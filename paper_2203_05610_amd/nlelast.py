@@ -25,7 +25,7 @@ NLE_DIVERGED_LINEAR, NLE_BFGS_BREAKDOWN = 4, 5
 NLE_E_INVAL, NLE_E_BADMESH, NLE_E_STATE = -1, -2, -3
 NLE_E_OOM, NLE_E_HIP, NLE_E_UNSUPPORTED = -4, -5, -6
 NLE_FP64, NLE_FP32 = 0, 1
-NLE_MAT_M1, NLE_MAT_M2, NLE_MAT_M4 = 1, 2, 4
+NLE_MAT_M1, NLE_MAT_M2, NLE_MAT_M3, NLE_MAT_M4 = 1, 2, 3, 4
 NLE_NK, NLE_INK, NLE_BFGS = 0, 1, 2
 NLE_KSP_GMRES, NLE_KSP_CG, NLE_KSP_MINRES = 0, 1, 2
 NLE_ORTH_MGS, NLE_ORTH_CGS2 = 0, 1
@@ -48,7 +48,7 @@ EXPORTS = [
     "nle_solve_bfgs", "nle_partition_info", "nle_batch_create", "nle_batch_destroy",
     "nle_batch_last_error", "nle_batch_add", "nle_batch_finalize", "nle_batch_layout",
     "nle_batch_solve", "nle_set_fibres", "nle_set_active_tension", "nle_set_pressure",
-    "nle_set_robin",
+    "nle_set_robin", "nle_upload_mesh_mixed",
 ]
 
 
@@ -110,6 +110,7 @@ def lib() -> ctypes.CDLL:
         "nle_set_body_force": (I32, [P, P]),
         "nle_set_load_scale": (I32, [P, D]),
         "nle_set_fibres": (I32, [P, P]),
+        "nle_upload_mesh_mixed": (I32, [P, I64, P, I64, P, I64, P]),
         "nle_set_active_tension": (I32, [P, D]),
         "nle_set_pressure": (I32, [P, I64, P, D]),
         "nle_set_robin": (I32, [P, I64, P, D, D]),
@@ -179,6 +180,12 @@ class Context:
         self.handle = h
         self.n_nodes = 0
         self.n_elems = 0
+        self.n_press = 0
+
+    @property
+    def n_dofs(self) -> int:
+        """Unknowns: 3 per node, plus one per pressure node on mixed meshes."""
+        return 3 * self.n_nodes + self.n_press
 
     def close(self):
         if getattr(self, "handle", None):
@@ -203,7 +210,7 @@ class Context:
             raise ValueError("expected a contiguous tensor on the context's device")
         if dtype is not None and t.dtype != dtype:
             raise ValueError(f"expected dtype {dtype}, got {t.dtype}")
-        n = 3 * self.n_nodes if n is None else n
+        n = self.n_dofs if n is None else n
         if t.numel() != n:
             raise ValueError(f"expected {n} entries, got {t.numel()}")
         return ctypes.c_void_p(t.data_ptr())
@@ -243,6 +250,20 @@ def nle_upload_mesh(ctx: Context, X, conn) -> None:
     ctx.check(lib().nle_upload_mesh(ctx.handle, X.shape[0], px, conn.shape[0], conn.shape[1], pc))
     ctx.n_nodes = X.shape[0]
     ctx.n_elems = conn.shape[0]
+    ctx.n_press = 0
+
+
+def nle_upload_mesh_mixed(ctx: Context, X, conn, n_pnodes: int, pconn) -> None:
+    X, px = _host(X, np.float64)
+    conn, pc = _host(conn, np.int32)
+    pconn, ppc = _host(pconn, np.int32)
+    if X.ndim != 2 or X.shape[1] != 3 or conn.shape[1:] != (10,) or pconn.shape != (conn.shape[0], 4):
+        raise ValueError("X must be (n, 3), conn (n_e, 10) and pconn (n_e, 4)")
+    ctx.check(lib().nle_upload_mesh_mixed(ctx.handle, X.shape[0], px, conn.shape[0], pc,
+                                          int(n_pnodes), ppc))
+    ctx.n_nodes = X.shape[0]
+    ctx.n_elems = conn.shape[0]
+    ctx.n_press = int(n_pnodes)
 
 
 def nle_set_material(ctx: Context, kind: int, params) -> None:

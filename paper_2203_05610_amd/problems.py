@@ -157,3 +157,49 @@ def solve_heartbeat(ctx: nl.Context, u, method: str, opts, schedule, gamma_max: 
 def heartbeat_ok(reps, schedule) -> bool:
     acc = [r["t"] for r in reps if r["accepted"]]
     return bool(acc) and acc[-1] == float(schedule[-1][0])
+
+
+def setup_twist(ctx: nl.Context, mesh, mu: float, theta: float = 0.0) -> None:
+    """Twist test (Sec. 4): quadratic displacement / linear pressure mesh, law
+    M3, bottom clamped, top x/y rotated by theta about x = y = 1/2.  The
+    Dirichlet data come from synthetic.twist_dirichlet via set_twist_angle."""
+    nl.nle_upload_mesh_mixed(ctx, mesh.X, mesh.conn, mesh.n_pressure, mesh.pconn)
+    nl.nle_set_material(ctx, nl.NLE_MAT_M3, [mu])
+    nl.nle_set_load_scale(ctx, 1.0)
+
+
+def solve_twist(ctx: nl.Context, x, method: str, opts, angles, dirichlet, hist_cap: int = 4096,
+                max_cuts: int = 8, start: float = 0.0):
+    """Rotate the top face through the given angles in turn (warm-started).
+    dirichlet(theta) -> (dofs, values).  A failed step is retried from the last
+    converged state at the mid angle (at most max_cuts times in total).
+    Reports carry 'theta' and 'accepted'."""
+    reps = []
+    targets = [float(a) for a in angles]
+    backup = x.clone()
+    prev = float(start)
+    cuts = 0
+    i = 0
+    while i < len(targets):
+        th = targets[i]
+        dofs, vals = dirichlet(th)
+        nl.nle_set_dirichlet(ctx, dofs, vals)
+        st, rep = SOLVERS[method](ctx, x, opts, hist_cap)
+        rep.update(theta=th, accepted=st == nl.NLE_OK)
+        reps.append(rep)
+        if st == nl.NLE_OK:
+            backup.copy_(x)
+            prev = th
+            i += 1
+            continue
+        x.copy_(backup)
+        if cuts >= max_cuts:
+            break
+        cuts += 1
+        targets.insert(i, 0.5 * (prev + th))
+    return reps
+
+
+def twist_ok(reps, angles) -> bool:
+    acc = [r["theta"] for r in reps if r["accepted"]]
+    return bool(acc) and acc[-1] == float(angles[-1])
