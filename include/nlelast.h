@@ -122,7 +122,8 @@ typedef struct {
   int32_t reserved;
   double ksp_rtol, ksp_atol;        /* NK: 1e-6, 1e-10                    */
   double ew_rtol0, ew_rtolmax;      /* iNK: 0.1, 0.1                      */
-  double ew_rtolmin;                /* lower clip of eta (0: none)        */
+  double ew_rtolmin;                /* lower clip of eta (0: none); mixed
+                                       precision clips at 1e-4 at least   */
   double ew_gamma, ew_alpha, ew_alpha2, ew_threshold; /* 1, phi, phi, 0.1 */
   double ink_ksp_atol;              /* iNK absolute tolerance: 1e-14      */
   double snes_rtol, snes_atol;      /* ||r_k|| <= max(rtol ||r_0||, atol) */
@@ -261,9 +262,15 @@ nle_status nle_energy(nle_ctx *ctx, const double *u_dev, double *pi_host);
 /* Defaults of App. A for the method (NK, iNK or BFGS); ksp_type CG. */
 void nle_default_opts(int32_t method, nle_solver_opts *opts);
 /* Solve r(u) = 0 at the current load scale, starting from u (double,
- * device, overwritten with the result; Dirichlet values are lifted first).
+ * device, overwritten with the result).  If u does not hold the prescribed
+ * Dirichlet values (a new load step of a displacement-driven problem), the
+ * change w = g - u is first carried into the interior: u += w + d with
+ * K_ff d = -(r(u) + K w)_f at the current u, solved by the configured Krylov
+ * method to ksp_rtol / ksp_atol (BFGS: only with h0 = KSP); then the values
+ * are lifted.
  * Convergence: ||r_k||_2 <= max(snes_rtol ||r_0||_2, snes_atol) with r_0
- * the residual after the lift.  `report` may be NULL. */
+ * the residual after the lift, or the imbalance ||(r(u) + K w)_f|| of the
+ * step above when that is larger.  `report` may be NULL. */
 nle_status nle_solve_nk(nle_ctx *ctx, double *u_dev, const nle_solver_opts *opts, nle_report *report);
 nle_status nle_solve_ink(nle_ctx *ctx, double *u_dev, const nle_solver_opts *opts, nle_report *report);
 nle_status nle_solve_bfgs(nle_ctx *ctx, double *u_dev, const nle_solver_opts *opts, nle_report *report);

@@ -367,6 +367,7 @@ nle_status solve(Batch *b, int method, const nle_solver_opts &o, double *u, nle_
           if (stol > o.ew_threshold) eta = std::max(eta, stol);
         }
         eta = std::max(std::min(eta, o.ew_rtolmax), o.ew_rtolmin);
+        if (prec == NLE_FP32) eta = std::max(eta, 1e-4);  // FP32 Krylov floor
         atol = o.ink_ksp_atol;
       }
       I.eta = eta;

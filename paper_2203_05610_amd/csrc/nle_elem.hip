@@ -40,6 +40,7 @@ struct ElemArgs {
   double *red;        // per-workgroup partial sums (residual norm^2 / energy)
   int32_t *flag;      // set to 1 when some det F <= 0
   const int32_t *skip;// if non-null and *skip != 0 the launch does nothing
+  int32_t nomask;     // Jv: keep v on Dirichlet dofs, zero Dirichlet rows
   // Jv epilogue (optional): out = J v - c w with c = *ep_coef, and partial sums
   // of v.out written to ep_red (one per workgroup of each kernel)
   const T *ep_w;
@@ -73,6 +74,7 @@ struct MergeArgs {
   const double *ep_coef;
   double *ep_red;
   const T *fs;
+  int32_t nomask;
   const int32_t *mwg_inst;  // batched mode: instance of each merge workgroup
   const double *inst_s;
   const int32_t *inst_done;
@@ -242,7 +244,8 @@ __device__ __forceinline__ double energy_density(const Kin<T> &k, const T H[3][3
 template <typename T, int OP>
 __device__ __forceinline__ void finalize_node(uint32_t g, uint32_t mk, const T acc[3], const T *v,
                                               T *out, const double *fext, double s,
-                                              double &nrm, const T *epw, T epc, const T *fs) {
+                                              double &nrm, const T *epw, T epc, const T *fs,
+                                              int nomask) {
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     const int64_t d = 3 * int64_t(g) + i;
@@ -254,7 +257,7 @@ __device__ __forceinline__ void finalize_node(uint32_t g, uint32_t mk, const T a
       nrm += r * r;
     } else if (OP == OP_JV) {
       const T vd = v[d];
-      T y = fixed ? vd : a;
+      T y = fixed ? (nomask ? T(0) : vd) : a;
       if (epw) y -= epc * epw[d];
       out[d] = y;
       nrm += double(vd * y);
@@ -487,7 +490,7 @@ __global__ __launch_bounds__(NT) void k_elem_block(ElemArgs<T> A) {
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       uS[i * NL + l] = A.u[g3 + i];
-      if (OP == OP_JV) vS[i * NL + l] = ((mk >> i) & 1u) ? T(0) : A.v[g3 + i];
+      if (OP == OP_JV) vS[i * NL + l] = (!A.nomask && ((mk >> i) & 1u)) ? T(0) : A.v[g3 + i];
     }
   }
   __syncthreads();
@@ -540,7 +543,7 @@ __global__ __launch_bounds__(NT) void k_elem_block(ElemArgs<T> A) {
       pp[2] = acc[2];
     } else {
       finalize_node<T, OP>(w & NODE_MASK, (w >> 28) & 7u, acc, A.v, A.out, A.fext, lscale, nrm,
-                           A.ep_w, epc, A.fs);
+                           A.ep_w, epc, A.fs, A.nomask);
     }
   }
   if (OP == OP_RES || (OP == OP_JV && A.ep_red)) {
@@ -584,7 +587,7 @@ __global__ __launch_bounds__(NT) void k_elem_merge(MergeArgs<T> A) {
     }
     const uint32_t w = A.fx_node[k];
     finalize_node<T, OP>(w & NODE_MASK, (w >> 28) & 7u, acc, A.v, A.out, A.fext, lscale, nrm,
-                         A.ep_w, A.ep_coef ? T(A.ep_coef[0]) : T(0), A.fs);
+                         A.ep_w, A.ep_coef ? T(A.ep_coef[0]) : T(0), A.fs, A.nomask);
   }
   if (OP == OP_RES || (OP == OP_JV && A.ep_red)) {
     const double s = block_sum(nrm, rs);
@@ -625,6 +628,7 @@ int launch(Ctx *c, int op, const T *G, const T *V, const T *u, const T *v, T *ou
   A.red = red;
   A.flag = c->inst_inv ? c->inst_inv : c->dflag;
   A.skip = c->elem_skip;
+  A.nomask = (op == OP_JV && c->jv_nomask) ? 1 : 0;
   A.ep_w = static_cast<const T *>(c->ep.w);
   A.ep_coef = c->ep.coef;
   A.ep_red = op == OP_JV ? c->ep.red : nullptr;
@@ -682,6 +686,7 @@ int launch(Ctx *c, int op, const T *G, const T *V, const T *u, const T *v, T *ou
     B.inst_s = c->inst_s;
     B.inst_done = c->inst_done;
     B.skip = c->elem_skip;
+    B.nomask = A.nomask;
     B.ep_w = static_cast<const T *>(c->ep.w);
     B.ep_coef = c->ep.coef;
     B.ep_red = (op == OP_JV && c->ep.red) ? c->ep.red + M.nblk : nullptr;

@@ -162,6 +162,10 @@ struct Ctx {
   double *dscal = nullptr;   // device scalars
   int32_t *dflag = nullptr;  // device flags: [0] inverted element
   const int32_t *elem_skip = nullptr;  // Krylov done flag seen by element kernels
+  // Jacobian action with the Dirichlet columns kept and the Dirichlet rows
+  // zero: y = (K w) on free rows, the coupling a change of prescribed values
+  // induces (used by the step that carries such a change into the interior)
+  bool jv_nomask = false;
   // Jv epilogue used by the Krylov loops: out = J v - (*coef) w; partial sums
   // of v.out to red (block partials, then merge partials)
   struct {
@@ -254,6 +258,8 @@ hipError_t vec_cast_scale(Ctx *c, int px, const void *x, int py, void *y, double
 hipError_t vec_axpy(Ctx *c, int px, const void *x, int py, void *y, double a_host,
                     const double *a_dev, int64_t n);
 hipError_t vec_lift(Ctx *c, double *u);
+// w[d] = (prescribed value - u[d]) on the Dirichlet dofs; other entries untouched
+hipError_t vec_dir_delta(Ctx *c, const double *u, double *w);
 // partials of sum_i a_i b_i (and sum b_i^2 if sq != 0) -> red; returns count
 int vec_dot_partials(Ctx *c, int prec, const void *a, const void *b, int64_t n, double *red,
                      hipError_t *err);

@@ -48,6 +48,7 @@ struct MixArgs {
   double *red;
   int32_t *flag;
   const int32_t *skip;
+  int32_t nomask;
 };
 
 template <typename T, int OP>
@@ -75,7 +76,7 @@ __global__ __launch_bounds__(NT) void k_mixed_elem(MixArgs<T> A) {
     T U[10][3], W[10][3], P4[4], WP[4];
 #pragma unroll
     for (int a = 0; a < 10; ++a) {
-      const uint32_t mk = OP == OP_JV ? A.umask[cn[a]] : 0u;
+      const uint32_t mk = (OP == OP_JV && !A.nomask) ? A.umask[cn[a]] : 0u;
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         U[a][i] = A.x[3 * int64_t(cn[a]) + i];
@@ -248,6 +249,7 @@ struct GatherArgs {
   const T *ep_w;
   const double *ep_coef;
   const int32_t *skip;
+  int32_t nomask;
 };
 
 template <typename T, int OP>
@@ -276,7 +278,7 @@ __global__ __launch_bounds__(NT) void k_mixed_gather(GatherArgs<T> A) {
         nrm += r * r;
       } else if (OP == OP_JV) {
         const T vd = A.v[d];
-        T y = fixed ? vd : acc[i];
+        T y = fixed ? (A.nomask ? T(0) : vd) : acc[i];
         if (A.ep_w) y -= epc * A.ep_w[d];
         A.out[d] = y;
         nrm += double(vd * y);
@@ -335,6 +337,7 @@ int launch_mixed(Ctx *c, int op, const T *G, const T *V, const T *x, const T *v,
   A.red = red;
   A.flag = c->dflag;
   A.skip = c->elem_skip;
+  A.nomask = (op == OP_JV && c->jv_nomask) ? 1 : 0;
   const int g1 = int((M.n_e + NT - 1) / NT);
   switch (op) {
     case OP_RES:
@@ -370,6 +373,7 @@ int launch_mixed(Ctx *c, int op, const T *G, const T *V, const T *x, const T *v,
   B.s = c->load_scale;
   B.mu = c->mat.mu;
   B.skip = c->elem_skip;
+  B.nomask = A.nomask;
   const bool jv_ep = op == OP_JV && c->ep.red;
   B.red = op == OP_RES ? red : (jv_ep ? c->ep.red : nullptr);
   B.ep_w = op == OP_JV ? static_cast<const T *>(c->ep.w) : nullptr;

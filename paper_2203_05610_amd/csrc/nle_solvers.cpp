@@ -114,13 +114,29 @@ nle_status run_chunks(Ctx *c, const std::vector<uint64_t> &key, int chunk, int m
     c->gexec = ex;
     c->gkey = key;
   }
+  // Stagnation: the squared residual norm (scalar slot 3 of both CG and
+  // MINRES) has not dropped 2% below its best value for max(4000, its/4)
+  // iterations.  This happens when the solve precision's rounding floor lies
+  // above the requested tolerance (FP32 recurrences on ill-conditioned
+  // systems); the iterate is returned as after the iteration limit.
+  double best = -1.0;
+  int best_at = 0;
   for (int done = 0; done < max_it; done += chunk) {
     NLE_HIP(c, hipGraphLaunch(c->gexec, c->stream));
-    nle_status s = read_scalars(c, flag, 8);
-    if (s != NLE_OK) return s;
+    NLE_HIP(c, hipMemcpyAsync(c->hpin, flag, 8, hipMemcpyDeviceToHost, c->stream));
+    NLE_HIP(c, hipMemcpyAsync(c->hpin + 1, c->dscal + 3, 8, hipMemcpyDeviceToHost, c->stream));
+    NLE_HIP(c, hipStreamSynchronize(c->stream));
     int32_t f;
     std::memcpy(&f, c->hpin, 4);
     if (f != 0) break;
+    const double rr = c->hpin[1];
+    const int its = done + chunk;
+    if (best < 0.0 || rr < 0.98 * best) {
+      best = rr;
+      best_at = its;
+    } else if (its - best_at >= std::max(4000, its / 4)) {
+      break;
+    }
   }
   return NLE_OK;
 }
@@ -193,7 +209,8 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
                                    uint64_t(uintptr_t(x)), uint64_t(uintptr_t(a.r)),
                                    uint64_t(uintptr_t(dinv)), uint64_t(uintptr_t(ulin)),
                                    uint64_t(uintptr_t(c->red)), uint64_t(uintptr_t(c->m.G32)),
-                                   uint64_t(uintptr_t(c->m.nodes)), uint64_t(c->mat.kind)};
+                                   uint64_t(uintptr_t(c->m.nodes)), uint64_t(c->mat.kind),
+                                   uint64_t(uintptr_t(c->mx.G32)), uint64_t(uintptr_t(c->mx.cu))};
       st = run_chunks(c, key, check, o.max_it, flag, iter);
     } else {
       MinresArgs a;
@@ -232,7 +249,8 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
                                    uint64_t(uintptr_t(x)), uint64_t(uintptr_t(a.r1)),
                                    uint64_t(uintptr_t(dinv)), uint64_t(uintptr_t(ulin)),
                                    uint64_t(uintptr_t(c->red)), uint64_t(uintptr_t(c->m.G32)),
-                                   uint64_t(uintptr_t(c->m.nodes)), uint64_t(c->mat.kind)};
+                                   uint64_t(uintptr_t(c->m.nodes)), uint64_t(c->mat.kind),
+                                   uint64_t(uintptr_t(c->mx.G32)), uint64_t(uintptr_t(c->mx.cu))};
       st = run_chunks(c, key, check, o.max_it, flag, iter);
     }
     if (st != NLE_OK) return st;
@@ -330,6 +348,8 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
   return NLE_OK;
 }
 
+constexpr double kEtaMinFP32 = 1e-4;
+
 double ew_eta(const nle_solver_opts &o, int k, double rn, double rn_prev, double linres_prev,
               double eta_prev) {
   if (k == 0) return std::min(o.ew_rtol0, o.ew_rtolmax);
@@ -406,6 +426,66 @@ nle_status check_ready(Ctx *c, double *u, const nle_solver_opts *o) {
   return NLE_OK;
 }
 
+// Carry a change of the prescribed Dirichlet values into the interior before
+// the Newton loop: with w = g - u on the Dirichlet dofs (0 elsewhere), solve
+// K_ff d = -(r(u) + K w)_f with the tangent at the current u and set
+// u += w + d (the first Newton step of the problem whose boundary increment
+// is part of the unknown step).  Lifting u to g directly can invert the
+// elements next to a rotated face.  Nothing is done when u already holds
+// the prescribed values, or when r(u) shows an inverted element.  *imb
+// receives ||(r(u) + K w)_f|| (the step's initial imbalance, 0 if skipped).
+nle_status dirichlet_step(Ctx *c, double *u, const KspOpts &ko, int prec, double *w64, double *r,
+                          void *b, void *dx, void *tmp, Carver &W, size_t ksp_off,
+                          int64_t *n_jv, int64_t *lit_total, int64_t *n_res, double *imb) {
+  *imb = 0.0;
+  if (c->n_dir == 0) return NLE_OK;
+  const int64_t n = ndof(c);
+  NLE_HIP(c, vec_fill(c, NLE_FP64, w64, 0.0, n));
+  NLE_HIP(c, vec_dir_delta(c, u, w64));
+  hipError_t e;
+  int np = vec_dot_partials(c, NLE_FP64, w64, w64, n, c->red, &e);
+  if (e != hipSuccess) return fail(c, NLE_E_HIP, "Dirichlet step norm");
+  NLE_HIP(c, reduce_scalar(c, c->red, np, c->dscal + 62));
+  nle_status s = read_scalars(c, c->dscal + 62, 8);
+  if (s != NLE_OK) return s;
+  if (!(c->hpin[0] > 0.0)) return NLE_OK;
+  double rn = 0.0;
+  bool inv = false;
+  s = residual_norm(c, u, r, &rn, &inv);
+  if (s != NLE_OK) return s;
+  ++*n_res;
+  if (inv || !std::isfinite(rn)) return NLE_OK;
+  s = linearize(c, u, prec);
+  if (s != NLE_OK) return s;
+  NLE_HIP(c, vec_cast_scale(c, NLE_FP64, w64, prec, dx, 1.0, n));
+  c->jv_nomask = true;
+  s = jv(c, dx, tmp, prec);
+  c->jv_nomask = false;
+  if (s != NLE_OK) return s;
+  ++*n_jv;
+  NLE_HIP(c, vec_axpy(c, prec, tmp, NLE_FP64, r, 1.0, nullptr, n));
+  np = vec_dot_partials(c, NLE_FP64, r, r, n, c->red, &e);
+  if (e != hipSuccess) return fail(c, NLE_E_HIP, "Dirichlet step norm");
+  NLE_HIP(c, reduce_scalar(c, c->red, np, c->dscal + 62));
+  s = read_scalars(c, c->dscal + 62, 8);
+  if (s != NLE_OK) return s;
+  const double bn = std::sqrt(c->hpin[0]);
+  *imb = std::isfinite(bn) ? bn : 0.0;
+  NLE_HIP(c, vec_axpy(c, NLE_FP64, w64, NLE_FP64, u, 1.0, nullptr, n));
+  if (!(bn > 0.0) || !std::isfinite(bn)) return NLE_OK;
+  NLE_HIP(c, vec_cast_scale(c, NLE_FP64, r, prec, b, -1.0 / bn, n));
+  KspOpts kk = ko;
+  kk.atol = ko.atol / bn;
+  KspResult kr;
+  W.off = ksp_off;
+  s = ksp_solve(c, kk, prec, b, dx, W, &kr, n_jv);
+  if (s != NLE_OK) return s;
+  *lit_total += kr.its;
+  if (kr.flag == 3) return NLE_OK;  // no usable interior step: the lift alone
+  NLE_HIP(c, vec_axpy(c, prec, dx, NLE_FP64, u, bn, nullptr, n));
+  return NLE_OK;
+}
+
 nle_status finish(Ctx *c, Report &rep, nle_status st, int nit, double rn0, double rn, Timer &t) {
   const double ms = t.stop();
   if (rep.r) {
@@ -429,23 +509,32 @@ nle_status newton(Ctx *c, double *u, const nle_solver_opts &o, nle_report *repor
              o.ksp_rtol, o.ksp_atol};
   const size_t vb64 = (size_t(n) * 8 + 255) & ~size_t(255);
   const size_t vbp = (size_t(n) * esz(prec) + 255) & ~size_t(255);
-  nle_status s = ensure_ws(c, vb64 + 3 * vbp + ksp_bytes(ko, n, prec));
+  nle_status s = ensure_ws(c, 2 * vb64 + 3 * vbp + ksp_bytes(ko, n, prec));
   if (s != NLE_OK) return s;
   Carver W{static_cast<char *>(c->ws)};
   double *r = static_cast<double *>(W.take(vb64));
+  double *w64 = static_cast<double *>(W.take(vb64));
   void *b = W.take(vbp);
   void *dx = W.take(vbp);
   void *tmp = W.take(vbp);
   const size_t ksp_off = W.off;
   int64_t n_jv = 0, n_res = 0, lit_total = 0;
 
+  // the boundary increment is carried in at the NK tolerances (a loose
+  // interior step can invert the elements next to a moved face)
+  double imb = 0.0;
+  s = dirichlet_step(c, u, ko, prec, w64, r, b, dx, tmp, W, ksp_off, &n_jv, &lit_total, &n_res,
+                     &imb);
+  if (s != NLE_OK) return s;
   NLE_HIP(c, vec_lift(c, u));
   double rn = 0.0;
   bool inv = false;
   s = residual_norm(c, u, r, &rn, &inv);
   if (s != NLE_OK) return s;
   ++n_res;
-  const double rn0 = rn;
+  // relative to the load step's initial imbalance when a boundary increment
+  // was carried in (the residual after that step is already reduced)
+  const double rn0 = imb > rn ? imb : rn;
   const double tol = std::max(o.snes_rtol * rn0, o.snes_atol);
   double rn_prev = 0.0, linres_prev = 0.0, eta_prev = 0.0;
   int k = 0;
@@ -480,6 +569,9 @@ nle_status newton(Ctx *c, double *u, const nle_solver_opts &o, nle_report *repor
     double eta = o.ksp_rtol, atol = o.ksp_atol;
     if (inexact) {
       eta = ew_eta(o, k, rn, rn_prev, linres_prev, eta_prev);
+      // an FP32 Krylov solve cannot reach much below the single-precision
+      // rounding level of its recurrences
+      if (prec == NLE_FP32) eta = std::max(eta, kEtaMinFP32);
       atol = o.ink_ksp_atol;
     }
     // b = -r / ||r||: the solve is scaled to a unit right-hand side
@@ -558,13 +650,22 @@ nle_status bfgs(Ctx *c, double *u, const nle_solver_opts &o, nle_report *report)
   std::vector<int> free_slots;
   for (int i = m; i >= 0; --i) free_slots.push_back(i);
 
+  double imb = 0.0;
+  if (o.h0 == NLE_H0_KSP) {  // with a Krylov method configured for H0
+    KspOpts kp = ko;
+    kp.rtol = o.ksp_rtol;
+    kp.atol = o.ksp_atol;
+    s = dirichlet_step(c, u, kp, prec, y64, g, b, q, z, W, ksp_off, &n_jv, &lit_total, &n_res,
+                       &imb);
+    if (s != NLE_OK) return s;
+  }
   NLE_HIP(c, vec_lift(c, u));
   double rn = 0.0;
   bool inv = false;
   s = residual_norm(c, u, g, &rn, &inv);
   if (s != NLE_OK) return s;
   ++n_res;
-  const double rn0 = rn;
+  const double rn0 = imb > rn ? imb : rn;
   const double tol = std::max(o.snes_rtol * rn0, o.snes_atol);
   if (rn > tol && std::isfinite(rn) && !inv) {
     s = linearize(c, u, prec);  // the single linearization of the step

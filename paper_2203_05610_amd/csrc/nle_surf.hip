@@ -38,6 +38,7 @@ struct SurfArgs {
   T *fs;
   double *red;          // energy partials (one per workgroup)
   const int32_t *skip;
+  int32_t nomask;       // Jv: keep v on Dirichlet dofs
 };
 
 template <typename T>
@@ -80,7 +81,7 @@ __global__ __launch_bounds__(NT) void k_surface(SurfArgs<T> A) {
           } else {
             // the tangent has identity rows and columns on Dirichlet dofs:
             // v's prescribed components do not enter the coupling
-            const uint32_t fm = A.fmask[f];
+            const uint32_t fm = A.nomask ? 0u : A.fmask[f];
             T d1[3], d2[3];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
@@ -104,7 +105,7 @@ __global__ __launch_bounds__(NT) void k_surface(SurfArgs<T> A) {
           for (int i = 0; i < 3; ++i) acc[i] += area / T(6) * (kpar + dk * N[i] * N[i]);
         } else {
           const T *w = OP == OP_JV ? A.v : A.u;
-          const uint32_t fm = OP == OP_JV ? A.fmask[f] : 0u;
+          const uint32_t fm = (OP == OP_JV && !A.nomask) ? A.fmask[f] : 0u;
 #pragma unroll
           for (int b = 0; b < 3; ++b) {
             const T m = area / T(12) * (n[b] == g ? T(2) : T(1));
@@ -168,6 +169,7 @@ void launch_surface(Ctx *c, int op, const T *u, const T *v, T *fs, double *red, 
   A.fs = fs;
   A.red = red;
   A.skip = c->elem_skip;
+  A.nomask = (op == OP_JV && c->jv_nomask) ? 1 : 0;
   const int grid = int((S.nsn + NT - 1) / NT);
   switch (op) {
     case OP_RES:

@@ -77,6 +77,13 @@ __global__ __launch_bounds__(NT) void k_lift(double *u, const int64_t *dofs, con
     u[dofs[i]] = vals[i];
 }
 
+// w[d] = g_d - u[d] on the Dirichlet dofs (w is zero elsewhere)
+__global__ __launch_bounds__(NT) void k_dir_delta(const double *u, const int64_t *dofs,
+                                                  const double *vals, double *w, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT)
+    w[dofs[i]] = vals[i] - u[dofs[i]];
+}
+
 template <typename T>
 __global__ __launch_bounds__(NT) void k_dot(const T *a, const T *b, int64_t n, double *red) {
   __shared__ T sh[NT / 64];
@@ -673,6 +680,12 @@ hipError_t vec_recip(Ctx *c, const double *d, double *di, int64_t n) {
 hipError_t vec_lift(Ctx *c, double *u) {
   if (c->n_dir == 0) return hipSuccess;
   LAUNCH(k_lift, vgrid(c->n_dir), u, c->dir_dofs, c->dir_vals, c->n_dir);
+  return hipGetLastError();
+}
+
+hipError_t vec_dir_delta(Ctx *c, const double *u, double *w) {
+  if (c->n_dir == 0) return hipSuccess;
+  LAUNCH(k_dir_delta, vgrid(c->n_dir), u, c->dir_dofs, c->dir_vals, w, c->n_dir);
   return hipGetLastError();
 }
 
