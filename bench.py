@@ -257,6 +257,100 @@ def batch_c4(nl, torch, count: int, serial_stride: int, steps: int):
     }
 
 
+TWIST_METHODS = {
+    "nk_fp64": ("nk", "fp64", {"ksp": "minres"}),
+    "ink_fp64": ("ink", "fp64", {"ksp": "minres"}),
+    "nk_mixed": ("nk", "mixed", {"ksp": "minres"}),
+    "ink_mixed": ("ink", "mixed", {"ksp": "minres"}),
+}
+
+
+def twist_c3(nl, torch, n: int, methods):
+    """Twist test: unit cube, n^3 cells -> 6 n^3 quadratic tets with linear
+    pressure, mu = 1, top face rotated 10 deg per step to 90 deg (9 steps),
+    MINRES with the block-diagonal preconditioner (Jacobi on u, lumped
+    pressure mass / mu on p).  Setup outside the timed region."""
+    import math
+
+    import synthetic as syn
+    from paper_2203_05610_amd import problems
+
+    mesh = syn.twist_p2_mesh(n)
+    ctx = nl.Context(0)
+    problems.setup_twist(ctx, mesh, 1.0)
+    angles = [math.radians(10 * s) for s in range(1, 10)]
+    dirf = lambda th: syn.twist_dirichlet(mesh.X, mesh.sets["bottom"], mesh.sets["top"], th)  # noqa: E731
+    out = {"workload": f"twist {n}^3 cells -> {mesh.n_elems} P2 tets + P1 pressure, "
+                       f"{ctx.n_dofs} unknowns, mu=1, 9 x 10 deg", "methods": {}}
+    for m in methods:
+        name, prec, kw = TWIST_METHODS[m]
+        opts = problems.make_opts(name, prec, **dict(kw))
+        x = torch.zeros(ctx.n_dofs, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        reps = problems.solve_twist(ctx, x, name, opts, angles, dirf)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        out["methods"][m] = {"seconds": round(dt, 3), "ok": problems.twist_ok(reps, angles),
+                             "nit": [r["nit"] for r in reps],
+                             "lit": int(sum(r["lit_total"] for r in reps)),
+                             "cutbacks": sum(1 for r in reps if not r["accepted"])}
+        print(f"[bench] twist {m}: {dt:.2f}s ok={out['methods'][m]['ok']}", file=sys.stderr,
+              flush=True)
+    ctx.close()
+    return out
+
+
+CARDIAC_METHODS = {
+    "ink_fp64": ("ink", "fp64", {"ksp": "minres"}),
+    "ink_mixed": ("ink", "mixed", {"ksp": "minres"}),
+    "nk_fp64": ("nk", "fp64", {"ksp": "minres"}),
+    "bfgs_ib_fp64": ("bfgs", "fp64", {"ksp": "minres", "h0": "ksp", "qn_m": 10}),
+}
+
+
+def cardiac_c5(nl, torch, grid, methods, n_steps: int):
+    """Heartbeat (cardiac-like law M4, fibres, active tension, follower
+    endocardial pressure, epicardial springs), time steps of the activation
+    schedule; MINRES + Jacobi (the follower-pressure asymmetry is ~1e-6 of the
+    tangent; MINRES's residual is tracked as b - A x, so its stopping test
+    stays exact)."""
+    import synthetic as syn
+    from paper_2203_05610_amd import problems
+
+    C = syn.CARDIAC
+    mesh = syn.shell_mesh(*grid)
+    ctx = nl.Context(0)
+    problems.setup_cardiac(ctx, mesh, C, syn.shell_dirichlet(mesh))
+    steps = syn.heartbeat_schedule()[:n_steps]
+    out = {"workload": f"ventricle shell {grid[0]}x{grid[1]}x{grid[2]} -> {mesh.n_elems} P1 tets, "
+                       f"{mesh.n_dofs} dofs, {len(steps)} time steps", "methods": {}}
+    for m in methods:
+        name, prec, kw = CARDIAC_METHODS[m]
+        opts = problems.make_opts(name, prec, **dict(kw))
+        u = torch.zeros(mesh.n_dofs, dtype=torch.float64, device="cuda")
+        prev = (0.0, 0.0)
+        t = time.perf_counter()
+        reps_all, ok = [], True
+        for stp in steps:  # one call per step so progress is printed
+            reps = problems.solve_heartbeat(ctx, u, name, opts, [stp], C["gamma_max"], start=prev)
+            reps_all += reps
+            prev = stp
+            print(f"[bench] cardiac {m} t={stp[0]:.2f}: {reps[-1]['status_name']} "
+                  f"nit={[r['nit'] for r in reps]}", file=sys.stderr, flush=True)
+            if not reps[-1]["accepted"]:
+                ok = False
+                break
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        out["methods"][m] = {"seconds": round(dt, 3), "ok": ok,
+                             "nit": [r["nit"] for r in reps_all],
+                             "lit": int(sum(r["lit_total"] for r in reps_all)),
+                             "cutbacks": sum(1 for r in reps_all if not r["accepted"])}
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -274,6 +368,14 @@ def main():
     ap.add_argument("--batch-serial-stride", type=int, default=64,
                     help="serial FP64 NK baseline on every k-th batch instance (0 skips it)")
     ap.add_argument("--batch-only", action="store_true", help="only the batched-solve leg")
+    ap.add_argument("--twist", type=int, default=24, help="twist cube cells per edge (0 skips)")
+    ap.add_argument("--twist-methods", default="nk_fp64,ink_mixed")
+    ap.add_argument("--cardiac", default="", help="ventricle shell grid n_t,n_s,n_c (e.g. "
+                    "8,80,256); empty skips this leg (minutes at full size)")
+    ap.add_argument("--cardiac-methods", default="ink_fp64,ink_mixed")
+    ap.add_argument("--cardiac-steps", type=int, default=20)
+    ap.add_argument("--legs-only", action="store_true",
+                    help="only the twist and cardiac legs (for their own runs)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the Jv roofline phase (plus a 256 MB copy kernel used to "
                          "calibrate HBM byte counters); for profiling runs")
@@ -303,6 +405,16 @@ def main():
         print(json.dumps({"batch_only": True,
                           "batch": batch_c4(nl, torch, args.batch, args.batch_serial_stride,
                                             max(args.steps, 1))}))
+        return
+
+    if args.legs_only:
+        res = {"legs_only": True}
+        if args.twist > 0:
+            res["twist"] = twist_c3(nl, torch, args.twist, args.twist_methods.split(","))
+        if args.cardiac:
+            res["cardiac"] = cardiac_c5(nl, torch, tuple(int(x) for x in args.cardiac.split(",")),
+                                        args.cardiac_methods.split(","), args.cardiac_steps)
+        print(json.dumps(res))
         return
 
     schedule = load_schedule()
@@ -376,6 +488,11 @@ def main():
     batch = None
     if args.batch > 0:
         batch = batch_c4(nl, torch, args.batch, args.batch_serial_stride, 1)
+    twist = twist_c3(nl, torch, args.twist, args.twist_methods.split(",")) if args.twist > 0 else None
+    cardiac = None
+    if args.cardiac:
+        cardiac = cardiac_c5(nl, torch, tuple(int(x) for x in args.cardiac.split(",")),
+                             args.cardiac_methods.split(","), args.cardiac_steps)
 
     cpu = None
     if not args.no_cpu:
@@ -414,6 +531,8 @@ def main():
                                     if base and base["ok"] and all_ok else None),
         "compare": extra or None,
         "batch": batch,
+        "twist": twist,
+        "cardiac": cardiac,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
