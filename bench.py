@@ -109,7 +109,9 @@ def jv_roofline(nl, torch, reps: int):
         e1.record(ctx.stream)
         e1.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        balg = mesh.n_elems * (16 + 10 * s) + mesh.n_nodes * 9 * s
+        # per element: 16-byte index record, 9 gradient entries, volume and the
+        # one cached tangent coefficient of law M1; per node: u, v read, y written
+        balg = mesh.n_elems * (16 + 11 * s) + mesh.n_nodes * 9 * s
         out["fp32" if s == 4 else "fp64"] = {
             "ms": ms, "bytes": balg, "gbs": balg / ms / 1e6,
             "n_elems": mesh.n_elems, "n_nodes": mesh.n_nodes,
@@ -121,7 +123,7 @@ def jv_roofline(nl, torch, reps: int):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("nle_elem.hip",):
+    for f in ("nle_elem.hip", "nle_kin.hpp"):
         with open(os.path.join(ROOT, "paper_2203_05610_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -420,7 +420,8 @@ nle_status solve(Batch *b, int method, const nle_solver_opts &o, double *u, nle_
     const int chunk = std::max(1, o.check_every);
     std::vector<uint64_t> key = {7, uint64_t(prec), uint64_t(nd), uint64_t(chunk),
                                  uint64_t(uintptr_t(c->ws)), uint64_t(uintptr_t(c->red)),
-                                 uint64_t(uintptr_t(ulin))};
+                                 uint64_t(uintptr_t(ulin)),
+                                 uint64_t(uintptr_t(c->lc_valid ? c->lc64 : nullptr))};
     if (c->gkey != key) {
       drop_graph(c);
       hipError_t eb = hipStreamBeginCapture(c->kstream, hipStreamCaptureModeThreadLocal);

@@ -92,12 +92,34 @@ nle_status residual_norm(Ctx *c, const double *u, double *r, double *rn, bool *i
 nle_status linearize(Ctx *c, const double *u, int prec) {
   const int64_t n = ndof(c);
   NLE_HIP(c, surf_set_linear_pressure(c));
+  c->lc_valid = false;
+  if (!c->mixed) {  // room for the per-element tangent coefficients
+    const int nk = c->mat.kind == NLE_MAT_M1 ? 1 : (c->mat.kind == NLE_MAT_M2 ? 3 : 7);
+    const int64_t need = int64_t(nk) * c->m.n_elems;
+    if (need > c->lc_cap) {
+      drop_graph(c);
+      NLE_HIP(c, hipStreamSynchronize(c->stream));
+      dfree(c, c->lc64);
+      dfree(c, c->lc32);
+      c->lc64 = static_cast<double *>(dalloc(c, size_t(need) * 8));
+      c->lc32 = static_cast<float *>(dalloc(c, size_t(need) * 4));
+      c->lc_cap = (c->lc64 && c->lc32) ? need : 0;
+      if (!c->lc_cap) {
+        dfree(c, c->lc64);
+        dfree(c, c->lc32);
+        c->lc64 = nullptr;
+        c->lc32 = nullptr;
+        return fail(c, NLE_E_OOM, "device allocation failed (linearization cache)");
+      }
+    }
+  }
   if (u != c->ulin64)
     NLE_HIP(c, hipMemcpyAsync(c->ulin64, u, n * 8, hipMemcpyDeviceToDevice, c->stream));
   hipError_t e;
   elem_apply(c, OP_DIAG, NLE_FP64, c->ulin64, nullptr, c->diag64, nullptr, &e);
   if (e != hipSuccess) return fail(c, NLE_E_HIP, std::string("diag: ") + hipGetErrorString(e));
   NLE_HIP(c, vec_recip(c, c->diag64, c->dinv64, n));
+  c->lc_valid = !c->mixed && c->lc64 != nullptr;
   c->lin64 = true;
   c->lin32 = false;
   if (prec == NLE_FP32) {
@@ -194,6 +216,8 @@ void nle_destroy(nle_ctx *ctx) {
   dfree(c, c->dflag);
   dfree(c, c->dir_dofs);
   dfree(c, c->dir_vals);
+  dfree(c, c->lc64);
+  dfree(c, c->lc32);
   for (void *p : c->fib_allocs) dfree(c, p);
   free_surface(c);
   if (c->hpin) (void)hipHostFree(c->hpin);
@@ -223,6 +247,11 @@ nle_status nle_upload_mesh(nle_ctx *ctx, int64_t n_nodes, const double *X, int64
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, NLE_E_HIP, "hipSetDevice failed");
     c->has_mesh = false;
     drop_graph(c);
+    dfree(c, c->lc64);
+    dfree(c, c->lc32);
+    c->lc64 = nullptr;
+    c->lc32 = nullptr;
+    c->lc_cap = 0;
     nle_status s = build_mesh(c, n_nodes, X, n_elems, conn);
     if (s != NLE_OK) return s;
     // per-element and per-face data of the previous mesh no longer apply
@@ -283,7 +312,7 @@ nle_status nle_set_material(nle_ctx *ctx, int32_t kind, const double *p, int32_t
     drop_graph(c);
     c->mat = m;
     c->has_mat = true;
-    c->lin64 = c->lin32 = false;
+    c->lin64 = c->lin32 = c->lc_valid = false;
     return NLE_OK;
   } else if (kind == NLE_MAT_M1) {
     if (np != 2) return fail(c, NLE_E_INVAL, "M1 takes (mu, lambda)");
@@ -316,7 +345,7 @@ nle_status nle_set_material(nle_ctx *ctx, int32_t kind, const double *p, int32_t
     drop_graph(c);
     c->mat = m;
     c->has_mat = true;
-    c->lin64 = c->lin32 = false;
+    c->lin64 = c->lin32 = c->lc_valid = false;
     return NLE_OK;
   } else {
     return fail(c, NLE_E_UNSUPPORTED, "unknown material kind");
@@ -328,7 +357,7 @@ nle_status nle_set_material(nle_ctx *ctx, int32_t kind, const double *p, int32_t
   drop_graph(c);
   c->mat = m;
   c->has_mat = true;
-  c->lin64 = c->lin32 = false;
+  c->lin64 = c->lin32 = c->lc_valid = false;
   return NLE_OK;
 }
 
@@ -363,7 +392,7 @@ nle_status nle_set_dirichlet(nle_ctx *ctx, int64_t n, const int64_t *dofs, const
     const bool changed = mask != c->h_mask;
     c->h_mask = mask;
     if (changed) {
-      c->lin64 = c->lin32 = false;
+      c->lin64 = c->lin32 = c->lc_valid = false;
       return upload_node_masks(c);
     }
     NLE_HIP(c, hipStreamSynchronize(c->stream));
@@ -457,7 +486,7 @@ nle_status nle_set_fibres(nle_ctx *ctx, const double *fib) {
     NLE_HIP(c, hipMemcpyAsync(c->fib64, f64.data(), f64.size() * 8, hipMemcpyHostToDevice, c->stream));
     NLE_HIP(c, hipMemcpyAsync(c->fib32, f32.data(), f32.size() * 4, hipMemcpyHostToDevice, c->stream));
     NLE_HIP(c, hipStreamSynchronize(c->stream));
-    c->lin64 = c->lin32 = false;
+    c->lin64 = c->lin32 = c->lc_valid = false;
     return NLE_OK;
   });
 }
@@ -469,7 +498,7 @@ nle_status nle_set_active_tension(nle_ctx *ctx, double gamma) {
   if (gamma != c->mat.gamma) {
     drop_graph(c);
     c->mat.gamma = gamma;
-    c->lin64 = c->lin32 = false;
+    c->lin64 = c->lin32 = c->lc_valid = false;
   }
   return NLE_OK;
 }
@@ -495,7 +524,7 @@ nle_status nle_set_pressure(nle_ctx *ctx, int64_t nf, const int32_t *tri, double
     nle_status st = check_tri(c, nf, tri, &t);
     if (st != NLE_OK) return st;
     c->surf.p = p;
-    c->lin64 = c->lin32 = false;
+    c->lin64 = c->lin32 = c->lc_valid = false;
     if (t == c->surf.h_ptri) return NLE_OK;
     c->surf.h_ptri = t;
     return build_surface(c);
@@ -516,7 +545,7 @@ nle_status nle_set_robin(nle_ctx *ctx, int64_t nf, const int32_t *tri, double k_
     if (k_perp != c->surf.kperp || k_par != c->surf.kpar) drop_graph(c);
     c->surf.kperp = k_perp;
     c->surf.kpar = k_par;
-    c->lin64 = c->lin32 = false;
+    c->lin64 = c->lin32 = c->lc_valid = false;
     if (t == c->surf.h_rtri) return NLE_OK;
     c->surf.h_rtri = t;
     return build_surface(c);

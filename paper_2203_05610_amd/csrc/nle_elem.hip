@@ -27,6 +27,7 @@ struct ElemArgs {
   const uint4 *lcp;   // per element: 4 slot-local vertex ids, 4 contribution positions (u16)
   const uint16_t *csr_end;
   const uint32_t *nodes;
+  const int32_t *mpos;
   const int32_t *blk_elem;
   const int32_t *blk_node;
   int64_t n_e;
@@ -48,6 +49,11 @@ struct ElemArgs {
   double *ep_red;
   MatParams mp;
   const T *fib;       // law M4: unit fibre per element, [3][n_e]
+  // linearization cache: per-element tangent coefficients at u_lin, [k][n_e]
+  // (written by the diagonal pass, read by the Jacobian action)
+  const T *lcoef;
+  double *lc64;
+  float *lc32;
   const T *fs;        // surface-load contributions per dof (null without surface loads)
   // batched mode (all null for a single problem): instance of each block,
   // per-instance load scale, material (mu, lam, cvol, kappa) and done mask
@@ -61,7 +67,6 @@ template <typename T>
 struct MergeArgs {
   const uint32_t *fx_node;
   const int32_t *fx_ptr;
-  const int32_t *fx_slot;
   int64_t n_sh;
   const T *partial;
   const T *v;
@@ -93,8 +98,12 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
-// Fixed-order workgroup sum; the result is valid in thread 0.
-template <typename T>
+// Threads per workgroup of the element-block kernel: one element per thread
+// at the default block size, so the LDS a block needs carries eight waves.
+constexpr int NTB = 512;
+
+// Fixed-order workgroup sum over NTH threads; the result is valid in thread 0.
+template <int NTH, typename T>
 __device__ __forceinline__ T block_sum(T v, T *sh) {
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -103,7 +112,7 @@ __device__ __forceinline__ T block_sum(T v, T *sh) {
   __syncthreads();
   T r = 0;
   if (threadIdx.x == 0)
-    for (int k = 0; k < NT / 64; ++k) r += sh[k];
+    for (int k = 0; k < NTH / 64; ++k) r += sh[k];
   return r;
 }
 
@@ -274,6 +283,7 @@ struct ElemIn {
   T g[3][3];   // grad N_1..3
   T vol;
   T f[3];      // fibre direction (law M4)
+  uint32_t ge; // renumbered element index
 };
 
 __device__ __forceinline__ int lo16(uint32_t w) { return int(w & 0xFFFFu); }
@@ -294,6 +304,7 @@ __device__ __forceinline__ void load_elem(const ElemArgs<T> &A, uint32_t ge, Ele
       d.g[a][j] = Gk[ge];
     }
   d.vol = A.V[ge];
+  d.ge = ge;
   if (MAT == NLE_MAT_M4) {
 #pragma unroll
     for (int j = 0; j < 3; ++j) d.f[j] = A.fib[size_t(j) * ne + ge];
@@ -301,10 +312,103 @@ __device__ __forceinline__ void load_elem(const ElemArgs<T> &A, uint32_t ge, Ele
 }
 
 // Element force vector (12 values, vertex-major) of one element.
+// Number of cached tangent coefficients per element and law (the others
+// follow from the material constants): M1 cX; M2 a, cT, cX (cF = cM = -2a/3);
+// M4 a, cF (= cM), cFF, cT, cX, h1, h2.
+template <int MAT>
+__host__ __device__ constexpr int n_lcoef() {
+  return MAT == NLE_MAT_M1 ? 1 : (MAT == NLE_MAT_M2 ? 3 : 7);
+}
+
+template <int MAT>
+__device__ __forceinline__ void pack_coef(const Coef &c, double q[7]) {
+  if (MAT == NLE_MAT_M1) {
+    q[0] = c.cX;
+  } else if (MAT == NLE_MAT_M2) {
+    q[0] = c.a;
+    q[1] = c.cT;
+    q[2] = c.cX;
+  } else {
+    q[0] = c.a;
+    q[1] = c.cF;
+    q[2] = c.cFF;
+    q[3] = c.cT;
+    q[4] = c.cX;
+    q[5] = c.h1;
+    q[6] = c.h2;
+  }
+}
+
+template <int MAT, typename T>
+__device__ __forceinline__ Coef unpack_coef(const T *lc, uint32_t ne, uint32_t ge,
+                                            const MatParams &mp) {
+  Coef c;
+  c.pT = 0.0;
+  c.cFF = 0.0;
+  c.h1 = 0.0;
+  c.h2 = 0.0;
+  if (MAT == NLE_MAT_M1) {
+    c.a = mp.mu;
+    c.cF = 0.0;
+    c.cM = 0.0;
+    c.cT = mp.lam;
+    c.cX = double(lc[ge]);
+  } else if (MAT == NLE_MAT_M2) {
+    c.a = double(lc[ge]);
+    c.cT = double(lc[size_t(ne) + ge]);
+    c.cX = double(lc[2 * size_t(ne) + ge]);
+    c.cF = -2.0 / 3.0 * c.a;
+    c.cM = c.cF;
+  } else {
+    c.a = double(lc[ge]);
+    c.cF = double(lc[size_t(ne) + ge]);
+    c.cM = c.cF;
+    c.cFF = double(lc[2 * size_t(ne) + ge]);
+    c.cT = double(lc[3 * size_t(ne) + ge]);
+    c.cX = double(lc[4 * size_t(ne) + ge]);
+    c.h1 = double(lc[5 * size_t(ne) + ge]);
+    c.h2 = double(lc[6 * size_t(ne) + ge]);
+  }
+  return c;
+}
+
+// F = I + H and F^-T = cof(F) / det(F) in the kernel's precision (enough for
+// the tangent; J - 1 and ln J are not needed once the coefficients are cached).
+template <typename T>
+__device__ __forceinline__ void kinematics_light(const T H[3][3], Kin<T> &k) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) k.F[i][j] = H[i][j] + (i == j ? T(1) : T(0));
+  const T(&F)[3][3] = k.F;
+  T c[3][3];
+  c[0][0] = F[1][1] * F[2][2] - F[1][2] * F[2][1];
+  c[0][1] = F[1][2] * F[2][0] - F[1][0] * F[2][2];
+  c[0][2] = F[1][0] * F[2][1] - F[1][1] * F[2][0];
+  c[1][0] = F[0][2] * F[2][1] - F[0][1] * F[2][2];
+  c[1][1] = F[0][0] * F[2][2] - F[0][2] * F[2][0];
+  c[1][2] = F[0][1] * F[2][0] - F[0][0] * F[2][1];
+  c[2][0] = F[0][1] * F[1][2] - F[0][2] * F[1][1];
+  c[2][1] = F[0][2] * F[1][0] - F[0][0] * F[1][2];
+  c[2][2] = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+  const T J = F[0][0] * c[0][0] + F[0][1] * c[0][1] + F[0][2] * c[0][2];
+  T ij;
+  if (sizeof(T) == 8)
+    ij = T(1) / J;
+  else
+    ij = T(__builtin_amdgcn_rcpf(float(J)));
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) k.FiT[i][j] = c[i][j] * ij;
+  k.bad = false;
+}
+
 template <typename T, int OP, int MAT>
 __device__ __forceinline__ void element_forces(const ElemIn<T> &d, const T *uS, const T *vS,
                                                int NL, const MatParams &mp, T out[4][3],
-                                               bool &bad, double &eacc) {
+                                               bool &bad, double &eacc, const ElemArgs<T> &A,
+                                               uint32_t ge) {
   const int la[4] = {lo16(d.lcp.x), hi16(d.lcp.x), lo16(d.lcp.y), hi16(d.lcp.y)};
   T g[4][3];
 #pragma unroll
@@ -327,22 +431,46 @@ __device__ __forceinline__ void element_forces(const ElemIn<T> &d, const T *uS, 
       for (int j = 0; j < 3; ++j) H[i][j] += ua * g[a][j];
     }
   Kin<T> k;
-  kinematics(H, k);
-  bad |= k.bad;
   const double V = double(d.vol);
-  FibreKin fk;
-  if (MAT == NLE_MAT_M4) fk = fibre_kinematics(H, d.f);
-  if (OP == OP_ENERGY) {
-    eacc += V * energy_density<MAT>(k, H, fk, mp);
-    return;
-  }
-  const Coef cf = coefficients<MAT>(k, H, fk, mp);
+  Coef cf;
   T Ff[3], f[3];
-  if (MAT == NLE_MAT_M4) {
+  if (OP == OP_JV) {
+    // Jacobian action from the linearization cache (always present: the
+    // diagonal pass of the linearization writes it)
+    kinematics_light(H, k);
+    cf = unpack_coef<MAT>(A.lcoef, uint32_t(A.n_e), ge, mp);
+    if (MAT == NLE_MAT_M4) {
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      Ff[i] = T(fk.Ff[i]);
-      f[i] = d.f[i];
+      for (int i = 0; i < 3; ++i) {
+        f[i] = d.f[i];
+        Ff[i] = f[i] + H[i][0] * d.f[0] + H[i][1] * d.f[1] + H[i][2] * d.f[2];
+      }
+    }
+  } else {
+    kinematics(H, k);
+    bad |= k.bad;
+    FibreKin fk;
+    if (MAT == NLE_MAT_M4) fk = fibre_kinematics(H, d.f);
+    if (OP == OP_ENERGY) {
+      eacc += V * energy_density<MAT>(k, H, fk, mp);
+      return;
+    }
+    cf = coefficients<MAT>(k, H, fk, mp);
+    if (OP == OP_DIAG && A.lc64) {
+      double q[7];
+      pack_coef<MAT>(cf, q);
+#pragma unroll
+      for (int t = 0; t < n_lcoef<MAT>(); ++t) {
+        A.lc64[size_t(t) * size_t(A.n_e) + ge] = q[t];
+        A.lc32[size_t(t) * size_t(A.n_e) + ge] = float(q[t]);
+      }
+    }
+    if (MAT == NLE_MAT_M4) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        Ff[i] = T(fk.Ff[i]);
+        f[i] = d.f[i];
+      }
     }
   }
   if (OP == OP_RES) {
@@ -448,7 +576,7 @@ __device__ __forceinline__ void element_forces(const ElemIn<T> &d, const T *uS, 
 }
 
 template <typename T, int OP, int MAT>
-__global__ __launch_bounds__(NT) void k_elem_block(ElemArgs<T> A) {
+__global__ __launch_bounds__(NTB) void k_elem_block(ElemArgs<T> A) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T *lds = reinterpret_cast<T *>(lds_raw);
   // Reduction partials are stored at the block's index b (consumers sum the
@@ -474,17 +602,27 @@ __global__ __launch_bounds__(NT) void k_elem_block(ElemArgs<T> A) {
   T *uS = lds;                 // [3][NL]
   T *vS = lds + 3 * NL;        // [3][NL]      (Jv only)
   T *cS = lds + 6 * NL;        // [3][4 BE]    contributions in slot-sorted order
-  double *rs = reinterpret_cast<double *>(lds);  // reduction scratch (reused)
+  double *rs = reinterpret_cast<double *>(lds + 6 * NL + 12 * A.be_max);  // reduction scratch
 
   // The inputs of this thread's first two elements are requested before the
   // node gather so all of these loads are in flight together.
   ElemIn<T> ea, eb;
   if (tid < ne) load_elem<MAT>(A, uint32_t(e0 + tid), ea);
-  if (tid + NT < ne) load_elem<MAT>(A, uint32_t(e0 + tid + NT), eb);
+  if (tid + NTB < ne) load_elem<MAT>(A, uint32_t(e0 + tid + NTB), eb);
 
-  // Phase 1: gather nodal state (and direction) of the block.
-  for (int l = tid; l < nl; l += NT) {
-    const uint32_t w = A.nodes[p0 + l];
+  // Phase 1: gather nodal state (and direction) of the block.  The first slot
+  // of each thread also has its phase-3 data (word, range, partial position)
+  // requested here and kept in registers.
+  uint32_t w0 = 0;
+  int beg0 = 0, end0 = 0, mp0 = -1;
+  if (tid < nl) {
+    w0 = A.nodes[p0 + tid];
+    end0 = A.csr_end[p0 + tid];
+    beg0 = tid == 0 ? 0 : int(A.csr_end[p0 + tid - 1]);
+    if (OP != OP_ENERGY && (w0 & 0x80000000u)) mp0 = A.mpos[p0 + tid];
+  }
+  for (int l = tid; l < nl; l += NTB) {
+    const uint32_t w = l == tid ? w0 : A.nodes[p0 + l];
     const int64_t g3 = 3 * int64_t(w & NODE_MASK);
     const uint32_t mk = (w >> 28) & 7u;
 #pragma unroll
@@ -500,7 +638,7 @@ __global__ __launch_bounds__(NT) void k_elem_block(ElemArgs<T> A) {
   double eacc = 0.0;
   auto run = [&](const ElemIn<T> &d) {
     T out[4][3];
-    element_forces<T, OP, MAT>(d, uS, vS, NL, mp, out, bad, eacc);
+    element_forces<T, OP, MAT>(d, uS, vS, NL, mp, out, bad, eacc, A, d.ge);
     if (OP != OP_ENERGY) {
       const int cp[4] = {lo16(d.lcp.z), hi16(d.lcp.z), lo16(d.lcp.w), hi16(d.lcp.w)};
 #pragma unroll
@@ -510,15 +648,15 @@ __global__ __launch_bounds__(NT) void k_elem_block(ElemArgs<T> A) {
     }
   };
   if (tid < ne) run(ea);
-  if (tid + NT < ne) run(eb);
-  for (int e = tid + 2 * NT; e < ne; e += NT) {
+  if (tid + NTB < ne) run(eb);
+  for (int e = tid + 2 * NTB; e < ne; e += NTB) {
     load_elem<MAT>(A, uint32_t(e0 + e), ea);
     run(ea);
   }
   if (bad && A.flag) A.flag[inst] = 1;
 
   if (OP == OP_ENERGY) {
-    const double s = block_sum(eacc, rs);
+    const double s = block_sum<NTB>(eacc, rs);
     if (tid == 0) A.red[b] = s;
     return;
   }
@@ -527,17 +665,19 @@ __global__ __launch_bounds__(NT) void k_elem_block(ElemArgs<T> A) {
   // Phase 3: node sums over contiguous ranges, in (element, vertex) order.
   double nrm = 0.0;
   const T epc = A.ep_coef ? T(A.ep_coef[0]) : T(0);
-  for (int l = tid; l < nl; l += NT) {
-    const int beg = l == 0 ? 0 : int(A.csr_end[p0 + l - 1]);
-    const int end = A.csr_end[p0 + l];
+  for (int l = tid; l < nl; l += NTB) {
+    const bool first = l == tid;
+    const int beg = first ? beg0 : int(A.csr_end[p0 + l - 1]);
+    const int end = first ? end0 : int(A.csr_end[p0 + l]);
     T acc[3] = {T(0), T(0), T(0)};
     for (int q = beg; q < end; ++q) {
 #pragma unroll
       for (int i = 0; i < 3; ++i) acc[i] += cS[i * C4 + q];
     }
-    const uint32_t w = A.nodes[p0 + l];
+    const uint32_t w = first ? w0 : A.nodes[p0 + l];
     if (w & 0x80000000u) {
-      T *pp = A.partial + 3 * int64_t(p0 + l);
+      const int mp = first ? mp0 : A.mpos[p0 + l];
+      T *pp = A.partial + 3 * int64_t(mp);
       pp[0] = acc[0];
       pp[1] = acc[1];
       pp[2] = acc[2];
@@ -547,7 +687,7 @@ __global__ __launch_bounds__(NT) void k_elem_block(ElemArgs<T> A) {
     }
   }
   if (OP == OP_RES || (OP == OP_JV && A.ep_red)) {
-    const double s = block_sum(nrm, rs);
+    const double s = block_sum<NTB>(nrm, rs);
     if (tid == 0) (OP == OP_RES ? A.red : A.ep_red)[b] = s;
   }
 }
@@ -568,18 +708,16 @@ __global__ __launch_bounds__(NT) void k_elem_merge(MergeArgs<T> A) {
     const int q0 = A.fx_ptr[k], q1 = A.fx_ptr[k + 1];
     // slots in groups of four: the four gathers are issued before the sums,
     // which are still taken in slot order
+    // the node's partials are contiguous (block order); four loads in flight
     for (int q = q0; q < q1; q += 4) {
-      int sl[4];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) sl[t] = q + t < q1 ? A.fx_slot[q + t] : -1;
       T pv[4][3];
 #pragma unroll
       for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int i = 0; i < 3; ++i) pv[t][i] = sl[t] >= 0 ? A.partial[3 * int64_t(sl[t]) + i] : T(0);
+        for (int i = 0; i < 3; ++i) pv[t][i] = q + t < q1 ? A.partial[3 * int64_t(q + t) + i] : T(0);
 #pragma unroll
       for (int t = 0; t < 4; ++t)
-        if (sl[t] >= 0) {
+        if (q + t < q1) {
           acc[0] += pv[t][0];
           acc[1] += pv[t][1];
           acc[2] += pv[t][2];
@@ -590,9 +728,16 @@ __global__ __launch_bounds__(NT) void k_elem_merge(MergeArgs<T> A) {
                          A.ep_w, A.ep_coef ? T(A.ep_coef[0]) : T(0), A.fs, A.nomask);
   }
   if (OP == OP_RES || (OP == OP_JV && A.ep_red)) {
-    const double s = block_sum(nrm, rs);
+    const double s = block_sum<NT>(nrm, rs);
     if (threadIdx.x == 0) (OP == OP_RES ? A.red : A.ep_red)[blockIdx.x] = s;
   }
+}
+
+template <typename T, int OP, int MAT>
+void launch_block(Ctx *c, ElemArgs<T> &A, size_t lds) {
+  A.per_xcd = c->xcd_remap ? (A.nblk + 7) / 8 : 0;
+  const int grid = A.per_xcd > 0 ? 8 * A.per_xcd : A.nblk;
+  hipLaunchKernelGGL((k_elem_block<T, OP, MAT>), dim3(grid), dim3(NTB), lds, c->stream, A);
 }
 
 template <typename T>
@@ -612,6 +757,7 @@ int launch(Ctx *c, int op, const T *G, const T *V, const T *u, const T *v, T *ou
   A.lcp = M.lcp;
   A.csr_end = M.csr_end;
   A.nodes = M.nodes;
+  A.mpos = M.mpos;
   A.blk_elem = M.blk_elem;
   A.blk_node = M.blk_node;
   A.n_e = M.n_elems;
@@ -636,21 +782,31 @@ int launch(Ctx *c, int op, const T *G, const T *V, const T *u, const T *v, T *ou
   A.fib = static_cast<const T *>(sizeof(T) == 8 ? static_cast<const void *>(c->fib64)
                                                 : static_cast<const void *>(c->fib32));
   A.fs = op == OP_ENERGY ? nullptr : static_cast<T *>(fs);
+  A.lcoef = nullptr;
+  A.lc64 = nullptr;
+  A.lc32 = nullptr;
+  if (op == OP_JV)
+    A.lcoef = static_cast<const T *>(sizeof(T) == 8 ? static_cast<const void *>(c->lc64)
+                                                    : static_cast<const void *>(c->lc32));
+  if (op == OP_DIAG && c->lc64) {
+    A.lc64 = c->lc64;
+    A.lc32 = c->lc32;
+  }
   A.blk_inst = M.blk_inst;
   A.inst_s = c->inst_s;
   A.inst_mat = c->inst_mat;
   A.inst_done = c->inst_done;
-  const int grid = A.per_xcd > 0 ? 8 * A.per_xcd : M.nblk;
   size_t lds = size_t(6 * M.nl_max + 12 * M.be_max) * sizeof(T);
-  lds = std::max(lds, size_t(NT / 64) * sizeof(double));
+  lds = (lds + 7) & ~size_t(7);
+  lds += size_t(NTB / 64) * sizeof(double);  // reduction scratch after the arrays
   const int kind = c->mat.kind;
-#define NLE_LAUNCH_BLOCK(OPV)                                                                 \
-  if (kind == NLE_MAT_M2)                                                                     \
-    hipLaunchKernelGGL((k_elem_block<T, OPV, NLE_MAT_M2>), dim3(grid), dim3(NT), lds, c->stream, A); \
-  else if (kind == NLE_MAT_M4)                                                                \
-    hipLaunchKernelGGL((k_elem_block<T, OPV, NLE_MAT_M4>), dim3(grid), dim3(NT), lds, c->stream, A); \
-  else                                                                                        \
-    hipLaunchKernelGGL((k_elem_block<T, OPV, NLE_MAT_M1>), dim3(grid), dim3(NT), lds, c->stream, A);
+#define NLE_LAUNCH_BLOCK(OPV)                                             \
+  if (kind == NLE_MAT_M2)                                                 \
+    launch_block<T, OPV, NLE_MAT_M2>(c, A, lds);                          \
+  else if (kind == NLE_MAT_M4)                                            \
+    launch_block<T, OPV, NLE_MAT_M4>(c, A, lds);                          \
+  else                                                                    \
+    launch_block<T, OPV, NLE_MAT_M1>(c, A, lds);
   switch (op) {
     case OP_RES:
       NLE_LAUNCH_BLOCK(OP_RES);
@@ -674,7 +830,6 @@ int launch(Ctx *c, int op, const T *G, const T *V, const T *u, const T *v, T *ou
     MergeArgs<T> B;
     B.fx_node = M.fx_node;
     B.fx_ptr = M.fx_ptr;
-    B.fx_slot = M.fx_slot;
     B.n_sh = M.n_shared;
     B.partial = static_cast<const T *>(c->partial);
     B.v = v;

@@ -48,7 +48,8 @@ struct Mesh {
   std::vector<int64_t> h_inst_node, h_inst_elem;   // [n_inst+1] offsets
   std::vector<int32_t> h_inst_blk, h_inst_mwg;     // [n_inst+1] block / merge-WG offsets
   uint32_t *fx_node = nullptr;                  // [n_shared] id | mask<<28
-  int32_t *fx_ptr = nullptr, *fx_slot = nullptr;     // merge CSR over slots
+  int32_t *fx_ptr = nullptr;  // [n_shared+1] ranges of each shared node's partials
+  int32_t *mpos = nullptr;    // [n_slots] partial position of a shared slot
   // host mirrors needed later
   std::vector<uint32_t> h_nodes, h_fx_node;     // ids and shared bit, no mask
   std::vector<int32_t> h_conn;                  // user connectivity (user order)
@@ -112,6 +113,14 @@ struct Ctx {
   std::vector<double> h_ftrac, h_fbody;
   double *fext = nullptr;
   double load_scale = 1.0;
+
+  // linearization cache: per-element tangent coefficients at u_lin ([k][n_e],
+  // k < 7), written by the diagonal pass of nle_linearize, read by the
+  // Jacobian action of P1 meshes; lc_valid while they match u_lin
+  double *lc64 = nullptr;
+  float *lc32 = nullptr;
+  int64_t lc_cap = 0;   // elements x coefficients allocated
+  bool lc_valid = false;
 
   // law M4: unit fibre per element, [3][n_elems] in the renumbered order
   double *fib64 = nullptr;

@@ -212,11 +212,17 @@ nle_status build_mesh(Ctx *c, int64_t nn, const double *X, int64_t ne, const int
   }
   for (int64_t k = 0; k < n_sh; ++k) fx_ptr[k + 1] += fx_ptr[k];
   fx_slot.resize(fx_ptr[n_sh]);
+  // mpos[p]: where a shared slot writes its partial sum, so that each shared
+  // node's partials are contiguous (in block order) for the merge
+  std::vector<int32_t> mpos(n_slots, -1);
   {
     std::vector<int32_t> fp(fx_ptr.begin(), fx_ptr.end() - 1);
     for (int64_t p = 0; p < n_slots; ++p) {  // slots are in block order
       int32_t f = fx_id[nodes[p] & NODE_MASK];
-      if (f >= 0) fx_slot[fp[f]++] = int32_t(p);
+      if (f >= 0) {
+        mpos[p] = fp[f];
+        fx_slot[fp[f]++] = int32_t(p);
+      }
     }
   }
   for (int64_t g = 0; g < nn; ++g)
@@ -224,7 +230,8 @@ nle_status build_mesh(Ctx *c, int64_t nn, const double *X, int64_t ne, const int
       return fail(c, NLE_E_BADMESH, "node " + std::to_string(g) + " belongs to no element");
 
   // ---- LDS budget ---------------------------------------------------------------
-  const size_t lds64 = size_t(6 * nl_max + 12 * be_max) * 8;  // see the element kernel
+  // see the element kernel: nodal state, contributions, reduction scratch
+  const size_t lds64 = size_t(6 * nl_max + 12 * be_max) * 8 + 512 / 64 * 8;
   if (lds64 > c->lds_limit)
     return fail(c, NLE_E_UNSUPPORTED,
                 "element block needs " + std::to_string(lds64) + " B of LDS (limit " +
@@ -262,6 +269,7 @@ nle_status build_mesh(Ctx *c, int64_t nn, const double *X, int64_t ne, const int
   M.lcp = reinterpret_cast<uint4 *>(upload(c, lcp, &herr));
   M.csr_end = upload(c, csr_end, &herr);
   M.nodes = upload(c, nodes, &herr);
+  M.mpos = upload(c, mpos, &herr);
   M.blk_elem = upload(c, blk_elem, &herr);
   M.blk_node = upload(c, blk_node, &herr);
   M.n_inst = n_inst;
@@ -277,7 +285,6 @@ nle_status build_mesh(Ctx *c, int64_t nn, const double *X, int64_t ne, const int
   if (n_sh > 0) {
     M.fx_node = upload(c, fx_node, &herr);
     M.fx_ptr = upload(c, fx_ptr, &herr);
-    M.fx_slot = upload(c, fx_slot, &herr);
   }
   void *part = dalloc(c, size_t(n_slots) * 3 * sizeof(double));
   if (!part) herr = hipErrorOutOfMemory;
@@ -320,7 +327,7 @@ nle_status build_mesh(Ctx *c, int64_t nn, const double *X, int64_t ne, const int
   c->h_ftrac.assign(3 * nn, 0.0);
   c->h_fbody.assign(3 * nn, 0.0);
   c->n_dir = 0;
-  c->lin64 = c->lin32 = false;
+  c->lin64 = c->lin32 = c->lc_valid = false;
   c->load_scale = 1.0;
   NLE_HIP(c, hipStreamSynchronize(c->stream));
   c->mixed = false;

@@ -563,7 +563,7 @@ nle_status build_mixed_mesh(Ctx *c, int64_t nu, const double *X, int64_t ne, con
   c->h_ftrac.assign(3 * nu, 0.0);
   c->h_fbody.assign(3 * nu, 0.0);
   c->n_dir = 0;
-  c->lin64 = c->lin32 = false;
+  c->lin64 = c->lin32 = c->lc_valid = false;
   c->load_scale = 1.0;
   NLE_HIP(c, hipStreamSynchronize(c->stream));
   c->has_mesh = true;

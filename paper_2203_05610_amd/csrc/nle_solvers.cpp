@@ -210,7 +210,8 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
                                    uint64_t(uintptr_t(dinv)), uint64_t(uintptr_t(ulin)),
                                    uint64_t(uintptr_t(c->red)), uint64_t(uintptr_t(c->m.G32)),
                                    uint64_t(uintptr_t(c->m.nodes)), uint64_t(c->mat.kind),
-                                   uint64_t(uintptr_t(c->mx.G32)), uint64_t(uintptr_t(c->mx.cu))};
+                                   uint64_t(uintptr_t(c->mx.G32)), uint64_t(uintptr_t(c->mx.cu)),
+                                   uint64_t(uintptr_t(c->lc_valid ? c->lc64 : nullptr))};
       st = run_chunks(c, key, check, o.max_it, flag, iter);
     } else {
       MinresArgs a;
@@ -250,7 +251,8 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
                                    uint64_t(uintptr_t(dinv)), uint64_t(uintptr_t(ulin)),
                                    uint64_t(uintptr_t(c->red)), uint64_t(uintptr_t(c->m.G32)),
                                    uint64_t(uintptr_t(c->m.nodes)), uint64_t(c->mat.kind),
-                                   uint64_t(uintptr_t(c->mx.G32)), uint64_t(uintptr_t(c->mx.cu))};
+                                   uint64_t(uintptr_t(c->mx.G32)), uint64_t(uintptr_t(c->mx.cu)),
+                                   uint64_t(uintptr_t(c->lc_valid ? c->lc64 : nullptr))};
       st = run_chunks(c, key, check, o.max_it, flag, iter);
     }
     if (st != NLE_OK) return st;

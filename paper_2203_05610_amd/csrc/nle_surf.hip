@@ -305,7 +305,7 @@ nle_status build_surface(Ctx *c) {
   NLE_HIP(c, hipMemsetAsync(S.fs32, 0, size_t(3 * nn) * 4, c->stream));
   NLE_HIP(c, hipMemsetAsync(S.plin, 0, 8, c->stream));
   S.h_tri = tri;
-  c->lin64 = c->lin32 = false;
+  c->lin64 = c->lin32 = c->lc_valid = false;
   return upload_surface_masks(c);
 }
 
