@@ -54,11 +54,14 @@ def load_schedule():
     return fields.cook_load_schedule(16.0)
 
 
+PC = {"pc": "jacobi"}  # preconditioner of every Cook solve (--pc)
+
+
 def run_solve(ctx, u, method, schedule):
     from paper_2203_05610_amd import problems
 
     solver, prec, kw = METHODS[method]
-    opts = problems.make_opts(solver, prec, **dict(kw))
+    opts = problems.make_opts(solver, prec, pc=PC["pc"], **dict(kw))
     u.zero_()
     reps = problems.solve_schedule(ctx, u, solver, opts, schedule)
     return problems.schedule_ok(reps, schedule), reps
@@ -362,6 +365,8 @@ def main():
     ap.add_argument("--baseline", default="nk_fp64", choices=sorted(METHODS))
     ap.add_argument("--compare", default="", help="comma-separated extra methods, run once each")
     ap.add_argument("--jv-reps", type=int, default=200)
+    ap.add_argument("--pc", default="jacobi", choices=["jacobi", "bjacobi3"],
+                    help="preconditioner of the Cook solves (point or nodal 3x3 block Jacobi)")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-baseline", action="store_true")
@@ -382,9 +387,10 @@ def main():
                     help="only the Jv roofline phase (plus a 256 MB copy kernel used to "
                          "calibrate HBM byte counters); for profiling runs")
     args = ap.parse_args()
+    PC["pc"] = args.pc
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "path is a design in DESIGN.md, not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); sharding a "
+              "solve over several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -521,7 +527,7 @@ def main():
             "method": args.method,
             "precision": "FP32 inner (tangent, Jacobi, Krylov, L-BFGS vectors), FP64 residual/state"
             if METHODS[args.method][1] == "mixed" else "FP64",
-            "preconditioner": "Jacobi",
+            "preconditioner": {"jacobi": "Jacobi", "bjacobi3": "nodal 3x3 block Jacobi"}[PC["pc"]],
             "krylov": METHODS[args.method][2].get("ksp", "cg"),
             "parallelism": "1 GPU",
         },

@@ -87,6 +87,9 @@ typedef int32_t nle_status;
 
 #define NLE_PC_NONE 0
 #define NLE_PC_JACOBI 1 /* point Jacobi: inverse of the tangent diagonal     */
+#define NLE_PC_BJACOBI3 2 /* nodal block Jacobi: inverse of each node's 3x3
+                             diagonal block of the tangent (P1 meshes; the
+                             bs = 3 point-block Jacobi of a PETSc setup)  */
 
 #define NLE_H0_PREONLY 0 /* BFGS-preonly: H0 = one preconditioner application */
 #define NLE_H0_KSP 1     /* inexact BFGS: H0 = Krylov solve on J(u0)          */
@@ -111,7 +114,7 @@ typedef struct {
   int32_t precision;  /* NLE_PREC_FP64 / NLE_PREC_MIXED                      */
   int32_t ksp_type;   /* NLE_KSP_GMRES / NLE_KSP_CG / NLE_KSP_MINRES          */
   int32_t orth;       /* GMRES orthogonalisation                              */
-  int32_t pc;         /* NLE_PC_JACOBI / NLE_PC_NONE                          */
+  int32_t pc;         /* NLE_PC_JACOBI / NLE_PC_BJACOBI3 / NLE_PC_NONE        */
   int32_t restart;    /* GMRES restart length; <= 0 means ksp_max_it          */
   int32_t ksp_max_it; /* Krylov iteration limit per linear solve              */
   int32_t snes_max_it;/* nonlinear iteration limit                            */
@@ -253,6 +256,20 @@ nle_status nle_jv(nle_ctx *ctx, const void *v_dev, void *y_dev, int32_t prec);
 /* Jacobi data of the current linearization: d = diag J (1 on Dirichlet
  * dofs), double, device. */
 nle_status nle_diag(nle_ctx *ctx, double *d_dev);
+/* Nodal diagonal blocks of the current linearization (P1 meshes): b[n_nodes]
+ * [6] = (K_xx, K_yy, K_zz, K_xy, K_yz, K_xz) of the 3x3 block of node k,
+ * double, device.  The blocks are symmetric: they hold the tangent of the
+ * strain energy and of the Robin springs; a follower pressure adds only a
+ * skew-symmetric part to a node's own block, which is left out.  Dirichlet
+ * dofs have identity rows and columns.  NLE_E_UNSUPPORTED on a mixed mesh,
+ * NLE_E_STATE before nle_linearize. */
+nle_status nle_block_diag(nle_ctx *ctx, double *b_dev);
+/* y = M^-1 x for the preconditioner pc of the current linearization:
+ * NLE_PC_NONE (copy), NLE_PC_JACOBI (y_i = x_i / J_ii) or NLE_PC_BJACOBI3
+ * (per node, the inverse of its block from nle_block_diag).  x and y are
+ * device vectors of the unknown length, double for NLE_FP64 and float for
+ * NLE_FP32 (which needs a linearization in NLE_FP32); they may not overlap. */
+nle_status nle_pc_apply(nle_ctx *ctx, int32_t pc, int32_t prec, const void *x_dev, void *y_dev);
 /* Potential Pi(u) = sum_e V_e Psi(F_e) - s f_ext . u + u.R u / 2 with R
  * the spring matrix (synchronises).  NLE_E_UNSUPPORTED with a follower
  * pressure set. */

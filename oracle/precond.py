@@ -1,0 +1,70 @@
+"""Jacobi-type preconditioners of the assembled tangent (FP64).
+
+Test infrastructure: only the tests, the smoke check and the CPU baseline
+timing use this package.
+
+The Krylov solvers of the paper are preconditioned (Sec. 3 and App. A, where
+the nonlinear solvers' linear systems run through PETSc with a
+preconditioner and block size 3).  Two diagonal preconditioners are defined
+here from the assembled tangent K of `fem.Problem.stiffness`:
+
+* point Jacobi: M = diag(K);
+* nodal block Jacobi (point-block Jacobi with block size 3): M is block
+  diagonal with, for node k, the 3x3 block K[3k:3k+3, 3k:3k+3].
+
+The strain-energy and Robin-spring parts of a node's own block are
+symmetric.  A follower pressure adds a skew-symmetric part only: the load at
+vertex a of a face is p/6 times (x_b - x_a) x (x_c - x_a), whose derivative
+with respect to x_a is the cross-product map d -> d x (x_b - x_c).  The block
+preconditioner takes the symmetric part of each block, which is then the
+strain-energy and spring part.  Dirichlet dofs have identity rows and
+columns in K, hence in the blocks.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+
+def node_blocks(K, n_nodes: int) -> np.ndarray:
+    """Symmetric parts of the 3x3 diagonal blocks of K, shape (n_nodes, 3, 3)."""
+    K = K.tocsr()
+    B = np.empty((n_nodes, 3, 3))
+    for k in range(n_nodes):
+        blk = K[3 * k:3 * k + 3, 3 * k:3 * k + 3].toarray()
+        B[k] = 0.5 * (blk + blk.T)
+    return B
+
+
+def block_jacobi_apply(blocks: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """z with blocks[k] z_k = x_k for every node k (z, x node-interleaved)."""
+    xk = np.asarray(x, dtype=np.float64).reshape(-1, 3)
+    return np.linalg.solve(blocks, xk[:, :, None])[:, :, 0].reshape(-1)
+
+
+def point_jacobi_apply(K, x: np.ndarray) -> np.ndarray:
+    """z = x / diag(K)."""
+    return np.asarray(x, dtype=np.float64) / K.diagonal()
+
+
+def pcg(K, b: np.ndarray, apply_minv, rtol: float = 1e-10, max_it: int = 10000):
+    """Textbook preconditioned CG from x = 0 (Hestenes-Stiefel form); returns
+    (x, iterations).  Stops when ||b - K x|| <= rtol ||b||."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    z = apply_minv(r)
+    p = z.copy()
+    rz = r @ z
+    nb = np.linalg.norm(b)
+    for it in range(max_it):
+        if np.linalg.norm(r) <= rtol * nb:
+            return x, it
+        q = K @ p
+        alpha = rz / (p @ q)
+        x += alpha * p
+        r -= alpha * q
+        z = apply_minv(r)
+        rz_new = r @ z
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return x, max_it

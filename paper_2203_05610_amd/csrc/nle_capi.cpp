@@ -119,6 +119,7 @@ nle_status linearize(Ctx *c, const double *u, int prec) {
   elem_apply(c, OP_DIAG, NLE_FP64, c->ulin64, nullptr, c->diag64, nullptr, &e);
   if (e != hipSuccess) return fail(c, NLE_E_HIP, std::string("diag: ") + hipGetErrorString(e));
   NLE_HIP(c, vec_recip(c, c->diag64, c->dinv64, n));
+  c->blk_valid = false;
   c->lc_valid = !c->mixed && c->lc64 != nullptr;
   c->lin64 = true;
   c->lin32 = false;
@@ -127,6 +128,38 @@ nle_status linearize(Ctx *c, const double *u, int prec) {
     NLE_HIP(c, vec_cast_scale(c, NLE_FP64, c->dinv64, NLE_FP32, c->dinv32, 1.0, n));
     c->lin32 = true;
   }
+  return NLE_OK;
+}
+
+// Nodal 3x3 diagonal blocks of the tangent at the current linearization and
+// their inverses (binv64 / binv32), computed once per linearization.
+nle_status ensure_block(Ctx *c) {
+  if (c->mixed) return fail(c, NLE_E_UNSUPPORTED, "nodal block Jacobi needs a P1 mesh");
+  if (!c->lin64) return fail(c, NLE_E_STATE, "not linearized");
+  if (c->blk_valid) return NLE_OK;
+  const int64_t nn = c->m.n_nodes;
+  if (!c->odiag64) {
+    c->odiag64 = static_cast<double *>(dalloc(c, size_t(3 * nn) * 8));
+    c->binv64 = static_cast<double *>(dalloc(c, size_t(6 * nn) * 8));
+    c->binv32 = static_cast<float *>(dalloc(c, size_t(6 * nn) * 4));
+    for (void *p : {(void *)c->odiag64, (void *)c->binv64, (void *)c->binv32})
+      if (p) c->mesh_allocs.push_back(p);
+    if (!c->odiag64 || !c->binv64 || !c->binv32) {
+      for (void *p : {(void *)c->odiag64, (void *)c->binv64, (void *)c->binv32}) {
+        if (!p) continue;
+        dfree(c, p);
+        c->mesh_allocs.erase(std::find(c->mesh_allocs.begin(), c->mesh_allocs.end(), p));
+      }
+      c->odiag64 = c->binv64 = nullptr;
+      c->binv32 = nullptr;
+      return fail(c, NLE_E_OOM, "device allocation failed (block preconditioner)");
+    }
+  }
+  hipError_t e;
+  elem_apply(c, OP_ODIAG, NLE_FP64, c->ulin64, nullptr, c->odiag64, nullptr, &e);
+  if (e != hipSuccess) return fail(c, NLE_E_HIP, std::string("block diag: ") + hipGetErrorString(e));
+  NLE_HIP(c, block_inverse(c, nn));
+  c->blk_valid = true;
   return NLE_OK;
 }
 
@@ -611,6 +644,51 @@ nle_status nle_diag(nle_ctx *ctx, double *d) {
   if (!d) return fail(c, NLE_E_INVAL, "null vector");
   if (!c->lin64) return fail(c, NLE_E_STATE, "nle_diag needs nle_linearize first");
   NLE_HIP(c, hipMemcpyAsync(d, c->diag64, ndof(c) * 8, hipMemcpyDeviceToDevice, c->stream));
+  return NLE_OK;
+}
+
+nle_status nle_block_diag(nle_ctx *ctx, double *b) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  nle_status s = need_mesh(c);
+  if (s != NLE_OK) return s;
+  if (!b) return fail(c, NLE_E_INVAL, "null vector");
+  if (!c->lin64) return fail(c, NLE_E_STATE, "nle_block_diag needs nle_linearize first");
+  s = ensure_block(c);
+  if (s != NLE_OK) return s;
+  const size_t nn = size_t(c->m.n_nodes);
+  NLE_HIP(c, hipMemcpy2DAsync(b, 48, c->diag64, 24, 24, nn, hipMemcpyDeviceToDevice, c->stream));
+  NLE_HIP(c, hipMemcpy2DAsync(b + 3, 48, c->odiag64, 24, 24, nn, hipMemcpyDeviceToDevice,
+                              c->stream));
+  return NLE_OK;
+}
+
+nle_status nle_pc_apply(nle_ctx *ctx, int32_t pc, int32_t prec, const void *x, void *y) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  nle_status s = need_mesh(c);
+  if (s != NLE_OK) return s;
+  if (!x || !y) return fail(c, NLE_E_INVAL, "null vector");
+  if (prec != NLE_FP64 && prec != NLE_FP32) return fail(c, NLE_E_INVAL, "bad precision");
+  if (pc != NLE_PC_NONE && pc != NLE_PC_JACOBI && pc != NLE_PC_BJACOBI3)
+    return fail(c, NLE_E_INVAL, "bad pc");
+  if (!(prec == NLE_FP32 ? c->lin32 : c->lin64))
+    return fail(c, NLE_E_STATE, "nle_pc_apply needs nle_linearize at this precision first");
+  const int64_t n = ndof(c);
+  if (pc == NLE_PC_NONE) {
+    NLE_HIP(c, hipMemcpyAsync(y, x, size_t(n) * (prec == NLE_FP32 ? 4 : 8),
+                              hipMemcpyDeviceToDevice, c->stream));
+    return NLE_OK;
+  }
+  const void *d;
+  int pcb = 1;
+  if (pc == NLE_PC_BJACOBI3) {
+    s = ensure_block(c);
+    if (s != NLE_OK) return s;
+    d = prec == NLE_FP32 ? static_cast<const void *>(c->binv32) : static_cast<const void *>(c->binv64);
+    pcb = 3;
+  } else {
+    d = prec == NLE_FP32 ? static_cast<const void *>(c->dinv32) : static_cast<const void *>(c->dinv64);
+  }
+  NLE_HIP(c, pc_apply(c, prec, pcb, d, x, y, n));
   return NLE_OK;
 }
 

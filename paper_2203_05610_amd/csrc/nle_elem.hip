@@ -272,6 +272,10 @@ __device__ __forceinline__ void finalize_node(uint32_t g, uint32_t mk, const T a
       nrm += double(vd * y);
     } else if (OP == OP_DIAG) {
       out[d] = fixed ? T(1) : a;
+    } else if (OP == OP_ODIAG) {
+      // entry i pairs components (i, i+1 mod 3): xy, yz, zx
+      const bool fx2 = (mk >> ((i + 1) % 3)) & 1u;
+      out[d] = (fixed || fx2) ? T(0) : a;
     }
   }
 }
@@ -456,7 +460,7 @@ __device__ __forceinline__ void element_forces(const ElemIn<T> &d, const T *uS, 
       return;
     }
     cf = coefficients<MAT>(k, H, fk, mp);
-    if (OP == OP_DIAG && A.lc64) {
+    if (OP == OP_DIAG && A.lc64) {  // (the off-diagonal pass leaves the cache)
       double q[7];
       pack_coef<MAT>(cf, q);
 #pragma unroll
@@ -551,6 +555,34 @@ __device__ __forceinline__ void element_forces(const ElemIn<T> &d, const T *uS, 
 #pragma unroll
       for (int i = 0; i < 3; ++i)
         out[a][i] = dP[i][0] * g[a][0] + dP[i][1] * g[a][1] + dP[i][2] * g[a][2];
+  } else if (OP == OP_ODIAG) {
+    // entry (i, k) of vertex a's self block, k = i+1 mod 3: with w = F^-T g,
+    // z = F g (g = grad N_a) and c1 = cF + cM (= 2 cF, major symmetry),
+    //   V [c1/2 (w_i z_k + z_i w_k) + cFF z_i z_k + (cT + cX) w_i w_k
+    //      + h2 (g.f)^2 (Ff)_i (Ff)_k]
+    const double c1 = 0.5 * V * (cf.cF + cf.cM), c2 = V * (cf.cT + cf.cX);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      T w[3], z[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        w[i] = k.FiT[i][0] * g[a][0] + k.FiT[i][1] * g[a][1] + k.FiT[i][2] * g[a][2];
+        z[i] = k.F[i][0] * g[a][0] + k.F[i][1] * g[a][1] + k.F[i][2] * g[a][2];
+      }
+      T gf2 = T(0);
+      if (MAT == NLE_MAT_M4) {
+        const T gf = g[a][0] * f[0] + g[a][1] * f[1] + g[a][2] * f[2];
+        gf2 = gf * gf;
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const int q = (i + 1) % 3;
+        T o = T(c1) * (w[i] * z[q] + z[i] * w[q]) + T(c2) * w[i] * w[q];
+        if (MAT == NLE_MAT_M4) o += T(V * cf.cFF) * z[i] * z[q] + T(V * cf.h2) * gf2 * Ff[i] * Ff[q];
+        out[a][i] = o;
+      }
+    }
+    return;
   } else {  // OP_DIAG: dF = e_i (x) g_a, one column at a time
     const double ca = V * cf.a, c1 = V * (cf.cF + cf.cM), c2 = V * (cf.cT + cf.cX);
 #pragma unroll
@@ -604,11 +636,10 @@ __global__ __launch_bounds__(NTB) void k_elem_block(ElemArgs<T> A) {
   T *cS = lds + 6 * NL;        // [3][4 BE]    contributions in slot-sorted order
   double *rs = reinterpret_cast<double *>(lds + 6 * NL + 12 * A.be_max);  // reduction scratch
 
-  // The inputs of this thread's first two elements are requested before the
-  // node gather so all of these loads are in flight together.
-  ElemIn<T> ea, eb;
+  // The inputs of this thread's first element are requested before the node
+  // gather so all of these loads are in flight together.
+  ElemIn<T> ea;
   if (tid < ne) load_elem<MAT>(A, uint32_t(e0 + tid), ea);
-  if (tid + NTB < ne) load_elem<MAT>(A, uint32_t(e0 + tid + NTB), eb);
 
   // Phase 1: gather nodal state (and direction) of the block.  The first slot
   // of each thread also has its phase-3 data (word, range, partial position)
@@ -647,10 +678,8 @@ __global__ __launch_bounds__(NTB) void k_elem_block(ElemArgs<T> A) {
         for (int i = 0; i < 3; ++i) cS[i * C4 + cp[a]] = out[a][i];
     }
   };
-  if (tid < ne) run(ea);
-  if (tid + NTB < ne) run(eb);
-  for (int e = tid + 2 * NTB; e < ne; e += NTB) {
-    load_elem<MAT>(A, uint32_t(e0 + e), ea);
+  for (int e = tid; e < ne; e += NTB) {
+    if (e != tid) load_elem<MAT>(A, uint32_t(e0 + e), ea);
     run(ea);
   }
   if (bad && A.flag) A.flag[inst] = 1;
@@ -817,6 +846,14 @@ int launch(Ctx *c, int op, const T *G, const T *V, const T *u, const T *v, T *ou
     case OP_DIAG:
       NLE_LAUNCH_BLOCK(OP_DIAG);
       break;
+    case OP_ODIAG:
+      if constexpr (sizeof(T) == 8) {
+        NLE_LAUNCH_BLOCK(OP_ODIAG);
+      } else {
+        *err = hipErrorInvalidValue;
+        return 0;
+      }
+      break;
     default:
       NLE_LAUNCH_BLOCK(OP_ENERGY);
       break;
@@ -855,6 +892,10 @@ int launch(Ctx *c, int op, const T *G, const T *V, const T *u, const T *v, T *ou
       case OP_JV:
         hipLaunchKernelGGL((k_elem_merge<T, OP_JV>), dim3(g2), dim3(NT), 0, c->stream, B);
         if (c->ep.red) nred += g2;
+        break;
+      case OP_ODIAG:
+        if constexpr (sizeof(T) == 8)
+          hipLaunchKernelGGL((k_elem_merge<T, OP_ODIAG>), dim3(g2), dim3(NT), 0, c->stream, B);
         break;
       default:
         hipLaunchKernelGGL((k_elem_merge<T, OP_DIAG>), dim3(g2), dim3(NT), 0, c->stream, B);

@@ -16,7 +16,9 @@ constexpr int VGRID_MAX = 1024;    // workgroups of the streaming vector kernels
 constexpr uint32_t NODE_MASK = 0x0FFFFFFFu;  // node id bits of a block-node word
 
 // Element kernel operations.
-enum ElemOp : int { OP_RES = 0, OP_JV = 1, OP_DIAG = 2, OP_ENERGY = 3 };
+// OP_ODIAG: the off-diagonal entries (xy, yz, xz) of each node's diagonal
+// 3x3 tangent block (FP64, P1 meshes only).
+enum ElemOp : int { OP_RES = 0, OP_JV = 1, OP_DIAG = 2, OP_ENERGY = 3, OP_ODIAG = 4 };
 
 struct MatParams {
   int32_t kind;   // NLE_MAT_M1 / NLE_MAT_M2 / NLE_MAT_M3 / NLE_MAT_M4
@@ -163,6 +165,13 @@ struct Ctx {
   double *diag64 = nullptr;
   double *dinv64 = nullptr;
   float *dinv32 = nullptr;
+  // nodal block Jacobi (computed on first use after each linearization):
+  // odiag64 [3 n_n] off-diagonals of the diagonal blocks, binv [6][n_n] the
+  // symmetric block inverses (xx, yy, zz, xy, yz, xz), component-major
+  bool blk_valid = false;
+  double *odiag64 = nullptr;
+  double *binv64 = nullptr;
+  float *binv32 = nullptr;
 
   // scratch
   void *partial = nullptr;   // [n_slots][3] doubles (shared-slot partial sums)
@@ -277,6 +286,13 @@ hipError_t reduce_scalar(Ctx *c, const double *red, int np, double *out);
 hipError_t reduce_scalars(Ctx *c, const double *red, int np, int count, double *out);
 hipError_t vec_mul(Ctx *c, int prec, const void *a, const void *b, void *y, int64_t n);
 hipError_t vec_recip(Ctx *c, const double *d, double *dinv, int64_t n);
+// y = M^-1 x with pcb = 1 (d: inverse diagonal, identity if null) or
+// pcb = 3 (d: nodal block inverses [6][n/3], see block_inverse)
+hipError_t pc_apply(Ctx *c, int prec, int pcb, const void *d, const void *x, void *y, int64_t n);
+// binv64 / binv32 from diag64 and odiag64 (nn nodes)
+hipError_t block_inverse(Ctx *c, int64_t nn);
+// odiag64 and the block inverses at the current linearization (P1 meshes)
+nle_status ensure_block(Ctx *c);
 
 // CG kernels (no per-iteration host arguments: a chunk of iterations can be
 // captured as a graph)
@@ -285,6 +301,7 @@ struct CgArgs {
   int64_t n;
   void *x, *r, *z, *p, *Ap;
   const void *dinv;   // may be null (no preconditioner)
+  int pcb = 1;        // 1: point Jacobi dinv; 3: nodal block inverses in dinv
   double *red_a;      // partials of p.Ap (from the Jacobian-action epilogue)
   int np_a;
   double *red_b;      // partials of (r.z, r.r), 2 x VGRID_MAX
@@ -301,6 +318,7 @@ struct MinresArgs {
   int64_t n;
   void *x, *r1, *r2, *y, *v, *av, *wa, *wb, *za, *zb, *r;
   const void *dinv;
+  int pcb = 1;  // as in CgArgs
   double *red_a;  // partials of v.(A v - coef r1) from the Jacobian-action epilogue
   int np_a;
   double *red_b;  // partials of t.(M^-1 t)
@@ -322,6 +340,7 @@ struct GmresArgs {
   void *z;           // [n] work (preconditioned)
   void *x;           // [n] solution
   const void *dinv;  // may be null
+  int pcb = 1;       // as in CgArgs
   double *red;       // partials [(m+2) x VGRID_MAX]
   double *H;         // device Hessenberg [(m+1) x m] column-major, + rotations
   double *scal;

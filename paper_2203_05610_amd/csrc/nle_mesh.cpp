@@ -240,6 +240,9 @@ nle_status build_mesh(Ctx *c, int64_t nn, const double *X, int64_t ne, const int
   // ---- upload ---------------------------------------------------------------------
   for (void *p : c->mesh_allocs) dfree(c, p);
   c->mesh_allocs.clear();
+  c->odiag64 = c->binv64 = nullptr;
+  c->binv32 = nullptr;
+  c->blk_valid = false;
   Mesh &M = c->m;
   M = Mesh();
   M.n_nodes = nn;

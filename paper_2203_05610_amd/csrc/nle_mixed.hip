@@ -339,6 +339,10 @@ int launch_mixed(Ctx *c, int op, const T *G, const T *V, const T *x, const T *v,
   A.skip = c->elem_skip;
   A.nomask = (op == OP_JV && c->jv_nomask) ? 1 : 0;
   const int g1 = int((M.n_e + NT - 1) / NT);
+  if (op == OP_ODIAG) {  // nodal blocks are defined for the P1 form only
+    *err = hipErrorInvalidValue;
+    return 0;
+  }
   switch (op) {
     case OP_RES:
       hipLaunchKernelGGL((k_mixed_elem<T, OP_RES>), dim3(g1), dim3(NT), 0, c->stream, A);
@@ -505,6 +509,9 @@ nle_status build_mixed_mesh(Ctx *c, int64_t nu, const double *X, int64_t ne, con
 
   for (void *p : c->mesh_allocs) dfree(c, p);
   c->mesh_allocs.clear();
+  c->odiag64 = c->binv64 = nullptr;
+  c->binv32 = nullptr;
+  c->blk_valid = false;
   c->m = Mesh();
   c->mx = MixedMesh();
   MixedMesh &M = c->mx;

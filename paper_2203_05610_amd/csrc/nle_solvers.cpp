@@ -148,9 +148,17 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
   const int64_t n = ndof(c);
   const size_t vb = size_t(n) * esz(prec);
   const void *dinv = nullptr;
-  if (o.pc == NLE_PC_JACOBI)
+  int pcb = 1;
+  if (o.pc == NLE_PC_JACOBI) {
     dinv = prec == NLE_FP32 ? static_cast<const void *>(c->dinv32)
                             : static_cast<const void *>(c->dinv64);
+  } else if (o.pc == NLE_PC_BJACOBI3) {
+    const nle_status sb = ensure_block(c);
+    if (sb != NLE_OK) return sb;
+    dinv = prec == NLE_FP32 ? static_cast<const void *>(c->binv32)
+                            : static_cast<const void *>(c->binv64);
+    pcb = 3;
+  }
   const void *ulin = prec == NLE_FP32 ? static_cast<const void *>(c->ulin32)
                                       : static_cast<const void *>(c->ulin64);
   int32_t *flag = c->dflag + 8;
@@ -189,6 +197,7 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
       a.p = W.take(vb);
       a.Ap = W.take(vb);
       a.dinv = dinv;
+      a.pcb = pcb;
       a.red_a = red_a;
       a.red_b = red_b;
       a.scal = c->dscal;
@@ -211,7 +220,8 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
                                    uint64_t(uintptr_t(c->red)), uint64_t(uintptr_t(c->m.G32)),
                                    uint64_t(uintptr_t(c->m.nodes)), uint64_t(c->mat.kind),
                                    uint64_t(uintptr_t(c->mx.G32)), uint64_t(uintptr_t(c->mx.cu)),
-                                   uint64_t(uintptr_t(c->lc_valid ? c->lc64 : nullptr))};
+                                   uint64_t(uintptr_t(c->lc_valid ? c->lc64 : nullptr)),
+                                   uint64_t(pcb)};
       st = run_chunks(c, key, check, o.max_it, flag, iter);
     } else {
       MinresArgs a;
@@ -229,6 +239,7 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
       a.zb = W.take(vb);
       a.r = W.take(vb);
       a.dinv = dinv;
+      a.pcb = pcb;
       a.red_a = red_a;
       a.red_b = red_b;
       a.red_r = red_r;
@@ -252,7 +263,8 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
                                    uint64_t(uintptr_t(c->red)), uint64_t(uintptr_t(c->m.G32)),
                                    uint64_t(uintptr_t(c->m.nodes)), uint64_t(c->mat.kind),
                                    uint64_t(uintptr_t(c->mx.G32)), uint64_t(uintptr_t(c->mx.cu)),
-                                   uint64_t(uintptr_t(c->lc_valid ? c->lc64 : nullptr))};
+                                   uint64_t(uintptr_t(c->lc_valid ? c->lc64 : nullptr)),
+                                   uint64_t(pcb)};
       st = run_chunks(c, key, check, o.max_it, flag, iter);
     }
     if (st != NLE_OK) return st;
@@ -279,6 +291,7 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
   a.z = W.take(vb);
   a.x = x;
   a.dinv = dinv;
+  a.pcb = pcb;
   a.H = static_cast<double *>(W.take(size_t((m + 1) * m + 4 * m + 8) * 8));
   a.red = static_cast<double *>(W.take(size_t(m + 3) * VGRID_MAX * 8));
   a.scal = static_cast<double *>(W.take(size_t(8 + 2 * (m + 1)) * 8));
@@ -295,7 +308,7 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
       const void *vj = static_cast<const char *>(a.V) + size_t(j) * vb;
       hipError_t e = hipSuccess;
       if (dinv)
-        e = vec_mul(c, prec, dinv, vj, a.z, n);
+        e = pc_apply(c, prec, pcb, dinv, vj, a.z, n);
       else
         e = hipMemcpyAsync(a.z, vj, vb, hipMemcpyDeviceToDevice, c->stream);
       if (e == hipSuccess)
@@ -422,7 +435,10 @@ nle_status check_ready(Ctx *c, double *u, const nle_solver_opts *o) {
   if (o->ksp_type != NLE_KSP_CG && o->ksp_type != NLE_KSP_GMRES &&
       o->ksp_type != NLE_KSP_MINRES)
     return fail(c, NLE_E_INVAL, "bad ksp_type");
-  if (o->pc != NLE_PC_JACOBI && o->pc != NLE_PC_NONE) return fail(c, NLE_E_INVAL, "bad pc");
+  if (o->pc != NLE_PC_JACOBI && o->pc != NLE_PC_NONE && o->pc != NLE_PC_BJACOBI3)
+    return fail(c, NLE_E_INVAL, "bad pc");
+  if (o->pc == NLE_PC_BJACOBI3 && c->mixed)
+    return fail(c, NLE_E_UNSUPPORTED, "nodal block Jacobi needs a P1 mesh");
   if (o->ksp_max_it < 1 || o->snes_max_it < 0) return fail(c, NLE_E_INVAL, "bad iteration limits");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, NLE_E_HIP, "hipSetDevice failed");
   return NLE_OK;
@@ -672,9 +688,16 @@ nle_status bfgs(Ctx *c, double *u, const nle_solver_opts &o, nle_report *report)
   if (rn > tol && std::isfinite(rn) && !inv) {
     s = linearize(c, u, prec);  // the single linearization of the step
     if (s != NLE_OK) return s;
+    if (o.pc == NLE_PC_BJACOBI3 && o.h0 != NLE_H0_KSP) {
+      s = ensure_block(c);
+      if (s != NLE_OK) return s;
+    }
   }
-  const void *dinv = prec == NLE_FP32 ? static_cast<const void *>(c->dinv32)
-                                      : static_cast<const void *>(c->dinv64);
+  const bool blk = o.pc == NLE_PC_BJACOBI3;
+  const void *dinv = blk ? (prec == NLE_FP32 ? static_cast<const void *>(c->binv32)
+                                             : static_cast<const void *>(c->binv64))
+                         : (prec == NLE_FP32 ? static_cast<const void *>(c->dinv32)
+                                             : static_cast<const void *>(c->dinv64));
   double *redA = c->red, *redB = c->red + VGRID_MAX;
   int k = 0;
   nle_status st = NLE_DIVERGED_MAXIT;
@@ -722,8 +745,8 @@ nle_status bfgs(Ctx *c, double *u, const nle_solver_opts &o, nle_report *report)
         st = fail(c, NLE_DIVERGED_LINEAR, "H0 Krylov solve produced NaN");
         break;
       }
-    } else if (o.pc == NLE_PC_JACOBI) {
-      NLE_HIP(c, vec_mul(c, prec, dinv, q, z, n));
+    } else if (o.pc == NLE_PC_JACOBI || blk) {
+      NLE_HIP(c, pc_apply(c, prec, blk ? 3 : 1, dinv, q, z, n));
     } else {
       NLE_HIP(c, hipMemcpyAsync(z, q, size_t(n) * esz(prec), hipMemcpyDeviceToDevice, c->stream));
     }

@@ -103,6 +103,9 @@ __global__ __launch_bounds__(NT) void k_surface(SurfArgs<T> A) {
         if (OP == OP_DIAG) {
 #pragma unroll
           for (int i = 0; i < 3; ++i) acc[i] += area / T(6) * (kpar + dk * N[i] * N[i]);
+        } else if (OP == OP_ODIAG) {
+#pragma unroll
+          for (int i = 0; i < 3; ++i) acc[i] += area / T(6) * dk * N[i] * N[(i + 1) % 3];
         } else {
           const T *w = OP == OP_JV ? A.v : A.u;
           const uint32_t fm = (OP == OP_JV && !A.nomask) ? A.fmask[f] : 0u;
@@ -180,6 +183,9 @@ void launch_surface(Ctx *c, int op, const T *u, const T *v, T *fs, double *red, 
       break;
     case OP_DIAG:
       hipLaunchKernelGGL((k_surface<T, OP_DIAG>), dim3(grid), dim3(NT), 0, c->stream, A);
+      break;
+    case OP_ODIAG:
+      hipLaunchKernelGGL((k_surface<T, OP_ODIAG>), dim3(grid), dim3(NT), 0, c->stream, A);
       break;
     default:
       hipLaunchKernelGGL((k_surface<T, OP_ENERGY>), dim3(grid), dim3(NT), 0, c->stream, A);

@@ -116,20 +116,91 @@ enum {
   M_INVBETA = 21
 };
 
-template <typename T>
+// Preconditioner on one unit of BS consecutive entries (unit u of nu):
+//   BS = 1: point Jacobi, z = d r (d the inverse diagonal; identity if null);
+//   BS = 3: nodal block Jacobi, z = B r with B the symmetric inverse of the
+//           node's diagonal 3x3 tangent block, d = [6][nu] component-major
+//           (xx, yy, zz, xy, yz, xz).
+template <int BS, typename T>
+__device__ __forceinline__ void pc_unit(const T *d, int64_t u, int64_t nu, const T *r, T *z) {
+  if constexpr (BS == 1) {
+    z[0] = d ? d[u] * r[0] : r[0];
+  } else {
+    const T bxx = d[u], byy = d[nu + u], bzz = d[2 * nu + u];
+    const T bxy = d[3 * nu + u], byz = d[4 * nu + u], bxz = d[5 * nu + u];
+    z[0] = bxx * r[0] + bxy * r[1] + bxz * r[2];
+    z[1] = bxy * r[0] + byy * r[1] + byz * r[2];
+    z[2] = bxz * r[0] + byz * r[1] + bzz * r[2];
+  }
+}
+
+#define UNIT_LOOP(u, nu)                                                            \
+  for (int64_t u = int64_t(blockIdx.x) * NT + threadIdx.x; u < (nu); u += int64_t(gridDim.x) * NT)
+
+template <typename T, int BS>
+__global__ __launch_bounds__(NT) void k_pc_apply(const T *d, const T *x, T *y, int64_t n) {
+  const int64_t nu = n / BS;
+  UNIT_LOOP(u, nu) {
+    T r[BS], z[BS];
+#pragma unroll
+    for (int c = 0; c < BS; ++c) r[c] = x[BS * u + c];
+    pc_unit<BS>(d, u, nu, r, z);
+#pragma unroll
+    for (int c = 0; c < BS; ++c) y[BS * u + c] = z[c];
+  }
+}
+
+// Symmetric 3x3 block inverses from the diagonal (d: xx yy zz per node,
+// interleaved) and off-diagonal entries (o: xy yz zx per node), by cofactors
+// in FP64; written as [6][nn] in FP64 and FP32.
+__global__ __launch_bounds__(NT) void k_block_inv(const double *d, const double *o, double *b64,
+                                                  float *b32, int64_t nn) {
+  UNIT_LOOP(k, nn) {
+    const double a00 = d[3 * k], a11 = d[3 * k + 1], a22 = d[3 * k + 2];
+    const double a01 = o[3 * k], a12 = o[3 * k + 1], a02 = o[3 * k + 2];
+    const double c00 = a11 * a22 - a12 * a12, c11 = a00 * a22 - a02 * a02;
+    const double c22 = a00 * a11 - a01 * a01;
+    const double c01 = a02 * a12 - a01 * a22, c12 = a01 * a02 - a00 * a12;
+    const double c02 = a01 * a12 - a02 * a11;
+    const double det = a00 * c00 + a01 * c01 + a02 * c02;
+    const double id = 1.0 / det;
+    const double v[6] = {c00 * id, c11 * id, c22 * id, c01 * id, c12 * id, c02 * id};
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+      b64[t * nn + k] = v[t];
+      b32[t * nn + k] = float(v[t]);
+    }
+  }
+}
+
+// Preconditioned CG (Hestenes-Stiefel).  One iteration: the Jacobian action
+// Ap = J p (its epilogue gives the partials of p.Ap), cg_update, cg_direction.
+// (The single-reduction arrangement, which carries s = A p by recurrence and
+// saves one launch, was measured: in FP32 its recurrence drifts and the
+// inexact Newton solves needed ~50% more iterations, so it is not used.)
+template <typename T, int BS>
 __global__ __launch_bounds__(NT) void k_cg_start(const T *b, T *x, T *r, T *z, T *p, const T *dinv,
                                                  int64_t n, double *red) {
   __shared__ T sh[NT / 64];
   T arz = T(0), arr = T(0);
-  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT) {
-    const T bi = b[i];
-    const T zi = dinv ? dinv[i] * bi : bi;
-    x[i] = T(0);
-    r[i] = bi;
-    z[i] = zi;
-    p[i] = zi;
-    arz += bi * zi;
-    arr += bi * bi;
+  const int64_t nu = n / BS;
+  UNIT_LOOP(k, nu) {
+    T bi[BS], zi[BS];
+#pragma unroll
+    for (int c = 0; c < BS; ++c) {
+      const int64_t i = BS * k + c;
+      bi[c] = b[i];
+      x[i] = T(0);
+      r[i] = bi[c];
+    }
+    pc_unit<BS>(dinv, k, nu, bi, zi);
+#pragma unroll
+    for (int c = 0; c < BS; ++c) {
+      z[BS * k + c] = zi[c];
+      p[BS * k + c] = zi[c];
+      arz += bi[c] * zi[c];
+      arr += bi[c] * bi[c];
+    }
   }
   arz = block_sum_all(arz, sh);
   arr = block_sum_all(arr, sh);
@@ -159,7 +230,7 @@ __global__ __launch_bounds__(NT) void k_cg_start2(const double *red, int np, dou
 
 // alpha = rz / p.Ap;  x += alpha p;  r -= alpha Ap;  z = M^-1 r; partials of
 // r.z and r.r.  p.Ap partials come from the Jacobian-action epilogue.
-template <typename T>
+template <typename T, int BS>
 __global__ __launch_bounds__(NT) void k_cg_update(T *x, T *r, T *z, const T *p, const T *Ap,
                                                   const T *dinv, int64_t n, const double *red_a,
                                                   int np_a, double *red_b, double *scal,
@@ -177,14 +248,23 @@ __global__ __launch_bounds__(NT) void k_cg_update(T *x, T *r, T *z, const T *p, 
   if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_RZOLD] = rz;
   const T a = T(alpha);
   T arz = T(0), arr = T(0);
-  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT) {
-    const T ri = r[i] - a * Ap[i];
-    const T zi = dinv ? dinv[i] * ri : ri;
-    x[i] += a * p[i];
-    r[i] = ri;
-    z[i] = zi;
-    arz += ri * zi;
-    arr += ri * ri;
+  const int64_t nu = n / BS;
+  UNIT_LOOP(k, nu) {
+    T ri[BS], zi[BS];
+#pragma unroll
+    for (int c = 0; c < BS; ++c) {
+      const int64_t i = BS * k + c;
+      ri[c] = r[i] - a * Ap[i];
+      x[i] += a * p[i];
+      r[i] = ri[c];
+    }
+    pc_unit<BS>(dinv, k, nu, ri, zi);
+#pragma unroll
+    for (int c = 0; c < BS; ++c) {
+      z[BS * k + c] = zi[c];
+      arz += ri[c] * zi[c];
+      arr += ri[c] * ri[c];
+    }
   }
   arz = block_sum_all(arz, sh);
   arr = block_sum_all(arr, sh);
@@ -225,26 +305,35 @@ __global__ __launch_bounds__(NT) void k_cg_direction(T *p, const T *z, int64_t n
 // Preconditioned MINRES (Paige & Saunders 1975; the Lanczos / Givens form).
 // Besides the solution it carries z = A w and the true residual r = b - A x,
 // so the stopping test is on ||b - A x||_2 like the other Krylov methods.
-template <typename T>
+template <typename T, int BS>
 __global__ __launch_bounds__(NT) void k_mr_start(const T *b, T *x, T *r1, T *r2, T *y, T *r,
                                                  T *wa, T *wb, T *za, T *zb, const T *dinv,
                                                  int64_t n, double *red) {
   __shared__ T sh[NT / 64];
   T aby = T(0), abb = T(0);
-  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT) {
-    const T bi = b[i];
-    const T yi = dinv ? dinv[i] * bi : bi;
-    x[i] = T(0);
-    r1[i] = bi;
-    r2[i] = bi;
-    r[i] = bi;
-    y[i] = yi;
-    wa[i] = T(0);
-    wb[i] = T(0);
-    za[i] = T(0);
-    zb[i] = T(0);
-    aby += bi * yi;
-    abb += bi * bi;
+  const int64_t nu = n / BS;
+  UNIT_LOOP(k, nu) {
+    T bi[BS], yi[BS];
+#pragma unroll
+    for (int c = 0; c < BS; ++c) {
+      const int64_t i = BS * k + c;
+      bi[c] = b[i];
+      x[i] = T(0);
+      r1[i] = bi[c];
+      r2[i] = bi[c];
+      r[i] = bi[c];
+      wa[i] = T(0);
+      wb[i] = T(0);
+      za[i] = T(0);
+      zb[i] = T(0);
+    }
+    pc_unit<BS>(dinv, k, nu, bi, yi);
+#pragma unroll
+    for (int c = 0; c < BS; ++c) {
+      y[BS * k + c] = yi[c];
+      aby += bi[c] * yi[c];
+      abb += bi[c] * bi[c];
+    }
   }
   aby = block_sum_all(aby, sh);
   abb = block_sum_all(abb, sh);
@@ -301,7 +390,7 @@ __global__ __launch_bounds__(NT) void k_mr_v(const T *y, T *v, int64_t n, const 
 // After the Jacobian action (with epilogue) y = A v - coef r1 and partials of
 // alfa = v.y:  av = A v;  t = y - (alfa / beta) r2;  r1 = r2;  r2 = t;
 // y = M^-1 t;  partials of t.y.
-template <typename T>
+template <typename T, int BS>
 __global__ __launch_bounds__(NT) void k_mr_c(T *y, T *r1, T *r2, T *av, const T *dinv, int64_t n,
                                              const double *red_a, int np_a, double *red_b,
                                              double *scal, const int32_t *flag) {
@@ -313,16 +402,25 @@ __global__ __launch_bounds__(NT) void k_mr_c(T *y, T *r1, T *r2, T *av, const T 
   const T c = T(scal[M_COEF]);
   const T ab = T(alfa * scal[M_INVBETA]);
   T acc = T(0);
-  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT) {
-    const T yi = y[i];
-    const T r1i = r1[i], r2i = r2[i];
-    av[i] = yi + c * r1i;
-    const T t = yi - ab * r2i;
-    r1[i] = r2i;
-    r2[i] = t;
-    const T yn = dinv ? dinv[i] * t : t;
-    y[i] = yn;
-    acc += t * yn;
+  const int64_t nu = n / BS;
+  UNIT_LOOP(k, nu) {
+    T t[BS], yn[BS];
+#pragma unroll
+    for (int q = 0; q < BS; ++q) {
+      const int64_t i = BS * k + q;
+      const T yi = y[i];
+      const T r1i = r1[i], r2i = r2[i];
+      av[i] = yi + c * r1i;
+      t[q] = yi - ab * r2i;
+      r1[i] = r2i;
+      r2[i] = t[q];
+    }
+    pc_unit<BS>(dinv, k, nu, t, yn);
+#pragma unroll
+    for (int q = 0; q < BS; ++q) {
+      y[BS * k + q] = yn[q];
+      acc += t[q] * yn[q];
+    }
   }
   acc = block_sum_all(acc, sh);
   if (threadIdx.x == 0) red_b[blockIdx.x] = double(acc);
@@ -533,7 +631,7 @@ __global__ void k_gm_solve(double *H, int m, const int32_t *flag) {
 }
 
 // x += M^-1 (sum_i y_i V_i)
-template <typename T>
+template <typename T, int BS>
 __global__ __launch_bounds__(NT) void k_gm_update(const T *V, T *x, const T *dinv, int64_t n,
                                                   const double *H, int m, const int32_t *flag) {
   __shared__ double ys[256];
@@ -541,11 +639,27 @@ __global__ __launch_bounds__(NT) void k_gm_update(const T *V, T *x, const T *din
   const double *y = H + (m + 1) * m + 3 * m + 1;
   for (int i = threadIdx.x; i < k && i < 256; i += NT) ys[i] = y[i];
   __syncthreads();
-  for (int64_t q = int64_t(blockIdx.x) * NT + threadIdx.x; q < n; q += int64_t(gridDim.x) * NT) {
-    double s = 0.0;
-    for (int i = 0; i < k; ++i) s += (i < 256 ? ys[i] : y[i]) * double(V[int64_t(i) * n + q]);
-    const double d = dinv ? double(dinv[q]) : 1.0;
-    x[q] = T(double(x[q]) + d * s);
+  const int64_t nu = n / BS;
+  UNIT_LOOP(u, nu) {
+    double s[BS];
+#pragma unroll
+    for (int c = 0; c < BS; ++c) {
+      const int64_t q = BS * u + c;
+      s[c] = 0.0;
+      for (int i = 0; i < k; ++i) s[c] += (i < 256 ? ys[i] : y[i]) * double(V[int64_t(i) * n + q]);
+    }
+    if constexpr (BS == 1) {
+      const double d = dinv ? double(dinv[u]) : 1.0;
+      x[u] = T(double(x[u]) + d * s[0]);
+    } else {
+      const double bxx = dinv[u], byy = dinv[nu + u], bzz = dinv[2 * nu + u];
+      const double bxy = dinv[3 * nu + u], byz = dinv[4 * nu + u], bxz = dinv[5 * nu + u];
+      const double z[3] = {bxx * s[0] + bxy * s[1] + bxz * s[2],
+                           bxy * s[0] + byy * s[1] + byz * s[2],
+                           bxz * s[0] + byz * s[1] + bzz * s[2]};
+#pragma unroll
+      for (int c = 0; c < 3; ++c) x[3 * u + c] = T(double(x[3 * u + c]) + z[c]);
+    }
   }
 }
 
@@ -672,6 +786,31 @@ hipError_t vec_mul(Ctx *c, int prec, const void *a, const void *b, void *y, int6
   return hipGetLastError();
 }
 
+hipError_t pc_apply(Ctx *c, int prec, int pcb, const void *d, const void *x, void *y, int64_t n) {
+  const int g = vgrid(n);
+  if (prec == NLE_FP32) {
+    if (pcb == 3)
+      LAUNCH((k_pc_apply<float, 3>), g, static_cast<const float *>(d), static_cast<const float *>(x),
+             static_cast<float *>(y), n);
+    else
+      LAUNCH((k_pc_apply<float, 1>), g, static_cast<const float *>(d), static_cast<const float *>(x),
+             static_cast<float *>(y), n);
+  } else {
+    if (pcb == 3)
+      LAUNCH((k_pc_apply<double, 3>), g, static_cast<const double *>(d),
+             static_cast<const double *>(x), static_cast<double *>(y), n);
+    else
+      LAUNCH((k_pc_apply<double, 1>), g, static_cast<const double *>(d),
+             static_cast<const double *>(x), static_cast<double *>(y), n);
+  }
+  return hipGetLastError();
+}
+
+hipError_t block_inverse(Ctx *c, int64_t nn) {
+  LAUNCH(k_block_inv, vgrid(nn), c->diag64, c->odiag64, c->binv64, c->binv32, nn);
+  return hipGetLastError();
+}
+
 hipError_t vec_recip(Ctx *c, const double *d, double *di, int64_t n) {
   LAUNCH(k_recip, vgrid(n), d, di, n);
   return hipGetLastError();
@@ -713,30 +852,32 @@ hipError_t reduce_scalars(Ctx *c, const double *red, int np, int count, double *
 // ------------------------------------------------------------------ CG
 hipError_t cg_start(Ctx *c, const CgArgs &a, const void *b, double rtol, double atol, int max_it) {
   const int g = vgrid(a.n);
-  if (a.prec == NLE_FP32)
-    LAUNCH(k_cg_start<float>, g, static_cast<const float *>(b), static_cast<float *>(a.x),
-           static_cast<float *>(a.r), static_cast<float *>(a.z), static_cast<float *>(a.p),
-           static_cast<const float *>(a.dinv), a.n, a.red_b);
-  else
-    LAUNCH(k_cg_start<double>, g, static_cast<const double *>(b), static_cast<double *>(a.x),
-           static_cast<double *>(a.r), static_cast<double *>(a.z), static_cast<double *>(a.p),
-           static_cast<const double *>(a.dinv), a.n, a.red_b);
+#define CG_START(T, BS)                                                                        \
+  LAUNCH((k_cg_start<T, BS>), g, static_cast<const T *>(b), static_cast<T *>(a.x),              \
+         static_cast<T *>(a.r), static_cast<T *>(a.z), static_cast<T *>(a.p),                   \
+         static_cast<const T *>(a.dinv), a.n, a.red_b)
+  if (a.prec == NLE_FP32) {
+    if (a.pcb == 3) CG_START(float, 3); else CG_START(float, 1);
+  } else {
+    if (a.pcb == 3) CG_START(double, 3); else CG_START(double, 1);
+  }
+#undef CG_START
   LAUNCH(k_cg_start2, 1, a.red_b, g, a.scal, a.flag, rtol, atol, max_it);
   return hipGetLastError();
 }
 
 hipError_t cg_update(Ctx *c, const CgArgs &a) {
   const int g = vgrid(a.n);
-  if (a.prec == NLE_FP32)
-    LAUNCH(k_cg_update<float>, g, static_cast<float *>(a.x), static_cast<float *>(a.r),
-           static_cast<float *>(a.z), static_cast<const float *>(a.p),
-           static_cast<const float *>(a.Ap), static_cast<const float *>(a.dinv), a.n, a.red_a,
-           a.np_a, a.red_b, a.scal, a.flag);
-  else
-    LAUNCH(k_cg_update<double>, g, static_cast<double *>(a.x), static_cast<double *>(a.r),
-           static_cast<double *>(a.z), static_cast<const double *>(a.p),
-           static_cast<const double *>(a.Ap), static_cast<const double *>(a.dinv), a.n, a.red_a,
-           a.np_a, a.red_b, a.scal, a.flag);
+#define CG_UPD(T, BS)                                                                          \
+  LAUNCH((k_cg_update<T, BS>), g, static_cast<T *>(a.x), static_cast<T *>(a.r),                 \
+         static_cast<T *>(a.z), static_cast<const T *>(a.p), static_cast<const T *>(a.Ap),      \
+         static_cast<const T *>(a.dinv), a.n, a.red_a, a.np_a, a.red_b, a.scal, a.flag)
+  if (a.prec == NLE_FP32) {
+    if (a.pcb == 3) CG_UPD(float, 3); else CG_UPD(float, 1);
+  } else {
+    if (a.pcb == 3) CG_UPD(double, 3); else CG_UPD(double, 1);
+  }
+#undef CG_UPD
   return hipGetLastError();
 }
 
@@ -760,10 +901,17 @@ hipError_t cg_direction(Ctx *c, const CgArgs &a) {
 hipError_t mr_start(Ctx *c, const MinresArgs &a, const void *b, double rtol, double atol,
                     int max_it) {
   const int g = vgrid(a.n);
-  if (a.prec == NLE_FP32)
-    LAUNCH(k_mr_start<float>, g, static_cast<const float *>(b), MR_PTRS(float), a.n, a.red_b);
-  else
-    LAUNCH(k_mr_start<double>, g, static_cast<const double *>(b), MR_PTRS(double), a.n, a.red_b);
+  if (a.prec == NLE_FP32) {
+    if (a.pcb == 3)
+      LAUNCH((k_mr_start<float, 3>), g, static_cast<const float *>(b), MR_PTRS(float), a.n, a.red_b);
+    else
+      LAUNCH((k_mr_start<float, 1>), g, static_cast<const float *>(b), MR_PTRS(float), a.n, a.red_b);
+  } else {
+    if (a.pcb == 3)
+      LAUNCH((k_mr_start<double, 3>), g, static_cast<const double *>(b), MR_PTRS(double), a.n, a.red_b);
+    else
+      LAUNCH((k_mr_start<double, 1>), g, static_cast<const double *>(b), MR_PTRS(double), a.n, a.red_b);
+  }
   LAUNCH(k_mr_start2, 1, a.red_b, g, a.scal, a.flag, rtol, atol, max_it);
   if (a.prec == NLE_FP32)
     LAUNCH(k_mr_v<float>, g, static_cast<const float *>(a.y), static_cast<float *>(a.v), a.n,
@@ -777,14 +925,16 @@ hipError_t mr_start(Ctx *c, const MinresArgs &a, const void *b, double rtol, dou
 // the three vector / scalar steps after the Jacobian action of one iteration
 hipError_t mr_iterate(Ctx *c, const MinresArgs &a) {
   const int g = vgrid(a.n);
-  if (a.prec == NLE_FP32)
-    LAUNCH(k_mr_c<float>, g, static_cast<float *>(a.y), static_cast<float *>(a.r1),
-           static_cast<float *>(a.r2), static_cast<float *>(a.av), static_cast<const float *>(a.dinv),
-           a.n, a.red_a, a.np_a, a.red_b, a.scal, a.flag);
-  else
-    LAUNCH(k_mr_c<double>, g, static_cast<double *>(a.y), static_cast<double *>(a.r1),
-           static_cast<double *>(a.r2), static_cast<double *>(a.av),
-           static_cast<const double *>(a.dinv), a.n, a.red_a, a.np_a, a.red_b, a.scal, a.flag);
+#define MR_C(T, BS)                                                                            \
+  LAUNCH((k_mr_c<T, BS>), g, static_cast<T *>(a.y), static_cast<T *>(a.r1),                    \
+         static_cast<T *>(a.r2), static_cast<T *>(a.av), static_cast<const T *>(a.dinv), a.n,   \
+         a.red_a, a.np_a, a.red_b, a.scal, a.flag)
+  if (a.prec == NLE_FP32) {
+    if (a.pcb == 3) MR_C(float, 3); else MR_C(float, 1);
+  } else {
+    if (a.pcb == 3) MR_C(double, 3); else MR_C(double, 1);
+  }
+#undef MR_C
   LAUNCH(k_mr_d, 1, a.red_b, g, a.red_r, g, a.scal, a.flag);
   if (a.prec == NLE_FP32)
     LAUNCH(k_mr_e<float>, g, static_cast<float *>(a.x), static_cast<float *>(a.v),
@@ -886,12 +1036,15 @@ hipError_t gmres_finish_col(Ctx *c, const GmresArgs &a, int j, int mgs) {
 hipError_t gmres_update_x(Ctx *c, const GmresArgs &a) {
   hipLaunchKernelGGL(k_gm_solve, dim3(1), dim3(64), 0, c->stream, a.H, a.m, a.flag);
   const int g = vgrid(a.n);
-  if (a.prec == NLE_FP32)
-    LAUNCH(k_gm_update<float>, g, static_cast<const float *>(a.V), static_cast<float *>(a.x),
-           static_cast<const float *>(a.dinv), a.n, a.H, a.m, a.flag);
-  else
-    LAUNCH(k_gm_update<double>, g, static_cast<const double *>(a.V), static_cast<double *>(a.x),
-           static_cast<const double *>(a.dinv), a.n, a.H, a.m, a.flag);
+#define GM_UPD(T, BS)                                                                          \
+  LAUNCH((k_gm_update<T, BS>), g, static_cast<const T *>(a.V), static_cast<T *>(a.x),           \
+         static_cast<const T *>(a.dinv), a.n, a.H, a.m, a.flag)
+  if (a.prec == NLE_FP32) {
+    if (a.pcb == 3) GM_UPD(float, 3); else GM_UPD(float, 1);
+  } else {
+    if (a.pcb == 3) GM_UPD(double, 3); else GM_UPD(double, 1);
+  }
+#undef GM_UPD
   return hipGetLastError();
 }
 

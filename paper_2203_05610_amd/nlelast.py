@@ -29,7 +29,7 @@ NLE_MAT_M1, NLE_MAT_M2, NLE_MAT_M3, NLE_MAT_M4 = 1, 2, 3, 4
 NLE_NK, NLE_INK, NLE_BFGS = 0, 1, 2
 NLE_KSP_GMRES, NLE_KSP_CG, NLE_KSP_MINRES = 0, 1, 2
 NLE_ORTH_MGS, NLE_ORTH_CGS2 = 0, 1
-NLE_PC_NONE, NLE_PC_JACOBI = 0, 1
+NLE_PC_NONE, NLE_PC_JACOBI, NLE_PC_BJACOBI3 = 0, 1, 2
 NLE_H0_PREONLY, NLE_H0_KSP = 0, 1
 NLE_PREC_FP64, NLE_PREC_MIXED = 0, 1
 
@@ -48,7 +48,7 @@ EXPORTS = [
     "nle_solve_bfgs", "nle_partition_info", "nle_batch_create", "nle_batch_destroy",
     "nle_batch_last_error", "nle_batch_add", "nle_batch_finalize", "nle_batch_layout",
     "nle_batch_solve", "nle_set_fibres", "nle_set_active_tension", "nle_set_pressure",
-    "nle_set_robin", "nle_upload_mesh_mixed",
+    "nle_set_robin", "nle_upload_mesh_mixed", "nle_block_diag", "nle_pc_apply",
 ]
 
 
@@ -119,6 +119,8 @@ def lib() -> ctypes.CDLL:
         "nle_linearize": (I32, [P, P, I32]),
         "nle_jv": (I32, [P, P, P, I32]),
         "nle_diag": (I32, [P, P]),
+        "nle_block_diag": (I32, [P, P]),
+        "nle_pc_apply": (I32, [P, I32, I32, P, P]),
         "nle_energy": (I32, [P, P, ctypes.POINTER(D)]),
         "nle_default_opts": (None, [I32, ctypes.POINTER(nle_solver_opts)]),
         "nle_solve_nk": (I32, [P, P, ctypes.POINTER(nle_solver_opts), ctypes.POINTER(nle_report)]),
@@ -346,6 +348,19 @@ def nle_jv(ctx: Context, v, y, prec: int = NLE_FP64) -> None:
 
 def nle_diag(ctx: Context, d) -> None:
     ctx.check(lib().nle_diag(ctx.handle, ctx.vec(d, ctx.torch.float64)))
+
+
+def nle_block_diag(ctx: Context, b) -> None:
+    """b: float64 device tensor of 6 n_nodes entries (xx, yy, zz, xy, yz, xz per node)."""
+    if not (b.is_cuda and b.dtype == ctx.torch.float64 and b.is_contiguous()
+            and b.numel() == 6 * ctx.n_nodes):
+        raise ValueError("expected a contiguous float64 CUDA tensor of 6 n_nodes entries")
+    ctx.check(lib().nle_block_diag(ctx.handle, ctypes.c_void_p(b.data_ptr())))
+
+
+def nle_pc_apply(ctx: Context, pc: int, x, y, prec: int = NLE_FP64) -> None:
+    T = ctx.torch.float32 if prec == NLE_FP32 else ctx.torch.float64
+    ctx.check(lib().nle_pc_apply(ctx.handle, int(pc), int(prec), ctx.vec(x, T), ctx.vec(y, T)))
 
 
 def nle_energy(ctx: Context, u) -> float:
