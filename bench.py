@@ -98,6 +98,7 @@ def jv_roofline(nl, torch, reps: int):
     u = (torch.tensor(mesh.X, device="cuda") * 1e-3).reshape(-1).contiguous()
     nl.nle_linearize(ctx, u, nl.NLE_FP32)
     out = {}
+    n_slots = nl.nle_partition_info(ctx)["block_node_slots"]
     for prec, dt, s in ((nl.NLE_FP32, torch.float32, 4), (nl.NLE_FP64, torch.float64, 8)):
         v = torch.randn(n, dtype=dt, device="cuda", generator=g)
         y = torch.empty_like(v)
@@ -112,12 +113,14 @@ def jv_roofline(nl, torch, reps: int):
         e1.record(ctx.stream)
         e1.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        # per element: 16-byte index record, 9 gradient entries, volume and the
-        # one cached tangent coefficient of law M1; per node: u, v read, y written
-        balg = mesh.n_elems * (16 + 11 * s) + mesh.n_nodes * 9 * s
+        # per element: 16-byte index record and the one cached tangent
+        # coefficient of law M1; per block-node slot: its 3 relative
+        # coordinates (the kernel forms grad N and V from them); per node: u
+        # and v read, y written
+        balg = mesh.n_elems * (16 + s) + n_slots * 3 * s + mesh.n_nodes * 9 * s
         out["fp32" if s == 4 else "fp64"] = {
             "ms": ms, "bytes": balg, "gbs": balg / ms / 1e6,
-            "n_elems": mesh.n_elems, "n_nodes": mesh.n_nodes,
+            "n_elems": mesh.n_elems, "n_nodes": mesh.n_nodes, "n_slots": n_slots,
         }
     out["partition"] = nl.nle_partition_info(ctx)
     ctx.close()

@@ -738,8 +738,8 @@ nle_status nle_partition_info(const nle_ctx *ctx, int64_t *info) {
   info[3] = M.n_slots;
   info[4] = M.n_shared;
   info[5] = M.n_fx;
-  info[6] = int64_t(6 * M.nl_max + 12 * M.be_max) * 8;
-  info[7] = int64_t(6 * M.nl_max + 12 * M.be_max) * 4;
+  info[6] = int64_t(9 * M.nl_max + 12 * M.be_max) * 8;
+  info[7] = int64_t(9 * M.nl_max + 12 * M.be_max) * 4;
   return NLE_OK;
 }
 

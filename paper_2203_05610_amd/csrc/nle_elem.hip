@@ -22,8 +22,7 @@ namespace {
 
 template <typename T>
 struct ElemArgs {
-  const T *G;
-  const T *V;
+  const T *xr;        // [n_slots][3] slot coordinates relative to the block's first slot
   const uint4 *lcp;   // per element: 4 slot-local vertex ids, 4 contribution positions (u16)
   const uint16_t *csr_end;
   const uint32_t *nodes;
@@ -284,8 +283,6 @@ __device__ __forceinline__ void finalize_node(uint32_t g, uint32_t mk, const T a
 template <typename T>
 struct ElemIn {
   uint4 lcp;   // 8 x u16: slot-local vertex ids, then contribution positions
-  T g[3][3];   // grad N_1..3
-  T vol;
   T f[3];      // fibre direction (law M4)
   uint32_t ge; // renumbered element index
 };
@@ -293,21 +290,13 @@ struct ElemIn {
 __device__ __forceinline__ int lo16(uint32_t w) { return int(w & 0xFFFFu); }
 __device__ __forceinline__ int hi16(uint32_t w) { return int(w >> 16); }
 
-// Component k of the gradients lives at G + k n_e: with a 32-bit element
+// Per-element arrays are component-major ([k][n_e]): with a 32-bit element
 // index and uniform per-component base pointers every load is a scalar base
 // plus one shared 32-bit lane offset.
 template <int MAT, typename T>
 __device__ __forceinline__ void load_elem(const ElemArgs<T> &A, uint32_t ge, ElemIn<T> &d) {
   d.lcp = A.lcp[ge];
   const uint32_t ne = uint32_t(A.n_e);
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      const T *Gk = A.G + size_t(3 * a + j) * ne;
-      d.g[a][j] = Gk[ge];
-    }
-  d.vol = A.V[ge];
   d.ge = ge;
   if (MAT == NLE_MAT_M4) {
 #pragma unroll
@@ -410,15 +399,41 @@ __device__ __forceinline__ void kinematics_light(const T H[3][3], Kin<T> &k) {
 
 template <typename T, int OP, int MAT>
 __device__ __forceinline__ void element_forces(const ElemIn<T> &d, const T *uS, const T *vS,
-                                               int NL, const MatParams &mp, T out[4][3],
-                                               bool &bad, double &eacc, const ElemArgs<T> &A,
-                                               uint32_t ge) {
+                                               const T *xS, int NL, const MatParams &mp,
+                                               T out[4][3], bool &bad, double &eacc,
+                                               const ElemArgs<T> &A, uint32_t ge) {
   const int la[4] = {lo16(d.lcp.x), hi16(d.lcp.x), lo16(d.lcp.y), hi16(d.lcp.y)};
+  // geometry from the block's slot coordinates: D = [x1-x0 | x2-x0 | x3-x0],
+  // grad N_a = row a-1 of D^-1 = column a-1 of cof(D) / det D (a = 1..3),
+  // grad N_0 = -(grad N_1 + grad N_2 + grad N_3), V = det D / 6
   T g[4][3];
+  T Vt;
+  {
+    T D[3][3];
 #pragma unroll
-  for (int a = 1; a < 4; ++a)
+    for (int i = 0; i < 3; ++i) {
+      const T x0 = xS[i * NL + la[0]];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) g[a][j] = d.g[a - 1][j];
+      for (int a = 1; a < 4; ++a) D[i][a - 1] = xS[i * NL + la[a]] - x0;
+    }
+    T C[3][3];
+    C[0][0] = D[1][1] * D[2][2] - D[1][2] * D[2][1];
+    C[0][1] = D[1][2] * D[2][0] - D[1][0] * D[2][2];
+    C[0][2] = D[1][0] * D[2][1] - D[1][1] * D[2][0];
+    C[1][0] = D[0][2] * D[2][1] - D[0][1] * D[2][2];
+    C[1][1] = D[0][0] * D[2][2] - D[0][2] * D[2][0];
+    C[1][2] = D[0][1] * D[2][0] - D[0][0] * D[2][1];
+    C[2][0] = D[0][1] * D[1][2] - D[0][2] * D[1][1];
+    C[2][1] = D[0][2] * D[1][0] - D[0][0] * D[1][2];
+    C[2][2] = D[0][0] * D[1][1] - D[0][1] * D[1][0];
+    const T det = D[0][0] * C[0][0] + D[0][1] * C[0][1] + D[0][2] * C[0][2];
+    const T id = T(1) / det;
+#pragma unroll
+    for (int a = 1; a < 4; ++a)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) g[a][j] = C[j][a - 1] * id;
+    Vt = det / T(6);
+  }
 #pragma unroll
   for (int j = 0; j < 3; ++j) g[0][j] = -(g[1][j] + g[2][j] + g[3][j]);
   T H[3][3];
@@ -435,7 +450,7 @@ __device__ __forceinline__ void element_forces(const ElemIn<T> &d, const T *uS, 
       for (int j = 0; j < 3; ++j) H[i][j] += ua * g[a][j];
     }
   Kin<T> k;
-  const double V = double(d.vol);
+  const double V = double(Vt);
   Coef cf;
   T Ff[3], f[3];
   if (OP == OP_JV) {
@@ -633,8 +648,9 @@ __global__ __launch_bounds__(NTB) void k_elem_block(ElemArgs<T> A) {
   const int NL = A.nl_max, C4 = 4 * A.be_max;
   T *uS = lds;                 // [3][NL]
   T *vS = lds + 3 * NL;        // [3][NL]      (Jv only)
-  T *cS = lds + 6 * NL;        // [3][4 BE]    contributions in slot-sorted order
-  double *rs = reinterpret_cast<double *>(lds + 6 * NL + 12 * A.be_max);  // reduction scratch
+  T *xS = lds + 6 * NL;        // [3][NL]      slot coordinates
+  T *cS = lds + 9 * NL;        // [3][4 BE]    contributions in slot-sorted order
+  double *rs = reinterpret_cast<double *>(lds + 9 * NL + 12 * A.be_max);  // reduction scratch
 
   // The inputs of this thread's first element are requested before the node
   // gather so all of these loads are in flight together.
@@ -656,9 +672,11 @@ __global__ __launch_bounds__(NTB) void k_elem_block(ElemArgs<T> A) {
     const uint32_t w = l == tid ? w0 : A.nodes[p0 + l];
     const int64_t g3 = 3 * int64_t(w & NODE_MASK);
     const uint32_t mk = (w >> 28) & 7u;
+    const int64_t s3 = 3 * int64_t(p0 + l);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       uS[i * NL + l] = A.u[g3 + i];
+      xS[i * NL + l] = A.xr[s3 + i];
       if (OP == OP_JV) vS[i * NL + l] = (!A.nomask && ((mk >> i) & 1u)) ? T(0) : A.v[g3 + i];
     }
   }
@@ -669,7 +687,7 @@ __global__ __launch_bounds__(NTB) void k_elem_block(ElemArgs<T> A) {
   double eacc = 0.0;
   auto run = [&](const ElemIn<T> &d) {
     T out[4][3];
-    element_forces<T, OP, MAT>(d, uS, vS, NL, mp, out, bad, eacc, A, d.ge);
+    element_forces<T, OP, MAT>(d, uS, vS, xS, NL, mp, out, bad, eacc, A, d.ge);
     if (OP != OP_ENERGY) {
       const int cp[4] = {lo16(d.lcp.z), hi16(d.lcp.z), lo16(d.lcp.w), hi16(d.lcp.w)};
 #pragma unroll
@@ -770,7 +788,7 @@ void launch_block(Ctx *c, ElemArgs<T> &A, size_t lds) {
 }
 
 template <typename T>
-int launch(Ctx *c, int op, const T *G, const T *V, const T *u, const T *v, T *out, double *red,
+int launch(Ctx *c, int op, const T *xr, const T *u, const T *v, T *out, double *red,
            hipError_t *err) {
   const Mesh &M = c->m;
   // surface loads (follower pressure, springs): their nodal contributions are
@@ -781,8 +799,7 @@ int launch(Ctx *c, int op, const T *G, const T *V, const T *u, const T *v, T *ou
     if (*err != hipSuccess) return 0;
   }
   ElemArgs<T> A;
-  A.G = G;
-  A.V = V;
+  A.xr = xr;
   A.lcp = M.lcp;
   A.csr_end = M.csr_end;
   A.nodes = M.nodes;
@@ -825,7 +842,7 @@ int launch(Ctx *c, int op, const T *G, const T *V, const T *u, const T *v, T *ou
   A.inst_s = c->inst_s;
   A.inst_mat = c->inst_mat;
   A.inst_done = c->inst_done;
-  size_t lds = size_t(6 * M.nl_max + 12 * M.be_max) * sizeof(T);
+  size_t lds = size_t(9 * M.nl_max + 12 * M.be_max) * sizeof(T);
   lds = (lds + 7) & ~size_t(7);
   lds += size_t(NTB / 64) * sizeof(double);  // reduction scratch after the arrays
   const int kind = c->mat.kind;
@@ -920,9 +937,9 @@ int elem_apply(Ctx *c, int op, int prec, const void *u, const void *v, void *out
   if (c->mixed) return mixed_apply(c, op, prec, u, v, out, red, err);
   const Mesh &M = c->m;
   if (prec == NLE_FP32)
-    return launch<float>(c, op, M.G32, M.V32, static_cast<const float *>(u),
+    return launch<float>(c, op, M.xr32, static_cast<const float *>(u),
                          static_cast<const float *>(v), static_cast<float *>(out), red, err);
-  return launch<double>(c, op, M.G64, M.V64, static_cast<const double *>(u),
+  return launch<double>(c, op, M.xr64, static_cast<const double *>(u),
                         static_cast<const double *>(v), static_cast<double *>(out), red, err);
 }
 

@@ -36,8 +36,9 @@ struct Mesh {
   int64_t n_nodes = 0, n_elems = 0;
   int32_t nblk = 0, be_max = 0, nl_max = 0;
   int64_t n_slots = 0, n_shared = 0, n_fx = 0;
-  double *G64 = nullptr; float *G32 = nullptr;  // [9][n_elems] grad N_1..3 rows
-  double *V64 = nullptr; float *V32 = nullptr;  // [n_elems]
+  // [n_slots][3] coordinates of each slot's node relative to the block's
+  // first slot (the element kernels form grad N and V from them)
+  double *xr64 = nullptr; float *xr32 = nullptr;
   uint4 *lcp = nullptr;   // [n_elems] 4 slot-local vertex ids, 4 slot-sorted positions (u16)
   uint16_t *csr_end = nullptr;                  // [n_slots] end of the slot's range
   uint32_t *nodes = nullptr;                    // [n_slots] id | mask<<28 | shared<<31

@@ -181,6 +181,20 @@ nle_status build_mesh(Ctx *c, int64_t nn, const double *X, int64_t ne, const int
   }
   blk_node[nblk] = int32_t(nodes.size());
   const int64_t n_slots = int64_t(nodes.size());
+  // slot coordinates relative to the block's first slot: small numbers, so
+  // their FP32 copy resolves element edges to ~1e-6 of the edge length
+  std::vector<double> xr64(3 * n_slots);
+  std::vector<float> xr32(3 * n_slots);
+  for (int32_t b = 0; b < nblk; ++b) {
+    const double *x0 = X + 3 * int64_t(nodes[blk_node[b]]);
+    for (int64_t p = blk_node[b]; p < blk_node[b + 1]; ++p) {
+      const double *x = X + 3 * int64_t(nodes[p]);
+      for (int i = 0; i < 3; ++i) {
+        xr64[3 * p + i] = x[i] - x0[i];
+        xr32[3 * p + i] = float(x[i] - x0[i]);
+      }
+    }
+  }
 
   // ---- shared nodes and their merge lists (slots in block order) -------------
   // With several instances each instance's shared nodes start on a whole
@@ -231,7 +245,7 @@ nle_status build_mesh(Ctx *c, int64_t nn, const double *X, int64_t ne, const int
 
   // ---- LDS budget ---------------------------------------------------------------
   // see the element kernel: nodal state, contributions, reduction scratch
-  const size_t lds64 = size_t(6 * nl_max + 12 * be_max) * 8 + 512 / 64 * 8;
+  const size_t lds64 = size_t(9 * nl_max + 12 * be_max) * 8 + 512 / 64 * 8;
   if (lds64 > c->lds_limit)
     return fail(c, NLE_E_UNSUPPORTED,
                 "element block needs " + std::to_string(lds64) + " B of LDS (limit " +
@@ -253,22 +267,9 @@ nle_status build_mesh(Ctx *c, int64_t nn, const double *X, int64_t ne, const int
   M.n_slots = n_slots;
   M.n_shared = n_sh;
   M.n_fx = int64_t(fx_slot.size());
-  std::vector<double> Gp(9 * ne), Vp(ne);
-  std::vector<float> G32(9 * ne), V32(ne);
-  for (int64_t k = 0; k < ne; ++k) {
-    const int64_t e = perm[k];
-    for (int q = 0; q < 9; ++q) {
-      Gp[q * ne + k] = G[q * ne + e];
-      G32[q * ne + k] = float(G[q * ne + e]);
-    }
-    Vp[k] = V[e];
-    V32[k] = float(V[e]);
-  }
   hipError_t herr = hipSuccess;
-  M.G64 = upload(c, Gp, &herr);
-  M.G32 = upload(c, G32, &herr);
-  M.V64 = upload(c, Vp, &herr);
-  M.V32 = upload(c, V32, &herr);
+  M.xr64 = upload(c, xr64, &herr);
+  M.xr32 = upload(c, xr32, &herr);
   M.lcp = reinterpret_cast<uint4 *>(upload(c, lcp, &herr));
   M.csr_end = upload(c, csr_end, &herr);
   M.nodes = upload(c, nodes, &herr);

@@ -217,7 +217,7 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
       std::vector<uint64_t> key = {1, uint64_t(prec), uint64_t(n), uint64_t(check),
                                    uint64_t(uintptr_t(x)), uint64_t(uintptr_t(a.r)),
                                    uint64_t(uintptr_t(dinv)), uint64_t(uintptr_t(ulin)),
-                                   uint64_t(uintptr_t(c->red)), uint64_t(uintptr_t(c->m.G32)),
+                                   uint64_t(uintptr_t(c->red)), uint64_t(uintptr_t(c->m.xr32)),
                                    uint64_t(uintptr_t(c->m.nodes)), uint64_t(c->mat.kind),
                                    uint64_t(uintptr_t(c->mx.G32)), uint64_t(uintptr_t(c->mx.cu)),
                                    uint64_t(uintptr_t(c->lc_valid ? c->lc64 : nullptr)),
@@ -260,7 +260,7 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
       std::vector<uint64_t> key = {2, uint64_t(prec), uint64_t(n), uint64_t(check),
                                    uint64_t(uintptr_t(x)), uint64_t(uintptr_t(a.r1)),
                                    uint64_t(uintptr_t(dinv)), uint64_t(uintptr_t(ulin)),
-                                   uint64_t(uintptr_t(c->red)), uint64_t(uintptr_t(c->m.G32)),
+                                   uint64_t(uintptr_t(c->red)), uint64_t(uintptr_t(c->m.xr32)),
                                    uint64_t(uintptr_t(c->m.nodes)), uint64_t(c->mat.kind),
                                    uint64_t(uintptr_t(c->mx.G32)), uint64_t(uintptr_t(c->mx.cu)),
                                    uint64_t(uintptr_t(c->lc_valid ? c->lc64 : nullptr)),
