@@ -60,6 +60,12 @@ struct ElemArgs {
   const double *inst_s;
   const double *inst_mat;
   const int32_t *inst_done;
+  // CG direction formed here (Jv only, see Ctx::cg): v = vz + beta * v
+  const T *vz;
+  const double *cg_red;
+  int32_t cg_np;
+  double *cg_scal;
+  int32_t *cg_flag;
 };
 
 template <typename T>
@@ -82,6 +88,8 @@ struct MergeArgs {
   const int32_t *mwg_inst;  // batched mode: instance of each merge workgroup
   const double *inst_s;
   const int32_t *inst_done;
+  const T *vz;              // CG direction v = vz + beta * v, beta = cg_scal[BETA]
+  const double *cg_scal;
 };
 
 __device__ __forceinline__ int block_id(int nblk, int per_xcd) {
@@ -100,6 +108,23 @@ __device__ __forceinline__ T wave_sum(T v) {
 // Threads per workgroup of the element-block kernel: one element per thread
 // at the default block size, so the LDS a block needs carries eight waves.
 constexpr int NTB = 512;
+
+// Sum of red[0..np) in the order of the vector kernels' fixed-order sum
+// (256 threads, strided, then the four wave sums in order), so the value is
+// bitwise the one those kernels form; broadcast to all threads.  sh: 8 doubles.
+__device__ __forceinline__ double sum_partials_256(const double *red, int np, double *sh) {
+  double v = 0.0;
+  if (threadIdx.x < 256)
+    for (int k = threadIdx.x; k < np; k += 256) v += red[k];
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = sh[0];
+  for (int k = 1; k < 4; ++k) r += sh[k];
+  return r;
+}
 
 // Fixed-order workgroup sum over NTH threads; the result is valid in thread 0.
 template <int NTH, typename T>
@@ -251,6 +276,7 @@ __device__ __forceinline__ double energy_density(const Kin<T> &k, const T H[3][3
 // fs (nullable) holds the surface-load contributions of the same operation.
 template <typename T, int OP>
 __device__ __forceinline__ void finalize_node(uint32_t g, uint32_t mk, const T acc[3], const T *v,
+                                              const T *vz, T bt,
                                               T *out, const double *fext, double s,
                                               double &nrm, const T *epw, T epc, const T *fs,
                                               int nomask) {
@@ -264,7 +290,7 @@ __device__ __forceinline__ void finalize_node(uint32_t g, uint32_t mk, const T a
       out[d] = T(r);
       nrm += r * r;
     } else if (OP == OP_JV) {
-      const T vd = v[d];
+      const T vd = vz ? vz[d] + bt * v[d] : v[d];
       T y = fixed ? (nomask ? T(0) : vd) : a;
       if (epw) y -= epc * epw[d];
       out[d] = y;
@@ -658,18 +684,70 @@ __global__ __launch_bounds__(NTB) void k_elem_block(ElemArgs<T> A) {
   if (tid < ne) load_elem<MAT>(A, uint32_t(e0 + tid), ea);
 
   // Phase 1: gather nodal state (and direction) of the block.  The first slot
-  // of each thread also has its phase-3 data (word, range, partial position)
-  // requested here and kept in registers.
+  // of each thread is requested into registers together with its phase-3
+  // data (word, range, partial position), which stay in registers.
   uint32_t w0 = 0;
   int beg0 = 0, end0 = 0, mp0 = -1;
+  T u1[3] = {T(0), T(0), T(0)}, x1[3] = {T(0), T(0), T(0)};
+  T v1[3] = {T(0), T(0), T(0)}, z1[3] = {T(0), T(0), T(0)};
   if (tid < nl) {
     w0 = A.nodes[p0 + tid];
     end0 = A.csr_end[p0 + tid];
     beg0 = tid == 0 ? 0 : int(A.csr_end[p0 + tid - 1]);
     if (OP != OP_ENERGY && (w0 & 0x80000000u)) mp0 = A.mpos[p0 + tid];
+    const int64_t g3 = 3 * int64_t(w0 & NODE_MASK), s3 = 3 * int64_t(p0 + tid);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      u1[i] = A.u[g3 + i];
+      x1[i] = A.xr[s3 + i];
+      if (OP == OP_JV) {
+        v1[i] = A.v[g3 + i];
+        if (A.vz) z1[i] = A.vz[g3 + i];
+      }
+    }
   }
-  for (int l = tid; l < nl; l += NTB) {
-    const uint32_t w = l == tid ? w0 : A.nodes[p0 + l];
+
+  // CG direction formed here (v = z + beta p): beta and the stopping test
+  // from the previous update's partials, taken identically by every
+  // workgroup while the slot loads above are in flight; block 0 records them
+  // (the update kernel of this iteration reads r.z and beta)
+  T bt = T(0);
+  if (OP == OP_JV && A.vz) {
+    const double rz = sum_partials_256(A.cg_red, A.cg_np, rs);
+    const double rr = sum_partials_256(A.cg_red + VGRID_MAX, A.cg_np, rs);
+    const double rzo = A.cg_scal[cgslot::RZOLD];
+    int stop = 0;
+    if (!(rr == rr))
+      stop = 3;
+    else if (rr <= A.cg_scal[cgslot::TOL2])
+      stop = 1;
+    else if (double(A.cg_flag[1]) >= A.cg_scal[cgslot::MAXIT])
+      stop = 5;
+    const double beta = rzo > 0.0 ? rz / rzo : 0.0;
+    if (b == 0 && tid == 0) {
+      A.cg_scal[cgslot::RZ] = rz;
+      A.cg_scal[cgslot::RR] = rr;
+      A.cg_scal[cgslot::BETA] = beta;
+      if (stop) A.cg_flag[0] = stop;
+    }
+    if (stop) return;
+    bt = T(beta);
+  }
+
+  if (tid < nl) {
+    const uint32_t mk = (w0 >> 28) & 7u;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      uS[i * NL + tid] = u1[i];
+      xS[i * NL + tid] = x1[i];
+      if (OP == OP_JV) {
+        const T vd = A.vz ? z1[i] + bt * v1[i] : v1[i];
+        vS[i * NL + tid] = (!A.nomask && ((mk >> i) & 1u)) ? T(0) : vd;
+      }
+    }
+  }
+  for (int l = tid + NTB; l < nl; l += NTB) {
+    const uint32_t w = A.nodes[p0 + l];
     const int64_t g3 = 3 * int64_t(w & NODE_MASK);
     const uint32_t mk = (w >> 28) & 7u;
     const int64_t s3 = 3 * int64_t(p0 + l);
@@ -677,7 +755,10 @@ __global__ __launch_bounds__(NTB) void k_elem_block(ElemArgs<T> A) {
     for (int i = 0; i < 3; ++i) {
       uS[i * NL + l] = A.u[g3 + i];
       xS[i * NL + l] = A.xr[s3 + i];
-      if (OP == OP_JV) vS[i * NL + l] = (!A.nomask && ((mk >> i) & 1u)) ? T(0) : A.v[g3 + i];
+      if (OP == OP_JV) {
+        const T vd = A.vz ? A.vz[g3 + i] + bt * A.v[g3 + i] : A.v[g3 + i];
+        vS[i * NL + l] = (!A.nomask && ((mk >> i) & 1u)) ? T(0) : vd;
+      }
     }
   }
   __syncthreads();
@@ -729,7 +810,8 @@ __global__ __launch_bounds__(NTB) void k_elem_block(ElemArgs<T> A) {
       pp[1] = acc[1];
       pp[2] = acc[2];
     } else {
-      finalize_node<T, OP>(w & NODE_MASK, (w >> 28) & 7u, acc, A.v, A.out, A.fext, lscale, nrm,
+      finalize_node<T, OP>(w & NODE_MASK, (w >> 28) & 7u, acc, A.v, A.vz, bt, A.out, A.fext,
+                           lscale, nrm,
                            A.ep_w, epc, A.fs, A.nomask);
     }
   }
@@ -771,7 +853,8 @@ __global__ __launch_bounds__(NT) void k_elem_merge(MergeArgs<T> A) {
         }
     }
     const uint32_t w = A.fx_node[k];
-    finalize_node<T, OP>(w & NODE_MASK, (w >> 28) & 7u, acc, A.v, A.out, A.fext, lscale, nrm,
+    finalize_node<T, OP>(w & NODE_MASK, (w >> 28) & 7u, acc, A.v, A.vz,
+                         A.vz ? T(A.cg_scal[cgslot::BETA]) : T(0), A.out, A.fext, lscale, nrm,
                          A.ep_w, A.ep_coef ? T(A.ep_coef[0]) : T(0), A.fs, A.nomask);
   }
   if (OP == OP_RES || (OP == OP_JV && A.ep_red)) {
@@ -842,6 +925,11 @@ int launch(Ctx *c, int op, const T *xr, const T *u, const T *v, T *out, double *
   A.inst_s = c->inst_s;
   A.inst_mat = c->inst_mat;
   A.inst_done = c->inst_done;
+  A.vz = op == OP_JV ? static_cast<const T *>(c->cg.z) : nullptr;
+  A.cg_red = c->cg.red;
+  A.cg_np = c->cg.np;
+  A.cg_scal = c->cg.scal;
+  A.cg_flag = c->cg.flag;
   size_t lds = size_t(9 * M.nl_max + 12 * M.be_max) * sizeof(T);
   lds = (lds + 7) & ~size_t(7);
   lds += size_t(NTB / 64) * sizeof(double);  // reduction scratch after the arrays
@@ -900,6 +988,8 @@ int launch(Ctx *c, int op, const T *xr, const T *u, const T *v, T *out, double *
     B.ep_coef = c->ep.coef;
     B.ep_red = (op == OP_JV && c->ep.red) ? c->ep.red + M.nblk : nullptr;
     B.fs = A.fs;
+    B.vz = A.vz;
+    B.cg_scal = c->cg.scal;
     const int g2 = int((M.n_shared + NT - 1) / NT);
     switch (op) {
       case OP_RES:

@@ -15,6 +15,12 @@ constexpr int NT = 256;            // threads per workgroup (four wave64)
 constexpr int VGRID_MAX = 1024;    // workgroups of the streaming vector kernels
 constexpr uint32_t NODE_MASK = 0x0FFFFFFFu;  // node id bits of a block-node word
 
+// Device scalar slots of the CG loop (shared by the vector kernels and the
+// element kernels that form the CG direction).
+namespace cgslot {
+enum { RZ = 0, RZOLD = 1, TOL2 = 2, RR = 3, B2 = 4, MAXIT = 5, BETA = 6 };
+}
+
 // Element kernel operations.
 // OP_ODIAG: the off-diagonal entries (xy, yz, xz) of each node's diagonal
 // 3x3 tangent block (FP64, P1 meshes only).
@@ -181,6 +187,18 @@ struct Ctx {
   double *dscal = nullptr;   // device scalars
   int32_t *dflag = nullptr;  // device flags: [0] inverted element
   const int32_t *elem_skip = nullptr;  // Krylov done flag seen by element kernels
+  // CG with the direction formed inside the Jacobian action (three launches
+  // per iteration): when cg.z is set, the element kernels use the direction
+  // v = z + beta p (p = their v argument), where every element workgroup
+  // forms beta = (r.z) / scal[S_RZOLD] and the stopping test from the
+  // previous update's partials (red: r.z at [0, np), r.r at [VGRID_MAX, ...))
+  struct {
+    const void *z = nullptr;
+    const double *red = nullptr;
+    int np = 0;
+    double *scal = nullptr;
+    int32_t *flag = nullptr;
+  } cg;
   // Jacobian action with the Dirichlet columns kept and the Dirichlet rows
   // zero: y = (K w) on free rows, the coupling a change of prescribed values
   // induces (used by the step that carries such a change into the interior)
@@ -310,7 +328,7 @@ struct CgArgs {
   int32_t *flag;      // [0] state (1 converged, 2 breakdown, 3 NaN, 5 limit), [1] its
 };
 hipError_t cg_start(Ctx *c, const CgArgs &a, const void *b, double rtol, double atol, int max_it);
-hipError_t cg_update(Ctx *c, const CgArgs &a);
+hipError_t cg_update(Ctx *c, const CgArgs &a, bool fused = false);
 hipError_t cg_direction(Ctx *c, const CgArgs &a);
 
 // MINRES kernels

@@ -68,6 +68,7 @@ nle_status ensure_ws(Ctx *c, size_t bytes) {
 struct KspOpts {
   int type, orth, pc, restart, max_it, check_every;
   double rtol, atol;
+  int cg_launches;
 };
 
 struct KspResult {
@@ -179,6 +180,7 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
       hipStream_t user;
       ~Restore() {
         c->elem_skip = nullptr;
+        c->cg.z = nullptr;
         c->ep.w = nullptr;
         c->ep.coef = nullptr;
         c->ep.red = nullptr;
@@ -206,12 +208,25 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
       NLE_HIP(c, cg_start(c, a, b, o.rtol, o.atol, o.max_it));
       c->elem_skip = flag;
       c->ep.red = red_a;
+      // three launches per iteration (the next direction and the stopping
+      // test formed inside the Jacobian action) on request, where the element
+      // kernels support it; four otherwise.  On the 64x64x4 Cook mesh both
+      // take ~20 us per iteration: the fused form saves a launch but adds the
+      // partial sums to the Jacobian action's critical path.
+      const bool fuse = !c->mixed && c->surf.nsn == 0 && o.cg_launches == 3;
+      if (fuse) {
+        c->cg.z = a.z;
+        c->cg.red = red_b;
+        c->cg.np = vgrid(n);
+        c->cg.scal = c->dscal;
+        c->cg.flag = flag;
+      }
       auto iter = [&]() -> hipError_t {
         hipError_t err;
         a.np_a = elem_apply(c, OP_JV, prec, ulin, a.p, a.Ap, nullptr, &err);
         if (err != hipSuccess) return err;
-        err = cg_update(c, a);
-        if (err != hipSuccess) return err;
+        err = cg_update(c, a, fuse);
+        if (err != hipSuccess || fuse) return err;
         return cg_direction(c, a);
       };
       std::vector<uint64_t> key = {1, uint64_t(prec), uint64_t(n), uint64_t(check),
@@ -221,7 +236,7 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
                                    uint64_t(uintptr_t(c->m.nodes)), uint64_t(c->mat.kind),
                                    uint64_t(uintptr_t(c->mx.G32)), uint64_t(uintptr_t(c->mx.cu)),
                                    uint64_t(uintptr_t(c->lc_valid ? c->lc64 : nullptr)),
-                                   uint64_t(pcb)};
+                                   uint64_t(pcb), uint64_t(fuse)};
       st = run_chunks(c, key, check, o.max_it, flag, iter);
     } else {
       MinresArgs a;
@@ -440,6 +455,8 @@ nle_status check_ready(Ctx *c, double *u, const nle_solver_opts *o) {
   if (o->pc == NLE_PC_BJACOBI3 && c->mixed)
     return fail(c, NLE_E_UNSUPPORTED, "nodal block Jacobi needs a P1 mesh");
   if (o->ksp_max_it < 1 || o->snes_max_it < 0) return fail(c, NLE_E_INVAL, "bad iteration limits");
+  if (o->cg_launches != 0 && o->cg_launches != 3 && o->cg_launches != 4)
+    return fail(c, NLE_E_INVAL, "bad cg_launches");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, NLE_E_HIP, "hipSetDevice failed");
   return NLE_OK;
 }
@@ -524,7 +541,7 @@ nle_status newton(Ctx *c, double *u, const nle_solver_opts &o, nle_report *repor
   const int prec = o.precision == NLE_PREC_MIXED ? NLE_FP32 : NLE_FP64;
   const int64_t n = ndof(c);
   KspOpts ko{o.ksp_type, o.orth, o.pc, o.restart, o.ksp_max_it, std::max(1, o.check_every),
-             o.ksp_rtol, o.ksp_atol};
+             o.ksp_rtol, o.ksp_atol, o.cg_launches};
   const size_t vb64 = (size_t(n) * 8 + 255) & ~size_t(255);
   const size_t vbp = (size_t(n) * esz(prec) + 255) & ~size_t(255);
   nle_status s = ensure_ws(c, 2 * vb64 + 3 * vbp + ksp_bytes(ko, n, prec));
@@ -639,7 +656,7 @@ nle_status bfgs(Ctx *c, double *u, const nle_solver_opts &o, nle_report *report)
   const int64_t n = ndof(c);
   const int m = std::max(1, o.qn_m);
   KspOpts ko{o.ksp_type, o.orth, o.pc, o.restart, o.ksp_max_it, std::max(1, o.check_every),
-             o.h0_rtol, o.h0_atol};
+             o.h0_rtol, o.h0_atol, o.cg_launches};
   const size_t vb64 = (size_t(n) * 8 + 255) & ~size_t(255);
   const size_t vbp = (size_t(n) * esz(prec) + 255) & ~size_t(255);
   size_t need = 3 * vb64 + size_t(2 * m + 5) * vbp + 8 * size_t(m + 8) + 4096;

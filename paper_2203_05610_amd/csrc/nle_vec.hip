@@ -109,7 +109,8 @@ __global__ __launch_bounds__(NT) void k_reduce(const double *red, int np, int st
 //   flag[0]: 0 running, 1 converged, 2 breakdown, 3 NaN, 5 iteration limit
 //   flag[1]: completed iterations
 enum {
-  S_RZ = 0, S_RZOLD = 1, S_TOL2 = 2, S_RR = 3, S_B2 = 4, S_MAXIT = 5,
+  S_RZ = cgslot::RZ, S_RZOLD = cgslot::RZOLD, S_TOL2 = cgslot::TOL2, S_RR = cgslot::RR,
+  S_B2 = cgslot::B2, S_MAXIT = cgslot::MAXIT, S_BETA = cgslot::BETA,
   // MINRES
   M_BETA = 8, M_OLDB = 9, M_ALFA = 10, M_CS = 11, M_SN = 12, M_DBAR = 13, M_EPS = 14,
   M_OLDEPS = 15, M_DELTA = 16, M_PHI = 17, M_PHIBAR = 18, M_DENOM = 19, M_COEF = 20,
@@ -219,6 +220,8 @@ __global__ __launch_bounds__(NT) void k_cg_start2(const double *red, int np, dou
   if (threadIdx.x == 0) {
     const double tol2 = fmax(rtol * rtol * rr, atol * atol);
     scal[S_RZ] = rz;
+    scal[S_RZOLD] = 0.0;  // the first direction is z itself (beta = 0)
+    scal[S_BETA] = 0.0;
     scal[S_TOL2] = tol2;
     scal[S_RR] = rr;
     scal[S_B2] = rr;
@@ -230,8 +233,11 @@ __global__ __launch_bounds__(NT) void k_cg_start2(const double *red, int np, dou
 
 // alpha = rz / p.Ap;  x += alpha p;  r -= alpha Ap;  z = M^-1 r; partials of
 // r.z and r.r.  p.Ap partials come from the Jacobian-action epilogue.
-template <typename T, int BS>
-__global__ __launch_bounds__(NT) void k_cg_update(T *x, T *r, T *z, const T *p, const T *Ap,
+// FUSED: the direction of this iteration is formed here as p = z + beta p
+// (beta = scal[S_BETA], written by the Jacobian action that used the same
+// direction) and the iteration count advances here (no direction kernel).
+template <typename T, int BS, bool FUSED>
+__global__ __launch_bounds__(NT) void k_cg_update(T *x, T *r, T *z, T *p, const T *Ap,
                                                   const T *dinv, int64_t n, const double *red_a,
                                                   int np_a, double *red_b, double *scal,
                                                   int32_t *flag) {
@@ -245,8 +251,12 @@ __global__ __launch_bounds__(NT) void k_cg_update(T *x, T *r, T *z, const T *p, 
   }
   const double rz = scal[S_RZ];
   const double alpha = rz / pAp;
-  if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_RZOLD] = rz;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    scal[S_RZOLD] = rz;
+    if (FUSED) flag[1] = flag[1] + 1;
+  }
   const T a = T(alpha);
+  const T bt = FUSED ? T(scal[S_BETA]) : T(0);
   T arz = T(0), arr = T(0);
   const int64_t nu = n / BS;
   UNIT_LOOP(k, nu) {
@@ -255,7 +265,13 @@ __global__ __launch_bounds__(NT) void k_cg_update(T *x, T *r, T *z, const T *p, 
     for (int c = 0; c < BS; ++c) {
       const int64_t i = BS * k + c;
       ri[c] = r[i] - a * Ap[i];
-      x[i] += a * p[i];
+      if (FUSED) {
+        const T pn = z[i] + bt * p[i];
+        p[i] = pn;
+        x[i] += a * pn;
+      } else {
+        x[i] += a * p[i];
+      }
       r[i] = ri[c];
     }
     pc_unit<BS>(dinv, k, nu, ri, zi);
@@ -866,17 +882,20 @@ hipError_t cg_start(Ctx *c, const CgArgs &a, const void *b, double rtol, double 
   return hipGetLastError();
 }
 
-hipError_t cg_update(Ctx *c, const CgArgs &a) {
+hipError_t cg_update(Ctx *c, const CgArgs &a, bool fused) {
   const int g = vgrid(a.n);
-#define CG_UPD(T, BS)                                                                          \
-  LAUNCH((k_cg_update<T, BS>), g, static_cast<T *>(a.x), static_cast<T *>(a.r),                 \
-         static_cast<T *>(a.z), static_cast<const T *>(a.p), static_cast<const T *>(a.Ap),      \
+#define CG_UPD(T, BS, F)                                                                       \
+  LAUNCH((k_cg_update<T, BS, F>), g, static_cast<T *>(a.x), static_cast<T *>(a.r),              \
+         static_cast<T *>(a.z), static_cast<T *>(a.p), static_cast<const T *>(a.Ap),            \
          static_cast<const T *>(a.dinv), a.n, a.red_a, a.np_a, a.red_b, a.scal, a.flag)
+#define CG_UPD2(T, BS)                                                                         \
+  if (fused) CG_UPD(T, BS, true); else CG_UPD(T, BS, false)
   if (a.prec == NLE_FP32) {
-    if (a.pcb == 3) CG_UPD(float, 3); else CG_UPD(float, 1);
+    if (a.pcb == 3) CG_UPD2(float, 3); else CG_UPD2(float, 1);
   } else {
-    if (a.pcb == 3) CG_UPD(double, 3); else CG_UPD(double, 1);
+    if (a.pcb == 3) CG_UPD2(double, 3); else CG_UPD2(double, 1);
   }
+#undef CG_UPD2
 #undef CG_UPD
   return hipGetLastError();
 }

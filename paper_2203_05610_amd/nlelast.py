@@ -67,7 +67,7 @@ class nle_allocator(ctypes.Structure):
 class nle_solver_opts(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "precision", "ksp_type", "orth", "pc", "restart", "ksp_max_it", "snes_max_it",
-        "ew_version", "qn_m", "h0", "check_every", "reserved")] + [
+        "ew_version", "qn_m", "h0", "check_every", "cg_launches")] + [
         (n, ctypes.c_double) for n in (
             "ksp_rtol", "ksp_atol", "ew_rtol0", "ew_rtolmax", "ew_rtolmin", "ew_gamma",
             "ew_alpha", "ew_alpha2", "ew_threshold", "ink_ksp_atol", "snes_rtol", "snes_atol",

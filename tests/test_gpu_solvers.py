@@ -213,3 +213,26 @@ def test_nan_state_is_reported():
     u[100] = float("nan")
     st, rep = nl.nle_solve_nk(ctx, u, problems.make_opts("nk"))
     assert st in (nl.NLE_DIVERGED_NAN, nl.NLE_DIVERGED_INVERTED)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("pc", ["jacobi", "bjacobi3"])
+def test_cg_three_and_four_launch_forms_are_bitwise_equal(precision, pc):
+    # forming the next CG direction inside the Jacobian action (3 launches per
+    # iteration) takes the same operations in the same order as the separate
+    # direction kernel (4 launches): same iterates, bit for bit
+    mesh, P, ctx = _cook(12, 12, 2, 50.0, be=128, tau=2.0)
+    out = {}
+    for launches in (3, 4):
+        u = torch.zeros(P.n_dofs, dtype=torch.float64, device="cuda")
+        o = problems.make_opts("ink", precision, ksp="cg", pc=pc, cg_launches=launches)
+        st, rep = nl.nle_solve_ink(ctx, u, o)
+        assert st == nl.NLE_OK, rep
+        out[launches] = (u.cpu().numpy(), rep["lit_hist"], rep["rnorm_hist"])
+    assert np.array_equal(out[3][0], out[4][0])
+    assert out[3][1] == out[4][1]
+    assert out[3][2] == out[4][2]
+    bad = problems.make_opts("ink", precision, cg_launches=5)
+    with pytest.raises(nl.NleError) as e:
+        nl.nle_solve_ink(ctx, torch.zeros(P.n_dofs, dtype=torch.float64, device="cuda"), bad)
+    assert e.value.status == nl.NLE_E_INVAL
