@@ -45,6 +45,12 @@ METHODS = {
     "bfgs_ib_fp64": ("bfgs", "fp64", {"h0": "ksp", "qn_m": 10, "ksp": "cg"}),
     "bfgs_ib_mixed": ("bfgs", "mixed", {"h0": "ksp", "qn_m": 10, "ksp": "cg"}),
     "bfgs_b_mixed": ("bfgs", "mixed", {"h0": "preonly", "qn_m": 10}),
+    # BFGS with the Jacobian reassembled every 20 iterations (an extension the
+    # paper's conclusions name); MINRES for the H0 solves, since the tangent
+    # turns indefinite at large load
+    "bfgs_ib_mixed_r20": ("bfgs", "mixed", {"h0": "ksp", "qn_m": 10, "ksp": "minres",
+                                            "h0_refresh": 20}),
+    "bfgs_ib_mixed_minres": ("bfgs", "mixed", {"h0": "ksp", "qn_m": 10, "ksp": "minres"}),
 }
 
 

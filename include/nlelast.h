@@ -138,6 +138,11 @@ typedef struct {
   double snes_rtol, snes_atol;      /* ||r_k|| <= max(rtol ||r_0||, atol) */
   double h0_rtol, h0_atol;          /* inexact BFGS H0 solve: 1e-2, 1e-14 */
   double curvature_eps;             /* skip pair if s.y <= eps |s||y|     */
+  int32_t h0_refresh; /* BFGS: every h0_refresh iterations re-linearize at
+                         the current iterate (new tangent, preconditioner
+                         and H0) and drop the stored pairs; 0 = once per
+                         solve, the single assembly of Sec. 3            */
+  int32_t reserved;
 } nle_solver_opts;
 
 /* Solve report.  Histories are written to caller buffers of hist_cap

@@ -291,11 +291,16 @@ def newton_krylov(residual: Callable, linearize: Callable, u0: np.ndarray, *,
 
 def lbfgs(residual: Callable, h0: Callable, u0: np.ndarray, *, m: int = 10,
           rtol: float = 1e-8, atol: float = 0.0, max_it: int = 1000,
-          curvature_eps: float = 1e-12):
+          curvature_eps: float = 1e-12, refresh: int = 0,
+          relinearize: Optional[Callable] = None):
     """L-BFGS root finder on g = r(u) with full steps (p = -H g, u += p).
 
     h0 is the initial inverse-Hessian action (built by the caller once, at
     the first iterate).  A pair (s, y) with s.y <= eps ||s|| ||y|| is skipped.
+    With refresh > 0, every `refresh` iterations the initial inverse Hessian
+    is rebuilt at the current iterate (h0 = relinearize(u)) and the stored
+    pairs are dropped: the occasional Jacobian reassembly for BFGS that the
+    paper's conclusions (Sec. 6) name as an extension.
     """
     u = np.array(u0, dtype=np.float64, copy=True)
     g = residual(u)
@@ -305,6 +310,9 @@ def lbfgs(residual: Callable, h0: Callable, u0: np.ndarray, *, m: int = 10,
     skipped = 0
     k = 0
     while rn[-1] > max(rtol * r0, atol) and k < max_it:
+        if refresh > 0 and k > 0 and k % refresh == 0:
+            h0 = relinearize(u)
+            pairs = []
         p = -two_loop(g, pairs, h0)
         u = u + p
         g_new = residual(u)

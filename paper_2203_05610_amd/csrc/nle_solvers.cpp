@@ -457,6 +457,7 @@ nle_status check_ready(Ctx *c, double *u, const nle_solver_opts *o) {
   if (o->ksp_max_it < 1 || o->snes_max_it < 0) return fail(c, NLE_E_INVAL, "bad iteration limits");
   if (o->cg_launches != 0 && o->cg_launches != 3 && o->cg_launches != 4)
     return fail(c, NLE_E_INVAL, "bad cg_launches");
+  if (o->h0_refresh < 0) return fail(c, NLE_E_INVAL, "bad h0_refresh");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, NLE_E_HIP, "hipSetDevice failed");
   return NLE_OK;
 }
@@ -735,6 +736,20 @@ nle_status bfgs(Ctx *c, double *u, const nle_solver_opts &o, nle_report *report)
     if (k >= o.snes_max_it) {
       rep.hist(k, rn, 0.0, 0);
       break;
+    }
+    if (o.h0_refresh > 0 && k > 0 && k % o.h0_refresh == 0) {
+      // periodic reassembly: tangent, preconditioner and H0 at the current
+      // iterate; the stored pairs refer to the old H0 and are dropped
+      s = linearize(c, u, prec);
+      if (s != NLE_OK) return s;
+      if (blk && o.h0 != NLE_H0_KSP) {
+        s = ensure_block(c);
+        if (s != NLE_OK) return s;
+      }
+      while (!pairs.empty()) {
+        free_slots.push_back(pairs.back());
+        pairs.pop_back();
+      }
     }
     // q = g / ||g||
     NLE_HIP(c, vec_cast_scale(c, NLE_FP64, g, prec, q, 1.0 / rn, n));

@@ -43,10 +43,32 @@ def test_version_and_default_options():
     assert b.snes_max_it == 1000
 
 
-def test_opts_struct_layout_matches_header():
-    # 12 int32 fields then 15 doubles
-    assert ctypes.sizeof(nl.nle_solver_opts) == 12 * 4 + 15 * 8
-    assert nl.nle_report.rnorm_hist.offset % 8 == 0
+def test_opts_struct_layout_matches_header(tmp_path):
+    # the binding's structs against the C compiler's layout of the header
+    import shutil
+    import subprocess
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    fields = [f[0] for f in nl.nle_solver_opts._fields_]
+    rfields = [f[0] for f in nl.nle_report._fields_]
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "nlelast.h"', "int main(void) {",
+           'printf("%zu\\n", sizeof(nle_solver_opts));']
+    src += [f'printf("%zu\\n", offsetof(nle_solver_opts, {f}));' for f in fields]
+    src += ['printf("%zu\\n", sizeof(nle_report));']
+    src += [f'printf("%zu\\n", offsetof(nle_report, {f}));' for f in rfields]
+    src += ["return 0; }"]
+    (tmp_path / "layout.c").write_text("\n".join(src) + "\n")
+    exe = str(tmp_path / "layout")
+    subprocess.run([cc, "-I", inc, str(tmp_path / "layout.c"), "-o", exe], check=True)
+    vals = [int(x) for x in subprocess.run([exe], check=True, capture_output=True,
+                                           text=True).stdout.split()]
+    want = [ctypes.sizeof(nl.nle_solver_opts)]
+    want += [getattr(nl.nle_solver_opts, f).offset for f in fields]
+    want += [ctypes.sizeof(nl.nle_report)] + [getattr(nl.nle_report, f).offset for f in rfields]
+    assert vals == want
 
 
 def test_null_and_bad_arguments_are_rejected_without_a_device():

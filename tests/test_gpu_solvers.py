@@ -178,6 +178,40 @@ def test_bfgs_preonly_follows_oracle_lbfgs(m):
         assert err <= 1e-6, (prec, err)
 
 
+def test_bfgs_h0_refresh_follows_oracle_lbfgs():
+    # periodic reassembly (every 4 iterations): H0 = inverse tangent diagonal
+    # at the current iterate and the pairs dropped, the same on the CPU
+    mesh, P, ctx = _cook(4, 4, 1, 5.0, be=64, tau=0.5)
+    d0 = P.diagonal(np.zeros(P.n_dofs))
+    n_cmp = 14
+    relin = lambda u: (lambda q, d=P.diagonal(u): q / d)
+    ref = solvers.lbfgs(lambda u: P.residual(u), lambda q: q / d0, np.zeros(P.n_dofs), m=10,
+                        max_it=n_cmp, refresh=4, relinearize=relin)
+    u = torch.zeros(P.n_dofs, dtype=torch.float64, device="cuda")
+    o = problems.make_opts("bfgs", h0="preonly", qn_m=10, h0_refresh=4)
+    o.snes_max_it = n_cmp
+    st, rep = nl.nle_solve_bfgs(ctx, u, o)
+    assert rep["nit"] == min(n_cmp, ref["nit"])
+    h = np.array(rep["rnorm_hist"][: rep["nit"] + 1])
+    assert np.allclose(h, ref["rnorm"][: rep["nit"] + 1], rtol=1e-7)
+    # without refresh the histories differ after the first reassembly point
+    ref0 = solvers.lbfgs(lambda u: P.residual(u), lambda q: q / d0, np.zeros(P.n_dofs), m=10,
+                         max_it=n_cmp)
+    assert not np.allclose(ref0["rnorm"][5:8], ref["rnorm"][5:8], rtol=1e-7)
+    # inexact BFGS with reassembly reaches the oracle root
+    ustar = newton.newton_exact(P, np.zeros(P.n_dofs), 1.0)[0]
+    for prec in ("fp64", "mixed"):
+        u.zero_()
+        st, rep = nl.nle_solve_bfgs(ctx, u, problems.make_opts("bfgs", prec, h0="ksp", qn_m=10,
+                                                                 h0_refresh=3))
+        assert st == nl.NLE_OK, rep["nit"]
+        err = np.linalg.norm(u.cpu().numpy() - ustar) / np.linalg.norm(ustar)
+        assert err <= 1e-6, (prec, err)
+    with pytest.raises(nl.NleError) as e:
+        nl.nle_solve_bfgs(ctx, u, problems.make_opts("bfgs", h0_refresh=-1))
+    assert e.value.status == nl.NLE_E_INVAL
+
+
 def test_load_schedule_and_zero_load():
     mesh, P, ctx = _cook(8, 8, 2, 20.0, be=128)
     scales = [0.5, 1.0, 2.0]

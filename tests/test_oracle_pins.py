@@ -403,3 +403,26 @@ def test_inexact_newton_and_bfgs_reach_exact_root():
     res = solvers.lbfgs(lambda u: P.residual(u), lu.solve, np.zeros(P.n_dofs), m=10, rtol=1e-10)
     assert res["converged"]
     assert np.linalg.norm(res["u"] - ustar) <= 1e-7 * np.linalg.norm(ustar)
+
+
+def test_lbfgs_refresh_rebuilds_h0_and_drops_pairs():
+    # on a quadratic g = A u - b with an exact relinearization (H0 = A^-1),
+    # the first refreshed step lands on the root; without refresh and with a
+    # poor H0 the same iteration count does not
+    from oracle import solvers
+
+    rng = np.random.default_rng(2)
+    n = 12
+    Q = rng.standard_normal((n, n))
+    A = Q @ Q.T + n * np.eye(n)
+    b = rng.standard_normal(n)
+    ustar = np.linalg.solve(A, b)
+    res = lambda u: A @ u - b
+    poor = lambda q: q / (4.0 * np.diag(A))
+    exact = lambda u: (lambda q: np.linalg.solve(A, q))
+    r = solvers.lbfgs(res, poor, np.zeros(n), m=3, max_it=3, refresh=2, relinearize=exact,
+                      rtol=1e-14)
+    assert np.linalg.norm(r["u"] - ustar) <= 1e-10 * np.linalg.norm(ustar)
+    assert r["nit"] == 3
+    r0 = solvers.lbfgs(res, poor, np.zeros(n), m=3, max_it=3, rtol=1e-14)
+    assert np.linalg.norm(r0["u"] - ustar) > 1e-6 * np.linalg.norm(ustar)
