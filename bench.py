@@ -372,7 +372,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--method", default="ink_mixed", choices=sorted(METHODS))
     ap.add_argument("--baseline", default="nk_fp64", choices=sorted(METHODS))
-    ap.add_argument("--compare", default="", help="comma-separated extra methods, run once each")
+    ap.add_argument("--compare", default="bfgs_ib_mixed_r20",
+                    help="comma-separated extra methods, run once each ('' for none)")
     ap.add_argument("--jv-reps", type=int, default=200)
     ap.add_argument("--pc", default="jacobi", choices=["jacobi", "bjacobi3"],
                     help="preconditioner of the Cook solves (point or nodal 3x3 block Jacobi)")
