@@ -193,7 +193,7 @@ def cpu_baseline(n_load_steps: int):
     }
 
 
-def batch_c4(nl, torch, count: int, serial_stride: int, steps: int):
+def batch_c4(nl, torch, count: int, serial_stride: int, steps: int, autotune: bool = True):
     """Batched solves: `count` sampled Cook instances (uneven size, lambda/mu and
     traction; doubling load schedules ending at each tau) solved in one batch
     with mixed iNK, against serial FP64 NK solves of every `serial_stride`-th
@@ -214,11 +214,12 @@ def batch_c4(nl, torch, count: int, serial_stride: int, steps: int):
         n_elems += m.conn.shape[0]
     nl.nle_batch_finalize(B)
     off = nl.nle_batch_layout(B)
+    block_size = nl.nle_batch_autotune(B, nl.NLE_FP32, budget_ms=400.0) if autotune else 512
     u = torch.zeros(int(3 * off[-1]), dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t
-    print(f"[bench] batch of {count}: {n_elems} tets, {int(off[-1])} nodes, setup {t_setup:.1f}s",
-          file=sys.stderr, flush=True)
+    print(f"[bench] batch of {count}: {n_elems} tets, {int(off[-1])} nodes, setup {t_setup:.1f}s, "
+          f"{block_size} elements per block", file=sys.stderr, flush=True)
     opts = problems.make_opts("ink", "mixed", ksp="cg")
     times, oks = [], []
     for k in range(steps):
@@ -262,7 +263,7 @@ def batch_c4(nl, torch, count: int, serial_stride: int, steps: int):
     return {
         "workload": f"{count} Cook instances (n x n x nz, n in 8..48, nz in 1..3, "
                     "lambda/mu log-uniform 10..1e4, tau 2^U(0,5)), seed 0",
-        "tets": n_elems, "nodes": int(off[-1]), "setup_s": round(t_setup, 2),
+        "tets": n_elems, "nodes": int(off[-1]), "setup_s": round(t_setup, 2), "elements_per_block": block_size,
         "method": "iNK mixed, CG + Jacobi, all instances per launch",
         "seconds": [round(x, 3) for x in times], "solved": f"{min(oks)}/{count}",
         "instances_per_s": round(count / t_batch, 3),

@@ -328,6 +328,15 @@ nle_status nle_batch_add(nle_batch *b, int64_t n_nodes, const double *X, int64_t
                          int32_t *id);
 /* Upload the disjoint union of all instances (partition, geometry). */
 nle_status nle_batch_finalize(nle_batch *b);
+/* Choose the element-block size of the batch's partition for speed: each
+ * candidate (128, 256, 512 and 1024 elements per block, those whose LDS need
+ * fits the device) re-partitions the union mesh, and the Jacobian action of
+ * the whole batch in precision prec (NLE_FP32 for mixed solves) at the lifted
+ * zero state is timed with HIP events, within about budget_ms in total.  The
+ * fastest partition is kept (the batch stays finalized; the node layout does
+ * not change) and *block_size (nullable) receives its size.  NLE_E_STATE
+ * before nle_batch_finalize, NLE_E_INVAL on a bad precision or budget. */
+nle_status nle_batch_autotune(nle_batch *b, int32_t prec, double budget_ms, int32_t *block_size);
 /* node_offsets[n_inst + 1]: instance i owns nodes [off[i], off[i+1]) of the
  * concatenated vector (dof = 3 * node + component). */
 nle_status nle_batch_layout(const nle_batch *b, int64_t *node_offsets);

@@ -39,12 +39,16 @@ struct Batch {
   std::string err;
   BatchDev B;
   std::vector<int64_t> node_off;
+  std::vector<int32_t> h_inst_seg;  // [n_inst+1] segment offsets
   std::vector<void *> allocs;
   // per-instance device arrays
   double *d_coef = nullptr, *d_rtol = nullptr, *d_atol = nullptr, *d_out = nullptr;
   double *d_kscal = nullptr;
   int32_t *d_mask = nullptr, *d_active = nullptr, *d_kdone = nullptr, *d_kits = nullptr;
   int32_t *d_inv = nullptr;
+  // work lists of the instances taking a Newton step (blocks, merge
+  // workgroups, segments), rebuilt every round
+  int32_t *d_blist = nullptr, *d_mlist = nullptr, *d_slist = nullptr;
   double *h_pin = nullptr;  // pinned host staging, 16 n_inst doubles
 };
 
@@ -172,6 +176,7 @@ nle_status finalize(Batch *b) {
   b->B.seg_inst = bupload(b, seg_inst, &e);
   b->B.seg_beg = bupload(b, seg_beg, &e);
   b->B.inst_seg = bupload(b, inst_seg, &e);
+  b->h_inst_seg = inst_seg;
   b->B.inst_blk = bupload(b, c->m.h_inst_blk, &e);
   b->B.inst_mwg = bupload(b, c->m.h_inst_mwg, &e);
   c->inst_mat = bupload(b, mat, &e);
@@ -186,6 +191,9 @@ nle_status finalize(Batch *b) {
   b->d_active = balloc<int32_t>(b, n, &e);
   b->d_kdone = balloc<int32_t>(b, n, &e);
   b->d_kits = balloc<int32_t>(b, n, &e);
+  b->d_blist = balloc<int32_t>(b, size_t(std::max(1, c->m.nblk)), &e);
+  b->d_mlist = balloc<int32_t>(b, size_t(std::max(1, c->m.n_mwg)), &e);
+  b->d_slist = balloc<int32_t>(b, size_t(std::max(1, b->B.nseg)), &e);
   if (e != hipSuccess) return bfail(b, NLE_E_OOM, "batch allocation failed");
   // reduction space: element partials (blocks + merge workgroups) and segments
   const int64_t need = int64_t(elem_red_capacity(c)) + 4 * int64_t(b->B.nseg) + 64;
@@ -200,6 +208,91 @@ nle_status finalize(Batch *b) {
   b->node_off = in;
   BHIP(b, hipStreamSynchronize(c->stream));
   b->finalized = true;
+  return NLE_OK;
+}
+
+// Element-block size for the batch: re-partition the union mesh with each
+// candidate and time the whole batch's Jacobian action (precision prec, at the
+// lifted zero state), keeping the fastest.
+nle_status autotune(Batch *b, int prec, double budget_ms, int32_t *chosen) {
+  Ctx *c = b->c;
+  const int32_t cand[] = {128, 256, 512, 1024};
+  const int ncand = 4;
+  const int64_t nd = 3 * c->m.n_nodes;
+  const size_t es = prec == NLE_FP32 ? 4 : 8;
+  double *u = static_cast<double *>(dalloc(c, size_t(nd) * 8));
+  void *v = dalloc(c, size_t(nd) * es);
+  void *y = dalloc(c, size_t(nd) * es);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  struct Free {
+    Ctx *c;
+    void *p[3];
+    hipEvent_t *e[2];
+    ~Free() {
+      for (void *q : p) dfree(c, q);
+      for (hipEvent_t *q : e)
+        if (*q) (void)hipEventDestroy(*q);
+    }
+  } fr{c, {u, v, y}, {&e0, &e1}};
+  if (!u || !v || !y) return bfail(b, NLE_E_OOM, "autotune allocation failed");
+  BHIP(b, hipEventCreate(&e0));
+  BHIP(b, hipEventCreate(&e1));
+  const int32_t be0 = c->be_req;
+  int32_t best = -1, current = -1;  // fastest so far, partition now in place
+  double best_ms = 0.0;
+  for (int k = 0; k < ncand; ++k) {
+    c->be_req = cand[k];
+    b->finalized = false;
+    nle_status s = finalize(b);
+    if (s == NLE_E_UNSUPPORTED) continue;  // the block's LDS need exceeds the device's
+    if (s != NLE_OK) {
+      c->be_req = be0;
+      return s;
+    }
+    current = cand[k];
+    BHIP(b, vec_fill(c, NLE_FP64, u, 0.0, nd));
+    BHIP(b, vec_lift(c, u));
+    s = linearize(c, u, prec);
+    if (s != NLE_OK) return bfail(b, s, c->err);
+    BHIP(b, vec_fill(c, prec, v, 1.0, nd));
+    hipError_t e = hipSuccess;
+    for (int w = 0; w < 2 && e == hipSuccess; ++w) elem_apply(c, OP_JV, prec, prec == NLE_FP32 ? (const void *)c->ulin32 : (const void *)c->ulin64, v, y, nullptr, &e);
+    // one timed call sizes the repetition count to this candidate's share
+    int reps = 1;
+    float ms = 0.0f;
+    for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
+      BHIP(b, hipEventRecord(e0, c->stream));
+      for (int r = 0; r < reps && e == hipSuccess; ++r)
+        elem_apply(c, OP_JV, prec, prec == NLE_FP32 ? (const void *)c->ulin32 : (const void *)c->ulin64, v, y, nullptr, &e);
+      BHIP(b, hipEventRecord(e1, c->stream));
+      BHIP(b, hipEventSynchronize(e1));
+      BHIP(b, hipEventElapsedTime(&ms, e0, e1));
+      if (pass == 0) {
+        const double share = budget_ms / ncand;
+        reps = int(std::min(200.0, std::max(3.0, share / std::max(double(ms), 1e-3))));
+      }
+    }
+    if (e != hipSuccess) return bfail(b, NLE_E_HIP, std::string("autotune: ") + hipGetErrorString(e));
+    const double per = double(ms) / reps;
+    if (best < 0 || per < best_ms) {
+      best = cand[k];
+      best_ms = per;
+    }
+  }
+  if (best < 0) {
+    c->be_req = be0;
+    b->finalized = false;
+    nle_status s = finalize(b);
+    return s != NLE_OK ? s : bfail(b, NLE_E_UNSUPPORTED, "no block size fits the device");
+  }
+  c->be_req = best;
+  if (best != current) {
+    b->finalized = false;
+    nle_status s = finalize(b);
+    if (s != NLE_OK) return s;
+  }
+  c->lin64 = c->lin32 = c->lc_valid = false;
+  if (chosen) *chosen = best;
   return NLE_OK;
 }
 
@@ -275,6 +368,8 @@ nle_status solve(Batch *b, int method, const nle_solver_opts &o, double *u, nle_
   BHIP(b, hipMemcpyAsync(ub, u, size_t(nd) * 8, hipMemcpyDeviceToDevice, c->stream));
   std::vector<double> hs(n), hcoef(n), hrtol(n), hatol(n);
   std::vector<int32_t> hmask(n), hact(n);
+  std::vector<int32_t> hblist, hmlist, hslist;
+  const std::vector<int32_t> &hinst_seg = b->h_inst_seg;
   auto upload_d = [&](double *dst, const std::vector<double> &v) {
     return hipMemcpyAsync(dst, v.data(), size_t(n) * 8, hipMemcpyHostToDevice, c->stream);
   };
@@ -407,25 +502,72 @@ nle_status solve(Batch *b, int method, const nle_solver_opts &o, double *u, nle_
     BHIP(b, upload_i(b->d_active, hact));
     // ---- batched CG ------------------------------------------------------------
     BHIP(b, batch_cg_start(c, b->B, cg, bv, b->d_rtol, b->d_atol, b->d_active, o.ksp_max_it));
-    c->inst_done = b->d_kdone;
-    c->ep.w = nullptr;
-    c->ep.coef = nullptr;
-    c->ep.red = cg.red_a;
+    // The iterations launch only the work of the instances still iterating
+    // (blocks, merge workgroups, segments from per-round lists): instances
+    // take very different iteration counts, and the lists are rebuilt (and
+    // the chunk graph recaptured) whenever the listed blocks could halve.
+    BatchDev BL = b->B;
+    BL.seg_list = b->d_slist;
+    struct ClearLists {
+      Ctx *c;
+      ~ClearLists() {
+        c->blk_list = c->mwg_list = nullptr;
+        c->n_blist = c->n_mlist = 0;
+      }
+    } clear_lists{c};
+    auto set_lists = [&](const int32_t *done) -> hipError_t {
+      hblist.clear();
+      hmlist.clear();
+      hslist.clear();
+      for (int32_t i = 0; i < n; ++i) {
+        if (!S[i].newton || (done && done[i] != 0)) continue;
+        for (int32_t q = c->m.h_inst_blk[i]; q < c->m.h_inst_blk[i + 1]; ++q) hblist.push_back(q);
+        for (int32_t q = c->m.h_inst_mwg[i]; q < c->m.h_inst_mwg[i + 1]; ++q) hmlist.push_back(q);
+        for (int32_t q = hinst_seg[i]; q < hinst_seg[i + 1]; ++q) hslist.push_back(q);
+      }
+      hipError_t r = hipSuccess;
+      if (!hblist.empty())
+        r = hipMemcpyAsync(b->d_blist, hblist.data(), hblist.size() * 4, hipMemcpyHostToDevice,
+                           c->kstream);
+      if (r == hipSuccess && !hmlist.empty())
+        r = hipMemcpyAsync(b->d_mlist, hmlist.data(), hmlist.size() * 4, hipMemcpyHostToDevice,
+                           c->kstream);
+      if (r == hipSuccess && !hslist.empty())
+        r = hipMemcpyAsync(b->d_slist, hslist.data(), hslist.size() * 4, hipMemcpyHostToDevice,
+                           c->kstream);
+      BL.n_slist = int32_t(hslist.size());
+      c->blk_list = b->d_blist;
+      c->n_blist = int32_t(hblist.size());
+      c->mwg_list = b->d_mlist;
+      c->n_mlist = int32_t(hmlist.size());
+      return r;
+    };
     auto iter = [&]() -> hipError_t {
       hipError_t err;
       elem_apply(c, OP_JV, prec, ulin, cg.p, cg.Ap, nullptr, &err);
       if (err != hipSuccess) return err;
-      return batch_cg_step(c, b->B, cg);
+      return batch_cg_step(c, BL, cg);
     };
     const int chunk = std::max(1, o.check_every);
-    std::vector<uint64_t> key = {7, uint64_t(prec), uint64_t(nd), uint64_t(chunk),
-                                 uint64_t(uintptr_t(c->ws)), uint64_t(uintptr_t(c->red)),
-                                 uint64_t(uintptr_t(ulin)),
-                                 uint64_t(uintptr_t(c->lc_valid ? c->lc64 : nullptr))};
-    if (c->gkey != key) {
+    auto ensure_graph = [&]() -> nle_status {
+      std::vector<uint64_t> key = {7, uint64_t(prec), uint64_t(nd), uint64_t(chunk),
+                                   uint64_t(uintptr_t(c->ws)), uint64_t(uintptr_t(c->red)),
+                                   uint64_t(uintptr_t(ulin)),
+                                   uint64_t(uintptr_t(c->lc_valid ? c->lc64 : nullptr)),
+                                   uint64_t(hblist.size()), uint64_t(hmlist.size()),
+                                   uint64_t(hslist.size()), uint64_t(uintptr_t(b->d_blist))};
+      if (c->gkey == key) return NLE_OK;
       drop_graph(c);
+      c->inst_done = b->d_kdone;
+      c->ep.w = nullptr;
+      c->ep.coef = nullptr;
+      c->ep.red = cg.red_a;
       hipError_t eb = hipStreamBeginCapture(c->kstream, hipStreamCaptureModeThreadLocal);
-      if (eb != hipSuccess) return bfail(b, NLE_E_HIP, "capture");
+      if (eb != hipSuccess) {
+        c->inst_done = nullptr;
+        c->ep.red = nullptr;
+        return bfail(b, NLE_E_HIP, "capture");
+      }
       hipStream_t user = c->stream;
       c->stream = c->kstream;
       hipError_t ei = hipSuccess;
@@ -433,35 +575,48 @@ nle_status solve(Batch *b, int method, const nle_solver_opts &o, double *u, nle_
       c->stream = user;
       hipGraph_t g = nullptr;
       hipError_t ee = hipStreamEndCapture(c->kstream, &g);
+      c->inst_done = nullptr;
+      c->ep.red = nullptr;
       if (ei != hipSuccess || ee != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
-        c->inst_done = nullptr;
-        c->ep.red = nullptr;
         return bfail(b, NLE_E_HIP, "batched CG capture");
       }
       hipGraphExec_t ex = nullptr;
       if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
         (void)hipGraphDestroy(g);
-        c->inst_done = nullptr;
-        c->ep.red = nullptr;
         return bfail(b, NLE_E_HIP, "batched CG instantiate");
       }
       c->graph = g;
       c->gexec = ex;
       c->gkey = key;
-    }
-    c->inst_done = nullptr;
-    c->ep.red = nullptr;
+      return NLE_OK;
+    };
     BHIP(b, hipEventRecord(c->ev_a, c->stream));
     BHIP(b, hipStreamWaitEvent(c->kstream, c->ev_a, 0));
+    BHIP(b, set_lists(nullptr));
+    {
+      const nle_status sg = ensure_graph();
+      if (sg != NLE_OK) return sg;
+    }
     for (int done_its = 0; done_its < o.ksp_max_it; done_its += chunk) {
       BHIP(b, hipGraphLaunch(c->gexec, c->kstream));
       BHIP(b, hipMemcpyAsync(b->h_pin, b->d_kdone, size_t(n) * 4, hipMemcpyDeviceToHost, c->kstream));
       BHIP(b, hipStreamSynchronize(c->kstream));
       const int32_t *dn = reinterpret_cast<const int32_t *>(b->h_pin);
       bool all = true;
-      for (int32_t i = 0; i < n; ++i) all &= dn[i] != 0;
+      size_t left = 0;
+      for (int32_t i = 0; i < n; ++i) {
+        all &= dn[i] != 0;
+        if (S[i].newton && dn[i] == 0)
+          left += size_t(c->m.h_inst_blk[i + 1] - c->m.h_inst_blk[i]);
+      }
       if (all) break;
+      if (2 * left <= hblist.size()) {
+        std::vector<int32_t> dcopy(dn, dn + n);
+        BHIP(b, set_lists(dcopy.data()));
+        const nle_status sg = ensure_graph();
+        if (sg != NLE_OK) return sg;
+      }
     }
     BHIP(b, hipMemcpyAsync(b->h_pin, b->d_kits, size_t(n) * 4, hipMemcpyDeviceToHost, c->kstream));
     BHIP(b, hipMemcpyAsync(reinterpret_cast<int32_t *>(b->h_pin) + n, b->d_kdone, size_t(n) * 4,
@@ -469,6 +624,8 @@ nle_status solve(Batch *b, int method, const nle_solver_opts &o, double *u, nle_
     BHIP(b, hipStreamSynchronize(c->kstream));
     BHIP(b, hipEventRecord(c->ev_b, c->kstream));
     BHIP(b, hipStreamWaitEvent(c->stream, c->ev_b, 0));
+    c->blk_list = c->mwg_list = nullptr;  // the steps below cover every stepping instance
+    c->n_blist = c->n_mlist = 0;
     {
       const int32_t *its = reinterpret_cast<const int32_t *>(b->h_pin);
       for (int32_t i = 0; i < n; ++i)
@@ -643,6 +800,20 @@ nle_status nle_batch_finalize(nle_batch *h) {
   if (hipSetDevice(b->c->device) != hipSuccess) return bfail(b, NLE_E_HIP, "hipSetDevice");
   try {
     return finalize(b);
+  } catch (const std::bad_alloc &) {
+    return bfail(b, NLE_E_OOM, "host allocation failed");
+  }
+}
+
+nle_status nle_batch_autotune(nle_batch *h, int32_t prec, double budget_ms, int32_t *block_size) {
+  if (!h) return NLE_E_INVAL;
+  Batch *b = &h->b;
+  if (!b->finalized) return bfail(b, NLE_E_STATE, "nle_batch_finalize first");
+  if (prec != NLE_FP32 && prec != NLE_FP64) return bfail(b, NLE_E_INVAL, "bad precision");
+  if (!(budget_ms > 0.0)) return bfail(b, NLE_E_INVAL, "budget_ms must be positive");
+  if (hipSetDevice(b->c->device) != hipSuccess) return bfail(b, NLE_E_HIP, "hipSetDevice");
+  try {
+    return autotune(b, prec, budget_ms, block_size);
   } catch (const std::bad_alloc &) {
     return bfail(b, NLE_E_OOM, "host allocation failed");
   }

@@ -16,6 +16,9 @@ struct BatchDev {
   const int32_t *inst_seg = nullptr;  // [n_inst+1] segment offsets
   const int32_t *inst_blk = nullptr;  // [n_inst+1] element-block offsets
   const int32_t *inst_mwg = nullptr;  // [n_inst+1] merge-workgroup offsets
+  // when set, a launch covers only the listed segments (one workgroup each)
+  const int32_t *seg_list = nullptr;
+  int32_t n_slist = 0;
 };
 
 struct BatchCg {

@@ -159,7 +159,7 @@ __global__ __launch_bounds__(NT) void kb_cg_update(BatchDev B, T *x, T *r, T *z,
                                                    double *red_b, double *scal, int32_t *done) {
   __shared__ double shd[NT / 64];
   __shared__ T sh[NT / 64];
-  const int s = blockIdx.x, i = B.seg_inst[s];
+  const int s = B.seg_list ? B.seg_list[blockIdx.x] : int(blockIdx.x), i = B.seg_inst[s];
   if (done[i] != 0) return;
   const double pAp = elem_sum(B, red_a, i, shd);
   double *S = scal + BS * i;
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(NT) void kb_cg_direction(BatchDev B, T *p, const T 
                                                       const double *red_b, double *scal,
                                                       int32_t *done, int32_t *its) {
   __shared__ double sh[NT / 64];
-  const int s = blockIdx.x, i = B.seg_inst[s];
+  const int s = B.seg_list ? B.seg_list[blockIdx.x] : int(blockIdx.x), i = B.seg_inst[s];
   if (done[i] != 0) return;
   const double rz = seg_sum(B, red_b, i, sh);
   const double rr = seg_sum(B, red_b + B.nseg, i, sh);
@@ -284,18 +284,19 @@ hipError_t batch_cg_start(Ctx *c, const BatchDev &B, const BatchCg &a, const voi
 }
 
 hipError_t batch_cg_step(Ctx *c, const BatchDev &B, const BatchCg &a) {
+  const int g = B.seg_list ? B.n_slist : B.nseg;
   if (a.prec == NLE_FP32) {
-    BLAUNCH(kb_cg_update<float>, B.nseg, B, static_cast<float *>(a.x), static_cast<float *>(a.r),
+    BLAUNCH(kb_cg_update<float>, g, B, static_cast<float *>(a.x), static_cast<float *>(a.r),
             static_cast<float *>(a.z), static_cast<const float *>(a.p), static_cast<const float *>(a.Ap),
             static_cast<const float *>(a.dinv), a.red_a, a.red_b, a.scal, a.done);
-    BLAUNCH(kb_cg_direction<float>, B.nseg, B, static_cast<float *>(a.p), static_cast<const float *>(a.z),
+    BLAUNCH(kb_cg_direction<float>, g, B, static_cast<float *>(a.p), static_cast<const float *>(a.z),
             a.red_b, a.scal, a.done, a.its);
   } else {
-    BLAUNCH(kb_cg_update<double>, B.nseg, B, static_cast<double *>(a.x), static_cast<double *>(a.r),
+    BLAUNCH(kb_cg_update<double>, g, B, static_cast<double *>(a.x), static_cast<double *>(a.r),
             static_cast<double *>(a.z), static_cast<const double *>(a.p),
             static_cast<const double *>(a.Ap), static_cast<const double *>(a.dinv), a.red_a, a.red_b,
             a.scal, a.done);
-    BLAUNCH(kb_cg_direction<double>, B.nseg, B, static_cast<double *>(a.p), static_cast<const double *>(a.z),
+    BLAUNCH(kb_cg_direction<double>, g, B, static_cast<double *>(a.p), static_cast<const double *>(a.z),
             a.red_b, a.scal, a.done, a.its);
   }
   return hipGetLastError();

@@ -60,6 +60,8 @@ struct ElemArgs {
   const double *inst_s;
   const double *inst_mat;
   const int32_t *inst_done;
+  const int32_t *blk_list;  // when set, workgroup w runs block blk_list[w] (n_list of them)
+  int32_t n_list;
   // CG direction formed here (Jv only, see Ctx::cg): v = vz + beta * v
   const T *vz;
   const double *cg_red;
@@ -88,6 +90,7 @@ struct MergeArgs {
   const int32_t *mwg_inst;  // batched mode: instance of each merge workgroup
   const double *inst_s;
   const int32_t *inst_done;
+  const int32_t *mwg_list;  // when set, workgroup w runs merge workgroup mwg_list[w]
   const T *vz;              // CG direction v = vz + beta * v, beta = cg_scal[BETA]
   const double *cg_scal;
 };
@@ -654,8 +657,10 @@ __global__ __launch_bounds__(NTB) void k_elem_block(ElemArgs<T> A) {
   T *lds = reinterpret_cast<T *>(lds_raw);
   // Reduction partials are stored at the block's index b (consumers sum the
   // blocks of one problem instance, which are contiguous).
-  const int b = block_id(A.nblk, A.per_xcd);
-  if (b >= A.nblk) return;  // padding workgroup of the XCD remap
+  const int nrun = A.blk_list ? A.n_list : A.nblk;
+  const int bw = block_id(nrun, A.per_xcd);
+  if (bw >= nrun) return;  // padding workgroup of the XCD remap
+  const int b = A.blk_list ? A.blk_list[bw] : bw;
   if (A.skip && A.skip[0] != 0) return;
   const int inst = A.blk_inst ? A.blk_inst[b] : 0;
   if (A.inst_done && A.inst_done[inst]) return;
@@ -825,10 +830,11 @@ template <typename T, int OP>
 __global__ __launch_bounds__(NT) void k_elem_merge(MergeArgs<T> A) {
   __shared__ double rs[NT / 64];
   if (A.skip && A.skip[0] != 0) return;
-  const int inst = A.mwg_inst ? A.mwg_inst[blockIdx.x] : 0;
+  const int wg = A.mwg_list ? A.mwg_list[blockIdx.x] : int(blockIdx.x);
+  const int inst = A.mwg_inst ? A.mwg_inst[wg] : 0;
   if (A.inst_done && A.inst_done[inst]) return;
   const double lscale = A.inst_s ? A.inst_s[inst] : A.s;
-  const int64_t k = int64_t(blockIdx.x) * NT + threadIdx.x;
+  const int64_t k = int64_t(wg) * NT + threadIdx.x;
   double nrm = 0.0;
   // padding entries (batched mode aligns each instance to whole workgroups)
   // have an empty slot range and the id 0xFFFFFFFF
@@ -859,14 +865,15 @@ __global__ __launch_bounds__(NT) void k_elem_merge(MergeArgs<T> A) {
   }
   if (OP == OP_RES || (OP == OP_JV && A.ep_red)) {
     const double s = block_sum<NT>(nrm, rs);
-    if (threadIdx.x == 0) (OP == OP_RES ? A.red : A.ep_red)[blockIdx.x] = s;
+    if (threadIdx.x == 0) (OP == OP_RES ? A.red : A.ep_red)[wg] = s;
   }
 }
 
 template <typename T, int OP, int MAT>
 void launch_block(Ctx *c, ElemArgs<T> &A, size_t lds) {
-  A.per_xcd = c->xcd_remap ? (A.nblk + 7) / 8 : 0;
-  const int grid = A.per_xcd > 0 ? 8 * A.per_xcd : A.nblk;
+  const int nrun = A.blk_list ? A.n_list : A.nblk;
+  A.per_xcd = c->xcd_remap ? (nrun + 7) / 8 : 0;
+  const int grid = A.per_xcd > 0 ? 8 * A.per_xcd : nrun;
   hipLaunchKernelGGL((k_elem_block<T, OP, MAT>), dim3(grid), dim3(NTB), lds, c->stream, A);
 }
 
@@ -922,6 +929,8 @@ int launch(Ctx *c, int op, const T *xr, const T *u, const T *v, T *out, double *
     A.lc32 = c->lc32;
   }
   A.blk_inst = M.blk_inst;
+  A.blk_list = c->blk_list;
+  A.n_list = c->n_blist;
   A.inst_s = c->inst_s;
   A.inst_mat = c->inst_mat;
   A.inst_done = c->inst_done;
@@ -968,7 +977,8 @@ int launch(Ctx *c, int op, const T *xr, const T *u, const T *v, T *out, double *
   if (*err != hipSuccess) return 0;
   if (op == OP_ENERGY) return M.nblk;
   int nred = (op == OP_RES || (op == OP_JV && c->ep.red)) ? M.nblk : 0;
-  if (M.n_shared > 0) {
+  const int g2 = c->mwg_list ? c->n_mlist : int((M.n_shared + NT - 1) / NT);
+  if (M.n_shared > 0 && g2 > 0) {
     MergeArgs<T> B;
     B.fx_node = M.fx_node;
     B.fx_ptr = M.fx_ptr;
@@ -980,6 +990,7 @@ int launch(Ctx *c, int op, const T *xr, const T *u, const T *v, T *out, double *
     B.s = c->load_scale;
     B.red = red ? red + M.nblk : nullptr;
     B.mwg_inst = M.mwg_inst;
+    B.mwg_list = c->mwg_list;
     B.inst_s = c->inst_s;
     B.inst_done = c->inst_done;
     B.skip = c->elem_skip;
@@ -990,7 +1001,6 @@ int launch(Ctx *c, int op, const T *xr, const T *u, const T *v, T *out, double *
     B.fs = A.fs;
     B.vz = A.vz;
     B.cg_scal = c->cg.scal;
-    const int g2 = int((M.n_shared + NT - 1) / NT);
     switch (op) {
       case OP_RES:
         hipLaunchKernelGGL((k_elem_merge<T, OP_RES>), dim3(g2), dim3(NT), 0, c->stream, B);

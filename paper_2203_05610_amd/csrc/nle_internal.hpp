@@ -164,6 +164,10 @@ struct Ctx {
   double *inst_mat = nullptr;
   int32_t *inst_done = nullptr;
   int32_t *inst_inv = nullptr;  // per-instance "some det F <= 0" flags
+  // batched mode: when set, the element kernels run only the listed blocks
+  // and merge workgroups (those of the instances still iterating)
+  const int32_t *blk_list = nullptr, *mwg_list = nullptr;
+  int32_t n_blist = 0, n_mlist = 0;
 
   // linearization
   bool lin64 = false, lin32 = false;

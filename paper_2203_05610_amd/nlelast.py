@@ -48,7 +48,7 @@ EXPORTS = [
     "nle_solve_bfgs", "nle_partition_info", "nle_batch_create", "nle_batch_destroy",
     "nle_batch_last_error", "nle_batch_add", "nle_batch_finalize", "nle_batch_layout",
     "nle_batch_solve", "nle_set_fibres", "nle_set_active_tension", "nle_set_pressure",
-    "nle_set_robin", "nle_upload_mesh_mixed", "nle_block_diag", "nle_pc_apply",
+    "nle_set_robin", "nle_upload_mesh_mixed", "nle_block_diag", "nle_pc_apply", "nle_batch_autotune",
 ]
 
 
@@ -134,6 +134,7 @@ def lib() -> ctypes.CDLL:
         "nle_batch_add": (I32, [P, I64, P, I64, P, I32, P, I32, I64, P, P, I64, P, P, I32, P,
                                 ctypes.POINTER(I32)]),
         "nle_batch_finalize": (I32, [P]),
+        "nle_batch_autotune": (I32, [P, I32, D, P]),
         "nle_batch_layout": (I32, [P, ctypes.POINTER(I64)]),
         "nle_batch_solve": (I32, [P, I32, ctypes.POINTER(nle_solver_opts), P,
                                   ctypes.POINTER(nle_report), ctypes.POINTER(D)]),
@@ -508,6 +509,13 @@ def nle_batch_finalize(b: Batch) -> None:
     off = (ctypes.c_int64 * (b.n_inst + 1))()
     b.check(lib().nle_batch_layout(b.handle, off))
     b.offsets = np.array(off[:], dtype=np.int64)
+
+
+def nle_batch_autotune(b: Batch, prec: int = NLE_FP32, budget_ms: float = 200.0) -> int:
+    """Pick the element-block size of the batch's partition; returns it."""
+    out = ctypes.c_int32()
+    b.check(lib().nle_batch_autotune(b.handle, int(prec), float(budget_ms), ctypes.byref(out)))
+    return out.value
 
 
 def nle_batch_layout(b: Batch):

@@ -94,3 +94,24 @@ def test_batch_usage_errors():
     u = torch.zeros(3 * m.n_nodes, dtype=torch.float64, device="cuda")
     with pytest.raises(nl.NleError):
         nl.nle_batch_solve(B, nl.NLE_BFGS, problems.make_opts("bfgs"), u)
+
+
+def test_batch_autotune_keeps_layout_and_results():
+    data = _roots()
+    B = nl.Batch(0)
+    for (m, P, sched, _), (nx, ny, nz, ratio, tau) in zip(data, INSTANCES):
+        problems.add_cook_instance(B, m, MU, ratio * MU, 1.0, sched)
+    nl.nle_batch_finalize(B)
+    off = nl.nle_batch_layout(B).copy()
+    with pytest.raises(nl.NleError):
+        nl.nle_batch_autotune(B, prec=7)
+    be = nl.nle_batch_autotune(B, nl.NLE_FP32, budget_ms=50.0)
+    assert be in (128, 256, 512, 1024)
+    assert np.array_equal(nl.nle_batch_layout(B), off)
+    u = torch.zeros(int(3 * off[-1]), dtype=torch.float64, device="cuda")
+    st, reps, tms = nl.nle_batch_solve(B, nl.NLE_INK, problems.make_opts("ink", "mixed", ksp="cg"), u)
+    assert st == nl.NLE_OK, reps
+    uh = u.cpu().numpy()
+    for i, (m, P, sched, ustar) in enumerate(data):
+        ui = uh[3 * off[i]: 3 * off[i + 1]]
+        assert np.linalg.norm(ui - ustar) <= 1e-6 * np.linalg.norm(ustar), i
