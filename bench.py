@@ -321,6 +321,13 @@ CARDIAC_METHODS = {
     "ink_mixed": ("ink", "mixed", {"ksp": "minres"}),
     "nk_fp64": ("nk", "fp64", {"ksp": "minres"}),
     "bfgs_ib_fp64": ("bfgs", "fp64", {"ksp": "minres", "h0": "ksp", "qn_m": 10}),
+    "bfgs_ib_fp64_r20": ("bfgs", "fp64", {"ksp": "minres", "h0": "ksp", "qn_m": 10,
+                                          "h0_refresh": 20}),
+    "ink_fp64_bj": ("ink", "fp64", {"ksp": "minres", "pc": "bjacobi3"}),
+    "bfgs_ib_fp64_r20_bj": ("bfgs", "fp64", {"ksp": "minres", "h0": "ksp", "qn_m": 10,
+                                             "h0_refresh": 20, "pc": "bjacobi3"}),
+    "bfgs_ib_mixed_r20_bj": ("bfgs", "mixed", {"ksp": "minres", "h0": "ksp", "qn_m": 10,
+                                               "h0_refresh": 20, "pc": "bjacobi3"}),
 }
 
 
@@ -390,7 +397,7 @@ def main():
     ap.add_argument("--twist-methods", default="nk_fp64,ink_mixed")
     ap.add_argument("--cardiac", default="", help="ventricle shell grid n_t,n_s,n_c (e.g. "
                     "8,80,256); empty skips this leg (minutes at full size)")
-    ap.add_argument("--cardiac-methods", default="ink_fp64,ink_mixed")
+    ap.add_argument("--cardiac-methods", default="ink_fp64,bfgs_ib_fp64_r20_bj")
     ap.add_argument("--cardiac-steps", type=int, default=20)
     ap.add_argument("--legs-only", action="store_true",
                     help="only the twist and cardiac legs (for their own runs)")
