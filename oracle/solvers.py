@@ -300,7 +300,7 @@ def lbfgs(residual: Callable, h0: Callable, u0: np.ndarray, *, m: int = 10,
     With refresh > 0, every `refresh` iterations the initial inverse Hessian
     is rebuilt at the current iterate (h0 = relinearize(u)) and the stored
     pairs are dropped: the occasional Jacobian reassembly for BFGS that the
-    paper's conclusions (Sec. 6) name as an extension.
+    paper's conclusions (Sec. 7) name as an extension.
     """
     u = np.array(u0, dtype=np.float64, copy=True)
     g = residual(u)
