@@ -142,6 +142,18 @@ typedef struct {
                          the current iterate (new tangent, preconditioner
                          and H0) and drop the stored pairs; 0 = once per
                          solve, the single assembly of Sec. 3            */
+  int32_t jac_lag;    /* NK / iNK: re-linearize every jac_lag Newton
+                         iterations and reuse the last tangent (and
+                         preconditioner) in between; 0 or 1 = every
+                         iteration.  Jacobian lagging, an extension the
+                         conclusions (Sec. 7) name                       */
+  int32_t h0_ew;      /* inexact BFGS: nonzero = the H0 solve's relative
+                         tolerance follows Eisenstat-Walker choice 2 on
+                         the BFGS residual norms, eta_k = gamma (|g_k| /
+                         |g_k-1|)^alpha with its safeguard, eta_0 and the
+                         upper clip h0_rtol, the lower clip ew_rtolmin
+                         (and 1e-4 in mixed precision); 0 = fixed h0_rtol.
+                         The adaptive variant Sec. 3 leaves open         */
   int32_t reserved;
 } nle_solver_opts;
 

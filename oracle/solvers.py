@@ -253,11 +253,14 @@ def newton_krylov(residual: Callable, linearize: Callable, u0: np.ndarray, *,
                   inexact: bool = False, rtol: float = 1e-8, atol: float = 0.0,
                   max_it: int = 50, ksp_rtol: float = 1e-6, ksp_atol: float = 1e-10,
                   ksp: str = "gmres", restart: Optional[int] = None, ksp_max_it: int = 10000,
-                  ew_version: int = 1, ew_rtol0: float = 0.1, ew_rtolmax: float = 0.1):
+                  ew_version: int = 1, ew_rtol0: float = 0.1, ew_rtolmax: float = 0.1,
+                  lag: int = 1):
     """NK (inexact=False) or iNK (inexact=True) with full steps.
 
     residual(u) -> r;  linearize(u) -> (matvec, precond) at u.
-    Converged when ||r_k|| <= max(rtol ||r_0||, atol).
+    Converged when ||r_k|| <= max(rtol ||r_0||, atol).  With lag > 1 the
+    tangent is rebuilt only every `lag` iterations and reused in between
+    (Jacobian lagging, named as an extension in the conclusions, Sec. 7).
     """
     u = np.array(u0, dtype=np.float64, copy=True)
     r = residual(u)
@@ -267,7 +270,8 @@ def newton_krylov(residual: Callable, linearize: Callable, u0: np.ndarray, *,
     eta_prev, linres_prev = 0.0, 0.0
     k = 0
     while rn[-1] > max(rtol * r0, atol) and k < max_it:
-        matvec, prec = linearize(u)
+        if lag <= 1 or k % lag == 0:
+            matvec, prec = linearize(u)
         if inexact:
             eta = ew_forcing(k, rn[-1], rn[-2] if k > 0 else 0.0, linres_prev, eta_prev,
                              version=ew_version, rtol0=ew_rtol0, rtolmax=ew_rtolmax)

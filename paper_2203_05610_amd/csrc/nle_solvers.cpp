@@ -458,6 +458,8 @@ nle_status check_ready(Ctx *c, double *u, const nle_solver_opts *o) {
   if (o->cg_launches != 0 && o->cg_launches != 3 && o->cg_launches != 4)
     return fail(c, NLE_E_INVAL, "bad cg_launches");
   if (o->h0_refresh < 0) return fail(c, NLE_E_INVAL, "bad h0_refresh");
+  if (o->jac_lag < 0) return fail(c, NLE_E_INVAL, "bad jac_lag");
+  if (o->reserved != 0) return fail(c, NLE_E_INVAL, "reserved option field must be 0");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, NLE_E_HIP, "hipSetDevice failed");
   return NLE_OK;
 }
@@ -600,8 +602,10 @@ nle_status newton(Ctx *c, double *u, const nle_solver_opts &o, nle_report *repor
       rep.hist(k, rn, 0.0, 0);
       break;
     }
-    s = linearize(c, u, prec);
-    if (s != NLE_OK) return s;
+    if (o.jac_lag <= 1 || k % o.jac_lag == 0) {  // else the lagged tangent is reused
+      s = linearize(c, u, prec);
+      if (s != NLE_OK) return s;
+    }
     double eta = o.ksp_rtol, atol = o.ksp_atol;
     if (inexact) {
       eta = ew_eta(o, k, rn, rn_prev, linres_prev, eta_prev);
@@ -717,6 +721,7 @@ nle_status bfgs(Ctx *c, double *u, const nle_solver_opts &o, nle_report *report)
                          : (prec == NLE_FP32 ? static_cast<const void *>(c->dinv32)
                                              : static_cast<const void *>(c->dinv64));
   double *redA = c->red, *redB = c->red + VGRID_MAX;
+  double rn_prev_it = rn, h0_eta_prev = o.h0_rtol;  // inexact-BFGS forcing state
   int k = 0;
   nle_status st = NLE_DIVERGED_MAXIT;
   for (;; ++k) {
@@ -766,10 +771,22 @@ nle_status bfgs(Ctx *c, double *u, const nle_solver_opts &o, nle_report *report)
     }
     // z = H0 q
     int lit = 0;
+    double h0_eta = o.h0_rtol;
+    if (o.h0 == NLE_H0_KSP && o.h0_ew && k > 0) {
+      // Eisenstat-Walker choice 2 on the BFGS residual norms, capped at h0_rtol
+      h0_eta = o.ew_gamma * std::pow(rn / rn_prev_it, o.ew_alpha);
+      const double stol = o.ew_gamma * std::pow(h0_eta_prev, o.ew_alpha);
+      if (stol > o.ew_threshold) h0_eta = std::max(h0_eta, stol);
+      h0_eta = std::max(std::min(h0_eta, o.h0_rtol), o.ew_rtolmin);
+      if (prec == NLE_FP32) h0_eta = std::max(h0_eta, kEtaMinFP32);
+    }
+    h0_eta_prev = h0_eta;
     if (o.h0 == NLE_H0_KSP) {
       KspResult kr;
       W.off = ksp_off;
-      s = ksp_solve(c, ko, prec, q, z, W, &kr, &n_jv);
+      KspOpts kh = ko;
+      kh.rtol = h0_eta;
+      s = ksp_solve(c, kh, prec, q, z, W, &kr, &n_jv);
       if (s != NLE_OK) return s;
       lit = kr.its;
       lit_total += kr.its;
@@ -791,7 +808,7 @@ nle_status bfgs(Ctx *c, double *u, const nle_solver_opts &o, nle_report *report)
                                  ynext ? redB : nullptr, n));
       std::swap(redA, redB);
     }
-    rep.hist(k, rn, o.h0 == NLE_H0_KSP ? o.h0_rtol : 0.0, lit);
+    rep.hist(k, rn, o.h0 == NLE_H0_KSP ? h0_eta : 0.0, lit);
     // step p = -||g|| z ; u += p ; s = p
     const int slot = free_slots.back();
     free_slots.pop_back();
@@ -799,6 +816,7 @@ nle_status bfgs(Ctx *c, double *u, const nle_solver_opts &o, nle_report *report)
     NLE_HIP(c, vec_axpy(c, prec, z, NLE_FP64, u, -rn, nullptr, n));
     // new gradient, y = g_new - g
     const double rn_old = rn;
+    rn_prev_it = rn;
     hipError_t e;
     NLE_HIP(c, hipMemsetAsync(c->dflag, 0, 4, c->stream));
     const int npr = elem_apply(c, OP_RES, NLE_FP64, u, nullptr, gn, c->red + 4 * VGRID_MAX, &e);

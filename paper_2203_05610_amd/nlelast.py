@@ -72,7 +72,8 @@ class nle_solver_opts(ctypes.Structure):
             "ksp_rtol", "ksp_atol", "ew_rtol0", "ew_rtolmax", "ew_rtolmin", "ew_gamma",
             "ew_alpha", "ew_alpha2", "ew_threshold", "ink_ksp_atol", "snes_rtol", "snes_atol",
             "h0_rtol", "h0_atol", "curvature_eps")] + [
-        ("h0_refresh", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+        ("h0_refresh", ctypes.c_int32), ("jac_lag", ctypes.c_int32),
+        ("h0_ew", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class nle_report(ctypes.Structure):

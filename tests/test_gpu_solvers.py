@@ -212,6 +212,60 @@ def test_bfgs_h0_refresh_follows_oracle_lbfgs():
     assert e.value.status == nl.NLE_E_INVAL
 
 
+def test_nk_jacobian_lag_follows_oracle():
+    # the tangent rebuilt every third Newton iteration, the same on the CPU
+    mesh, P, ctx = _cook(*C1, be=64)
+
+    def lin(u):
+        K = P.stiffness(u)
+        d = K.diagonal()
+        return (lambda v: K @ v), (lambda v: v / d)
+
+    ref = solvers.newton_krylov(lambda u: P.residual(u), lin, np.zeros(P.n_dofs), lag=3,
+                                ksp="minres")
+    assert ref["converged"]
+    u = torch.zeros(P.n_dofs, dtype=torch.float64, device="cuda")
+    o = problems.make_opts("nk", ksp="minres", jac_lag=3)
+    st, rep = nl.nle_solve_nk(ctx, u, o)
+    assert st == nl.NLE_OK
+    assert abs(rep["nit"] - ref["nit"]) <= 1, (rep["nit"], ref["nit"])
+    for a, b in zip(rep["rnorm_hist"][1:4], ref["rnorm"][1:4]):
+        assert abs(a - b) <= 1e-3 * b + 1e-6 * ref["rnorm"][0]
+    # lagging costs Newton iterations against the exact tangent every step
+    o1 = problems.make_opts("nk", ksp="minres")
+    u1 = torch.zeros_like(u)
+    st1, rep1 = nl.nle_solve_nk(ctx, u1, o1)
+    assert rep["nit"] > rep1["nit"]
+    ustar = _root("c1", P, [1.0])
+    assert np.linalg.norm(u.cpu().numpy() - ustar) <= 1e-6 * np.linalg.norm(ustar)
+    with pytest.raises(nl.NleError) as e:
+        nl.nle_solve_nk(ctx, u, problems.make_opts("nk", jac_lag=-2))
+    assert e.value.status == nl.NLE_E_INVAL
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_inexact_bfgs_adaptive_h0_tolerance(precision):
+    # the H0 solve's tolerance follows Eisenstat-Walker choice 2 on the BFGS
+    # residual norms (the oracle's forcing function), capped at h0_rtol
+    mesh, P, ctx = _cook(*C1, be=64)
+    u = torch.zeros(P.n_dofs, dtype=torch.float64, device="cuda")
+    o = problems.make_opts("bfgs", precision, h0="ksp", qn_m=10, ksp="minres", h0_ew=1)
+    st, rep = nl.nle_solve_bfgs(ctx, u, o)
+    assert st == nl.NLE_OK, rep["nit"]
+    rh, eh = rep["rnorm_hist"], rep["eta_hist"]
+    eta_prev = o.h0_rtol
+    for k in range(rep["nit"]):
+        want = solvers.ew_forcing(k, rh[k], rh[k - 1] if k else 0.0, 0.0, eta_prev, version=2,
+                                  rtol0=o.h0_rtol, rtolmax=o.h0_rtol, gamma=o.ew_gamma,
+                                  alpha=o.ew_alpha, threshold=o.ew_threshold,
+                                  rtolmin=max(o.ew_rtolmin, 1e-4 if precision == "mixed" else 0))
+        assert abs(eh[k] - want) <= 1e-12 * want, (k, eh[k], want)
+        eta_prev = eh[k]
+    assert min(eh[: rep["nit"]]) < o.h0_rtol  # it does tighten near the root
+    ustar = _root("c1", P, [1.0])
+    assert np.linalg.norm(u.cpu().numpy() - ustar) <= 1e-6 * np.linalg.norm(ustar)
+
+
 def test_load_schedule_and_zero_load():
     mesh, P, ctx = _cook(8, 8, 2, 20.0, be=128)
     scales = [0.5, 1.0, 2.0]

@@ -426,3 +426,33 @@ def test_lbfgs_refresh_rebuilds_h0_and_drops_pairs():
     assert r["nit"] == 3
     r0 = solvers.lbfgs(res, poor, np.zeros(n), m=3, max_it=3, rtol=1e-14)
     assert np.linalg.norm(r0["u"] - ustar) > 1e-6 * np.linalg.norm(ustar)
+
+
+def test_newton_lag_reuses_the_first_tangent_on_a_quadratic_residual():
+    # r(u) = A u + 0.1 u^3 - b: with lag = 3 the second and third iterations
+    # use the tangent at u0, exactly the chord iteration written out here
+    from oracle import solvers
+
+    rng = np.random.default_rng(4)
+    n = 8
+    Q = rng.standard_normal((n, n))
+    A = Q @ Q.T + n * np.eye(n)
+    b = rng.standard_normal(n)
+    res = lambda u: A @ u + 0.1 * u ** 3 - b
+    jac = lambda u: A + np.diag(0.3 * u ** 2)
+    calls = []
+
+    def lin(u):
+        calls.append(u.copy())
+        K = jac(u)
+        return (lambda v: K @ v), (lambda v: v)
+
+    r = solvers.newton_krylov(res, lin, np.zeros(n), lag=3, max_it=4, ksp_rtol=1e-14,
+                              ksp_atol=0.0, rtol=1e-30)
+    assert len(calls) == 2  # iterations 0 and 3
+    u = np.zeros(n)
+    K0 = jac(u)
+    for _ in range(3):
+        u = u - np.linalg.solve(K0, res(u))
+    u = u - np.linalg.solve(jac(u), res(u))
+    assert np.linalg.norm(r["u"] - u) <= 1e-10 * np.linalg.norm(u)
