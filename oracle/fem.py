@@ -123,6 +123,51 @@ def follower_pressure_jacobian(X: np.ndarray, u: np.ndarray, tri: np.ndarray, p:
     return sp.coo_matrix((Kf.reshape(-1), (rows, cols)), shape=(n, n)).tocsr()
 
 
+def follower_traction(X: np.ndarray, u: np.ndarray, tri: np.ndarray, t: Sequence[float]) -> np.ndarray:
+    """Consistent nodal forces of a traction t of fixed spatial direction per
+    unit CURRENT area (the Cook load "in the deformed configuration", Sec. 4,
+    read as a Cauchy traction of fixed direction): on a flat linear triangle
+    with current area |a|, a = (x1 - x0) x (x2 - x0) / 2, each vertex gets
+    t |a| / 3 (exact).  Valid for complex u (complex-step derivatives)."""
+    x = np.asarray(X)[tri] + np.asarray(u).reshape(-1, 3)[tri]
+    a2 = np.cross(x[:, 1] - x[:, 0], x[:, 2] - x[:, 0])
+    area = 0.5 * np.sqrt(np.sum(a2 * a2, axis=1))  # analytic, so complex-step safe
+    tt = np.asarray(t)
+    out = np.zeros((X.shape[0], 3), dtype=area.dtype)
+    idx = tri.reshape(-1)
+    for i in range(3):
+        w = np.repeat(tt[i] * area / 3.0, 3)
+        if np.iscomplexobj(w):
+            out[:, i] = (np.bincount(idx, weights=w.real, minlength=X.shape[0])
+                         + 1j * np.bincount(idx, weights=w.imag, minlength=X.shape[0]))
+        else:
+            out[:, i] = np.bincount(idx, weights=w, minlength=X.shape[0])
+    return out.reshape(-1)
+
+
+def follower_traction_jacobian(X: np.ndarray, u: np.ndarray, tri: np.ndarray, t: Sequence[float],
+                               h: float = 1e-30) -> sp.csr_matrix:
+    """d(follower_traction)/du from per-face complex-step blocks (9 x 9 per
+    triangle); not symmetric."""
+    X = np.asarray(X, dtype=np.float64)
+    x = X[tri] + np.asarray(u, dtype=np.float64).reshape(-1, 3)[tri]
+    tt = np.asarray(t, dtype=np.float64)
+    nf = tri.shape[0]
+    Kf = np.empty((nf, 3, 3, 3, 3))  # [f, a, i, b, k]
+    for b in range(3):
+        for k in range(3):
+            xc = x.astype(np.complex128)
+            xc[:, b, k] += 1j * h
+            a2 = np.cross(xc[:, 1] - xc[:, 0], xc[:, 2] - xc[:, 0])
+            darea = (0.5 * np.sqrt(np.sum(a2 * a2, axis=1))).imag / h  # (f,)
+            Kf[:, :, :, b, k] = (darea[:, None, None] / 3.0) * tt[None, None, :]
+    dofs = (3 * tri[:, :, None] + np.arange(3)[None, None, :]).reshape(nf, 9)
+    rows = np.repeat(dofs, 9, axis=1).reshape(-1)
+    cols = np.tile(dofs, (1, 9)).reshape(-1)
+    n = 3 * X.shape[0]
+    return sp.coo_matrix((Kf.reshape(-1), (rows, cols)), shape=(n, n)).tocsr()
+
+
 def robin_matrix(X: np.ndarray, tri: np.ndarray, k_perp: float, k_par: float) -> sp.csr_matrix:
     """Elastic Robin condition of Sec. 4 ("Heartbeat test", epicardium, without
     its damping terms): traction -[k_perp N (x) N + k_par (I - N (x) N)] u with
@@ -165,6 +210,10 @@ class Problem:
     robin_tri: Optional[np.ndarray] = None
     k_perp: float = 0.0
     k_par: float = 0.0
+    # follower traction (fixed direction, per unit current area), scaled by
+    # the load scale like f_ext
+    ftrac_tri: Optional[np.ndarray] = None
+    ftrac: tuple = (0.0, 0.0, 0.0)
 
     def __post_init__(self):
         self.conn = np.asarray(self.conn)[:, :4].astype(np.int64)
@@ -187,6 +236,9 @@ class Problem:
                                      load_scale * self.pressure)
         if self.R is not None:
             out += self.R @ u
+        if self.ftrac_tri is not None:
+            out -= load_scale * follower_traction(self.X, u, np.asarray(self.ftrac_tri),
+                                                  self.ftrac)
         return out
 
     # -- evaluation -------------------------------------------------------
@@ -211,8 +263,8 @@ class Problem:
 
     def energy(self, u: np.ndarray, load_scale: float = 1.0) -> float:
         F = deformation_gradient(u, self.conn, self.G)
-        if self.pressure_tri is not None:
-            raise ValueError("a follower pressure has no potential")
+        if self.pressure_tri is not None or self.ftrac_tri is not None:
+            raise ValueError("a follower load has no potential")
         psi = materials.energy(self.material, F, self.params)
         springs = 0.5 * float(u @ (self.R @ u)) if self.R is not None else 0.0
         return float(np.sum(self.V * psi) - load_scale * np.dot(self.f_ext, u)) + springs
@@ -238,6 +290,9 @@ class Problem:
                                                load_scale * self.pressure)
         if self.R is not None:
             K = K + self.R
+        if self.ftrac_tri is not None:
+            K = K - load_scale * follower_traction_jacobian(self.X, u, np.asarray(self.ftrac_tri),
+                                                            self.ftrac)
         if dirichlet:
             Dfree = sp.diags(self.free.astype(np.float64))
             K = (Dfree @ K @ Dfree + sp.diags(self.fixed.astype(np.float64))).tocsr()
@@ -253,14 +308,21 @@ class Problem:
 
 
 def cook_problem(mesh, mu: float = 80.194, lam: float = 400.9, tau: float = 1.0,
-                 material: str = materials.M1, c_vol: Optional[float] = None) -> Problem:
-    """Cook's membrane: clamp x = 0, dead shear traction (0, tau, 0) on x = 48.
+                 material: str = materials.M1, c_vol: Optional[float] = None,
+                 follower: bool = False) -> Problem:
+    """Cook's membrane: clamp x = 0, shear traction (0, tau, 0) on x = 48:
+    per unit reference area (dead load, the default) or, with follower=True,
+    per unit current area with fixed direction (the load in the deformed
+    configuration of Sec. 4).
 
     f_ext is for traction tau; the residual's load_scale multiplies it.
     """
     params = (mu, lam) if material == materials.M1 else (mu, lam, 0.25 if c_vol is None else c_vol)
-    f_ext = dead_traction(mesh.X, mesh.faces["load"], (0.0, tau, 0.0))
     ddofs = mesh.dirichlet_dofs("clamp")
+    if follower:
+        return Problem(mesh.X, mesh.conn, material, params, np.zeros(3 * mesh.n_nodes), ddofs,
+                       np.zeros(ddofs.size), ftrac_tri=mesh.faces["load"], ftrac=(0.0, tau, 0.0))
+    f_ext = dead_traction(mesh.X, mesh.faces["load"], (0.0, tau, 0.0))
     return Problem(mesh.X, mesh.conn, material, params, f_ext, ddofs, np.zeros(ddofs.size))
 
 
