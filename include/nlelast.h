@@ -253,6 +253,17 @@ nle_status nle_set_active_tension(nle_ctx *ctx, double gamma);
  * pressure faces; n_faces = 0 removes them.  With a pressure set, nle_energy
  * returns NLE_E_UNSUPPORTED (no potential). */
 nle_status nle_set_pressure(nle_ctx *ctx, int64_t n_faces, const int32_t *tri, double p);
+/* Follower traction on n_faces triangles tri[n][3] (node ids): the
+ * traction t[3] has a fixed spatial direction and acts per unit CURRENT area
+ * (Sec. 4 applies the Cook load in the deformed configuration; this reads it
+ * as a Cauchy traction of fixed direction), scaled by the load scale: each
+ * vertex of a face with current area vector a = (x1-x0) x (x2-x0)/2 receives
+ * s t |a| / 3.  Its tangent is not symmetric (use GMRES), the diagonal and
+ * nodal blocks take its own-node part (blocks: the symmetric part), and
+ * nle_energy refuses it.  Replaces any earlier follower traction; P1 meshes
+ * only.  Host arrays, copied. */
+nle_status nle_set_traction_follower(nle_ctx *ctx, int64_t n_faces, const int32_t *tri,
+                                     const double *t);
 /* Elastic Robin springs on n_faces triangles (the epicardial condition of
  * Sec. 4 without its damping terms): traction -(k_perp N (x) N + k_par
  * (I - N (x) N)) u with the reference unit normal N, integrated exactly
@@ -281,9 +292,10 @@ nle_status nle_jv(nle_ctx *ctx, const void *v_dev, void *y_dev, int32_t prec);
 nle_status nle_diag(nle_ctx *ctx, double *d_dev);
 /* Nodal diagonal blocks of the current linearization (P1 meshes): b[n_nodes]
  * [6] = (K_xx, K_yy, K_zz, K_xy, K_yz, K_xz) of the 3x3 block of node k,
- * double, device.  The blocks are symmetric: they hold the tangent of the
- * strain energy and of the Robin springs; a follower pressure adds only a
- * skew-symmetric part to a node's own block, which is left out.  Dirichlet
+ * double, device.  The blocks are the symmetric parts of the tangent's
+ * own-node blocks: the strain energy and the Robin springs give symmetric
+ * blocks, a follower pressure only a skew part (which drops out), a follower
+ * traction a rank-one part (whose symmetric part enters).  Dirichlet
  * dofs have identity rows and columns.  NLE_E_UNSUPPORTED on a mixed mesh,
  * NLE_E_STATE before nle_linearize. */
 nle_status nle_block_diag(nle_ctx *ctx, double *b_dev);

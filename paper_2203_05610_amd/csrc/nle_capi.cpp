@@ -564,6 +564,27 @@ nle_status nle_set_pressure(nle_ctx *ctx, int64_t nf, const int32_t *tri, double
   });
 }
 
+nle_status nle_set_traction_follower(nle_ctx *ctx, int64_t nf, const int32_t *tri, const double *t) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  nle_status s = need_mesh(c);
+  if (s != NLE_OK) return s;
+  if (c->mixed) return fail(c, NLE_E_UNSUPPORTED, "not available on mixed meshes");
+  if (!t) return fail(c, NLE_E_INVAL, "null traction");
+  for (int i = 0; i < 3; ++i)
+    if (!std::isfinite(t[i])) return fail(c, NLE_E_INVAL, "non-finite traction");
+  return guarded(c, [&]() -> nle_status {
+    std::vector<int32_t> tv;
+    nle_status st = check_tri(c, nf, tri, &tv);
+    if (st != NLE_OK) return st;
+    for (int i = 0; i < 3; ++i) c->surf.tf[i] = t[i];
+    drop_graph(c);  // the traction is a kernel argument of captured chunks
+    c->lin64 = c->lin32 = c->lc_valid = false;
+    if (tv == c->surf.h_ttri) return NLE_OK;
+    c->surf.h_ttri = tv;
+    return build_surface(c);
+  });
+}
+
 nle_status nle_set_robin(nle_ctx *ctx, int64_t nf, const int32_t *tri, double k_perp, double k_par) {
   Ctx *c = reinterpret_cast<Ctx *>(ctx);
   nle_status s = need_mesh(c);
@@ -698,7 +719,8 @@ nle_status nle_energy(nle_ctx *ctx, const double *u, double *pi) {
   if (s != NLE_OK) return s;
   if (!c->has_mat) return fail(c, NLE_E_STATE, "no material set");
   if (!u || !pi) return fail(c, NLE_E_INVAL, "null argument");
-  if (c->surf.npf > 0) return fail(c, NLE_E_UNSUPPORTED, "a follower pressure has no potential");
+  if (c->surf.npf + c->surf.ntf > 0)
+    return fail(c, NLE_E_UNSUPPORTED, "a follower load has no potential");
   s = need_fibres(c);
   if (s != NLE_OK) return s;
   hipError_t e;

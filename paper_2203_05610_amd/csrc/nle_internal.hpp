@@ -140,21 +140,23 @@ struct Ctx {
   // springs, evaluated node by node over the incident faces
   struct Surf {
     int64_t nsn = 0;             // face nodes
-    int32_t npf = 0, nrf = 0;    // pressure faces, spring faces (faces numbered in that order)
+    // pressure faces, follower-traction faces, spring faces (numbered in that order)
+    int32_t npf = 0, ntf = 0, nrf = 0;
     int32_t *node = nullptr;     // [nsn] node ids
     int32_t *ptr = nullptr;      // [nsn+1] incident-face ranges
     int32_t *ent = nullptr;      // incident faces, increasing
-    int32_t *tri = nullptr;      // [npf+nrf][3]
-    uint32_t *fmask = nullptr;   // [npf+nrf] Dirichlet bits of the 3 vertices (3 each)
-    double *pgeo64 = nullptr;    // [npf][9] reference vertex coordinates
+    int32_t *tri = nullptr;      // [npf+ntf+nrf][3]
+    uint32_t *fmask = nullptr;   // [npf+ntf+nrf] Dirichlet bits of the 3 vertices (3 each)
+    double *pgeo64 = nullptr;    // [npf+ntf][9] reference vertex coordinates
     float *pgeo32 = nullptr;
     double *rgeo64 = nullptr;    // [nrf][4] reference unit normal, area
     float *rgeo32 = nullptr;
-    double *plin = nullptr;      // device: effective pressure at the linearization
+    double *plin = nullptr;      // device: [0] effective pressure, [1] load scale, at the linearization
     double *fs64 = nullptr;      // [3 n_nodes] contributions (zero off the face nodes)
     float *fs32 = nullptr;
     double p = 0.0, kperp = 0.0, kpar = 0.0;
-    std::vector<int32_t> h_ptri, h_rtri, h_tri;
+    double tf[3] = {0.0, 0.0, 0.0};  // follower traction per unit current area
+    std::vector<int32_t> h_ptri, h_ttri, h_rtri, h_tri;
     std::vector<void *> allocs;
   } surf;
 

@@ -12,7 +12,13 @@
 // in the residual, and p [(v1-v0) x (x2-x0) + (x1-x0) x (v2-v0)] / 6 in the
 // Jacobian action (not symmetric).  Springs with reference unit normal N and
 // area A: the residual gains M K u with M_ab = A (1 + delta_ab) / 12 and
-// K = k_par I + (k_perp - k_par) N (x) N (symmetric, constant).
+// K = k_par I + (k_perp - k_par) N (x) N (symmetric, constant).  A follower
+// traction t (fixed direction, per unit current area, times the load scale
+// s) gives each vertex s t l / 6 with l = |(x1-x0) x (x2-x0)|, subtracted
+// from the residual; in the Jacobian action s t (n . dl_v) / 6 with
+// dl_v = (v1-v0) x (x2-x0) + (x1-x0) x (v2-v0), n = the unit normal; its own
+// 3x3 block at vertex a is -s/6 t (x) dl/dx_a, dl/dx_0 = (e1 - e2) x n,
+// dl/dx_1 = e2 x n, dl/dx_2 = n x e1 (e1 = x1 - x0, e2 = x2 - x0).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -27,12 +33,14 @@ namespace {
 template <typename T>
 struct SurfArgs {
   int64_t nsn;
-  int32_t npf;
+  int32_t npf, ntf;
   const int32_t *node, *ptr, *ent, *tri;
   const uint32_t *fmask;  // per face: Dirichlet bits of vertex a at bits 3a..3a+2
   const T *pgeo, *rgeo;
   double p;             // effective pressure (residual)
-  const double *plin;   // effective pressure at the linearization (Jacobian action)
+  double s;             // load scale (residual, diagonal)
+  const double *plin;   // effective pressure and load scale at the linearization (Jacobian action)
+  double tf[3];         // follower traction
   double kperp, kpar;
   const T *u, *v;
   T *fs;
@@ -61,8 +69,9 @@ __global__ __launch_bounds__(NT) void k_surface(SurfArgs<T> A) {
     for (int q = A.ptr[k]; q < A.ptr[k + 1]; ++q) {
       const int32_t f = A.ent[q];
       const int32_t n[3] = {A.tri[3 * f], A.tri[3 * f + 1], A.tri[3 * f + 2]};
-      if (f < A.npf) {
-        if (OP == OP_RES || OP == OP_JV) {
+      if (f < A.npf + A.ntf) {
+        const bool trac = f >= A.npf;
+        if (OP == OP_RES || OP == OP_JV || (trac && (OP == OP_DIAG || OP == OP_ODIAG))) {
           const T *Xf = A.pgeo + 9 * int64_t(f);
           T x[3][3];
 #pragma unroll
@@ -76,9 +85,57 @@ __global__ __launch_bounds__(NT) void k_surface(SurfArgs<T> A) {
             e2[i] = x[2][i] - x[0][i];
           }
           const T s = pe / T(6);
-          if (OP == OP_RES) {
+          if (trac) {
+            T a2[3] = {T(0), T(0), T(0)};
+            cross_acc(e1, e2, T(1), a2);
+            const T l = sqrt(a2[0] * a2[0] + a2[1] * a2[1] + a2[2] * a2[2]);
+            const T tv[3] = {T(A.tf[0]), T(A.tf[1]), T(A.tf[2])};
+            // the Jacobian action and the (lazily formed) nodal blocks use the
+            // load scale of the linearization
+            const T sc = ((OP == OP_JV || OP == OP_ODIAG) ? T(A.plin[1]) : T(A.s)) / T(6);
+            if (OP == OP_RES) {
+#pragma unroll
+              for (int i = 0; i < 3; ++i) acc[i] -= sc * l * tv[i];
+            } else if (OP == OP_JV) {
+              const uint32_t fm = A.nomask ? 0u : A.fmask[f];
+              T d1[3], d2[3];
+#pragma unroll
+              for (int i = 0; i < 3; ++i) {
+                const T v0 = ((fm >> i) & 1u) ? T(0) : A.v[3 * int64_t(n[0]) + i];
+                const T v1 = ((fm >> (3 + i)) & 1u) ? T(0) : A.v[3 * int64_t(n[1]) + i];
+                const T v2 = ((fm >> (6 + i)) & 1u) ? T(0) : A.v[3 * int64_t(n[2]) + i];
+                d1[i] = v1 - v0;
+                d2[i] = v2 - v0;
+              }
+              T da[3] = {T(0), T(0), T(0)};
+              cross_acc(d1, e2, T(1), da);
+              cross_acc(e1, d2, T(1), da);
+              const T dl = (a2[0] * da[0] + a2[1] * da[1] + a2[2] * da[2]) / l;
+#pragma unroll
+              for (int i = 0; i < 3; ++i) acc[i] -= sc * dl * tv[i];
+            } else {
+              // this node's own block: -s/6 t (x) dl/dx_a
+              const int a = n[0] == g ? 0 : (n[1] == g ? 1 : 2);
+              const T nh[3] = {a2[0] / l, a2[1] / l, a2[2] / l};
+              T w[3];
+#pragma unroll
+              for (int i = 0; i < 3; ++i) w[i] = a == 0 ? e1[i] - e2[i] : (a == 1 ? e2[i] : T(0));
+              T ga[3] = {T(0), T(0), T(0)};
+              if (a == 2)
+                cross_acc(nh, e1, T(1), ga);
+              else
+                cross_acc(w, nh, T(1), ga);
+#pragma unroll
+              for (int i = 0; i < 3; ++i) {
+                if (OP == OP_DIAG)
+                  acc[i] -= sc * tv[i] * ga[i];
+                else
+                  acc[i] -= T(0.5) * sc * (tv[i] * ga[(i + 1) % 3] + ga[i] * tv[(i + 1) % 3]);
+              }
+            }
+          } else if (OP == OP_RES) {
             cross_acc(e1, e2, s, acc);
-          } else {
+          } else if (OP == OP_JV) {
             // the tangent has identity rows and columns on Dirichlet dofs:
             // v's prescribed components do not enter the coupling
             const uint32_t fm = A.nomask ? 0u : A.fmask[f];
@@ -96,7 +153,7 @@ __global__ __launch_bounds__(NT) void k_surface(SurfArgs<T> A) {
           }
         }
       } else {
-        const T *R = A.rgeo + 4 * int64_t(f - A.npf);
+        const T *R = A.rgeo + 4 * int64_t(f - A.npf - A.ntf);
         const T N[3] = {R[0], R[1], R[2]};
         const T area = R[3];
         const T kpar = T(A.kpar), dk = T(A.kperp - A.kpar);
@@ -156,6 +213,7 @@ void launch_surface(Ctx *c, int op, const T *u, const T *v, T *fs, double *red, 
   SurfArgs<T> A;
   A.nsn = S.nsn;
   A.npf = S.npf;
+  A.ntf = S.ntf;
   A.node = S.node;
   A.ptr = S.ptr;
   A.ent = S.ent;
@@ -164,7 +222,9 @@ void launch_surface(Ctx *c, int op, const T *u, const T *v, T *fs, double *red, 
   A.pgeo = pgeo;
   A.rgeo = rgeo;
   A.p = c->load_scale * S.p;
+  A.s = c->load_scale;
   A.plin = S.plin;
+  for (int i = 0; i < 3; ++i) A.tf[i] = S.tf[i];
   A.kperp = S.kperp;
   A.kpar = S.kpar;
   A.u = u;
@@ -216,7 +276,7 @@ void free_surface(Ctx *c) {
   for (void *p : S.allocs) dfree(c, p);
   S.allocs.clear();
   S.nsn = 0;
-  S.npf = S.nrf = 0;
+  S.npf = S.ntf = S.nrf = 0;
   S.node = S.ptr = S.ent = S.tri = nullptr;
   S.fmask = nullptr;
   S.pgeo64 = S.rgeo64 = S.plin = S.fs64 = nullptr;
@@ -228,12 +288,15 @@ nle_status build_surface(Ctx *c) {
   drop_graph(c);
   NLE_HIP(c, hipStreamSynchronize(c->stream));
   free_surface(c);
-  const int64_t npf = int64_t(S.h_ptri.size() / 3), nrf = int64_t(S.h_rtri.size() / 3);
+  const int64_t npf0 = int64_t(S.h_ptri.size() / 3), ntf = int64_t(S.h_ttri.size() / 3);
+  const int64_t nrf = int64_t(S.h_rtri.size() / 3);
+  const int64_t npf = npf0 + ntf;  // faces carrying reference coordinates
   if (npf + nrf == 0) return NLE_OK;
   if (npf + nrf >= (int64_t(1) << 31) / 3) return fail(c, NLE_E_UNSUPPORTED, "too many faces");
   const int64_t nn = c->m.n_nodes;
   const double *X = c->m.h_X.data();
   std::vector<int32_t> tri(S.h_ptri);
+  tri.insert(tri.end(), S.h_ttri.begin(), S.h_ttri.end());
   tri.insert(tri.end(), S.h_rtri.begin(), S.h_rtri.end());
   // incident faces of each node (CSR over nodes, faces in increasing order)
   std::vector<int32_t> cnt(nn + 1, 0);
@@ -278,7 +341,8 @@ nle_status build_surface(Ctx *c) {
   }
   std::vector<float> pg32(pg.begin(), pg.end()), rg32(rg.begin(), rg.end());
   hipError_t e = hipSuccess;
-  S.npf = int32_t(npf);
+  S.npf = int32_t(npf0);
+  S.ntf = int32_t(ntf);
   S.nrf = int32_t(nrf);
   S.nsn = int64_t(fnode.size());
   S.node = bupload(c, fnode, &e);
@@ -309,7 +373,7 @@ nle_status build_surface(Ctx *c) {
   // entries off the face nodes stay zero for good
   NLE_HIP(c, hipMemsetAsync(S.fs64, 0, size_t(3 * nn) * 8, c->stream));
   NLE_HIP(c, hipMemsetAsync(S.fs32, 0, size_t(3 * nn) * 4, c->stream));
-  NLE_HIP(c, hipMemsetAsync(S.plin, 0, 8, c->stream));
+  NLE_HIP(c, hipMemsetAsync(S.plin, 0, 16, c->stream));
   S.h_tri = tri;
   c->lin64 = c->lin32 = c->lc_valid = false;
   return upload_surface_masks(c);
@@ -332,6 +396,8 @@ hipError_t surf_set_linear_pressure(Ctx *c) {
   if (c->surf.nsn == 0) return hipSuccess;
   hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(64), 0, c->stream, c->surf.plin,
                      c->load_scale * c->surf.p);
+  hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(64), 0, c->stream, c->surf.plin + 1,
+                     c->load_scale);
   return hipGetLastError();
 }
 

@@ -48,7 +48,7 @@ EXPORTS = [
     "nle_solve_bfgs", "nle_partition_info", "nle_batch_create", "nle_batch_destroy",
     "nle_batch_last_error", "nle_batch_add", "nle_batch_finalize", "nle_batch_layout",
     "nle_batch_solve", "nle_set_fibres", "nle_set_active_tension", "nle_set_pressure",
-    "nle_set_robin", "nle_upload_mesh_mixed", "nle_block_diag", "nle_pc_apply", "nle_batch_autotune",
+    "nle_set_robin", "nle_set_traction_follower", "nle_upload_mesh_mixed", "nle_block_diag", "nle_pc_apply", "nle_batch_autotune",
 ]
 
 
@@ -116,6 +116,7 @@ def lib() -> ctypes.CDLL:
         "nle_set_active_tension": (I32, [P, D]),
         "nle_set_pressure": (I32, [P, I64, P, D]),
         "nle_set_robin": (I32, [P, I64, P, D, D]),
+        "nle_set_traction_follower": (I32, [P, I64, P, P]),
         "nle_lift": (I32, [P, P]),
         "nle_residual": (I32, [P, P, P, ctypes.POINTER(D)]),
         "nle_linearize": (I32, [P, P, I32]),
@@ -304,6 +305,12 @@ def nle_set_active_tension(ctx: Context, gamma: float) -> None:
 def nle_set_pressure(ctx: Context, tri, p: float) -> None:
     f, pf = _host(tri, np.int32)
     ctx.check(lib().nle_set_pressure(ctx.handle, f.shape[0] if f.size else 0, pf, float(p)))
+
+
+def nle_set_traction_follower(ctx: Context, tri, t) -> None:
+    f, pf = _host(tri, np.int32)
+    tt, pt = _host(t, np.float64)
+    ctx.check(lib().nle_set_traction_follower(ctx.handle, f.shape[0] if f.size else 0, pf, pt))
 
 
 def nle_set_robin(ctx: Context, tri, k_perp: float, k_par: float) -> None:

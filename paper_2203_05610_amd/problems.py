@@ -14,7 +14,11 @@ from . import nlelast as nl
 
 
 def setup_cook(ctx: nl.Context, mesh, mu: float, lam: float, tau: float = 1.0,
-               material: int = nl.NLE_MAT_M1, c_vol=None, block_size=None) -> None:
+               material: int = nl.NLE_MAT_M1, c_vol=None, block_size=None,
+               follower: bool = False) -> None:
+    """Cook's membrane (Sec. 4): clamp x = 0, shear traction (0, tau, 0) on
+    x = 48, per unit reference area (dead) or, with follower=True, per unit
+    current area with fixed direction."""
     if block_size is not None:
         nl.nle_set_block_size(ctx, block_size)
     nl.nle_upload_mesh(ctx, mesh.X, mesh.conn)
@@ -22,7 +26,10 @@ def setup_cook(ctx: nl.Context, mesh, mu: float, lam: float, tau: float = 1.0,
     nl.nle_set_material(ctx, material, params)
     dofs = mesh.dirichlet_dofs("clamp")
     nl.nle_set_dirichlet(ctx, dofs, np.zeros(dofs.size))
-    nl.nle_set_traction(ctx, mesh.faces["load"], [0.0, tau, 0.0])
+    if follower:
+        nl.nle_set_traction_follower(ctx, mesh.faces["load"], [0.0, tau, 0.0])
+    else:
+        nl.nle_set_traction(ctx, mesh.faces["load"], [0.0, tau, 0.0])
     nl.nle_set_load_scale(ctx, 1.0)
 
 
