@@ -373,6 +373,56 @@ def cardiac_c5(nl, torch, grid, methods, n_steps: int):
     return out
 
 
+FOLLOWER_METHODS = {
+    "ink_mixed": ("ink", "mixed", {"ksp": "gmres", "orth": "cgs2", "restart": 300}),
+    "nk_fp64": ("nk", "fp64", {"ksp": "gmres", "orth": "cgs2", "restart": 300}),
+    "bfgs_ib_mixed_r20": ("bfgs", "mixed", {"h0": "ksp", "qn_m": 10, "ksp": "gmres",
+                                            "orth": "cgs2", "restart": 300, "h0_refresh": 20}),
+}
+
+
+def follower_cook(nl, torch, grid, ratio: float, methods):
+    """Cook's membrane with the traction per unit current area (fixed
+    direction; the load in the deformed configuration), doubling schedule to
+    tau = 16, GMRES(300) + Jacobi (the tangent is not symmetric), at most 5000
+    Krylov iterations per linear solve."""
+    import synthetic as syn
+    from paper_2203_05610_amd import problems
+
+    mesh = syn.cook_mesh(*grid)
+    ctx = nl.Context(0)
+    problems.setup_cook(ctx, mesh, MU, ratio * MU, 1.0, follower=True)
+    sched = load_schedule()
+    out = {"workload": f"follower Cook {grid[0]}x{grid[1]}x{grid[2]} -> {mesh.n_elems} P1 tets, "
+                       f"{mesh.n_dofs} dofs, lambda/mu={ratio:g}, tau " + ",".join(f"{s:g}" for s in sched),
+           "methods": {}}
+    u = torch.zeros(mesh.n_dofs, dtype=torch.float64, device="cuda")
+    for m in methods:
+        name, prec, kw = FOLLOWER_METHODS[m]
+        opts = problems.make_opts(name, prec, **dict(kw))
+        opts.ksp_max_it = 5000
+        u.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        prev, ok, reps_all = 0.0, True, []
+        for s in sched:  # one call per load step so progress is printed
+            reps = problems.solve_schedule(ctx, u, name, opts, [s], start_scale=prev)
+            reps_all += reps
+            prev = s
+            print(f"[bench] follower {m} tau={s:g}: {reps[-1]['status_name']} "
+                  f"nit={[r['nit'] for r in reps]}", file=sys.stderr, flush=True)
+            if not problems.schedule_ok(reps, [s]):
+                ok = False
+                break
+        torch.cuda.synchronize()
+        out["methods"][m] = {"seconds": round(time.perf_counter() - t, 3), "ok": ok,
+                             "nit": [r["nit"] for r in reps_all],
+                             "lit": int(sum(r["lit_total"] for r in reps_all)),
+                             "cutbacks": sum(1 for r in reps_all if not r["accepted"])}
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -399,6 +449,10 @@ def main():
                     "8,80,256); empty skips this leg (minutes at full size)")
     ap.add_argument("--cardiac-methods", default="ink_fp64,bfgs_ib_fp64_r20_bj")
     ap.add_argument("--cardiac-steps", type=int, default=20)
+    ap.add_argument("--follower", default="", help="follower-load Cook grid nx,ny,nz (e.g. "
+                    "64,64,4; empty skips)")
+    ap.add_argument("--follower-ratio", type=float, default=5.0, help="lambda/mu of that leg")
+    ap.add_argument("--follower-methods", default="ink_mixed,nk_fp64,bfgs_ib_mixed_r20")
     ap.add_argument("--legs-only", action="store_true",
                     help="only the twist and cardiac legs (for their own runs)")
     ap.add_argument("--roofline-only", action="store_true",
@@ -440,6 +494,9 @@ def main():
         if args.cardiac:
             res["cardiac"] = cardiac_c5(nl, torch, tuple(int(x) for x in args.cardiac.split(",")),
                                         args.cardiac_methods.split(","), args.cardiac_steps)
+        if args.follower:
+            res["follower"] = follower_cook(nl, torch, tuple(int(x) for x in args.follower.split(",")),
+                                            args.follower_ratio, args.follower_methods.split(","))
         print(json.dumps(res))
         return
 
@@ -519,6 +576,10 @@ def main():
     if args.cardiac:
         cardiac = cardiac_c5(nl, torch, tuple(int(x) for x in args.cardiac.split(",")),
                              args.cardiac_methods.split(","), args.cardiac_steps)
+    follower = None
+    if args.follower:
+        follower = follower_cook(nl, torch, tuple(int(x) for x in args.follower.split(",")),
+                                 args.follower_ratio, args.follower_methods.split(","))
 
     cpu = None
     if not args.no_cpu:
@@ -559,6 +620,7 @@ def main():
         "batch": batch,
         "twist": twist,
         "cardiac": cardiac,
+        "follower": follower,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
