@@ -18,6 +18,8 @@ from .meshes import (  # noqa: F401
     cook_mesh,
     cube_mesh,
     twist_p2_mesh,
+    cook_p2_mesh,
+    p2_from_p1,
     shell_mesh,
     boundary_faces,
     COOK_CORNERS,

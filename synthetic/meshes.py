@@ -319,3 +319,29 @@ def shell_mesh(n_t: int = 8, n_s: int = 80, n_c: int = 256,
     fib /= np.linalg.norm(fib, axis=1)[:, None]
     return Mesh(X=X, conn=conn, sets=sets, faces=faces, elem_fibre=fib,
                 grid=(n_t, n_s, n_c), name=f"shell{n_t}x{n_s}x{n_c}")
+
+
+def p2_from_p1(mesh: Mesh) -> Mesh:
+    """Quadratic (10-node) version of a P1 mesh: one node at the midpoint of
+    every edge (straight-sided), appended after the vertices, which keep their
+    ids; conn[:, 4:] are the midpoints of edges (0,1), (1,2), (0,2), (0,3),
+    (1,3), (2,3).  Node sets are extended to a midpoint when both ends of its
+    edge belong to the set; faces keep their three vertex ids."""
+    c1 = np.asarray(mesh.conn)[:, :4].astype(np.int64)
+    ne = c1.shape[0]
+    ends = np.stack([np.sort(np.stack([c1[:, a], c1[:, b]], 1), axis=1) for a, b in P2_EDGES], 1)
+    flat = ends.reshape(-1, 2)
+    uniq, inv = np.unique(flat, axis=0, return_inverse=True)
+    n1 = mesh.n_nodes
+    X = np.vstack([mesh.X, 0.5 * (mesh.X[uniq[:, 0]] + mesh.X[uniq[:, 1]])])
+    conn = np.empty((ne, 10), dtype=np.int64)
+    conn[:, :4] = c1
+    conn[:, 4:] = n1 + inv.reshape(ne, 6)
+    sets = {k: np.concatenate([v, v[uniq[:, 0]] & v[uniq[:, 1]]]) for k, v in mesh.sets.items()}
+    return Mesh(X=X, conn=conn.astype(np.int32), sets=sets, faces=dict(mesh.faces),
+                elem_fibre=mesh.elem_fibre, grid=mesh.grid, name=mesh.name + "_p2")
+
+
+def cook_p2_mesh(nx: int, ny: int, nz: int) -> Mesh:
+    """Cook's membrane with quadratic tetrahedra (the P1 mesh's edges halved)."""
+    return p2_from_p1(cook_mesh(nx, ny, nz))
