@@ -3,6 +3,8 @@
 #include <cstring>
 #include <exception>
 #include <new>
+#include <unordered_map>
+#include <algorithm>
 
 #include "nle_internal.hpp"
 
@@ -275,8 +277,10 @@ nle_status nle_upload_mesh(nle_ctx *ctx, int64_t n_nodes, const double *X, int64
                            int32_t npe, const int32_t *conn) {
   Ctx *c = reinterpret_cast<Ctx *>(ctx);
   if (!c) return NLE_E_INVAL;
+  if (npe == 10)  // second-order displacement elements (no pressure field)
+    return nle_upload_mesh_mixed(ctx, n_nodes, X, n_elems, conn, 0, nullptr);
   return guarded(c, [&]() -> nle_status {
-    if (npe != 4) return fail(c, NLE_E_UNSUPPORTED, "only 4-node (P1) tetrahedra are supported");
+    if (npe != 4) return fail(c, NLE_E_UNSUPPORTED, "nodes_per_elem must be 4 or 10");
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, NLE_E_HIP, "hipSetDevice failed");
     c->has_mesh = false;
     drop_graph(c);
@@ -441,6 +445,41 @@ nle_status nle_set_traction(nle_ctx *ctx, int64_t nf, const int32_t *tri, const 
     if (nf < 0 || (nf > 0 && (!tri || !t))) return fail(c, NLE_E_INVAL, "bad traction arrays");
     std::vector<double> f(3 * c->m.n_nodes, 0.0);
     const double *X = c->m.h_X.data();
+    if (c->mixed) {
+      // flat 6-node faces: the quadratic shape functions integrate to 0 at
+      // the vertices and to A/3 at each edge midpoint
+      std::unordered_map<uint64_t, int32_t> mid;
+      const std::vector<int32_t> &cn = c->mx.h_conn;
+      static const int ea[6] = {0, 1, 0, 0, 1, 2}, eb[6] = {1, 2, 2, 3, 3, 3};
+      for (size_t e = 0; e + 9 < cn.size(); e += 10)
+        for (int q = 0; q < 6; ++q) {
+          const uint32_t va = uint32_t(cn[e + ea[q]]), vb = uint32_t(cn[e + eb[q]]);
+          mid[(uint64_t(std::min(va, vb)) << 32) | std::max(va, vb)] = cn[e + 4 + q];
+        }
+      for (int64_t k = 0; k < nf; ++k) {
+        const int32_t *v = tri + 3 * k;
+        for (int a = 0; a < 3; ++a)
+          if (v[a] < 0 || v[a] >= c->m.n_nodes) return fail(c, NLE_E_INVAL, "face node out of range");
+        double e1[3], e2[3];
+        for (int i = 0; i < 3; ++i) {
+          e1[i] = X[3 * v[1] + i] - X[3 * v[0] + i];
+          e2[i] = X[3 * v[2] + i] - X[3 * v[0] + i];
+        }
+        const double cx = e1[1] * e2[2] - e1[2] * e2[1];
+        const double cy = e1[2] * e2[0] - e1[0] * e2[2];
+        const double cz = e1[0] * e2[1] - e1[1] * e2[0];
+        const double area = 0.5 * std::sqrt(cx * cx + cy * cy + cz * cz);
+        static const int fa[3] = {0, 1, 0}, fb[3] = {1, 2, 2};
+        for (int q = 0; q < 3; ++q) {
+          const uint32_t va = uint32_t(v[fa[q]]), vb = uint32_t(v[fb[q]]);
+          auto it = mid.find((uint64_t(std::min(va, vb)) << 32) | std::max(va, vb));
+          if (it == mid.end()) return fail(c, NLE_E_INVAL, "face edge is not an element edge");
+          for (int i = 0; i < 3; ++i) f[3 * int64_t(it->second) + i] += t[i] * area / 3.0;
+        }
+      }
+      c->h_ftrac = f;
+      return rebuild_fext(c);
+    }
     for (int64_t k = 0; k < nf; ++k) {
       const int32_t *v = tri + 3 * k;
       for (int a = 0; a < 3; ++a)

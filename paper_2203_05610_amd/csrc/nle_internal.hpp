@@ -83,6 +83,7 @@ struct MixedMesh {
   double *mlump = nullptr;    // [n_p] lumped pressure mass
   void *cu = nullptr;         // [n_e*10][4] element contributions (double or float)
   void *cp = nullptr;         // [n_e*4]
+  std::vector<int32_t> h_conn;  // [n_e][10] (host, for the face loads)
 };
 
 struct Ctx;
@@ -235,8 +236,12 @@ nle_status fail(Ctx *c, nle_status code, const std::string &msg);
 inline int64_t ndof(const Ctx *c) { return 3 * c->m.n_nodes + (c->mixed ? c->mx.n_p : 0); }
 // The material must suit the mesh (M3 on mixed meshes only), and M4 needs fibres.
 inline nle_status need_fibres(Ctx *c) {
-  if ((c->mat.kind == NLE_MAT_M3) != c->mixed)
+  if (c->mixed && c->mx.n_p == 0) {
+    if (c->mat.kind != NLE_MAT_M1)
+      return fail(c, NLE_E_STATE, "quadratic displacement meshes support law M1");
+  } else if ((c->mat.kind == NLE_MAT_M3) != c->mixed) {
     return fail(c, NLE_E_STATE, "law M3 goes with a mixed mesh, the other laws with P1 meshes");
+  }
   if (c->mat.kind == NLE_MAT_M4 && !c->fib64)
     return fail(c, NLE_E_STATE, "law M4 needs nle_set_fibres");
   return NLE_OK;

@@ -19,6 +19,11 @@
 // The diagonal used by the preconditioner is that of the displacement block
 // and, on pressure rows, the lumped pressure mass over mu (the usual
 // spectrally equivalent stand-in for the Schur complement).
+//
+// The same elements without a pressure field (second-order displacement
+// elements, Sec. 6 tables) carry the compressible law M1:
+//   P = mu F + (lam ln J - mu) F^-T,
+//   dP = mu dF + (mu - lam ln J) F^-T dF^T F^-T + lam L F^-T.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -44,15 +49,17 @@ struct MixArgs {
   const uint8_t *umask;
   const T *x, *v;
   T *cu, *cp;
-  double mu;
+  double mu, lam;
   double *red;
   int32_t *flag;
   const int32_t *skip;
   int32_t nomask;
 };
 
-template <typename T, int OP>
+// LAW: NLE_MAT_M3 (with the linear pressure field) or NLE_MAT_M1 (none).
+template <typename T, int OP, int LAW>
 __global__ __launch_bounds__(NT) void k_mixed_elem(MixArgs<T> A) {
+  constexpr bool PRES = LAW == NLE_MAT_M3;
   __shared__ double sh[NT / 64];
   if (A.skip && A.skip[0] != 0) return;
   const int64_t e = int64_t(blockIdx.x) * NT + threadIdx.x;
@@ -60,11 +67,13 @@ __global__ __launch_bounds__(NT) void k_mixed_elem(MixArgs<T> A) {
   bool bad = false;
   if (e < A.ne) {
     const uint32_t ne = uint32_t(A.ne);
-    int32_t cn[10], pn[4];
+    int32_t cn[10], pn[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int a = 0; a < 10; ++a) cn[a] = A.conn[size_t(a) * ne + e];
+    if (PRES) {
 #pragma unroll
-    for (int b = 0; b < 4; ++b) pn[b] = A.pconn[size_t(b) * ne + e];
+      for (int b = 0; b < 4; ++b) pn[b] = A.pconn[size_t(b) * ne + e];
+    }
     T g[4][3];
 #pragma unroll
     for (int a = 1; a < 4; ++a)
@@ -73,7 +82,7 @@ __global__ __launch_bounds__(NT) void k_mixed_elem(MixArgs<T> A) {
 #pragma unroll
     for (int j = 0; j < 3; ++j) g[0][j] = -(g[1][j] + g[2][j] + g[3][j]);
     const double w = double(A.V[e]) * 0.25;
-    T U[10][3], W[10][3], P4[4], WP[4];
+    T U[10][3], W[10][3], P4[4] = {T(0), T(0), T(0), T(0)}, WP[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
     for (int a = 0; a < 10; ++a) {
       const uint32_t mk = (OP == OP_JV && !A.nomask) ? A.umask[cn[a]] : 0u;
@@ -83,10 +92,12 @@ __global__ __launch_bounds__(NT) void k_mixed_elem(MixArgs<T> A) {
         if (OP == OP_JV) W[a][i] = ((mk >> i) & 1u) ? T(0) : A.v[3 * int64_t(cn[a]) + i];
       }
     }
+    if (PRES) {
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      P4[b] = A.x[3 * A.nu + pn[b]];
-      if (OP == OP_JV) WP[b] = A.v[3 * A.nu + pn[b]];
+      for (int b = 0; b < 4; ++b) {
+        P4[b] = A.x[3 * A.nu + pn[b]];
+        if (OP == OP_JV) WP[b] = A.v[3 * A.nu + pn[b]];
+      }
     }
     T cu[10][3], cpv[4];
 #pragma unroll
@@ -96,6 +107,7 @@ __global__ __launch_bounds__(NT) void k_mixed_elem(MixArgs<T> A) {
 #pragma unroll
     for (int b = 0; b < 4; ++b) cpv[b] = T(0);
     const T mu = T(A.mu);
+    const double lamd = A.lam;
     for (int q = 0; q < 4; ++q) {
       T lam[4];
 #pragma unroll
@@ -136,11 +148,14 @@ __global__ __launch_bounds__(NT) void k_mixed_elem(MixArgs<T> A) {
 #pragma unroll
           for (int j = 0; j < 3; ++j) hh += double(H[i][j]) * double(H[i][j]);
         }
-        eacc += w * (0.5 * A.mu * (2.0 * trH + hh) - A.mu * k.lnJ - double(pq) * k.jm1);
+        if (PRES)
+          eacc += w * (0.5 * A.mu * (2.0 * trH + hh) - A.mu * k.lnJ - double(pq) * k.jm1);
+        else
+          eacc += w * (0.5 * A.mu * (2.0 * trH + hh) - A.mu * k.lnJ + 0.5 * lamd * k.lnJ * k.lnJ);
         continue;
       }
       if (OP == OP_RES) {
-        const T cT = -(mu + pq * J);
+        const T cT = PRES ? -(mu + pq * J) : T(lamd * k.lnJ - A.mu);
         T P[3][3];
 #pragma unroll
         for (int i = 0; i < 3; ++i)
@@ -151,9 +166,11 @@ __global__ __launch_bounds__(NT) void k_mixed_elem(MixArgs<T> A) {
 #pragma unroll
           for (int i = 0; i < 3; ++i)
             cu[a][i] += P[i][0] * gN[a][0] + P[i][1] * gN[a][1] + P[i][2] * gN[a][2];
-        const T rp = -T(w * k.jm1);
+        if (PRES) {
+          const T rp = -T(w * k.jm1);
 #pragma unroll
-        for (int b = 0; b < 4; ++b) cpv[b] += rp * lam[b];
+          for (int b = 0; b < 4; ++b) cpv[b] += rp * lam[b];
+        }
       } else if (OP == OP_JV) {
         T dF[3][3];
 #pragma unroll
@@ -180,7 +197,8 @@ __global__ __launch_bounds__(NT) void k_mixed_elem(MixArgs<T> A) {
           for (int j = 0; j < 3; ++j)
             M[r][j] = dF[0][r] * k.FiT[0][j] + dF[1][r] * k.FiT[1][j] + dF[2][r] * k.FiT[2][j];
         const T pJ = pq * J;
-        const T cX = mu + pJ, cT = -(pJ * L + dp * J);
+        const T cX = PRES ? mu + pJ : T(A.mu - lamd * k.lnJ);
+        const T cT = PRES ? -(pJ * L + dp * J) : T(lamd) * L;
         T dP[3][3];
 #pragma unroll
         for (int i = 0; i < 3; ++i)
@@ -194,17 +212,21 @@ __global__ __launch_bounds__(NT) void k_mixed_elem(MixArgs<T> A) {
 #pragma unroll
           for (int i = 0; i < 3; ++i)
             cu[a][i] += dP[i][0] * gN[a][0] + dP[i][1] * gN[a][1] + dP[i][2] * gN[a][2];
-        const T rp = -T(w) * J * L;
+        if (PRES) {
+          const T rp = -T(w) * J * L;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) cpv[b] += rp * lam[b];
-      } else {  // OP_DIAG: mu |g|^2 + mu ((F^-T g)_i)^2 (pressure terms cancel)
+          for (int b = 0; b < 4; ++b) cpv[b] += rp * lam[b];
+        }
+      } else {  // OP_DIAG: mu |g|^2 + mu ((F^-T g)_i)^2 (pressure terms cancel);
+                // law M1: mu |g|^2 + (mu - lam ln J + lam) ((F^-T g)_i)^2
+        const T ct = PRES ? mu : T(A.mu - lamd * k.lnJ + lamd);
 #pragma unroll
         for (int a = 0; a < 10; ++a) {
           const T gg = gN[a][0] * gN[a][0] + gN[a][1] * gN[a][1] + gN[a][2] * gN[a][2];
 #pragma unroll
           for (int i = 0; i < 3; ++i) {
             const T t = k.FiT[i][0] * gN[a][0] + k.FiT[i][1] * gN[a][1] + k.FiT[i][2] * gN[a][2];
-            cu[a][i] += T(w) * mu * (gg + t * t);
+            cu[a][i] += T(w) * (mu * gg + ct * t * t);
           }
         }
       }
@@ -214,7 +236,7 @@ __global__ __launch_bounds__(NT) void k_mixed_elem(MixArgs<T> A) {
       for (int a = 0; a < 10; ++a)
 #pragma unroll
         for (int i = 0; i < 3; ++i) A.cu[4 * (10 * e + a) + i] = cu[a][i];
-      if (OP != OP_DIAG) {
+      if (PRES && OP != OP_DIAG) {
 #pragma unroll
         for (int b = 0; b < 4; ++b) A.cp[4 * e + b] = cpv[b];
       }
@@ -334,6 +356,7 @@ int launch_mixed(Ctx *c, int op, const T *G, const T *V, const T *x, const T *v,
   A.cu = static_cast<T *>(M.cu);
   A.cp = static_cast<T *>(M.cp);
   A.mu = c->mat.mu;
+  A.lam = c->mat.lam;
   A.red = red;
   A.flag = c->dflag;
   A.skip = c->elem_skip;
@@ -343,21 +366,28 @@ int launch_mixed(Ctx *c, int op, const T *G, const T *V, const T *x, const T *v,
     *err = hipErrorInvalidValue;
     return 0;
   }
+  const bool pres = M.n_p > 0;
+#define NLE_MIXED_ELEM(OPV)                                                             \
+  if (pres)                                                                             \
+    hipLaunchKernelGGL((k_mixed_elem<T, OPV, NLE_MAT_M3>), dim3(g1), dim3(NT), 0, c->stream, A); \
+  else                                                                                  \
+    hipLaunchKernelGGL((k_mixed_elem<T, OPV, NLE_MAT_M1>), dim3(g1), dim3(NT), 0, c->stream, A)
   switch (op) {
     case OP_RES:
-      hipLaunchKernelGGL((k_mixed_elem<T, OP_RES>), dim3(g1), dim3(NT), 0, c->stream, A);
+      NLE_MIXED_ELEM(OP_RES);
       break;
     case OP_JV:
-      hipLaunchKernelGGL((k_mixed_elem<T, OP_JV>), dim3(g1), dim3(NT), 0, c->stream, A);
+      NLE_MIXED_ELEM(OP_JV);
       break;
     case OP_DIAG:
-      hipLaunchKernelGGL((k_mixed_elem<T, OP_DIAG>), dim3(g1), dim3(NT), 0, c->stream, A);
+      NLE_MIXED_ELEM(OP_DIAG);
       break;
     default:
-      hipLaunchKernelGGL((k_mixed_elem<T, OP_ENERGY>), dim3(g1), dim3(NT), 0, c->stream, A);
+      NLE_MIXED_ELEM(OP_ENERGY);
       *err = hipGetLastError();
       return g1;
   }
+#undef NLE_MIXED_ELEM
   *err = hipGetLastError();
   if (*err != hipSuccess) return 0;
   GatherArgs<T> B;
@@ -439,15 +469,17 @@ nle_status upload_mixed_masks(Ctx *c) {
 
 nle_status build_mixed_mesh(Ctx *c, int64_t nu, const double *X, int64_t ne, const int32_t *conn,
                             int64_t np, const int32_t *pconn) {
-  if (nu <= 0 || ne <= 0 || np <= 0) return fail(c, NLE_E_INVAL, "empty mixed mesh");
-  if (!X || !conn || !pconn) return fail(c, NLE_E_INVAL, "null mesh array");
+  // np == 0: second-order displacement elements without a pressure field
+  if (nu <= 0 || ne <= 0 || np < 0) return fail(c, NLE_E_INVAL, "empty mixed mesh");
+  if (!X || !conn || (np > 0 && !pconn)) return fail(c, NLE_E_INVAL, "null mesh array");
   if (nu >= (int64_t(1) << 28) || np >= (int64_t(1) << 28) || 10 * ne >= (int64_t(1) << 31))
     return fail(c, NLE_E_UNSUPPORTED, "mixed mesh too large");
   for (int64_t k = 0; k < 10 * ne; ++k)
     if (conn[k] < 0 || conn[k] >= nu) return fail(c, NLE_E_BADMESH, "node index out of range");
-  for (int64_t k = 0; k < 4 * ne; ++k)
-    if (pconn[k] < 0 || pconn[k] >= np)
-      return fail(c, NLE_E_BADMESH, "pressure node index out of range");
+  if (np > 0)
+    for (int64_t k = 0; k < 4 * ne; ++k)
+      if (pconn[k] < 0 || pconn[k] >= np)
+        return fail(c, NLE_E_BADMESH, "pressure node index out of range");
   for (int64_t i = 0; i < 3 * nu; ++i)
     if (!std::isfinite(X[i])) return fail(c, NLE_E_BADMESH, "non-finite coordinate");
   // vertex geometry: rows of D^-1, D = [X1-X0, X2-X0, X3-X0]
@@ -485,10 +517,11 @@ nle_status build_mixed_mesh(Ctx *c, int64_t nu, const double *X, int64_t ne, con
     V[e] = det / 6.0;
     V32[e] = float(V[e]);
   }
-  std::vector<int32_t> cs(10 * ne), ps(4 * ne);
+  std::vector<int32_t> cs(10 * ne), ps(np > 0 ? 4 * ne : 0);
   for (int64_t e = 0; e < ne; ++e) {
     for (int a = 0; a < 10; ++a) cs[size_t(a) * ne + e] = conn[10 * e + a];
-    for (int b = 0; b < 4; ++b) ps[size_t(b) * ne + e] = pconn[4 * e + b];
+    if (np > 0)
+      for (int b = 0; b < 4; ++b) ps[size_t(b) * ne + e] = pconn[4 * e + b];
   }
   // node-centred entry lists (entries in increasing element order)
   auto csr = [](int64_t n, const int32_t *cn, int per, int64_t ne_, std::vector<int32_t> *ptr,
@@ -502,10 +535,14 @@ nle_status build_mixed_mesh(Ctx *c, int64_t nu, const double *X, int64_t ne, con
   };
   std::vector<int32_t> uptr, uent, pptr, pent;
   csr(nu, conn, 10, ne, &uptr, &uent);
-  csr(np, pconn, 4, ne, &pptr, &pent);
   std::vector<double> ml(np, 0.0);
-  for (int64_t e = 0; e < ne; ++e)
-    for (int b = 0; b < 4; ++b) ml[pconn[4 * e + b]] += V[e] / 4.0;
+  if (np > 0) {
+    csr(np, pconn, 4, ne, &pptr, &pent);
+    for (int64_t e = 0; e < ne; ++e)
+      for (int b = 0; b < 4; ++b) ml[pconn[4 * e + b]] += V[e] / 4.0;
+  } else {
+    pptr.assign(1, 0);
+  }
 
   for (void *p : c->mesh_allocs) dfree(c, p);
   c->mesh_allocs.clear();
@@ -518,6 +555,7 @@ nle_status build_mixed_mesh(Ctx *c, int64_t nu, const double *X, int64_t ne, con
   M.n_u = nu;
   M.n_p = np;
   M.n_e = ne;
+  M.h_conn.assign(conn, conn + 10 * ne);
   hipError_t herr = hipSuccess;
   M.conn = mupload(c, cs, &herr);
   M.pconn = mupload(c, ps, &herr);

@@ -214,3 +214,15 @@ def solve_twist(ctx: nl.Context, x, method: str, opts, angles, dirichlet, hist_c
 def twist_ok(reps, angles) -> bool:
     acc = [r["theta"] for r in reps if r["accepted"]]
     return bool(acc) and acc[-1] == float(angles[-1])
+
+
+def setup_cook_p2(ctx: nl.Context, mesh2, mu: float, lam: float, tau: float = 1.0) -> None:
+    """Cook's membrane with quadratic (10-node) displacement tetrahedra, law
+    M1, clamped on x = 0 (vertices and edge midpoints), dead shear traction
+    (0, tau, 0) on x = 48 (consistent P2 loads)."""
+    nl.nle_upload_mesh(ctx, mesh2.X, mesh2.conn)
+    nl.nle_set_material(ctx, nl.NLE_MAT_M1, [mu, lam])
+    dofs = mesh2.dirichlet_dofs("clamp")
+    nl.nle_set_dirichlet(ctx, dofs, np.zeros(dofs.size))
+    nl.nle_set_traction(ctx, mesh2.faces["load"], [0.0, tau, 0.0])
+    nl.nle_set_load_scale(ctx, 1.0)

@@ -1,0 +1,106 @@
+"""GPU parity of the quadratic-displacement (10-node) Cook problem with law M1
+(the second-order elements of the paper's Sec. 6 tables) against the FP64
+oracle: residual, Jacobian action (FP64, FP32), diagonal and potential at
+seeded states, and NK / iNK / inexact-BFGS solves against the oracle's
+exact-Newton root.
+
+Tolerances: kernels FP64 <= 1e-12 (max-norm relative to the largest entry),
+FP32 Jacobian action <= 1e-5 (2-norm); solutions <= 1e-8 (FP64 at a 1e-11
+stopping rule) and <= 1e-6 (mixed).
+"""
+
+import numpy as np
+import pytest
+
+import synthetic as syn
+from oracle import newton, p2
+from tests.gpu_common import MU, relmax, relnorm
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2203_05610_amd import nlelast as nl  # noqa: E402
+from paper_2203_05610_amd import problems  # noqa: E402
+
+
+def _t(x, dtype=torch.float64):
+    return torch.tensor(np.asarray(x), dtype=dtype, device="cuda")
+
+
+def _setup(nx, ny, nz, ratio, tau=1.0):
+    mesh = syn.cook_p2_mesh(nx, ny, nz)
+    P = p2.cook_p2_problem(mesh, mu=MU, lam=ratio * MU, tau=tau)
+    ctx = nl.Context(0)
+    problems.setup_cook_p2(ctx, mesh, MU, ratio * MU, tau)
+    return mesh, P, ctx
+
+
+def _state(mesh, P, seed, amp=0.01):
+    rng = np.random.default_rng(seed)
+    A = amp * rng.standard_normal((3, 3))
+    u = (mesh.X @ A.T).reshape(-1) + 0.002 * rng.standard_normal(P.n_dofs)
+    return P.lift(u)
+
+
+@pytest.mark.parametrize("grid", [(3, 2, 1, 5.0), (6, 5, 2, 500.0)])
+def test_p2_kernels_parity(grid):
+    mesh, P, ctx = _setup(*grid)
+    assert ctx.n_dofs == P.n_dofs
+    u = _state(mesh, P, seed=7)
+    for s in (0.4, 1.0):
+        nl.nle_set_load_scale(ctx, s)
+        r = torch.empty(P.n_dofs, dtype=torch.float64, device="cuda")
+        rn = nl.nle_residual(ctx, _t(u), r)
+        ref = P.residual(u, s)
+        assert relmax(r.cpu().numpy(), ref) < 1e-12, s
+        assert abs(rn - np.linalg.norm(ref)) <= 1e-12 * np.linalg.norm(ref)
+        pi = nl.nle_energy(ctx, _t(u))
+        assert abs(pi - P.energy(u, s)) <= 1e-12 * abs(P.energy(u, s))
+    nl.nle_linearize(ctx, _t(u), nl.NLE_FP32)
+    K = P.stiffness(u)
+    v = syn.random_field(P.n_dofs, 1.0, seed=8)
+    y = torch.empty(P.n_dofs, dtype=torch.float64, device="cuda")
+    nl.nle_jv(ctx, _t(v), y, nl.NLE_FP64)
+    assert relmax(y.cpu().numpy(), K @ v) < 1e-12
+    y32 = torch.empty(P.n_dofs, dtype=torch.float32, device="cuda")
+    nl.nle_jv(ctx, _t(v, torch.float32), y32, nl.NLE_FP32)
+    assert relnorm(y32.double().cpu().numpy(), K @ v) < 1e-5
+    d = torch.empty(P.n_dofs, dtype=torch.float64, device="cuda")
+    nl.nle_diag(ctx, d)
+    assert relmax(d.cpu().numpy(), K.diagonal()) < 1e-12
+
+
+def test_p2_usage_errors():
+    mesh, P, ctx = _setup(2, 2, 1, 5.0)
+    nl.nle_set_material(ctx, nl.NLE_MAT_M2, [MU, 5 * MU])
+    x = torch.zeros(P.n_dofs, dtype=torch.float64, device="cuda")
+    with pytest.raises(nl.NleError) as e:
+        nl.nle_residual(ctx, x, torch.empty_like(x))
+    assert e.value.status == nl.NLE_E_STATE
+    nl.nle_set_material(ctx, nl.NLE_MAT_M1, [MU, 5 * MU])
+    # a triangle whose edges are not element edges has no midpoints
+    with pytest.raises(nl.NleError) as e:
+        nl.nle_set_traction(ctx, np.array([[0, 5, 40]], dtype=np.int32), [0.0, 1.0, 0.0])
+    assert e.value.status == nl.NLE_E_INVAL
+
+
+SOLVES = [
+    ("nk", "fp64", {"ksp": "cg"}),
+    ("ink", "mixed", {"ksp": "cg"}),
+    ("bfgs", "mixed", {"h0": "ksp", "qn_m": 10, "ksp": "cg", "h0_refresh": 10}),
+]
+
+
+@pytest.mark.parametrize("method,prec,kw", SOLVES)
+def test_p2_cook_solves_match_oracle(method, prec, kw):
+    mesh, P, ctx = _setup(4, 4, 1, 5.0, tau=2.0)
+    scales = [0.5, 1.0]
+    ustar = newton.solve_schedule(P, scales)[0]
+    u = torch.zeros(P.n_dofs, dtype=torch.float64, device="cuda")
+    opts = problems.make_opts(method, prec, **dict(kw))
+    tight = prec == "fp64"
+    if tight:
+        opts.snes_rtol = 1e-11
+    reps = problems.solve_schedule(ctx, u, method, opts, scales)
+    assert problems.schedule_ok(reps, scales), [(r["load_scale"], r["status_name"]) for r in reps]
+    assert relnorm(u.cpu().numpy(), ustar) <= (1e-8 if tight else 1e-6)
