@@ -423,6 +423,53 @@ def follower_cook(nl, torch, grid, ratio: float, methods):
     return out
 
 
+P2_METHODS = {
+    "ink_mixed": ("ink", "mixed", {"ksp": "cg"}),
+    "nk_fp64": ("nk", "fp64", {"ksp": "minres"}),
+    "bfgs_ib_mixed_r20": ("bfgs", "mixed", {"h0": "ksp", "qn_m": 10, "ksp": "minres",
+                                            "h0_refresh": 20}),
+}
+
+
+def p2_cook(nl, torch, grid, ratio: float, methods):
+    """Cook's membrane with quadratic (10-node) displacement tetrahedra, law
+    M1, dead traction, doubling schedule to tau = 16, Jacobi-preconditioned."""
+    import synthetic as syn
+    from paper_2203_05610_amd import problems
+
+    mesh = syn.cook_p2_mesh(*grid)
+    ctx = nl.Context(0)
+    problems.setup_cook_p2(ctx, mesh, MU, ratio * MU, 1.0)
+    sched = load_schedule()
+    out = {"workload": f"P2 Cook {grid[0]}x{grid[1]}x{grid[2]} -> {mesh.n_elems} 10-node tets, "
+                       f"{mesh.n_dofs} dofs, lambda/mu={ratio:g}, tau " + ",".join(f"{s:g}" for s in sched),
+           "methods": {}}
+    u = torch.zeros(mesh.n_dofs, dtype=torch.float64, device="cuda")
+    for m in methods:
+        name, prec, kw = P2_METHODS[m]
+        opts = problems.make_opts(name, prec, **dict(kw))
+        u.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        prev, ok, reps_all = 0.0, True, []
+        for s in sched:
+            reps = problems.solve_schedule(ctx, u, name, opts, [s], start_scale=prev)
+            reps_all += reps
+            prev = s
+            print(f"[bench] p2 {m} tau={s:g}: {reps[-1]['status_name']} "
+                  f"nit={[r['nit'] for r in reps]}", file=sys.stderr, flush=True)
+            if not problems.schedule_ok(reps, [s]):
+                ok = False
+                break
+        torch.cuda.synchronize()
+        out["methods"][m] = {"seconds": round(time.perf_counter() - t, 3), "ok": ok,
+                             "nit": [r["nit"] for r in reps_all],
+                             "lit": int(sum(r["lit_total"] for r in reps_all)),
+                             "cutbacks": sum(1 for r in reps_all if not r["accepted"])}
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -453,6 +500,9 @@ def main():
                     "64,64,4; empty skips)")
     ap.add_argument("--follower-ratio", type=float, default=5.0, help="lambda/mu of that leg")
     ap.add_argument("--follower-methods", default="ink_mixed,nk_fp64,bfgs_ib_mixed_r20")
+    ap.add_argument("--p2", default="", help="P2 Cook grid nx,ny,nz (e.g. 32,32,2; empty skips)")
+    ap.add_argument("--p2-ratio", type=float, default=5.0, help="lambda/mu of that leg")
+    ap.add_argument("--p2-methods", default="ink_mixed,nk_fp64,bfgs_ib_mixed_r20")
     ap.add_argument("--legs-only", action="store_true",
                     help="only the twist and cardiac legs (for their own runs)")
     ap.add_argument("--roofline-only", action="store_true",
@@ -497,6 +547,9 @@ def main():
         if args.follower:
             res["follower"] = follower_cook(nl, torch, tuple(int(x) for x in args.follower.split(",")),
                                             args.follower_ratio, args.follower_methods.split(","))
+        if args.p2:
+            res["p2"] = p2_cook(nl, torch, tuple(int(x) for x in args.p2.split(",")), args.p2_ratio,
+                                args.p2_methods.split(","))
         print(json.dumps(res))
         return
 
@@ -580,6 +633,10 @@ def main():
     if args.follower:
         follower = follower_cook(nl, torch, tuple(int(x) for x in args.follower.split(",")),
                                  args.follower_ratio, args.follower_methods.split(","))
+    p2 = None
+    if args.p2:
+        p2 = p2_cook(nl, torch, tuple(int(x) for x in args.p2.split(",")), args.p2_ratio,
+                     args.p2_methods.split(","))
 
     cpu = None
     if not args.no_cpu:
@@ -621,6 +678,7 @@ def main():
         "twist": twist,
         "cardiac": cardiac,
         "follower": follower,
+        "p2": p2,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
