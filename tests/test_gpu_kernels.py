@@ -130,6 +130,41 @@ def test_full_size_cook_parity_in_bench_configuration():
     assert relnorm(y32.double().cpu().numpy(), ref) < 1e-5
 
 
+def test_cook_xl_sampled_parity_in_roofline_configuration():
+    # 256x256x16 (6,291,456 tets, 1,122,833 nodes), the Jacobian action the
+    # roofline measurement times (default block size, lambda/mu = 5000, clamp,
+    # no load): residual and J v at 3000 sampled nodes against the oracle on
+    # the elements that touch them (every contribution to those nodes)
+    mesh = syn.cook_mesh(256, 256, 16, with_faces=False)
+    ctx = nl.Context(0)
+    nl.nle_upload_mesh(ctx, mesh.X, mesh.conn)
+    nl.nle_set_material(ctx, nl.NLE_MAT_M1, [MU, 5000 * MU])
+    d = mesh.dirichlet_dofs("clamp")
+    nl.nle_set_dirichlet(ctx, d, np.zeros(d.size))
+    rng = np.random.default_rng(21)
+    A = 0.003 * rng.standard_normal((3, 3))
+    u_h = (mesh.X @ A.T).reshape(-1)
+    u_h[d] = 0.0
+    v_h = rng.standard_normal(mesh.n_dofs)
+    r = torch.empty(mesh.n_dofs, dtype=torch.float64, device="cuda")
+    nl.nle_residual(ctx, _t(u_h), r)
+    nl.nle_linearize(ctx, _t(u_h), nl.NLE_FP32)
+    y = torch.empty_like(r)
+    nl.nle_jv(ctx, _t(v_h), y, nl.NLE_FP64)
+    y32 = torch.empty(mesh.n_dofs, dtype=torch.float32, device="cuda")
+    nl.nle_jv(ctx, _t(v_h, torch.float32), y32, nl.NLE_FP32)
+    nodes = np.unique(rng.integers(0, mesh.n_nodes, 3000))
+    touch = np.isin(mesh.conn, nodes).any(axis=1)
+    sub = fem.Problem(mesh.X, mesh.conn[touch], "M1", (MU, 5000 * MU), np.zeros(mesh.n_dofs), d,
+                      np.zeros(d.size))
+    dofs = (3 * nodes[:, None] + np.arange(3)[None, :]).reshape(-1)
+    ref_r = sub.residual(u_h)[dofs]
+    ref_y = (sub.stiffness(u_h) @ v_h)[dofs]
+    assert relmax(r.cpu().numpy()[dofs], ref_r) < 1e-12
+    assert relmax(y.cpu().numpy()[dofs], ref_y) < 1e-12
+    assert relnorm(y32.double().cpu().numpy()[dofs], ref_y) < 1e-5
+
+
 def test_single_element_and_fully_constrained():
     X = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], float)
     conn = np.array([[0, 1, 2, 3]], np.int32)
