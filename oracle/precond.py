@@ -37,9 +37,22 @@ def node_blocks(K, n_nodes: int) -> np.ndarray:
 
 
 def block_jacobi_apply(blocks: np.ndarray, x: np.ndarray) -> np.ndarray:
-    """z with blocks[k] z_k = x_k for every node k (z, x node-interleaved)."""
+    """z with blocks[k] z_k = x_k for every node k (z, x node-interleaved).
+
+    A block that is not positive definite (some leading principal minor
+    <= 0) is replaced by its diagonal, so the preconditioner is positive
+    definite wherever point Jacobi is (the reading of the nodal block Jacobi
+    used here)."""
+    B = np.array(blocks, dtype=np.float64, copy=True)
+    m1 = B[:, 0, 0]
+    m2 = B[:, 0, 0] * B[:, 1, 1] - B[:, 0, 1] * B[:, 1, 0]
+    m3 = np.linalg.det(B)
+    bad = ~((m1 > 0) & (m2 > 0) & (m3 > 0))
+    if np.any(bad):
+        diag = np.einsum("kii->ki", B[bad])
+        B[bad] = np.einsum("ki,ij->kij", diag, np.eye(3))
     xk = np.asarray(x, dtype=np.float64).reshape(-1, 3)
-    return np.linalg.solve(blocks, xk[:, :, None])[:, :, 0].reshape(-1)
+    return np.linalg.solve(B, xk[:, :, None])[:, :, 0].reshape(-1)
 
 
 def point_jacobi_apply(K, x: np.ndarray) -> np.ndarray:

@@ -314,7 +314,6 @@ int vec_dot_partials(Ctx *c, int prec, const void *a, const void *b, int64_t n, 
 // single-workgroup fixed-order sum of red[0..np) (stride 1) -> out[0]
 hipError_t reduce_scalar(Ctx *c, const double *red, int np, double *out);
 hipError_t reduce_scalars(Ctx *c, const double *red, int np, int count, double *out);
-hipError_t vec_mul(Ctx *c, int prec, const void *a, const void *b, void *y, int64_t n);
 hipError_t vec_recip(Ctx *c, const double *d, double *dinv, int64_t n);
 // y = M^-1 x with pcb = 1 (d: inverse diagonal, identity if null) or
 // pcb = 3 (d: nodal block inverses [6][n/3], see block_inverse)

@@ -60,12 +60,6 @@ __global__ __launch_bounds__(NT) void k_axpy(const S *x, D *y, double a, const d
     y[i] = D(double(y[i]) + alpha * double(x[i]));
 }
 
-template <typename T>
-__global__ __launch_bounds__(NT) void k_mul(const T *a, const T *b, T *y, int64_t n) {
-  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT)
-    y[i] = a[i] * b[i];
-}
-
 __global__ __launch_bounds__(NT) void k_recip(const double *d, double *di, int64_t n) {
   for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT)
     di[i] = 1.0 / d[i];
@@ -153,7 +147,11 @@ __global__ __launch_bounds__(NT) void k_pc_apply(const T *d, const T *x, T *y, i
 
 // Symmetric 3x3 block inverses from the diagonal (d: xx yy zz per node,
 // interleaved) and off-diagonal entries (o: xy yz zx per node), by cofactors
-// in FP64; written as [6][nn] in FP64 and FP32.
+// in FP64; written as [6][nn] in FP64 and FP32.  A block that is not positive
+// definite (a leading principal minor <= 0, as happens at nodes of a loaded
+// tangent that has turned indefinite) gives that node the point-Jacobi
+// entries instead, so the preconditioner stays symmetric positive definite
+// wherever point Jacobi is.
 __global__ __launch_bounds__(NT) void k_block_inv(const double *d, const double *o, double *b64,
                                                   float *b32, int64_t nn) {
   UNIT_LOOP(k, nn) {
@@ -164,8 +162,15 @@ __global__ __launch_bounds__(NT) void k_block_inv(const double *d, const double 
     const double c01 = a02 * a12 - a01 * a22, c12 = a01 * a02 - a00 * a12;
     const double c02 = a01 * a12 - a02 * a11;
     const double det = a00 * c00 + a01 * c01 + a02 * c02;
-    const double id = 1.0 / det;
-    const double v[6] = {c00 * id, c11 * id, c22 * id, c01 * id, c12 * id, c02 * id};
+    double v[6];
+    if (a00 > 0.0 && c22 > 0.0 && det > 0.0) {
+      const double id = 1.0 / det;
+      v[0] = c00 * id, v[1] = c11 * id, v[2] = c22 * id;
+      v[3] = c01 * id, v[4] = c12 * id, v[5] = c02 * id;
+    } else {
+      v[0] = 1.0 / a00, v[1] = 1.0 / a11, v[2] = 1.0 / a22;
+      v[3] = v[4] = v[5] = 0.0;
+    }
 #pragma unroll
     for (int t = 0; t < 6; ++t) {
       b64[t * nn + k] = v[t];
@@ -789,16 +794,6 @@ hipError_t vec_axpy(Ctx *c, int px, const void *x, int py, void *y, double a, co
     LAUNCH((k_axpy<double, float>), g, static_cast<const double *>(x), static_cast<float *>(y), a, ad, n);
   else
     LAUNCH((k_axpy<float, float>), g, static_cast<const float *>(x), static_cast<float *>(y), a, ad, n);
-  return hipGetLastError();
-}
-
-hipError_t vec_mul(Ctx *c, int prec, const void *a, const void *b, void *y, int64_t n) {
-  if (prec == NLE_FP32)
-    LAUNCH(k_mul<float>, vgrid(n), static_cast<const float *>(a), static_cast<const float *>(b),
-           static_cast<float *>(y), n);
-  else
-    LAUNCH(k_mul<double>, vgrid(n), static_cast<const double *>(a), static_cast<const double *>(b),
-           static_cast<double *>(y), n);
   return hipGetLastError();
 }
 

@@ -93,3 +93,13 @@ def test_pcg_with_block_jacobi_solves_the_system():
     xp, itp = precond.pcg(K, b, lambda r: precond.point_jacobi_apply(K, r), rtol=1e-12)
     assert np.linalg.norm(xp - xd) <= 1e-9 * np.linalg.norm(xd)
     assert its < 400 and itp < 400
+
+
+def test_indefinite_block_falls_back_to_its_diagonal():
+    # an indefinite block (eigenvalues 3, -1, 2) next to an SPD one
+    Bi = np.array([[1.0, 2.0, 0.0], [2.0, 1.0, 0.0], [0.0, 0.0, 2.0]])
+    Bs = np.array([[4.0, 1.0, 0.0], [1.0, 3.0, 0.5], [0.0, 0.5, 2.0]])
+    x = np.array([1.0, -2.0, 0.5, 0.3, 0.7, -1.1])
+    z = precond.block_jacobi_apply(np.stack([Bi, Bs]), x)
+    assert np.allclose(z[:3], x[:3] / np.diag(Bi), rtol=1e-15)
+    assert np.allclose(Bs @ z[3:], x[3:], rtol=1e-14)
