@@ -214,6 +214,8 @@ class Problem:
     # the load scale like f_ext
     ftrac_tri: Optional[np.ndarray] = None
     ftrac: tuple = (0.0, 0.0, 0.0)
+    # inertia of an implicit time step (set_inertia): (c, m per dof, u_tilde)
+    inertia: Optional[tuple] = None
 
     def __post_init__(self):
         self.conn = np.asarray(self.conn)[:, :4].astype(np.int64)
@@ -228,6 +230,22 @@ class Problem:
         self.R = (robin_matrix(self.X, np.asarray(self.robin_tri), self.k_perp, self.k_par)
                   if self.robin_tri is not None else None)
 
+    def lumped_mass(self, rho: float) -> np.ndarray:
+        """Row-sum lumped P1 mass per dof: rho V / 4 from each element to each
+        of its vertices (every component)."""
+        m = np.zeros(self.n_nodes)
+        np.add.at(m, self.conn.reshape(-1), np.repeat(rho * self.V / 4.0, 4))
+        return np.repeat(m, 3)
+
+    def set_inertia(self, rho: float, c: float, u_tilde: np.ndarray) -> None:
+        """Add c M (u - u_tilde) to the residual (M lumped with density rho):
+        the inertia of an implicit Newmark step with c = 1 / (beta dt^2).
+        rho = 0 or c = 0 removes it."""
+        if rho == 0.0 or c == 0.0:
+            self.inertia = None
+        else:
+            self.inertia = (c, self.lumped_mass(rho), np.array(u_tilde, dtype=np.float64))
+
     def surface_force(self, u: np.ndarray, load_scale: float = 1.0) -> np.ndarray:
         """Residual contribution of the follower pressure and the springs."""
         out = np.zeros(self.n_dofs)
@@ -239,6 +257,9 @@ class Problem:
         if self.ftrac_tri is not None:
             out -= load_scale * follower_traction(self.X, u, np.asarray(self.ftrac_tri),
                                                   self.ftrac)
+        if self.inertia is not None:
+            c, m, ut = self.inertia
+            out += c * m * (u - ut)
         return out
 
     # -- evaluation -------------------------------------------------------
@@ -267,7 +288,11 @@ class Problem:
             raise ValueError("a follower load has no potential")
         psi = materials.energy(self.material, F, self.params)
         springs = 0.5 * float(u @ (self.R @ u)) if self.R is not None else 0.0
-        return float(np.sum(self.V * psi) - load_scale * np.dot(self.f_ext, u)) + springs
+        kin = 0.0
+        if self.inertia is not None:
+            c, m, ut = self.inertia
+            kin = 0.5 * c * float(np.sum(m * (u - ut) ** 2))
+        return float(np.sum(self.V * psi) - load_scale * np.dot(self.f_ext, u)) + springs + kin
 
     # -- tangent ----------------------------------------------------------
     def element_stiffness(self, u: np.ndarray) -> np.ndarray:
@@ -293,6 +318,8 @@ class Problem:
         if self.ftrac_tri is not None:
             K = K - load_scale * follower_traction_jacobian(self.X, u, np.asarray(self.ftrac_tri),
                                                             self.ftrac)
+        if self.inertia is not None:
+            K = K + sp.diags(self.inertia[0] * self.inertia[1])
         if dirichlet:
             Dfree = sp.diags(self.free.astype(np.float64))
             K = (Dfree @ K @ Dfree + sp.diags(self.fixed.astype(np.float64))).tocsr()

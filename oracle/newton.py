@@ -64,6 +64,44 @@ def solve_schedule(problem, scales, u0=None, **kw):
     return u, hists
 
 
+def newmark_predict(u, v, a, dt: float, beta: float):
+    """Newmark predictor u~ = u + dt v + dt^2 (1/2 - beta) a."""
+    return u + dt * v + dt * dt * (0.5 - beta) * a
+
+
+def newmark_correct(u_new, u_tilde, v, a, dt: float, beta: float, gamma: float):
+    """Newmark corrector: a' = (u' - u~) / (beta dt^2), v' = v + dt ((1 - gamma) a + gamma a')."""
+    a_new = (u_new - u_tilde) / (beta * dt * dt)
+    return v + dt * ((1.0 - gamma) * a + gamma * a_new), a_new
+
+
+def solve_heartbeat_dynamic(problem, schedule, gamma_max: float, rho: float, dt: float,
+                            beta: float = 0.25, gamma: float = 0.5, u0=None, **kw):
+    """Heartbeat with inertia (Sec. 2, eq. "momentum strong" with the
+    acceleration kept): Newmark's average-acceleration rule (beta = 1/4,
+    gamma = 1/2) with the lumped mass of density rho; each step sets the
+    activation of its time as in solve_heartbeat and solves the implicit step
+    c M (u - u~) + r(u) = 0, c = 1 / (beta dt^2), by exact Newton.  Starts at
+    rest.  Returns (u, v, a, Newton histories)."""
+    from .fem import set_active_tension
+
+    n = problem.n_dofs
+    u = np.zeros(n) if u0 is None else np.array(u0, dtype=np.float64)
+    v = np.zeros(n)
+    a = np.zeros(n)
+    c = 1.0 / (beta * dt * dt)
+    hists = []
+    for _, shape in schedule:
+        ut = newmark_predict(u, v, a, dt, beta)
+        problem.set_inertia(rho, c, ut)
+        set_active_tension(problem, gamma_max * shape)
+        u, h = newton_exact(problem, u, shape, **kw)
+        v, a = newmark_correct(u, ut, v, a, dt, beta, gamma)
+        hists.append(h)
+    problem.set_inertia(0.0, 0.0, u)
+    return u, v, a, hists
+
+
 def solve_heartbeat(problem, schedule, gamma_max: float, u0=None, **kw):
     """Quasi-static heartbeat (Sec. 4): for each time step (t, shape) set the
     active tension gamma_max * shape and the pressure load scale shape, then

@@ -1,0 +1,79 @@
+"""Pins of the oracle's implicit dynamics (lumped mass, Newmark's average
+acceleration rule): the lumped mass equals density times volume; the
+residual with inertia is the gradient of the incremental potential; and a
+small-amplitude free vibration follows the linear average-acceleration
+recursion written out with the independent small-strain stiffness (which
+conserves the energy exactly)."""
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import synthetic as syn
+from oracle import fem, linear, newton
+
+MU, LAM = 80.194, 400.9
+
+
+def test_lumped_mass_total():
+    m = syn.cook_mesh(3, 3, 1)
+    P = fem.cook_problem(m, mu=MU, lam=LAM)
+    M = P.lumped_mass(1.3e-3).reshape(-1, 3)
+    assert np.allclose(M.sum(0), 1.3e-3 * 14400.0, rtol=1e-13)
+
+
+def test_inertia_residual_is_gradient_of_incremental_potential():
+    m = syn.cook_mesh(3, 3, 1)
+    P = fem.cook_problem(m, mu=MU, lam=LAM)
+    rng = np.random.default_rng(4)
+    ut = P.lift(0.01 * rng.standard_normal(P.n_dofs))
+    P.set_inertia(1e-3, 2.5e3, ut)
+    u = P.lift(0.01 * rng.standard_normal(P.n_dofs))
+    w = rng.standard_normal(P.n_dofs)
+    w[P.fixed] = 0.0
+    h = 1e-6
+    d = (P.energy(u + h * w, 0.6) - P.energy(u - h * w, 0.6)) / (2 * h)
+    assert abs(d - P.residual(u, 0.6) @ w) <= 1e-7 * abs(d)
+    K = P.stiffness(u, dirichlet=False)
+    fd = (P.residual(u + h * w, 0.6) - P.residual(u - h * w, 0.6)) / (2 * h)
+    fd[P.fixed] = 0.0
+    Kw = K @ w
+    Kw[P.fixed] = 0.0
+    assert np.abs(Kw - fd).max() <= 1e-6 * np.abs(fd).max()
+
+
+def test_small_amplitude_vibration_follows_linear_newmark():
+    # at strains ~1e-7 the nonlinear step is the linear one: compare with
+    # M u'' + K0 u = 0 stepped by the average-acceleration rule written out
+    # with the independent small-strain stiffness K0, and check that this
+    # linear trajectory keeps its energy (the rule conserves it exactly)
+    m = syn.cook_mesh(4, 4, 1)
+    P = fem.cook_problem(m, mu=MU, lam=LAM, tau=0.0)
+    rho, dt, beta, gamma = 1e-3, 2e-3, 0.25, 0.5
+    rng = np.random.default_rng(6)
+    v0 = 1e-5 * rng.standard_normal(P.n_dofs)
+    v0[P.fixed] = 0.0
+    M = P.lumped_mass(rho)
+    free = P.free
+    K0 = linear.stiffness_linear(m.X, m.conn, LAM, MU).tocsc()[free][:, free]
+    Mf = M[free]
+    c = 1.0 / (beta * dt * dt)
+    A = (K0 + sp.diags(c * Mf)).tocsc()
+    ul, vl, al = np.zeros(free.sum()), v0[free].copy(), np.zeros(free.sum())
+    e_lin0 = 0.5 * float(np.sum(Mf * vl * vl))
+    u, v, a = np.zeros(P.n_dofs), v0.copy(), np.zeros(P.n_dofs)
+    for _ in range(10):
+        ut = newton.newmark_predict(u, v, a, dt, beta)
+        P.set_inertia(rho, c, ut)
+        u, _ = newton.newton_exact(P, u, 1.0, rtol=1e-14)
+        v, a = newton.newmark_correct(u, ut, v, a, dt, beta, gamma)
+        utl = ul + dt * vl + dt * dt * (0.5 - beta) * al
+        ul = spla.spsolve(A, c * Mf * utl)
+        anew = c * (ul - utl)
+        vl = vl + dt * ((1 - gamma) * al + gamma * anew)
+        al = anew
+    P.set_inertia(0.0, 0.0, u)
+    assert np.linalg.norm(u[free] - ul) <= 1e-5 * np.linalg.norm(ul)
+    assert np.linalg.norm(v[free] - vl) <= 1e-5 * np.linalg.norm(vl)
+    e_lin = 0.5 * float(np.sum(Mf * vl * vl)) + 0.5 * float(ul @ (K0 @ ul))
+    assert abs(e_lin - e_lin0) <= 1e-10 * e_lin0
