@@ -270,6 +270,30 @@ nle_status nle_set_traction_follower(nle_ctx *ctx, int64_t n_faces, const int32_
  * (consistent P1 face mass).  Replaces previous spring faces. */
 nle_status nle_set_robin(nle_ctx *ctx, int64_t n_faces, const int32_t *tri, double k_perp,
                          double k_par);
+/* Inertia of one implicit time step (Sec. 4 "Heartbeat test" is a dynamic
+ * problem; its time integration is not given, this library offers the
+ * Newmark average-acceleration step).  With M the row-sum lumped P1 mass of
+ * density rho (rho V / 4 per element vertex and direction), the residual
+ * gains coef M (u - u_tilde), the tangent coef M, the Jacobi and block
+ * diagonals coef M, and nle_energy coef/2 (u - u_tilde)^T M (u - u_tilde)
+ * (Dirichlet dofs keep identity rows).  For Newmark, coef = 1/(beta dt^2)
+ * and u_tilde comes from nle_newmark_predict.  u_tilde_dev (double, device,
+ * 3 n_nodes) is copied.  rho = 0 or coef = 0 switches the term off.  P1
+ * meshes only (NLE_E_UNSUPPORTED on a mixed mesh); NLE_E_INVAL for negative
+ * or non-finite values or a null u_tilde while on.  Resets linearizations. */
+nle_status nle_set_inertia(nle_ctx *ctx, double rho, double coef, const double *u_tilde_dev);
+/* Newmark predictor (double, device, 3 n_nodes each):
+ * u_tilde = u + dt v + dt^2 (1/2 - beta) a.  NLE_E_INVAL for dt <= 0 or
+ * beta <= 0. */
+nle_status nle_newmark_predict(nle_ctx *ctx, double dt, double beta, const double *u_dev,
+                               const double *v_dev, const double *a_dev, double *u_tilde_dev);
+/* Newmark corrector after the step's solve, in place (double, device):
+ * a_new = (u - u_tilde) / (beta dt^2), v += dt ((1 - gamma) a + gamma a_new),
+ * a = a_new.  Dirichlet dofs are not special-cased: with fixed values there
+ * u - u_tilde gives their prescribed motion. */
+nle_status nle_newmark_correct(nle_ctx *ctx, double dt, double beta, double gamma,
+                               const double *u_dev, const double *u_tilde_dev, double *v_dev,
+                               double *a_dev);
 
 /* ---- kernels (device vectors of 3 n_nodes entries) ---------------------- */
 /* Write the prescribed Dirichlet values into u (double, device). */

@@ -624,6 +624,82 @@ nle_status nle_set_traction_follower(nle_ctx *ctx, int64_t nf, const int32_t *tr
   });
 }
 
+nle_status nle_set_inertia(nle_ctx *ctx, double rho, double coef, const double *ut) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  nle_status s = need_mesh(c);
+  if (s != NLE_OK) return s;
+  if (c->mixed) return fail(c, NLE_E_UNSUPPORTED, "not available on mixed meshes");
+  if (!std::isfinite(rho) || !std::isfinite(coef) || rho < 0.0 || coef < 0.0)
+    return fail(c, NLE_E_INVAL, "rho and the coefficient must be finite and >= 0");
+  return guarded(c, [&]() -> nle_status {
+    const bool on = rho > 0.0 && coef > 0.0;
+    if (on && !ut) return fail(c, NLE_E_INVAL, "null u_tilde");
+    const int64_t nn = c->m.n_nodes, n = 3 * nn;
+    if (on != c->inr.on) drop_graph(c);  // the inertia pointers are kernel arguments
+    if (on && !c->inr.cm64) {
+      c->inr.cm64 = static_cast<double *>(dalloc(c, size_t(n) * 8));
+      c->inr.cm32 = static_cast<float *>(dalloc(c, size_t(n) * 4));
+      c->inr.ut = static_cast<double *>(dalloc(c, size_t(n) * 8));
+      for (void *p : {(void *)c->inr.cm64, (void *)c->inr.cm32, (void *)c->inr.ut})
+        if (p) c->mesh_allocs.push_back(p);
+      if (!c->inr.cm64 || !c->inr.cm32 || !c->inr.ut) {
+        for (void *p : {(void *)c->inr.cm64, (void *)c->inr.cm32, (void *)c->inr.ut}) {
+          if (!p) continue;
+          dfree(c, p);
+          c->mesh_allocs.erase(std::find(c->mesh_allocs.begin(), c->mesh_allocs.end(), p));
+        }
+        c->inr = decltype(c->inr)();
+        return fail(c, NLE_E_OOM, "device allocation failed (inertia)");
+      }
+      c->inr.rho = c->inr.c = -1.0;  // force the mass upload below
+    }
+    c->inr.on = on;
+    c->lin64 = c->lin32 = c->lc_valid = false;
+    if (!on) return NLE_OK;
+    if (rho != c->inr.rho || coef != c->inr.c) {
+      // row-sum lumped P1 mass: rho V / 4 per element vertex, times coef
+      std::vector<double> m(nn, 0.0);
+      for (int64_t e = 0; e < c->m.n_elems; ++e)
+        for (int a = 0; a < 4; ++a) m[c->m.h_conn[4 * e + a]] += rho * c->m.h_V[e] / 4.0;
+      std::vector<double> cm(n);
+      std::vector<float> cm32(n);
+      for (int64_t k = 0; k < n; ++k) {
+        cm[k] = coef * m[k / 3];
+        cm32[k] = float(cm[k]);
+      }
+      NLE_HIP(c, hipMemcpyAsync(c->inr.cm64, cm.data(), n * 8, hipMemcpyHostToDevice, c->stream));
+      NLE_HIP(c, hipMemcpyAsync(c->inr.cm32, cm32.data(), n * 4, hipMemcpyHostToDevice, c->stream));
+      NLE_HIP(c, hipStreamSynchronize(c->stream));
+      c->inr.rho = rho;
+      c->inr.c = coef;
+    }
+    NLE_HIP(c, hipMemcpyAsync(c->inr.ut, ut, n * 8, hipMemcpyDeviceToDevice, c->stream));
+    return NLE_OK;
+  });
+}
+
+nle_status nle_newmark_predict(nle_ctx *ctx, double dt, double beta, const double *u,
+                               const double *v, const double *a, double *ut) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  nle_status s = need_mesh(c);
+  if (s != NLE_OK) return s;
+  if (!u || !v || !a || !ut) return fail(c, NLE_E_INVAL, "null vector");
+  if (!(dt > 0.0) || !(beta > 0.0)) return fail(c, NLE_E_INVAL, "dt and beta must be positive");
+  NLE_HIP(c, newmark_predict(c, u, v, a, ut, dt, beta, ndof(c)));
+  return NLE_OK;
+}
+
+nle_status nle_newmark_correct(nle_ctx *ctx, double dt, double beta, double gamma,
+                               const double *u, const double *ut, double *v, double *a) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  nle_status s = need_mesh(c);
+  if (s != NLE_OK) return s;
+  if (!u || !ut || !v || !a) return fail(c, NLE_E_INVAL, "null vector");
+  if (!(dt > 0.0) || !(beta > 0.0)) return fail(c, NLE_E_INVAL, "dt and beta must be positive");
+  NLE_HIP(c, newmark_correct(c, u, ut, v, a, dt, beta, gamma, ndof(c)));
+  return NLE_OK;
+}
+
 nle_status nle_set_robin(nle_ctx *ctx, int64_t nf, const int32_t *tri, double k_perp, double k_par) {
   Ctx *c = reinterpret_cast<Ctx *>(ctx);
   nle_status s = need_mesh(c);
@@ -781,9 +857,21 @@ nle_status nle_energy(nle_ctx *ctx, const double *u, double *pi) {
   } else {
     NLE_HIP(c, hipMemsetAsync(c->dscal + 62, 0, 8, c->stream));
   }
-  s = read_scalars(c, c->dscal + 60, 24);
+  // inertia of the time step: c/2 (u - u~)^T M (u - u~)
+  if (c->inr.on) {
+    double *red4 = red3 + np3;
+    const int64_t n = 3 * c->m.n_nodes;
+    if (np + np2 + nsg + vgrid(n) > c->red_cap)
+      return fail(c, NLE_E_UNSUPPORTED, "reduction space");
+    const int np4 = vec_wdiff2_partials(c, c->inr.cm64, u, c->inr.ut, n, red4, &e);
+    if (e != hipSuccess) return fail(c, NLE_E_HIP, "inertia energy");
+    NLE_HIP(c, reduce_scalar(c, red4, np4, c->dscal + 63));
+  } else {
+    NLE_HIP(c, hipMemsetAsync(c->dscal + 63, 0, 8, c->stream));
+  }
+  s = read_scalars(c, c->dscal + 60, 32);
   if (s != NLE_OK) return s;
-  *pi = c->hpin[0] - c->load_scale * c->hpin[1] + c->hpin[2];
+  *pi = c->hpin[0] - c->load_scale * c->hpin[1] + c->hpin[2] + 0.5 * c->hpin[3];
   return NLE_OK;
 }
 

@@ -62,6 +62,8 @@ struct ElemArgs {
   const int32_t *inst_done;
   const int32_t *blk_list;  // when set, workgroup w runs block blk_list[w] (n_list of them)
   int32_t n_list;
+  const T *icm;             // inertia: c * m per dof (null: none), and u_tilde
+  const double *iut;
   // CG direction formed here (Jv only, see Ctx::cg): v = vz + beta * v
   const T *vz;
   const double *cg_red;
@@ -93,6 +95,9 @@ struct MergeArgs {
   const int32_t *mwg_list;  // when set, workgroup w runs merge workgroup mwg_list[w]
   const T *vz;              // CG direction v = vz + beta * v, beta = cg_scal[BETA]
   const double *cg_scal;
+  const T *u;               // state (residual with inertia)
+  const T *icm;             // inertia: c * m per dof (null: none), and u_tilde
+  const double *iut;
 };
 
 __device__ __forceinline__ int block_id(int nblk, int per_xcd) {
@@ -276,30 +281,35 @@ __device__ __forceinline__ double energy_density(const Kin<T> &k, const T H[3][3
 
 // Final value of one node (all three components) from its summed element
 // contributions.  mk = Dirichlet bits of the node.
-// fs (nullable) holds the surface-load contributions of the same operation.
+// fs (nullable) holds the surface-load contributions of the same operation;
+// icm (nullable) the inertia coefficients c m per dof, with u and u_tilde
+// (iut) for the residual's c m (u - u_tilde).
 template <typename T, int OP>
 __device__ __forceinline__ void finalize_node(uint32_t g, uint32_t mk, const T acc[3], const T *v,
                                               const T *vz, T bt,
                                               T *out, const double *fext, double s,
                                               double &nrm, const T *epw, T epc, const T *fs,
-                                              int nomask) {
+                                              int nomask, const T *icm, const double *iut,
+                                              const T *u) {
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     const int64_t d = 3 * int64_t(g) + i;
     const bool fixed = (mk >> i) & 1u;
     const T a = fs ? acc[i] + fs[d] : acc[i];
     if (OP == OP_RES) {
-      const double r = fixed ? 0.0 : double(a) - s * fext[d];
+      double ra = double(a);
+      if (icm) ra += double(icm[d]) * (double(u[d]) - iut[d]);
+      const double r = fixed ? 0.0 : ra - s * fext[d];
       out[d] = T(r);
       nrm += r * r;
     } else if (OP == OP_JV) {
       const T vd = vz ? vz[d] + bt * v[d] : v[d];
-      T y = fixed ? (nomask ? T(0) : vd) : a;
+      T y = fixed ? (nomask ? T(0) : vd) : (icm ? a + icm[d] * vd : a);
       if (epw) y -= epc * epw[d];
       out[d] = y;
       nrm += double(vd * y);
     } else if (OP == OP_DIAG) {
-      out[d] = fixed ? T(1) : a;
+      out[d] = fixed ? T(1) : (icm ? a + icm[d] : a);
     } else if (OP == OP_ODIAG) {
       // entry i pairs components (i, i+1 mod 3): xy, yz, zx
       const bool fx2 = (mk >> ((i + 1) % 3)) & 1u;
@@ -816,8 +826,7 @@ __global__ __launch_bounds__(NTB) void k_elem_block(ElemArgs<T> A) {
       pp[2] = acc[2];
     } else {
       finalize_node<T, OP>(w & NODE_MASK, (w >> 28) & 7u, acc, A.v, A.vz, bt, A.out, A.fext,
-                           lscale, nrm,
-                           A.ep_w, epc, A.fs, A.nomask);
+                           lscale, nrm, A.ep_w, epc, A.fs, A.nomask, A.icm, A.iut, A.u);
     }
   }
   if (OP == OP_RES || (OP == OP_JV && A.ep_red)) {
@@ -861,7 +870,8 @@ __global__ __launch_bounds__(NT) void k_elem_merge(MergeArgs<T> A) {
     const uint32_t w = A.fx_node[k];
     finalize_node<T, OP>(w & NODE_MASK, (w >> 28) & 7u, acc, A.v, A.vz,
                          A.vz ? T(A.cg_scal[cgslot::BETA]) : T(0), A.out, A.fext, lscale, nrm,
-                         A.ep_w, A.ep_coef ? T(A.ep_coef[0]) : T(0), A.fs, A.nomask);
+                         A.ep_w, A.ep_coef ? T(A.ep_coef[0]) : T(0), A.fs, A.nomask, A.icm,
+                         A.iut, A.u);
   }
   if (OP == OP_RES || (OP == OP_JV && A.ep_red)) {
     const double s = block_sum<NT>(nrm, rs);
@@ -931,6 +941,11 @@ int launch(Ctx *c, int op, const T *xr, const T *u, const T *v, T *out, double *
   A.blk_inst = M.blk_inst;
   A.blk_list = c->blk_list;
   A.n_list = c->n_blist;
+  A.icm = (c->inr.on && (op == OP_RES || op == OP_JV || op == OP_DIAG))
+              ? static_cast<const T *>(sizeof(T) == 8 ? static_cast<const void *>(c->inr.cm64)
+                                                      : static_cast<const void *>(c->inr.cm32))
+              : nullptr;
+  A.iut = c->inr.ut;
   A.inst_s = c->inst_s;
   A.inst_mat = c->inst_mat;
   A.inst_done = c->inst_done;
@@ -1001,6 +1016,9 @@ int launch(Ctx *c, int op, const T *xr, const T *u, const T *v, T *out, double *
     B.fs = A.fs;
     B.vz = A.vz;
     B.cg_scal = c->cg.scal;
+    B.u = u;
+    B.icm = A.icm;
+    B.iut = A.iut;
     switch (op) {
       case OP_RES:
         hipLaunchKernelGGL((k_elem_merge<T, OP_RES>), dim3(g2), dim3(NT), 0, c->stream, B);

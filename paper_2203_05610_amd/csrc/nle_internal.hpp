@@ -167,6 +167,16 @@ struct Ctx {
   double *inst_mat = nullptr;
   int32_t *inst_done = nullptr;
   int32_t *inst_inv = nullptr;  // per-instance "some det F <= 0" flags
+  // inertia of an implicit time step: c M (u - u_tilde) in the residual,
+  // c M in the tangent (M the row-sum lumped P1 mass of density rho)
+  struct {
+    bool on = false;
+    double rho = 0.0, c = 0.0;
+    double *cm64 = nullptr;  // [3 n_nodes] c * m per dof
+    float *cm32 = nullptr;
+    double *ut = nullptr;    // [3 n_nodes] u_tilde
+  } inr;
+
   // batched mode: when set, the element kernels run only the listed blocks
   // and merge workgroups (those of the instances still iterating)
   const int32_t *blk_list = nullptr, *mwg_list = nullptr;
@@ -315,6 +325,12 @@ int vec_dot_partials(Ctx *c, int prec, const void *a, const void *b, int64_t n, 
 hipError_t reduce_scalar(Ctx *c, const double *red, int np, double *out);
 hipError_t reduce_scalars(Ctx *c, const double *red, int np, int count, double *out);
 hipError_t vec_recip(Ctx *c, const double *d, double *dinv, int64_t n);
+hipError_t newmark_predict(Ctx *c, const double *u, const double *v, const double *a, double *ut,
+                           double dt, double beta, int64_t n);
+hipError_t newmark_correct(Ctx *c, const double *u, const double *ut, double *v, double *a,
+                           double dt, double beta, double gamma, int64_t n);
+int vec_wdiff2_partials(Ctx *c, const double *w, const double *x, const double *y, int64_t n,
+                        double *red, hipError_t *err);
 // y = M^-1 x with pcb = 1 (d: inverse diagonal, identity if null) or
 // pcb = 3 (d: nodal block inverses [6][n/3], see block_inverse)
 hipError_t pc_apply(Ctx *c, int prec, int pcb, const void *d, const void *x, void *y, int64_t n);

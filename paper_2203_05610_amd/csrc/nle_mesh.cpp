@@ -257,6 +257,7 @@ nle_status build_mesh(Ctx *c, int64_t nn, const double *X, int64_t ne, const int
   c->odiag64 = c->binv64 = nullptr;
   c->binv32 = nullptr;
   c->blk_valid = false;
+  c->inr = decltype(c->inr)();
   Mesh &M = c->m;
   M = Mesh();
   M.n_nodes = nn;

@@ -549,6 +549,7 @@ nle_status build_mixed_mesh(Ctx *c, int64_t nu, const double *X, int64_t ne, con
   c->odiag64 = c->binv64 = nullptr;
   c->binv32 = nullptr;
   c->blk_valid = false;
+  c->inr = decltype(c->inr)();
   c->m = Mesh();
   c->mx = MixedMesh();
   MixedMesh &M = c->mx;

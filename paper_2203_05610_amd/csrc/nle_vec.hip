@@ -60,6 +60,40 @@ __global__ __launch_bounds__(NT) void k_axpy(const S *x, D *y, double a, const d
     y[i] = D(double(y[i]) + alpha * double(x[i]));
 }
 
+// Newmark's average-acceleration family: predictor u~ = u + dt v + dt^2 (1/2 - beta) a
+// and corrector a' = (u' - u~) / (beta dt^2), v' = v + dt ((1 - gamma) a + gamma a').
+__global__ __launch_bounds__(NT) void k_newmark_predict(const double *u, const double *v,
+                                                        const double *a, double *ut, double dt,
+                                                        double beta, int64_t n) {
+  const double h2 = dt * dt * (0.5 - beta);
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT)
+    ut[i] = u[i] + dt * v[i] + h2 * a[i];
+}
+
+__global__ __launch_bounds__(NT) void k_newmark_correct(const double *u, const double *ut,
+                                                        double *v, double *a, double dt,
+                                                        double beta, double gamma, int64_t n) {
+  const double c = 1.0 / (beta * dt * dt);
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT) {
+    const double an = c * (u[i] - ut[i]);
+    v[i] = v[i] + dt * ((1.0 - gamma) * a[i] + gamma * an);
+    a[i] = an;
+  }
+}
+
+// partials of sum_i w_i (x_i - y_i)^2
+__global__ __launch_bounds__(NT) void k_wdiff2(const double *w, const double *x, const double *y,
+                                               int64_t n, double *red) {
+  __shared__ double sh[NT / 64];
+  double acc = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT) {
+    const double d = x[i] - y[i];
+    acc += w[i] * d * d;
+  }
+  acc = block_sum_all(acc, sh);
+  if (threadIdx.x == 0) red[blockIdx.x] = acc;
+}
+
 __global__ __launch_bounds__(NT) void k_recip(const double *d, double *di, int64_t n) {
   for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT)
     di[i] = 1.0 / d[i];
@@ -820,6 +854,26 @@ hipError_t pc_apply(Ctx *c, int prec, int pcb, const void *d, const void *x, voi
 hipError_t block_inverse(Ctx *c, int64_t nn) {
   LAUNCH(k_block_inv, vgrid(nn), c->diag64, c->odiag64, c->binv64, c->binv32, nn);
   return hipGetLastError();
+}
+
+hipError_t newmark_predict(Ctx *c, const double *u, const double *v, const double *a, double *ut,
+                           double dt, double beta, int64_t n) {
+  LAUNCH(k_newmark_predict, vgrid(n), u, v, a, ut, dt, beta, n);
+  return hipGetLastError();
+}
+
+hipError_t newmark_correct(Ctx *c, const double *u, const double *ut, double *v, double *a,
+                           double dt, double beta, double gamma, int64_t n) {
+  LAUNCH(k_newmark_correct, vgrid(n), u, ut, v, a, dt, beta, gamma, n);
+  return hipGetLastError();
+}
+
+int vec_wdiff2_partials(Ctx *c, const double *w, const double *x, const double *y, int64_t n,
+                        double *red, hipError_t *err) {
+  const int g = vgrid(n);
+  LAUNCH(k_wdiff2, g, w, x, y, n, red);
+  *err = hipGetLastError();
+  return g;
 }
 
 hipError_t vec_recip(Ctx *c, const double *d, double *di, int64_t n) {

@@ -49,6 +49,7 @@ EXPORTS = [
     "nle_batch_last_error", "nle_batch_add", "nle_batch_finalize", "nle_batch_layout",
     "nle_batch_solve", "nle_set_fibres", "nle_set_active_tension", "nle_set_pressure",
     "nle_set_robin", "nle_set_traction_follower", "nle_upload_mesh_mixed", "nle_block_diag", "nle_pc_apply", "nle_batch_autotune",
+    "nle_set_inertia", "nle_newmark_predict", "nle_newmark_correct",
 ]
 
 
@@ -117,6 +118,9 @@ def lib() -> ctypes.CDLL:
         "nle_set_pressure": (I32, [P, I64, P, D]),
         "nle_set_robin": (I32, [P, I64, P, D, D]),
         "nle_set_traction_follower": (I32, [P, I64, P, P]),
+        "nle_set_inertia": (I32, [P, D, D, P]),
+        "nle_newmark_predict": (I32, [P, D, D, P, P, P, P]),
+        "nle_newmark_correct": (I32, [P, D, D, D, P, P, P, P]),
         "nle_lift": (I32, [P, P]),
         "nle_residual": (I32, [P, P, P, ctypes.POINTER(D)]),
         "nle_linearize": (I32, [P, P, I32]),
@@ -317,6 +321,25 @@ def nle_set_robin(ctx: Context, tri, k_perp: float, k_par: float) -> None:
     f, pf = _host(tri, np.int32)
     ctx.check(lib().nle_set_robin(ctx.handle, f.shape[0] if f.size else 0, pf, float(k_perp),
                                   float(k_par)))
+
+
+def nle_set_inertia(ctx: Context, rho: float, coef: float, u_tilde=None) -> None:
+    pu = None if u_tilde is None else ctx.vec(u_tilde, ctx.torch.float64)
+    ctx.check(lib().nle_set_inertia(ctx.handle, float(rho), float(coef), pu))
+
+
+def nle_newmark_predict(ctx: Context, dt: float, beta: float, u, v, a, u_tilde) -> None:
+    T = ctx.torch.float64
+    ctx.check(lib().nle_newmark_predict(ctx.handle, float(dt), float(beta), ctx.vec(u, T),
+                                        ctx.vec(v, T), ctx.vec(a, T), ctx.vec(u_tilde, T)))
+
+
+def nle_newmark_correct(ctx: Context, dt: float, beta: float, gamma: float, u, u_tilde, v,
+                        a) -> None:
+    T = ctx.torch.float64
+    ctx.check(lib().nle_newmark_correct(ctx.handle, float(dt), float(beta), float(gamma),
+                                        ctx.vec(u, T), ctx.vec(u_tilde, T), ctx.vec(v, T),
+                                        ctx.vec(a, T)))
 
 
 def nle_set_body_force(ctx: Context, f) -> None:

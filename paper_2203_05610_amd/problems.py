@@ -165,6 +165,39 @@ def solve_heartbeat(ctx: nl.Context, u, method: str, opts, schedule, gamma_max: 
     return reps
 
 
+def solve_heartbeat_dynamic(ctx: nl.Context, u, method: str, opts, schedule, gamma_max: float,
+                            rho: float, dt: float, beta: float = 0.25, gamma: float = 0.5,
+                            v=None, a=None, hist_cap: int = 4096):
+    """Heartbeat with inertia: each time step (t, shape) predicts u~ with
+    Newmark's rule, sets the inertia c M (u - u~) with c = 1 / (beta dt^2)
+    and density rho, the active tension gamma_max * shape and the pressure
+    load scale shape, solves the implicit step warm-started from u, then
+    corrects v and a in place (both start at zero unless given).  Stops at
+    the first step that fails (a smaller step would change c).  The inertia
+    is switched off on return.  Returns (reports, v, a)."""
+    torch = ctx.torch
+    v = torch.zeros_like(u) if v is None else v
+    a = torch.zeros_like(u) if a is None else a
+    ut = torch.empty_like(u)
+    c = 1.0 / (beta * dt * dt)
+    reps = []
+    try:
+        for t, sh in schedule:
+            nl.nle_newmark_predict(ctx, dt, beta, u, v, a, ut)
+            nl.nle_set_inertia(ctx, rho, c, ut)
+            nl.nle_set_active_tension(ctx, gamma_max * sh)
+            nl.nle_set_load_scale(ctx, sh)
+            st, rep = SOLVERS[method](ctx, u, opts, hist_cap)
+            rep.update(t=float(t), shape=float(sh), accepted=st == nl.NLE_OK)
+            reps.append(rep)
+            if st != nl.NLE_OK:
+                break
+            nl.nle_newmark_correct(ctx, dt, beta, gamma, u, ut, v, a)
+    finally:
+        nl.nle_set_inertia(ctx, 0.0, 0.0, None)
+    return reps, v, a
+
+
 def heartbeat_ok(reps, schedule) -> bool:
     acc = [r["t"] for r in reps if r["accepted"]]
     return bool(acc) and acc[-1] == float(schedule[-1][0])
