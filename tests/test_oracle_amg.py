@@ -1,0 +1,140 @@
+"""Pins of the oracle's aggregation multigrid (oracle/amg.py) against what
+the definition and the mathematics fix: the aggregation's structure (roots
+with their whole neighbourhood, members within distance two of the root,
+roots three apart), orthonormal tentative prolongators whose range holds
+every rigid motion, Galerkin coarse operators that annihilate the coarse
+rigid modes of a floating body, a one-level hierarchy that is the exact
+solve, a symmetric positive definite cycle for a symmetric positive definite
+tangent with a convergent error propagator, the power-iteration estimate
+against the spectrum, and fewer Krylov iterations than point Jacobi."""
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import synthetic as syn
+from oracle import amg, fem
+
+MU = 80.194
+
+
+def _cook(nx, ny, nz, ratio=5.0, dirichlet=True):
+    mesh = syn.cook_mesh(nx, ny, nz)
+    P = fem.cook_problem(mesh, mu=MU, lam=ratio * MU, tau=1.0)
+    K = P.stiffness(np.zeros(P.n_dofs), dirichlet=dirichlet)
+    fixed = P.fixed if dirichlet else np.zeros(P.n_dofs, dtype=bool)
+    return mesh, P, K, fixed
+
+
+def test_start_vector_is_the_golden_ratio_sequence():
+    # 2654435761 / 2^32 is the fractional part of the golden ratio to 2e-9
+    x = amg.start_vector(3)
+    assert x[0] == -0.5
+    assert abs(x[1] - ((np.sqrt(5.0) - 1.0) / 2.0 - 0.5)) < 2.5e-9
+    assert abs(x[2] - ((2.0 * (np.sqrt(5.0) - 1.0) / 2.0) % 1.0 - 0.5)) < 5e-9
+
+
+def test_aggregation_structure():
+    mesh = syn.cook_mesh(8, 6, 2)
+    adj = amg.node_graph(mesh.conn, mesh.n_nodes)
+    agg, n_agg = amg.aggregate(adj)
+    assert agg.min() == 0 and set(agg.tolist()) == set(range(n_agg))
+    roots = []
+    for a in range(n_agg):
+        mem = set(np.flatnonzero(agg == a).tolist())
+        # a root: a member whose closed neighbourhood lies in the aggregate
+        cand = [v for v in sorted(mem) if set(adj[v]) <= mem]
+        assert cand, a
+        r = cand[0]
+        roots.append(r)
+        ring1 = set(adj[r])
+        ring2 = set(w for v in ring1 for w in adj[v])
+        assert mem <= {r} | ring1 | ring2
+    # roots' neighbourhoods are disjoint (pass 1): distinct roots are >= 3 apart
+    for i, r in enumerate(roots):
+        n1 = {r} | set(adj[r])
+        for s in roots[i + 1:]:
+            assert not (n1 & ({s} | set(adj[s])))
+
+
+def test_prolongator_orthonormal_and_spans_rigid_motions():
+    mesh, P, K, fixed = _cook(8, 6, 2)
+    H = amg.setup(K, mesh.X, mesh.conn, fixed)
+    P0 = H.P[0].toarray()
+    assert np.abs(P0.T @ P0 - np.eye(P0.shape[1])).max() < 1e-12
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        t, w = rng.standard_normal(3), rng.standard_normal(3)
+        u = (t[None, :] + np.cross(w[None, :], mesh.X)).reshape(-1)
+        u[fixed] = 0.0
+        assert np.linalg.norm(P0 @ (P0.T @ u) - u) <= 1e-12 * np.linalg.norm(u)
+    # Dirichlet rows are zero
+    assert np.abs(P0[fixed]).max() == 0.0
+
+
+def test_galerkin_operators_annihilate_coarse_rigid_modes():
+    # a floating body at rest: K annihilates rigid motions, hence every
+    # coarse operator annihilates their coarse representation
+    mesh, P, K, fixed = _cook(20, 16, 3, dirichlet=False)
+    H = amg.setup(K, mesh.X, mesh.conn, fixed)
+    assert H.n_levels >= 3
+    rng = np.random.default_rng(4)
+    t, w = rng.standard_normal(3), rng.standard_normal(3)
+    u = (t[None, :] + np.cross(w[None, :], mesh.X)).reshape(-1)
+    assert np.linalg.norm(K @ u) <= 1e-10 * abs(K).max() * np.linalg.norm(u)
+    v = u
+    for lev in range(H.n_levels - 1):
+        v = H.P[lev].T @ v  # P is orthonormal and spans v: this is its coordinates
+        assert np.linalg.norm(H.P[lev] @ v - (u if lev == 0 else vprev)) <= 1e-10 * np.linalg.norm(v)
+        A = H.A[lev + 1]
+        assert np.linalg.norm(A @ v) <= 1e-9 * abs(A).max() * np.linalg.norm(v)
+        vprev = v
+
+
+def test_one_level_is_the_exact_solve(monkeypatch):
+    mesh, P, K, fixed = _cook(4, 4, 1)
+    monkeypatch.setattr(amg, "N_COARSE", 10 ** 6)
+    H = amg.setup(K, mesh.X, mesh.conn, fixed)
+    assert H.n_levels == 1
+    b = np.random.default_rng(5).standard_normal(P.n_dofs)
+    x = amg.vcycle(H, b)
+    assert np.linalg.norm(K @ x - b) <= 1e-10 * np.linalg.norm(b)
+
+
+def test_cycle_is_spd_and_convergent_for_an_spd_tangent():
+    mesh, P, K, fixed = _cook(8, 8, 1)
+    H = amg.setup(K, mesh.X, mesh.conn, fixed)
+    assert H.n_levels == 2
+    n = P.n_dofs
+    M = np.column_stack([amg.vcycle(H, e) for e in np.eye(n)])
+    assert np.abs(M - M.T).max() <= 1e-12 * np.abs(M).max()
+    assert np.linalg.eigvalsh(0.5 * (M + M.T)).min() > 0.0
+    # error propagation I - M K has spectral radius < 1
+    Kd = K.toarray()
+    rho = np.abs(np.linalg.eigvals(np.eye(n) - M @ Kd)).max()
+    assert rho < 1.0, rho
+
+
+def test_power_iteration_brackets_the_spectral_radius():
+    mesh, P, K, fixed = _cook(8, 8, 1)
+    D = K.diagonal()
+    lam = np.abs(np.linalg.eigvals(np.diag(1.0 / D) @ K.toarray())).max()
+    est = amg.spectral_radius(K, D)
+    assert 0.8 * lam <= est <= lam * (1.0 + 1e-12), (est, lam)
+    # a diagonal matrix with one dominant entry: the estimate converges to it
+    A = sp.diags(np.r_[np.ones(20), 10.0])
+    assert abs(amg.spectral_radius(A, np.ones(21)) - 10.0) < 1e-9
+
+
+def test_fewer_iterations_than_point_jacobi():
+    mesh, P, K, fixed = _cook(16, 16, 2)
+    b = -P.residual(np.zeros(P.n_dofs), 1.0)
+    H = amg.setup(K, mesh.X, mesh.conn, fixed)
+    x, it = amg.gmres_amg(K, H, b, 1e-8, max_it=800)
+    assert np.linalg.norm(b - K @ x) <= 1.01e-8 * np.linalg.norm(b)
+    # point-Jacobi GMRES with the same (true residual) stopping rule
+    cnt = [0]
+    Mj = spla.LinearOperator(K.shape, matvec=lambda v: v / K.diagonal())
+    spla.gmres(K, b, M=Mj, rtol=1e-8, restart=3000, maxiter=1,
+               callback=lambda r: cnt.__setitem__(0, cnt[0] + 1), callback_type="pr_norm")
+    assert 3 * it < cnt[0], (it, cnt[0])
