@@ -90,6 +90,10 @@ typedef int32_t nle_status;
 #define NLE_PC_BJACOBI3 2 /* nodal block Jacobi: inverse of each node's 3x3
                              diagonal block of the tangent (P1 meshes; the
                              bs = 3 point-block Jacobi of a PETSc setup)  */
+#define NLE_PC_AMG 3 /* aggregation multigrid, one V(1,1)-cycle (the AMG of
+                        Sec. 4 and App. A; its construction is this
+                        library's, see nle_pc_apply); P1 meshes, GMRES or
+                        BFGS-preonly only */
 
 #define NLE_H0_PREONLY 0 /* BFGS-preonly: H0 = one preconditioner application */
 #define NLE_H0_KSP 1     /* inexact BFGS: H0 = Krylov solve on J(u0)          */
@@ -324,10 +328,31 @@ nle_status nle_diag(nle_ctx *ctx, double *d_dev);
  * NLE_E_STATE before nle_linearize. */
 nle_status nle_block_diag(nle_ctx *ctx, double *b_dev);
 /* y = M^-1 x for the preconditioner pc of the current linearization:
- * NLE_PC_NONE (copy), NLE_PC_JACOBI (y_i = x_i / J_ii) or NLE_PC_BJACOBI3
- * (per node, the inverse of its block from nle_block_diag).  x and y are
- * device vectors of the unknown length, double for NLE_FP64 and float for
- * NLE_FP32 (which needs a linearization in NLE_FP32); they may not overlap. */
+ * NLE_PC_NONE (copy), NLE_PC_JACOBI (y_i = x_i / J_ii), NLE_PC_BJACOBI3
+ * (per node, the inverse of its block from nle_block_diag) or NLE_PC_AMG.
+ * x and y are device vectors of the unknown length, double for NLE_FP64 and
+ * float for NLE_FP32 (which needs a linearization in NLE_FP32); they may
+ * not overlap.
+ * NLE_PC_AMG (P1 meshes; NLE_E_UNSUPPORTED on a mixed mesh): one V(1,1)-
+ * cycle of an aggregation multigrid for J.  Candidates: the six rigid-body
+ * modes (translations, rotations e_k x X about the origin), zero on
+ * Dirichlet dofs.  Each level's graph (level 0: nodes sharing an element)
+ * is aggregated in two passes over its vertices in order (a vertex whose
+ * neighbours are all free forms an aggregate with them; leftovers join the
+ * aggregate of their lowest-numbered neighbour aggregated in the first
+ * pass); each aggregate's candidate columns are orthonormalised by modified
+ * Gram-Schmidt in order (a column is dropped below 1e-8 of its norm) into
+ * the prolongator P_l, the projections become the next level's candidates,
+ * A_{l+1} = P_l^T A_l P_l; coarsening stops at <= 300 unknowns (solved by a
+ * dense inverse) or 10 levels.  Smoother: one damped Jacobi step before and
+ * after the coarse correction, weight 1/rho with rho a 15-step power
+ * estimate of the spectral radius of D^-1 A_l from the fixed start vector
+ * x_i = frac(i 2654435761 / 2^32) - 1/2.  The hierarchy's structure is
+ * built on first use per mesh and Dirichlet set, its operators once per
+ * linearization (synchronising; level 1 by probing with J v), and the
+ * cycle runs in precision prec.  NLE_E_UNSUPPORTED if the coarsest level
+ * stays above 4000 unknowns, NLE_E_STATE for a zero coarse diagonal or a
+ * singular coarsest level. */
 nle_status nle_pc_apply(nle_ctx *ctx, int32_t pc, int32_t prec, const void *x_dev, void *y_dev);
 /* Potential Pi(u) = sum_e V_e Psi(F_e) - s f_ext . u + u.R u / 2 with R
  * the spring matrix (synchronises).  NLE_E_UNSUPPORTED with a follower
@@ -397,6 +422,11 @@ nle_status nle_batch_layout(const nle_batch *b, int64_t *node_offsets);
  * every instance finished its schedule, else the last failing status. */
 nle_status nle_batch_solve(nle_batch *b, int32_t method, const nle_solver_opts *opts, double *u_dev,
                            nle_report *reports, double *t_ms);
+
+/* Unknowns per level of the multigrid hierarchy built by the last NLE_PC_AMG
+ * use (finest first): *n_levels = number of levels (0 if none is built),
+ * sizes[0 .. min(n_levels, cap)) filled. */
+nle_status nle_amg_levels(const nle_ctx *ctx, int32_t *n_levels, int64_t *sizes, int32_t cap);
 
 /* ---- mesh partition inspection (for tests and tuning) --------------------- */
 /* info[0..7] = n_blocks, max elems per block, max nodes per block,

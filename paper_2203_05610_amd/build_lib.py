@@ -21,7 +21,8 @@ LIB = os.path.join(PKG, "libnlelast.so")
 BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["nle_mesh.cpp", "nle_capi.cpp", "nle_solvers.cpp", "nle_batch.cpp", "nle_elem.hip",
-           "nle_vec.hip", "nle_batchk.hip", "nle_surf.hip", "nle_mixed.hip"]
+           "nle_vec.hip", "nle_batchk.hip", "nle_surf.hip", "nle_mixed.hip", "nle_amg.cpp",
+           "nle_amgk.hip"]
 
 ARCH = os.environ.get("NLE_OFFLOAD_ARCH", "gfx950")
 

@@ -122,6 +122,7 @@ nle_status linearize(Ctx *c, const double *u, int prec) {
   if (e != hipSuccess) return fail(c, NLE_E_HIP, std::string("diag: ") + hipGetErrorString(e));
   NLE_HIP(c, vec_recip(c, c->diag64, c->dinv64, n));
   c->blk_valid = false;
+  amg_invalidate(c);
   c->lc_valid = !c->mixed && c->lc64 != nullptr;
   c->lin64 = true;
   c->lin32 = false;
@@ -244,6 +245,7 @@ void nle_destroy(nle_ctx *ctx) {
   (void)hipStreamSynchronize(c->stream);
   if (c->kstream) (void)hipStreamSynchronize(c->kstream);
   drop_graph(c);
+  amg_release(c);
   for (void *p : c->mesh_allocs) dfree(c, p);
   for (void *p : c->ws_allocs) dfree(c, p);
   dfree(c, c->red);
@@ -430,6 +432,7 @@ nle_status nle_set_dirichlet(nle_ctx *ctx, int64_t n, const int64_t *dofs, const
     c->h_mask = mask;
     if (changed) {
       c->lin64 = c->lin32 = c->lc_valid = false;
+      amg_release(c);  // its candidates vanish on Dirichlet dofs
       return upload_node_masks(c);
     }
     NLE_HIP(c, hipStreamSynchronize(c->stream));
@@ -804,11 +807,18 @@ nle_status nle_pc_apply(nle_ctx *ctx, int32_t pc, int32_t prec, const void *x, v
   if (s != NLE_OK) return s;
   if (!x || !y) return fail(c, NLE_E_INVAL, "null vector");
   if (prec != NLE_FP64 && prec != NLE_FP32) return fail(c, NLE_E_INVAL, "bad precision");
-  if (pc != NLE_PC_NONE && pc != NLE_PC_JACOBI && pc != NLE_PC_BJACOBI3)
+  if (pc != NLE_PC_NONE && pc != NLE_PC_JACOBI && pc != NLE_PC_BJACOBI3 && pc != NLE_PC_AMG)
     return fail(c, NLE_E_INVAL, "bad pc");
   if (!(prec == NLE_FP32 ? c->lin32 : c->lin64))
     return fail(c, NLE_E_STATE, "nle_pc_apply needs nle_linearize at this precision first");
   const int64_t n = ndof(c);
+  if (pc == NLE_PC_AMG) {
+    if (x == y) return fail(c, NLE_E_INVAL, "the multigrid cycle cannot run in place");
+    s = amg_prepare(c);
+    if (s != NLE_OK) return s;
+    NLE_HIP(c, amg_apply(c, prec, x, y));
+    return NLE_OK;
+  }
   if (pc == NLE_PC_NONE) {
     NLE_HIP(c, hipMemcpyAsync(y, x, size_t(n) * (prec == NLE_FP32 ? 4 : 8),
                               hipMemcpyDeviceToDevice, c->stream));
@@ -872,6 +882,13 @@ nle_status nle_energy(nle_ctx *ctx, const double *u, double *pi) {
   s = read_scalars(c, c->dscal + 60, 32);
   if (s != NLE_OK) return s;
   *pi = c->hpin[0] - c->load_scale * c->hpin[1] + c->hpin[2] + 0.5 * c->hpin[3];
+  return NLE_OK;
+}
+
+nle_status nle_amg_levels(const nle_ctx *ctx, int32_t *n_levels, int64_t *sizes, int32_t cap) {
+  const Ctx *c = reinterpret_cast<const Ctx *>(ctx);
+  if (!c || !n_levels || (cap > 0 && !sizes) || cap < 0) return NLE_E_INVAL;
+  *n_levels = amg_levels(c, sizes, cap);
   return NLE_OK;
 }
 

@@ -167,6 +167,9 @@ struct Ctx {
   double *inst_mat = nullptr;
   int32_t *inst_done = nullptr;
   int32_t *inst_inv = nullptr;  // per-instance "some det F <= 0" flags
+  // aggregation multigrid (nle_amg.cpp), built on first use
+  void *amg = nullptr;
+
   // inertia of an implicit time step: c M (u - u_tilde) in the residual,
   // c M in the tangent (M the row-sum lumped P1 mass of density rho)
   struct {
@@ -325,6 +328,17 @@ int vec_dot_partials(Ctx *c, int prec, const void *a, const void *b, int64_t n, 
 hipError_t reduce_scalar(Ctx *c, const double *red, int np, double *out);
 hipError_t reduce_scalars(Ctx *c, const double *red, int np, int count, double *out);
 hipError_t vec_recip(Ctx *c, const double *d, double *dinv, int64_t n);
+// ---- aggregation multigrid (nle_amg.cpp) ----------------------------------------
+// amg_prepare builds what is missing for the current linearization (NLE_OK or
+// an error set on c); amg_apply is one V-cycle x = M^-1 b in precision prec;
+// amg_invalidate marks the values stale (new linearization); amg_release
+// frees everything (new mesh or Dirichlet set, destroy).
+nle_status amg_prepare(Ctx *c);
+hipError_t amg_apply(Ctx *c, int prec, const void *b, void *x);
+void amg_invalidate(Ctx *c);
+void amg_release(Ctx *c);
+int amg_levels(const Ctx *c, int64_t *sizes, int cap);
+
 hipError_t newmark_predict(Ctx *c, const double *u, const double *v, const double *a, double *ut,
                            double dt, double beta, int64_t n);
 hipError_t newmark_correct(Ctx *c, const double *u, const double *ut, double *v, double *a,

@@ -258,6 +258,7 @@ nle_status build_mesh(Ctx *c, int64_t nn, const double *X, int64_t ne, const int
   c->binv32 = nullptr;
   c->blk_valid = false;
   c->inr = decltype(c->inr)();
+  amg_release(c);
   Mesh &M = c->m;
   M = Mesh();
   M.n_nodes = nn;

@@ -550,6 +550,7 @@ nle_status build_mixed_mesh(Ctx *c, int64_t nu, const double *X, int64_t ne, con
   c->binv32 = nullptr;
   c->blk_valid = false;
   c->inr = decltype(c->inr)();
+  amg_release(c);
   c->m = Mesh();
   c->mx = MixedMesh();
   MixedMesh &M = c->mx;

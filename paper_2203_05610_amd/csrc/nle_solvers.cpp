@@ -150,6 +150,13 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
   const size_t vb = size_t(n) * esz(prec);
   const void *dinv = nullptr;
   int pcb = 1;
+  const bool amg = o.pc == NLE_PC_AMG;
+  if (amg) {
+    if (o.type != NLE_KSP_GMRES)
+      return fail(c, NLE_E_UNSUPPORTED, "the multigrid preconditioner runs with GMRES");
+    const nle_status sa = amg_prepare(c);
+    if (sa != NLE_OK) return sa;
+  }
   if (o.pc == NLE_PC_JACOBI) {
     dinv = prec == NLE_FP32 ? static_cast<const void *>(c->dinv32)
                             : static_cast<const void *>(c->dinv64);
@@ -322,7 +329,9 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
     for (int j = 0; j < m && total + queued < o.max_it; ++j) {
       const void *vj = static_cast<const char *>(a.V) + size_t(j) * vb;
       hipError_t e = hipSuccess;
-      if (dinv)
+      if (amg)
+        e = amg_apply(c, prec, vj, a.z);
+      else if (dinv)
         e = pc_apply(c, prec, pcb, dinv, vj, a.z, n);
       else
         e = hipMemcpyAsync(a.z, vj, vb, hipMemcpyDeviceToDevice, c->stream);
@@ -357,7 +366,19 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
       }
     }
     c->elem_skip = nullptr;
-    NLE_HIP(c, gmres_update_x(c, a));
+    if (amg) {
+      // x += M^-1 (V y): form V y in z, then one cycle into w
+      GmresArgs t = a;
+      t.x = a.z;
+      t.dinv = nullptr;
+      t.pcb = 1;
+      NLE_HIP(c, vec_fill(c, prec, a.z, 0.0, n));
+      NLE_HIP(c, gmres_update_x(c, t));
+      NLE_HIP(c, amg_apply(c, prec, a.z, a.w));
+      NLE_HIP(c, vec_axpy(c, prec, a.w, prec, x, 1.0, nullptr, n));
+    } else {
+      NLE_HIP(c, gmres_update_x(c, a));
+    }
     nle_status s = read_scalars(c, flag, 8);
     if (s != NLE_OK) return s;
     std::memcpy(f, c->hpin, 8);
@@ -450,10 +471,15 @@ nle_status check_ready(Ctx *c, double *u, const nle_solver_opts *o) {
   if (o->ksp_type != NLE_KSP_CG && o->ksp_type != NLE_KSP_GMRES &&
       o->ksp_type != NLE_KSP_MINRES)
     return fail(c, NLE_E_INVAL, "bad ksp_type");
-  if (o->pc != NLE_PC_JACOBI && o->pc != NLE_PC_NONE && o->pc != NLE_PC_BJACOBI3)
+  if (o->pc != NLE_PC_JACOBI && o->pc != NLE_PC_NONE && o->pc != NLE_PC_BJACOBI3 &&
+      o->pc != NLE_PC_AMG)
     return fail(c, NLE_E_INVAL, "bad pc");
   if (o->pc == NLE_PC_BJACOBI3 && c->mixed)
     return fail(c, NLE_E_UNSUPPORTED, "nodal block Jacobi needs a P1 mesh");
+  if (o->pc == NLE_PC_AMG && c->mixed)
+    return fail(c, NLE_E_UNSUPPORTED, "the multigrid preconditioner needs a P1 mesh");
+  if (o->pc == NLE_PC_AMG && o->ksp_type != NLE_KSP_GMRES)
+    return fail(c, NLE_E_UNSUPPORTED, "the multigrid preconditioner runs with GMRES");
   if (o->ksp_max_it < 1 || o->snes_max_it < 0) return fail(c, NLE_E_INVAL, "bad iteration limits");
   if (o->cg_launches != 0 && o->cg_launches != 3 && o->cg_launches != 4)
     return fail(c, NLE_E_INVAL, "bad cg_launches");
@@ -794,6 +820,11 @@ nle_status bfgs(Ctx *c, double *u, const nle_solver_opts &o, nle_report *report)
         st = fail(c, NLE_DIVERGED_LINEAR, "H0 Krylov solve produced NaN");
         break;
       }
+    } else if (o.pc == NLE_PC_AMG) {
+      // BFGS-preonly with one V-cycle as H0 (App. A)
+      s = amg_prepare(c);
+      if (s != NLE_OK) return s;
+      NLE_HIP(c, amg_apply(c, prec, q, z));
     } else if (o.pc == NLE_PC_JACOBI || blk) {
       NLE_HIP(c, pc_apply(c, prec, blk ? 3 : 1, dinv, q, z, n));
     } else {

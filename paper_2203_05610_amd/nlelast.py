@@ -29,7 +29,7 @@ NLE_MAT_M1, NLE_MAT_M2, NLE_MAT_M3, NLE_MAT_M4 = 1, 2, 3, 4
 NLE_NK, NLE_INK, NLE_BFGS = 0, 1, 2
 NLE_KSP_GMRES, NLE_KSP_CG, NLE_KSP_MINRES = 0, 1, 2
 NLE_ORTH_MGS, NLE_ORTH_CGS2 = 0, 1
-NLE_PC_NONE, NLE_PC_JACOBI, NLE_PC_BJACOBI3 = 0, 1, 2
+NLE_PC_NONE, NLE_PC_JACOBI, NLE_PC_BJACOBI3, NLE_PC_AMG = 0, 1, 2, 3
 NLE_H0_PREONLY, NLE_H0_KSP = 0, 1
 NLE_PREC_FP64, NLE_PREC_MIXED = 0, 1
 
@@ -49,7 +49,7 @@ EXPORTS = [
     "nle_batch_last_error", "nle_batch_add", "nle_batch_finalize", "nle_batch_layout",
     "nle_batch_solve", "nle_set_fibres", "nle_set_active_tension", "nle_set_pressure",
     "nle_set_robin", "nle_set_traction_follower", "nle_upload_mesh_mixed", "nle_block_diag", "nle_pc_apply", "nle_batch_autotune",
-    "nle_set_inertia", "nle_newmark_predict", "nle_newmark_correct",
+    "nle_set_inertia", "nle_newmark_predict", "nle_newmark_correct", "nle_amg_levels",
 ]
 
 
@@ -119,6 +119,7 @@ def lib() -> ctypes.CDLL:
         "nle_set_robin": (I32, [P, I64, P, D, D]),
         "nle_set_traction_follower": (I32, [P, I64, P, P]),
         "nle_set_inertia": (I32, [P, D, D, P]),
+        "nle_amg_levels": (I32, [P, P, P, I32]),
         "nle_newmark_predict": (I32, [P, D, D, P, P, P, P]),
         "nle_newmark_correct": (I32, [P, D, D, D, P, P, P, P]),
         "nle_lift": (I32, [P, P]),
@@ -389,6 +390,14 @@ def nle_block_diag(ctx: Context, b) -> None:
             and b.numel() == 6 * ctx.n_nodes):
         raise ValueError("expected a contiguous float64 CUDA tensor of 6 n_nodes entries")
     ctx.check(lib().nle_block_diag(ctx.handle, ctypes.c_void_p(b.data_ptr())))
+
+
+def nle_amg_levels(ctx: Context) -> list:
+    """Unknowns per level of the multigrid hierarchy (finest first)."""
+    n = ctypes.c_int32()
+    sizes = (ctypes.c_int64 * 16)()
+    ctx.check(lib().nle_amg_levels(ctx.handle, ctypes.byref(n), sizes, 16))
+    return [int(sizes[i]) for i in range(min(n.value, 16))]
 
 
 def nle_pc_apply(ctx: Context, pc: int, x, y, prec: int = NLE_FP64) -> None:

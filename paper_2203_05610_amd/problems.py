@@ -54,7 +54,7 @@ def make_opts(method: str, precision: str = "fp64", **over) -> nl.nle_solver_opt
     pc = over.pop("pc", None)
     if pc is not None:
         o.pc = {"none": nl.NLE_PC_NONE, "jacobi": nl.NLE_PC_JACOBI,
-                "bjacobi3": nl.NLE_PC_BJACOBI3}[pc]
+                "bjacobi3": nl.NLE_PC_BJACOBI3, "amg": nl.NLE_PC_AMG}[pc]
     orth = over.pop("orth", None)
     if orth is not None:
         o.orth = nl.NLE_ORTH_MGS if orth == "mgs" else nl.NLE_ORTH_CGS2
