@@ -51,6 +51,20 @@ METHODS = {
     "bfgs_ib_mixed_r20": ("bfgs", "mixed", {"h0": "ksp", "qn_m": 10, "ksp": "minres",
                                             "h0_refresh": 20}),
     "bfgs_ib_mixed_minres": ("bfgs", "mixed", {"h0": "ksp", "qn_m": 10, "ksp": "minres"}),
+    # aggregation multigrid (one V-cycle) with GMRES, and BFGS-preonly with
+    # the cycle as H0 (the paper's B method)
+    "nk_fp64_amg": ("nk", "fp64", {"ksp": "gmres", "pc": "amg"}),
+    "ink_mixed_amg": ("ink", "mixed", {"ksp": "gmres", "pc": "amg"}),
+    "ink_fp64_amg": ("ink", "fp64", {"ksp": "gmres", "pc": "amg"}),
+    "bfgs_b_mixed_amg": ("bfgs", "mixed", {"h0": "preonly", "qn_m": 10, "ksp": "gmres",
+                                           "pc": "amg"}),
+    "bfgs_ib_mixed_amg": ("bfgs", "mixed", {"h0": "ksp", "qn_m": 10, "ksp": "gmres",
+                                            "pc": "amg", "h0_refresh": 20}),
+    # the cycle is symmetric for the symmetric dead-load tangent: CG with it
+    "ink_mixed_cg_amg": ("ink", "mixed", {"ksp": "cg", "pc": "amg"}),
+    "ink_fp64_cg_amg": ("ink", "fp64", {"ksp": "cg", "pc": "amg"}),
+    "bfgs_ib_mixed_cg_amg": ("bfgs", "mixed", {"h0": "ksp", "qn_m": 10, "ksp": "cg",
+                                               "pc": "amg", "h0_refresh": 20}),
 }
 
 
@@ -67,7 +81,7 @@ def run_solve(ctx, u, method, schedule):
     from paper_2203_05610_amd import problems
 
     solver, prec, kw = METHODS[method]
-    opts = problems.make_opts(solver, prec, pc=PC["pc"], **dict(kw))
+    opts = problems.make_opts(solver, prec, **{"pc": PC["pc"], **kw})
     u.zero_()
     reps = problems.solve_schedule(ctx, u, solver, opts, schedule)
     return problems.schedule_ok(reps, schedule), reps
@@ -328,6 +342,12 @@ CARDIAC_METHODS = {
                                              "h0_refresh": 20, "pc": "bjacobi3"}),
     "bfgs_ib_mixed_r20_bj": ("bfgs", "mixed", {"ksp": "minres", "h0": "ksp", "qn_m": 10,
                                                "h0_refresh": 20, "pc": "bjacobi3"}),
+    "ink_fp64_amg": ("ink", "fp64", {"ksp": "gmres", "pc": "amg"}),
+    "nk_fp64_amg": ("nk", "fp64", {"ksp": "gmres", "pc": "amg"}),
+    "bfgs_b_fp64_amg": ("bfgs", "fp64", {"ksp": "gmres", "h0": "preonly", "qn_m": 10,
+                                         "pc": "amg"}),
+    "bfgs_ib_fp64_r20_amg": ("bfgs", "fp64", {"ksp": "gmres", "h0": "ksp", "qn_m": 10,
+                                              "h0_refresh": 20, "pc": "amg"}),
 }
 
 

@@ -92,8 +92,9 @@ typedef int32_t nle_status;
                              bs = 3 point-block Jacobi of a PETSc setup)  */
 #define NLE_PC_AMG 3 /* aggregation multigrid, one V(1,1)-cycle (the AMG of
                         Sec. 4 and App. A; its construction is this
-                        library's, see nle_pc_apply); P1 meshes, GMRES or
-                        BFGS-preonly only */
+                        library's, see nle_pc_apply); P1 meshes, with GMRES,
+                        CG (the cycle is symmetric for a symmetric tangent)
+                        or as the H0 of BFGS-preonly; not with MINRES */
 
 #define NLE_H0_PREONLY 0 /* BFGS-preonly: H0 = one preconditioner application */
 #define NLE_H0_KSP 1     /* inexact BFGS: H0 = Krylov solve on J(u0)          */

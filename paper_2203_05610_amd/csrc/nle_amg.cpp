@@ -681,6 +681,7 @@ nle_status amg_prepare(Ctx *c) {
   const nle_status s = build_values(c, A);
   if (s != NLE_OK) return s;
   A->valid = true;
+  ++c->amg_gen;
   return NLE_OK;
 }
 

@@ -167,8 +167,10 @@ struct Ctx {
   double *inst_mat = nullptr;
   int32_t *inst_done = nullptr;
   int32_t *inst_inv = nullptr;  // per-instance "some det F <= 0" flags
-  // aggregation multigrid (nle_amg.cpp), built on first use
+  // aggregation multigrid (nle_amg.cpp), built on first use; amg_gen counts
+  // its operator builds (captured Krylov chunks hold its smoother weights)
   void *amg = nullptr;
+  uint64_t amg_gen = 0;
 
   // inertia of an implicit time step: c M (u - u_tilde) in the residual,
   // c M in the tangent (M the row-sum lumped P1 mass of density rho)
@@ -367,7 +369,11 @@ struct CgArgs {
   double *scal;       // device scalars
   int32_t *flag;      // [0] state (1 converged, 2 breakdown, 3 NaN, 5 limit), [1] its
 };
-hipError_t cg_start(Ctx *c, const CgArgs &a, const void *b, double rtol, double atol, int max_it);
+// finish = false leaves out the final reduction (cg_start_finish), so that a
+// preconditioner applied outside the kernels can replace z, p and the r.z partials
+hipError_t cg_start(Ctx *c, const CgArgs &a, const void *b, double rtol, double atol, int max_it,
+                    bool finish = true);
+hipError_t cg_start_finish(Ctx *c, const CgArgs &a, double rtol, double atol, int max_it);
 hipError_t cg_update(Ctx *c, const CgArgs &a, bool fused = false);
 hipError_t cg_direction(Ctx *c, const CgArgs &a);
 

@@ -152,8 +152,8 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
   int pcb = 1;
   const bool amg = o.pc == NLE_PC_AMG;
   if (amg) {
-    if (o.type != NLE_KSP_GMRES)
-      return fail(c, NLE_E_UNSUPPORTED, "the multigrid preconditioner runs with GMRES");
+    if (o.type == NLE_KSP_MINRES)
+      return fail(c, NLE_E_UNSUPPORTED, "the multigrid preconditioner runs with CG or GMRES");
     const nle_status sa = amg_prepare(c);
     if (sa != NLE_OK) return sa;
   }
@@ -212,7 +212,17 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
       a.scal = c->dscal;
       a.flag = flag;
       a.np_a = 0;
-      NLE_HIP(c, cg_start(c, a, b, o.rtol, o.atol, o.max_it));
+      if (amg) {
+        // the cycle replaces z = p = M^-1 b and the r.z partials
+        NLE_HIP(c, cg_start(c, a, b, o.rtol, o.atol, o.max_it, false));
+        NLE_HIP(c, amg_apply(c, prec, a.r, a.z));
+        NLE_HIP(c, hipMemcpyAsync(a.p, a.z, vb, hipMemcpyDeviceToDevice, c->stream));
+        vec_dot_partials(c, prec, a.r, a.z, n, red_b, &e);
+        NLE_HIP(c, e);
+        NLE_HIP(c, cg_start_finish(c, a, o.rtol, o.atol, o.max_it));
+      } else {
+        NLE_HIP(c, cg_start(c, a, b, o.rtol, o.atol, o.max_it));
+      }
       c->elem_skip = flag;
       c->ep.red = red_a;
       // three launches per iteration (the next direction and the stopping
@@ -220,7 +230,7 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
       // kernels support it; four otherwise.  On the 64x64x4 Cook mesh both
       // take ~20 us per iteration: the fused form saves a launch but adds the
       // partial sums to the Jacobian action's critical path.
-      const bool fuse = !c->mixed && c->surf.nsn == 0 && o.cg_launches == 3;
+      const bool fuse = !c->mixed && c->surf.nsn == 0 && o.cg_launches == 3 && !amg;
       if (fuse) {
         c->cg.z = a.z;
         c->cg.red = red_b;
@@ -234,6 +244,11 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
         if (err != hipSuccess) return err;
         err = cg_update(c, a, fuse);
         if (err != hipSuccess || fuse) return err;
+        if (amg) {  // z = M^-1 r by one cycle (the update left z = r), then r.z
+          if ((err = amg_apply(c, prec, a.r, a.z)) != hipSuccess) return err;
+          vec_dot_partials(c, prec, a.r, a.z, n, red_b, &err);
+          if (err != hipSuccess) return err;
+        }
         return cg_direction(c, a);
       };
       std::vector<uint64_t> key = {1, uint64_t(prec), uint64_t(n), uint64_t(check),
@@ -243,7 +258,8 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
                                    uint64_t(uintptr_t(c->m.nodes)), uint64_t(c->mat.kind),
                                    uint64_t(uintptr_t(c->mx.G32)), uint64_t(uintptr_t(c->mx.cu)),
                                    uint64_t(uintptr_t(c->lc_valid ? c->lc64 : nullptr)),
-                                   uint64_t(pcb), uint64_t(fuse)};
+                                   uint64_t(pcb), uint64_t(fuse), uint64_t(amg),
+                                   amg ? c->amg_gen : 0};
       st = run_chunks(c, key, check, o.max_it, flag, iter);
     } else {
       MinresArgs a;
@@ -478,8 +494,8 @@ nle_status check_ready(Ctx *c, double *u, const nle_solver_opts *o) {
     return fail(c, NLE_E_UNSUPPORTED, "nodal block Jacobi needs a P1 mesh");
   if (o->pc == NLE_PC_AMG && c->mixed)
     return fail(c, NLE_E_UNSUPPORTED, "the multigrid preconditioner needs a P1 mesh");
-  if (o->pc == NLE_PC_AMG && o->ksp_type != NLE_KSP_GMRES)
-    return fail(c, NLE_E_UNSUPPORTED, "the multigrid preconditioner runs with GMRES");
+  if (o->pc == NLE_PC_AMG && o->ksp_type == NLE_KSP_MINRES)
+    return fail(c, NLE_E_UNSUPPORTED, "the multigrid preconditioner runs with CG or GMRES");
   if (o->ksp_max_it < 1 || o->snes_max_it < 0) return fail(c, NLE_E_INVAL, "bad iteration limits");
   if (o->cg_launches != 0 && o->cg_launches != 3 && o->cg_launches != 4)
     return fail(c, NLE_E_INVAL, "bad cg_launches");

@@ -915,7 +915,8 @@ hipError_t reduce_scalars(Ctx *c, const double *red, int np, int count, double *
 }
 
 // ------------------------------------------------------------------ CG
-hipError_t cg_start(Ctx *c, const CgArgs &a, const void *b, double rtol, double atol, int max_it) {
+hipError_t cg_start(Ctx *c, const CgArgs &a, const void *b, double rtol, double atol, int max_it,
+                    bool finish) {
   const int g = vgrid(a.n);
 #define CG_START(T, BS)                                                                        \
   LAUNCH((k_cg_start<T, BS>), g, static_cast<const T *>(b), static_cast<T *>(a.x),              \
@@ -927,7 +928,12 @@ hipError_t cg_start(Ctx *c, const CgArgs &a, const void *b, double rtol, double 
     if (a.pcb == 3) CG_START(double, 3); else CG_START(double, 1);
   }
 #undef CG_START
-  LAUNCH(k_cg_start2, 1, a.red_b, g, a.scal, a.flag, rtol, atol, max_it);
+  if (!finish) return hipGetLastError();
+  return cg_start_finish(c, a, rtol, atol, max_it);
+}
+
+hipError_t cg_start_finish(Ctx *c, const CgArgs &a, double rtol, double atol, int max_it) {
+  LAUNCH(k_cg_start2, 1, a.red_b, vgrid(a.n), a.scal, a.flag, rtol, atol, max_it);
   return hipGetLastError();
 }
 

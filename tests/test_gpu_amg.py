@@ -116,9 +116,31 @@ def test_nk_gmres_counts_follow_oracle_loop():
     assert 3 * rep["lit_total"] < rep2["lit_total"], (rep["lit_total"], rep2["lit_total"])
 
 
+def test_nk_cg_counts_follow_oracle_loop():
+    # the cycle is symmetric for the symmetric dead-load tangent: CG with it
+    mesh, P, ctx = _cook(16, 16, 2, tau=2.0)
+
+    def lin(u):
+        K = P.stiffness(u)
+        H = amg.setup(K, mesh.X, mesh.conn, P.fixed)
+        return (lambda v: K @ v), (lambda v: amg.vcycle(H, v))
+
+    ref = solvers.newton_krylov(lambda u: P.residual(u), lin, np.zeros(P.n_dofs), ksp="cg")
+    u = torch.zeros(P.n_dofs, dtype=torch.float64, device="cuda")
+    o = problems.make_opts("nk", ksp="cg", pc="amg")
+    o.check_every = 4
+    st, rep = nl.nle_solve_nk(ctx, u, o)
+    assert st == nl.NLE_OK, rep
+    assert abs(rep["nit"] - ref["nit"]) <= 1
+    for a, b in zip(rep["lit_hist"], ref["lits"]):
+        assert abs(a - b) <= max(2, 0.02 * b), (rep["lit_hist"], ref["lits"])
+
+
 SOLVES = [
     ("nk", "fp64", {"snes_rtol": 1e-11, "ksp_atol": 1e-15}),
+    ("nk", "fp64", {"snes_rtol": 1e-11, "ksp_atol": 1e-15, "ksp": "cg"}),
     ("ink", "mixed", {}),
+    ("ink", "mixed", {"ksp": "cg"}),
     ("bfgs", "fp64", {"h0": "preonly", "qn_m": 20, "snes_rtol": 1e-11, "snes_max_it": 400}),
 ]
 
@@ -128,8 +150,8 @@ def test_cook_solves_match_oracle_root(method, prec, kw):
     mesh, P, ctx = _cook(16, 16, 2, tau=2.0)
     ustar, _ = newton.newton_exact(P, np.zeros(P.n_dofs), 1.0)
     u = torch.zeros(P.n_dofs, dtype=torch.float64, device="cuda")
-    st, rep = problems.SOLVERS[method](ctx, u, problems.make_opts(method, prec, ksp="gmres",
-                                                                   pc="amg", **dict(kw)))
+    st, rep = problems.SOLVERS[method](ctx, u, problems.make_opts(
+        method, prec, **{"ksp": "gmres", "pc": "amg", **kw}))
     assert st == nl.NLE_OK, rep
     err = relnorm(u.cpu().numpy(), ustar)
     assert err <= (1e-8 if prec == "fp64" else 1e-6), err
@@ -153,7 +175,7 @@ def test_multigrid_usage_errors():
     mesh, P, ctx = _cook(8, 8, 1)
     u = torch.zeros(P.n_dofs, dtype=torch.float64, device="cuda")
     with pytest.raises(nl.NleError) as e:
-        nl.nle_solve_nk(ctx, u, problems.make_opts("nk", ksp="cg", pc="amg"))
+        nl.nle_solve_nk(ctx, u, problems.make_opts("nk", ksp="minres", pc="amg"))
     assert e.value.status == nl.NLE_E_UNSUPPORTED
     nl.nle_linearize(ctx, u, nl.NLE_FP64)
     with pytest.raises(nl.NleError) as e:
