@@ -348,6 +348,9 @@ CARDIAC_METHODS = {
                                          "pc": "amg"}),
     "bfgs_ib_fp64_r20_amg": ("bfgs", "fp64", {"ksp": "gmres", "h0": "ksp", "qn_m": 10,
                                               "h0_refresh": 20, "pc": "amg"}),
+    "ink_fp64_cg_amg": ("ink", "fp64", {"ksp": "cg", "pc": "amg"}),
+    "bfgs_ib_fp64_r20_cg_amg": ("bfgs", "fp64", {"ksp": "cg", "h0": "ksp", "qn_m": 10,
+                                                 "h0_refresh": 20, "pc": "amg"}),
 }
 
 

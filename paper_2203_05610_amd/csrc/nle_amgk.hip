@@ -1,7 +1,8 @@
 // Kernels of the aggregation multigrid: probing of the level-1 Galerkin
 // operator, the power iteration of the finest level, and the V-cycle's
 // smoother, restriction, prolongation, sparse residual and dense coarse solve.
-// Every sum runs in a fixed order (one thread per output entry), so the
+// Every sum runs in a fixed order (one thread, or one wave with a fixed
+// butterfly, per output entry), so the
 // cycle is bitwise repeatable.
 
 #include <hip/hip_runtime.h>
@@ -18,6 +19,9 @@ inline int grid_for(int64_t n) {
   const int64_t g = (n + NT - 1) / NT;
   return int(g < 1 ? 1 : (g > 65535 ? 65535 : g));
 }
+
+// one wave64 per item
+inline int grid_waves(int64_t n) { return grid_for(64 * n); }
 
 // z[r] = coefficient k of row r's aggregate when that aggregate has colour
 // `colour` and at least k+1 coarse dofs, else 0
@@ -101,28 +105,47 @@ __global__ __launch_bounds__(NT) void k_jac_upd(T *x, const T *b, const T *t, co
   }
 }
 
+// Sum over a wave64 in a fixed butterfly order (the same on every run).
+template <typename T>
+__device__ __forceinline__ T wave_total(T s) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  return s;
+}
+
+// One wave per row (rows of the coarse operators hold ~100 entries and there
+// are only a few thousand rows: a thread per row would leave most of the
+// chip idle); lanes stride over the row, then a fixed-order wave sum.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_csr_res(T *r, const T *b, const T *x, const int32_t *rp,
                                                 const int32_t *ci, const T *v, int64_t n) {
-  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w0 = (int64_t(blockIdx.x) * NT + threadIdx.x) >> 6;
+  const int64_t nw = (int64_t(gridDim.x) * NT) >> 6;
+  for (int64_t i = w0; i < n; i += nw) {
     T s = T(0);
-    for (int32_t q = rp[i]; q < rp[i + 1]; ++q) s += v[q] * x[ci[q]];
-    r[i] = b[i] - s;
+    for (int32_t q = rp[i] + lane; q < rp[i + 1]; q += 64) s += v[q] * x[ci[q]];
+    s = wave_total(s);
+    if (lane == 0) r[i] = b[i] - s;
   }
 }
 
+// One wave per coarse dof: the rows of its aggregate, strided over the lanes.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_restrict(T *bc, const T *b, const T *t, AmgXfer<T> X) {
-  for (int64_t R = int64_t(blockIdx.x) * NT + threadIdx.x; R < X.nc;
-       R += int64_t(gridDim.x) * NT) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w0 = (int64_t(blockIdx.x) * NT + threadIdx.x) >> 6;
+  const int64_t nw = (int64_t(gridDim.x) * NT) >> 6;
+  for (int64_t R = w0; R < X.nc; R += nw) {
     const int i = X.ri[R];
     T s = T(0);
-    for (int32_t q = X.rs[R]; q < X.re[R]; ++q) {
+    for (int32_t q = X.rs[R] + lane; q < X.re[R]; q += 64) {
       const int64_t r = X.arows[q];
       const T v = t ? b[r] - t[r] : b[r];
       s += X.pv[6 * r + i] * v;
     }
-    bc[R] = s;
+    s = wave_total(s);
+    if (lane == 0) bc[R] = s;
   }
 }
 
@@ -207,10 +230,10 @@ hipError_t amg_jac_upd(Ctx *c, int prec, void *x, const void *b, const void *t, 
 hipError_t amg_csr_res(Ctx *c, int prec, void *r, const void *b, const void *x, const int32_t *rp,
                        const int32_t *ci, const void *v, int64_t n) {
   if (prec == NLE_FP32)
-    LAUNCH(k_csr_res<float>, grid_for(n), static_cast<float *>(r), static_cast<const float *>(b),
+    LAUNCH(k_csr_res<float>, grid_waves(n), static_cast<float *>(r), static_cast<const float *>(b),
            static_cast<const float *>(x), rp, ci, static_cast<const float *>(v), n);
   else
-    LAUNCH(k_csr_res<double>, grid_for(n), static_cast<double *>(r),
+    LAUNCH(k_csr_res<double>, grid_waves(n), static_cast<double *>(r),
            static_cast<const double *>(b), static_cast<const double *>(x), rp, ci,
            static_cast<const double *>(v), n);
   return hipGetLastError();
@@ -219,10 +242,10 @@ hipError_t amg_csr_res(Ctx *c, int prec, void *r, const void *b, const void *x, 
 hipError_t amg_restrict(Ctx *c, int prec, void *bc, const void *b, const void *t,
                         const AmgXfer<void> &X) {
   if (prec == NLE_FP32)
-    LAUNCH(k_restrict<float>, grid_for(X.nc), static_cast<float *>(bc),
+    LAUNCH(k_restrict<float>, grid_waves(X.nc), static_cast<float *>(bc),
            static_cast<const float *>(b), static_cast<const float *>(t), typed<float>(X));
   else
-    LAUNCH(k_restrict<double>, grid_for(X.nc), static_cast<double *>(bc),
+    LAUNCH(k_restrict<double>, grid_waves(X.nc), static_cast<double *>(bc),
            static_cast<const double *>(b), static_cast<const double *>(t), typed<double>(X));
   return hipGetLastError();
 }
