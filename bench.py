@@ -498,13 +498,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--method", default="ink_mixed", choices=sorted(METHODS))
+    ap.add_argument("--method", default="ink_mixed_cg_amg", choices=sorted(METHODS))
     ap.add_argument("--baseline", default="nk_fp64", choices=sorted(METHODS))
-    ap.add_argument("--compare", default="bfgs_ib_mixed_r20",
+    ap.add_argument("--compare", default="ink_mixed,bfgs_ib_mixed_r20",
                     help="comma-separated extra methods, run once each ('' for none)")
     ap.add_argument("--jv-reps", type=int, default=200)
     ap.add_argument("--pc", default="jacobi", choices=["jacobi", "bjacobi3"],
-                    help="preconditioner of the Cook solves (point or nodal 3x3 block Jacobi)")
+                    help="preconditioner of the Cook methods that name none (point or nodal "
+                         "3x3 block Jacobi)")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-baseline", action="store_true")
@@ -517,7 +518,7 @@ def main():
     ap.add_argument("--twist-methods", default="nk_fp64,ink_mixed")
     ap.add_argument("--cardiac", default="", help="ventricle shell grid n_t,n_s,n_c (e.g. "
                     "8,80,256); empty skips this leg (minutes at full size)")
-    ap.add_argument("--cardiac-methods", default="ink_fp64,bfgs_ib_fp64_r20_bj")
+    ap.add_argument("--cardiac-methods", default="ink_fp64_cg_amg,bfgs_ib_fp64_r20_bj")
     ap.add_argument("--cardiac-steps", type=int, default=20)
     ap.add_argument("--follower", default="", help="follower-load Cook grid nx,ny,nz (e.g. "
                     "64,64,4; empty skips)")
@@ -684,9 +685,11 @@ def main():
             "workload": "Cook's membrane 64x64x4 hexes -> 98,304 P1 tets, 63,375 dofs, "
                         "lambda/mu=5000, traction schedule " + ",".join(f"{s:g}" for s in schedule),
             "method": args.method,
-            "precision": "FP32 inner (tangent, Jacobi, Krylov, L-BFGS vectors), FP64 residual/state"
-            if METHODS[args.method][1] == "mixed" else "FP64",
-            "preconditioner": {"jacobi": "Jacobi", "bjacobi3": "nodal 3x3 block Jacobi"}[PC["pc"]],
+            "precision": "FP32 inner (tangent, preconditioner, Krylov, L-BFGS vectors), FP64 "
+                         "residual/state" if METHODS[args.method][1] == "mixed" else "FP64",
+            "preconditioner": {"jacobi": "Jacobi", "bjacobi3": "nodal 3x3 block Jacobi",
+                               "amg": "aggregation multigrid, one V(1,1)-cycle"}[
+                METHODS[args.method][2].get("pc", PC["pc"])],
             "krylov": METHODS[args.method][2].get("ksp", "cg"),
             "parallelism": "1 GPU",
         },
