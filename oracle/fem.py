@@ -216,6 +216,11 @@ class Problem:
     ftrac: tuple = (0.0, 0.0, 0.0)
     # inertia of an implicit time step (set_inertia): (c, m per dof, u_tilde)
     inertia: Optional[tuple] = None
+    # viscous Robin damping on the spring faces (set_robin_damping): the
+    # face matrix of the dashpot coefficients, and the step's velocity
+    # v(u) = v_tilde + cv (u - u_tilde) (set_step_velocity): (cv, v_tilde)
+    RC: Optional[object] = None
+    step_velocity: Optional[tuple] = None
 
     def __post_init__(self):
         self.conn = np.asarray(self.conn)[:, :4].astype(np.int64)
@@ -246,6 +251,27 @@ class Problem:
         else:
             self.inertia = (c, self.lumped_mass(rho), np.array(u_tilde, dtype=np.float64))
 
+    def set_robin_damping(self, c_perp: float, c_par: float) -> None:
+        """Dashpots on the spring faces (the damping terms of the epicardial
+        condition of Sec. 4): traction -[c_perp N (x) N + c_par (I - N (x) N)] v
+        with v the velocity, integrated like the springs (consistent P1 face
+        mass).  Zero coefficients remove them."""
+        if self.robin_tri is None or (c_perp == 0.0 and c_par == 0.0):
+            self.RC = None
+        else:
+            self.RC = robin_matrix(self.X, np.asarray(self.robin_tri), c_perp, c_par)
+
+    def set_step_velocity(self, cv: float, v_tilde) -> None:
+        """The implicit step's velocity as a function of u,
+        v(u) = v_tilde + cv (u - u_tilde) (u_tilde from set_inertia), which the
+        dashpots act on; for Newmark cv = gamma / (beta dt) and
+        v_tilde = v_n + dt (1 - gamma) a_n.  cv = 0 removes it."""
+        self.step_velocity = None if cv == 0.0 else (cv, np.array(v_tilde, dtype=np.float64))
+
+    def _damping_active(self) -> bool:
+        return (self.RC is not None and self.step_velocity is not None
+                and self.inertia is not None)
+
     def surface_force(self, u: np.ndarray, load_scale: float = 1.0) -> np.ndarray:
         """Residual contribution of the follower pressure and the springs."""
         out = np.zeros(self.n_dofs)
@@ -260,6 +286,9 @@ class Problem:
         if self.inertia is not None:
             c, m, ut = self.inertia
             out += c * m * (u - ut)
+        if self._damping_active():
+            cv, vt = self.step_velocity
+            out += self.RC @ (vt + cv * (u - self.inertia[2]))
         return out
 
     # -- evaluation -------------------------------------------------------
@@ -286,6 +315,8 @@ class Problem:
         F = deformation_gradient(u, self.conn, self.G)
         if self.pressure_tri is not None or self.ftrac_tri is not None:
             raise ValueError("a follower load has no potential")
+        if self._damping_active():
+            raise ValueError("the dashpots are not evaluated in the potential")
         psi = materials.energy(self.material, F, self.params)
         springs = 0.5 * float(u @ (self.R @ u)) if self.R is not None else 0.0
         kin = 0.0
@@ -320,6 +351,8 @@ class Problem:
                                                             self.ftrac)
         if self.inertia is not None:
             K = K + sp.diags(self.inertia[0] * self.inertia[1])
+        if self._damping_active():
+            K = K + self.step_velocity[0] * self.RC
         if dirichlet:
             Dfree = sp.diags(self.free.astype(np.float64))
             K = (Dfree @ K @ Dfree + sp.diags(self.fixed.astype(np.float64))).tocsr()

@@ -81,8 +81,11 @@ def solve_heartbeat_dynamic(problem, schedule, gamma_max: float, rho: float, dt:
     acceleration kept): Newmark's average-acceleration rule (beta = 1/4,
     gamma = 1/2) with the lumped mass of density rho; each step sets the
     activation of its time as in solve_heartbeat and solves the implicit step
-    c M (u - u~) + r(u) = 0, c = 1 / (beta dt^2), by exact Newton.  Starts at
-    rest.  Returns (u, v, a, Newton histories)."""
+    c M (u - u~) + r(u) = 0, c = 1 / (beta dt^2), by exact Newton.  With
+    dashpots set on the problem (set_robin_damping) the residual also holds
+    their force at the step's velocity v~ + gamma / (beta dt) (u - u~),
+    v~ = v + dt (1 - gamma) a.  Starts at rest.  Returns (u, v, a, Newton
+    histories)."""
     from .fem import set_active_tension
 
     n = problem.n_dofs
@@ -94,11 +97,13 @@ def solve_heartbeat_dynamic(problem, schedule, gamma_max: float, rho: float, dt:
     for _, shape in schedule:
         ut = newmark_predict(u, v, a, dt, beta)
         problem.set_inertia(rho, c, ut)
+        problem.set_step_velocity(gamma / (beta * dt), v + dt * (1.0 - gamma) * a)
         set_active_tension(problem, gamma_max * shape)
         u, h = newton_exact(problem, u, shape, **kw)
         v, a = newmark_correct(u, ut, v, a, dt, beta, gamma)
         hists.append(h)
     problem.set_inertia(0.0, 0.0, u)
+    problem.set_step_velocity(0.0, None)
     return u, v, a, hists
 
 

@@ -77,3 +77,56 @@ def test_small_amplitude_vibration_follows_linear_newmark():
     assert np.linalg.norm(v[free] - vl) <= 1e-5 * np.linalg.norm(vl)
     e_lin = 0.5 * float(np.sum(Mf * vl * vl)) + 0.5 * float(ul @ (K0 @ ul))
     assert abs(e_lin - e_lin0) <= 1e-10 * e_lin0
+
+
+def test_damped_vibration_follows_linear_newmark_and_dissipates():
+    # dashpots on the x = 48 face: at strains ~1e-7 the nonlinear implicit
+    # steps equal the linear recursion written out with the independent
+    # small-strain stiffness K0 and the face damping matrix C, which loses
+    # energy at exactly the rate the trapezoidal rule implies,
+    # E_{n+1} - E_n = -(dt/4) (v_n + v_{n+1})^T C (v_n + v_{n+1})
+    m = syn.cook_mesh(4, 4, 1)
+    base = fem.cook_problem(m, mu=MU, lam=LAM, tau=0.0)
+    P = fem.Problem(base.X, base.conn, base.material, base.params, base.f_ext, base.ddofs,
+                    base.dvals, robin_tri=m.faces["load"], k_perp=0.0, k_par=0.0)
+    c_perp, c_par = 40.0, 10.0
+    P.set_robin_damping(c_perp, c_par)
+    rho, dt, beta, gamma = 1e-3, 2e-3, 0.25, 0.5
+    c, cv = 1.0 / (beta * dt * dt), gamma / (beta * dt)
+    rng = np.random.default_rng(7)
+    v0 = 1e-5 * rng.standard_normal(P.n_dofs)
+    v0[P.fixed] = 0.0
+    M = P.lumped_mass(rho)
+    free = P.free
+    K0 = linear.stiffness_linear(m.X, m.conn, LAM, MU).tocsc()[free][:, free]
+    C = fem.robin_matrix(m.X, m.faces["load"], c_perp, c_par).tocsc()[free][:, free]
+    Mf = M[free]
+    a0 = np.zeros(P.n_dofs)
+    a0[free] = -(C @ v0[free]) / Mf  # consistent start at u = 0
+    A = (K0 + sp.diags(c * Mf) + cv * C).tocsc()
+    ul, vl, al = np.zeros(free.sum()), v0[free].copy(), a0[free].copy()
+    u, v, a = np.zeros(P.n_dofs), v0.copy(), a0.copy()
+    energy = lambda uu, vv: 0.5 * float(np.sum(Mf * vv * vv)) + 0.5 * float(uu @ (K0 @ uu))
+    e_prev, lost = energy(ul, vl), 0.0
+    for _ in range(10):
+        ut = newton.newmark_predict(u, v, a, dt, beta)
+        P.set_inertia(rho, c, ut)
+        P.set_step_velocity(cv, v + dt * (1.0 - gamma) * a)
+        u, _ = newton.newton_exact(P, u, 1.0, rtol=1e-14)
+        v, a = newton.newmark_correct(u, ut, v, a, dt, beta, gamma)
+        utl = ul + dt * vl + dt * dt * (0.5 - beta) * al
+        vtl = vl + dt * (1.0 - gamma) * al
+        vold = vl
+        ul = spla.spsolve(A, c * Mf * utl + C @ (cv * utl - vtl))
+        anew = c * (ul - utl)
+        vl = vl + dt * ((1 - gamma) * al + gamma * anew)
+        al = anew
+        vb = vold + vl
+        d = -0.25 * dt * float(vb @ (C @ vb))
+        e_new = energy(ul, vl)
+        assert abs((e_new - e_prev) - d) <= 1e-9 * e_prev
+        lost -= d
+        e_prev = e_new
+    assert lost > 1e-3 * energy(np.zeros_like(ul), v0[free])  # the dashpots matter
+    assert np.linalg.norm(u[free] - ul) <= 1e-5 * np.linalg.norm(ul)
+    assert np.linalg.norm(v[free] - vl) <= 1e-5 * np.linalg.norm(vl)
