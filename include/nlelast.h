@@ -288,10 +288,29 @@ nle_status nle_set_robin(nle_ctx *ctx, int64_t n_faces, const int32_t *tri, doub
  * or non-finite values or a null u_tilde while on.  Resets linearizations. */
 nle_status nle_set_inertia(nle_ctx *ctx, double rho, double coef, const double *u_tilde_dev);
 /* Newmark predictor (double, device, 3 n_nodes each):
- * u_tilde = u + dt v + dt^2 (1/2 - beta) a.  NLE_E_INVAL for dt <= 0 or
- * beta <= 0. */
-nle_status nle_newmark_predict(nle_ctx *ctx, double dt, double beta, const double *u_dev,
-                               const double *v_dev, const double *a_dev, double *u_tilde_dev);
+ * u_tilde = u + dt v + dt^2 (1/2 - beta) a and, if v_tilde_dev is not NULL,
+ * v_tilde = v + dt (1 - gamma) a (the part of the new velocity known before
+ * the solve; see nle_set_step_velocity).  NLE_E_INVAL for dt <= 0,
+ * beta <= 0 or a non-finite gamma. */
+nle_status nle_newmark_predict(nle_ctx *ctx, double dt, double beta, double gamma,
+                               const double *u_dev, const double *v_dev, const double *a_dev,
+                               double *u_tilde_dev, double *v_tilde_dev);
+/* Viscous dashpots on the spring faces (the damping terms of the epicardial
+ * Robin condition of Sec. 4): traction -(c_perp N (x) N + c_par (I - N (x) N))
+ * v with v the velocity, integrated like the springs.  They act only in an
+ * implicit step, with inertia on (nle_set_inertia) and the step's velocity
+ * set (nle_set_step_velocity): the residual gains M_C (v_tilde + cv (u -
+ * u_tilde)), the tangent and its diagonals cv M_C; nle_energy refuses them.
+ * Zero coefficients switch them off.  NLE_E_INVAL for negative or
+ * non-finite values; P1 meshes only.  Resets linearizations. */
+nle_status nle_set_robin_damping(nle_ctx *ctx, double c_perp, double c_par);
+/* The implicit step's velocity as an affine function of the unknown u:
+ * v(u) = v_tilde + cv (u - u_tilde) (u_tilde from nle_set_inertia).  For
+ * Newmark cv = gamma / (beta dt) and v_tilde from nle_newmark_predict.
+ * v_tilde_dev (double, device, 3 n_nodes) is copied; cv = 0 switches it off.
+ * NLE_E_INVAL for a negative or non-finite cv, or a null v_tilde while on.
+ * Resets linearizations. */
+nle_status nle_set_step_velocity(nle_ctx *ctx, double cv, const double *v_tilde_dev);
 /* Newmark corrector after the step's solve, in place (double, device):
  * a_new = (u - u_tilde) / (beta dt^2), v += dt ((1 - gamma) a + gamma a_new),
  * a = a_new.  Dirichlet dofs are not special-cased: with fixed values there

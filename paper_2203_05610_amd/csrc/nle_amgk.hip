@@ -161,13 +161,18 @@ __global__ __launch_bounds__(NT) void k_prolong(T *x, const T *xc, AmgXfer<T> X)
   }
 }
 
+// coarsest solve: one wave per row of the dense inverse
 template <typename T>
 __global__ __launch_bounds__(NT) void k_dense_mv(T *x, const T *A, const T *b, int64_t n) {
-  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w0 = (int64_t(blockIdx.x) * NT + threadIdx.x) >> 6;
+  const int64_t nw = (int64_t(gridDim.x) * NT) >> 6;
+  for (int64_t i = w0; i < n; i += nw) {
     T s = T(0);
     const T *row = A + i * n;
-    for (int64_t j = 0; j < n; ++j) s += row[j] * b[j];
-    x[i] = s;
+    for (int64_t j = lane; j < n; j += 64) s += row[j] * b[j];
+    s = wave_total(s);
+    if (lane == 0) x[i] = s;
   }
 }
 
@@ -262,10 +267,10 @@ hipError_t amg_prolong_add(Ctx *c, int prec, void *x, const void *xc, const AmgX
 
 hipError_t amg_dense_mv(Ctx *c, int prec, void *x, const void *Ainv, const void *b, int64_t n) {
   if (prec == NLE_FP32)
-    LAUNCH(k_dense_mv<float>, grid_for(n), static_cast<float *>(x),
+    LAUNCH(k_dense_mv<float>, grid_waves(n), static_cast<float *>(x),
            static_cast<const float *>(Ainv), static_cast<const float *>(b), n);
   else
-    LAUNCH(k_dense_mv<double>, grid_for(n), static_cast<double *>(x),
+    LAUNCH(k_dense_mv<double>, grid_waves(n), static_cast<double *>(x),
            static_cast<const double *>(Ainv), static_cast<const double *>(b), n);
   return hipGetLastError();
 }

@@ -681,15 +681,54 @@ nle_status nle_set_inertia(nle_ctx *ctx, double rho, double coef, const double *
   });
 }
 
-nle_status nle_newmark_predict(nle_ctx *ctx, double dt, double beta, const double *u,
-                               const double *v, const double *a, double *ut) {
+nle_status nle_newmark_predict(nle_ctx *ctx, double dt, double beta, double gamma,
+                               const double *u, const double *v, const double *a, double *ut,
+                               double *vt) {
   Ctx *c = reinterpret_cast<Ctx *>(ctx);
   nle_status s = need_mesh(c);
   if (s != NLE_OK) return s;
   if (!u || !v || !a || !ut) return fail(c, NLE_E_INVAL, "null vector");
   if (!(dt > 0.0) || !(beta > 0.0)) return fail(c, NLE_E_INVAL, "dt and beta must be positive");
-  NLE_HIP(c, newmark_predict(c, u, v, a, ut, dt, beta, ndof(c)));
+  if (!std::isfinite(gamma)) return fail(c, NLE_E_INVAL, "non-finite gamma");
+  NLE_HIP(c, newmark_predict(c, u, v, a, ut, vt, dt, beta, gamma, ndof(c)));
   return NLE_OK;
+}
+
+nle_status nle_set_robin_damping(nle_ctx *ctx, double c_perp, double c_par) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  nle_status s = need_mesh(c);
+  if (s != NLE_OK) return s;
+  if (c->mixed) return fail(c, NLE_E_UNSUPPORTED, "not available on mixed meshes");
+  if (!std::isfinite(c_perp) || !std::isfinite(c_par) || c_perp < 0.0 || c_par < 0.0)
+    return fail(c, NLE_E_INVAL, "dashpot coefficients must be finite and >= 0");
+  drop_graph(c);  // kernel arguments of captured chunks
+  c->surf.cperp = c_perp;
+  c->surf.cpar = c_par;
+  c->lin64 = c->lin32 = c->lc_valid = false;
+  return NLE_OK;
+}
+
+nle_status nle_set_step_velocity(nle_ctx *ctx, double cv, const double *vt) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  nle_status s = need_mesh(c);
+  if (s != NLE_OK) return s;
+  if (c->mixed) return fail(c, NLE_E_UNSUPPORTED, "not available on mixed meshes");
+  if (!std::isfinite(cv) || cv < 0.0) return fail(c, NLE_E_INVAL, "cv must be finite and >= 0");
+  if (cv > 0.0 && !vt) return fail(c, NLE_E_INVAL, "null v_tilde");
+  return guarded(c, [&]() -> nle_status {
+    const int64_t n = 3 * c->m.n_nodes;
+    if (cv > 0.0 && !c->inr.vt) {
+      c->inr.vt = static_cast<double *>(dalloc(c, size_t(n) * 8));
+      if (!c->inr.vt) return fail(c, NLE_E_OOM, "device allocation failed (step velocity)");
+      c->mesh_allocs.push_back(c->inr.vt);
+    }
+    if (cv != c->inr.cv) drop_graph(c);  // a kernel argument of captured chunks
+    c->inr.cv = cv;
+    c->lin64 = c->lin32 = c->lc_valid = false;
+    if (cv > 0.0)
+      NLE_HIP(c, hipMemcpyAsync(c->inr.vt, vt, n * 8, hipMemcpyDeviceToDevice, c->stream));
+    return NLE_OK;
+  });
 }
 
 nle_status nle_newmark_correct(nle_ctx *ctx, double dt, double beta, double gamma,
@@ -846,6 +885,7 @@ nle_status nle_energy(nle_ctx *ctx, const double *u, double *pi) {
   if (!u || !pi) return fail(c, NLE_E_INVAL, "null argument");
   if (c->surf.npf + c->surf.ntf > 0)
     return fail(c, NLE_E_UNSUPPORTED, "a follower load has no potential");
+  if (damping_on(c)) return fail(c, NLE_E_UNSUPPORTED, "dashpots have no potential here");
   s = need_fibres(c);
   if (s != NLE_OK) return s;
   hipError_t e;

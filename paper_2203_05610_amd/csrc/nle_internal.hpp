@@ -156,6 +156,7 @@ struct Ctx {
     double *fs64 = nullptr;      // [3 n_nodes] contributions (zero off the face nodes)
     float *fs32 = nullptr;
     double p = 0.0, kperp = 0.0, kpar = 0.0;
+    double cperp = 0.0, cpar = 0.0;  // dashpots on the spring faces
     double tf[3] = {0.0, 0.0, 0.0};  // follower traction per unit current area
     std::vector<int32_t> h_ptri, h_ttri, h_rtri, h_tri;
     std::vector<void *> allocs;
@@ -180,6 +181,9 @@ struct Ctx {
     double *cm64 = nullptr;  // [3 n_nodes] c * m per dof
     float *cm32 = nullptr;
     double *ut = nullptr;    // [3 n_nodes] u_tilde
+    // the step's velocity v(u) = vt + cv (u - ut), which the dashpots act on
+    double cv = 0.0;
+    double *vt = nullptr;    // [3 n_nodes]
   } inr;
 
   // batched mode: when set, the element kernels run only the listed blocks
@@ -341,8 +345,14 @@ void amg_invalidate(Ctx *c);
 void amg_release(Ctx *c);
 int amg_levels(const Ctx *c, int64_t *sizes, int cap);
 
+// dashpots act only in an implicit step with a velocity set
+inline bool damping_on(const Ctx *c) {
+  return c->inr.on && c->inr.cv > 0.0 && c->inr.vt && c->surf.nrf > 0 &&
+         (c->surf.cperp != 0.0 || c->surf.cpar != 0.0);
+}
+// ut = u + dt v + dt^2 (1/2 - beta) a; vt (if not null) = v + dt (1 - gamma) a
 hipError_t newmark_predict(Ctx *c, const double *u, const double *v, const double *a, double *ut,
-                           double dt, double beta, int64_t n);
+                           double *vt, double dt, double beta, double gamma, int64_t n);
 hipError_t newmark_correct(Ctx *c, const double *u, const double *ut, double *v, double *a,
                            double dt, double beta, double gamma, int64_t n);
 int vec_wdiff2_partials(Ctx *c, const double *w, const double *x, const double *y, int64_t n,

@@ -42,6 +42,9 @@ struct SurfArgs {
   const double *plin;   // effective pressure and load scale at the linearization (Jacobian action)
   double tf[3];         // follower traction
   double kperp, kpar;
+  int32_t damp;         // dashpots: velocity vt + cv (u - ut) through cperp, cpar
+  double cperp, cpar, cv;
+  const double *vt, *ut;
   const T *u, *v;
   T *fs;
   double *red;          // energy partials (one per workgroup)
@@ -157,25 +160,40 @@ __global__ __launch_bounds__(NT) void k_surface(SurfArgs<T> A) {
         const T N[3] = {R[0], R[1], R[2]};
         const T area = R[3];
         const T kpar = T(A.kpar), dk = T(A.kperp - A.kpar);
+        // the dashpots' force C (vt + cv (u - ut)) adds cv C to the tangent
+        const T kpe = A.damp ? T(A.kpar + A.cv * A.cpar) : kpar;
+        const T dke = A.damp ? T(A.kperp - A.kpar + A.cv * (A.cperp - A.cpar)) : dk;
         if (OP == OP_DIAG) {
 #pragma unroll
-          for (int i = 0; i < 3; ++i) acc[i] += area / T(6) * (kpar + dk * N[i] * N[i]);
+          for (int i = 0; i < 3; ++i) acc[i] += area / T(6) * (kpe + dke * N[i] * N[i]);
         } else if (OP == OP_ODIAG) {
 #pragma unroll
-          for (int i = 0; i < 3; ++i) acc[i] += area / T(6) * dk * N[i] * N[(i + 1) % 3];
+          for (int i = 0; i < 3; ++i) acc[i] += area / T(6) * dke * N[i] * N[(i + 1) % 3];
         } else {
           const T *w = OP == OP_JV ? A.v : A.u;
           const uint32_t fm = (OP == OP_JV && !A.nomask) ? A.fmask[f] : 0u;
+          const T kw = OP == OP_JV ? kpe : kpar, dw = OP == OP_JV ? dke : dk;
 #pragma unroll
           for (int b = 0; b < 3; ++b) {
             const T m = area / T(12) * (n[b] == g ? T(2) : T(1));
+            const int64_t nb = int64_t(n[b]);
             T wb[3];
 #pragma unroll
             for (int i = 0; i < 3; ++i)
-              wb[i] = ((fm >> (3 * b + i)) & 1u) ? T(0) : w[3 * int64_t(n[b]) + i];
+              wb[i] = ((fm >> (3 * b + i)) & 1u) ? T(0) : w[3 * nb + i];
             const T nw = N[0] * wb[0] + N[1] * wb[1] + N[2] * wb[2];
 #pragma unroll
-            for (int i = 0; i < 3; ++i) acc[i] += m * (kpar * wb[i] + dk * nw * N[i]);
+            for (int i = 0; i < 3; ++i) acc[i] += m * (kw * wb[i] + dw * nw * N[i]);
+            if (OP == OP_RES && A.damp) {
+              T z[3];
+#pragma unroll
+              for (int i = 0; i < 3; ++i)
+                z[i] = T(A.vt[3 * nb + i] + A.cv * (double(A.u[3 * nb + i]) - A.ut[3 * nb + i]));
+              const T nz = N[0] * z[0] + N[1] * z[1] + N[2] * z[2];
+              const T cpar = T(A.cpar), dc = T(A.cperp - A.cpar);
+#pragma unroll
+              for (int i = 0; i < 3; ++i) acc[i] += m * (cpar * z[i] + dc * nz * N[i]);
+            }
           }
         }
       }
@@ -227,6 +245,12 @@ void launch_surface(Ctx *c, int op, const T *u, const T *v, T *fs, double *red, 
   for (int i = 0; i < 3; ++i) A.tf[i] = S.tf[i];
   A.kperp = S.kperp;
   A.kpar = S.kpar;
+  A.damp = damping_on(c) ? 1 : 0;
+  A.cperp = S.cperp;
+  A.cpar = S.cpar;
+  A.cv = c->inr.cv;
+  A.vt = c->inr.vt;
+  A.ut = c->inr.ut;
   A.u = u;
   A.v = v;
   A.fs = fs;

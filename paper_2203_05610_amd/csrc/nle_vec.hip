@@ -63,11 +63,14 @@ __global__ __launch_bounds__(NT) void k_axpy(const S *x, D *y, double a, const d
 // Newmark's average-acceleration family: predictor u~ = u + dt v + dt^2 (1/2 - beta) a
 // and corrector a' = (u' - u~) / (beta dt^2), v' = v + dt ((1 - gamma) a + gamma a').
 __global__ __launch_bounds__(NT) void k_newmark_predict(const double *u, const double *v,
-                                                        const double *a, double *ut, double dt,
-                                                        double beta, int64_t n) {
-  const double h2 = dt * dt * (0.5 - beta);
-  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT)
+                                                        const double *a, double *ut, double *vt,
+                                                        double dt, double beta, double gamma,
+                                                        int64_t n) {
+  const double h2 = dt * dt * (0.5 - beta), h1 = dt * (1.0 - gamma);
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT) {
     ut[i] = u[i] + dt * v[i] + h2 * a[i];
+    if (vt) vt[i] = v[i] + h1 * a[i];
+  }
 }
 
 __global__ __launch_bounds__(NT) void k_newmark_correct(const double *u, const double *ut,
@@ -857,8 +860,8 @@ hipError_t block_inverse(Ctx *c, int64_t nn) {
 }
 
 hipError_t newmark_predict(Ctx *c, const double *u, const double *v, const double *a, double *ut,
-                           double dt, double beta, int64_t n) {
-  LAUNCH(k_newmark_predict, vgrid(n), u, v, a, ut, dt, beta, n);
+                           double *vt, double dt, double beta, double gamma, int64_t n) {
+  LAUNCH(k_newmark_predict, vgrid(n), u, v, a, ut, vt, dt, beta, gamma, n);
   return hipGetLastError();
 }
 

@@ -50,6 +50,7 @@ EXPORTS = [
     "nle_batch_solve", "nle_set_fibres", "nle_set_active_tension", "nle_set_pressure",
     "nle_set_robin", "nle_set_traction_follower", "nle_upload_mesh_mixed", "nle_block_diag", "nle_pc_apply", "nle_batch_autotune",
     "nle_set_inertia", "nle_newmark_predict", "nle_newmark_correct", "nle_amg_levels",
+    "nle_set_robin_damping", "nle_set_step_velocity",
 ]
 
 
@@ -120,7 +121,9 @@ def lib() -> ctypes.CDLL:
         "nle_set_traction_follower": (I32, [P, I64, P, P]),
         "nle_set_inertia": (I32, [P, D, D, P]),
         "nle_amg_levels": (I32, [P, P, P, I32]),
-        "nle_newmark_predict": (I32, [P, D, D, P, P, P, P]),
+        "nle_newmark_predict": (I32, [P, D, D, D, P, P, P, P, P]),
+        "nle_set_robin_damping": (I32, [P, D, D]),
+        "nle_set_step_velocity": (I32, [P, D, P]),
         "nle_newmark_correct": (I32, [P, D, D, D, P, P, P, P]),
         "nle_lift": (I32, [P, P]),
         "nle_residual": (I32, [P, P, P, ctypes.POINTER(D)]),
@@ -329,10 +332,22 @@ def nle_set_inertia(ctx: Context, rho: float, coef: float, u_tilde=None) -> None
     ctx.check(lib().nle_set_inertia(ctx.handle, float(rho), float(coef), pu))
 
 
-def nle_newmark_predict(ctx: Context, dt: float, beta: float, u, v, a, u_tilde) -> None:
+def nle_newmark_predict(ctx: Context, dt: float, beta: float, u, v, a, u_tilde,
+                        gamma: float = 0.5, v_tilde=None) -> None:
     T = ctx.torch.float64
-    ctx.check(lib().nle_newmark_predict(ctx.handle, float(dt), float(beta), ctx.vec(u, T),
-                                        ctx.vec(v, T), ctx.vec(a, T), ctx.vec(u_tilde, T)))
+    pv = None if v_tilde is None else ctx.vec(v_tilde, T)
+    ctx.check(lib().nle_newmark_predict(ctx.handle, float(dt), float(beta), float(gamma),
+                                        ctx.vec(u, T), ctx.vec(v, T), ctx.vec(a, T),
+                                        ctx.vec(u_tilde, T), pv))
+
+
+def nle_set_robin_damping(ctx: Context, c_perp: float, c_par: float) -> None:
+    ctx.check(lib().nle_set_robin_damping(ctx.handle, float(c_perp), float(c_par)))
+
+
+def nle_set_step_velocity(ctx: Context, cv: float, v_tilde=None) -> None:
+    pv = None if v_tilde is None else ctx.vec(v_tilde, ctx.torch.float64)
+    ctx.check(lib().nle_set_step_velocity(ctx.handle, float(cv), pv))
 
 
 def nle_newmark_correct(ctx: Context, dt: float, beta: float, gamma: float, u, u_tilde, v,

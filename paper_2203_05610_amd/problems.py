@@ -168,23 +168,27 @@ def solve_heartbeat(ctx: nl.Context, u, method: str, opts, schedule, gamma_max: 
 def solve_heartbeat_dynamic(ctx: nl.Context, u, method: str, opts, schedule, gamma_max: float,
                             rho: float, dt: float, beta: float = 0.25, gamma: float = 0.5,
                             v=None, a=None, hist_cap: int = 4096):
-    """Heartbeat with inertia: each time step (t, shape) predicts u~ with
-    Newmark's rule, sets the inertia c M (u - u~) with c = 1 / (beta dt^2)
-    and density rho, the active tension gamma_max * shape and the pressure
-    load scale shape, solves the implicit step warm-started from u, then
-    corrects v and a in place (both start at zero unless given).  Stops at
-    the first step that fails (a smaller step would change c).  The inertia
-    is switched off on return.  Returns (reports, v, a)."""
+    """Heartbeat with inertia: each time step (t, shape) predicts u~ and v~
+    with Newmark's rule, sets the inertia c M (u - u~) with c = 1 / (beta
+    dt^2) and density rho and the step velocity v~ + gamma / (beta dt)
+    (u - u~) (which dashpots set with nle_set_robin_damping act on), the
+    active tension gamma_max * shape and the pressure load scale shape,
+    solves the implicit step warm-started from u, then corrects v and a in
+    place (both start at zero unless given).  Stops at the first step that
+    fails (a smaller step would change c).  The inertia and the step
+    velocity are switched off on return.  Returns (reports, v, a)."""
     torch = ctx.torch
     v = torch.zeros_like(u) if v is None else v
     a = torch.zeros_like(u) if a is None else a
     ut = torch.empty_like(u)
+    vt = torch.empty_like(u)
     c = 1.0 / (beta * dt * dt)
     reps = []
     try:
         for t, sh in schedule:
-            nl.nle_newmark_predict(ctx, dt, beta, u, v, a, ut)
+            nl.nle_newmark_predict(ctx, dt, beta, u, v, a, ut, gamma=gamma, v_tilde=vt)
             nl.nle_set_inertia(ctx, rho, c, ut)
+            nl.nle_set_step_velocity(ctx, gamma / (beta * dt), vt)
             nl.nle_set_active_tension(ctx, gamma_max * sh)
             nl.nle_set_load_scale(ctx, sh)
             st, rep = SOLVERS[method](ctx, u, opts, hist_cap)
@@ -195,6 +199,7 @@ def solve_heartbeat_dynamic(ctx: nl.Context, u, method: str, opts, schedule, gam
             nl.nle_newmark_correct(ctx, dt, beta, gamma, u, ut, v, a)
     finally:
         nl.nle_set_inertia(ctx, 0.0, 0.0, None)
+        nl.nle_set_step_velocity(ctx, 0.0, None)
     return reps, v, a
 
 

@@ -27,6 +27,8 @@ from paper_2203_05610_amd import problems  # noqa: E402
 C = syn.CARDIAC
 RHO = 1e-7  # moves the 5-step cardiac trajectory ~20% away from the quasi-static one
 BETA, GAMMA = 0.25, 0.5
+# epicardial dashpots: move the 5-step damped trajectory ~11% from the undamped one
+C_PERP, C_PAR = 2e-5, 2e-6
 
 
 def _t(x, dtype=torch.float64):
@@ -108,9 +110,11 @@ def test_newmark_vectors():
     u, v, a, un = (rng.standard_normal(P.n_dofs) for _ in range(4))
     dt = 0.013
     ut = torch.empty(P.n_dofs, dtype=torch.float64, device="cuda")
-    nl.nle_newmark_predict(ctx, dt, BETA, _t(u), _t(v), _t(a), ut)
+    vt = torch.empty_like(ut)
+    nl.nle_newmark_predict(ctx, dt, BETA, _t(u), _t(v), _t(a), ut, gamma=GAMMA, v_tilde=vt)
     ut_ref = newton.newmark_predict(u, v, a, dt, BETA)
     assert relmax(ut.cpu().numpy(), ut_ref) < 1e-14
+    assert relmax(vt.cpu().numpy(), v + dt * (1.0 - GAMMA) * a) < 1e-14
     vd, ad = _t(v), _t(a)
     nl.nle_newmark_correct(ctx, dt, BETA, GAMMA, _t(un), ut, vd, ad)
     v_ref, a_ref = newton.newmark_correct(un, ut.cpu().numpy(), v, a, dt, BETA, GAMMA)
@@ -146,6 +150,54 @@ def test_inertia_usage_errors():
     r = torch.empty_like(z)
     nl.nle_residual(ctx, _t(u), r)
     assert relmax(r.cpu().numpy(), P.residual(u, 1.0)) < 1e-12
+
+
+def test_dashpot_kernels_cardiac():
+    mesh, P, ctx = _cardiac(128)
+    u = P.lift(smooth_state(mesh, P.n_dofs, seed=76, amp=0.02))
+    ut = P.lift(smooth_state(mesh, P.n_dofs, seed=77, amp=0.02))
+    vt = syn.random_field(P.n_dofs, 0.05, seed=78)
+    vt[P.fixed] = 0.0
+    c, cv = 1.0 / (BETA * C["dt"] ** 2), GAMMA / (BETA * C["dt"])
+    P.set_inertia(RHO, c, ut)
+    P.set_robin_damping(C_PERP, C_PAR)
+    P.set_step_velocity(cv, vt)
+    nl.nle_set_inertia(ctx, RHO, c, _t(ut))
+    nl.nle_set_robin_damping(ctx, C_PERP, C_PAR)
+    nl.nle_set_step_velocity(ctx, cv, _t(vt))
+    s = 0.6
+    nl.nle_set_load_scale(ctx, s)
+    r = torch.empty(P.n_dofs, dtype=torch.float64, device="cuda")
+    nl.nle_residual(ctx, _t(u), r)
+    ref = P.residual(u, s)
+    assert relmax(r.cpu().numpy(), ref) < 1e-12
+    # the dashpots change the residual well above rounding
+    P.set_robin_damping(0.0, 0.0)
+    assert relmax(P.residual(u, s), ref) > 1e-6
+    P.set_robin_damping(C_PERP, C_PAR)
+    nl.nle_linearize(ctx, _t(u), nl.NLE_FP32)
+    K = P.stiffness(u, load_scale=s)
+    v = syn.random_field(P.n_dofs, 1.0, seed=79)
+    y = torch.empty(P.n_dofs, dtype=torch.float64, device="cuda")
+    nl.nle_jv(ctx, _t(v), y, nl.NLE_FP64)
+    assert relmax(y.cpu().numpy(), K @ v) < 1e-12
+    y32 = torch.empty(P.n_dofs, dtype=torch.float32, device="cuda")
+    nl.nle_jv(ctx, _t(v, torch.float32), y32, nl.NLE_FP32)
+    assert relnorm(y32.double().cpu().numpy(), K @ v) < 1e-5
+    d = torch.empty(P.n_dofs, dtype=torch.float64, device="cuda")
+    nl.nle_diag(ctx, d)
+    assert relmax(d.cpu().numpy(), K.diagonal()) < 1e-12
+    b = torch.empty(6 * mesh.n_nodes, dtype=torch.float64, device="cuda")
+    nl.nle_block_diag(ctx, b)
+    B = precond.node_blocks(K, mesh.n_nodes)
+    ref6 = np.stack([B[:, 0, 0], B[:, 1, 1], B[:, 2, 2], B[:, 0, 1], B[:, 1, 2], B[:, 0, 2]], 1)
+    assert relmax(b.cpu().numpy().reshape(-1, 6), ref6) < 1e-12
+    with pytest.raises(nl.NleError) as e:
+        nl.nle_set_robin_damping(ctx, -1.0, 0.0)
+    assert e.value.status == nl.NLE_E_INVAL
+    with pytest.raises(nl.NleError) as e:
+        nl.nle_set_step_velocity(ctx, 1.0, None)
+    assert e.value.status == nl.NLE_E_INVAL
 
 
 N_STEPS = 5
@@ -185,3 +237,25 @@ def test_dynamic_heartbeat_matches_oracle(method, prec, kw):
     # the step left, a difference of much larger element forces: rounding
     # sits near 1e-11 of it, while a leftover inertia term would be O(1)
     assert relmax(r.cpu().numpy(), P.residual(u.cpu().numpy(), steps[-1][1])) < 1e-9
+
+
+@pytest.mark.parametrize("method,prec,kw", DYN[:2])
+def test_damped_dynamic_heartbeat_matches_oracle(method, prec, kw):
+    mesh = syn.shell_mesh(2, 6, 12)
+    steps = syn.heartbeat_schedule()[:N_STEPS]
+    P = fem.cardiac_problem(mesh, C)
+    P.set_robin_damping(C_PERP, C_PAR)
+    u_ref, v_ref, a_ref, _ = newton.solve_heartbeat_dynamic(P, steps, C["gamma_max"], RHO,
+                                                            C["dt"], rtol=1e-13)
+    ctx = nl.Context(0)
+    problems.setup_cardiac(ctx, mesh, C, syn.shell_dirichlet(mesh), block_size=128)
+    nl.nle_set_robin_damping(ctx, C_PERP, C_PAR)
+    opts = problems.make_opts(method, prec, ksp="gmres", restart=1000, **dict(kw))
+    u = torch.zeros(mesh.n_dofs, dtype=torch.float64, device="cuda")
+    reps, v, a = problems.solve_heartbeat_dynamic(ctx, u, method, opts, steps, C["gamma_max"],
+                                                  RHO, C["dt"], BETA, GAMMA)
+    assert problems.heartbeat_ok(reps, steps), [(r["t"], r["status_name"]) for r in reps]
+    tol = 1e-8 if prec == "fp64" else 1e-6
+    for got, ref in ((u, u_ref), (v, v_ref), (a, a_ref)):
+        err = relnorm(got.cpu().numpy(), ref)
+        assert err <= tol, err
