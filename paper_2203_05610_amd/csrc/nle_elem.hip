@@ -466,12 +466,18 @@ __device__ __forceinline__ void element_forces(const ElemIn<T> &d, const T *uS, 
     C[2][1] = D[0][2] * D[1][0] - D[0][0] * D[1][2];
     C[2][2] = D[0][0] * D[1][1] - D[0][1] * D[1][0];
     const T det = D[0][0] * C[0][0] + D[0][1] * C[0][1] + D[0][2] * C[0][2];
-    const T id = T(1) / det;
+    // FP32: the hardware reciprocal (1 ulp) instead of a correctly rounded
+    // division sequence; FP64 keeps the division
+    T id;
+    if (sizeof(T) == 8)
+      id = T(1) / det;
+    else
+      id = T(__builtin_amdgcn_rcpf(float(det)));
 #pragma unroll
     for (int a = 1; a < 4; ++a)
 #pragma unroll
       for (int j = 0; j < 3; ++j) g[a][j] = C[j][a - 1] * id;
-    Vt = det / T(6);
+    Vt = det * T(1.0 / 6.0);
   }
 #pragma unroll
   for (int j = 0; j < 3; ++j) g[0][j] = -(g[1][j] + g[2][j] + g[3][j]);
@@ -579,17 +585,18 @@ __device__ __forceinline__ void element_forces(const ElemIn<T> &d, const T *uS, 
 #pragma unroll
       for (int j = 0; j < 3; ++j)
         M[p][j] = dF[0][p] * k.FiT[0][j] + dF[1][p] * k.FiT[1][j] + dF[2][p] * k.FiT[2][j];
-    const T ca = T(V * cf.a), cX = T(V * cf.cX);
-    const T sT = T(V * cf.cT) * L + (MAT != NLE_MAT_M1 ? T(V * cf.cM) * FdF : T(0));
-    T sF = MAT != NLE_MAT_M1 ? T(V * cf.cF) * L : T(0);
-    if (MAT == NLE_MAT_M4) sF += T(V * cf.cFF) * FdF;
+    // coefficient products in the action's own precision (V = Vt exactly)
+    const T ca = Vt * T(cf.a), cX = Vt * T(cf.cX);
+    const T sT = Vt * T(cf.cT) * L + (MAT != NLE_MAT_M1 ? Vt * T(cf.cM) * FdF : T(0));
+    T sF = MAT != NLE_MAT_M1 ? Vt * T(cf.cF) * L : T(0);
+    if (MAT == NLE_MAT_M4) sF += Vt * T(cf.cFF) * FdF;
     // fibre terms (M4): h1 (dF f) (x) f + h2 ((F f).(dF f)) (F f) (x) f
     T dFf[3] = {T(0), T(0), T(0)}, s2 = T(0);
     if (MAT == NLE_MAT_M4) {
 #pragma unroll
       for (int i = 0; i < 3; ++i) dFf[i] = dF[i][0] * f[0] + dF[i][1] * f[1] + dF[i][2] * f[2];
-      s2 = T(V * cf.h2) * (Ff[0] * dFf[0] + Ff[1] * dFf[1] + Ff[2] * dFf[2]);
-      const T c1 = T(V * cf.h1);
+      s2 = Vt * T(cf.h2) * (Ff[0] * dFf[0] + Ff[1] * dFf[1] + Ff[2] * dFf[2]);
+      const T c1 = Vt * T(cf.h1);
 #pragma unroll
       for (int i = 0; i < 3; ++i) dFf[i] *= c1;
     }
