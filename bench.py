@@ -451,12 +451,15 @@ P2_METHODS = {
     "nk_fp64": ("nk", "fp64", {"ksp": "minres"}),
     "bfgs_ib_mixed_r20": ("bfgs", "mixed", {"h0": "ksp", "qn_m": 10, "ksp": "minres",
                                             "h0_refresh": 20}),
+    "ink_mixed_cg_amg": ("ink", "mixed", {"ksp": "cg", "pc": "amg"}),
+    "nk_fp64_cg_amg": ("nk", "fp64", {"ksp": "cg", "pc": "amg"}),
 }
 
 
 def p2_cook(nl, torch, grid, ratio: float, methods):
     """Cook's membrane with quadratic (10-node) displacement tetrahedra, law
-    M1, dead traction, doubling schedule to tau = 16, Jacobi-preconditioned."""
+    M1, dead traction, doubling schedule to tau = 16; Jacobi-preconditioned
+    unless the method names the multigrid."""
     import synthetic as syn
     from paper_2203_05610_amd import problems
 

@@ -92,9 +92,10 @@ typedef int32_t nle_status;
                              bs = 3 point-block Jacobi of a PETSc setup)  */
 #define NLE_PC_AMG 3 /* aggregation multigrid, one V(1,1)-cycle (the AMG of
                         Sec. 4 and App. A; its construction is this
-                        library's, see nle_pc_apply); P1 meshes, with GMRES,
-                        CG (the cycle is symmetric for a symmetric tangent)
-                        or as the H0 of BFGS-preonly; not with MINRES */
+                        library's, see nle_pc_apply); P1 and displacement-
+                        only quadratic meshes, with GMRES, CG (the cycle is
+                        symmetric for a symmetric tangent) or as the H0 of
+                        BFGS-preonly; not with MINRES */
 
 #define NLE_H0_PREONLY 0 /* BFGS-preonly: H0 = one preconditioner application */
 #define NLE_H0_KSP 1     /* inexact BFGS: H0 = Krylov solve on J(u0)          */
@@ -353,10 +354,12 @@ nle_status nle_block_diag(nle_ctx *ctx, double *b_dev);
  * x and y are device vectors of the unknown length, double for NLE_FP64 and
  * float for NLE_FP32 (which needs a linearization in NLE_FP32); they may
  * not overlap.
- * NLE_PC_AMG (P1 meshes; NLE_E_UNSUPPORTED on a mixed mesh): one V(1,1)-
+ * NLE_PC_AMG (P1 or displacement-only quadratic meshes; NLE_E_UNSUPPORTED
+ * with a pressure field): one V(1,1)-
  * cycle of an aggregation multigrid for J.  Candidates: the six rigid-body
  * modes (translations, rotations e_k x X about the origin), zero on
- * Dirichlet dofs.  Each level's graph (level 0: nodes sharing an element)
+ * Dirichlet dofs.  Each level's graph (level 0: nodes sharing an element,
+ * all ten of a quadratic one)
  * is aggregated in two passes over its vertices in order (a vertex whose
  * neighbours are all free forms an aggregate with them; leftovers join the
  * aggregate of their lowest-numbered neighbour aggregated in the first

@@ -11,7 +11,8 @@ the rigid-body modes as near-nullspace (the standard choice for elasticity
 with block size 3 and known coordinates):
 
 * Level 0 is the tangent K (identity rows and columns on Dirichlet dofs) on
-  the mesh's node graph (nodes adjacent when they share an element), with
+  the mesh's node graph (nodes adjacent when they share an element; all ten
+  nodes of a quadratic element), with
   candidates B_0 (n_dofs x 6): the translations e_x, e_y, e_z and the
   rotations e_k x X (X the reference position), zero on Dirichlet dofs.
 * Aggregation of a graph, in two passes over the vertices in increasing
@@ -61,9 +62,9 @@ DROP_TOL = 1e-8
 
 
 def node_graph(conn: np.ndarray, n_nodes: int) -> list:
-    """Sorted neighbour lists of the P1 mesh's nodes (sharing an element)."""
+    """Sorted neighbour lists of the mesh's nodes (sharing an element)."""
     nb = [set() for _ in range(n_nodes)]
-    for e in np.asarray(conn)[:, :4]:
+    for e in np.asarray(conn):
         for a in e:
             for b in e:
                 if a != b:

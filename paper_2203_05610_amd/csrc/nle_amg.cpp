@@ -199,14 +199,17 @@ nle_status build_structure(Ctx *c, Amg *A) {
     l0.n = 3 * nn;
     l0.vbeg.resize(nn + 1);
     for (int64_t v = 0; v <= nn; ++v) l0.vbeg[v] = 3 * v;
+    // nodes sharing an element (all ten nodes of a quadratic element)
+    const int npe = c->mixed ? 10 : 4;
+    const std::vector<int32_t> &conn = c->mixed ? c->mx.h_conn : M.h_conn;
     std::vector<uint64_t> pairs;
-    pairs.reserve(size_t(M.n_elems) * 12);
+    pairs.reserve(size_t(M.n_elems) * npe * (npe - 1));
     for (int64_t e = 0; e < M.n_elems; ++e)
-      for (int a = 0; a < 4; ++a)
-        for (int b = 0; b < 4; ++b)
+      for (int a = 0; a < npe; ++a)
+        for (int b = 0; b < npe; ++b)
           if (a != b)
-            pairs.push_back((uint64_t(uint32_t(M.h_conn[4 * e + a])) << 32) |
-                            uint32_t(M.h_conn[4 * e + b]));
+            pairs.push_back((uint64_t(uint32_t(conn[npe * e + a])) << 32) |
+                            uint32_t(conn[npe * e + b]));
     std::sort(pairs.begin(), pairs.end());
     pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
     l0.adjp.assign(nn + 1, 0);
@@ -665,7 +668,8 @@ void amg_invalidate(Ctx *c) {
 }
 
 nle_status amg_prepare(Ctx *c) {
-  if (c->mixed) return fail(c, NLE_E_UNSUPPORTED, "multigrid needs a P1 mesh");
+  if (c->mixed && c->mx.n_p > 0)
+    return fail(c, NLE_E_UNSUPPORTED, "multigrid needs a displacement-only mesh");
   if (!c->lin64) return fail(c, NLE_E_STATE, "multigrid needs a linearization");
   Amg *A = state(c);
   if (A && A->valid) return NLE_OK;

@@ -82,6 +82,32 @@ def test_cycle_parity_cardiac():
     _cycle_parity(mesh, P, ctx, u, 0.7, seed=84)
 
 
+def test_cycle_parity_p2_cook():
+    # quadratic displacement tetrahedra: the node graph takes all ten nodes
+    from oracle import p2
+    mesh = syn.cook_p2_mesh(8, 6, 2)
+    P = p2.cook_p2_problem(mesh, mu=MU, lam=5.0 * MU, tau=2.0)
+    ctx = nl.Context(0)
+    problems.setup_cook_p2(ctx, mesh, MU, 5.0 * MU, 2.0)
+    u = P.lift(smooth_state(mesh, P.n_dofs, seed=87, amp=0.03))
+    nl.nle_linearize(ctx, _t(u), nl.NLE_FP32)
+    K = P.stiffness(u)
+    H = amg.setup(K, mesh.X, mesh.conn, P.fixed)
+    assert H.n_levels >= 2
+    b = syn.random_field(P.n_dofs, 1.0, seed=88)
+    y = torch.empty(P.n_dofs, dtype=torch.float64, device="cuda")
+    nl.nle_pc_apply(ctx, nl.NLE_PC_AMG, _t(b), y, nl.NLE_FP64)
+    assert nl.nle_amg_levels(ctx) == [A.shape[0] for A in H.A]
+    assert relmax(y.cpu().numpy(), amg.vcycle(H, b)) < 1e-10
+    # and a solve with CG and the cycle against the oracle root
+    ustar, _ = newton.newton_exact(P, np.zeros(P.n_dofs), 1.0)
+    z = torch.zeros(P.n_dofs, dtype=torch.float64, device="cuda")
+    st, rep = nl.nle_solve_nk(ctx, z, problems.make_opts(
+        "nk", ksp="cg", pc="amg", snes_rtol=1e-11, ksp_atol=1e-15))
+    assert st == nl.NLE_OK, rep
+    assert relnorm(z.cpu().numpy(), ustar) <= 1e-8
+
+
 def test_one_level_hierarchy_is_the_exact_solve():
     mesh, P, ctx = _cook(4, 4, 1)  # 150 unknowns: below the coarsening threshold
     u = P.lift(smooth_state(mesh, P.n_dofs, seed=85, amp=0.03))
@@ -181,9 +207,10 @@ def test_multigrid_usage_errors():
     with pytest.raises(nl.NleError) as e:
         nl.nle_pc_apply(ctx, nl.NLE_PC_AMG, u, u, nl.NLE_FP64)
     assert e.value.status == nl.NLE_E_INVAL
-    m2 = syn.cook_p2_mesh(3, 3, 1)
+    # a displacement-pressure mesh is not supported
+    mt = syn.twist_p2_mesh(2)
     ctx2 = nl.Context(0)
-    problems.setup_cook_p2(ctx2, m2, MU, 5.0 * MU)
+    problems.setup_twist(ctx2, mt, 1.0)
     z2 = torch.zeros(ctx2.n_dofs, dtype=torch.float64, device="cuda")
     with pytest.raises(nl.NleError) as e:
         nl.nle_solve_nk(ctx2, z2, problems.make_opts("nk", ksp="gmres", pc="amg"))
