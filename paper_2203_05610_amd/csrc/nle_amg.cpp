@@ -619,9 +619,14 @@ AmgXfer<void> xfer(const Level &l, const Level &nx, int prec) {
                        l.d_rs, l.d_re, l.d_ri, l.d_arows, l.n, nx.n};
 }
 
-hipError_t cycle(Ctx *c, Amg *A, int prec, size_t li, const void *b, void *x) {
+// One V-cycle at level li for b.  Level 0 leaves the result in x; a coarser
+// level returns in *res where its result is (x, or its residual buffer, which
+// the fused post-smoother writes to).
+hipError_t cycle(Ctx *c, Amg *A, int prec, size_t li, const void *b, void *x,
+                 const void **res) {
   const Level &l = A->L[li];
   const bool f32 = prec == NLE_FP32;
+  *res = x;
   if (li + 1 == A->L.size())
     return amg_dense_mv(c, prec, x, f32 ? static_cast<const void *>(A->d_inv32) : A->d_inv64, b,
                         l.n);
@@ -635,21 +640,25 @@ hipError_t cycle(Ctx *c, Amg *A, int prec, size_t li, const void *b, void *x) {
     elem_apply(c, OP_JV, prec, ulin, x, A->d_t, nullptr, &e);
     if (e != hipSuccess) return e;
     if ((e = amg_restrict(c, prec, nx.d_b, b, A->d_t, X)) != hipSuccess) return e;
-    if ((e = cycle(c, A, prec, 1, nx.d_b, nx.d_x)) != hipSuccess) return e;
-    if ((e = amg_prolong_add(c, prec, x, nx.d_x, X)) != hipSuccess) return e;
+    const void *xc = nullptr;
+    if ((e = cycle(c, A, prec, 1, nx.d_b, nx.d_x, &xc)) != hipSuccess) return e;
+    if ((e = amg_prolong_add(c, prec, x, xc, X)) != hipSuccess) return e;
     elem_apply(c, OP_JV, prec, ulin, x, A->d_t, nullptr, &e);
     if (e != hipSuccess) return e;
     return amg_jac_upd(c, prec, x, b, A->d_t, dinv, l.w, l.n);
   }
   const void *dinv = f32 ? static_cast<const void *>(l.d_dinv32) : l.d_dinv64;
   const void *v = f32 ? static_cast<const void *>(l.d_v32) : l.d_v64;
-  if ((e = amg_jac_first(c, prec, x, b, dinv, l.w, l.n)) != hipSuccess) return e;
-  if ((e = amg_csr_res(c, prec, l.d_r, b, x, l.d_rp, l.d_ci, v, l.n)) != hipSuccess) return e;
+  if ((e = amg_csr_pre(c, prec, x, l.d_r, b, dinv, l.w, l.d_rp, l.d_ci, v, l.n)) != hipSuccess)
+    return e;
   if ((e = amg_restrict(c, prec, nx.d_b, l.d_r, nullptr, X)) != hipSuccess) return e;
-  if ((e = cycle(c, A, prec, li + 1, nx.d_b, nx.d_x)) != hipSuccess) return e;
-  if ((e = amg_prolong_add(c, prec, x, nx.d_x, X)) != hipSuccess) return e;
-  if ((e = amg_csr_res(c, prec, l.d_r, b, x, l.d_rp, l.d_ci, v, l.n)) != hipSuccess) return e;
-  return amg_jac_upd(c, prec, x, l.d_r, nullptr, dinv, l.w, l.n);
+  const void *xc = nullptr;
+  if ((e = cycle(c, A, prec, li + 1, nx.d_b, nx.d_x, &xc)) != hipSuccess) return e;
+  if ((e = amg_prolong_add(c, prec, x, xc, X)) != hipSuccess) return e;
+  // the restriction has consumed the residual buffer: the post-smoothed
+  // iterate goes there
+  *res = l.d_r;
+  return amg_csr_post(c, prec, l.d_r, x, b, dinv, l.w, l.d_rp, l.d_ci, v, l.n);
 }
 
 }  // namespace
@@ -692,7 +701,8 @@ nle_status amg_prepare(Ctx *c) {
 hipError_t amg_apply(Ctx *c, int prec, const void *b, void *x) {
   Amg *A = state(c);
   if (!A || !A->valid) return hipErrorNotReady;
-  return cycle(c, A, prec, 0, b, x);
+  const void *res = nullptr;
+  return cycle(c, A, prec, 0, b, x, &res);  // level 0 works in place: res == x
 }
 
 int amg_levels(const Ctx *c, int64_t *sizes, int cap) {

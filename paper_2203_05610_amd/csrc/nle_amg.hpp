@@ -42,8 +42,13 @@ hipError_t amg_jac_first(Ctx *c, int prec, void *x, const void *b, const void *d
                          int64_t n);
 hipError_t amg_jac_upd(Ctx *c, int prec, void *x, const void *b, const void *t, const void *dinv,
                        double w, int64_t n);
-hipError_t amg_csr_res(Ctx *c, int prec, void *r, const void *b, const void *x, const int32_t *rp,
-                       const int32_t *ci, const void *v, int64_t n);
+// coarse-level smoothing fused with the sparse residual:
+// pre: x = w D^-1 b, r = b - A x;  post: xo = x + w D^-1 (b - A x) (xo != x)
+hipError_t amg_csr_pre(Ctx *c, int prec, void *x, void *r, const void *b, const void *dinv,
+                       double w, const int32_t *rp, const int32_t *ci, const void *v, int64_t n);
+hipError_t amg_csr_post(Ctx *c, int prec, void *xo, const void *x, const void *b,
+                        const void *dinv, double w, const int32_t *rp, const int32_t *ci,
+                        const void *v, int64_t n);
 // bc = P^T (b - t) (t may be null: bc = P^T b)
 hipError_t amg_restrict(Ctx *c, int prec, void *bc, const void *b, const void *t,
                         const AmgXfer<void> &X);

@@ -113,12 +113,41 @@ __device__ __forceinline__ T wave_total(T s) {
   return s;
 }
 
-// One wave per row (rows of the coarse operators hold ~100 entries and there
-// are only a few thousand rows: a thread per row would leave most of the
-// chip idle); lanes stride over the row, then a fixed-order wave sum.
+// Coarse-level kernels run one wave per row (rows of the coarse operators
+// hold ~100 entries and there are only a few thousand rows: a thread per row
+// would leave most of the chip idle); lanes stride over the row, then a
+// fixed-order wave sum.
+
+// Pre-smoothing from zero fused with the residual: x = w D^-1 b and
+// r = b - A x, the x_j formed in place from b_j (the same arithmetic as the
+// separate smoothing step, so the result is identical).
 template <typename T>
-__global__ __launch_bounds__(NT) void k_csr_res(T *r, const T *b, const T *x, const int32_t *rp,
-                                                const int32_t *ci, const T *v, int64_t n) {
+__global__ __launch_bounds__(NT) void k_csr_pre(T *x, T *r, const T *b, const T *dinv, T w,
+                                                const int32_t *rp, const int32_t *ci, const T *v,
+                                                int64_t n) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w0 = (int64_t(blockIdx.x) * NT + threadIdx.x) >> 6;
+  const int64_t nw = (int64_t(gridDim.x) * NT) >> 6;
+  for (int64_t i = w0; i < n; i += nw) {
+    T s = T(0);
+    for (int32_t q = rp[i] + lane; q < rp[i + 1]; q += 64) {
+      const int32_t j = ci[q];
+      s += v[q] * (w * (dinv[j] * b[j]));
+    }
+    s = wave_total(s);
+    if (lane == 0) {
+      x[i] = w * (dinv[i] * b[i]);
+      r[i] = b[i] - s;
+    }
+  }
+}
+
+// Post-smoothing fused with its residual: xo = x + w D^-1 (b - A x) into a
+// separate vector (other rows still read x).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_csr_post(T *xo, const T *x, const T *b, const T *dinv,
+                                                 T w, const int32_t *rp, const int32_t *ci,
+                                                 const T *v, int64_t n) {
   const int lane = threadIdx.x & 63;
   const int64_t w0 = (int64_t(blockIdx.x) * NT + threadIdx.x) >> 6;
   const int64_t nw = (int64_t(gridDim.x) * NT) >> 6;
@@ -126,7 +155,10 @@ __global__ __launch_bounds__(NT) void k_csr_res(T *r, const T *b, const T *x, co
     T s = T(0);
     for (int32_t q = rp[i] + lane; q < rp[i + 1]; q += 64) s += v[q] * x[ci[q]];
     s = wave_total(s);
-    if (lane == 0) r[i] = b[i] - s;
+    if (lane == 0) {
+      const T r = b[i] - s;
+      xo[i] = x[i] + w * (dinv[i] * r);
+    }
   }
 }
 
@@ -232,15 +264,30 @@ hipError_t amg_jac_upd(Ctx *c, int prec, void *x, const void *b, const void *t, 
   return hipGetLastError();
 }
 
-hipError_t amg_csr_res(Ctx *c, int prec, void *r, const void *b, const void *x, const int32_t *rp,
-                       const int32_t *ci, const void *v, int64_t n) {
+hipError_t amg_csr_pre(Ctx *c, int prec, void *x, void *r, const void *b, const void *dinv,
+                       double w, const int32_t *rp, const int32_t *ci, const void *v, int64_t n) {
   if (prec == NLE_FP32)
-    LAUNCH(k_csr_res<float>, grid_waves(n), static_cast<float *>(r), static_cast<const float *>(b),
-           static_cast<const float *>(x), rp, ci, static_cast<const float *>(v), n);
+    LAUNCH(k_csr_pre<float>, grid_waves(n), static_cast<float *>(x), static_cast<float *>(r),
+           static_cast<const float *>(b), static_cast<const float *>(dinv), float(w), rp, ci,
+           static_cast<const float *>(v), n);
   else
-    LAUNCH(k_csr_res<double>, grid_waves(n), static_cast<double *>(r),
-           static_cast<const double *>(b), static_cast<const double *>(x), rp, ci,
+    LAUNCH(k_csr_pre<double>, grid_waves(n), static_cast<double *>(x), static_cast<double *>(r),
+           static_cast<const double *>(b), static_cast<const double *>(dinv), w, rp, ci,
            static_cast<const double *>(v), n);
+  return hipGetLastError();
+}
+
+hipError_t amg_csr_post(Ctx *c, int prec, void *xo, const void *x, const void *b,
+                        const void *dinv, double w, const int32_t *rp, const int32_t *ci,
+                        const void *v, int64_t n) {
+  if (prec == NLE_FP32)
+    LAUNCH(k_csr_post<float>, grid_waves(n), static_cast<float *>(xo),
+           static_cast<const float *>(x), static_cast<const float *>(b),
+           static_cast<const float *>(dinv), float(w), rp, ci, static_cast<const float *>(v), n);
+  else
+    LAUNCH(k_csr_post<double>, grid_waves(n), static_cast<double *>(xo),
+           static_cast<const double *>(x), static_cast<const double *>(b),
+           static_cast<const double *>(dinv), w, rp, ci, static_cast<const double *>(v), n);
   return hipGetLastError();
 }
 
