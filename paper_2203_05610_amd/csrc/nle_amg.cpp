@@ -623,7 +623,7 @@ AmgXfer<void> xfer(const Level &l, const Level &nx, int prec) {
 // level returns in *res where its result is (x, or its residual buffer, which
 // the fused post-smoother writes to).
 hipError_t cycle(Ctx *c, Amg *A, int prec, size_t li, const void *b, void *x,
-                 const void **res) {
+                 const void **res, double *red_dot) {
   const Level &l = A->L[li];
   const bool f32 = prec == NLE_FP32;
   *res = x;
@@ -641,10 +641,14 @@ hipError_t cycle(Ctx *c, Amg *A, int prec, size_t li, const void *b, void *x,
     if (e != hipSuccess) return e;
     if ((e = amg_restrict(c, prec, nx.d_b, b, A->d_t, X)) != hipSuccess) return e;
     const void *xc = nullptr;
-    if ((e = cycle(c, A, prec, 1, nx.d_b, nx.d_x, &xc)) != hipSuccess) return e;
+    if ((e = cycle(c, A, prec, 1, nx.d_b, nx.d_x, &xc, nullptr)) != hipSuccess) return e;
     if ((e = amg_prolong_add(c, prec, x, xc, X)) != hipSuccess) return e;
     elem_apply(c, OP_JV, prec, ulin, x, A->d_t, nullptr, &e);
     if (e != hipSuccess) return e;
+    if (red_dot) {
+      amg_jac_upd_dot(c, prec, x, b, A->d_t, dinv, l.w, l.n, red_dot, &e);
+      return e;
+    }
     return amg_jac_upd(c, prec, x, b, A->d_t, dinv, l.w, l.n);
   }
   const void *dinv = f32 ? static_cast<const void *>(l.d_dinv32) : l.d_dinv64;
@@ -653,7 +657,7 @@ hipError_t cycle(Ctx *c, Amg *A, int prec, size_t li, const void *b, void *x,
     return e;
   if ((e = amg_restrict(c, prec, nx.d_b, l.d_r, nullptr, X)) != hipSuccess) return e;
   const void *xc = nullptr;
-  if ((e = cycle(c, A, prec, li + 1, nx.d_b, nx.d_x, &xc)) != hipSuccess) return e;
+  if ((e = cycle(c, A, prec, li + 1, nx.d_b, nx.d_x, &xc, nullptr)) != hipSuccess) return e;
   if ((e = amg_prolong_add(c, prec, x, xc, X)) != hipSuccess) return e;
   // the restriction has consumed the residual buffer: the post-smoothed
   // iterate goes there
@@ -698,11 +702,17 @@ nle_status amg_prepare(Ctx *c) {
   return NLE_OK;
 }
 
-hipError_t amg_apply(Ctx *c, int prec, const void *b, void *x) {
+hipError_t amg_apply(Ctx *c, int prec, const void *b, void *x, double *red_dot) {
   Amg *A = state(c);
   if (!A || !A->valid) return hipErrorNotReady;
   const void *res = nullptr;
-  return cycle(c, A, prec, 0, b, x, &res);  // level 0 works in place: res == x
+  if (red_dot && A->L.size() == 1) {  // one level: the dense solve, then the dot
+    hipError_t e = cycle(c, A, prec, 0, b, x, &res, nullptr);
+    if (e != hipSuccess) return e;
+    vec_dot_partials(c, prec, b, x, A->L[0].n, red_dot, &e);
+    return e;
+  }
+  return cycle(c, A, prec, 0, b, x, &res, red_dot);  // level 0 works in place: res == x
 }
 
 int amg_levels(const Ctx *c, int64_t *sizes, int cap) {

@@ -42,6 +42,9 @@ hipError_t amg_jac_first(Ctx *c, int prec, void *x, const void *b, const void *d
                          int64_t n);
 hipError_t amg_jac_upd(Ctx *c, int prec, void *x, const void *b, const void *t, const void *dinv,
                        double w, int64_t n);
+// x += w D^-1 (b - t) with the partials of b . x at red[0 .. vgrid(n)); returns the count
+int amg_jac_upd_dot(Ctx *c, int prec, void *x, const void *b, const void *t, const void *dinv,
+                    double w, int64_t n, double *red, hipError_t *err);
 // coarse-level smoothing fused with the sparse residual:
 // pre: x = w D^-1 b, r = b - A x;  post: xo = x + w D^-1 (b - A x) (xo != x)
 hipError_t amg_csr_pre(Ctx *c, int prec, void *x, void *r, const void *b, const void *dinv,

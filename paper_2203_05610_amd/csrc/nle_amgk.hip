@@ -113,6 +113,30 @@ __device__ __forceinline__ T wave_total(T s) {
   return s;
 }
 
+// The last step of a cycle inside CG: x += w D^-1 (b - t) and the
+// per-workgroup partials of b . x (b = r, x = z: the r.z the direction
+// kernel sums, one partial per workgroup of a vgrid(n) launch).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_jac_upd_dot(T *x, const T *b, const T *t, const T *dinv,
+                                                    T w, int64_t n, double *red) {
+  __shared__ double sh[NT / 64];
+  double acc = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT) {
+    const T xi = x[i] + w * (dinv[i] * (b[i] - t[i]));
+    x[i] = xi;
+    acc += double(b[i]) * double(xi);
+  }
+  acc = wave_total(acc);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = sh[0];
+    for (int k = 1; k < NT / 64; ++k) s += sh[k];
+    red[blockIdx.x] = s;
+  }
+}
+
 // Coarse-level kernels run one wave per row (rows of the coarse operators
 // hold ~100 entries and there are only a few thousand rows: a thread per row
 // would leave most of the chip idle); lanes stride over the row, then a
@@ -262,6 +286,19 @@ hipError_t amg_jac_upd(Ctx *c, int prec, void *x, const void *b, const void *t, 
     LAUNCH(k_jac_upd<double>, vgrid(n), static_cast<double *>(x), static_cast<const double *>(b),
            static_cast<const double *>(t), static_cast<const double *>(dinv), w, n);
   return hipGetLastError();
+}
+
+int amg_jac_upd_dot(Ctx *c, int prec, void *x, const void *b, const void *t, const void *dinv,
+                    double w, int64_t n, double *red, hipError_t *err) {
+  const int g = vgrid(n);
+  if (prec == NLE_FP32)
+    LAUNCH(k_jac_upd_dot<float>, g, static_cast<float *>(x), static_cast<const float *>(b),
+           static_cast<const float *>(t), static_cast<const float *>(dinv), float(w), n, red);
+  else
+    LAUNCH(k_jac_upd_dot<double>, g, static_cast<double *>(x), static_cast<const double *>(b),
+           static_cast<const double *>(t), static_cast<const double *>(dinv), w, n, red);
+  *err = hipGetLastError();
+  return g;
 }
 
 hipError_t amg_csr_pre(Ctx *c, int prec, void *x, void *r, const void *b, const void *dinv,

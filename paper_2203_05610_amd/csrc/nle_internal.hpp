@@ -336,11 +336,13 @@ hipError_t reduce_scalars(Ctx *c, const double *red, int np, int count, double *
 hipError_t vec_recip(Ctx *c, const double *d, double *dinv, int64_t n);
 // ---- aggregation multigrid (nle_amg.cpp) ----------------------------------------
 // amg_prepare builds what is missing for the current linearization (NLE_OK or
-// an error set on c); amg_apply is one V-cycle x = M^-1 b in precision prec;
+// an error set on c); amg_apply is one V-cycle x = M^-1 b in precision prec
+// (x must not alias b);
 // amg_invalidate marks the values stale (new linearization); amg_release
 // frees everything (new mesh or Dirichlet set, destroy).
 nle_status amg_prepare(Ctx *c);
-hipError_t amg_apply(Ctx *c, int prec, const void *b, void *x);
+// red_dot (nullable): also write the partials of b . x at red_dot[0 .. vgrid(n))
+hipError_t amg_apply(Ctx *c, int prec, const void *b, void *x, double *red_dot = nullptr);
 void amg_invalidate(Ctx *c);
 void amg_release(Ctx *c);
 int amg_levels(const Ctx *c, int64_t *sizes, int cap);

@@ -215,10 +215,8 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
       if (amg) {
         // the cycle replaces z = p = M^-1 b and the r.z partials
         NLE_HIP(c, cg_start(c, a, b, o.rtol, o.atol, o.max_it, false));
-        NLE_HIP(c, amg_apply(c, prec, a.r, a.z));
+        NLE_HIP(c, amg_apply(c, prec, a.r, a.z, red_b));
         NLE_HIP(c, hipMemcpyAsync(a.p, a.z, vb, hipMemcpyDeviceToDevice, c->stream));
-        vec_dot_partials(c, prec, a.r, a.z, n, red_b, &e);
-        NLE_HIP(c, e);
         NLE_HIP(c, cg_start_finish(c, a, o.rtol, o.atol, o.max_it));
       } else {
         NLE_HIP(c, cg_start(c, a, b, o.rtol, o.atol, o.max_it));
@@ -244,10 +242,8 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
         if (err != hipSuccess) return err;
         err = cg_update(c, a, fuse);
         if (err != hipSuccess || fuse) return err;
-        if (amg) {  // z = M^-1 r by one cycle (the update left z = r), then r.z
-          if ((err = amg_apply(c, prec, a.r, a.z)) != hipSuccess) return err;
-          vec_dot_partials(c, prec, a.r, a.z, n, red_b, &err);
-          if (err != hipSuccess) return err;
+        if (amg) {  // z = M^-1 r by one cycle (the update left z = r), with the r.z partials
+          if ((err = amg_apply(c, prec, a.r, a.z, red_b)) != hipSuccess) return err;
         }
         return cg_direction(c, a);
       };
