@@ -349,6 +349,7 @@ CARDIAC_METHODS = {
     "bfgs_ib_fp64_r20_amg": ("bfgs", "fp64", {"ksp": "gmres", "h0": "ksp", "qn_m": 10,
                                               "h0_refresh": 20, "pc": "amg"}),
     "ink_fp64_cg_amg": ("ink", "fp64", {"ksp": "cg", "pc": "amg"}),
+    "ink_fp64_gmres30_amg": ("ink", "fp64", {"ksp": "gmres", "restart": 30, "pc": "amg"}),
     "bfgs_ib_fp64_r20_cg_amg": ("bfgs", "fp64", {"ksp": "cg", "h0": "ksp", "qn_m": 10,
                                                  "h0_refresh": 20, "pc": "amg"}),
 }
@@ -401,6 +402,13 @@ FOLLOWER_METHODS = {
     "nk_fp64": ("nk", "fp64", {"ksp": "gmres", "orth": "cgs2", "restart": 300}),
     "bfgs_ib_mixed_r20": ("bfgs", "mixed", {"h0": "ksp", "qn_m": 10, "ksp": "gmres",
                                             "orth": "cgs2", "restart": 300, "h0_refresh": 20}),
+    # restarted GMRES with the multigrid cycle
+    "ink_mixed_amg": ("ink", "mixed", {"ksp": "gmres", "orth": "cgs2", "restart": 30,
+                                       "pc": "amg"}),
+    "nk_fp64_amg": ("nk", "fp64", {"ksp": "gmres", "orth": "cgs2", "restart": 30, "pc": "amg"}),
+    "bfgs_ib_mixed_r20_amg": ("bfgs", "mixed", {"h0": "ksp", "qn_m": 10, "ksp": "gmres",
+                                                "orth": "cgs2", "restart": 30, "h0_refresh": 20,
+                                                "pc": "amg"}),
 }
 
 
