@@ -49,7 +49,7 @@ struct Level {
   float *d_v32 = nullptr, *d_dinv32 = nullptr, *d_pv32 = nullptr;
   int32_t *d_poff = nullptr, *d_pk = nullptr, *d_rs = nullptr, *d_re = nullptr, *d_ri = nullptr,
           *d_arows = nullptr;
-  void *d_b = nullptr, *d_x = nullptr, *d_r = nullptr;
+  double *d_b = nullptr, *d_x = nullptr, *d_r = nullptr;  // work vectors (FP32 uses the front)
 };
 
 struct Amg {
@@ -446,9 +446,8 @@ nle_status build_structure(Ctx *c, Amg *A) {
       ok = ok && upload(c, A, &l.d_rp, l.rp) && upload(c, A, &l.d_ci, l.ci);
       ok = ok && alloc(c, A, &l.d_v64, l.ci.size() + 1) && alloc(c, A, &l.d_v32, l.ci.size() + 1);
       ok = ok && alloc(c, A, &l.d_dinv64, size_t(l.n)) && alloc(c, A, &l.d_dinv32, size_t(l.n));
-      ok = ok && alloc(c, A, reinterpret_cast<double **>(&l.d_b), size_t(l.n)) &&
-           alloc(c, A, reinterpret_cast<double **>(&l.d_x), size_t(l.n)) &&
-           alloc(c, A, reinterpret_cast<double **>(&l.d_r), size_t(l.n));
+      ok = ok && alloc(c, A, &l.d_b, size_t(l.n)) && alloc(c, A, &l.d_x, size_t(l.n)) &&
+           alloc(c, A, &l.d_r, size_t(l.n));
     }
     if (li + 1 < A->L.size()) {
       ok = ok && upload(c, A, &l.d_poff, l.poff) && upload(c, A, &l.d_pk, l.pk) &&
