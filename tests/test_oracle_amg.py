@@ -138,3 +138,25 @@ def test_fewer_iterations_than_point_jacobi():
     spla.gmres(K, b, M=Mj, rtol=1e-8, restart=3000, maxiter=1,
                callback=lambda r: cnt.__setitem__(0, cnt[0] + 1), callback_type="pr_norm")
     assert 3 * it < cnt[0], (it, cnt[0])
+
+
+def test_chebyshev_smoother_follows_the_chebyshev_polynomial():
+    # on A = diag(lambda), D = I, the error after k steps from x = 0 is
+    # T_k((theta - lambda) / delta) / T_k(theta / delta) times the exact solution
+    rng = np.random.default_rng(9)
+    rho = 3.7
+    hi = amg.CHEB_SAFETY * rho
+    lo = hi / amg.CHEB_RATIO
+    theta, delta = 0.5 * (hi + lo), 0.5 * (hi - lo)
+    lam = np.r_[rng.uniform(lo, hi, 40), 0.5 * lo, 0.9 * lo]
+    A = sp.diags(lam)
+    xs = rng.standard_normal(lam.size)
+    b = lam * xs
+    for k in (1, 2, 3):
+        x = amg.chebyshev(A, np.ones(lam.size), b, np.zeros(lam.size), rho, degree=k)
+        Tk = np.polynomial.chebyshev.Chebyshev.basis(k)
+        factor = Tk((theta - lam) / delta) / Tk(theta / delta)
+        assert np.allclose(xs - x, factor * xs, rtol=1e-10, atol=1e-12), k
+        # inside the interval the error shrinks by at least 1 / T_k(theta / delta)
+        inside = (lam >= lo) & (lam <= hi)
+        assert np.all(np.abs(factor[inside]) <= 1.0 / abs(Tk(theta / delta)) + 1e-12)
