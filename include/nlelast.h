@@ -367,10 +367,12 @@ nle_status nle_block_diag(nle_ctx *ctx, double *b_dev);
  * Gram-Schmidt in order (a column is dropped below 1e-8 of its norm) into
  * the prolongator P_l, the projections become the next level's candidates,
  * A_{l+1} = P_l^T A_l P_l; coarsening stops at <= 300 unknowns (solved by a
- * dense inverse) or 10 levels.  Smoother: one damped Jacobi step before and
- * after the coarse correction, weight 1/rho with rho a 15-step power
- * estimate of the spectral radius of D^-1 A_l from the fixed start vector
- * x_i = frac(i 2654435761 / 2^32) - 1/2.  The hierarchy's structure is
+ * dense inverse) or 10 levels.  Smoothing before and after the coarse
+ * correction, with rho_l a 15-step power estimate of the spectral radius of
+ * D^-1 A_l from the fixed start vector x_i = frac(i 2654435761 / 2^32) - 1/2:
+ * on the finest level the degree-2 Chebyshev smoother on
+ * [1.2 rho_0 / 30, 1.2 rho_0], on the coarser levels one Jacobi step of
+ * weight 1/rho_l.  The hierarchy's structure is
  * built on first use per mesh and Dirichlet set, its operators once per
  * linearization (synchronising; level 1 by probing with J v), and the
  * cycle runs in precision prec.  NLE_E_UNSUPPORTED if the coarsest level

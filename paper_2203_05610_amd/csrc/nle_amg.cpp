@@ -1,8 +1,9 @@
 // Aggregation multigrid preconditioner (the AMG of Sec. 4 and App. A, whose
 // construction the paper leaves to its library): rigid-body candidates,
 // two-pass greedy aggregation, orthonormal tentative prolongators by
-// modified Gram-Schmidt, Galerkin coarse operators, damped Jacobi smoothing
-// with power-iteration weights, one V(1,1)-cycle per application.
+// modified Gram-Schmidt, Galerkin coarse operators, a degree-2 Chebyshev
+// smoother on the finest level and damped Jacobi below (both scaled by
+// power-iteration estimates), one V(1,1)-cycle per application.
 //
 // What depends on the mesh and the Dirichlet set only (graphs, aggregates,
 // prolongators, operator patterns, probing tasks) is built once, on the host.
@@ -26,6 +27,9 @@ namespace nle {
 namespace {
 
 constexpr int POWER_ITS = 15;
+// finest-level Chebyshev smoother: degree, interval [hi / RATIO, hi], hi = SAFETY rho
+constexpr int CHEB_DEGREE = 2;
+constexpr double CHEB_RATIO = 30.0, CHEB_SAFETY = 1.2;
 constexpr int64_t N_COARSE = 300;
 constexpr int MAX_LEVELS = 10;
 constexpr double DROP_TOL = 1e-8;
@@ -64,6 +68,9 @@ struct Amg {
           *d_nodes = nullptr, *d_dcol = nullptr;
   int64_t *d_tdest = nullptr;
   double *d_z = nullptr, *d_y = nullptr, *d_t = nullptr, *d_red = nullptr, *d_s = nullptr;
+  double *d_cd = nullptr;  // the Chebyshev direction on the finest level
+  // Chebyshev steps j = 1 .. CHEB_DEGREE: d <- cd[j] d + cr[j] D^-1 (b - A x)
+  double cheb_cd[CHEB_DEGREE] = {}, cheb_cr[CHEB_DEGREE] = {};
   std::vector<int32_t> agg0, keep0;  // finest aggregation: node -> aggregate -> level-1 vertex
   bool valid = false;
   std::vector<void *> allocs;
@@ -469,7 +476,7 @@ nle_status build_structure(Ctx *c, Amg *A) {
        upload(c, A, &A->d_dcol, dcol);
   ok = ok && alloc(c, A, &A->d_z, size_t(n0)) && alloc(c, A, &A->d_y, size_t(n0)) &&
        alloc(c, A, &A->d_t, size_t(n0)) && alloc(c, A, &A->d_red, size_t(2 * VGRID_MAX)) &&
-       alloc(c, A, &A->d_s, 8);
+       alloc(c, A, &A->d_s, 8) && alloc(c, A, &A->d_cd, size_t(n0));
   if (ok) ok = hipStreamSynchronize(c->stream) == hipSuccess;
   if (!ok) return fail(c, NLE_E_OOM, "multigrid: device allocation or copy failed");
   return NLE_OK;
@@ -515,6 +522,18 @@ nle_status build_values(Ctx *c, Amg *A) {
       if (!(lam > 0.0) || !std::isfinite(lam))
         return fail(c, NLE_E_STATE, "multigrid: bad spectral radius estimate");
       A->L[0].w = 1.0 / lam;
+      // Chebyshev coefficients on [hi / RATIO, hi]
+      const double hi = CHEB_SAFETY * lam, lo = hi / CHEB_RATIO;
+      const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+      A->cheb_cd[0] = 0.0;
+      A->cheb_cr[0] = 1.0 / theta;
+      double rho_prev = 1.0 / sigma;
+      for (int j = 1; j < CHEB_DEGREE; ++j) {
+        const double rho_j = 1.0 / (2.0 * sigma - rho_prev);
+        A->cheb_cd[j] = rho_j * rho_prev;
+        A->cheb_cr[j] = 2.0 * rho_j / delta;
+        rho_prev = rho_j;
+      }
     }
     // level 1 by probing
     Level &l1 = A->L[1];
@@ -633,22 +652,32 @@ hipError_t cycle(Ctx *c, Amg *A, int prec, size_t li, const void *b, void *x,
   const AmgXfer<void> X = xfer(l, nx, prec);
   hipError_t e;
   if (li == 0) {
+    // finest level: Chebyshev smoothing with the matrix-free Jacobian action
     const void *dinv = f32 ? static_cast<const void *>(c->dinv32) : c->dinv64;
     const void *ulin = f32 ? static_cast<const void *>(c->ulin32) : c->ulin64;
-    if ((e = amg_jac_first(c, prec, x, b, dinv, l.w, l.n)) != hipSuccess) return e;
+    if ((e = amg_cheb_first(c, prec, x, A->d_cd, b, dinv, A->cheb_cr[0], l.n)) != hipSuccess)
+      return e;
+    for (int j = 1; j < CHEB_DEGREE; ++j) {
+      elem_apply(c, OP_JV, prec, ulin, x, A->d_t, nullptr, &e);
+      if (e != hipSuccess) return e;
+      amg_cheb_step(c, prec, x, A->d_cd, b, A->d_t, dinv, A->cheb_cd[j], A->cheb_cr[j], l.n,
+                    nullptr, &e);
+      if (e != hipSuccess) return e;
+    }
     elem_apply(c, OP_JV, prec, ulin, x, A->d_t, nullptr, &e);
     if (e != hipSuccess) return e;
     if ((e = amg_restrict(c, prec, nx.d_b, b, A->d_t, X)) != hipSuccess) return e;
     const void *xc = nullptr;
     if ((e = cycle(c, A, prec, 1, nx.d_b, nx.d_x, &xc, nullptr)) != hipSuccess) return e;
     if ((e = amg_prolong_add(c, prec, x, xc, X)) != hipSuccess) return e;
-    elem_apply(c, OP_JV, prec, ulin, x, A->d_t, nullptr, &e);
-    if (e != hipSuccess) return e;
-    if (red_dot) {
-      amg_jac_upd_dot(c, prec, x, b, A->d_t, dinv, l.w, l.n, red_dot, &e);
-      return e;
+    for (int j = 0; j < CHEB_DEGREE; ++j) {  // the recurrence restarts (cd[0] = 0)
+      elem_apply(c, OP_JV, prec, ulin, x, A->d_t, nullptr, &e);
+      if (e != hipSuccess) return e;
+      amg_cheb_step(c, prec, x, A->d_cd, b, A->d_t, dinv, A->cheb_cd[j], A->cheb_cr[j], l.n,
+                    j + 1 == CHEB_DEGREE ? red_dot : nullptr, &e);
+      if (e != hipSuccess) return e;
     }
-    return amg_jac_upd(c, prec, x, b, A->d_t, dinv, l.w, l.n);
+    return hipSuccess;
   }
   const void *dinv = f32 ? static_cast<const void *>(l.d_dinv32) : l.d_dinv64;
   const void *v = f32 ? static_cast<const void *>(l.d_v32) : l.d_v64;

@@ -38,13 +38,14 @@ int amg_power_partials(Ctx *c, const double *t, const double *dinv, const double
 hipError_t amg_power_scale(Ctx *c, const double *y, const double *s, double *x, int64_t n);
 
 // V-cycle pieces (prec: NLE_FP64 or NLE_FP32, vectors and matrices in it)
-hipError_t amg_jac_first(Ctx *c, int prec, void *x, const void *b, const void *dinv, double w,
-                         int64_t n);
-hipError_t amg_jac_upd(Ctx *c, int prec, void *x, const void *b, const void *t, const void *dinv,
-                       double w, int64_t n);
-// x += w D^-1 (b - t) with the partials of b . x at red[0 .. vgrid(n)); returns the count
-int amg_jac_upd_dot(Ctx *c, int prec, void *x, const void *b, const void *t, const void *dinv,
-                    double w, int64_t n, double *red, hipError_t *err);
+// Chebyshev smoother steps on the finest level: first from x = 0 (x = d =
+// D^-1 b / theta), then d <- cd d + cr D^-1 (b - t), x += d, with the
+// per-workgroup partials of b . x at red[0 .. vgrid(n)) (if not null; returns the count)
+hipError_t amg_cheb_first(Ctx *c, int prec, void *x, void *d, const void *b, const void *dinv,
+                          double inv_theta, int64_t n);
+int amg_cheb_step(Ctx *c, int prec, void *x, void *d, const void *b, const void *t,
+                  const void *dinv, double cd, double cr, int64_t n, double *red,
+                  hipError_t *err);
 // coarse-level smoothing fused with the sparse residual:
 // pre: x = w D^-1 b, r = b - A x;  post: xo = x + w D^-1 (b - A x) (xo != x)
 hipError_t amg_csr_pre(Ctx *c, int prec, void *x, void *r, const void *b, const void *dinv,

@@ -88,23 +88,6 @@ __global__ __launch_bounds__(NT) void k_power_scale(const double *y, const doubl
     x[i] = y[i] * f;
 }
 
-template <typename T>
-__global__ __launch_bounds__(NT) void k_jac_first(T *x, const T *b, const T *dinv, T w,
-                                                  int64_t n) {
-  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT)
-    x[i] = w * (dinv[i] * b[i]);
-}
-
-// x += w dinv (b - t); t null: x += w dinv b (t holds the residual already)
-template <typename T>
-__global__ __launch_bounds__(NT) void k_jac_upd(T *x, const T *b, const T *t, const T *dinv, T w,
-                                                int64_t n) {
-  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT) {
-    const T r = t ? b[i] - t[i] : b[i];
-    x[i] += w * (dinv[i] * r);
-  }
-}
-
 // Sum over a wave64 in a fixed butterfly order (the same on every run).
 template <typename T>
 __device__ __forceinline__ T wave_total(T s) {
@@ -113,19 +96,35 @@ __device__ __forceinline__ T wave_total(T s) {
   return s;
 }
 
-// The last step of a cycle inside CG: x += w D^-1 (b - t) and the
-// per-workgroup partials of b . x (b = r, x = z: the r.z the direction
-// kernel sums, one partial per workgroup of a vgrid(n) launch).
+// Chebyshev smoother on the finest level.  First step from x = 0:
+// d = D^-1 b / theta, x = d.  Any other step, with t = A x:
+// d <- cd d + cr D^-1 (b - t), x += d (cd = 0 restarts the recurrence);
+// with red set also the per-workgroup partials of b . x (the r.z of CG).
 template <typename T>
-__global__ __launch_bounds__(NT) void k_jac_upd_dot(T *x, const T *b, const T *t, const T *dinv,
-                                                    T w, int64_t n, double *red) {
+__global__ __launch_bounds__(NT) void k_cheb_first(T *x, T *d, const T *b, const T *dinv,
+                                                   T inv_theta, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT) {
+    const T di = inv_theta * (dinv[i] * b[i]);
+    d[i] = di;
+    x[i] = di;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_cheb_step(T *x, T *d, const T *b, const T *t,
+                                                  const T *dinv, T cd, T cr, int64_t n,
+                                                  double *red) {
   __shared__ double sh[NT / 64];
   double acc = 0.0;
   for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < n; i += int64_t(gridDim.x) * NT) {
-    const T xi = x[i] + w * (dinv[i] * (b[i] - t[i]));
+    const T r = dinv[i] * (b[i] - t[i]);
+    const T di = cd == T(0) ? cr * r : cd * d[i] + cr * r;
+    d[i] = di;
+    const T xi = x[i] + di;
     x[i] = xi;
     acc += double(b[i]) * double(xi);
   }
+  if (!red) return;
   acc = wave_total(acc);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane == 0) sh[wid] = acc;
@@ -266,37 +265,29 @@ hipError_t amg_power_scale(Ctx *c, const double *y, const double *s, double *x, 
   return hipGetLastError();
 }
 
-hipError_t amg_jac_first(Ctx *c, int prec, void *x, const void *b, const void *dinv, double w,
-                         int64_t n) {
+hipError_t amg_cheb_first(Ctx *c, int prec, void *x, void *d, const void *b, const void *dinv,
+                          double inv_theta, int64_t n) {
   if (prec == NLE_FP32)
-    LAUNCH(k_jac_first<float>, vgrid(n), static_cast<float *>(x), static_cast<const float *>(b),
-           static_cast<const float *>(dinv), float(w), n);
+    LAUNCH(k_cheb_first<float>, vgrid(n), static_cast<float *>(x), static_cast<float *>(d),
+           static_cast<const float *>(b), static_cast<const float *>(dinv), float(inv_theta), n);
   else
-    LAUNCH(k_jac_first<double>, vgrid(n), static_cast<double *>(x),
-           static_cast<const double *>(b), static_cast<const double *>(dinv), w, n);
+    LAUNCH(k_cheb_first<double>, vgrid(n), static_cast<double *>(x), static_cast<double *>(d),
+           static_cast<const double *>(b), static_cast<const double *>(dinv), inv_theta, n);
   return hipGetLastError();
 }
 
-hipError_t amg_jac_upd(Ctx *c, int prec, void *x, const void *b, const void *t, const void *dinv,
-                       double w, int64_t n) {
-  if (prec == NLE_FP32)
-    LAUNCH(k_jac_upd<float>, vgrid(n), static_cast<float *>(x), static_cast<const float *>(b),
-           static_cast<const float *>(t), static_cast<const float *>(dinv), float(w), n);
-  else
-    LAUNCH(k_jac_upd<double>, vgrid(n), static_cast<double *>(x), static_cast<const double *>(b),
-           static_cast<const double *>(t), static_cast<const double *>(dinv), w, n);
-  return hipGetLastError();
-}
-
-int amg_jac_upd_dot(Ctx *c, int prec, void *x, const void *b, const void *t, const void *dinv,
-                    double w, int64_t n, double *red, hipError_t *err) {
+int amg_cheb_step(Ctx *c, int prec, void *x, void *d, const void *b, const void *t,
+                  const void *dinv, double cd, double cr, int64_t n, double *red,
+                  hipError_t *err) {
   const int g = vgrid(n);
   if (prec == NLE_FP32)
-    LAUNCH(k_jac_upd_dot<float>, g, static_cast<float *>(x), static_cast<const float *>(b),
-           static_cast<const float *>(t), static_cast<const float *>(dinv), float(w), n, red);
+    LAUNCH(k_cheb_step<float>, g, static_cast<float *>(x), static_cast<float *>(d),
+           static_cast<const float *>(b), static_cast<const float *>(t),
+           static_cast<const float *>(dinv), float(cd), float(cr), n, red);
   else
-    LAUNCH(k_jac_upd_dot<double>, g, static_cast<double *>(x), static_cast<const double *>(b),
-           static_cast<const double *>(t), static_cast<const double *>(dinv), w, n, red);
+    LAUNCH(k_cheb_step<double>, g, static_cast<double *>(x), static_cast<double *>(d),
+           static_cast<const double *>(b), static_cast<const double *>(t),
+           static_cast<const double *>(dinv), cd, cr, n, red);
   *err = hipGetLastError();
   return g;
 }
