@@ -7,7 +7,7 @@ chosen method (mesh upload, partition and material setup are done once,
 outside the timed region; every load step's linearizations are inside).
 Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--method ink_mixed]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--method ink_mixed_cg_amg]
 """
 
 from __future__ import annotations
