@@ -291,6 +291,10 @@ TWIST_METHODS = {
     "ink_fp64": ("ink", "fp64", {"ksp": "minres"}),
     "nk_mixed": ("nk", "mixed", {"ksp": "minres"}),
     "ink_mixed": ("ink", "mixed", {"ksp": "minres"}),
+    # GMRES with the field split: the multigrid cycle on the displacement block
+    "nk_fp64_amg": ("nk", "fp64", {"ksp": "gmres", "pc": "amg"}),
+    "ink_fp64_amg": ("ink", "fp64", {"ksp": "gmres", "pc": "amg"}),
+    "ink_mixed_amg": ("ink", "mixed", {"ksp": "gmres", "pc": "amg"}),
 }
 
 

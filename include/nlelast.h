@@ -92,10 +92,10 @@ typedef int32_t nle_status;
                              bs = 3 point-block Jacobi of a PETSc setup)  */
 #define NLE_PC_AMG 3 /* aggregation multigrid, one V(1,1)-cycle (the AMG of
                         Sec. 4 and App. A; its construction is this
-                        library's, see nle_pc_apply); P1 and displacement-
-                        only quadratic meshes, with GMRES, CG (the cycle is
-                        symmetric for a symmetric tangent) or as the H0 of
-                        BFGS-preonly; not with MINRES */
+                        library's, see nle_pc_apply), with GMRES, CG (the
+                        cycle is symmetric for a symmetric tangent) or as the
+                        H0 of BFGS-preonly; not with MINRES.  With a pressure
+                        field: the block-diagonal field split, GMRES only */
 
 #define NLE_H0_PREONLY 0 /* BFGS-preonly: H0 = one preconditioner application */
 #define NLE_H0_KSP 1     /* inexact BFGS: H0 = Krylov solve on J(u0)          */
@@ -354,8 +354,7 @@ nle_status nle_block_diag(nle_ctx *ctx, double *b_dev);
  * x and y are device vectors of the unknown length, double for NLE_FP64 and
  * float for NLE_FP32 (which needs a linearization in NLE_FP32); they may
  * not overlap.
- * NLE_PC_AMG (P1 or displacement-only quadratic meshes; NLE_E_UNSUPPORTED
- * with a pressure field): one V(1,1)-
+ * NLE_PC_AMG: one V(1,1)-
  * cycle of an aggregation multigrid for J.  Candidates: the six rigid-body
  * modes (translations, rotations e_k x X about the origin), zero on
  * Dirichlet dofs.  Each level's graph (level 0: nodes sharing an element,
@@ -377,7 +376,11 @@ nle_status nle_block_diag(nle_ctx *ctx, double *b_dev);
  * linearization (synchronising; level 1 by probing with J v), and the
  * cycle runs in precision prec.  NLE_E_UNSUPPORTED if the coarsest level
  * stays above 4000 unknowns, NLE_E_STATE for a zero coarse diagonal or a
- * singular coarsest level. */
+ * singular coarsest level.  With a pressure field (mixed meshes) the
+ * hierarchy is built for the displacement block (the Jacobian action with
+ * zero pressures) and y = (cycle on the displacements, x_p / d_p on the
+ * pressures), d_p the pressure entries of nle_diag: the block-diagonal
+ * field split. */
 nle_status nle_pc_apply(nle_ctx *ctx, int32_t pc, int32_t prec, const void *x_dev, void *y_dev);
 /* Potential Pi(u) = sum_e V_e Psi(F_e) - s f_ext . u + u.R u / 2 with R
  * the spring matrix (synchronises).  NLE_E_UNSUPPORTED with a follower

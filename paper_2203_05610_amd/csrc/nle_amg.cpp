@@ -14,6 +14,11 @@
 // (aggregate, aggregate) pair by a GPU kernel; the small coarser operators
 // (a few percent of the fine size) on the host; the coarsest level inverted
 // densely.  The cycle itself runs on the GPU, in the Krylov loop's precision.
+//
+// With a pressure field (the mixed displacement-pressure meshes) the
+// hierarchy is built for the displacement block and the preconditioner is
+// the block-diagonal field split: the cycle on the displacements, the
+// pressure block's diagonal on the pressures.
 
 #include <algorithm>
 #include <cmath>
@@ -474,9 +479,13 @@ nle_status build_structure(Ctx *c, Amg *A) {
        upload(c, A, &A->d_tkp, tkp) && upload(c, A, &A->d_tka, tka) &&
        upload(c, A, &A->d_tdest, tdest) && upload(c, A, &A->d_nodes, nodes) &&
        upload(c, A, &A->d_dcol, dcol);
-  ok = ok && alloc(c, A, &A->d_z, size_t(n0)) && alloc(c, A, &A->d_y, size_t(n0)) &&
-       alloc(c, A, &A->d_t, size_t(n0)) && alloc(c, A, &A->d_red, size_t(2 * VGRID_MAX)) &&
+  // vectors the Jacobian action reads or writes span all unknowns (a pressure
+  // field's entries stay zero in the inputs)
+  const int64_t nfull = ndof(c);
+  ok = ok && alloc(c, A, &A->d_z, size_t(nfull)) && alloc(c, A, &A->d_y, size_t(nfull)) &&
+       alloc(c, A, &A->d_t, size_t(nfull)) && alloc(c, A, &A->d_red, size_t(2 * VGRID_MAX)) &&
        alloc(c, A, &A->d_s, 8) && alloc(c, A, &A->d_cd, size_t(n0));
+  ok = ok && hipMemsetAsync(A->d_z, 0, size_t(nfull) * 8, c->stream) == hipSuccess;
   if (ok) ok = hipStreamSynchronize(c->stream) == hipSuccess;
   if (!ok) return fail(c, NLE_E_OOM, "multigrid: device allocation or copy failed");
   return NLE_OK;
@@ -490,7 +499,7 @@ nle_status build_values(Ctx *c, Amg *A) {
     // one level: the tangent itself, column by column
     std::vector<double> K(size_t(n0 * n0)), col(n0);
     for (int64_t j = 0; j < n0; ++j) {
-      NLE_HIP(c, hipMemsetAsync(A->d_z, 0, size_t(n0) * 8, c->stream));
+      NLE_HIP(c, hipMemsetAsync(A->d_z, 0, size_t(ndof(c)) * 8, c->stream));
       const double one = 1.0;
       NLE_HIP(c, hipMemcpyAsync(A->d_z + j, &one, 8, hipMemcpyHostToDevice, c->stream));
       elem_apply(c, OP_JV, NLE_FP64, c->ulin64, A->d_z, A->d_y, nullptr, &e);
@@ -709,8 +718,6 @@ void amg_invalidate(Ctx *c) {
 }
 
 nle_status amg_prepare(Ctx *c) {
-  if (c->mixed && c->mx.n_p > 0)
-    return fail(c, NLE_E_UNSUPPORTED, "multigrid needs a displacement-only mesh");
   if (!c->lin64) return fail(c, NLE_E_STATE, "multigrid needs a linearization");
   Amg *A = state(c);
   if (A && A->valid) return NLE_OK;
@@ -734,6 +741,21 @@ hipError_t amg_apply(Ctx *c, int prec, const void *b, void *x, double *red_dot) 
   Amg *A = state(c);
   if (!A || !A->valid) return hipErrorNotReady;
   const void *res = nullptr;
+  if (c->mixed && c->mx.n_p > 0) {
+    // field split: the cycle on the displacements (whose Jacobian actions
+    // see zero pressures), the pressure block's diagonal on the pressures
+    if (red_dot) return hipErrorInvalidValue;
+    const int64_t n0 = A->L[0].n, np = c->mx.n_p;
+    const size_t es = prec == NLE_FP32 ? 4 : 8;
+    void *xp = static_cast<char *>(x) + size_t(n0) * es;
+    const void *bp = static_cast<const char *>(b) + size_t(n0) * es;
+    const void *dp = prec == NLE_FP32 ? static_cast<const void *>(c->dinv32 + n0)
+                                      : static_cast<const void *>(c->dinv64 + n0);
+    hipError_t e = vec_fill(c, prec, xp, 0.0, np);
+    if (e != hipSuccess) return e;
+    if ((e = cycle(c, A, prec, 0, b, x, &res, nullptr)) != hipSuccess) return e;
+    return pc_apply(c, prec, 1, dp, bp, xp, np);
+  }
   if (red_dot && A->L.size() == 1) {  // one level: the dense solve, then the dot
     hipError_t e = cycle(c, A, prec, 0, b, x, &res, nullptr);
     if (e != hipSuccess) return e;

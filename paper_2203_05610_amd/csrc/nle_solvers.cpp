@@ -154,6 +154,8 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
   if (amg) {
     if (o.type == NLE_KSP_MINRES)
       return fail(c, NLE_E_UNSUPPORTED, "the multigrid preconditioner runs with CG or GMRES");
+    if (c->mixed && c->mx.n_p > 0 && o.type != NLE_KSP_GMRES)
+      return fail(c, NLE_E_UNSUPPORTED, "with a pressure field the multigrid runs with GMRES");
     const nle_status sa = amg_prepare(c);
     if (sa != NLE_OK) return sa;
   }
@@ -488,9 +490,8 @@ nle_status check_ready(Ctx *c, double *u, const nle_solver_opts *o) {
     return fail(c, NLE_E_INVAL, "bad pc");
   if (o->pc == NLE_PC_BJACOBI3 && c->mixed)
     return fail(c, NLE_E_UNSUPPORTED, "nodal block Jacobi needs a P1 mesh");
-  if (o->pc == NLE_PC_AMG && c->mixed && c->mx.n_p > 0)
-    return fail(c, NLE_E_UNSUPPORTED,
-                "the multigrid preconditioner needs a displacement-only mesh");
+  if (o->pc == NLE_PC_AMG && c->mixed && c->mx.n_p > 0 && o->ksp_type != NLE_KSP_GMRES)
+    return fail(c, NLE_E_UNSUPPORTED, "with a pressure field the multigrid runs with GMRES");
   if (o->pc == NLE_PC_AMG && o->ksp_type == NLE_KSP_MINRES)
     return fail(c, NLE_E_UNSUPPORTED, "the multigrid preconditioner runs with CG or GMRES");
   if (o->ksp_max_it < 1 || o->snes_max_it < 0) return fail(c, NLE_E_INVAL, "bad iteration limits");

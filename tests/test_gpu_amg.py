@@ -108,6 +108,57 @@ def test_cycle_parity_p2_cook():
     assert relnorm(z.cpu().numpy(), ustar) <= 1e-8
 
 
+def test_field_split_cycle_parity_twist():
+    # displacement-pressure mesh: the cycle on the displacement block of the
+    # tangent, the pressure entries scaled by the inverse lumped mass over mu
+    from oracle import mixed
+    mesh = syn.twist_p2_mesh(3)
+    P = mixed.twist_problem(mesh, 1.0, 0.1)
+    ctx = nl.Context(0)
+    problems.setup_twist(ctx, mesh, 1.0)
+    dofs, vals = syn.twist_dirichlet(mesh.X, mesh.sets["bottom"], mesh.sets["top"], 0.1)
+    nl.nle_set_dirichlet(ctx, dofs, vals)
+    rng = np.random.default_rng(89)
+    x = P.lift(0.01 * rng.standard_normal(P.n_dofs))
+    nl.nle_linearize(ctx, _t(x), nl.NLE_FP32)
+    nu = 3 * P.n_u
+    K = P.stiffness(x).tocsr()
+    H = amg.setup(K[:nu, :nu], mesh.X, mesh.conn, P.fixed[:nu])
+    assert H.n_levels >= 2
+    v = syn.random_field(P.n_dofs, 1.0, seed=90)
+    y = torch.empty(P.n_dofs, dtype=torch.float64, device="cuda")
+    nl.nle_pc_apply(ctx, nl.NLE_PC_AMG, _t(v), y, nl.NLE_FP64)
+    assert nl.nle_amg_levels(ctx) == [A.shape[0] for A in H.A]
+    ref = np.concatenate([amg.vcycle(H, v[:nu]), v[nu:] / (P.pressure_mass_lumped() / 1.0)])
+    assert relmax(y.cpu().numpy()[:nu], ref[:nu]) < 1e-10
+    assert relmax(y.cpu().numpy()[nu:], ref[nu:]) < 1e-12
+
+
+def test_twist_schedule_with_field_split():
+    import math
+    from oracle import mixed
+    mesh = syn.twist_p2_mesh(2)
+    angles = [math.radians(10 * s) for s in range(1, 4)]
+    P = mixed.twist_problem(mesh, 1.0, 0.0)
+    xs = np.zeros(P.n_dofs)
+    for th in angles:
+        mixed.set_twist_angle(P, mesh, th)
+        xs, _ = newton.newton_exact(P, xs, 1.0)
+    ctx = nl.Context(0)
+    problems.setup_twist(ctx, mesh, 1.0)
+    opts = problems.make_opts("nk", "fp64", ksp="gmres", pc="amg", restart=1000,
+                              snes_rtol=1e-10, ksp_atol=1e-14)
+    x = torch.zeros(P.n_dofs, dtype=torch.float64, device="cuda")
+    reps = problems.solve_twist(
+        ctx, x, "nk", opts, angles,
+        lambda th: syn.twist_dirichlet(mesh.X, mesh.sets["bottom"], mesh.sets["top"], th))
+    assert problems.twist_ok(reps, angles), [(r["theta"], r["status_name"]) for r in reps]
+    xh = x.cpu().numpy()
+    nu = 3 * P.n_u
+    assert relnorm(xh[:nu], xs[:nu]) <= 1e-8
+    assert relnorm(xh[nu:], xs[nu:]) <= 1e-8
+
+
 def test_one_level_hierarchy_is_the_exact_solve():
     mesh, P, ctx = _cook(4, 4, 1)  # 150 unknowns: below the coarsening threshold
     u = P.lift(smooth_state(mesh, P.n_dofs, seed=85, amp=0.03))
@@ -207,13 +258,13 @@ def test_multigrid_usage_errors():
     with pytest.raises(nl.NleError) as e:
         nl.nle_pc_apply(ctx, nl.NLE_PC_AMG, u, u, nl.NLE_FP64)
     assert e.value.status == nl.NLE_E_INVAL
-    # a displacement-pressure mesh is not supported
+    # with a pressure field the field split runs with GMRES only
     mt = syn.twist_p2_mesh(2)
     ctx2 = nl.Context(0)
     problems.setup_twist(ctx2, mt, 1.0)
     z2 = torch.zeros(ctx2.n_dofs, dtype=torch.float64, device="cuda")
     with pytest.raises(nl.NleError) as e:
-        nl.nle_solve_nk(ctx2, z2, problems.make_opts("nk", ksp="gmres", pc="amg"))
+        nl.nle_solve_nk(ctx2, z2, problems.make_opts("nk", ksp="cg", pc="amg"))
     assert e.value.status == nl.NLE_E_UNSUPPORTED
     # a new Dirichlet set rebuilds the hierarchy
     y = torch.empty_like(u)
