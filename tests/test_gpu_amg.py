@@ -1,8 +1,9 @@
 """GPU parity of the aggregation multigrid preconditioner (NLE_PC_AMG; the
 AMG of Sec. 4 and App. A with the construction fixed in oracle/amg.py)
 against the FP64 oracle: the hierarchy's level sizes, one V-cycle applied to
-seeded vectors on Cook (symmetric tangent) and on the cardiac shell
-(follower pressure, springs: nonsymmetric), GMRES iteration counts of an NK
+seeded vectors on Cook (symmetric tangent), the follower-traction Cook and the
+cardiac shell (nonsymmetric), the shell with an implicit step's inertia and
+dashpots, the quadratic Cook mesh and the twist's field split, GMRES iteration counts of an NK
 solve against the oracle's loop with the same cycle, and solves (NK, iNK
 mixed, BFGS-preonly with the cycle as H0, a heartbeat step) against the
 oracle's roots.
@@ -157,6 +158,40 @@ def test_twist_schedule_with_field_split():
     nu = 3 * P.n_u
     assert relnorm(xh[:nu], xs[:nu]) <= 1e-8
     assert relnorm(xh[nu:], xs[nu:]) <= 1e-8
+
+
+def test_cycle_parity_follower_cook():
+    # the follower traction makes the tangent nonsymmetric
+    mesh = syn.cook_mesh(16, 12, 2)
+    P = fem.cook_problem(mesh, mu=MU, lam=5.0 * MU, tau=4.0, follower=True)
+    ctx = nl.Context(0)
+    problems.setup_cook(ctx, mesh, MU, 5.0 * MU, 4.0, block_size=256, follower=True)
+    u = P.lift(smooth_state(mesh, P.n_dofs, seed=91, amp=0.03))
+    H = _cycle_parity(mesh, P, ctx, u, 0.9, seed=92)
+    assert H.n_levels >= 2
+
+
+def test_cycle_parity_with_inertia_and_dashpots():
+    # an implicit heartbeat step: lumped-mass inertia and epicardial dashpots
+    # enter the tangent the hierarchy is built from
+    mesh = syn.shell_mesh(2, 8, 16)
+    P = fem.cardiac_problem(mesh, C, gamma=0.03)
+    ctx = nl.Context(0)
+    problems.setup_cardiac(ctx, mesh, C, syn.shell_dirichlet(mesh), block_size=128)
+    nl.nle_set_active_tension(ctx, 0.03)
+    rho, dt, beta, gamma = 1e-7, C["dt"], 0.25, 0.5
+    c, cv = 1.0 / (beta * dt * dt), gamma / (beta * dt)
+    ut = P.lift(smooth_state(mesh, P.n_dofs, seed=93, amp=0.02))
+    vt = syn.random_field(P.n_dofs, 0.05, seed=94)
+    vt[P.fixed] = 0.0
+    P.set_inertia(rho, c, ut)
+    P.set_robin_damping(2e-5, 2e-6)
+    P.set_step_velocity(cv, vt)
+    nl.nle_set_inertia(ctx, rho, c, _t(ut))
+    nl.nle_set_robin_damping(ctx, 2e-5, 2e-6)
+    nl.nle_set_step_velocity(ctx, cv, _t(vt))
+    u = P.lift(smooth_state(mesh, P.n_dofs, seed=95, amp=0.02))
+    _cycle_parity(mesh, P, ctx, u, 0.5, seed=96)
 
 
 def test_one_level_hierarchy_is_the_exact_solve():
