@@ -120,7 +120,8 @@ typedef struct {
   int32_t precision;  /* NLE_PREC_FP64 / NLE_PREC_MIXED                      */
   int32_t ksp_type;   /* NLE_KSP_GMRES / NLE_KSP_CG / NLE_KSP_MINRES          */
   int32_t orth;       /* GMRES orthogonalisation                              */
-  int32_t pc;         /* NLE_PC_JACOBI / NLE_PC_BJACOBI3 / NLE_PC_NONE        */
+  int32_t pc;         /* NLE_PC_JACOBI / NLE_PC_BJACOBI3 / NLE_PC_AMG /
+                         NLE_PC_NONE (batched solves: Jacobi only)          */
   int32_t restart;    /* GMRES restart length; <= 0 means ksp_max_it          */
   int32_t ksp_max_it; /* Krylov iteration limit per linear solve              */
   int32_t snes_max_it;/* nonlinear iteration limit                            */
