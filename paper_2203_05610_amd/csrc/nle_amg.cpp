@@ -664,39 +664,28 @@ hipError_t cycle(Ctx *c, Amg *A, int prec, size_t li, const void *b, void *x,
     // finest level: Chebyshev smoothing with the matrix-free Jacobian action
     const void *dinv = f32 ? static_cast<const void *>(c->dinv32) : c->dinv64;
     const void *ulin = f32 ? static_cast<const void *>(c->ulin32) : c->ulin64;
-    // one Chebyshev step after a Jacobian action of x: on P1 meshes fused into
-    // the action's finalize (the same arithmetic, one launch fewer), else a
-    // separate kernel (which also forms the b . x partials when asked)
-    auto step = [&](int j, double *red) -> hipError_t {
-      hipError_t err = hipSuccess;
-      if (!c->mixed && !red) {
-        c->cheb.b = b;
-        c->cheb.dinv = dinv;
-        c->cheb.d = A->d_cd;
-        c->cheb.cd = A->cheb_cd[j];
-        c->cheb.cr = A->cheb_cr[j];
-        elem_apply(c, OP_JV, prec, ulin, x, x, nullptr, &err);
-        c->cheb.b = nullptr;
-        return err;
-      }
-      elem_apply(c, OP_JV, prec, ulin, x, A->d_t, nullptr, &err);
-      if (err != hipSuccess) return err;
-      amg_cheb_step(c, prec, x, A->d_cd, b, A->d_t, dinv, A->cheb_cd[j], A->cheb_cr[j], l.n, red,
-                    &err);
-      return err;
-    };
     if ((e = amg_cheb_first(c, prec, x, A->d_cd, b, dinv, A->cheb_cr[0], l.n)) != hipSuccess)
       return e;
-    for (int j = 1; j < CHEB_DEGREE; ++j)
-      if ((e = step(j, nullptr)) != hipSuccess) return e;
+    for (int j = 1; j < CHEB_DEGREE; ++j) {
+      elem_apply(c, OP_JV, prec, ulin, x, A->d_t, nullptr, &e);
+      if (e != hipSuccess) return e;
+      amg_cheb_step(c, prec, x, A->d_cd, b, A->d_t, dinv, A->cheb_cd[j], A->cheb_cr[j], l.n,
+                    nullptr, &e);
+      if (e != hipSuccess) return e;
+    }
     elem_apply(c, OP_JV, prec, ulin, x, A->d_t, nullptr, &e);
     if (e != hipSuccess) return e;
     if ((e = amg_restrict(c, prec, nx.d_b, b, A->d_t, X)) != hipSuccess) return e;
     const void *xc = nullptr;
     if ((e = cycle(c, A, prec, 1, nx.d_b, nx.d_x, &xc, nullptr)) != hipSuccess) return e;
     if ((e = amg_prolong_add(c, prec, x, xc, X)) != hipSuccess) return e;
-    for (int j = 0; j < CHEB_DEGREE; ++j)  // the recurrence restarts (cd[0] = 0)
-      if ((e = step(j, j + 1 == CHEB_DEGREE ? red_dot : nullptr)) != hipSuccess) return e;
+    for (int j = 0; j < CHEB_DEGREE; ++j) {  // the recurrence restarts (cd[0] = 0)
+      elem_apply(c, OP_JV, prec, ulin, x, A->d_t, nullptr, &e);
+      if (e != hipSuccess) return e;
+      amg_cheb_step(c, prec, x, A->d_cd, b, A->d_t, dinv, A->cheb_cd[j], A->cheb_cr[j], l.n,
+                    j + 1 == CHEB_DEGREE ? red_dot : nullptr, &e);
+      if (e != hipSuccess) return e;
+    }
     return hipSuccess;
   }
   const void *dinv = f32 ? static_cast<const void *>(l.d_dinv32) : l.d_dinv64;

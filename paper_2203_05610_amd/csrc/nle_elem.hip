@@ -20,14 +20,6 @@ namespace nle {
 
 namespace {
 
-// A Chebyshev smoothing step fused into the Jacobian action (b null: off).
-template <typename T>
-struct ChebEp {
-  const T *b = nullptr, *dinv = nullptr;
-  T *d = nullptr;
-  T cd = T(0), cr = T(0);
-};
-
 template <typename T>
 struct ElemArgs {
   const T *xr;        // [n_slots][3] slot coordinates relative to the block's first slot
@@ -72,7 +64,6 @@ struct ElemArgs {
   int32_t n_list;
   const T *icm;             // inertia: c * m per dof (null: none), and u_tilde
   const double *iut;
-  ChebEp<T> ch;             // Jv only: a Chebyshev smoothing step on the result
   // CG direction formed here (Jv only, see Ctx::cg): v = vz + beta * v
   const T *vz;
   const double *cg_red;
@@ -83,7 +74,6 @@ struct ElemArgs {
 
 template <typename T>
 struct MergeArgs {
-  ChebEp<T> ch;
   const uint32_t *fx_node;
   const int32_t *fx_ptr;
   int64_t n_sh;
@@ -291,9 +281,6 @@ __device__ __forceinline__ double energy_density(const Kin<T> &k, const T H[3][3
 
 // Final value of one node (all three components) from its summed element
 // contributions.  mk = Dirichlet bits of the node.
-// ch (Jv, when ch.b is set): instead of y = J v the node gets one Chebyshev
-// smoothing step with t = y: d <- cd d + cr D^-1 (b - y), out = v + d (out is
-// v itself: each node is written once, after every read of it).
 // fs (nullable) holds the surface-load contributions of the same operation;
 // icm (nullable) the inertia coefficients c m per dof, with u and u_tilde
 // (iut) for the residual's c m (u - u_tilde).
@@ -303,7 +290,7 @@ __device__ __forceinline__ void finalize_node(uint32_t g, uint32_t mk, const T a
                                               T *out, const double *fext, double s,
                                               double &nrm, const T *epw, T epc, const T *fs,
                                               int nomask, const T *icm, const double *iut,
-                                              const T *u, const ChebEp<T> &ch) {
+                                              const T *u) {
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     const int64_t d = 3 * int64_t(g) + i;
@@ -319,14 +306,7 @@ __device__ __forceinline__ void finalize_node(uint32_t g, uint32_t mk, const T a
       const T vd = vz ? vz[d] + bt * v[d] : v[d];
       T y = fixed ? (nomask ? T(0) : vd) : (icm ? a + icm[d] * vd : a);
       if (epw) y -= epc * epw[d];
-      if (ch.b) {
-        const T r = ch.dinv[d] * (ch.b[d] - y);
-        const T dn = ch.cd == T(0) ? ch.cr * r : ch.cd * ch.d[d] + ch.cr * r;
-        ch.d[d] = dn;
-        out[d] = vd + dn;
-      } else {
-        out[d] = y;
-      }
+      out[d] = y;
       nrm += double(vd * y);
     } else if (OP == OP_DIAG) {
       out[d] = fixed ? T(1) : (icm ? a + icm[d] : a);
@@ -853,8 +833,7 @@ __global__ __launch_bounds__(NTB) void k_elem_block(ElemArgs<T> A) {
       pp[2] = acc[2];
     } else {
       finalize_node<T, OP>(w & NODE_MASK, (w >> 28) & 7u, acc, A.v, A.vz, bt, A.out, A.fext,
-                           lscale, nrm, A.ep_w, epc, A.fs, A.nomask, A.icm, A.iut, A.u,
-                           A.ch);
+                           lscale, nrm, A.ep_w, epc, A.fs, A.nomask, A.icm, A.iut, A.u);
     }
   }
   if (OP == OP_RES || (OP == OP_JV && A.ep_red)) {
@@ -899,7 +878,7 @@ __global__ __launch_bounds__(NT) void k_elem_merge(MergeArgs<T> A) {
     finalize_node<T, OP>(w & NODE_MASK, (w >> 28) & 7u, acc, A.v, A.vz,
                          A.vz ? T(A.cg_scal[cgslot::BETA]) : T(0), A.out, A.fext, lscale, nrm,
                          A.ep_w, A.ep_coef ? T(A.ep_coef[0]) : T(0), A.fs, A.nomask, A.icm,
-                         A.iut, A.u, A.ch);
+                         A.iut, A.u);
   }
   if (OP == OP_RES || (OP == OP_JV && A.ep_red)) {
     const double s = block_sum<NT>(nrm, rs);
@@ -978,13 +957,6 @@ int launch(Ctx *c, int op, const T *xr, const T *u, const T *v, T *out, double *
   A.inst_mat = c->inst_mat;
   A.inst_done = c->inst_done;
   A.vz = op == OP_JV ? static_cast<const T *>(c->cg.z) : nullptr;
-  if (op == OP_JV && c->cheb.b) {
-    A.ch.b = static_cast<const T *>(c->cheb.b);
-    A.ch.dinv = static_cast<const T *>(c->cheb.dinv);
-    A.ch.d = static_cast<T *>(c->cheb.d);
-    A.ch.cd = T(c->cheb.cd);
-    A.ch.cr = T(c->cheb.cr);
-  }
   A.cg_red = c->cg.red;
   A.cg_np = c->cg.np;
   A.cg_scal = c->cg.scal;
@@ -1054,7 +1026,6 @@ int launch(Ctx *c, int op, const T *xr, const T *u, const T *v, T *out, double *
     B.u = u;
     B.icm = A.icm;
     B.iut = A.iut;
-    B.ch = A.ch;
     switch (op) {
       case OP_RES:
         hipLaunchKernelGGL((k_elem_merge<T, OP_RES>), dim3(g2), dim3(NT), 0, c->stream, B);

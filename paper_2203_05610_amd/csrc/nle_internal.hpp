@@ -172,14 +172,6 @@ struct Ctx {
   // its operator builds (captured Krylov chunks hold its smoother weights)
   void *amg = nullptr;
   uint64_t amg_gen = 0;
-  // a Chebyshev smoothing step fused into the next P1 Jacobian action (set
-  // and cleared by the multigrid cycle; b null: off): y is replaced by
-  // out = v + (d <- cd d + cr dinv (b - J v)), out == v
-  struct {
-    const void *b = nullptr, *dinv = nullptr;
-    void *d = nullptr;
-    double cd = 0.0, cr = 0.0;
-  } cheb;
 
   // inertia of an implicit time step: c M (u - u_tilde) in the residual,
   // c M in the tangent (M the row-sum lumped P1 mass of density rho)
