@@ -130,3 +130,38 @@ def test_damped_vibration_follows_linear_newmark_and_dissipates():
     assert lost > 1e-3 * energy(np.zeros_like(ul), v0[free])  # the dashpots matter
     assert np.linalg.norm(u[free] - ul) <= 1e-5 * np.linalg.norm(ul)
     assert np.linalg.norm(v[free] - vl) <= 1e-5 * np.linalg.norm(vl)
+
+
+def test_dashpot_force_is_the_spring_force_of_the_step_velocity():
+    # with the dashpot coefficients equal to spring coefficients, the dashpot
+    # force at velocity v~ + cv (u - u~) equals that spring matrix applied to
+    # the velocity; the dashpot tangent is cv times it, symmetric and
+    # positive semidefinite (one zero mode per off-face dof)
+    C = syn.CARDIAC
+    mesh = syn.shell_mesh(2, 6, 12)
+    P = fem.cardiac_problem(mesh, C)
+    rng = np.random.default_rng(11)
+    ut = P.lift(0.01 * rng.standard_normal(P.n_dofs))
+    vt = 0.1 * rng.standard_normal(P.n_dofs)
+    u = P.lift(0.01 * rng.standard_normal(P.n_dofs))
+    cv = 37.0
+    P.set_inertia(1e-7, 2.5e3, ut)
+    r0 = P.residual(u, 0.4)
+    P.set_robin_damping(3.0 * C["k_perp"], 5.0 * C["k_par"])
+    P.set_step_velocity(cv, vt)
+    r1 = P.residual(u, 0.4)
+    Rc = fem.robin_matrix(mesh.X, mesh.faces["epi"], 3.0 * C["k_perp"], 5.0 * C["k_par"])
+    expect = Rc @ (vt + cv * (u - ut))
+    expect[P.fixed] = 0.0
+    assert np.abs((r1 - r0) - expect).max() <= 1e-12 * np.abs(expect).max()
+    K1 = P.stiffness(u, load_scale=0.4).toarray()
+    P.set_robin_damping(0.0, 0.0)
+    K0 = P.stiffness(u, load_scale=0.4).toarray()
+    free = P.free
+    # the difference of two tangents carries their rounding (~1e-16 of |K|)
+    tol = 1e-13 * np.abs(K0).max()
+    D = (K1 - K0)[np.ix_(free, free)]
+    Dref = cv * Rc.toarray()[np.ix_(free, free)]
+    assert np.abs(D - Dref).max() <= tol
+    assert np.abs(Dref - Dref.T).max() <= 1e-14 * np.abs(Dref).max()
+    assert np.linalg.eigvalsh(Dref).min() >= -1e-12 * np.abs(Dref).max()
