@@ -328,12 +328,15 @@ def nle_set_robin(ctx: Context, tri, k_perp: float, k_par: float) -> None:
 
 
 def nle_set_inertia(ctx: Context, rho: float, coef: float, u_tilde=None) -> None:
+    """Inertia of an implicit step: coef M (u - u_tilde) with the lumped mass of
+    density rho (u_tilde: float64 device tensor; rho or coef 0 switches it off)."""
     pu = None if u_tilde is None else ctx.vec(u_tilde, ctx.torch.float64)
     ctx.check(lib().nle_set_inertia(ctx.handle, float(rho), float(coef), pu))
 
 
 def nle_newmark_predict(ctx: Context, dt: float, beta: float, u, v, a, u_tilde,
                         gamma: float = 0.5, v_tilde=None) -> None:
+    """u_tilde = u + dt v + dt^2 (1/2 - beta) a; v_tilde = v + dt (1 - gamma) a if given."""
     T = ctx.torch.float64
     pv = None if v_tilde is None else ctx.vec(v_tilde, T)
     ctx.check(lib().nle_newmark_predict(ctx.handle, float(dt), float(beta), float(gamma),
@@ -342,16 +345,19 @@ def nle_newmark_predict(ctx: Context, dt: float, beta: float, u, v, a, u_tilde,
 
 
 def nle_set_robin_damping(ctx: Context, c_perp: float, c_par: float) -> None:
+    """Dashpots on the spring faces, acting on the step velocity (nle_set_step_velocity)."""
     ctx.check(lib().nle_set_robin_damping(ctx.handle, float(c_perp), float(c_par)))
 
 
 def nle_set_step_velocity(ctx: Context, cv: float, v_tilde=None) -> None:
+    """The implicit step's velocity v(u) = v_tilde + cv (u - u_tilde); cv = 0 switches it off."""
     pv = None if v_tilde is None else ctx.vec(v_tilde, ctx.torch.float64)
     ctx.check(lib().nle_set_step_velocity(ctx.handle, float(cv), pv))
 
 
 def nle_newmark_correct(ctx: Context, dt: float, beta: float, gamma: float, u, u_tilde, v,
                         a) -> None:
+    """In place: a' = (u - u_tilde) / (beta dt^2), v += dt ((1 - gamma) a + gamma a'), a = a'."""
     T = ctx.torch.float64
     ctx.check(lib().nle_newmark_correct(ctx.handle, float(dt), float(beta), float(gamma),
                                         ctx.vec(u, T), ctx.vec(u_tilde, T), ctx.vec(v, T),
