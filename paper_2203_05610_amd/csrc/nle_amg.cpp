@@ -21,6 +21,7 @@
 // pressure block's diagonal on the pressures.
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -364,6 +365,8 @@ nle_status build_structure(Ctx *c, Amg *A) {
       std::sort(vs.begin(), vs.end());
       int64_t w = 0;
       for (int32_t b : vs) w += nx.vbeg[b + 1] - nx.vbeg[b];
+      if (int64_t(nx.rp[nx.vbeg[a]]) + w * (nx.vbeg[a + 1] - nx.vbeg[a]) > INT32_MAX)
+        return fail(c, NLE_E_UNSUPPORTED, "multigrid: a coarse operator exceeds 2^31 entries");
       for (int64_t R = nx.vbeg[a]; R < nx.vbeg[a + 1]; ++R) {
         nx.rp[R + 1] = int32_t(nx.rp[R] + w);
         for (int32_t b : vs)
@@ -428,6 +431,9 @@ nle_status build_structure(Ctx *c, Amg *A) {
         pairs[{v1[v], a}].push_back(int32_t(v));
       }
       for (const auto &kv : pairs) {
+        if (nodes.size() + kv.second.size() > size_t(INT32_MAX) ||
+            tbeg.size() + 6 > size_t(INT32_MAX))
+          return fail(c, NLE_E_UNSUPPORTED, "multigrid: probing lists exceed 2^31 entries");
         const int32_t b = kv.first.first, a = kv.first.second;
         const int32_t nb0 = int32_t(nodes.size());
         nodes.insert(nodes.end(), kv.second.begin(), kv.second.end());
