@@ -160,3 +160,50 @@ def test_chebyshev_smoother_follows_the_chebyshev_polynomial():
         # inside the interval the error shrinks by at least 1 / T_k(theta / delta)
         inside = (lam >= lo) & (lam <= hi)
         assert np.all(np.abs(factor[inside]) <= 1.0 / abs(Tk(theta / delta)) + 1e-12)
+
+
+def test_quadratic_mesh_hierarchy_keeps_rigid_motions():
+    # quadratic elements: the node graph joins all ten nodes of an element; the
+    # prolongator still spans every rigid motion and the Galerkin operators of a
+    # floating body annihilate them (quadratic fields contain the rigid motions)
+    from oracle import p2
+    m = syn.cook_p2_mesh(6, 4, 1)
+    P = p2.cook_p2_problem(m, mu=MU, lam=5.0 * MU)
+    K = P.stiffness(np.zeros(P.n_dofs), dirichlet=False).tocsr()
+    adj = amg.node_graph(np.asarray(m.conn), m.X.shape[0])
+    conn = np.asarray(m.conn)
+    for e in (0, conn.shape[0] // 2, conn.shape[0] - 1):
+        for a in conn[e]:
+            assert set(conn[e].tolist()) - {a} <= set(adj[a])
+    fixed = np.zeros(P.n_dofs, dtype=bool)
+    H = amg.setup(K, m.X, conn, fixed)
+    assert H.n_levels >= 2
+    P0 = H.P[0].toarray()
+    rng = np.random.default_rng(12)
+    t, w = rng.standard_normal(3), rng.standard_normal(3)
+    u = (t[None, :] + np.cross(w[None, :], m.X)).reshape(-1)
+    assert np.linalg.norm(K @ u) <= 1e-10 * abs(K).max() * np.linalg.norm(u)
+    assert np.linalg.norm(P0 @ (P0.T @ u) - u) <= 1e-12 * np.linalg.norm(u)
+    vc = P0.T @ u
+    assert np.linalg.norm(H.A[1] @ vc) <= 1e-9 * abs(H.A[1]).max() * np.linalg.norm(vc)
+
+
+def test_pressure_block_of_the_field_split_is_the_lumped_mass():
+    # the field split scales pressures by the lumped P1 pressure mass: row sums
+    # of the consistent mass, integral of phi_i phi_j = V (1 + delta_ij) / 20 on
+    # a tetrahedron, whose total is the domain's volume (the unit cube)
+    from oracle import mixed
+    m = syn.twist_p2_mesh(2)
+    P = mixed.twist_problem(m, 1.0, 0.0)
+    ml = P.pressure_mass_lumped()
+    assert abs(ml.sum() - 1.0) < 1e-13 and ml.min() > 0.0
+    pconn = np.asarray(m.pconn)
+    Xv = np.zeros((P.n_p, 3))
+    # pressure nodes sit at the elements' vertices (the first four displacement nodes)
+    Xv[pconn.reshape(-1)] = m.X[np.asarray(m.conn)[:, :4].reshape(-1)]
+    Mc = np.zeros((P.n_p, P.n_p))
+    for e in range(pconn.shape[0]):
+        x = Xv[pconn[e]]
+        V = abs(np.linalg.det(np.column_stack([x[1] - x[0], x[2] - x[0], x[3] - x[0]]))) / 6.0
+        Mc[np.ix_(pconn[e], pconn[e])] += V * (np.ones((4, 4)) + np.eye(4)) / 20.0
+    assert np.allclose(Mc.sum(1), ml, rtol=1e-13, atol=0.0)
