@@ -316,7 +316,8 @@ nle_status nle_set_step_velocity(nle_ctx *ctx, double cv, const double *v_tilde_
 /* Newmark corrector after the step's solve, in place (double, device):
  * a_new = (u - u_tilde) / (beta dt^2), v += dt ((1 - gamma) a + gamma a_new),
  * a = a_new.  Dirichlet dofs are not special-cased: with fixed values there
- * u - u_tilde gives their prescribed motion. */
+ * u - u_tilde gives their prescribed motion.  NLE_E_INVAL for a null vector,
+ * dt <= 0, beta <= 0 or a non-finite dt, beta or gamma. */
 nle_status nle_newmark_correct(nle_ctx *ctx, double dt, double beta, double gamma,
                                const double *u_dev, const double *u_tilde_dev, double *v_dev,
                                double *a_dev);
@@ -454,7 +455,8 @@ nle_status nle_batch_solve(nle_batch *b, int32_t method, const nle_solver_opts *
 
 /* Unknowns per level of the multigrid hierarchy built by the last NLE_PC_AMG
  * use (finest first): *n_levels = number of levels (0 if none is built),
- * sizes[0 .. min(n_levels, cap)) filled. */
+ * sizes[0 .. min(n_levels, cap)) filled (host arrays).  NLE_E_INVAL for a
+ * null ctx or n_levels, a negative cap, or a null sizes with cap > 0. */
 nle_status nle_amg_levels(const nle_ctx *ctx, int32_t *n_levels, int64_t *sizes, int32_t cap);
 
 /* ---- mesh partition inspection (for tests and tuning) --------------------- */

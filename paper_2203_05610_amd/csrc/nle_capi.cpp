@@ -738,6 +738,8 @@ nle_status nle_newmark_correct(nle_ctx *ctx, double dt, double beta, double gamm
   if (s != NLE_OK) return s;
   if (!u || !ut || !v || !a) return fail(c, NLE_E_INVAL, "null vector");
   if (!(dt > 0.0) || !(beta > 0.0)) return fail(c, NLE_E_INVAL, "dt and beta must be positive");
+  if (!std::isfinite(dt) || !std::isfinite(beta) || !std::isfinite(gamma))
+    return fail(c, NLE_E_INVAL, "dt, beta and gamma must be finite");
   NLE_HIP(c, newmark_correct(c, u, ut, v, a, dt, beta, gamma, ndof(c)));
   return NLE_OK;
 }

@@ -78,3 +78,16 @@ def test_null_and_bad_arguments_are_rejected_without_a_device():
     assert L.nle_set_block_size(None, 512) == nl.NLE_E_INVAL
     assert L.nle_last_error(None) == b"null context"
     L.nle_destroy(None)  # no-op
+
+
+def test_newer_calls_reject_null_arguments_without_a_device():
+    import ctypes as ct
+    L = nl.lib()
+    n = ct.c_int32(-1)
+    assert L.nle_amg_levels(None, ct.byref(n), None, 0) == nl.NLE_E_INVAL
+    assert n.value == -1  # nothing written on an error
+    assert L.nle_newmark_correct(None, 0.1, 0.25, 0.5, None, None, None, None) == nl.NLE_E_INVAL
+    assert L.nle_set_inertia(None, 1.0, 1.0, None) == nl.NLE_E_INVAL
+    assert L.nle_set_robin_damping(None, 1.0, 1.0) == nl.NLE_E_INVAL
+    assert L.nle_set_step_velocity(None, 1.0, None) == nl.NLE_E_INVAL
+    assert L.nle_newmark_predict(None, 0.1, 0.25, 0.5, None, None, None, None, None) == nl.NLE_E_INVAL
