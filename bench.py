@@ -295,6 +295,10 @@ TWIST_METHODS = {
     "nk_fp64_amg": ("nk", "fp64", {"ksp": "gmres", "pc": "amg"}),
     "ink_fp64_amg": ("ink", "fp64", {"ksp": "gmres", "pc": "amg"}),
     "ink_mixed_amg": ("ink", "mixed", {"ksp": "gmres", "pc": "amg"}),
+    # BFGS on the saddle-point system (the paper expects it to fail here):
+    # H0 a MINRES solve to rtol 1e-2, or the preconditioner alone
+    "bfgs_ib_fp64": ("bfgs", "fp64", {"ksp": "minres", "h0": "ksp", "qn_m": 10}),
+    "bfgs_b_fp64": ("bfgs", "fp64", {"ksp": "minres", "h0": "preonly", "qn_m": 10}),
 }
 
 
