@@ -17,7 +17,11 @@ import scipy.sparse.linalg as spla
 
 
 class NewtonFailure(RuntimeError):
-    pass
+    """Newton failed; `iterations` holds the Newton steps taken before."""
+
+    def __init__(self, msg: str, iterations: int = 0):
+        super().__init__(msg)
+        self.iterations = iterations
 
 
 def newton_exact(problem, u0: np.ndarray, load_scale: float = 1.0, rtol: float = 1e-13,
@@ -42,7 +46,7 @@ def newton_exact(problem, u0: np.ndarray, load_scale: float = 1.0, rtol: float =
         du = spla.splu(K.tocsc()).solve(-r)
         u_new = u + du
         if problem.min_jacobian(u_new) <= 0.0:
-            raise NewtonFailure("inverted element")
+            raise NewtonFailure("inverted element", len(hist))
         r_new = problem.residual(u_new, load_scale)
         n_new = float(np.linalg.norm(r_new))
         if hist[-1] <= floor_rtol * r0 and n_new > 0.5 * hist[-1]:
@@ -51,16 +55,44 @@ def newton_exact(problem, u0: np.ndarray, load_scale: float = 1.0, rtol: float =
         hist.append(n_new)
     if hist[-1] <= max(rtol, floor_rtol) * r0:
         return u, hist
-    raise NewtonFailure(f"no convergence in {max_it} iterations: {hist}")
+    raise NewtonFailure(f"no convergence in {max_it} iterations: {hist}", max_it)
 
 
-def solve_schedule(problem, scales, u0=None, **kw):
-    """Exact Newton over a sequence of load scales, warm-started."""
+def solve_schedule(problem, scales, u0=None, max_cuts: int = 0, start_scale: float = 0.0,
+                   log=None, **kw):
+    """Exact Newton over a sequence of load scales, warm-started.
+
+    With max_cuts > 0, a load step whose Newton iteration fails (an element
+    inverts or the iteration limit is reached) is retried from the last
+    converged state at the midpoint of the failed increment, at most
+    max_cuts times over the schedule (the load stepping of Sec. 4, read as
+    stepping with halving on failure).  Returns (u, Newton histories of the
+    accepted steps); with `log` (a list) each attempt appends
+    (scale, accepted, Newton iterations taken)."""
     u = np.zeros(problem.n_dofs) if u0 is None else np.array(u0, dtype=np.float64)
     hists = []
-    for s in scales:
-        u, h = newton_exact(problem, u, s, **kw)
+    targets = [float(x) for x in scales]
+    s_prev = float(start_scale)
+    cuts = 0
+    i = 0
+    while i < len(targets):
+        s = targets[i]
+        try:
+            u_new, h = newton_exact(problem, u, s, **kw)
+        except NewtonFailure as exc:
+            if log is not None:
+                log.append((s, False, exc.iterations))
+            if cuts >= max_cuts:
+                raise
+            cuts += 1
+            targets.insert(i, 0.5 * (s_prev + s))
+            continue
+        if log is not None:
+            log.append((s, True, len(h) - 1))
+        u = u_new
         hists.append(h)
+        s_prev = s
+        i += 1
     return u, hists
 
 

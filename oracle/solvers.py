@@ -134,7 +134,8 @@ def cg(matvec: Callable, b: np.ndarray, precond: Optional[Callable] = None,
 
 def minres(matvec: Callable, b: np.ndarray, precond: Optional[Callable] = None,
            rtol: float = 1e-6, atol: float = 1e-10, max_it: int = 10000):
-    """Preconditioned MINRES (Paige & Saunders) for symmetric, possibly
+    """Preconditioned MINRES (Paige & Saunders, SIAM J. Numer. Anal. 12, 1975;
+    the Lanczos recurrence with Givens rotations as published) for symmetric, possibly
     indefinite A with an SPD preconditioner M, from a zero initial guess.
 
     The k-th iterate minimises ||b - A x||_{M^-1} over the Krylov space

@@ -339,6 +339,47 @@ def test_gmres_restarted_and_cg_solve_spd():
     assert np.allclose(x1, xs, rtol=1e-9) and np.allclose(x2, xs, rtol=1e-9)
 
 
+def _krylov_minimizer_anorm(A, Minv, b, k):
+    """Brute force: argmin ||x - A^-1 b||_A over x in K_k(M^-1 A, M^-1 b).
+    The normal equations of that A-norm problem are (K^T A K) c = K^T b."""
+    MA = Minv @ A
+    Kb = np.zeros((b.size, 0))
+    w = Minv @ b
+    for _ in range(k):  # an orthonormal basis of the same space, column by column
+        for _ in range(2):
+            w = w - Kb @ (Kb.T @ w)
+        Kb = np.column_stack([Kb, w / np.linalg.norm(w)])
+        w = MA @ Kb[:, -1]
+    c = np.linalg.solve(Kb.T @ A @ Kb, Kb.T @ b)
+    return Kb @ c
+
+
+def test_cg_iterate_is_a_norm_krylov_minimizer():
+    """Preconditioned CG's k-th iterate minimises the A-norm of the error over
+    the k-dimensional Krylov space of M^-1 A and M^-1 b (the defining property
+    of CG; a wrong beta, alpha or inner product breaks it after step 1 or 2)."""
+    n = 12
+    A = _spd(n, 31, cond=50)
+    rng = np.random.default_rng(32)
+    d = np.diag(A) * (1.0 + 0.5 * rng.random(n))  # not the exact diagonal
+    Minv = np.diag(1.0 / d)
+    b = rng.standard_normal(n)
+    xs = np.linalg.solve(A, b)
+    errs = []
+    for k in (1, 2, 3, 5, 8):
+        x, its, _, _ = solvers.cg(lambda v: A @ v, b, lambda v: v / d, rtol=0, atol=0, max_it=k)
+        assert its == k
+        ref = _krylov_minimizer_anorm(A, Minv, b, k)
+        assert np.allclose(x, ref, rtol=1e-9, atol=1e-11), k
+        e = x - xs
+        errs.append(float(e @ A @ e))
+    # the A-norm error never increases (nested spaces)
+    assert all(errs[i + 1] <= errs[i] * (1 + 1e-12) for i in range(len(errs) - 1))
+    # and at k = n the iterate is the exact solution
+    x, its, _, _ = solvers.cg(lambda v: A @ v, b, lambda v: v / d, rtol=0, atol=0, max_it=n)
+    assert np.allclose(x, xs, rtol=1e-8, atol=1e-10)
+
+
 def _krylov_minimizer_weighted(A, Minv, b, k):
     """Brute force: argmin ||b - A x||_{M^-1} over x in K_k(M^-1 A, M^-1 b)."""
     MA = Minv @ A
