@@ -92,9 +92,10 @@ typedef int32_t nle_status;
                              bs = 3 point-block Jacobi of a PETSc setup)  */
 #define NLE_PC_AMG 3 /* aggregation multigrid, one V(1,1)-cycle (the AMG of
                         Sec. 4 and App. A; its construction is this
-                        library's, see nle_pc_apply), with GMRES, CG (the
-                        cycle is symmetric for a symmetric tangent) or as the
-                        H0 of BFGS-preonly; not with MINRES.  With a pressure
+                        library's, see nle_pc_apply), with GMRES, CG or
+                        MINRES (the cycle is symmetric for a symmetric
+                        tangent, and positive definite where the tangent
+                        is), or as the H0 of BFGS-preonly.  With a pressure
                         field: the block-diagonal field split, GMRES only */
 
 #define NLE_H0_PREONLY 0 /* BFGS-preonly: H0 = one preconditioner application */
@@ -331,8 +332,9 @@ nle_status nle_lift(nle_ctx *ctx, double *u_dev);
  * check synchronises; it is made only when rnorm_host != NULL). */
 nle_status nle_residual(nle_ctx *ctx, const double *u_dev, double *r_dev, double *rnorm_host);
 /* Fix the linearization point u (double, device): the tangent used by
- * nle_jv is J(u) until the next nle_linearize.  prec selects which copies
- * (NLE_FP64 or NLE_FP32) are prepared; both are kept if called twice. */
+ * nle_jv is J(u) until the next nle_linearize.  prec = NLE_FP64 prepares the
+ * FP64 tangent only; prec = NLE_FP32 prepares the FP64 and the FP32 copies.
+ * Each call replaces the previous linearization (both copies). */
 nle_status nle_linearize(nle_ctx *ctx, const double *u_dev, int32_t prec);
 /* y = J(u_lin) v (Sec. 3, eq. "newton" left-hand side), matrix-free, in
  * precision prec (v and y are double* for NLE_FP64, float* for NLE_FP32).

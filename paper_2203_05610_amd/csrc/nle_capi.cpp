@@ -416,15 +416,26 @@ nle_status nle_set_dirichlet(nle_ctx *ctx, int64_t n, const int64_t *dofs, const
       if (!std::isfinite(vals[k])) return fail(c, NLE_E_INVAL, "non-finite Dirichlet value");
       mask[d / 3] |= bit;
     }
+    // the new arrays are allocated before the old ones are released, so a
+    // failed allocation leaves the previous Dirichlet set intact and usable
+    int64_t *nd = nullptr;
+    double *nv = nullptr;
+    if (n > 0) {
+      nd = static_cast<int64_t *>(dalloc(c, n * 8));
+      nv = static_cast<double *>(dalloc(c, n * 8));
+      if (!nd || !nv) {
+        dfree(c, nd);
+        dfree(c, nv);
+        return fail(c, NLE_E_OOM, "device allocation failed");
+      }
+    }
+    NLE_HIP(c, hipStreamSynchronize(c->stream));  // no queued kernel reads the old arrays
     dfree(c, c->dir_dofs);
     dfree(c, c->dir_vals);
-    c->dir_dofs = nullptr;
-    c->dir_vals = nullptr;
+    c->dir_dofs = nd;
+    c->dir_vals = nv;
     c->n_dir = n;
     if (n > 0) {
-      c->dir_dofs = static_cast<int64_t *>(dalloc(c, n * 8));
-      c->dir_vals = static_cast<double *>(dalloc(c, n * 8));
-      if (!c->dir_dofs || !c->dir_vals) return fail(c, NLE_E_OOM, "device allocation failed");
       NLE_HIP(c, hipMemcpyAsync(c->dir_dofs, dofs, n * 8, hipMemcpyHostToDevice, c->stream));
       NLE_HIP(c, hipMemcpyAsync(c->dir_vals, vals, n * 8, hipMemcpyHostToDevice, c->stream));
     }

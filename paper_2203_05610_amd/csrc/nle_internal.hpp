@@ -403,9 +403,16 @@ struct MinresArgs {
   double *scal;
   int32_t *flag;
 };
+// finish = false leaves out the scalar set-up (mr_start_finish), so that a
+// preconditioner applied outside the kernels can replace y = M^-1 b and the
+// partials of b.y (with dinv null the kernels apply the identity)
 hipError_t mr_start(Ctx *c, const MinresArgs &a, const void *b, double rtol, double atol,
-                    int max_it);
-hipError_t mr_iterate(Ctx *c, const MinresArgs &a);
+                    int max_it, bool finish = true);
+hipError_t mr_start_finish(Ctx *c, const MinresArgs &a, double rtol, double atol, int max_it);
+// pc_outside (nullable): called after the first vector step, it must set
+// y = M^-1 r2 and write the partials of r2.y to red_b
+hipError_t mr_iterate(Ctx *c, const MinresArgs &a,
+                      hipError_t (*pc_outside)(Ctx *, const MinresArgs &) = nullptr);
 
 // GMRES kernels
 struct GmresArgs {

@@ -152,8 +152,6 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
   int pcb = 1;
   const bool amg = o.pc == NLE_PC_AMG;
   if (amg) {
-    if (o.type == NLE_KSP_MINRES)
-      return fail(c, NLE_E_UNSUPPORTED, "the multigrid preconditioner runs with CG or GMRES");
     if (c->mixed && c->mx.n_p > 0 && o.type != NLE_KSP_GMRES)
       return fail(c, NLE_E_UNSUPPORTED, "with a pressure field the multigrid runs with GMRES");
     const nle_status sa = amg_prepare(c);
@@ -282,7 +280,19 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
       a.scal = c->dscal;
       a.flag = flag;
       a.np_a = 0;
-      NLE_HIP(c, mr_start(c, a, b, o.rtol, o.atol, o.max_it));
+      // with the multigrid the vector kernels apply the identity and one
+      // cycle replaces y = M^-1 t and the t.y partials (the cycle is
+      // symmetric; positive definite for a positive definite tangent)
+      auto cycle = [](Ctx *cc, const MinresArgs &aa) -> hipError_t {
+        return amg_apply(cc, aa.prec, aa.r2, aa.y, aa.red_b);
+      };
+      if (amg) {
+        NLE_HIP(c, mr_start(c, a, b, o.rtol, o.atol, o.max_it, false));
+        NLE_HIP(c, amg_apply(c, prec, a.r1, a.y, red_b));
+        NLE_HIP(c, mr_start_finish(c, a, o.rtol, o.atol, o.max_it));
+      } else {
+        NLE_HIP(c, mr_start(c, a, b, o.rtol, o.atol, o.max_it));
+      }
       c->elem_skip = flag;
       c->ep.w = a.r1;
       c->ep.coef = c->dscal + 20;  // M_COEF
@@ -291,7 +301,7 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
         hipError_t err;
         a.np_a = elem_apply(c, OP_JV, prec, ulin, a.v, a.y, nullptr, &err);
         if (err != hipSuccess) return err;
-        return mr_iterate(c, a);
+        return mr_iterate(c, a, amg ? +cycle : nullptr);
       };
       std::vector<uint64_t> key = {2, uint64_t(prec), uint64_t(n), uint64_t(check),
                                    uint64_t(uintptr_t(x)), uint64_t(uintptr_t(a.r1)),
@@ -300,7 +310,7 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
                                    uint64_t(uintptr_t(c->m.nodes)), uint64_t(c->mat.kind),
                                    uint64_t(uintptr_t(c->mx.G32)), uint64_t(uintptr_t(c->mx.cu)),
                                    uint64_t(uintptr_t(c->lc_valid ? c->lc64 : nullptr)),
-                                   uint64_t(pcb)};
+                                   uint64_t(pcb), uint64_t(amg), amg ? c->amg_gen : 0};
       st = run_chunks(c, key, check, o.max_it, flag, iter);
     }
     if (st != NLE_OK) return st;
@@ -492,8 +502,6 @@ nle_status check_ready(Ctx *c, double *u, const nle_solver_opts *o) {
     return fail(c, NLE_E_UNSUPPORTED, "nodal block Jacobi needs a P1 mesh");
   if (o->pc == NLE_PC_AMG && c->mixed && c->mx.n_p > 0 && o->ksp_type != NLE_KSP_GMRES)
     return fail(c, NLE_E_UNSUPPORTED, "with a pressure field the multigrid runs with GMRES");
-  if (o->pc == NLE_PC_AMG && o->ksp_type == NLE_KSP_MINRES)
-    return fail(c, NLE_E_UNSUPPORTED, "the multigrid preconditioner runs with CG or GMRES");
   if (o->ksp_max_it < 1 || o->snes_max_it < 0) return fail(c, NLE_E_INVAL, "bad iteration limits");
   if (o->cg_launches != 0 && o->cg_launches != 3 && o->cg_launches != 4)
     return fail(c, NLE_E_INVAL, "bad cg_launches");

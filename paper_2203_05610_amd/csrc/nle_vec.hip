@@ -886,12 +886,14 @@ hipError_t vec_recip(Ctx *c, const double *d, double *di, int64_t n) {
 
 hipError_t vec_lift(Ctx *c, double *u) {
   if (c->n_dir == 0) return hipSuccess;
+  if (!c->dir_dofs || !c->dir_vals) return hipErrorInvalidValue;  // never launch on null arrays
   LAUNCH(k_lift, vgrid(c->n_dir), u, c->dir_dofs, c->dir_vals, c->n_dir);
   return hipGetLastError();
 }
 
 hipError_t vec_dir_delta(Ctx *c, const double *u, double *w) {
   if (c->n_dir == 0) return hipSuccess;
+  if (!c->dir_dofs || !c->dir_vals) return hipErrorInvalidValue;
   LAUNCH(k_dir_delta, vgrid(c->n_dir), u, c->dir_dofs, c->dir_vals, w, c->n_dir);
   return hipGetLastError();
 }
@@ -976,7 +978,7 @@ hipError_t cg_direction(Ctx *c, const CgArgs &a) {
       static_cast<T *>(a.za), static_cast<T *>(a.zb), static_cast<const T *>(a.dinv)
 
 hipError_t mr_start(Ctx *c, const MinresArgs &a, const void *b, double rtol, double atol,
-                    int max_it) {
+                    int max_it, bool finish) {
   const int g = vgrid(a.n);
   if (a.prec == NLE_FP32) {
     if (a.pcb == 3)
@@ -989,6 +991,12 @@ hipError_t mr_start(Ctx *c, const MinresArgs &a, const void *b, double rtol, dou
     else
       LAUNCH((k_mr_start<double, 1>), g, static_cast<const double *>(b), MR_PTRS(double), a.n, a.red_b);
   }
+  if (!finish) return hipGetLastError();
+  return mr_start_finish(c, a, rtol, atol, max_it);
+}
+
+hipError_t mr_start_finish(Ctx *c, const MinresArgs &a, double rtol, double atol, int max_it) {
+  const int g = vgrid(a.n);
   LAUNCH(k_mr_start2, 1, a.red_b, g, a.scal, a.flag, rtol, atol, max_it);
   if (a.prec == NLE_FP32)
     LAUNCH(k_mr_v<float>, g, static_cast<const float *>(a.y), static_cast<float *>(a.v), a.n,
@@ -1000,7 +1008,8 @@ hipError_t mr_start(Ctx *c, const MinresArgs &a, const void *b, double rtol, dou
 }
 
 // the three vector / scalar steps after the Jacobian action of one iteration
-hipError_t mr_iterate(Ctx *c, const MinresArgs &a) {
+hipError_t mr_iterate(Ctx *c, const MinresArgs &a,
+                      hipError_t (*pc_outside)(Ctx *, const MinresArgs &)) {
   const int g = vgrid(a.n);
 #define MR_C(T, BS)                                                                            \
   LAUNCH((k_mr_c<T, BS>), g, static_cast<T *>(a.y), static_cast<T *>(a.r1),                    \
@@ -1012,6 +1021,12 @@ hipError_t mr_iterate(Ctx *c, const MinresArgs &a) {
     if (a.pcb == 3) MR_C(double, 3); else MR_C(double, 1);
   }
 #undef MR_C
+  if (pc_outside) {
+    // the preconditioner runs outside these kernels (the multigrid cycle):
+    // y = M^-1 r2 and the partials of r2.y, then the scalar and vector steps
+    const hipError_t e = pc_outside(c, a);
+    if (e != hipSuccess) return e;
+  }
   LAUNCH(k_mr_d, 1, a.red_b, g, a.red_r, g, a.scal, a.flag);
   if (a.prec == NLE_FP32)
     LAUNCH(k_mr_e<float>, g, static_cast<float *>(a.x), static_cast<float *>(a.v),

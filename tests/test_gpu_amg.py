@@ -248,8 +248,32 @@ def test_nk_cg_counts_follow_oracle_loop():
         assert abs(a - b) <= max(2, 0.02 * b), (rep["lit_hist"], ref["lits"])
 
 
+def test_nk_minres_counts_follow_oracle_loop():
+    # MINRES with the cycle as its (symmetric positive definite) preconditioner
+    mesh, P, ctx = _cook(16, 16, 2, tau=2.0)
+
+    def lin(u):
+        K = P.stiffness(u)
+        H = amg.setup(K, mesh.X, mesh.conn, P.fixed)
+        return (lambda v: K @ v), (lambda v: amg.vcycle(H, v))
+
+    ref = solvers.newton_krylov(lambda u: P.residual(u), lin, np.zeros(P.n_dofs), ksp="minres")
+    for prec in ("fp64", "mixed"):
+        u = torch.zeros(P.n_dofs, dtype=torch.float64, device="cuda")
+        o = problems.make_opts("nk", prec, ksp="minres", pc="amg")
+        o.check_every = 4
+        st, rep = nl.nle_solve_nk(ctx, u, o)
+        assert st == nl.NLE_OK, rep
+        assert abs(rep["nit"] - ref["nit"]) <= 1
+        if prec == "fp64":
+            for a, b in zip(rep["lit_hist"], ref["lits"]):
+                assert abs(a - b) <= max(2, 0.02 * b), (rep["lit_hist"], ref["lits"])
+
+
 SOLVES = [
     ("nk", "fp64", {"snes_rtol": 1e-11, "ksp_atol": 1e-15}),
+    ("nk", "fp64", {"snes_rtol": 1e-11, "ksp_atol": 1e-15, "ksp": "minres"}),
+    ("ink", "mixed", {"ksp": "minres"}),
     ("nk", "fp64", {"snes_rtol": 1e-11, "ksp_atol": 1e-15, "ksp": "cg"}),
     ("ink", "mixed", {}),
     ("ink", "mixed", {"ksp": "cg"}),
@@ -286,9 +310,6 @@ def test_heartbeat_steps_with_multigrid():
 def test_multigrid_usage_errors():
     mesh, P, ctx = _cook(8, 8, 1)
     u = torch.zeros(P.n_dofs, dtype=torch.float64, device="cuda")
-    with pytest.raises(nl.NleError) as e:
-        nl.nle_solve_nk(ctx, u, problems.make_opts("nk", ksp="minres", pc="amg"))
-    assert e.value.status == nl.NLE_E_UNSUPPORTED
     nl.nle_linearize(ctx, u, nl.NLE_FP64)
     with pytest.raises(nl.NleError) as e:
         nl.nle_pc_apply(ctx, nl.NLE_PC_AMG, u, u, nl.NLE_FP64)
