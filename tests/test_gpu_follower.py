@@ -14,7 +14,7 @@ import pytest
 
 import synthetic as syn
 from oracle import fem, newton, precond
-from tests.gpu_common import MU, relmax, relnorm, smooth_state
+from tests.gpu_common import MU, assert_fp32_entrywise, relmax, relnorm, row_magnitude, smooth_state
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -58,6 +58,8 @@ def test_follower_kernels_parity(grid, be):
     y32 = torch.empty(P.n_dofs, dtype=torch.float32, device="cuda")
     nl.nle_jv(ctx, _t(v, torch.float32), y32, nl.NLE_FP32)
     assert relnorm(y32.double().cpu().numpy(), K @ v) < 1e-5
+    assert_fp32_entrywise(y32.cpu().numpy(), K @ v, row_magnitude(K, v, P, u),
+                          dir_dofs=P.ddofs, v=v)
     d = torch.empty(P.n_dofs, dtype=torch.float64, device="cuda")
     nl.nle_diag(ctx, d)
     assert relmax(d.cpu().numpy(), K.diagonal()) < 1e-12

@@ -13,7 +13,7 @@ import pytest
 
 import synthetic as syn
 from oracle import fem, materials
-from tests.gpu_common import MU, relmax, relnorm, smooth_state
+from tests.gpu_common import MU, assert_fp32_entrywise, relmax, relnorm, row_magnitude, smooth_state
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -71,6 +71,8 @@ def test_jacobian_action_parity(case):
     y32 = torch.empty(P.n_dofs, dtype=torch.float32, device="cuda")
     nl.nle_jv(ctx, _t(v_h, torch.float32), y32, nl.NLE_FP32)
     assert relnorm(y32.double().cpu().numpy(), ref) < 1e-5
+    assert_fp32_entrywise(y32.cpu().numpy(), ref, row_magnitude(P.stiffness(u_h), v_h, P, u_h),
+                          dir_dofs=P.ddofs, v=v_h)
 
 
 @pytest.mark.parametrize("case", CASES[1:3])
@@ -128,6 +130,8 @@ def test_full_size_cook_parity_in_bench_configuration():
     y32 = torch.empty(P.n_dofs, dtype=torch.float32, device="cuda")
     nl.nle_jv(ctx, _t(v_h, torch.float32), y32, nl.NLE_FP32)
     assert relnorm(y32.double().cpu().numpy(), ref) < 1e-5
+    assert_fp32_entrywise(y32.cpu().numpy(), ref, row_magnitude(P.stiffness(u_h), v_h, P, u_h),
+                          dir_dofs=P.ddofs, v=v_h)
 
 
 def test_cook_xl_sampled_parity_in_roofline_configuration():
@@ -163,6 +167,12 @@ def test_cook_xl_sampled_parity_in_roofline_configuration():
     assert relmax(r.cpu().numpy()[dofs], ref_r) < 1e-12
     assert relmax(y.cpu().numpy()[dofs], ref_y) < 1e-12
     assert relnorm(y32.double().cpu().numpy()[dofs], ref_y) < 1e-5
+    Ks = sub.stiffness(u_h)
+    mag = row_magnitude(Ks, v_h, sub, u_h)[dofs]
+    free = ~np.isin(dofs, d)
+    assert_fp32_entrywise(y32.cpu().numpy()[dofs][free], ref_y[free], mag[free])
+    fixed = dofs[~free]
+    assert np.array_equal(y32.cpu().numpy()[fixed], v_h.astype(np.float32)[fixed])
 
 
 def test_single_element_and_fully_constrained():

@@ -14,7 +14,7 @@ import pytest
 
 import synthetic as syn
 from oracle import newton, p2
-from tests.gpu_common import MU, relmax, relnorm
+from tests.gpu_common import MU, assert_fp32_entrywise, relmax, relnorm, row_magnitude
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -65,6 +65,7 @@ def test_p2_kernels_parity(grid):
     y32 = torch.empty(P.n_dofs, dtype=torch.float32, device="cuda")
     nl.nle_jv(ctx, _t(v, torch.float32), y32, nl.NLE_FP32)
     assert relnorm(y32.double().cpu().numpy(), K @ v) < 1e-5
+    assert_fp32_entrywise(y32.cpu().numpy(), K @ v, row_magnitude(K, v))
     d = torch.empty(P.n_dofs, dtype=torch.float64, device="cuda")
     nl.nle_diag(ctx, d)
     assert relmax(d.cpu().numpy(), K.diagonal()) < 1e-12

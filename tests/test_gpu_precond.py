@@ -12,7 +12,7 @@ import pytest
 
 import synthetic as syn
 from oracle import fem, materials, newton, precond
-from tests.gpu_common import MU, relmax, relnorm, smooth_state
+from tests.gpu_common import MU, assert_fp32_entrywise, relmax, relnorm, row_magnitude, smooth_state
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -78,6 +78,13 @@ def test_block_diagonal_and_applications_match_oracle(kind, args):
     y32 = torch.empty(P.n_dofs, dtype=torch.float32, device="cuda")
     nl.nle_pc_apply(ctx, nl.NLE_PC_BJACOBI3, _t(x, torch.float32), y32, nl.NLE_FP32)
     assert relnorm(y32.double().cpu().numpy(), ref) < 1e-5
+    # the applied 3x3 inverses, column by column (a block that is not
+    # positive definite is applied as its diagonal)
+    cols = [precond.block_jacobi_apply(B, np.tile(np.eye(3)[c], n_nodes)).reshape(-1, 3)
+            for c in range(3)]
+    Ainv = np.abs(np.stack(cols, axis=2))
+    mag = np.einsum("nij,nj->ni", Ainv, np.abs(x).reshape(-1, 3)).reshape(-1)
+    assert_fp32_entrywise(y32.cpu().numpy(), ref, mag, what="block Jacobi")
     nl.nle_pc_apply(ctx, nl.NLE_PC_JACOBI, _t(x), y)
     assert relmax(y.cpu().numpy(), precond.point_jacobi_apply(K, x)) < 1e-12
     nl.nle_pc_apply(ctx, nl.NLE_PC_NONE, _t(x), y)

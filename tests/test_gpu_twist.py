@@ -17,7 +17,7 @@ import pytest
 
 import synthetic as syn
 from oracle import mixed, newton
-from tests.gpu_common import relmax, relnorm
+from tests.gpu_common import assert_fp32_entrywise, relmax, relnorm, row_magnitude
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -70,6 +70,7 @@ def test_twist_kernels_parity(n):
     y32 = torch.empty(P.n_dofs, dtype=torch.float32, device="cuda")
     nl.nle_jv(ctx, _t(v, torch.float32), y32, nl.NLE_FP32)
     assert relnorm(y32.double().cpu().numpy(), K @ v) < 1e-5
+    assert_fp32_entrywise(y32.cpu().numpy(), K @ v, row_magnitude(K, v))
 
     d = torch.empty_like(r)
     nl.nle_diag(ctx, d)
