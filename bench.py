@@ -29,6 +29,7 @@ RATIO = 5000.0
 GRID = (64, 64, 4)
 XL_GRID = (256, 256, 16)
 HBM_PEAK_GBS = 8000.0
+JV_KERNEL = "nle_jv FP32 (k_elem_block<float,JV> + k_elem_merge<float,JV>)"
 
 # method name -> (solver, precision, option overrides)
 # NK keeps the Krylov tolerance of App. A (1e-6): at large load the tangent
@@ -63,9 +64,30 @@ METHODS = {
     # the cycle is symmetric for the symmetric dead-load tangent: CG with it
     "ink_mixed_cg_amg": ("ink", "mixed", {"ksp": "cg", "pc": "amg"}),
     "ink_fp64_cg_amg": ("ink", "fp64", {"ksp": "cg", "pc": "amg"}),
+    # plain FP64 Newton-Krylov with the same multigrid (the like-for-like
+    # baseline: App. A tolerances rtol 1e-6 / atol 1e-10)
+    "nk_fp64_cg_amg": ("nk", "fp64", {"ksp": "cg", "pc": "amg"}),
+    "nk_fp64_gmres30_amg": ("nk", "fp64", {"ksp": "gmres", "restart": 30, "orth": "cgs2",
+                                           "pc": "amg"}),
+    "nk_fp64_minres_amg": ("nk", "fp64", {"ksp": "minres", "pc": "amg"}),
+    "ink_mixed_minres_amg": ("ink", "mixed", {"ksp": "minres", "pc": "amg"}),
     "bfgs_ib_mixed_cg_amg": ("bfgs", "mixed", {"h0": "ksp", "qn_m": 10, "ksp": "cg",
                                                "pc": "amg", "h0_refresh": 20}),
 }
+
+
+def root_error(uh):
+    """|u - u*| / |u*| against the oracle's root of the timed schedule, stored
+    by tests/golden/make_golden.py (None if that file is absent)."""
+    import numpy as np
+
+    path = os.path.join(ROOT, "tests", "golden", "cook64x64x4_l5000_tau16.npy")
+    if not os.path.exists(path):
+        return None
+    ustar = np.load(path)
+    if ustar.shape != uh.shape:
+        return None
+    return float(np.linalg.norm(uh - ustar) / np.linalg.norm(ustar))
 
 
 def load_schedule():
@@ -133,13 +155,19 @@ def jv_roofline(nl, torch, reps: int):
         e1.record(ctx.stream)
         e1.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        # per element: 16-byte index record and the one cached tangent
-        # coefficient of law M1; per block-node slot: its 3 relative
-        # coordinates (the kernel forms grad N and V from them); per node: u
-        # and v read, y written
-        balg = mesh.n_elems * (16 + s) + n_slots * 3 * s + mesh.n_nodes * 9 * s
+        # algorithmic bytes of one Jacobian action (recompute design, each
+        # array of the method read or written once): per element 4 node
+        # indices (16 B) and 10 scalars (grad N: 9, V: 1); per node u and v
+        # read and y written (3 scalars each)
+        balg = mesh.n_elems * (16 + 10 * s) + mesh.n_nodes * 3 * 3 * s
+        # this library's own layout: per element a 16-byte index record and
+        # the one cached tangent coefficient of law M1; per block-node slot its
+        # 3 relative coordinates (grad N and V are formed from them); per node
+        # u, v, y
+        blay = mesh.n_elems * (16 + s) + n_slots * 3 * s + mesh.n_nodes * 9 * s
         out["fp32" if s == 4 else "fp64"] = {
             "ms": ms, "bytes": balg, "gbs": balg / ms / 1e6,
+            "layout_bytes": blay, "layout_gbs": blay / ms / 1e6,
             "n_elems": mesh.n_elems, "n_nodes": mesh.n_nodes, "n_slots": n_slots,
         }
     out["partition"] = nl.nle_partition_info(ctx)
@@ -183,27 +211,65 @@ print(json.dumps(dict(seconds=dt, iterations=len(hist) - 1)))
 """
 
 
+def _host_cpu():
+    """CPU model name and logical core count of the host (from lscpu)."""
+    model, cpus = None, os.cpu_count()
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() == "Model name":
+                model = v.strip()
+            elif k.strip() == "CPU(s)":
+                cpus = int(v.strip())
+    except (OSError, ValueError, subprocess.SubprocessError):
+        pass
+    return model, cpus
+
+
 def cpu_baseline(n_load_steps: int):
     """The oracle's exact Newton (assembled complex-step tangent + sparse LU,
-    one thread) on the same 64x64x4 mesh: a bounded sample of one complete
-    load step (tau = 1, to ||r|| <= 1e-8 ||r_0||), scaled by the number of load
-    steps of the schedule."""
+    one thread) on the same 64x64x4 mesh, timed on a bounded sample: the first
+    load step (tau = 1, from u = 0, to ||r|| <= 1e-8 ||r_0||).  The seconds
+    per Newton iteration are scaled by the number of Newton iterations the
+    oracle takes over the whole schedule (every attempt, the failed one
+    included), which tests/golden/make_golden.py recorded when it wrote the
+    stored root; without that record, by the number of load steps."""
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
     code = CPU_SNIPPET.format(root=ROOT, nx=GRID[0], ny=GRID[1], nz=GRID[2], mu=MU,
                               lam=RATIO * MU, scale=1.0)
-    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
-                       timeout=900)
+    try:
+        r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                           timeout=300)
+    except subprocess.TimeoutExpired:
+        return {"error": "oracle sample exceeded 300 s"}
     if r.returncode != 0:
         return {"error": r.stderr[-400:]}
     d = json.loads(r.stdout.strip().splitlines()[-1])
+    per_it = d["seconds"] / max(d["iterations"], 1)
+    model, cpus = _host_cpu()
+    meta_path = os.path.join(ROOT, "tests", "golden", "cook64x64x4_l5000_tau16.json")
+    total_its = None
+    if os.path.exists(meta_path):
+        with open(meta_path) as fh:
+            total_its = json.load(fh).get("newton_iterations")
+    if total_its:
+        value = per_it * total_its
+        how = (f"{d['iterations']} Newton iterations of the first load step (tau=1) in "
+               f"{d['seconds']:.1f} s = {per_it:.2f} s per iteration, times the {total_its} "
+               f"iterations the oracle takes over the schedule 1,2,4,8,16 with its cutback")
+    else:
+        value = d["seconds"] * n_load_steps
+        how = (f"one load step (tau=1): {d['iterations']} iterations in {d['seconds']:.1f} s, "
+               f"times the {n_load_steps} load steps")
     return {
-        "value": round(d["seconds"] * n_load_steps, 2),
+        "value": round(value, 2),
         "unit": "s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"one load step (tau=1) of exact Newton on the 64x64x4 mesh: "
-                   f"{d['iterations']} iterations in {d['seconds']:.1f} s on 1 thread, "
-                   f"times the {n_load_steps} load steps of the schedule"),
+        "sample": how + " (exact Newton, complex-step tangent, SuperLU, 1 thread, 64x64x4 mesh)",
+        "host_cpu": model,
+        "host_logical_cpus": cpus,
     }
 
 
@@ -357,6 +423,13 @@ CARDIAC_METHODS = {
     "bfgs_ib_fp64_r20_amg": ("bfgs", "fp64", {"ksp": "gmres", "h0": "ksp", "qn_m": 10,
                                               "h0_refresh": 20, "pc": "amg"}),
     "ink_fp64_cg_amg": ("ink", "fp64", {"ksp": "cg", "pc": "amg"}),
+    # plain FP64 Newton-Krylov with the same multigrid (the like-for-like
+    # baseline: App. A tolerances rtol 1e-6 / atol 1e-10)
+    "nk_fp64_cg_amg": ("nk", "fp64", {"ksp": "cg", "pc": "amg"}),
+    "nk_fp64_gmres30_amg": ("nk", "fp64", {"ksp": "gmres", "restart": 30, "orth": "cgs2",
+                                           "pc": "amg"}),
+    "nk_fp64_minres_amg": ("nk", "fp64", {"ksp": "minres", "pc": "amg"}),
+    "ink_mixed_minres_amg": ("ink", "mixed", {"ksp": "minres", "pc": "amg"}),
     "ink_fp64_gmres30_amg": ("ink", "fp64", {"ksp": "gmres", "restart": 30, "pc": "amg"}),
     "bfgs_ib_fp64_r20_cg_amg": ("bfgs", "fp64", {"ksp": "cg", "h0": "ksp", "qn_m": 10,
                                                  "h0_refresh": 20, "pc": "amg"}),
@@ -558,6 +631,7 @@ def main():
               "solve over several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
 
     import synthetic as syn
@@ -620,6 +694,8 @@ def main():
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1000.0 / max(args.steps, 1)
     all_ok = all(r["ok"] for r in runs)
+    u_method = u.detach().cpu().numpy().copy()
+    accuracy = {"method_vs_oracle_root": root_error(u_method)}
 
     extra = {}
     base = None
@@ -629,6 +705,10 @@ def main():
         ok, reps = run_solve(ctx, u, args.baseline, schedule)
         torch.cuda.synchronize()
         base = {"method": args.baseline, "seconds": time.perf_counter() - tb, **summarize(reps)}
+        u_base = u.detach().cpu().numpy()
+        accuracy["baseline_vs_oracle_root"] = root_error(u_base)
+        accuracy["method_vs_baseline"] = float(np.linalg.norm(u_method - u_base) /
+                                               max(np.linalg.norm(u_base), 1e-300))
         print(f"[bench] baseline {args.baseline}: {base['seconds']:.2f}s ok={base['ok']}",
               file=sys.stderr, flush=True)
     for m in [x for x in args.compare.split(",") if x]:
@@ -636,7 +716,8 @@ def main():
         tb = time.perf_counter()
         ok, reps = run_solve(ctx, u, m, schedule)
         torch.cuda.synchronize()
-        extra[m] = {"seconds": time.perf_counter() - tb, **summarize(reps)}
+        extra[m] = {"seconds": time.perf_counter() - tb, **summarize(reps),
+                    "rel_error_vs_oracle_root": root_error(u.detach().cpu().numpy())}
         print(f"[bench] compare {m}: {extra[m]['seconds']:.2f}s ok={extra[m]['ok']}",
               file=sys.stderr, flush=True)
     ctx.close()
@@ -654,10 +735,21 @@ def main():
             "unit": "GB/s",
             "frac": round(f["gbs"] / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "nle_jv FP32 (k_elem_block<float,JV> + k_elem_merge<float,JV>)",
-            "workload": "Cook 256x256x16, 6,291,456 P1 tets, 1,122,833 nodes",
+            "target_frac": 0.60,
+            "target_met": f["gbs"] / HBM_PEAK_GBS >= 0.60,
+            "kernel": JV_KERNEL,
+            "workload": "Cook 256x256x16, 6,291,456 P1 tets, 1,122,833 nodes, law M1, FP32",
+            "bytes_definition": "algorithmic: 56 B per element (4 int32 node ids, grad N and V "
+                                "as 10 FP32) + 36 B per node (u, v read, y written)",
             "bytes_per_launch": f["bytes"],
             "ms_per_launch": round(f["ms"], 5),
+            "traffic_over_bytes": round(traffic / f["bytes"], 3) if traffic else None,
+            "layout": {"definition": "this library's own arrays: 20 B per element, 12 B per "
+                                     "block-node slot, 36 B per node",
+                       "bytes_per_launch": f["layout_bytes"],
+                       "achieved": round(f["layout_gbs"], 1),
+                       "traffic_over_bytes": (round(traffic / f["layout_bytes"], 3)
+                                              if traffic else None)},
             "fp64": {"achieved": round(jv["fp64"]["gbs"], 1), "ms_per_launch":
                      round(jv["fp64"]["ms"], 5), "bytes_per_launch": jv["fp64"]["bytes"],
                      "frac": round(jv["fp64"]["gbs"] / HBM_PEAK_GBS, 4)},
@@ -698,7 +790,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if METHODS[args.method][1] == "mixed" else "f64",
+        "dtype": "f32+f64 (mixed)" if METHODS[args.method][1] == "mixed" else "f64",
         "data": "synthetic",
         "config": {
             "workload": "Cook's membrane 64x64x4 hexes -> 98,304 P1 tets, 63,375 dofs, "
@@ -724,6 +816,7 @@ def main():
         "cardiac": cardiac,
         "follower": follower,
         "p2": p2,
+        "accuracy": accuracy,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -115,3 +115,64 @@ def test_batch_autotune_keeps_layout_and_results():
     for i, (m, P, sched, ustar) in enumerate(data):
         ui = uh[3 * off[i]: 3 * off[i + 1]]
         assert np.linalg.norm(ui - ustar) <= 1e-6 * np.linalg.norm(ustar), i
+
+
+def test_batch_recipe_sample_matches_stored_oracle_roots():
+    # every 16th instance of the 256-instance batch recipe (default_rng(0)):
+    # meshes 8x8x1 .. 48x48x3, lambda/mu 10 .. 1e4, tau 1 .. 32 with doubling
+    # schedules; solved together as the benchmark solves the whole recipe
+    # (mixed iNK, CG + Jacobi), each against its stored oracle root
+    import os
+
+    gold = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                "batch16_roots.npz"))
+    recipe = syn.batch_recipe(256)
+    ids = list(range(0, 256, 16))
+    B = nl.Batch(0)
+    for i in ids:
+        r = recipe[i]
+        m = syn.cook_mesh(r["nx"], r["ny"], r["nz"])
+        problems.add_cook_instance(B, m, r["mu"], r["lam"], 1.0, syn.cook_load_schedule(r["tau"]))
+    nl.nle_batch_finalize(B)
+    off = nl.nle_batch_layout(B)
+    u = torch.zeros(int(3 * off[-1]), dtype=torch.float64, device="cuda")
+    st, reps, _ = nl.nle_batch_solve(B, nl.NLE_INK, problems.make_opts("ink", "mixed", ksp="cg"), u)
+    assert st == nl.NLE_OK, [(r["status"], r["nit"]) for r in reps]
+    uh = u.cpu().numpy()
+    errs = []
+    for k, i in enumerate(ids):
+        ustar = gold[f"i{i}"]
+        ui = uh[3 * off[k]: 3 * off[k + 1]]
+        assert ui.shape == ustar.shape
+        errs.append(float(np.linalg.norm(ui - ustar) / np.linalg.norm(ustar)))
+    assert max(errs) <= 1e-6, list(zip(ids, errs))
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_batch_invariance_bitwise(precision):
+    # an instance solved inside a batch of uneven neighbours gives bit for bit
+    # what it gives alone in a batch (per-instance reductions, decisions and
+    # work lists; the same element-block size)
+    sub = [INSTANCES[0], INSTANCES[1], INSTANCES[4]]
+    meshes = [syn.cook_mesh(nx, ny, nz) for nx, ny, nz, _, _ in sub]
+
+    def solve(which):
+        B = nl.Batch(0)
+        for k in which:
+            nx, ny, nz, ratio, tau = sub[k]
+            problems.add_cook_instance(B, meshes[k], MU, ratio * MU, 1.0,
+                                       syn.cook_load_schedule(tau))
+        nl.nle_batch_finalize(B)
+        off = nl.nle_batch_layout(B)
+        u = torch.zeros(int(3 * off[-1]), dtype=torch.float64, device="cuda")
+        st, reps, _ = nl.nle_batch_solve(B, nl.NLE_INK, problems.make_opts("ink", precision,
+                                                                           ksp="cg"), u)
+        assert st == nl.NLE_OK
+        return u, off, reps
+
+    u_all, off, reps_all = solve([0, 1, 2])
+    for k in range(3):
+        u_one, _, reps_one = solve([k])
+        assert torch.equal(u_all[3 * off[k]: 3 * off[k + 1]], u_one), k
+        assert reps_all[k]["nit"] == reps_one[0]["nit"]
+        assert reps_all[k]["lit_total"] == reps_one[0]["lit_total"]
