@@ -157,3 +157,23 @@ def divergence_p2p1(X: np.ndarray, conn10: np.ndarray, pconn: np.ndarray, n_p: i
         vals.append(Be.reshape(-1))
     return sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                          shape=(n_p, 3 * X.shape[0])).tocsr()
+
+
+def divergence_p2p0(X: np.ndarray, conn10: np.ndarray) -> sp.csr_matrix:
+    """B[e, (a, i)] = -int_e d(N_a)/dx_i (pressure constant on element e,
+    quadratic displacement basis N_a), exact rule; shape (n_e, 3 n_u)."""
+    ref, wref = _duffy_rule(3)
+    rows, cols, vals = [], [], []
+    for e in range(conn10.shape[0]):
+        c = conn10[e]
+        Xe = X[c]
+        J = np.stack([Xe[1] - Xe[0], Xe[2] - Xe[0], Xe[3] - Xe[0]], axis=1)
+        det = abs(np.linalg.det(J))
+        pts = Xe[0][None, :] + ref @ J.T
+        g = _quadratic_basis_gradients(Xe, pts)
+        Be = -np.einsum("q,qai->ai", wref * det, g).reshape(-1)
+        rows.append(np.full(30, e))
+        cols.append((3 * c[:, None] + np.arange(3)[None, :]).reshape(-1))
+        vals.append(Be)
+    return sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(conn10.shape[0], 3 * X.shape[0])).tocsr()

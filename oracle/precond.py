@@ -81,3 +81,43 @@ def pcg(K, b: np.ndarray, apply_minv, rtol: float = 1e-10, max_it: int = 10000):
         p = z + (rz_new / rz) * p
         rz = rz_new
     return x, max_it
+
+
+# ---- block preconditioners of the displacement / pressure saddle point ------
+# App. B: with the tangent in blocks M = [[A, B1], [B2, C]] (displacement
+# rows first), a Schur complement preconditioner comes from the block LU
+# factorisation M = L D U, L = [[I, 0], [B2 A^-1, I]], D = diag(A, S),
+# S = C - B2 A^-1 B1.  The lower form keeps L D = [[A, 0], [B2, S]]; its
+# inverse applied to r = (r_u, r_p) is
+#     z_u = A^-1 r_u,   z_p = S^-1 (r_p - B2 z_u).
+# The twist test (Sec. 4) approximates A^-1 by the displacement block's
+# preconditioner and S by SIMPLE, S ~ C - B2 diag(A)^-1 B1 (here C = 0, the
+# law is linear in p), whose diagonal stands in for the Schur block's own
+# preconditioner.  The block-diagonal form (middle factor only) is available
+# too; with C = 0 it is the variant App. B allows.
+
+def saddle_blocks(K, n_u: int):
+    """(A, B2) of the assembled tangent: the displacement block and the
+    pressure rows' displacement columns (Dirichlet columns are already zero
+    in K's pressure rows, Dirichlet rows of A are identity rows)."""
+    K = K.tocsr()
+    return K[:n_u, :n_u], K[n_u:, :n_u]
+
+
+def simple_schur_diagonal(K, n_u: int) -> np.ndarray:
+    """The diagonal of B2 diag(A)^-1 B2^T (positive): minus the diagonal of
+    the SIMPLE Schur approximation C - B2 diag(A)^-1 B1 with C = 0, B1 = B2^T."""
+    A, B = saddle_blocks(K, n_u)
+    d = A.diagonal()
+    Bsq = B.multiply(B)
+    return np.asarray(Bsq @ (1.0 / d)).reshape(-1)
+
+
+def schur_lower_apply(K, n_u: int, r: np.ndarray, apply_a, s_diag: np.ndarray) -> np.ndarray:
+    """z = (L D)^-1 r for the lower block-triangular preconditioner with the
+    Schur block approximated by -diag(s_diag) (s_diag > 0):
+    z_u = apply_a(r_u), z_p = -(r_p - B2 z_u) / s_diag."""
+    _, B = saddle_blocks(K, n_u)
+    zu = apply_a(r[:n_u])
+    zp = -(r[n_u:] - B @ zu) / s_diag
+    return np.concatenate([zu, zp])

@@ -130,3 +130,140 @@ def test_twist_exact_newton_converges_quadratically():
         k = int(np.argmax(hh < 1e-4))
         assert hh[k + 1] <= 10 * hh[k] ** 2 or hh[k + 1] <= 1e-13
     assert P.min_jacobian(x) > 0.5
+
+
+# ---- the paper's twist statement: law M5 on the P2-P0 pair (Sec. 4) -----------
+M5 = mixed.TWIST_M5
+
+
+def _rand_F(rng, n=5, amp=0.2):
+    return np.eye(3) + amp * rng.standard_normal((n, 3, 3))
+
+
+def test_m5_stress_free_reference_and_printed_balance():
+    F = np.eye(3)[None]
+    assert np.abs(mixed.m5_piola(F, np.zeros(1), M5)).max() <= 1e-10
+    # any other constants leave a stress at rest unless 2 a_p + 4 b_p = 4 b_s + 2 a_s
+    assert np.abs(mixed.m5_piola(F, np.zeros(1), (1.0, 2.0, 3.0, 4.0))).max() > 1.0
+    assert abs(mixed.m5_energy(F, np.zeros(1), M5)[0]) <= 1e-9
+
+
+def test_m5_piola_is_gradient_of_energy():
+    rng = np.random.default_rng(61)
+    F = _rand_F(rng)
+    p = rng.standard_normal(5) * 100.0
+    prm = (1.3, 0.7, 2.1, 0.4)  # generic constants: each term checked on its own
+    P = mixed.m5_piola(F, p, prm)
+    h = 1e-30
+    for i in range(3):
+        for j in range(3):
+            Fc = F.astype(np.complex128)
+            Fc[:, i, j] += 1j * h
+            d = mixed.m5_energy(Fc, p, prm).imag / h
+            assert np.allclose(P[:, i, j], d, rtol=1e-12, atol=1e-12)
+
+
+def test_m5_frame_indifference():
+    rng = np.random.default_rng(62)
+    F = _rand_F(rng)
+    p = rng.standard_normal(5)
+    Q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    if np.linalg.det(Q) < 0:
+        Q[:, 0] *= -1
+    P = mixed.m5_piola(F, p, M5)
+    PQ = mixed.m5_piola(Q[None] @ F, p, M5)
+    assert np.allclose(PQ, Q[None] @ P, rtol=1e-12, atol=1e-9)
+    # the energy is invariant too
+    assert np.allclose(mixed.m5_energy(Q[None] @ F, p, M5), mixed.m5_energy(F, p, M5),
+                       rtol=1e-12, atol=1e-9)
+
+
+def test_p2p0_tangent_at_rest_is_linear_elasticity_and_divergence():
+    # at rest (u = 0, p = 0) the displacement block is small-strain elasticity
+    # with mu = 2 (a_p + b_p), lambda = 4 b_p, and the pressure rows are
+    # -int div v on each element; both assembled independently in linear.py
+    m = syn.twist_p2_mesh(2)
+    P = mixed.twist_problem_p0(m, 0.0)
+    P.ddofs = np.zeros(0, np.int64)
+    P.dvals = np.zeros(0)
+    P.__post_init__()
+    K = P.stiffness(np.zeros(P.n_dofs))
+    nu = 3 * P.n_u
+    ap, bp = M5[0], M5[1]
+    Klin = linear.stiffness_linear_p2(m.X, m.conn, 4.0 * bp, 2.0 * (ap + bp))
+    assert abs(K[:nu, :nu] - Klin).max() <= 1e-9 * abs(Klin).max()
+    Bref = linear.divergence_p2p0(m.X, m.conn)
+    assert abs(K[nu:, :nu] - Bref).max() <= 1e-12 * abs(Bref).max()
+    assert abs(K[:nu, nu:] - Bref.T).max() <= 1e-12 * abs(Bref).max()
+    assert abs(K[nu:, nu:]).max() == 0.0
+    # lumped P0 pressure mass = element volumes; mu_eff of the law
+    assert np.allclose(P.pressure_mass_lumped(), P.V)
+    assert P.mu_eff == 2.0 * (ap + bp)
+
+
+def test_p2p0_twist_newton_reaches_incompressible_root():
+    # exact Newton on one twist step: quadratic convergence and, at the root,
+    # int_e (J - 1) = 0 on every element (the P0 constraint) to rounding
+    m = syn.twist_p2_mesh(2)
+    P = mixed.twist_problem_p0(m, math.radians(20))
+    x, hist = newton.newton_exact(P, np.zeros(P.n_dofs), 1.0)
+    assert hist[-1] <= 1e-10 * hist[0]
+    nu = 3 * P.n_u
+    r = P.residual(x)
+    assert np.abs(r[nu:]).max() <= 1e-12 * max(1.0, np.abs(x[:nu]).max())
+    assert np.abs(x[nu:]).max() > 1.0  # a nonzero pressure holds the constraint
+
+
+def _saddle(n_u=9, n_p=3, seed=71):
+    """A saddle-point matrix [[A, B^T], [B, 0]] with diagonal A and pressure
+    rows of disjoint supports, where SIMPLE's diag(A) is A itself and
+    B diag(A)^-1 B^T is diagonal: the Schur complement is exact."""
+    import scipy.sparse as sp
+
+    rng = np.random.default_rng(seed)
+    A = np.diag(1.0 + rng.random(n_u))
+    B = np.zeros((n_p, n_u))
+    for b in range(n_p):
+        B[b, 3 * b: 3 * b + 3] = rng.standard_normal(3)
+    K = np.block([[A, B.T], [B, np.zeros((n_p, n_p))]])
+    return sp.csr_matrix(K), np.diag(A)
+
+
+def test_schur_lower_with_exact_schur_converges_in_two_gmres_steps():
+    # App. B: with the exact Schur complement the lower block-triangular
+    # preconditioner leaves (M P^-1 - I)^2 = 0, so GMRES needs two steps; the
+    # block-diagonal form leaves three distinct eigenvalues, three steps
+    from oracle import precond, solvers
+
+    K, dA = _saddle()
+    n_u = dA.size
+    s = precond.simple_schur_diagonal(K, n_u)
+    b = np.random.default_rng(72).standard_normal(K.shape[0])
+    low = lambda r: precond.schur_lower_apply(K, n_u, r, lambda ru: ru / dA, s)  # noqa: E731
+    x, its, _, ok = solvers.gmres(lambda v: K @ v, b, low, rtol=1e-12, atol=0.0, max_it=20)
+    assert ok and its == 2
+    diag = lambda r: np.concatenate([r[:n_u] / dA, -r[n_u:] / s])  # noqa: E731
+    x2, its2, _, ok2 = solvers.gmres(lambda v: K @ v, b, diag, rtol=1e-12, atol=0.0, max_it=20)
+    assert ok2 and its2 == 3
+    assert np.allclose(K @ x, b, atol=1e-10) and np.allclose(K @ x2, b, atol=1e-10)
+
+
+def test_simple_schur_diagonal_of_p0_is_elementwise():
+    # with one pressure per element each pressure row lives on its element, so
+    # the SIMPLE diagonal is sum over the element's free dofs of B_ei^2 / A_ii
+    m = syn.twist_p2_mesh(2)
+    P = mixed.twist_problem_p0(m, math.radians(10))
+    x = P.lift(np.zeros(P.n_dofs))
+    K = P.stiffness(x)
+    nu = 3 * P.n_u
+    s = mixed_simple = None  # noqa: F841
+    from oracle import precond
+
+    s = precond.simple_schur_diagonal(K, nu)
+    dA = K.diagonal()[:nu]
+    Kd = K.toarray()
+    for e in (0, 5, P.conn.shape[0] - 1):
+        dofs = P.edofs[e, :30]
+        free = P.free[dofs]
+        ref = np.sum(Kd[nu + e, dofs[free]] ** 2 / dA[dofs[free]])
+        assert abs(s[e] - ref) <= 1e-12 * ref
