@@ -402,7 +402,21 @@ def cardiac_problem(mesh, consts: dict, gamma: float = 0.0) -> Problem:
 
 
 def set_active_tension(problem: Problem, gamma: float) -> None:
-    """Replace the active tension gamma of an M4 problem."""
+    """Replace the active tension gamma of an M4 or M6 problem."""
     p = list(problem.params)
-    p[5] = gamma
+    p[8 if problem.material == materials.M6 else 5] = gamma
     problem.params = tuple(p)
+
+
+def guccione_problem(mesh, consts: dict, law: tuple, gamma: float = 0.0) -> Problem:
+    """The heartbeat with the paper's Guccione law (M6; law = (C, b_ff,
+    b_ss, b_nn, b_fs, b_fn, b_sn, B)), the mesh's fibre and sheet
+    directions, and the loads and constraints of cardiac_problem."""
+    from synthetic import shell_dirichlet
+
+    c = consts
+    params = tuple(law) + (gamma, mesh.elem_fibre, mesh.elem_sheet)
+    ddofs = shell_dirichlet(mesh)
+    return Problem(mesh.X, mesh.conn, materials.M6, params, np.zeros(3 * mesh.n_nodes), ddofs,
+                   np.zeros(ddofs.size), pressure_tri=mesh.faces["endo"], pressure=c["p_max"],
+                   robin_tri=mesh.faces["epi"], k_perp=c["k_perp"], k_par=c["k_par"])

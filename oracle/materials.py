@@ -28,6 +28,19 @@ M4  the cardiac-like law: an exponential isotropic term of Holzapfel-Ogden
     direction(s), shape (..., 3) broadcasting against F.  The paper's own
     Guccione law needs constants it does not print; this law and its
     constants are a stated substitute.
+M6  the paper's heartbeat law (Sec. 4, "Heartbeat test"), Guccione's
+    exponential in the fibre frame plus the printed volumetric term and the
+    active stress:
+      Psi = C/2 (exp(Q) - 1) + B/2 (J - 1) ln J + gamma sqrt(I4),
+      Q   = b_ff E_ff^2 + b_ss E_ss^2 + b_nn E_nn^2 + b_fs (E_fs^2 + E_sf^2)
+            + b_fn (E_fn^2 + E_nf^2) + b_sn (E_sn^2 + E_ns^2),
+    E = (F^T F - I)/2, E_ab = (E a).b in the orthonormal frame {f, s, n}.
+    With Eb the frame components and bm the symmetric matrix of the b's,
+    S = R (C e^Q bm o Eb) R^T (R = [f s n], o the entrywise product) is
+    dPsi/dE, so P = F S + B/2 (J ln J + J - 1) F^-T + gamma (F f)(x)f/|F f|.
+    params = (C, b_ff, b_ss, b_nn, b_fs, b_fn, b_sn, B, gamma, fib, sheet):
+    the unit fibre f and sheet s per element (n = f x s).  The constants are
+    the caller's (the paper refers to Guccione's paper for them).
 """
 
 from __future__ import annotations
@@ -37,6 +50,7 @@ import numpy as np
 M1 = "M1"
 M2 = "M2"
 M4 = "M4"
+M6 = "M6"
 
 
 def _det(F):
@@ -77,8 +91,32 @@ def _fibre_terms(F, params):
     return f, Ff, I4
 
 
+def _guccione_frame(F, params):
+    """R = [f s n] (..., 3, 3), the frame components Eb = R^T E R of
+    E = (F^T F - I)/2, and the symmetric coefficient matrix bm."""
+    f = np.asarray(params[9], dtype=np.float64)
+    sh = np.asarray(params[10], dtype=np.float64)
+    n = np.cross(f, sh)
+    R = np.stack([f, sh, n], axis=-1)  # columns f, s, n
+    C = np.einsum("...ki,...kj->...ij", F, F)
+    E = 0.5 * (C - np.eye(3))
+    Eb = np.einsum("...ai,...ij,...jb->...ab", np.swapaxes(R, -1, -2), E, R)
+    bff, bss, bnn, bfs, bfn, bsn = (float(x) for x in params[1:7])
+    bm = np.array([[bff, bfs, bfn], [bfs, bss, bsn], [bfn, bsn, bnn]])
+    return R, Eb, bm
+
+
 def energy(kind: str, F, params):
     """Strain energy density Psi(F)."""
+    if kind == M6:
+        Cc, B, gamma = float(params[0]), float(params[7]), float(params[8])
+        _, Eb, bm = _guccione_frame(F, params)
+        Q = np.einsum("ab,...ab->...", bm, Eb * Eb)
+        J = _det(F)
+        f = np.asarray(params[9], dtype=np.float64)
+        Ff = np.einsum("...ij,...j->...i", F, f)
+        I4 = np.einsum("...i,...i->...", Ff, Ff)
+        return 0.5 * Cc * (np.exp(Q) - 1.0) + 0.5 * B * (J - 1.0) * np.log(J) + gamma * np.sqrt(I4)
     if kind == M4:
         a, b, af, bf, kappa, gamma = (float(x) for x in params[:6])
         J = _det(F)
@@ -105,6 +143,21 @@ def piola(kind: str, F, params):
     """First Piola-Kirchhoff stress P(F) = dPsi/dF."""
     J = _det(F)
     FiT = inv_transpose(F)
+    if kind == M6:
+        # dPsi/dEb = C e^Q (bm o Eb) (Q counts each off-diagonal pair twice),
+        # S = R (dPsi/dEb) R^T, P = F S; d[(J - 1) ln J]/dJ = ln J + 1 - 1/J
+        Cc, B, gamma = float(params[0]), float(params[7]), float(params[8])
+        R, Eb, bm = _guccione_frame(F, params)
+        Q = np.einsum("ab,...ab->...", bm, Eb * Eb)
+        Sb = (Cc * np.exp(Q))[..., None, None] * (bm * Eb)
+        S = np.einsum("...ia,...ab,...jb->...ij", R, Sb, R)
+        f = np.asarray(params[9], dtype=np.float64)
+        Ff = np.einsum("...ij,...j->...i", F, f)
+        I4 = np.einsum("...i,...i->...", Ff, Ff)
+        act = (gamma / np.sqrt(I4))[..., None, None] * np.einsum(
+            "...i,...j->...ij", Ff, np.broadcast_to(f, Ff.shape))
+        vol = (0.5 * B * (J * np.log(J) + J - 1.0))[..., None, None] * FiT
+        return np.einsum("...ik,...kj->...ij", F, S) + vol + act
     if kind == M4:
         # d(J^-2/3 I1)/dF = J^-2/3 (2F - 2/3 I1 F^-T), dI4/dF = 2 (Ff) (x) f,
         # dJ/dF = J F^-T, d sqrt(I4)/dF = (Ff) (x) f / sqrt(I4)

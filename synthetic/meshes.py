@@ -67,6 +67,8 @@ class Mesh:
     sets   : named boolean node masks (e.g. 'clamp', 'load', 'base').
     faces  : named (n_faces, 3) int32 outward-oriented boundary triangles.
     elem_fibre : optional (n_elems, 3) unit fibre direction per element.
+    elem_sheet : optional (n_elems, 3) unit sheet direction per element,
+             orthogonal to the fibre (the transmural direction).
     grid   : the hexahedral grid size the mesh came from.
     """
 
@@ -77,6 +79,7 @@ class Mesh:
     sets: Dict[str, np.ndarray] = field(default_factory=dict)
     faces: Dict[str, np.ndarray] = field(default_factory=dict)
     elem_fibre: Optional[np.ndarray] = None
+    elem_sheet: Optional[np.ndarray] = None
     grid: tuple = ()
     name: str = ""
 
@@ -317,7 +320,11 @@ def shell_mesh(n_t: int = 8, n_s: int = 80, n_c: int = 256,
     alpha = np.deg2rad(-60.0 + 120.0 * ic)
     fib = np.cos(alpha)[:, None] * e_circ + np.sin(alpha)[:, None] * e_long
     fib /= np.linalg.norm(fib, axis=1)[:, None]
-    return Mesh(X=X, conn=conn, sets=sets, faces=faces, elem_fibre=fib,
+    # sheet: the transmural unit normal of the (circumferential, longitudinal)
+    # tangent plane, orthogonal to the fibre
+    sheet = np.cross(e_circ, e_long)
+    sheet /= np.linalg.norm(sheet, axis=1)[:, None]
+    return Mesh(X=X, conn=conn, sets=sets, faces=faces, elem_fibre=fib, elem_sheet=sheet,
                 grid=(n_t, n_s, n_c), name=f"shell{n_t}x{n_s}x{n_c}")
 
 

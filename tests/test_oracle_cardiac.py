@@ -223,3 +223,112 @@ def test_heartbeat_oracle_converges_and_returns_to_rest():
     # the last step has (numerically) no activation and no pressure: rest
     assert sched[-1][1] < 1e-12
     assert np.abs(u).max() <= 1e-9
+
+
+# ---- the paper's Guccione law (M6, Sec. 4 "Heartbeat test") ---------------------
+def _frame(rng, n):
+    f = rng.standard_normal((n, 3))
+    f /= np.linalg.norm(f, axis=1)[:, None]
+    s = rng.standard_normal((n, 3))
+    s -= np.einsum("ni,ni->n", s, f)[:, None] * f
+    s /= np.linalg.norm(s, axis=1)[:, None]
+    return f, s
+
+
+G6 = (0.9, 18.0, 3.5, 2.5, 1.6, 1.2, 0.8, 50.0)  # C, b_ff, b_ss, b_nn, b_fs, b_fn, b_sn, B
+
+
+def _g6(f, s, gamma=0.0, law=G6):
+    return tuple(law) + (gamma, f, s)
+
+
+def test_m6_stress_free_and_active_stress_at_rest():
+    rng = np.random.default_rng(101)
+    f, s = _frame(rng, 4)
+    I = np.broadcast_to(np.eye(3), (4, 3, 3))
+    assert np.abs(materials.piola("M6", I, _g6(f, s))).max() <= 1e-14
+    # at F = I the active stress is gamma f (x) f
+    P = materials.piola("M6", I, _g6(f, s, gamma=0.3))
+    assert np.allclose(P, 0.3 * np.einsum("ni,nj->nij", f, f), atol=1e-14)
+
+
+def test_m6_piola_is_gradient_of_energy():
+    rng = np.random.default_rng(102)
+    f, s = _frame(rng, 6)
+    F = np.eye(3) + 0.15 * rng.standard_normal((6, 3, 3))
+    prm = _g6(f, s, gamma=0.2)
+    P = materials.piola("M6", F, prm)
+    h = 1e-30
+    for i in range(3):
+        for j in range(3):
+            Fc = F.astype(np.complex128)
+            Fc[:, i, j] += 1j * h
+            d = materials.energy("M6", Fc, prm).imag / h
+            assert np.allclose(P[:, i, j], d, rtol=1e-12, atol=1e-12)
+
+
+def test_m6_frame_indifference_and_material_frame_rotation():
+    rng = np.random.default_rng(103)
+    f, s = _frame(rng, 5)
+    F = np.eye(3) + 0.2 * rng.standard_normal((5, 3, 3))
+    Q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    if np.linalg.det(Q) < 0:
+        Q[:, 0] *= -1
+    prm = _g6(f, s, gamma=0.1)
+    # spatial rotation: P(QF) = Q P(F)
+    assert np.allclose(materials.piola("M6", Q[None] @ F, prm), Q[None] @ materials.piola("M6", F, prm),
+                       atol=1e-10)
+    # rotating the body and its fibre frame together: Psi(F Q^T; Q f, Q s) = Psi(F; f, s)
+    prm_r = _g6(f @ Q.T, s @ Q.T, gamma=0.1)
+    assert np.allclose(materials.energy("M6", F @ Q.T[None], prm_r), materials.energy("M6", F, prm),
+                       rtol=1e-12)
+
+
+def test_m6_isotropic_small_strain_limit_is_linear_elasticity():
+    # all b equal: Q = b |E|^2, and at small strain Psi = C b/2 |eps|^2 + B/2 (tr eps)^2,
+    # i.e. mu = C b / 2, lambda = B; the tangent at rest of a mesh equals the
+    # independent B-matrix assembly
+    m = syn.cook_mesh(3, 3, 1)
+    rng = np.random.default_rng(104)
+    f, s = _frame(rng, m.n_elems)
+    b = 4.0
+    law = (0.8, b, b, b, b, b, b, 30.0)
+    P = fem.Problem(m.X, m.conn, "M6", _g6(f, s, law=law), np.zeros(m.n_dofs), np.zeros(0, np.int64),
+                    np.zeros(0))
+    K = P.stiffness(np.zeros(m.n_dofs))
+    Klin = linear.stiffness_linear(m.X, m.conn, 30.0, 0.8 * b / 2.0)
+    assert abs(K - Klin).max() <= 1e-10 * abs(Klin).max()
+
+
+def test_m6_anisotropy_fibre_stretch_is_stiffer():
+    # uniaxial stretch along the fibre costs more than across it (b_ff > b_ss)
+    rng = np.random.default_rng(105)
+    f, s = _frame(rng, 1)
+    n = np.cross(f[0], s[0])
+    eps = 0.05
+    Ff = np.eye(3) + eps * np.outer(f[0], f[0])
+    Fs = np.eye(3) + eps * np.outer(s[0], s[0])
+    Fn = np.eye(3) + eps * np.outer(n, n)
+    law = (0.9, 18.0, 3.5, 2.5, 1.6, 1.2, 0.8, 0.0)
+    e = [materials.energy("M6", F[None], _g6(f, s, law=law))[0] for F in (Ff, Fs, Fn)]
+    assert e[0] > e[1] > e[2] > 0.0
+
+
+GUC = (0.1, 5.0, 2.0, 2.0, 1.0, 1.0, 1.0, 100.0)  # C, b_ff, b_ss, b_nn, b_fs, b_fn, b_sn, B (MPa)
+
+
+def test_guccione_heartbeat_steps_converge_quadratically():
+    # three activation steps of the shell with the paper's law: exact Newton
+    # converges quadratically in each (the tangent is the exact derivative)
+    m = syn.shell_mesh(2, 6, 12)
+    assert np.abs(np.einsum("ei,ei->e", m.elem_fibre, m.elem_sheet)).max() <= 1e-12
+    C = syn.CARDIAC
+    P = fem.guccione_problem(m, C, GUC)
+    u, hists = newton.solve_heartbeat(P, syn.heartbeat_schedule()[:3], C["gamma_max"])
+    for h in hists:
+        r = np.array(h) / h[0]
+        assert r[-1] <= 1e-10 and len(r) <= 8
+        # the last step squares the relative residual (up to a constant): the
+        # quadratic rate of Newton with the exact tangent
+        assert r[-1] <= 50.0 * r[-2] ** 2, r
+    assert np.abs(u).max() > 0.0
