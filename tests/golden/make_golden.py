@@ -15,6 +15,10 @@ Cases:
            (default_rng(0)), each over its doubling schedule ending at its tau:
            batch16_roots.npz (u* per instance, key "i<index>") and
            batch16_roots.json (attempts per instance).
+  twist6   the twist cube at 6^3 cells over 9 x 10 deg, P2-P1 (law M3) and
+           P2-P0 (law M5): twist6_p1.npy, twist6_p0.npy.
+  heart4   the 20-step quasi-static heartbeat on the 4x20x64 shell:
+           heart4x20x64_peak.npy (step 10), heart4x20x64.npy (step 20).
 """
 
 from __future__ import annotations
@@ -87,7 +91,51 @@ def batch16():
         json.dump(meta, fh, indent=1)
 
 
-CASES = {"cook64": cook64, "batch16": batch16}
+def _twist(n, p0):
+    import math
+
+    from oracle import mixed
+
+    mesh = syn.twist_p2_mesh(n)
+    P = mixed.twist_problem_p0(mesh, 0.0) if p0 else mixed.twist_problem(mesh, 1.0, 0.0)
+    xs = np.zeros(P.n_dofs)
+    its = []
+    t0 = time.perf_counter()
+    for s in range(1, 10):
+        mixed.set_twist_angle(P, mesh, math.radians(10 * s))
+        xs, h = newton.newton_exact(P, xs, 1.0)
+        its.append(len(h) - 1)
+    return xs, its, time.perf_counter() - t0
+
+
+def twist6():
+    """Twist 6^3 cells, 9 x 10 deg, exact Newton per angle: the P2-P1 form
+    with law M3 (mu = 1) and the paper's P2-P0 form with law M5 (all
+    constants 9000).  twist6_p1.npy, twist6_p0.npy."""
+    for p0, name in ((False, "twist6_p1"), (True, "twist6_p0")):
+        xs, its, dt = _twist(6, p0)
+        np.save(os.path.join(HERE, name + ".npy"), xs)
+        print(f"{name}: Newton iterations per angle {its}, {dt:.1f}s", flush=True)
+
+
+def heart4():
+    """Quasi-static heartbeat on the 4x20x64 ventricle shell (30,720 P1 tets),
+    law M4 with the synthetic constants, 20 time steps of the activation
+    schedule, exact Newton per step warm-started: heart4x20x64.npy (u at the
+    last step) and heart4x20x64_peak.npy (u at the activation peak, step 10)."""
+    C = syn.CARDIAC
+    mesh = syn.shell_mesh(4, 20, 64)
+    P = fem.cardiac_problem(mesh, C)
+    steps = syn.heartbeat_schedule()
+    t0 = time.perf_counter()
+    u_peak, _ = newton.solve_heartbeat(P, steps[:10], C["gamma_max"])
+    np.save(os.path.join(HERE, "heart4x20x64_peak.npy"), u_peak)
+    u, hists = newton.solve_heartbeat(P, steps[10:], C["gamma_max"], u0=u_peak)
+    np.save(os.path.join(HERE, "heart4x20x64.npy"), u)
+    print(f"heart4: {time.perf_counter() - t0:.1f}s", flush=True)
+
+
+CASES = {"cook64": cook64, "batch16": batch16, "twist6": twist6, "heart4": heart4}
 
 if __name__ == "__main__":
     for name in (sys.argv[1:] or list(CASES)):
