@@ -105,7 +105,12 @@ def run_solve(ctx, u, method, schedule):
     solver, prec, kw = METHODS[method]
     opts = problems.make_opts(solver, prec, **{"pc": PC["pc"], **kw})
     u.zero_()
-    reps = problems.solve_schedule(ctx, u, solver, opts, schedule)
+
+    def progress(rep):
+        print(f"[bench]   {method} tau={rep['load_scale']:g}: {rep['status_name']} "
+              f"nit={rep['nit']} lit={rep['lit_total']}", file=sys.stderr, flush=True)
+
+    reps = problems.solve_schedule(ctx, u, solver, opts, schedule, progress=progress)
     return problems.schedule_ok(reps, schedule), reps
 
 

@@ -72,6 +72,25 @@ typedef int32_t nle_status;
 #define NLE_MAT_M2 2
 #define NLE_MAT_M3 3
 #define NLE_MAT_M4 4
+/* M5 the twist test's polyconvex law (Sec. 4), on mixed meshes, params
+ * (alpha_p, beta_p, alpha_s, beta_s), printed values all 9000:
+ *      Psi = alpha_p (F:F - 3) + beta_p (cof F : cof F - 3)
+ *            - (4 beta_s + 2 alpha_s) ln J - p (J - 1),   cof F = J F^-T,
+ *    the printed "log(F)" read as ln det F (the reading with a stress-free
+ *    reference when 2 alpha_p + 4 beta_p = 4 beta_s + 2 alpha_s); small-strain
+ *    limit mu = 2 (alpha_p + beta_p), lambda = 4 beta_p. */
+#define NLE_MAT_M5 5
+/* M6 the heartbeat test's Guccione law (Sec. 4), P1 meshes, params
+ * (C, b_ff, b_ss, b_nn, b_fs, b_fn, b_sn, B) (the constants are the
+ * caller's; the paper refers to Guccione's paper for them):
+ *      Psi = C/2 (exp(Q) - 1) + B/2 (J - 1) ln J + gamma sqrt(I4),
+ *      Q = b_ff E_ff^2 + b_ss E_ss^2 + b_nn E_nn^2 + b_fs (E_fs^2 + E_sf^2)
+ *          + b_fn (E_fn^2 + E_nf^2) + b_sn (E_sn^2 + E_ns^2),
+ *    E = (F^T F - I)/2 in the per-element frame {f, s, n = f x s} of
+ *    nle_set_fibre_frame; gamma from nle_set_active_tension (the active
+ *    stress gamma (F f) (x) f / |F f|).  Nodal block Jacobi is not offered
+ *    for it. */
+#define NLE_MAT_M6 6
 
 #define NLE_NK 0   /* Newton-Krylov, fixed linear tolerance (App. A)        */
 #define NLE_INK 1  /* inexact NK, Eisenstat-Walker forcing (Sec. 3, App. A) */
@@ -162,8 +181,33 @@ typedef struct {
                          upper clip h0_rtol, the lower clip ew_rtolmin
                          (and 1e-4 in mixed precision); 0 = fixed h0_rtol.
                          The adaptive variant Sec. 3 leaves open         */
-  int32_t reserved;
+  int32_t schur;      /* displacement / pressure meshes: NLE_SCHUR_DIAG (the
+                         block-diagonal preconditioner, default), or the
+                         lower block-triangular form of App. B with GMRES,
+                         NLE_SCHUR_LOWER_MASS or NLE_SCHUR_LOWER_SIMPLE; the
+                         displacement block takes pc (JACOBI or AMG)      */
 } nle_solver_opts;
+
+/* Schur complement preconditioners of a displacement / pressure tangent
+ * [[A, B^T], [B, 0]] (App. B, eq. "schur"; Sec. 4 "Twist test"):
+ *  NLE_SCHUR_DIAG         diag(A^, S^) with S^ = M_p / mu_eff (positive:
+ *                         the lumped pressure mass over the law's
+ *                         small-strain shear modulus), symmetric positive
+ *                         definite, for MINRES or GMRES;
+ *  NLE_SCHUR_LOWER_MASS   the lower factor [[A^, 0], [B, S^]] with
+ *                         S^ = -M_p / mu_eff: z_u = A^^-1 r_u,
+ *                         z_p = S^^-1 (r_p - B z_u) (one extra Jacobian
+ *                         action per application);
+ *  NLE_SCHUR_LOWER_SIMPLE the lower factor with SIMPLE, S^ = -diag(B diag(A)^-1
+ *                         B^T) (A^-1 approximated by its diagonal, the Schur
+ *                         block then by its own diagonal); the constant-
+ *                         pressure pair only, where each row of B lives on
+ *                         one element.
+ * A^ is point Jacobi (pc = NLE_PC_JACOBI) or the multigrid cycle on the
+ * displacement block (pc = NLE_PC_AMG). */
+#define NLE_SCHUR_DIAG 0
+#define NLE_SCHUR_LOWER_MASS 1
+#define NLE_SCHUR_LOWER_SIMPLE 2
 
 /* Solve report.  Histories are written to caller buffers of hist_cap
  * entries (any may be NULL); entry k belongs to nonlinear iteration k. */
@@ -181,6 +225,10 @@ typedef struct {
   double *rnorm_hist;   /* [hist_cap] ||r_k||, k = 0..nit                   */
   double *eta_hist;     /* [hist_cap] linear relative tolerance used        */
   int32_t *lit_hist;    /* [hist_cap] Krylov iterations per step            */
+  int32_t cutbacks;     /* batched solves: halved load increments of the
+                           instance (0 for single solves, whose load stepping
+                           is the caller's)                                 */
+  int32_t reserved;
 } nle_report;
 
 /* ---- context ---------------------------------------------------------- */
@@ -214,17 +262,27 @@ nle_status nle_upload_mesh(nle_ctx *ctx, int64_t n_nodes, const double *X, int64
  * edges (0,1), (1,2), (0,2), (0,3), (1,3), (2,3); straight-sided), and
  * n_pnodes pressure nodes with pconn[n_elems][4] (the pressure at the four
  * vertices).  Host arrays, copied.  The unknown vector then has 3 n_nodes +
- * n_pnodes entries: [u (node-interleaved) | p].  Only law NLE_MAT_M3 applies:
+ * n_pnodes entries: [u (node-interleaved) | p].  Laws NLE_MAT_M3,
  *   L(u, p) = int mu/2 (I1 - 3) - mu ln J - p (J - 1)   (params = (mu)),
- * integrated by the 4-point degree-2 rule; the tangent is symmetric and
- * indefinite (use MINRES or GMRES).  The Jacobi data (nle_diag) are the
- * displacement-block diagonal and, on pressure rows, the lumped pressure mass
- * over mu, so NLE_PC_JACOBI is a block-diagonal SPD preconditioner.  Dirichlet
+ * and NLE_MAT_M5 apply, integrated by the 4-point degree-2 rule; the tangent
+ * is symmetric and indefinite (use MINRES or GMRES).  The Jacobi data
+ * (nle_diag) are the displacement-block diagonal and, on pressure rows, the
+ * lumped pressure mass over the law's small-strain shear modulus, so
+ * NLE_PC_JACOBI is a block-diagonal SPD preconditioner.  Dirichlet
  * dofs index displacement dofs.  Fibres, follower pressure, springs and body
  * forces are NLE_E_UNSUPPORTED on mixed meshes.  NLE_E_BADMESH on bad indices
  * or a non-positive vertex volume. */
 nle_status nle_upload_mesh_mixed(nle_ctx *ctx, int64_t n_nodes, const double *X, int64_t n_elems,
                                  const int32_t *conn, int64_t n_pnodes, const int32_t *pconn);
+/* The twist test's own pair (Sec. 4): quadratic displacement as in
+ * nle_upload_mesh_mixed (conn [n_elems][10]) with one pressure unknown per
+ * element (P2-P0; the pressure test function is 1 on its element,
+ * R_p[e] = -int_e (J - 1)).  The unknown vector is [u | p], p[e] for user
+ * element e, 3 n_nodes + n_elems entries.  Laws M3 and M5 apply; the Jacobi
+ * data on pressure rows are the element volume over the law's small-strain
+ * shear modulus.  Errors as nle_upload_mesh_mixed. */
+nle_status nle_upload_mesh_mixed_p0(nle_ctx *ctx, int64_t n_nodes, const double *X,
+                                    int64_t n_elems, const int32_t *conn);
 /* Material law and parameters (see NLE_MAT_*).  NLE_MAT_M4 (cardiac-like,
  * Sec. 4 "Heartbeat test" with a stated substitute for its Guccione law):
  *   Psi = a/(2b) (exp(b (J^-2/3 I1 - 3)) - 1)
@@ -249,8 +307,13 @@ nle_status nle_set_load_scale(nle_ctx *ctx, double s);
 /* Unit fibre direction per element for law M4: fib[n_elems][3] (host, user
  * element order, copied); NLE_E_INVAL unless every |f| = 1 to 1e-6. */
 nle_status nle_set_fibres(nle_ctx *ctx, const double *fib);
-/* Active tension gamma of law M4 (Sec. 4, the activation function's value at
- * the current time step; default 0). */
+/* Fibre frame per element for law M6: fib and sheet [n_elems][3] (host,
+ * user element order, copied), unit vectors to 1e-6 and orthogonal to 1e-6
+ * (NLE_E_INVAL otherwise); the third direction is n = f x s.  Also sets the
+ * fibres of law M4. */
+nle_status nle_set_fibre_frame(nle_ctx *ctx, const double *fib, const double *sheet);
+/* Active tension gamma of laws M4 and M6 (Sec. 4, the activation function's
+ * value at the current time step; default 0). */
 nle_status nle_set_active_tension(nle_ctx *ctx, double gamma);
 /* Follower pressure p (times the load scale) on n_faces triangles tri[][3]
  * whose (x1 - x0) x (x2 - x0) points out of the body: it acts on the current
@@ -386,6 +449,21 @@ nle_status nle_block_diag(nle_ctx *ctx, double *b_dev);
  * pressures), d_p the pressure entries of nle_diag: the block-diagonal
  * field split. */
 nle_status nle_pc_apply(nle_ctx *ctx, int32_t pc, int32_t prec, const void *x_dev, void *y_dev);
+/* y = M^-1 x for the lower block-triangular Schur preconditioner `schur`
+ * (NLE_SCHUR_LOWER_MASS or NLE_SCHUR_LOWER_SIMPLE, App. B) of the current
+ * linearization of a displacement / pressure mesh, with point Jacobi
+ * (pc = NLE_PC_JACOBI) or the multigrid cycle (NLE_PC_AMG) on the
+ * displacement block: y_u = A^^-1 x_u, y_p = S^^-1 (x_p - B y_u).  Vectors of
+ * the unknown length, double (NLE_FP64) or float (NLE_FP32, needs an FP32
+ * linearization), not overlapping.  Synchronises (it allocates two work
+ * vectors for the call).  NLE_E_UNSUPPORTED without a pressure field, or
+ * SIMPLE on the linear-pressure pair; NLE_E_STATE before nle_linearize. */
+nle_status nle_schur_apply(nle_ctx *ctx, int32_t pc, int32_t schur, int32_t prec,
+                           const void *x_dev, void *y_dev);
+/* The SIMPLE diagonal s_e = sum_i B_ei^2 / A_ii (over the element's free
+ * displacement dofs) of the constant-pressure pair at the current
+ * linearization: s_dev[n_elems] (double, device). */
+nle_status nle_simple_diag(nle_ctx *ctx, double *s_dev);
 /* Potential Pi(u) = sum_e V_e Psi(F_e) - s f_ext . u + u.R u / 2 with R
  * the spring matrix (synchronises).  NLE_E_UNSUPPORTED with a follower
  * pressure set. */

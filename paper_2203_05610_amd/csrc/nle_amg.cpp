@@ -746,6 +746,24 @@ nle_status amg_prepare(Ctx *c) {
 hipError_t amg_apply(Ctx *c, int prec, const void *b, void *x, double *red_dot) {
   Amg *A = state(c);
   if (!A || !A->valid) return hipErrorNotReady;
+  // the smoother's Jacobian actions are the plain tangent: a Krylov loop's
+  // epilogue (MINRES: y = J v - coef w with v.y partials) or fused CG
+  // direction must not act inside the cycle
+  struct Plain {
+    Ctx *c;
+    decltype(Ctx::ep) ep;
+    const void *cgz;
+    explicit Plain(Ctx *cc) : c(cc), ep(cc->ep), cgz(cc->cg.z) {
+      c->ep.w = nullptr;
+      c->ep.coef = nullptr;
+      c->ep.red = nullptr;
+      c->cg.z = nullptr;
+    }
+    ~Plain() {
+      c->ep = ep;
+      c->cg.z = cgz;
+    }
+  } plain(c);
   const void *res = nullptr;
   if (c->mixed && c->mx.n_p > 0) {
     // field split: the cycle on the displacements (whose Jacobian actions

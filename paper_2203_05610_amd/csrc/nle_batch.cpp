@@ -50,6 +50,7 @@ struct Batch {
   // workgroups, segments), rebuilt every round
   int32_t *d_blist = nullptr, *d_mlist = nullptr, *d_slist = nullptr;
   double *h_pin = nullptr;  // pinned host staging, 16 n_inst doubles
+  int64_t replays = 0;      // replays of captured Krylov chunks (graph launches)
 };
 
 nle_status bfail(Batch *b, nle_status s, const std::string &m) {
@@ -307,10 +308,152 @@ struct IState {
   double r0 = 0, rn = 0, rn_prev = 0, linres = 0, eta_prev = 0, eta = 0;
   int k = 0;              // Newton iterations in the current load step
   int cuts = 0;
+  int skipped = 0;        // L-BFGS pairs rejected by the curvature test
   int nit = 0;
   int64_t lit = 0, njv = 0, nres = 0;
   int status = NLE_OK;
 };
+
+// Batched CG on the instances flagged in `active`, b -> cg.x from zero with
+// the per-instance tolerances already in b->d_rtol / d_atol: chunks of
+// `chunk` iterations are captured as a graph and replayed; the launches cover
+// only the work of the instances still iterating (blocks, merge workgroups,
+// segments from per-round lists), which are rebuilt (and the graph
+// recaptured) whenever the listed blocks could halve.  its[i] receives the
+// iterations of instance i.
+nle_status batch_cg(Batch *b, const BatchCg &cg, int prec, const void *ulin, const void *bv,
+                    const std::vector<char> &active, int max_it, int chunk,
+                    std::vector<int32_t> *its_out) {
+  Ctx *c = b->c;
+  const int32_t n = b->B.n_inst;
+  const int64_t nd = 3 * c->m.n_nodes;
+  std::vector<int32_t> hact(n), hblist, hmlist, hslist;
+  for (int32_t i = 0; i < n; ++i) hact[i] = active[i] ? 1 : 0;
+  BHIP(b, hipMemcpyAsync(b->d_active, hact.data(), size_t(n) * 4, hipMemcpyHostToDevice,
+                         c->stream));
+  BHIP(b, batch_cg_start(c, b->B, cg, bv, b->d_rtol, b->d_atol, b->d_active, max_it));
+  const std::vector<int32_t> &hinst_seg = b->h_inst_seg;
+  BatchDev BL = b->B;
+  BL.seg_list = b->d_slist;
+  struct ClearLists {
+    Ctx *c;
+    ~ClearLists() {
+      c->blk_list = c->mwg_list = nullptr;
+      c->n_blist = c->n_mlist = 0;
+    }
+  } clear_lists{c};
+  auto set_lists = [&](const int32_t *done) -> hipError_t {
+    hblist.clear();
+    hmlist.clear();
+    hslist.clear();
+    for (int32_t i = 0; i < n; ++i) {
+      if (!active[i] || (done && done[i] != 0)) continue;
+      for (int32_t q = c->m.h_inst_blk[i]; q < c->m.h_inst_blk[i + 1]; ++q) hblist.push_back(q);
+      for (int32_t q = c->m.h_inst_mwg[i]; q < c->m.h_inst_mwg[i + 1]; ++q) hmlist.push_back(q);
+      for (int32_t q = hinst_seg[i]; q < hinst_seg[i + 1]; ++q) hslist.push_back(q);
+    }
+    hipError_t r = hipSuccess;
+    if (!hblist.empty())
+      r = hipMemcpyAsync(b->d_blist, hblist.data(), hblist.size() * 4, hipMemcpyHostToDevice,
+                         c->kstream);
+    if (r == hipSuccess && !hmlist.empty())
+      r = hipMemcpyAsync(b->d_mlist, hmlist.data(), hmlist.size() * 4, hipMemcpyHostToDevice,
+                         c->kstream);
+    if (r == hipSuccess && !hslist.empty())
+      r = hipMemcpyAsync(b->d_slist, hslist.data(), hslist.size() * 4, hipMemcpyHostToDevice,
+                         c->kstream);
+    BL.n_slist = int32_t(hslist.size());
+    c->blk_list = b->d_blist;
+    c->n_blist = int32_t(hblist.size());
+    c->mwg_list = b->d_mlist;
+    c->n_mlist = int32_t(hmlist.size());
+    return r;
+  };
+  auto iter = [&]() -> hipError_t {
+    hipError_t err;
+    elem_apply(c, OP_JV, prec, ulin, cg.p, cg.Ap, nullptr, &err);
+    if (err != hipSuccess) return err;
+    return batch_cg_step(c, BL, cg);
+  };
+  auto ensure_graph = [&]() -> nle_status {
+    std::vector<uint64_t> key = {7, uint64_t(prec), uint64_t(nd), uint64_t(chunk),
+                                 uint64_t(uintptr_t(c->ws)), uint64_t(uintptr_t(c->red)),
+                                 uint64_t(uintptr_t(ulin)), uint64_t(uintptr_t(cg.x)),
+                                 uint64_t(uintptr_t(c->lc_valid ? c->lc64 : nullptr)),
+                                 uint64_t(hblist.size()), uint64_t(hmlist.size()),
+                                 uint64_t(hslist.size()), uint64_t(uintptr_t(b->d_blist))};
+    if (c->gkey == key) return NLE_OK;
+    drop_graph(c);
+    c->inst_done = b->d_kdone;
+    c->ep.w = nullptr;
+    c->ep.coef = nullptr;
+    c->ep.red = cg.red_a;
+    hipError_t eb = hipStreamBeginCapture(c->kstream, hipStreamCaptureModeThreadLocal);
+    if (eb != hipSuccess) {
+      c->inst_done = nullptr;
+      c->ep.red = nullptr;
+      return bfail(b, NLE_E_HIP, "capture");
+    }
+    hipStream_t user = c->stream;
+    c->stream = c->kstream;
+    hipError_t ei = hipSuccess;
+    for (int q = 0; q < chunk && ei == hipSuccess; ++q) ei = iter();
+    c->stream = user;
+    hipGraph_t g = nullptr;
+    hipError_t ee = hipStreamEndCapture(c->kstream, &g);
+    c->inst_done = nullptr;
+    c->ep.red = nullptr;
+    if (ei != hipSuccess || ee != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return bfail(b, NLE_E_HIP, "batched CG capture");
+    }
+    hipGraphExec_t ex = nullptr;
+    if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return bfail(b, NLE_E_HIP, "batched CG instantiate");
+    }
+    c->graph = g;
+    c->gexec = ex;
+    c->gkey = key;
+    return NLE_OK;
+  };
+  BHIP(b, hipEventRecord(c->ev_a, c->stream));
+  BHIP(b, hipStreamWaitEvent(c->kstream, c->ev_a, 0));
+  BHIP(b, set_lists(nullptr));
+  {
+    const nle_status sg = ensure_graph();
+    if (sg != NLE_OK) return sg;
+  }
+  for (int done_its = 0; done_its < max_it; done_its += chunk) {
+    BHIP(b, hipGraphLaunch(c->gexec, c->kstream));
+    b->replays += 1;
+    BHIP(b, hipMemcpyAsync(b->h_pin, b->d_kdone, size_t(n) * 4, hipMemcpyDeviceToHost, c->kstream));
+    BHIP(b, hipStreamSynchronize(c->kstream));
+    const int32_t *dn = reinterpret_cast<const int32_t *>(b->h_pin);
+    bool all = true;
+    size_t left = 0;
+    for (int32_t i = 0; i < n; ++i) {
+      all &= dn[i] != 0;
+      if (active[i] && dn[i] == 0) left += size_t(c->m.h_inst_blk[i + 1] - c->m.h_inst_blk[i]);
+    }
+    if (all) break;
+    if (2 * left <= hblist.size()) {
+      std::vector<int32_t> dcopy(dn, dn + n);
+      BHIP(b, set_lists(dcopy.data()));
+      const nle_status sg = ensure_graph();
+      if (sg != NLE_OK) return sg;
+    }
+  }
+  BHIP(b, hipMemcpyAsync(b->h_pin, b->d_kits, size_t(n) * 4, hipMemcpyDeviceToHost, c->kstream));
+  BHIP(b, hipMemcpyAsync(reinterpret_cast<int32_t *>(b->h_pin) + n, b->d_kdone, size_t(n) * 4,
+                         hipMemcpyDeviceToHost, c->kstream));
+  BHIP(b, hipStreamSynchronize(c->kstream));
+  BHIP(b, hipEventRecord(c->ev_b, c->kstream));
+  BHIP(b, hipStreamWaitEvent(c->stream, c->ev_b, 0));
+  const int32_t *its = reinterpret_cast<const int32_t *>(b->h_pin);
+  its_out->assign(its, its + n);
+  return NLE_OK;
+}
 
 nle_status solve(Batch *b, int method, const nle_solver_opts &o, double *u, nle_report *reports,
                  double *t_ms) {
@@ -367,9 +510,7 @@ nle_status solve(Batch *b, int method, const nle_solver_opts &o, double *u, nle_
   NLE_HIP(c, vec_lift(c, u));
   BHIP(b, hipMemcpyAsync(ub, u, size_t(nd) * 8, hipMemcpyDeviceToDevice, c->stream));
   std::vector<double> hs(n), hcoef(n), hrtol(n), hatol(n);
-  std::vector<int32_t> hmask(n), hact(n);
-  std::vector<int32_t> hblist, hmlist, hslist;
-  const std::vector<int32_t> &hinst_seg = b->h_inst_seg;
+  std::vector<int32_t> hmask(n);
   auto upload_d = [&](double *dst, const std::vector<double> &v) {
     return hipMemcpyAsync(dst, v.data(), size_t(n) * 8, hipMemcpyHostToDevice, c->stream);
   };
@@ -486,7 +627,6 @@ nle_status solve(Batch *b, int method, const nle_solver_opts &o, double *u, nle_
     }
     if (!any_newton) continue;
     // ---- linearize (all instances; the cost is one pass) --------------------
-    for (int32_t i = 0; i < n; ++i) hact[i] = S[i].newton ? 1 : 0;
     for (int32_t i = 0; i < n; ++i) hmask[i] = S[i].newton ? 0 : 1;
     BHIP(b, upload_i(b->d_mask, hmask));
     c->inst_done = b->d_mask;
@@ -499,135 +639,13 @@ nle_status solve(Batch *b, int method, const nle_solver_opts &o, double *u, nle_
     BHIP(b, batch_scale(c, b->B, NLE_FP64, r, prec, bv, b->d_coef));
     BHIP(b, upload_d(b->d_rtol, hrtol));
     BHIP(b, upload_d(b->d_atol, hatol));
-    BHIP(b, upload_i(b->d_active, hact));
     // ---- batched CG ------------------------------------------------------------
-    BHIP(b, batch_cg_start(c, b->B, cg, bv, b->d_rtol, b->d_atol, b->d_active, o.ksp_max_it));
-    // The iterations launch only the work of the instances still iterating
-    // (blocks, merge workgroups, segments from per-round lists): instances
-    // take very different iteration counts, and the lists are rebuilt (and
-    // the chunk graph recaptured) whenever the listed blocks could halve.
-    BatchDev BL = b->B;
-    BL.seg_list = b->d_slist;
-    struct ClearLists {
-      Ctx *c;
-      ~ClearLists() {
-        c->blk_list = c->mwg_list = nullptr;
-        c->n_blist = c->n_mlist = 0;
-      }
-    } clear_lists{c};
-    auto set_lists = [&](const int32_t *done) -> hipError_t {
-      hblist.clear();
-      hmlist.clear();
-      hslist.clear();
-      for (int32_t i = 0; i < n; ++i) {
-        if (!S[i].newton || (done && done[i] != 0)) continue;
-        for (int32_t q = c->m.h_inst_blk[i]; q < c->m.h_inst_blk[i + 1]; ++q) hblist.push_back(q);
-        for (int32_t q = c->m.h_inst_mwg[i]; q < c->m.h_inst_mwg[i + 1]; ++q) hmlist.push_back(q);
-        for (int32_t q = hinst_seg[i]; q < hinst_seg[i + 1]; ++q) hslist.push_back(q);
-      }
-      hipError_t r = hipSuccess;
-      if (!hblist.empty())
-        r = hipMemcpyAsync(b->d_blist, hblist.data(), hblist.size() * 4, hipMemcpyHostToDevice,
-                           c->kstream);
-      if (r == hipSuccess && !hmlist.empty())
-        r = hipMemcpyAsync(b->d_mlist, hmlist.data(), hmlist.size() * 4, hipMemcpyHostToDevice,
-                           c->kstream);
-      if (r == hipSuccess && !hslist.empty())
-        r = hipMemcpyAsync(b->d_slist, hslist.data(), hslist.size() * 4, hipMemcpyHostToDevice,
-                           c->kstream);
-      BL.n_slist = int32_t(hslist.size());
-      c->blk_list = b->d_blist;
-      c->n_blist = int32_t(hblist.size());
-      c->mwg_list = b->d_mlist;
-      c->n_mlist = int32_t(hmlist.size());
-      return r;
-    };
-    auto iter = [&]() -> hipError_t {
-      hipError_t err;
-      elem_apply(c, OP_JV, prec, ulin, cg.p, cg.Ap, nullptr, &err);
-      if (err != hipSuccess) return err;
-      return batch_cg_step(c, BL, cg);
-    };
-    const int chunk = std::max(1, o.check_every);
-    auto ensure_graph = [&]() -> nle_status {
-      std::vector<uint64_t> key = {7, uint64_t(prec), uint64_t(nd), uint64_t(chunk),
-                                   uint64_t(uintptr_t(c->ws)), uint64_t(uintptr_t(c->red)),
-                                   uint64_t(uintptr_t(ulin)),
-                                   uint64_t(uintptr_t(c->lc_valid ? c->lc64 : nullptr)),
-                                   uint64_t(hblist.size()), uint64_t(hmlist.size()),
-                                   uint64_t(hslist.size()), uint64_t(uintptr_t(b->d_blist))};
-      if (c->gkey == key) return NLE_OK;
-      drop_graph(c);
-      c->inst_done = b->d_kdone;
-      c->ep.w = nullptr;
-      c->ep.coef = nullptr;
-      c->ep.red = cg.red_a;
-      hipError_t eb = hipStreamBeginCapture(c->kstream, hipStreamCaptureModeThreadLocal);
-      if (eb != hipSuccess) {
-        c->inst_done = nullptr;
-        c->ep.red = nullptr;
-        return bfail(b, NLE_E_HIP, "capture");
-      }
-      hipStream_t user = c->stream;
-      c->stream = c->kstream;
-      hipError_t ei = hipSuccess;
-      for (int q = 0; q < chunk && ei == hipSuccess; ++q) ei = iter();
-      c->stream = user;
-      hipGraph_t g = nullptr;
-      hipError_t ee = hipStreamEndCapture(c->kstream, &g);
-      c->inst_done = nullptr;
-      c->ep.red = nullptr;
-      if (ei != hipSuccess || ee != hipSuccess) {
-        if (g) (void)hipGraphDestroy(g);
-        return bfail(b, NLE_E_HIP, "batched CG capture");
-      }
-      hipGraphExec_t ex = nullptr;
-      if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
-        (void)hipGraphDestroy(g);
-        return bfail(b, NLE_E_HIP, "batched CG instantiate");
-      }
-      c->graph = g;
-      c->gexec = ex;
-      c->gkey = key;
-      return NLE_OK;
-    };
-    BHIP(b, hipEventRecord(c->ev_a, c->stream));
-    BHIP(b, hipStreamWaitEvent(c->kstream, c->ev_a, 0));
-    BHIP(b, set_lists(nullptr));
     {
-      const nle_status sg = ensure_graph();
-      if (sg != NLE_OK) return sg;
-    }
-    for (int done_its = 0; done_its < o.ksp_max_it; done_its += chunk) {
-      BHIP(b, hipGraphLaunch(c->gexec, c->kstream));
-      BHIP(b, hipMemcpyAsync(b->h_pin, b->d_kdone, size_t(n) * 4, hipMemcpyDeviceToHost, c->kstream));
-      BHIP(b, hipStreamSynchronize(c->kstream));
-      const int32_t *dn = reinterpret_cast<const int32_t *>(b->h_pin);
-      bool all = true;
-      size_t left = 0;
-      for (int32_t i = 0; i < n; ++i) {
-        all &= dn[i] != 0;
-        if (S[i].newton && dn[i] == 0)
-          left += size_t(c->m.h_inst_blk[i + 1] - c->m.h_inst_blk[i]);
-      }
-      if (all) break;
-      if (2 * left <= hblist.size()) {
-        std::vector<int32_t> dcopy(dn, dn + n);
-        BHIP(b, set_lists(dcopy.data()));
-        const nle_status sg = ensure_graph();
-        if (sg != NLE_OK) return sg;
-      }
-    }
-    BHIP(b, hipMemcpyAsync(b->h_pin, b->d_kits, size_t(n) * 4, hipMemcpyDeviceToHost, c->kstream));
-    BHIP(b, hipMemcpyAsync(reinterpret_cast<int32_t *>(b->h_pin) + n, b->d_kdone, size_t(n) * 4,
-                           hipMemcpyDeviceToHost, c->kstream));
-    BHIP(b, hipStreamSynchronize(c->kstream));
-    BHIP(b, hipEventRecord(c->ev_b, c->kstream));
-    BHIP(b, hipStreamWaitEvent(c->stream, c->ev_b, 0));
-    c->blk_list = c->mwg_list = nullptr;  // the steps below cover every stepping instance
-    c->n_blist = c->n_mlist = 0;
-    {
-      const int32_t *its = reinterpret_cast<const int32_t *>(b->h_pin);
+      std::vector<char> act(n);
+      for (int32_t i = 0; i < n; ++i) act[i] = S[i].newton ? 1 : 0;
+      std::vector<int32_t> its;
+      st = batch_cg(b, cg, prec, ulin, bv, act, o.ksp_max_it, std::max(1, o.check_every), &its);
+      if (st != NLE_OK) return st;
       for (int32_t i = 0; i < n; ++i)
         if (S[i].newton) {
           S[i].lit += its[i];
@@ -681,10 +699,385 @@ nle_status solve(Batch *b, int method, const nle_solver_opts &o, double *u, nle_
       R.lit_total = S[i].lit;
       R.n_jv = S[i].njv;
       R.n_residual = S[i].nres;
-      R.bfgs_skipped = S[i].cuts;  // load-step cutbacks of this instance
+      R.bfgs_skipped = S[i].skipped;
+      R.cutbacks = S[i].cuts;
       R.rnorm0 = S[i].r0;
       R.rnorm_final = S[i].rn;
       R.t_ms = ms;
+    }
+  }
+  return worst;
+}
+
+// Batched L-BFGS (Sec. 3; the single-problem solver's algorithm per
+// instance): every round evaluates the residuals of all unfinished instances,
+// takes the per-instance decisions (converged -> next load scale; diverged ->
+// restore and halve the increment; otherwise one BFGS iteration), forms the
+// new pairs (y = g - g_prev, curvature test), re-linearizes the instances
+// whose H0 is due (first iteration of a load step, or every h0_refresh
+// iterations, dropping their pairs), and runs the two-loop recursion for all
+// stepping instances at once: pairs sit in per-instance ring slots of [m+1]
+// union vectors, every dot product is reduced per instance, H0 is the point
+// Jacobi inverse (BFGS-preonly) or a batched CG solve (inexact BFGS).
+nle_status solve_bfgs(Batch *b, const nle_solver_opts &o, double *u, nle_report *reports,
+                      double *t_ms) {
+  Ctx *c = b->c;
+  const int32_t n = b->B.n_inst;
+  const int prec = o.precision == NLE_PREC_MIXED ? NLE_FP32 : NLE_FP64;
+  const size_t es = prec == NLE_FP32 ? 4 : 8;
+  const int64_t nd = 3 * c->m.n_nodes;
+  const int max_cuts = 8;
+  const int m = std::max(1, o.qn_m), ms = m + 1;  // pairs, ring slots
+  const bool ksp_h0 = o.h0 == NLE_H0_KSP;
+  // workspace: r, backup, g_prev (double); q, z, CG x r z p Ap (prec); S, Y
+  // [ms] (prec); per-instance tables
+  const size_t v64 = (size_t(nd) * 8 + 255) & ~size_t(255), vp = (size_t(nd) * es + 255) & ~size_t(255);
+  const size_t tab = (size_t(n) * (4 + 8) * size_t(3 * ms + 4) + 255) & ~size_t(255);
+  const size_t need = 3 * v64 + size_t(7 + 2 * ms) * vp + tab;
+  if (c->ws_bytes < need) {
+    drop_graph(c);
+    for (void *p : c->ws_allocs) dfree(c, p);
+    c->ws_allocs.clear();
+    c->ws = dalloc(c, need);
+    if (!c->ws) {
+      c->ws_bytes = 0;
+      return bfail(b, NLE_E_OOM, "batch workspace allocation failed");
+    }
+    c->ws_allocs.push_back(c->ws);
+    c->ws_bytes = need;
+  }
+  char *w = static_cast<char *>(c->ws);
+  double *r = reinterpret_cast<double *>(w);
+  double *ub = reinterpret_cast<double *>(w + v64);
+  double *gp = reinterpret_cast<double *>(w + 2 * v64);
+  char *wp = w + 3 * v64;
+  void *q = wp, *z = wp + vp;
+  BatchCg cg;
+  cg.prec = prec;
+  cg.x = z;
+  cg.r = wp + 2 * vp;
+  cg.z = wp + 3 * vp;
+  cg.p = wp + 4 * vp;
+  cg.Ap = wp + 5 * vp;
+  void *qs = wp + 6 * vp;  // the scaled right-hand side of the H0 solve
+  void *Sb = wp + 7 * vp, *Yb = wp + size_t(7 + ms) * vp;
+  const int64_t stride = int64_t(vp / es);
+  char *tb = wp + size_t(7 + 2 * ms) * vp;
+  int32_t *d_slot = reinterpret_cast<int32_t *>(tb);             // [ms][n] slots by age
+  double *d_rho = reinterpret_cast<double *>(tb + size_t(n) * 4 * ms);  // [ms][n]
+  double *d_alpha = d_rho + size_t(ms) * n;                       // [ms][n]
+  double *d_dot = d_alpha + size_t(ms) * n;                       // [n]
+  double *d_cf = d_dot + n;                                       // [n]
+  cg.dinv = prec == NLE_FP32 ? static_cast<const void *>(c->dinv32) : static_cast<const void *>(c->dinv64);
+  const int cap = elem_red_capacity(c);
+  cg.red_a = c->red;
+  cg.red_b = c->red + cap;
+  cg.scal = b->d_kscal;
+  cg.done = b->d_kdone;
+  cg.its = b->d_kits;
+  const void *ulin = prec == NLE_FP32 ? static_cast<const void *>(c->ulin32) : static_cast<const void *>(c->ulin64);
+
+  hipEvent_t e0, e1;
+  BHIP(b, hipEventCreate(&e0));
+  BHIP(b, hipEventCreate(&e1));
+  BHIP(b, hipEventRecord(e0, c->stream));
+  struct BState {
+    int step = 0;
+    double s_prev = 0.0, s_cur = 0.0;
+    bool need_r0 = true, finished = false, active = false;
+    double r0 = 0, rn = 0;
+    int k = 0, k_lin = 0, cuts = 0, skipped = 0, nit = 0;
+    int64_t lit = 0, njv = 0, nres = 0;
+    int status = NLE_OK;
+    int pos = 0, np = 0;     // ring: pairs in slots pos-np .. pos-1, pos free
+    bool have_prev = false;  // S[pos] holds the last step, gp its gradient
+    bool need_lin = true;
+    std::vector<double> rho;
+  };
+  std::vector<BState> S(n);
+  for (int32_t i = 0; i < n; ++i) {
+    S[i].s_cur = b->inst[i].scales.empty() ? 1.0 : b->inst[i].scales[0];
+    if (b->inst[i].scales.empty()) S[i].finished = true;
+    S[i].rho.assign(ms, 0.0);
+  }
+  NLE_HIP(c, vec_lift(c, u));
+  BHIP(b, hipMemcpyAsync(ub, u, size_t(nd) * 8, hipMemcpyDeviceToDevice, c->stream));
+  std::vector<double> hs(n), hcoef(n), hd(n), hrtol(n), hatol(n);
+  std::vector<int32_t> hmask(n), hslot(size_t(ms) * n);
+  std::vector<double> hrho(size_t(ms) * n);
+  auto upload_d = [&](double *dst, const std::vector<double> &v) {
+    return hipMemcpyAsync(dst, v.data(), v.size() * 8, hipMemcpyHostToDevice, c->stream);
+  };
+  auto upload_i = [&](int32_t *dst, const std::vector<int32_t> &v) {
+    return hipMemcpyAsync(dst, v.data(), v.size() * 4, hipMemcpyHostToDevice, c->stream);
+  };
+  // per-instance sums of segment partials (count arrays of nseg) into host
+  auto seg_sums = [&](const double *red, int count, double *host) -> nle_status {
+    for (int k = 0; k < count; ++k)
+      BHIP(b, batch_reduce_seg(c, b->B, red + size_t(k) * b->B.nseg, b->d_out + size_t(k) * n));
+    BHIP(b, hipMemcpyAsync(host, b->d_out, size_t(count) * n * 8, hipMemcpyDeviceToHost, c->stream));
+    BHIP(b, hipStreamSynchronize(c->stream));
+    return NLE_OK;
+  };
+  nle_status st = NLE_OK;
+  for (int round = 0; round < 1000000; ++round) {
+    bool any = false;
+    for (int32_t i = 0; i < n; ++i) any |= !S[i].finished;
+    if (!any) break;
+    // ---- residuals (the gradients g) of all unfinished instances -------------
+    for (int32_t i = 0; i < n; ++i) {
+      hs[i] = S[i].s_cur;
+      hmask[i] = S[i].finished ? 1 : 0;
+    }
+    BHIP(b, upload_d(c->inst_s, hs));
+    BHIP(b, upload_i(b->d_mask, hmask));
+    BHIP(b, hipMemsetAsync(c->inst_inv, 0, size_t(n) * 4, c->stream));
+    c->inst_done = b->d_mask;
+    hipError_t e;
+    elem_apply(c, OP_RES, NLE_FP64, u, nullptr, r, c->red, &e);
+    c->inst_done = nullptr;
+    if (e != hipSuccess) return bfail(b, NLE_E_HIP, "batched residual");
+    BHIP(b, batch_reduce_elem(c, b->B, c->red, b->d_out));
+    BHIP(b, hipMemcpyAsync(b->h_pin, b->d_out, size_t(n) * 8, hipMemcpyDeviceToHost, c->stream));
+    BHIP(b, hipMemcpyAsync(b->h_pin + n, c->inst_inv, size_t(n) * 4, hipMemcpyDeviceToHost, c->stream));
+    BHIP(b, hipStreamSynchronize(c->stream));
+    std::vector<double> rn2(b->h_pin, b->h_pin + n);
+    std::vector<int32_t> inv(reinterpret_cast<const int32_t *>(b->h_pin + n),
+                             reinterpret_cast<const int32_t *>(b->h_pin + n) + n);
+    // ---- the new pairs of instances that stepped last round ------------------
+    {
+      bool anyp = false;
+      for (int32_t i = 0; i < n; ++i) {
+        const bool p = !S[i].finished && S[i].have_prev && inv[i] == 0 && std::isfinite(rn2[i]);
+        hslot[i] = p ? S[i].pos : -1;
+        anyp |= p;
+      }
+      if (anyp) {
+        std::vector<int32_t> sl(hslot.begin(), hslot.begin() + n);
+        BHIP(b, upload_i(d_slot, sl));
+        BHIP(b, batch_lbfgs_pair(c, b->B, prec, Sb, Yb, stride, d_slot, r, gp, c->red));
+        std::vector<double> cur(3 * size_t(n));
+        st = seg_sums(c->red, 3, cur.data());
+        if (st != NLE_OK) return st;
+        for (int32_t i = 0; i < n; ++i) {
+          if (hslot[i] < 0) continue;
+          BState &I = S[i];
+          const double sy = cur[i], ss = cur[n + i], yy = cur[2 * n + i];
+          if (sy > o.curvature_eps * std::sqrt(ss * yy) && std::isfinite(sy)) {
+            I.rho[I.pos] = 1.0 / sy;
+            I.pos = (I.pos + 1) % ms;
+            I.np = std::min(I.np + 1, m);
+          } else {
+            I.skipped += 1;
+          }
+        }
+      }
+    }
+    // ---- per-instance decisions --------------------------------------------
+    std::vector<int32_t> restore(n, 0), save(n, 0);
+    bool any_step = false;
+    for (int32_t i = 0; i < n; ++i) {
+      BState &I = S[i];
+      I.active = false;
+      if (I.finished) continue;
+      I.nres += 1;
+      const double rn = std::sqrt(rn2[i]);
+      bool failed = inv[i] != 0 || !std::isfinite(rn);
+      if (!failed && I.need_r0) {
+        I.r0 = rn;
+        I.need_r0 = false;
+        I.k = 0;
+      }
+      const double tol = std::max(o.snes_rtol * I.r0, o.snes_atol);
+      auto reset_qn = [&]() {
+        I.np = 0;
+        I.have_prev = false;
+        I.need_lin = true;
+      };
+      if (!failed && rn <= tol) {  // load step converged
+        const std::vector<double> &sc = b->inst[i].scales;
+        save[i] = 1;
+        I.s_prev = I.s_cur;
+        I.rn = rn;
+        reset_qn();
+        while (I.step < int(sc.size()) && sc[I.step] <= I.s_cur) I.step += 1;
+        if (I.step >= int(sc.size())) {
+          I.finished = true;
+          I.status = NLE_OK;
+        } else {
+          I.s_cur = sc[I.step];
+          I.need_r0 = true;
+        }
+        continue;
+      }
+      if (!failed && I.k >= o.snes_max_it) failed = true;
+      if (failed) {
+        restore[i] = 1;
+        reset_qn();
+        if (I.cuts >= max_cuts) {
+          I.finished = true;
+          I.status = inv[i] ? NLE_DIVERGED_INVERTED
+                            : (std::isfinite(rn) ? NLE_DIVERGED_MAXIT : NLE_DIVERGED_NAN);
+          continue;
+        }
+        I.cuts += 1;
+        I.s_cur = 0.5 * (I.s_prev + I.s_cur);
+        I.need_r0 = true;
+        continue;
+      }
+      if (o.h0_refresh > 0 && I.k_lin >= o.h0_refresh) {  // periodic reassembly
+        I.need_lin = true;
+        I.np = 0;
+      }
+      I.active = true;
+      I.rn = rn;
+      any_step = true;
+    }
+    bool any_r = false, any_s = false;
+    for (int32_t i = 0; i < n; ++i) {
+      any_r |= restore[i] != 0;
+      any_s |= save[i] != 0;
+    }
+    if (any_r) {
+      BHIP(b, upload_i(b->d_mask, restore));
+      BHIP(b, batch_copy(c, b->B, ub, u, b->d_mask));
+    }
+    if (any_s) {
+      BHIP(b, upload_i(b->d_mask, save));
+      BHIP(b, batch_copy(c, b->B, u, ub, b->d_mask));
+    }
+    if (!any_step) continue;
+    // ---- H0 of the instances that need it: linearize those at u -------------
+    {
+      bool anyl = false;
+      for (int32_t i = 0; i < n; ++i) {
+        const bool l = S[i].active && S[i].need_lin;
+        hmask[i] = l ? 1 : 0;
+        anyl |= l;
+      }
+      if (anyl) {
+        BHIP(b, upload_i(b->d_mask, hmask));
+        BHIP(b, batch_copy(c, b->B, u, c->ulin64, b->d_mask));  // only their states move
+        for (int32_t i = 0; i < n; ++i) hmask[i] = hmask[i] ? 0 : 1;
+        BHIP(b, upload_i(b->d_mask, hmask));
+        c->inst_done = b->d_mask;
+        st = linearize(c, c->ulin64, prec);
+        c->inst_done = nullptr;
+        if (st != NLE_OK) return bfail(b, st, c->err);
+        for (int32_t i = 0; i < n; ++i)
+          if (S[i].active && S[i].need_lin) {
+            S[i].need_lin = false;
+            S[i].k_lin = 0;
+          }
+      }
+    }
+    // ---- two-loop recursion, all stepping instances together ----------------
+    int mmax = 0;
+    for (int32_t i = 0; i < n; ++i)
+      if (S[i].active) mmax = std::max(mmax, S[i].np);
+    for (int a = 0; a < mmax; ++a)
+      for (int32_t i = 0; i < n; ++i) {
+        const BState &I = S[i];
+        const bool has = I.active && a < I.np;
+        const int sl = has ? (I.pos - 1 - a + 2 * ms) % ms : -1;
+        hslot[size_t(a) * n + i] = sl;
+        hrho[size_t(a) * n + i] = has ? I.rho[sl] : 0.0;
+      }
+    if (mmax > 0) {
+      BHIP(b, hipMemcpyAsync(d_slot, hslot.data(), size_t(mmax) * n * 4, hipMemcpyHostToDevice,
+                             c->stream));
+      BHIP(b, hipMemcpyAsync(d_rho, hrho.data(), size_t(mmax) * n * 8, hipMemcpyHostToDevice,
+                             c->stream));
+    }
+    // q = g / ||g_i|| on the stepping instances, zero elsewhere
+    for (int32_t i = 0; i < n; ++i) hcoef[i] = S[i].active ? 1.0 / S[i].rn : 0.0;
+    BHIP(b, upload_d(b->d_coef, hcoef));
+    BHIP(b, batch_scale(c, b->B, NLE_FP64, r, prec, q, b->d_coef));
+    for (int a = 0; a < mmax; ++a) {  // newest to oldest: alpha = rho s.q, q -= alpha y
+      const int32_t *sl = d_slot + size_t(a) * n;
+      BHIP(b, batch_dot_slot(c, b->B, prec, Sb, stride, sl, q, c->red));
+      BHIP(b, batch_reduce_seg(c, b->B, c->red, d_dot));
+      BHIP(b, batch_lbfgs_coef(c, n, d_rho + size_t(a) * n, d_dot, d_alpha + size_t(a) * n, d_cf, 0));
+      BHIP(b, batch_axpy_slot(c, b->B, prec, Yb, stride, sl, prec, q, d_cf));
+    }
+    // z = H0 q
+    if (ksp_h0) {
+      for (int32_t i = 0; i < n; ++i) {
+        hrtol[i] = o.h0_rtol;
+        hatol[i] = S[i].active ? o.h0_atol / S[i].rn : 0.0;
+      }
+      BHIP(b, upload_d(b->d_rtol, hrtol));
+      BHIP(b, upload_d(b->d_atol, hatol));
+      BHIP(b, hipMemcpyAsync(qs, q, size_t(nd) * es, hipMemcpyDeviceToDevice, c->stream));
+      std::vector<char> act(n);
+      for (int32_t i = 0; i < n; ++i) act[i] = S[i].active ? 1 : 0;
+      std::vector<int32_t> its;
+      st = batch_cg(b, cg, prec, ulin, qs, act, o.ksp_max_it, std::max(1, o.check_every), &its);
+      if (st != NLE_OK) return st;
+      for (int32_t i = 0; i < n; ++i)
+        if (S[i].active) {
+          S[i].lit += its[i];
+          S[i].njv += its[i];
+        }
+    } else if (o.pc == NLE_PC_JACOBI) {
+      BHIP(b, pc_apply(c, prec, 1, cg.dinv, q, z, nd));
+    } else {
+      BHIP(b, hipMemcpyAsync(z, q, size_t(nd) * es, hipMemcpyDeviceToDevice, c->stream));
+    }
+    for (int a = mmax - 1; a >= 0; --a) {  // oldest to newest: z += (alpha - rho y.z) s
+      const int32_t *sl = d_slot + size_t(a) * n;
+      BHIP(b, batch_dot_slot(c, b->B, prec, Yb, stride, sl, z, c->red));
+      BHIP(b, batch_reduce_seg(c, b->B, c->red, d_dot));
+      BHIP(b, batch_lbfgs_coef(c, n, d_rho + size_t(a) * n, d_dot, d_alpha + size_t(a) * n, d_cf, 1));
+      BHIP(b, batch_axpy_slot(c, b->B, prec, Sb, stride, sl, prec, z, d_cf));
+    }
+    // ---- step p = -||g_i|| z into the free slot; u += p; g_prev = g ------------
+    {
+      std::vector<int32_t> sl(n);
+      for (int32_t i = 0; i < n; ++i) {
+        sl[i] = S[i].active ? S[i].pos : -1;
+        hcoef[i] = S[i].active ? -S[i].rn : 0.0;
+        hd[i] = S[i].active ? 1.0 : 0.0;
+        hmask[i] = S[i].active ? 1 : 0;
+      }
+      BHIP(b, upload_i(d_slot, sl));
+      BHIP(b, upload_d(b->d_coef, hcoef));
+      BHIP(b, batch_store_slot(c, b->B, prec, Sb, stride, d_slot, z, b->d_coef));
+      BHIP(b, upload_d(d_cf, hd));
+      BHIP(b, batch_axpy_slot(c, b->B, prec, Sb, stride, d_slot, NLE_FP64, u, d_cf));
+      BHIP(b, upload_i(b->d_mask, hmask));
+      BHIP(b, batch_copy(c, b->B, r, gp, b->d_mask));
+    }
+    for (int32_t i = 0; i < n; ++i)
+      if (S[i].active) {
+        S[i].have_prev = true;
+        S[i].k += 1;
+        S[i].k_lin += 1;
+        S[i].nit += 1;
+      }
+  }
+  BHIP(b, hipEventRecord(e1, c->stream));
+  BHIP(b, hipEventSynchronize(e1));
+  float ms_t = 0.f;
+  (void)hipEventElapsedTime(&ms_t, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (t_ms) *t_ms = ms_t;
+  nle_status worst = NLE_OK;
+  for (int32_t i = 0; i < n; ++i) {
+    if (S[i].status != NLE_OK) worst = S[i].status;
+    if (reports) {
+      nle_report &R = reports[i];
+      R.status = S[i].status;
+      R.nit = S[i].nit;
+      R.lit_total = S[i].lit;
+      R.n_jv = S[i].njv;
+      R.n_residual = S[i].nres;
+      R.bfgs_skipped = S[i].skipped;
+      R.cutbacks = S[i].cuts;
+      R.rnorm0 = S[i].r0;
+      R.rnorm_final = S[i].rn;
+      R.t_ms = ms_t;
     }
   }
   return worst;
@@ -832,13 +1225,21 @@ nle_status nle_batch_solve(nle_batch *h, int32_t method, const nle_solver_opts *
   Batch *b = &h->b;
   if (!b->finalized) return bfail(b, NLE_E_STATE, "nle_batch_finalize first");
   if (!o || !u) return bfail(b, NLE_E_INVAL, "null argument");
-  if (method != NLE_NK && method != NLE_INK)
-    return bfail(b, NLE_E_UNSUPPORTED, "batched solves support NK and iNK");
+  if (method != NLE_NK && method != NLE_INK && method != NLE_BFGS)
+    return bfail(b, NLE_E_INVAL, "bad method");
+  if (o->precision != NLE_PREC_FP64 && o->precision != NLE_PREC_MIXED)
+    return bfail(b, NLE_E_INVAL, "bad precision");
   if (o->ksp_type != NLE_KSP_CG) return bfail(b, NLE_E_UNSUPPORTED, "batched Krylov is CG");
-  if (o->pc != NLE_PC_JACOBI) return bfail(b, NLE_E_UNSUPPORTED, "batched preconditioner is Jacobi");
+  if (o->pc != NLE_PC_JACOBI && !(method == NLE_BFGS && o->h0 == NLE_H0_PREONLY &&
+                                  o->pc == NLE_PC_NONE))
+    return bfail(b, NLE_E_UNSUPPORTED, "batched preconditioner is Jacobi");
+  if (method == NLE_BFGS && (o->qn_m < 1 || o->qn_m > 64 || o->h0_refresh < 0))
+    return bfail(b, NLE_E_INVAL, "bad BFGS memory or refresh");
+  if (o->ksp_max_it < 1 || o->snes_max_it < 0) return bfail(b, NLE_E_INVAL, "bad iteration limits");
   if (hipSetDevice(b->c->device) != hipSuccess) return bfail(b, NLE_E_HIP, "hipSetDevice");
   try {
-    nle_status s = solve(b, method, *o, u, reports, t_ms);
+    nle_status s = method == NLE_BFGS ? solve_bfgs(b, *o, u, reports, t_ms)
+                                      : solve(b, method, *o, u, reports, t_ms);
     b->c->inst_done = nullptr;
     b->c->ep.red = nullptr;
     return s;

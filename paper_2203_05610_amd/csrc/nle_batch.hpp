@@ -45,5 +45,17 @@ hipError_t batch_cg_start(Ctx *c, const BatchDev &B, const BatchCg &a, const voi
                           const double *rtol, const double *atol, const int32_t *active,
                           int max_it);
 hipError_t batch_cg_step(Ctx *c, const BatchDev &B, const BatchCg &a);
+// batched L-BFGS (pairs in per-instance ring slots of [m][stride] arrays)
+hipError_t batch_dot_slot(Ctx *c, const BatchDev &B, int prec, const void *base, int64_t stride,
+                          const int32_t *slot, const void *x, double *red);
+hipError_t batch_axpy_slot(Ctx *c, const BatchDev &B, int px, const void *base, int64_t stride,
+                           const int32_t *slot, int py, void *y, const double *coef);
+hipError_t batch_store_slot(Ctx *c, const BatchDev &B, int prec, void *base, int64_t stride,
+                            const int32_t *slot, const void *x, const double *coef);
+hipError_t batch_lbfgs_pair(Ctx *c, const BatchDev &B, int prec, const void *Sbase, void *Ybase,
+                            int64_t stride, const int32_t *slot, const double *g, const double *gp,
+                            double *red);
+hipError_t batch_lbfgs_coef(Ctx *c, int n, const double *rho, const double *dot, double *alpha,
+                            double *coef, int second);
 
 }  // namespace nle

@@ -107,6 +107,98 @@ __global__ __launch_bounds__(NT) void kb_sub_norm(BatchDev B, T *t, const T *b, 
   if (threadIdx.x == 0) red[s] = double(acc);
 }
 
+// ---- batched L-BFGS: pairs in per-instance ring slots ----------------------------
+// The pairs (s_j, y_j) of all instances live in [m][n] arrays; instance i's
+// pair of a given age sits in slot[i] (negative: the instance has none).
+// partials of base[slot].x per segment
+template <typename T>
+__global__ __launch_bounds__(NT) void kb_dot_slot(BatchDev B, const T *base, int64_t stride,
+                                                  const int32_t *slot, const T *x, double *red) {
+  __shared__ T sh[NT / 64];
+  const int s = blockIdx.x, i = B.seg_inst[s];
+  const int k = slot[i];
+  T acc = T(0);
+  if (k >= 0) {
+    const T *v = base + int64_t(k) * stride;
+    SEG_LOOP(B, s, d) acc += v[d] * x[d];
+  }
+  acc = block_sum_all(acc, sh);
+  if (threadIdx.x == 0) red[s] = double(acc);
+}
+
+// y += coef[i] * base[slot[i]] (nothing where slot < 0 or coef == 0)
+template <typename S, typename D>
+__global__ __launch_bounds__(NT) void kb_axpy_slot(BatchDev B, D *y, const S *base, int64_t stride,
+                                                   const int32_t *slot, const double *coef) {
+  const int s = blockIdx.x, i = B.seg_inst[s];
+  const int k = slot[i];
+  const double a = coef[i];
+  if (k < 0 || a == 0.0) return;
+  const S *v = base + int64_t(k) * stride;
+  SEG_LOOP(B, s, d) y[d] = D(double(y[d]) + a * double(v[d]));
+}
+
+// base[slot[i]] = coef[i] * x (where slot >= 0)
+template <typename T>
+__global__ __launch_bounds__(NT) void kb_store_slot(BatchDev B, T *base, int64_t stride,
+                                                    const int32_t *slot, const T *x,
+                                                    const double *coef) {
+  const int s = blockIdx.x, i = B.seg_inst[s];
+  const int k = slot[i];
+  if (k < 0) return;
+  const T a = T(coef[i]);
+  T *v = base + int64_t(k) * stride;
+  SEG_LOOP(B, s, d) v[d] = a * x[d];
+}
+
+// The new pair of each instance with slot >= 0: y = g - g_prev into
+// Ybase[slot] (rounded to T), and per-segment partials of s.y, s.s, y.y
+// (s = Sbase[slot]) at red[0, nseg), red[nseg, 2 nseg), red[2 nseg, 3 nseg).
+template <typename T>
+__global__ __launch_bounds__(NT) void kb_lbfgs_pair(BatchDev B, const T *Sbase, T *Ybase,
+                                                    int64_t stride, const int32_t *slot,
+                                                    const double *g, const double *gp,
+                                                    double *red) {
+  __shared__ T sh[NT / 64];
+  const int s = blockIdx.x, i = B.seg_inst[s];
+  const int k = slot[i];
+  T sy = T(0), ss = T(0), yy = T(0);
+  if (k >= 0) {
+    const T *sv = Sbase + int64_t(k) * stride;
+    T *yv = Ybase + int64_t(k) * stride;
+    SEG_LOOP(B, s, d) {
+      const T y = T(g[d] - gp[d]);
+      yv[d] = y;
+      const T sd = sv[d];
+      sy += sd * y;
+      ss += sd * sd;
+      yy += y * y;
+    }
+  }
+  sy = block_sum_all(sy, sh);
+  ss = block_sum_all(ss, sh);
+  yy = block_sum_all(yy, sh);
+  if (threadIdx.x == 0) {
+    red[s] = double(sy);
+    red[B.nseg + s] = double(ss);
+    red[2 * B.nseg + s] = double(yy);
+  }
+}
+
+// per instance: first loop alpha = rho dot, coef = -alpha; second loop
+// coef = alpha - rho dot (beta)
+__global__ __launch_bounds__(NT) void kb_lbfgs_coef(int n, const double *rho, const double *dot,
+                                                    double *alpha, double *coef, int second) {
+  const int i = int(blockIdx.x) * NT + int(threadIdx.x);
+  if (i >= n) return;
+  if (second)
+    coef[i] = alpha[i] - rho[i] * dot[i];
+  else {
+    alpha[i] = rho[i] * dot[i];
+    coef[i] = -alpha[i];
+  }
+}
+
 // ---- batched CG ----------------------------------------------------------------
 // scal[i*BS + k]: 0 rz, 1 rz_old, 2 tol^2, 3 r.r ; done[i], its[i]
 template <typename T>
@@ -266,6 +358,62 @@ hipError_t batch_sub_norm(Ctx *c, const BatchDev &B, int prec, void *t, const vo
     BLAUNCH(kb_sub_norm<float>, B.nseg, B, static_cast<float *>(t), static_cast<const float *>(b), red);
   else
     BLAUNCH(kb_sub_norm<double>, B.nseg, B, static_cast<double *>(t), static_cast<const double *>(b), red);
+  return hipGetLastError();
+}
+
+hipError_t batch_dot_slot(Ctx *c, const BatchDev &B, int prec, const void *base, int64_t stride,
+                          const int32_t *slot, const void *x, double *red) {
+  if (prec == NLE_FP32)
+    BLAUNCH(kb_dot_slot<float>, B.nseg, B, static_cast<const float *>(base), stride, slot,
+            static_cast<const float *>(x), red);
+  else
+    BLAUNCH(kb_dot_slot<double>, B.nseg, B, static_cast<const double *>(base), stride, slot,
+            static_cast<const double *>(x), red);
+  return hipGetLastError();
+}
+
+hipError_t batch_axpy_slot(Ctx *c, const BatchDev &B, int px, const void *base, int64_t stride,
+                           const int32_t *slot, int py, void *y, const double *coef) {
+  if (px == NLE_FP32 && py == NLE_FP64)
+    BLAUNCH((kb_axpy_slot<float, double>), B.nseg, B, static_cast<double *>(y),
+            static_cast<const float *>(base), stride, slot, coef);
+  else if (px == NLE_FP32)
+    BLAUNCH((kb_axpy_slot<float, float>), B.nseg, B, static_cast<float *>(y),
+            static_cast<const float *>(base), stride, slot, coef);
+  else if (py == NLE_FP64)
+    BLAUNCH((kb_axpy_slot<double, double>), B.nseg, B, static_cast<double *>(y),
+            static_cast<const double *>(base), stride, slot, coef);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t batch_store_slot(Ctx *c, const BatchDev &B, int prec, void *base, int64_t stride,
+                            const int32_t *slot, const void *x, const double *coef) {
+  if (prec == NLE_FP32)
+    BLAUNCH(kb_store_slot<float>, B.nseg, B, static_cast<float *>(base), stride, slot,
+            static_cast<const float *>(x), coef);
+  else
+    BLAUNCH(kb_store_slot<double>, B.nseg, B, static_cast<double *>(base), stride, slot,
+            static_cast<const double *>(x), coef);
+  return hipGetLastError();
+}
+
+hipError_t batch_lbfgs_pair(Ctx *c, const BatchDev &B, int prec, const void *Sbase, void *Ybase,
+                            int64_t stride, const int32_t *slot, const double *g, const double *gp,
+                            double *red) {
+  if (prec == NLE_FP32)
+    BLAUNCH(kb_lbfgs_pair<float>, B.nseg, B, static_cast<const float *>(Sbase),
+            static_cast<float *>(Ybase), stride, slot, g, gp, red);
+  else
+    BLAUNCH(kb_lbfgs_pair<double>, B.nseg, B, static_cast<const double *>(Sbase),
+            static_cast<double *>(Ybase), stride, slot, g, gp, red);
+  return hipGetLastError();
+}
+
+hipError_t batch_lbfgs_coef(Ctx *c, int n, const double *rho, const double *dot, double *alpha,
+                            double *coef, int second) {
+  BLAUNCH(kb_lbfgs_coef, (n + NT - 1) / NT, n, rho, dot, alpha, coef, second);
   return hipGetLastError();
 }
 

@@ -96,7 +96,8 @@ nle_status linearize(Ctx *c, const double *u, int prec) {
   NLE_HIP(c, surf_set_linear_pressure(c));
   c->lc_valid = false;
   if (!c->mixed) {  // room for the per-element tangent coefficients
-    const int nk = c->mat.kind == NLE_MAT_M1 ? 1 : (c->mat.kind == NLE_MAT_M2 ? 3 : 7);
+    const int nk = c->mat.kind == NLE_MAT_M1 ? 1
+                   : (c->mat.kind == NLE_MAT_M2 ? 3 : (c->mat.kind == NLE_MAT_M6 ? 4 : 7));
     const int64_t need = int64_t(nk) * c->m.n_elems;
     if (need > c->lc_cap) {
       drop_graph(c);
@@ -138,6 +139,8 @@ nle_status linearize(Ctx *c, const double *u, int prec) {
 // their inverses (binv64 / binv32), computed once per linearization.
 nle_status ensure_block(Ctx *c) {
   if (c->mixed) return fail(c, NLE_E_UNSUPPORTED, "nodal block Jacobi needs a P1 mesh");
+  if (c->mat.kind == NLE_MAT_M6)
+    return fail(c, NLE_E_UNSUPPORTED, "nodal block Jacobi is not offered for law M6");
   if (!c->lin64) return fail(c, NLE_E_STATE, "not linearized");
   if (c->blk_valid) return NLE_OK;
   const int64_t nn = c->m.n_nodes;
@@ -298,6 +301,8 @@ nle_status nle_upload_mesh(nle_ctx *ctx, int64_t n_nodes, const double *X, int64
     c->fib_allocs.clear();
     c->fib64 = nullptr;
     c->fib32 = nullptr;
+    c->sh64 = nullptr;
+    c->sh32 = nullptr;
     free_surface(c);
     c->surf.h_ptri.clear();
     c->surf.h_rtri.clear();
@@ -309,10 +314,33 @@ nle_status nle_upload_mesh(nle_ctx *ctx, int64_t n_nodes, const double *X, int64
   });
 }
 
+namespace {
+nle_status upload_mixed(Ctx *c, int64_t n_nodes, const double *X, int64_t n_elems,
+                        const int32_t *conn, int64_t n_pnodes, const int32_t *pconn, int npe);
+}  // namespace
+
 nle_status nle_upload_mesh_mixed(nle_ctx *ctx, int64_t n_nodes, const double *X, int64_t n_elems,
                                  const int32_t *conn, int64_t n_pnodes, const int32_t *pconn) {
   Ctx *c = reinterpret_cast<Ctx *>(ctx);
   if (!c) return NLE_E_INVAL;
+  return upload_mixed(c, n_nodes, X, n_elems, conn, n_pnodes, pconn, 4);
+}
+
+nle_status nle_upload_mesh_mixed_p0(nle_ctx *ctx, int64_t n_nodes, const double *X,
+                                    int64_t n_elems, const int32_t *conn) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  if (!c) return NLE_E_INVAL;
+  if (n_elems <= 0 || n_elems >= (int64_t(1) << 28))
+    return fail(c, NLE_E_INVAL, "bad element count");
+  // the pressure unknown of element e is p[e]
+  std::vector<int32_t> pc(static_cast<size_t>(n_elems));
+  for (int64_t e = 0; e < n_elems; ++e) pc[size_t(e)] = int32_t(e);
+  return upload_mixed(c, n_nodes, X, n_elems, conn, n_elems, pc.data(), 1);
+}
+
+namespace {
+nle_status upload_mixed(Ctx *c, int64_t n_nodes, const double *X, int64_t n_elems,
+                        const int32_t *conn, int64_t n_pnodes, const int32_t *pconn, int npe) {
   return guarded(c, [&]() -> nle_status {
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, NLE_E_HIP, "hipSetDevice failed");
     c->has_mesh = false;
@@ -322,10 +350,12 @@ nle_status nle_upload_mesh_mixed(nle_ctx *ctx, int64_t n_nodes, const double *X,
     c->fib_allocs.clear();
     c->fib64 = nullptr;
     c->fib32 = nullptr;
+    c->sh64 = nullptr;
+    c->sh32 = nullptr;
     free_surface(c);
     c->surf.h_ptri.clear();
     c->surf.h_rtri.clear();
-    nle_status s = build_mixed_mesh(c, n_nodes, X, n_elems, conn, n_pnodes, pconn);
+    nle_status s = build_mixed_mesh(c, n_nodes, X, n_elems, conn, n_pnodes, pconn, npe);
     if (s != NLE_OK) return s;
     dfree(c, c->dir_dofs);
     dfree(c, c->dir_vals);
@@ -334,6 +364,7 @@ nle_status nle_upload_mesh_mixed(nle_ctx *ctx, int64_t n_nodes, const double *X,
     return NLE_OK;
   });
 }
+}  // namespace
 
 nle_status nle_set_material(nle_ctx *ctx, int32_t kind, const double *p, int32_t np) {
   Ctx *c = reinterpret_cast<Ctx *>(ctx);
@@ -348,6 +379,45 @@ nle_status nle_set_material(nle_ctx *ctx, int32_t kind, const double *p, int32_t
     m.lam = 0.0;
     m.cvol = 0.25;
     m.kappa = 0.0;
+    drop_graph(c);
+    c->mat = m;
+    c->has_mat = true;
+    c->lin64 = c->lin32 = c->lc_valid = false;
+    return NLE_OK;
+  } else if (kind == NLE_MAT_M5) {
+    if (np != 4) return fail(c, NLE_E_INVAL, "M5 takes (alpha_p, beta_p, alpha_s, beta_s)");
+    for (int i = 0; i < 4; ++i)
+      if (!std::isfinite(p[i]) || !(p[i] >= 0.0))
+        return fail(c, NLE_E_INVAL, "M5 needs finite non-negative constants");
+    if (!(p[0] + p[1] > 0.0)) return fail(c, NLE_E_INVAL, "M5 needs alpha_p + beta_p > 0");
+    m.kind = kind;
+    m.a_iso = p[0];                 // alpha_p
+    m.b_iso = p[1];                 // beta_p
+    m.a_f = 4.0 * p[3] + 2.0 * p[2];  // the logarithmic term's 4 beta_s + 2 alpha_s
+    m.b_f = 0.0;
+    m.mu = 2.0 * (p[0] + p[1]);     // small-strain shear modulus
+    m.lam = 4.0 * p[1];
+    m.cvol = 0.25;
+    m.kappa = 0.0;
+    drop_graph(c);
+    c->mat = m;
+    c->has_mat = true;
+    c->lin64 = c->lin32 = c->lc_valid = false;
+    return NLE_OK;
+  } else if (kind == NLE_MAT_M6) {
+    if (np != 8)
+      return fail(c, NLE_E_INVAL, "M6 takes (C, b_ff, b_ss, b_nn, b_fs, b_fn, b_sn, B)");
+    for (int i = 0; i < 8; ++i)
+      if (!std::isfinite(p[i]) || !(p[i] >= 0.0))
+        return fail(c, NLE_E_INVAL, "M6 needs finite non-negative constants");
+    if (!(p[0] > 0.0) || !(p[7] > 0.0)) return fail(c, NLE_E_INVAL, "M6 needs C > 0 and B > 0");
+    m.kind = kind;
+    for (int i = 0; i < 8; ++i) m.g6[i] = p[i];
+    m.gamma = c->mat.gamma;
+    m.mu = 0.5 * p[0] * p[1];  // a reported small-strain shear scale (C b_ff / 2)
+    m.lam = p[7];
+    m.cvol = 0.25;
+    m.kappa = p[7];
     drop_graph(c);
     c->mat = m;
     c->has_mat = true;
@@ -540,41 +610,73 @@ nle_status nle_set_load_scale(nle_ctx *ctx, double s) {
   return NLE_OK;
 }
 
-nle_status nle_set_fibres(nle_ctx *ctx, const double *fib) {
-  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+namespace {
+// Per-element unit fibres (and, when sheet is given, sheet directions
+// orthogonal to them), reordered into the element partition's order.
+nle_status set_frame(Ctx *c, const double *fib, const double *sheet) {
   nle_status s = need_mesh(c);
   if (s != NLE_OK) return s;
   if (c->mixed) return fail(c, NLE_E_UNSUPPORTED, "not available on mixed meshes");
   if (!fib) return fail(c, NLE_E_INVAL, "null fibre array");
   return guarded(c, [&]() -> nle_status {
     const int64_t ne = c->m.n_elems;
-    std::vector<double> f64(3 * ne);
-    std::vector<float> f32(3 * ne);
+    const int nv = sheet ? 2 : 1;
+    std::vector<double> f64(3 * nv * ne);
+    std::vector<float> f32(3 * nv * ne);
     for (int64_t k = 0; k < ne; ++k) {
       const int64_t e = c->m.h_perm[k];
-      const double *f = fib + 3 * e;
-      const double l2 = f[0] * f[0] + f[1] * f[1] + f[2] * f[2];
-      if (!std::isfinite(l2) || !(std::fabs(l2 - 1.0) <= 1e-6))
-        return fail(c, NLE_E_INVAL, "fibres must be finite unit vectors");
-      for (int j = 0; j < 3; ++j) {
-        f64[j * ne + k] = f[j];
-        f32[j * ne + k] = float(f[j]);
+      for (int v = 0; v < nv; ++v) {
+        const double *f = (v == 0 ? fib : sheet) + 3 * e;
+        const double l2 = f[0] * f[0] + f[1] * f[1] + f[2] * f[2];
+        if (!std::isfinite(l2) || !(std::fabs(l2 - 1.0) <= 1e-6))
+          return fail(c, NLE_E_INVAL, "fibres and sheets must be finite unit vectors");
+        for (int j = 0; j < 3; ++j) {
+          f64[(3 * v + j) * ne + k] = f[j];
+          f32[(3 * v + j) * ne + k] = float(f[j]);
+        }
+      }
+      if (sheet) {
+        const double *f = fib + 3 * e, *sh = sheet + 3 * e;
+        if (!(std::fabs(f[0] * sh[0] + f[1] * sh[1] + f[2] * sh[2]) <= 1e-6))
+          return fail(c, NLE_E_INVAL, "sheets must be orthogonal to the fibres");
       }
     }
     drop_graph(c);
     NLE_HIP(c, hipStreamSynchronize(c->stream));
     for (void *p : c->fib_allocs) dfree(c, p);
     c->fib_allocs.clear();
-    c->fib64 = static_cast<double *>(dalloc(c, size_t(3 * ne) * 8));
-    c->fib32 = static_cast<float *>(dalloc(c, size_t(3 * ne) * 4));
+    c->fib64 = static_cast<double *>(dalloc(c, f64.size() * 8));
+    c->fib32 = static_cast<float *>(dalloc(c, f32.size() * 4));
     c->fib_allocs = {c->fib64, c->fib32};
-    if (!c->fib64 || !c->fib32) return fail(c, NLE_E_OOM, "device allocation failed");
+    if (!c->fib64 || !c->fib32) {
+      c->fib64 = nullptr;
+      c->fib32 = nullptr;
+      c->sh64 = nullptr;
+      c->sh32 = nullptr;
+      return fail(c, NLE_E_OOM, "device allocation failed");
+    }
+    c->sh64 = sheet ? c->fib64 + 3 * ne : nullptr;
+    c->sh32 = sheet ? c->fib32 + 3 * ne : nullptr;
     NLE_HIP(c, hipMemcpyAsync(c->fib64, f64.data(), f64.size() * 8, hipMemcpyHostToDevice, c->stream));
     NLE_HIP(c, hipMemcpyAsync(c->fib32, f32.data(), f32.size() * 4, hipMemcpyHostToDevice, c->stream));
     NLE_HIP(c, hipStreamSynchronize(c->stream));
     c->lin64 = c->lin32 = c->lc_valid = false;
     return NLE_OK;
   });
+}
+}  // namespace
+
+nle_status nle_set_fibres(nle_ctx *ctx, const double *fib) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  if (!c) return NLE_E_INVAL;
+  return set_frame(c, fib, nullptr);
+}
+
+nle_status nle_set_fibre_frame(nle_ctx *ctx, const double *fib, const double *sheet) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  if (!c) return NLE_E_INVAL;
+  if (!sheet) return fail(c, NLE_E_INVAL, "null sheet array");
+  return set_frame(c, fib, sheet);
 }
 
 nle_status nle_set_active_tension(nle_ctx *ctx, double gamma) {
@@ -887,6 +989,57 @@ nle_status nle_pc_apply(nle_ctx *ctx, int32_t pc, int32_t prec, const void *x, v
     d = prec == NLE_FP32 ? static_cast<const void *>(c->dinv32) : static_cast<const void *>(c->dinv64);
   }
   NLE_HIP(c, pc_apply(c, prec, pcb, d, x, y, n));
+  return NLE_OK;
+}
+
+nle_status nle_schur_apply(nle_ctx *ctx, int32_t pc, int32_t schur, int32_t prec, const void *x,
+                           void *y) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  nle_status s = need_mesh(c);
+  if (s != NLE_OK) return s;
+  if (!x || !y) return fail(c, NLE_E_INVAL, "null vector");
+  if (x == y) return fail(c, NLE_E_INVAL, "the Schur preconditioner cannot run in place");
+  if (prec != NLE_FP64 && prec != NLE_FP32) return fail(c, NLE_E_INVAL, "bad precision");
+  if (pc != NLE_PC_JACOBI && pc != NLE_PC_AMG) return fail(c, NLE_E_INVAL, "bad pc");
+  if (schur != NLE_SCHUR_LOWER_MASS && schur != NLE_SCHUR_LOWER_SIMPLE)
+    return fail(c, NLE_E_INVAL, "bad schur");
+  if (!(c->mixed && c->mx.n_p > 0))
+    return fail(c, NLE_E_UNSUPPORTED, "the Schur forms need a displacement / pressure mesh");
+  if (schur == NLE_SCHUR_LOWER_SIMPLE && c->mx.npe != 1)
+    return fail(c, NLE_E_UNSUPPORTED, "SIMPLE is built for the constant-pressure pair");
+  if (!(prec == NLE_FP32 ? c->lin32 : c->lin64))
+    return fail(c, NLE_E_STATE, "nle_schur_apply needs nle_linearize at this precision first");
+  if (pc == NLE_PC_AMG) {
+    s = amg_prepare(c);
+    if (s != NLE_OK) return s;
+  }
+  if (schur == NLE_SCHUR_LOWER_SIMPLE) NLE_HIP(c, mixed_simple_diag(c));
+  const size_t vb = size_t(ndof(c)) * (prec == NLE_FP32 ? 4 : 8);
+  void *t1 = dalloc(c, vb), *t2 = dalloc(c, vb);
+  if (!t1 || !t2) {
+    dfree(c, t1);
+    dfree(c, t2);
+    return fail(c, NLE_E_OOM, "device allocation failed");
+  }
+  const hipError_t e = schur_lower_apply(c, prec, pc == NLE_PC_AMG, schur, x, y, t1, t2);
+  const hipError_t e2 = hipStreamSynchronize(c->stream);
+  dfree(c, t1);
+  dfree(c, t2);
+  if (e != hipSuccess || e2 != hipSuccess)
+    return fail(c, NLE_E_HIP, std::string("schur apply: ") +
+                                  hipGetErrorString(e != hipSuccess ? e : e2));
+  return NLE_OK;
+}
+
+nle_status nle_simple_diag(nle_ctx *ctx, double *s_dev) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  nle_status s = need_mesh(c);
+  if (s != NLE_OK) return s;
+  if (!s_dev) return fail(c, NLE_E_INVAL, "null vector");
+  if (!(c->mixed && c->mx.n_p > 0 && c->mx.npe == 1))
+    return fail(c, NLE_E_UNSUPPORTED, "SIMPLE is built for the constant-pressure pair");
+  if (!c->lin64) return fail(c, NLE_E_STATE, "nle_simple_diag needs nle_linearize first");
+  NLE_HIP(c, mixed_simple_diag(c, s_dev));
   return NLE_OK;
 }
 

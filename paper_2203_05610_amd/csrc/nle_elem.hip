@@ -47,7 +47,8 @@ struct ElemArgs {
   const double *ep_coef;
   double *ep_red;
   MatParams mp;
-  const T *fib;       // law M4: unit fibre per element, [3][n_e]
+  const T *fib;       // laws M4, M6: unit fibre per element, [3][n_e]
+  const T *sheet;     // law M6: unit sheet direction per element, [3][n_e]
   // linearization cache: per-element tangent coefficients at u_lin, [k][n_e]
   // (written by the diagonal pass, read by the Jacobian action)
   const T *lcoef;
@@ -178,6 +179,109 @@ __device__ __forceinline__ FibreKin fibre_kinematics(const T H[3][3], const T f[
   return q;
 }
 
+// Law M6 (Guccione): with R = [f s n] (n = f x s), Eb = R^T E R,
+// E = (H + H^T + H^T H) / 2, the symmetric coefficients bm, bE = bm o Eb
+// (entrywise) and Q = bE : Eb, the passive second Piola stress is
+// S = R (C e^Q bE) R^T and its derivative dS = R dSb R^T with
+// dSb = C e^Q (bm o dEb + 2 bE (bE : dEb)).
+template <typename T>
+struct Guc {
+  T R[3][3];   // columns f, s, n
+  T bE[3][3];  // bm o Eb
+  T S[3][3];   // passive second Piola stress
+  T Ce;        // C e^Q
+  double Q;
+};
+
+template <typename T>
+__device__ __forceinline__ void guccione(const T H[3][3], const T f[3], const T sh[3],
+                                         const MatParams &mp, Guc<T> &g) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    g.R[i][0] = f[i];
+    g.R[i][1] = sh[i];
+  }
+  g.R[0][2] = f[1] * sh[2] - f[2] * sh[1];
+  g.R[1][2] = f[2] * sh[0] - f[0] * sh[2];
+  g.R[2][2] = f[0] * sh[1] - f[1] * sh[0];
+  T E[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      E[i][j] = T(0.5) * (H[i][j] + H[j][i] + H[0][i] * H[0][j] + H[1][i] * H[1][j] +
+                          H[2][i] * H[2][j]);
+  T W[3][3];  // E R
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) W[i][b] = E[i][0] * g.R[0][b] + E[i][1] * g.R[1][b] + E[i][2] * g.R[2][b];
+  const double bm[3][3] = {{mp.g6[1], mp.g6[4], mp.g6[5]},
+                           {mp.g6[4], mp.g6[2], mp.g6[6]},
+                           {mp.g6[5], mp.g6[6], mp.g6[3]}};
+  double Q = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const T eb = g.R[0][a] * W[0][b] + g.R[1][a] * W[1][b] + g.R[2][a] * W[2][b];
+      g.bE[a][b] = T(bm[a][b]) * eb;
+      Q += double(g.bE[a][b]) * double(eb);
+    }
+  g.Q = Q;
+  g.Ce = T(mp.g6[0] * exp(Q));
+  T Sb[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) Sb[a][b] = g.Ce * g.bE[a][b];
+  T V[3][3];  // R Sb
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) V[i][b] = g.R[i][0] * Sb[0][b] + g.R[i][1] * Sb[1][b] + g.R[i][2] * Sb[2][b];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) g.S[i][j] = V[i][0] * g.R[j][0] + V[i][1] * g.R[j][1] + V[i][2] * g.R[j][2];
+}
+
+// dS for a symmetric strain increment dE (law M6), in the frame of g.
+template <typename T>
+__device__ __forceinline__ void guccione_dS(const Guc<T> &g, const T dE[3][3],
+                                            const MatParams &mp, T dS[3][3]) {
+  T W[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) W[i][b] = dE[i][0] * g.R[0][b] + dE[i][1] * g.R[1][b] + dE[i][2] * g.R[2][b];
+  const T bm[3][3] = {{T(mp.g6[1]), T(mp.g6[4]), T(mp.g6[5])},
+                      {T(mp.g6[4]), T(mp.g6[2]), T(mp.g6[6])},
+                      {T(mp.g6[5]), T(mp.g6[6]), T(mp.g6[3])}};
+  T deb[3][3], c = T(0);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      deb[a][b] = g.R[0][a] * W[0][b] + g.R[1][a] * W[1][b] + g.R[2][a] * W[2][b];
+      c += g.bE[a][b] * deb[a][b];
+    }
+  T dSb[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) dSb[a][b] = g.Ce * (bm[a][b] * deb[a][b] + T(2) * g.bE[a][b] * c);
+  T V[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) V[i][b] = g.R[i][0] * dSb[0][b] + g.R[i][1] * dSb[1][b] + g.R[i][2] * dSb[2][b];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) dS[i][j] = V[i][0] * g.R[j][0] + V[i][1] * g.R[j][1] + V[i][2] * g.R[j][2];
+}
+
 template <int MAT, typename T>
 __device__ __forceinline__ Coef coefficients(const Kin<T> &k, const T H[3][3], const FibreKin &fk,
                                              const MatParams &mp) {
@@ -185,6 +289,24 @@ __device__ __forceinline__ Coef coefficients(const Kin<T> &k, const T H[3][3], c
   c.cFF = 0.0;
   c.h1 = 0.0;
   c.h2 = 0.0;
+  if (MAT == NLE_MAT_M6) {
+    // B/2 (J - 1) ln J: P_vol = pT F^-T with pT = B/2 (J ln J + J - 1), whose
+    // derivative gives cT = B/2 J (ln J + 2) and cX = -pT; the passive
+    // Guccione part is added from S (guccione) and the active term gamma |F f|
+    // gives h1, h2 as in law M4
+    const double B = mp.g6[7];
+    c.a = 0.0;
+    c.cF = 0.0;
+    c.cM = 0.0;
+    c.pT = 0.5 * B * (k.J * k.lnJ + k.jm1);
+    c.cT = 0.5 * B * k.J * (k.lnJ + 2.0);
+    c.cX = -c.pT;
+    const double I4 = 1.0 + fk.e4;
+    const double rs = rsqrt(I4);
+    c.h1 = mp.gamma * rs;
+    c.h2 = -mp.gamma * rs / I4;
+    return c;
+  }
   if (MAT == NLE_MAT_M4) {
     // Psi = a/2b (exp(b (Ib1 - 3)) - 1) + af/2bf (exp(bf e4^2) - 1) [e4 > 0]
     //       + kappa/2 (J - 1)^2 + gamma sqrt(I4),  Ib1 = J^-2/3 I1, e4 = I4 - 1
@@ -261,6 +383,8 @@ __device__ __forceinline__ double energy_density(const Kin<T> &k, const T H[3][3
     for (int j = 0; j < 3; ++j) hh += double(H[i][j]) * double(H[i][j]);
   }
   const double i1m3 = 2.0 * trH + hh;
+  if (MAT == NLE_MAT_M6)  // volumetric and active parts; the passive part needs the frame
+    return 0.5 * mp.g6[7] * k.jm1 * k.lnJ + mp.gamma * sqrt(1.0 + fk.e4);
   if (MAT == NLE_MAT_M4) {
     double I1 = i1m3 + 3.0;
     const double j23m1 = expm1(-2.0 / 3.0 * k.lnJ);
@@ -322,9 +446,16 @@ __device__ __forceinline__ void finalize_node(uint32_t g, uint32_t mk, const T a
 template <typename T>
 struct ElemIn {
   uint4 lcp;   // 8 x u16: slot-local vertex ids, then contribution positions
-  T f[3];      // fibre direction (law M4)
+  T f[3];      // fibre direction (laws M4, M6)
+  T sh[3];     // sheet direction (law M6)
   uint32_t ge; // renumbered element index
 };
+
+// laws with a per-element fibre
+template <int MAT>
+__host__ __device__ constexpr bool has_fibre() {
+  return MAT == NLE_MAT_M4 || MAT == NLE_MAT_M6;
+}
 
 __device__ __forceinline__ int lo16(uint32_t w) { return int(w & 0xFFFFu); }
 __device__ __forceinline__ int hi16(uint32_t w) { return int(w >> 16); }
@@ -337,25 +468,35 @@ __device__ __forceinline__ void load_elem(const ElemArgs<T> &A, uint32_t ge, Ele
   d.lcp = A.lcp[ge];
   const uint32_t ne = uint32_t(A.n_e);
   d.ge = ge;
-  if (MAT == NLE_MAT_M4) {
+  if (has_fibre<MAT>()) {
 #pragma unroll
     for (int j = 0; j < 3; ++j) d.f[j] = A.fib[size_t(j) * ne + ge];
+  }
+  if (MAT == NLE_MAT_M6) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) d.sh[j] = A.sheet[size_t(j) * ne + ge];
   }
 }
 
 // Element force vector (12 values, vertex-major) of one element.
 // Number of cached tangent coefficients per element and law (the others
 // follow from the material constants): M1 cX; M2 a, cT, cX (cF = cM = -2a/3);
-// M4 a, cF (= cM), cFF, cT, cX, h1, h2.
+// M4 a, cF (= cM), cFF, cT, cX, h1, h2; M6 cT, cX, h1, h2 (its passive part
+// is formed from the state in the Jacobian action).
 template <int MAT>
 __host__ __device__ constexpr int n_lcoef() {
-  return MAT == NLE_MAT_M1 ? 1 : (MAT == NLE_MAT_M2 ? 3 : 7);
+  return MAT == NLE_MAT_M1 ? 1 : (MAT == NLE_MAT_M2 ? 3 : (MAT == NLE_MAT_M6 ? 4 : 7));
 }
 
 template <int MAT>
 __device__ __forceinline__ void pack_coef(const Coef &c, double q[7]) {
   if (MAT == NLE_MAT_M1) {
     q[0] = c.cX;
+  } else if (MAT == NLE_MAT_M6) {
+    q[0] = c.cT;
+    q[1] = c.cX;
+    q[2] = c.h1;
+    q[3] = c.h2;
   } else if (MAT == NLE_MAT_M2) {
     q[0] = c.a;
     q[1] = c.cT;
@@ -385,6 +526,14 @@ __device__ __forceinline__ Coef unpack_coef(const T *lc, uint32_t ne, uint32_t g
     c.cM = 0.0;
     c.cT = mp.lam;
     c.cX = double(lc[ge]);
+  } else if (MAT == NLE_MAT_M6) {
+    c.a = 0.0;
+    c.cF = 0.0;
+    c.cM = 0.0;
+    c.cT = double(lc[ge]);
+    c.cX = double(lc[size_t(ne) + ge]);
+    c.h1 = double(lc[2 * size_t(ne) + ge]);
+    c.h2 = double(lc[3 * size_t(ne) + ge]);
   } else if (MAT == NLE_MAT_M2) {
     c.a = double(lc[ge]);
     c.cT = double(lc[size_t(ne) + ge]);
@@ -498,6 +647,7 @@ __device__ __forceinline__ void element_forces(const ElemIn<T> &d, const T *uS, 
   const double V = double(Vt);
   Coef cf;
   T Ff[3], f[3];
+  Guc<T> gu;  // law M6: the passive Guccione part at this state
   if (OP == OP_JV) {
     // Jacobian action from the linearization cache (always present: the
     // diagonal pass of the linearization writes it)
@@ -514,9 +664,12 @@ __device__ __forceinline__ void element_forces(const ElemIn<T> &d, const T *uS, 
     kinematics(H, k);
     bad |= k.bad;
     FibreKin fk;
-    if (MAT == NLE_MAT_M4) fk = fibre_kinematics(H, d.f);
+    if (has_fibre<MAT>()) fk = fibre_kinematics(H, d.f);
+    if (MAT == NLE_MAT_M6 && OP != OP_ODIAG) guccione(H, d.f, d.sh, mp, gu);
     if (OP == OP_ENERGY) {
-      eacc += V * energy_density<MAT>(k, H, fk, mp);
+      double psi = energy_density<MAT>(k, H, fk, mp);
+      if (MAT == NLE_MAT_M6) psi += 0.5 * mp.g6[0] * expm1(gu.Q);
+      eacc += V * psi;
       return;
     }
     cf = coefficients<MAT>(k, H, fk, mp);
@@ -529,7 +682,7 @@ __device__ __forceinline__ void element_forces(const ElemIn<T> &d, const T *uS, 
         A.lc32[size_t(t) * size_t(A.n_e) + ge] = float(q[t]);
       }
     }
-    if (MAT == NLE_MAT_M4) {
+    if (has_fibre<MAT>()) {
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         Ff[i] = T(fk.Ff[i]);
@@ -544,7 +697,15 @@ __device__ __forceinline__ void element_forces(const ElemIn<T> &d, const T *uS, 
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j) P[i][j] = ca * k.F[i][j] + cp * k.FiT[i][j];
-    if (MAT == NLE_MAT_M4) {
+    if (MAT == NLE_MAT_M6) {  // passive part F S
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          P[i][j] += T(V) * (k.F[i][0] * gu.S[0][j] + k.F[i][1] * gu.S[1][j] +
+                             k.F[i][2] * gu.S[2][j]);
+    }
+    if (has_fibre<MAT>()) {
       const T ch = T(V * cf.h1);
 #pragma unroll
       for (int i = 0; i < 3; ++i)
@@ -646,17 +807,52 @@ __device__ __forceinline__ void element_forces(const ElemIn<T> &d, const T *uS, 
     return;
   } else {  // OP_DIAG: dF = e_i (x) g_a, one column at a time
     const double ca = V * cf.a, c1 = V * (cf.cF + cf.cM), c2 = V * (cf.cT + cf.cX);
+    // law M6, passive part: g.S g + dE : dS(dE) with dE = sym((F^T e_i) (x) g);
+    // in the frame dEb = sym(rb (x) gb), rb = R^T F^T e_i, gb = R^T g
+    T rb[3][3];  // rb[i][a] for component i
+    if (MAT == NLE_MAT_M6) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+          rb[i][b] = gu.R[0][b] * k.F[i][0] + gu.R[1][b] * k.F[i][1] + gu.R[2][b] * k.F[i][2];
+    }
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       const T gg = g[a][0] * g[a][0] + g[a][1] * g[a][1] + g[a][2] * g[a][2];
+      T gSg = T(0), gb[3] = {T(0), T(0), T(0)};
+      if (MAT == NLE_MAT_M6) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) gSg += g[a][i] * gu.S[i][j] * g[a][j];
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+          gb[b] = gu.R[0][b] * g[a][0] + gu.R[1][b] * g[a][1] + gu.R[2][b] * g[a][2];
+      }
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         const T w = k.FiT[i][0] * g[a][0] + k.FiT[i][1] * g[a][1] + k.FiT[i][2] * g[a][2];
         const T z = k.F[i][0] * g[a][0] + k.F[i][1] * g[a][1] + k.F[i][2] * g[a][2];
         T dg = T(ca) * gg + T(c1) * w * z + T(c2) * w * w;
-        if (MAT == NLE_MAT_M4) {
+        if (has_fibre<MAT>()) {
           const T gf = g[a][0] * f[0] + g[a][1] * f[1] + g[a][2] * f[2];
           dg += T(V * cf.cFF) * z * z + (T(V * cf.h1) + T(V * cf.h2) * Ff[i] * Ff[i]) * gf * gf;
+        }
+        if (MAT == NLE_MAT_M6) {
+          const T bm[3][3] = {{T(mp.g6[1]), T(mp.g6[4]), T(mp.g6[5])},
+                              {T(mp.g6[4]), T(mp.g6[2]), T(mp.g6[6])},
+                              {T(mp.g6[5]), T(mp.g6[6]), T(mp.g6[3])}};
+          T q2 = T(0), be = T(0);
+#pragma unroll
+          for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+              const T de = T(0.5) * (rb[i][p] * gb[q] + rb[i][q] * gb[p]);
+              q2 += bm[p][q] * de * de;
+              be += gu.bE[p][q] * de;
+            }
+          dg += T(V) * (gSg + gu.Ce * (q2 + T(2) * be * be));
         }
         out[a][i] = dg;
       }
@@ -668,7 +864,172 @@ __device__ __forceinline__ void element_forces(const ElemIn<T> &d, const T *uS, 
   for (int i = 0; i < 3; ++i) out[0][i] = -(out[1][i] + out[2][i] + out[3][i]);
 }
 
-template <typename T, int OP, int MAT>
+// Jacobian action of one element, 12 values (vertex-major), in the action's
+// precision from the coefficients cached at linearization.  Unnormalised
+// forms keep the instruction count down: with d_a = x_a - x_0 (a = 1..3) and
+// C the cofactor matrix of D = [d_1 d_2 d_3], grad N_a = c_a / det D (c_a
+// column a-1 of C), so H = Hh / det D, dF = dFh / det D with
+// Hh = sum_a (u_a - u_0) (x) c_a, dFh = sum_a (v_a - v_0) (x) c_a; with K =
+// cof F = J F^-T, F^-T = K / J.  The tangent form of coefficients() then
+// gives y_a = V dP grad N_a = Q c_a / (6 det D) with
+//   Q = a dFh + (cF Lh / J + cFF Fh) F + (cT Lh / J + cM Fh) K / J
+//       + cX / J^2 K dFh^T K + h1 (dFh f) (x) f + h2 ((F f).(dFh f)) (F f) (x) f,
+// Lh = K : dFh, Fh = F : dFh; y_0 = -(y_1 + y_2 + y_3).
+template <typename T, int MAT>
+__device__ __forceinline__ void element_jv(const ElemIn<T> &d, const T *uS, const T *vS,
+                                           const T *xS, int NL, const MatParams &mp,
+                                           T out[4][3], const ElemArgs<T> &A, uint32_t ge) {
+  const int la[4] = {lo16(d.lcp.x), hi16(d.lcp.x), lo16(d.lcp.y), hi16(d.lcp.y)};
+  T D[3][3], DU[3][3], DV[3][3];
+  {
+    T x0[3], u0[3], v0[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      x0[i] = xS[i * NL + la[0]];
+      u0[i] = uS[i * NL + la[0]];
+      v0[i] = vS[i * NL + la[0]];
+    }
+#pragma unroll
+    for (int a = 1; a < 4; ++a)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        D[i][a - 1] = xS[i * NL + la[a]] - x0[i];
+        DU[i][a - 1] = uS[i * NL + la[a]] - u0[i];
+        DV[i][a - 1] = vS[i * NL + la[a]] - v0[i];
+      }
+  }
+  T C[3][3];
+  C[0][0] = D[1][1] * D[2][2] - D[1][2] * D[2][1];
+  C[0][1] = D[1][2] * D[2][0] - D[1][0] * D[2][2];
+  C[0][2] = D[1][0] * D[2][1] - D[1][1] * D[2][0];
+  C[1][0] = D[0][2] * D[2][1] - D[0][1] * D[2][2];
+  C[1][1] = D[0][0] * D[2][2] - D[0][2] * D[2][0];
+  C[1][2] = D[0][1] * D[2][0] - D[0][0] * D[2][1];
+  C[2][0] = D[0][1] * D[1][2] - D[0][2] * D[1][1];
+  C[2][1] = D[0][2] * D[1][0] - D[0][0] * D[1][2];
+  C[2][2] = D[0][0] * D[1][1] - D[0][1] * D[1][0];
+  const T det = D[0][0] * C[0][0] + D[0][1] * C[0][1] + D[0][2] * C[0][2];
+  // column a-1 of C is c_a: Hh[i][j] = sum_a DU[i][a-1] C[j][a-1]
+  T F[3][3], dF[3][3];
+  T id;
+  if (sizeof(T) == 8)
+    id = T(1) / det;
+  else
+    id = T(__builtin_amdgcn_rcpf(float(det)));
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const T h = DU[i][0] * C[j][0] + DU[i][1] * C[j][1] + DU[i][2] * C[j][2];
+      F[i][j] = i == j ? h * id + T(1) : h * id;
+      dF[i][j] = DV[i][0] * C[j][0] + DV[i][1] * C[j][1] + DV[i][2] * C[j][2];
+    }
+  T K[3][3];
+  K[0][0] = F[1][1] * F[2][2] - F[1][2] * F[2][1];
+  K[0][1] = F[1][2] * F[2][0] - F[1][0] * F[2][2];
+  K[0][2] = F[1][0] * F[2][1] - F[1][1] * F[2][0];
+  K[1][0] = F[0][2] * F[2][1] - F[0][1] * F[2][2];
+  K[1][1] = F[0][0] * F[2][2] - F[0][2] * F[2][0];
+  K[1][2] = F[0][1] * F[2][0] - F[0][0] * F[2][1];
+  K[2][0] = F[0][1] * F[1][2] - F[0][2] * F[1][1];
+  K[2][1] = F[0][2] * F[1][0] - F[0][0] * F[1][2];
+  K[2][2] = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+  const T J = F[0][0] * K[0][0] + F[0][1] * K[0][1] + F[0][2] * K[0][2];
+  T iJ;
+  if (sizeof(T) == 8)
+    iJ = T(1) / J;
+  else
+    iJ = T(__builtin_amdgcn_rcpf(float(J)));
+  const Coef cf = unpack_coef<MAT>(A.lcoef, uint32_t(A.n_e), ge, mp);
+  const T s = id * T(1.0 / 6.0);  // 1 / (6 det D)
+  const T sJ = s * iJ, sJ2 = sJ * iJ;
+  const T ca = T(cf.a) * s, cX = T(cf.cX) * sJ2;
+  T Lh = T(0), Fh = T(0);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      Lh += K[i][j] * dF[i][j];
+      if (MAT != NLE_MAT_M1) Fh += F[i][j] * dF[i][j];
+    }
+  T sK = T(cf.cT) * sJ2 * Lh, sF = T(0);
+  if (MAT != NLE_MAT_M1) {
+    sK += T(cf.cM) * sJ * Fh;
+    sF = T(cf.cF) * sJ * Lh + T(cf.cFF) * s * Fh;
+  }
+  // fibre terms (M4, M6)
+  T Ff[3] = {T(0), T(0), T(0)}, dFf[3] = {T(0), T(0), T(0)}, f[3] = {T(0), T(0), T(0)};
+  T s2 = T(0);
+  if (has_fibre<MAT>()) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) f[i] = d.f[i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      Ff[i] = F[i][0] * f[0] + F[i][1] * f[1] + F[i][2] * f[2];
+      dFf[i] = dF[i][0] * f[0] + dF[i][1] * f[1] + dF[i][2] * f[2];
+    }
+    s2 = T(cf.h2) * s * (Ff[0] * dFf[0] + Ff[1] * dFf[1] + Ff[2] * dFf[2]);
+    const T c1 = T(cf.h1) * s;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) dFf[i] *= c1;
+  }
+  // M = dFh^T K, then Q = ca dFh + sK K + sF F + cX K M (+ fibre terms)
+  T M[3][3];
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      M[p][j] = dF[0][p] * K[0][j] + dF[1][p] * K[1][j] + dF[2][p] * K[2][j];
+  T Q[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const T X = K[i][0] * M[0][j] + K[i][1] * M[1][j] + K[i][2] * M[2][j];
+      T t = ca * dF[i][j] + sK * K[i][j] + cX * X;
+      if (MAT != NLE_MAT_M1) t += sF * F[i][j];
+      if (has_fibre<MAT>()) t += (dFf[i] + s2 * Ff[i]) * f[j];
+      Q[i][j] = t;
+    }
+  if (MAT == NLE_MAT_M6) {
+    // passive Guccione part, formed from the state: s (dFh S + F dS(dEh)),
+    // dEh = sym(F^T dFh)
+    T H[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) H[i][j] = F[i][j] - (i == j ? T(1) : T(0));
+    Guc<T> gu;
+    guccione(H, d.f, d.sh, mp, gu);
+    T dE[3][3], dS[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        dE[i][j] = T(0.5) * (F[0][i] * dF[0][j] + F[1][i] * dF[1][j] + F[2][i] * dF[2][j] +
+                             dF[0][i] * F[0][j] + dF[1][i] * F[1][j] + dF[2][i] * F[2][j]);
+    guccione_dS(gu, dE, mp, dS);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        Q[i][j] += s * (dF[i][0] * gu.S[0][j] + dF[i][1] * gu.S[1][j] + dF[i][2] * gu.S[2][j] +
+                        F[i][0] * dS[0][j] + F[i][1] * dS[1][j] + F[i][2] * dS[2][j]);
+  }
+#pragma unroll
+  for (int a = 1; a < 4; ++a)
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      out[a][i] = Q[i][0] * C[0][a - 1] + Q[i][1] * C[1][a - 1] + Q[i][2] * C[2][a - 1];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) out[0][i] = -(out[1][i] + out[2][i] + out[3][i]);
+}
+
+// NLC > 0: the block's slot count is at most NLC and its element count at
+// most NTB, and these compile-time strides of the LDS arrays turn every
+// gather and contribution address into one base plus immediate offsets;
+// NLC = 0 takes the strides from the mesh (nl_max, be_max) at run time.
+template <typename T, int OP, int MAT, int NLC>
 __global__ __launch_bounds__(NTB) void k_elem_block(ElemArgs<T> A) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T *lds = reinterpret_cast<T *>(lds_raw);
@@ -693,12 +1054,17 @@ __global__ __launch_bounds__(NTB) void k_elem_block(ElemArgs<T> A) {
   const int tid = threadIdx.x;
   const int e0 = A.blk_elem[b], ne = A.blk_elem[b + 1] - e0;
   const int p0 = A.blk_node[b], nl = A.blk_node[b + 1] - p0;
-  const int NL = A.nl_max, C4 = 4 * A.be_max;
+  const int NL = NLC > 0 ? NLC : A.nl_max;
+  const int BE = NLC > 0 ? NTB : A.be_max;
+  const int C4 = 4 * BE;
   T *uS = lds;                 // [3][NL]
   T *vS = lds + 3 * NL;        // [3][NL]      (Jv only)
   T *xS = lds + 6 * NL;        // [3][NL]      slot coordinates
   T *cS = lds + 9 * NL;        // [3][4 BE]    contributions in slot-sorted order
-  double *rs = reinterpret_cast<double *>(lds + 9 * NL + 12 * A.be_max);  // reduction scratch
+  // reduction scratch after the arrays, at the 8-byte aligned offset the
+  // host sizes the allocation with
+  double *rs = reinterpret_cast<double *>(
+      lds_raw + ((size_t(9 * NL + 12 * BE) * sizeof(T) + 7) & ~size_t(7)));
 
   // The inputs of this thread's first element are requested before the node
   // gather so all of these loads are in flight together.
@@ -790,7 +1156,10 @@ __global__ __launch_bounds__(NTB) void k_elem_block(ElemArgs<T> A) {
   double eacc = 0.0;
   auto run = [&](const ElemIn<T> &d) {
     T out[4][3];
-    element_forces<T, OP, MAT>(d, uS, vS, xS, NL, mp, out, bad, eacc, A, d.ge);
+    if constexpr (OP == OP_JV)
+      element_jv<T, MAT>(d, uS, vS, xS, NL, mp, out, A, d.ge);
+    else
+      element_forces<T, OP, MAT>(d, uS, vS, xS, NL, mp, out, bad, eacc, A, d.ge);
     if (OP != OP_ENERGY) {
       const int cp[4] = {lo16(d.lcp.z), hi16(d.lcp.z), lo16(d.lcp.w), hi16(d.lcp.w)};
 #pragma unroll
@@ -886,12 +1255,38 @@ __global__ __launch_bounds__(NT) void k_elem_merge(MergeArgs<T> A) {
   }
 }
 
-template <typename T, int OP, int MAT>
-void launch_block(Ctx *c, ElemArgs<T> &A, size_t lds) {
+// Compile-time LDS strides offered for the Jacobian action (slots per block).
+constexpr int NLC_BUCKETS[] = {256, 320, 384, 512};
+
+template <typename T, int OP, int MAT, int NLC>
+void launch_block_nl(Ctx *c, ElemArgs<T> &A) {
   const int nrun = A.blk_list ? A.n_list : A.nblk;
   A.per_xcd = c->xcd_remap ? (nrun + 7) / 8 : 0;
   const int grid = A.per_xcd > 0 ? 8 * A.per_xcd : nrun;
-  hipLaunchKernelGGL((k_elem_block<T, OP, MAT>), dim3(grid), dim3(NTB), lds, c->stream, A);
+  const int NL = NLC > 0 ? NLC : A.nl_max, BE = NLC > 0 ? NTB : A.be_max;
+  size_t lds = size_t(9 * NL + 12 * BE) * sizeof(T);
+  lds = (lds + 7) & ~size_t(7);
+  lds += size_t(NTB / 64) * sizeof(double);  // reduction scratch after the arrays
+  hipLaunchKernelGGL((k_elem_block<T, OP, MAT, NLC>), dim3(grid), dim3(NTB), lds, c->stream, A);
+}
+
+template <typename T, int OP, int MAT>
+void launch_block(Ctx *c, ElemArgs<T> &A) {
+  // a bucket is taken only if its LDS fits the device's per-workgroup limit
+  auto fits = [&](int nlc) {
+    return (size_t(9 * nlc + 12 * NTB) * sizeof(T) + 8 + NTB / 64 * 8) <= c->lds_limit;
+  };
+  if (OP == OP_JV && A.be_max <= NTB) {
+    if (A.nl_max <= NLC_BUCKETS[0] && fits(NLC_BUCKETS[0]))
+      return launch_block_nl<T, OP, MAT, NLC_BUCKETS[0]>(c, A);
+    if (A.nl_max <= NLC_BUCKETS[1] && fits(NLC_BUCKETS[1]))
+      return launch_block_nl<T, OP, MAT, NLC_BUCKETS[1]>(c, A);
+    if (A.nl_max <= NLC_BUCKETS[2] && fits(NLC_BUCKETS[2]))
+      return launch_block_nl<T, OP, MAT, NLC_BUCKETS[2]>(c, A);
+    if (A.nl_max <= NLC_BUCKETS[3] && fits(NLC_BUCKETS[3]))
+      return launch_block_nl<T, OP, MAT, NLC_BUCKETS[3]>(c, A);
+  }
+  launch_block_nl<T, OP, MAT, 0>(c, A);
 }
 
 template <typename T>
@@ -934,6 +1329,8 @@ int launch(Ctx *c, int op, const T *xr, const T *u, const T *v, T *out, double *
   A.mp = c->mat;
   A.fib = static_cast<const T *>(sizeof(T) == 8 ? static_cast<const void *>(c->fib64)
                                                 : static_cast<const void *>(c->fib32));
+  A.sheet = static_cast<const T *>(sizeof(T) == 8 ? static_cast<const void *>(c->sh64)
+                                                  : static_cast<const void *>(c->sh32));
   A.fs = op == OP_ENERGY ? nullptr : static_cast<T *>(fs);
   A.lcoef = nullptr;
   A.lc64 = nullptr;
@@ -961,17 +1358,16 @@ int launch(Ctx *c, int op, const T *xr, const T *u, const T *v, T *out, double *
   A.cg_np = c->cg.np;
   A.cg_scal = c->cg.scal;
   A.cg_flag = c->cg.flag;
-  size_t lds = size_t(9 * M.nl_max + 12 * M.be_max) * sizeof(T);
-  lds = (lds + 7) & ~size_t(7);
-  lds += size_t(NTB / 64) * sizeof(double);  // reduction scratch after the arrays
   const int kind = c->mat.kind;
 #define NLE_LAUNCH_BLOCK(OPV)                                             \
   if (kind == NLE_MAT_M2)                                                 \
-    launch_block<T, OPV, NLE_MAT_M2>(c, A, lds);                          \
+    launch_block<T, OPV, NLE_MAT_M2>(c, A);                               \
   else if (kind == NLE_MAT_M4)                                            \
-    launch_block<T, OPV, NLE_MAT_M4>(c, A, lds);                          \
+    launch_block<T, OPV, NLE_MAT_M4>(c, A);                               \
+  else if (kind == NLE_MAT_M6)                                            \
+    launch_block<T, OPV, NLE_MAT_M6>(c, A);                               \
   else                                                                    \
-    launch_block<T, OPV, NLE_MAT_M1>(c, A, lds);
+    launch_block<T, OPV, NLE_MAT_M1>(c, A);
   switch (op) {
     case OP_RES:
       NLE_LAUNCH_BLOCK(OP_RES);

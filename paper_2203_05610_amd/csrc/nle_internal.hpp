@@ -27,9 +27,11 @@ enum { RZ = 0, RZOLD = 1, TOL2 = 2, RR = 3, B2 = 4, MAXIT = 5, BETA = 6 };
 enum ElemOp : int { OP_RES = 0, OP_JV = 1, OP_DIAG = 2, OP_ENERGY = 3, OP_ODIAG = 4 };
 
 struct MatParams {
-  int32_t kind;   // NLE_MAT_M1 / NLE_MAT_M2 / NLE_MAT_M3 / NLE_MAT_M4
+  int32_t kind;   // NLE_MAT_M1 .. NLE_MAT_M6
   double mu, lam, cvol, kappa;
   double a_iso, b_iso, a_f, b_f, gamma;  // law M4 (kappa shared)
+  // law M6 (Guccione): C, b_ff, b_ss, b_nn, b_fs, b_fn, b_sn, B
+  double g6[8];
 };
 
 // Element partition and geometry on the device.  Elements are renumbered
@@ -71,8 +73,9 @@ struct Mesh {
 // data in user element order, node-centred gather lists.
 struct MixedMesh {
   int64_t n_u = 0, n_p = 0, n_e = 0;
+  int32_t npe = 0;            // pressure values per element: 4 (linear), 1 (constant), 0
   int32_t *conn = nullptr;    // [10][n_e] displacement nodes
-  int32_t *pconn = nullptr;   // [4][n_e] pressure nodes
+  int32_t *pconn = nullptr;   // [npe][n_e] pressure nodes
   double *G64 = nullptr;      // [9][n_e] grad lambda_1..3
   float *G32 = nullptr;
   double *V64 = nullptr;      // [n_e]
@@ -82,7 +85,11 @@ struct MixedMesh {
   uint8_t *umask = nullptr;   // [n_u] Dirichlet bits
   double *mlump = nullptr;    // [n_p] lumped pressure mass
   void *cu = nullptr;         // [n_e*10][4] element contributions (double or float)
-  void *cp = nullptr;         // [n_e*4]
+  void *cp = nullptr;         // [n_e*npe]
+  // constant pressure: the SIMPLE Schur diagonal s_e and its inverse (per
+  // linearization, computed on first use)
+  double *s64 = nullptr, *sinv64 = nullptr;
+  float *sinv32 = nullptr;
   std::vector<int32_t> h_conn;  // [n_e][10] (host, for the face loads)
 };
 
@@ -132,9 +139,12 @@ struct Ctx {
   int64_t lc_cap = 0;   // elements x coefficients allocated
   bool lc_valid = false;
 
-  // law M4: unit fibre per element, [3][n_elems] in the renumbered order
+  // laws M4, M6: unit fibre per element, [3][n_elems] in the renumbered
+  // order; law M6 also the sheet direction (n = f x s)
   double *fib64 = nullptr;
   float *fib32 = nullptr;
+  double *sh64 = nullptr;
+  float *sh32 = nullptr;
   std::vector<void *> fib_allocs;
 
   // surface loads: follower pressure (scaled by the load scale) and elastic
@@ -258,11 +268,14 @@ inline nle_status need_fibres(Ctx *c) {
   if (c->mixed && c->mx.n_p == 0) {
     if (c->mat.kind != NLE_MAT_M1)
       return fail(c, NLE_E_STATE, "quadratic displacement meshes support law M1");
-  } else if ((c->mat.kind == NLE_MAT_M3) != c->mixed) {
-    return fail(c, NLE_E_STATE, "law M3 goes with a mixed mesh, the other laws with P1 meshes");
+  } else if ((c->mat.kind == NLE_MAT_M3 || c->mat.kind == NLE_MAT_M5) != c->mixed) {
+    return fail(c, NLE_E_STATE,
+                "laws M3 and M5 go with a mixed mesh, the other laws with P1 meshes");
   }
   if (c->mat.kind == NLE_MAT_M4 && !c->fib64)
     return fail(c, NLE_E_STATE, "law M4 needs nle_set_fibres");
+  if (c->mat.kind == NLE_MAT_M6 && (!c->fib64 || !c->sh64))
+    return fail(c, NLE_E_STATE, "law M6 needs nle_set_fibre_frame");
   return NLE_OK;
 }
 void drop_graph(Ctx *c);
@@ -298,7 +311,12 @@ hipError_t surf_set_linear_pressure(Ctx *c);
 
 // ---- mixed quadratic / linear elements (nle_mixed.hip) --------------------
 nle_status build_mixed_mesh(Ctx *c, int64_t n_u, const double *X, int64_t n_e, const int32_t *conn,
-                            int64_t n_p, const int32_t *pconn);
+                            int64_t n_p, const int32_t *pconn, int npe = 4);
+// shear modulus of the mixed law's small-strain limit (pressure-mass scaling)
+double mixed_mu_eff(const Ctx *c);
+// the SIMPLE Schur diagonal of the constant-pressure pair at the current
+// linearization (into mx.s64 or s_out, inverses into mx.sinv64 / sinv32)
+hipError_t mixed_simple_diag(Ctx *c, double *s_out = nullptr);
 nle_status upload_mixed_masks(Ctx *c);
 int mixed_apply(Ctx *c, int op, int prec, const void *x, const void *v, void *out, double *red,
                 hipError_t *err);
@@ -362,6 +380,16 @@ int vec_wdiff2_partials(Ctx *c, const double *w, const double *x, const double *
 // y = M^-1 x with pcb = 1 (d: inverse diagonal, identity if null) or
 // pcb = 3 (d: nodal block inverses [6][n/3], see block_inverse)
 hipError_t pc_apply(Ctx *c, int prec, int pcb, const void *d, const void *x, void *y, int64_t n);
+// x_p = -(b_p - t_p) * sinv_p over np entries (lower Schur block)
+hipError_t schur_p(Ctx *c, int prec, const void *b, const void *t, const void *sinv, void *x,
+                   int64_t np);
+// Lower block-triangular preconditioner of a displacement / pressure tangent
+// (App. B): x_u = A^-1 b_u (point Jacobi, or the multigrid cycle when amg),
+// x_p = S^-1 (b_p - B x_u) with S = -M_p / mu_eff (schur = 1) or minus the
+// SIMPLE diagonal (schur = 2, constant pressure).  t1, t2: work vectors of
+// the unknown length.  x must not alias b.
+hipError_t schur_lower_apply(Ctx *c, int prec, bool amg, int schur, const void *b, void *x,
+                             void *t1, void *t2);
 // binv64 / binv32 from diag64 and odiag64 (nn nodes)
 hipError_t block_inverse(Ctx *c, int64_t nn);
 // odiag64 and the block inverses at the current linearization (P1 meshes)

@@ -20,6 +20,18 @@
 // and, on pressure rows, the lumped pressure mass over mu (the usual
 // spectrally equivalent stand-in for the Schur complement).
 //
+// The paper's own twist statement (Sec. 4) is the pair quadratic displacement
+// / constant pressure per element (P2-P0: the pressure test function is 1 on
+// its element, R_p[e] = -int_e (J - 1)) with the polyconvex law M5
+//   Psi = ap (I1 - 3) + bp (I2 - 3) - cs ln J - p (J - 1),  cs = 4 bs + 2 as,
+//   P = 2 ap F + 2 bp (I1 F - F C) - (cs + p J) F^-T,
+//   dP = 2 ap dF + 2 bp (2 (F:dF) F + I1 dF - dF C - F dF^T F - F F^T dF)
+//        + (cs + p J) F^-T dF^T F^-T - p J L F^-T - dp J F^-T,
+// I2 = |cof F|^2 = (I1^2 - C:C) / 2, C = F^T F; either law takes either pair.
+// Displacement-block diagonal of M5 for dof (a, i), g = grad N_a, z = F g,
+// w = F^-T g: 2 ap |g|^2 + 2 bp (z_i^2 + (I1 - (F F^T)_ii) |g|^2 - |z|^2)
+// + cs w_i^2 (the pressure terms cancel, as for M3).
+//
 // The same elements without a pressure field (second-order displacement
 // elements, Sec. 6 tables) carry the compressible law M1:
 //   P = mu F + (lam ln J - mu) F^-T,
@@ -50,16 +62,18 @@ struct MixArgs {
   const T *x, *v;
   T *cu, *cp;
   double mu, lam;
+  double ap, bp, cs;  // law M5: alpha_p, beta_p, 4 beta_s + 2 alpha_s
   double *red;
   int32_t *flag;
   const int32_t *skip;
   int32_t nomask;
 };
 
-// LAW: NLE_MAT_M3 (with the linear pressure field) or NLE_MAT_M1 (none).
-template <typename T, int OP, int LAW>
+// LAW: NLE_MAT_M3 or NLE_MAT_M5 (with a pressure field), NLE_MAT_M1 (none).
+// NPE: pressure values per element, 4 (linear) or 1 (constant).
+template <typename T, int OP, int LAW, int NPE>
 __global__ __launch_bounds__(NT) void k_mixed_elem(MixArgs<T> A) {
-  constexpr bool PRES = LAW == NLE_MAT_M3;
+  constexpr bool PRES = LAW != NLE_MAT_M1;
   __shared__ double sh[NT / 64];
   if (A.skip && A.skip[0] != 0) return;
   const int64_t e = int64_t(blockIdx.x) * NT + threadIdx.x;
@@ -72,7 +86,7 @@ __global__ __launch_bounds__(NT) void k_mixed_elem(MixArgs<T> A) {
     for (int a = 0; a < 10; ++a) cn[a] = A.conn[size_t(a) * ne + e];
     if (PRES) {
 #pragma unroll
-      for (int b = 0; b < 4; ++b) pn[b] = A.pconn[size_t(b) * ne + e];
+      for (int b = 0; b < NPE; ++b) pn[b] = A.pconn[size_t(b) * ne + e];
     }
     T g[4][3];
 #pragma unroll
@@ -94,7 +108,7 @@ __global__ __launch_bounds__(NT) void k_mixed_elem(MixArgs<T> A) {
     }
     if (PRES) {
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
+      for (int b = 0; b < NPE; ++b) {
         P4[b] = A.x[3 * A.nu + pn[b]];
         if (OP == OP_JV) WP[b] = A.v[3 * A.nu + pn[b]];
       }
@@ -112,6 +126,10 @@ __global__ __launch_bounds__(NT) void k_mixed_elem(MixArgs<T> A) {
       T lam[4];
 #pragma unroll
       for (int a = 0; a < 4; ++a) lam[a] = T(a == q ? QA : QB);
+      // pressure shape functions at the point: barycentric (linear) or 1
+      T pb[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) pb[b] = NPE == 1 ? T(b == 0 ? 1 : 0) : lam[b];
       T gN[10][3];
 #pragma unroll
       for (int a = 0; a < 4; ++a)
@@ -138,8 +156,27 @@ __global__ __launch_bounds__(NT) void k_mixed_elem(MixArgs<T> A) {
       bad |= k.bad;
       T pq = T(0);
 #pragma unroll
-      for (int b = 0; b < 4; ++b) pq += lam[b] * P4[b];
+      for (int b = 0; b < NPE; ++b) pq += pb[b] * P4[b];
       const T J = T(k.J);
+      // law M5: I1 = F:F, FC = F C = F F^T F, and the stress's F coefficient
+      T I1 = T(0), FC[3][3];
+      if (LAW == NLE_MAT_M5 && OP != OP_ENERGY) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) I1 += k.F[i][j] * k.F[i][j];
+        T B[3][3];  // F F^T
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j)
+            B[i][j] = k.F[i][0] * k.F[j][0] + k.F[i][1] * k.F[j][1] + k.F[i][2] * k.F[j][2];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j)
+            FC[i][j] = B[i][0] * k.F[0][j] + B[i][1] * k.F[1][j] + B[i][2] * k.F[2][j];
+      }
       if (OP == OP_ENERGY) {
         double trH = 0.0, hh = 0.0;
 #pragma unroll
@@ -148,19 +185,52 @@ __global__ __launch_bounds__(NT) void k_mixed_elem(MixArgs<T> A) {
 #pragma unroll
           for (int j = 0; j < 3; ++j) hh += double(H[i][j]) * double(H[i][j]);
         }
-        if (PRES)
+        if (LAW == NLE_MAT_M5) {
+          // I1 - 3 = 2 tr H + H:H; with E2 = C - I = H + H^T + H^T H,
+          // I2 - 3 = 2 tr E2 + ((tr E2)^2 - E2:E2) / 2 (no cancellation)
+          double E2[3][3];
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+              double t = double(H[i][j]) + double(H[j][i]);
+#pragma unroll
+              for (int m = 0; m < 3; ++m) t += double(H[m][i]) * double(H[m][j]);
+              E2[i][j] = t;
+            }
+          const double tE = E2[0][0] + E2[1][1] + E2[2][2];
+          double ee = 0.0;
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) ee += E2[i][j] * E2[i][j];
+          const double i2m3 = 2.0 * tE + 0.5 * (tE * tE - ee);
+          eacc += w * (A.ap * (2.0 * trH + hh) + A.bp * i2m3 - A.cs * k.lnJ -
+                       double(pq) * k.jm1);
+        } else if (PRES) {
           eacc += w * (0.5 * A.mu * (2.0 * trH + hh) - A.mu * k.lnJ - double(pq) * k.jm1);
-        else
+        } else {
           eacc += w * (0.5 * A.mu * (2.0 * trH + hh) - A.mu * k.lnJ + 0.5 * lamd * k.lnJ * k.lnJ);
+        }
         continue;
       }
       if (OP == OP_RES) {
-        const T cT = PRES ? -(mu + pq * J) : T(lamd * k.lnJ - A.mu);
         T P[3][3];
+        if (LAW == NLE_MAT_M5) {
+          const T a2 = T(2.0 * A.ap) + T(2.0 * A.bp) * I1, b2 = T(2.0 * A.bp);
+          const T cT = -(T(A.cs) + pq * J);
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
+          for (int i = 0; i < 3; ++i)
 #pragma unroll
-          for (int j = 0; j < 3; ++j) P[i][j] = T(w) * (mu * k.F[i][j] + cT * k.FiT[i][j]);
+            for (int j = 0; j < 3; ++j)
+              P[i][j] = T(w) * (a2 * k.F[i][j] - b2 * FC[i][j] + cT * k.FiT[i][j]);
+        } else {
+          const T cT = PRES ? -(mu + pq * J) : T(lamd * k.lnJ - A.mu);
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) P[i][j] = T(w) * (mu * k.F[i][j] + cT * k.FiT[i][j]);
+        }
 #pragma unroll
         for (int a = 0; a < 10; ++a)
 #pragma unroll
@@ -169,7 +239,7 @@ __global__ __launch_bounds__(NT) void k_mixed_elem(MixArgs<T> A) {
         if (PRES) {
           const T rp = -T(w * k.jm1);
 #pragma unroll
-          for (int b = 0; b < 4; ++b) cpv[b] += rp * lam[b];
+          for (int b = 0; b < NPE; ++b) cpv[b] += rp * pb[b];
         }
       } else if (OP == OP_JV) {
         T dF[3][3];
@@ -184,7 +254,7 @@ __global__ __launch_bounds__(NT) void k_mixed_elem(MixArgs<T> A) {
           }
         T dp = T(0);
 #pragma unroll
-        for (int b = 0; b < 4; ++b) dp += lam[b] * WP[b];
+        for (int b = 0; b < NPE; ++b) dp += pb[b] * WP[b];
         T L = T(0);
 #pragma unroll
         for (int i = 0; i < 3; ++i)
@@ -197,16 +267,46 @@ __global__ __launch_bounds__(NT) void k_mixed_elem(MixArgs<T> A) {
           for (int j = 0; j < 3; ++j)
             M[r][j] = dF[0][r] * k.FiT[0][j] + dF[1][r] * k.FiT[1][j] + dF[2][r] * k.FiT[2][j];
         const T pJ = pq * J;
-        const T cX = PRES ? mu + pJ : T(A.mu - lamd * k.lnJ);
+        const T cX = LAW == NLE_MAT_M5 ? T(A.cs) + pJ : (PRES ? mu + pJ : T(A.mu - lamd * k.lnJ));
         const T cT = PRES ? -(pJ * L + dp * J) : T(lamd) * L;
         T dP[3][3];
+        if (LAW == NLE_MAT_M5) {
+          // 2 bp (2 (F:dF) F + I1 dF - dF C - F dF^T F - F F^T dF)
+          T FdF = T(0);
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
+          for (int i = 0; i < 3; ++i)
 #pragma unroll
-          for (int j = 0; j < 3; ++j) {
-            const T X = k.FiT[i][0] * M[0][j] + k.FiT[i][1] * M[1][j] + k.FiT[i][2] * M[2][j];
-            dP[i][j] = T(w) * (mu * dF[i][j] + cX * X + cT * k.FiT[i][j]);
-          }
+            for (int j = 0; j < 3; ++j) FdF += k.F[i][j] * dF[i][j];
+          T Ct[3][3], G[3][3], Bt[3][3];  // C = F^T F, dF^T F, F F^T
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+              Ct[i][j] = k.F[0][i] * k.F[0][j] + k.F[1][i] * k.F[1][j] + k.F[2][i] * k.F[2][j];
+              G[i][j] = dF[0][i] * k.F[0][j] + dF[1][i] * k.F[1][j] + dF[2][i] * k.F[2][j];
+              Bt[i][j] = k.F[i][0] * k.F[j][0] + k.F[i][1] * k.F[j][1] + k.F[i][2] * k.F[j][2];
+            }
+          const T a2 = T(2.0 * A.ap) + T(2.0 * A.bp) * I1, b2 = T(2.0 * A.bp);
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+              const T X = k.FiT[i][0] * M[0][j] + k.FiT[i][1] * M[1][j] + k.FiT[i][2] * M[2][j];
+              T t = a2 * dF[i][j] + T(2) * b2 * FdF * k.F[i][j];
+#pragma unroll
+              for (int m = 0; m < 3; ++m)
+                t -= b2 * (dF[i][m] * Ct[m][j] + k.F[i][m] * G[m][j] + Bt[i][m] * dF[m][j]);
+              dP[i][j] = T(w) * (t + cX * X + cT * k.FiT[i][j]);
+            }
+        } else {
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+              const T X = k.FiT[i][0] * M[0][j] + k.FiT[i][1] * M[1][j] + k.FiT[i][2] * M[2][j];
+              dP[i][j] = T(w) * (mu * dF[i][j] + cX * X + cT * k.FiT[i][j]);
+            }
+        }
 #pragma unroll
         for (int a = 0; a < 10; ++a)
 #pragma unroll
@@ -215,7 +315,30 @@ __global__ __launch_bounds__(NT) void k_mixed_elem(MixArgs<T> A) {
         if (PRES) {
           const T rp = -T(w) * J * L;
 #pragma unroll
-          for (int b = 0; b < 4; ++b) cpv[b] += rp * lam[b];
+          for (int b = 0; b < NPE; ++b) cpv[b] += rp * pb[b];
+        }
+      } else if (LAW == NLE_MAT_M5) {  // OP_DIAG of law M5 (see the header)
+        T Bt[3][3];  // F F^T
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j)
+            Bt[i][j] = k.F[i][0] * k.F[j][0] + k.F[i][1] * k.F[j][1] + k.F[i][2] * k.F[j][2];
+        const T a2 = T(2.0 * A.ap), b2 = T(2.0 * A.bp), cs = T(A.cs);
+#pragma unroll
+        for (int a = 0; a < 10; ++a) {
+          const T gg = gN[a][0] * gN[a][0] + gN[a][1] * gN[a][1] + gN[a][2] * gN[a][2];
+          T z[3], wv[3];
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            z[i] = k.F[i][0] * gN[a][0] + k.F[i][1] * gN[a][1] + k.F[i][2] * gN[a][2];
+            wv[i] = k.FiT[i][0] * gN[a][0] + k.FiT[i][1] * gN[a][1] + k.FiT[i][2] * gN[a][2];
+          }
+          const T zz = z[0] * z[0] + z[1] * z[1] + z[2] * z[2];
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+            cu[a][i] += T(w) * (a2 * gg + b2 * (z[i] * z[i] + (I1 - Bt[i][i]) * gg - zz) +
+                                cs * wv[i] * wv[i]);
         }
       } else {  // OP_DIAG: mu |g|^2 + mu ((F^-T g)_i)^2 (pressure terms cancel);
                 // law M1: mu |g|^2 + (mu - lam ln J + lam) ((F^-T g)_i)^2
@@ -238,7 +361,7 @@ __global__ __launch_bounds__(NT) void k_mixed_elem(MixArgs<T> A) {
         for (int i = 0; i < 3; ++i) A.cu[4 * (10 * e + a) + i] = cu[a][i];
       if (PRES && OP != OP_DIAG) {
 #pragma unroll
-        for (int b = 0; b < 4; ++b) A.cp[4 * e + b] = cpv[b];
+        for (int b = 0; b < NPE; ++b) A.cp[NPE * e + b] = cpv[b];
       }
     }
   }
@@ -357,6 +480,9 @@ int launch_mixed(Ctx *c, int op, const T *G, const T *V, const T *x, const T *v,
   A.cp = static_cast<T *>(M.cp);
   A.mu = c->mat.mu;
   A.lam = c->mat.lam;
+  A.ap = c->mat.a_iso;   // law M5 keeps alpha_p, beta_p and 4 beta_s + 2 alpha_s here
+  A.bp = c->mat.b_iso;
+  A.cs = c->mat.a_f;
   A.red = red;
   A.flag = c->dflag;
   A.skip = c->elem_skip;
@@ -367,11 +493,18 @@ int launch_mixed(Ctx *c, int op, const T *G, const T *V, const T *x, const T *v,
     return 0;
   }
   const bool pres = M.n_p > 0;
-#define NLE_MIXED_ELEM(OPV)                                                             \
-  if (pres)                                                                             \
-    hipLaunchKernelGGL((k_mixed_elem<T, OPV, NLE_MAT_M3>), dim3(g1), dim3(NT), 0, c->stream, A); \
-  else                                                                                  \
-    hipLaunchKernelGGL((k_mixed_elem<T, OPV, NLE_MAT_M1>), dim3(g1), dim3(NT), 0, c->stream, A)
+  const bool m5 = c->mat.kind == NLE_MAT_M5;
+#define NLE_MIXED_ELEM(OPV)                                                                    \
+  if (!pres)                                                                                   \
+    hipLaunchKernelGGL((k_mixed_elem<T, OPV, NLE_MAT_M1, 0>), dim3(g1), dim3(NT), 0, c->stream, A); \
+  else if (M.npe == 1 && m5)                                                                   \
+    hipLaunchKernelGGL((k_mixed_elem<T, OPV, NLE_MAT_M5, 1>), dim3(g1), dim3(NT), 0, c->stream, A); \
+  else if (M.npe == 1)                                                                         \
+    hipLaunchKernelGGL((k_mixed_elem<T, OPV, NLE_MAT_M3, 1>), dim3(g1), dim3(NT), 0, c->stream, A); \
+  else if (m5)                                                                                 \
+    hipLaunchKernelGGL((k_mixed_elem<T, OPV, NLE_MAT_M5, 4>), dim3(g1), dim3(NT), 0, c->stream, A); \
+  else                                                                                         \
+    hipLaunchKernelGGL((k_mixed_elem<T, OPV, NLE_MAT_M3, 4>), dim3(g1), dim3(NT), 0, c->stream, A)
   switch (op) {
     case OP_RES:
       NLE_MIXED_ELEM(OP_RES);
@@ -405,7 +538,7 @@ int launch_mixed(Ctx *c, int op, const T *G, const T *V, const T *x, const T *v,
   B.out = out;
   B.fext = c->fext;
   B.s = c->load_scale;
-  B.mu = c->mat.mu;
+  B.mu = mixed_mu_eff(c);
   B.skip = c->elem_skip;
   B.nomask = A.nomask;
   const bool jv_ep = op == OP_JV && c->ep.red;
@@ -444,7 +577,147 @@ T *mupload(Ctx *c, const std::vector<T> &h, hipError_t *e) {
   return d;
 }
 
+// SIMPLE diagonal of the constant-pressure pair: with one pressure per
+// element, row e of the pressure-displacement block lives on element e,
+// B_e,(a,i) = -sum_q w_q J_q (F_q^-T grad N_a)_i, and
+//   s_e = sum over the element's free dofs of B_e,(a,i)^2 / A_(a,i)(a,i),
+// A's diagonal from the linearization (d = diag64, identity on Dirichlet
+// dofs).  Written as s (double) and 1/s in both precisions.
+__global__ __launch_bounds__(NT) void k_mixed_simple(int64_t ne, int64_t nu, const int32_t *conn,
+                                                     const double *G, const double *V,
+                                                     const uint8_t *umask, const double *x,
+                                                     const double *d, double *sinv64,
+                                                     float *sinv32, double *s_out) {
+  const int64_t e = int64_t(blockIdx.x) * NT + threadIdx.x;
+  if (e >= ne) return;
+  const uint32_t n = uint32_t(ne);
+  int32_t cn[10];
+#pragma unroll
+  for (int a = 0; a < 10; ++a) cn[a] = conn[size_t(a) * n + e];
+  double g[4][3];
+#pragma unroll
+  for (int a = 1; a < 4; ++a)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) g[a][j] = G[size_t(3 * (a - 1) + j) * n + e];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) g[0][j] = -(g[1][j] + g[2][j] + g[3][j]);
+  double U[10][3];
+#pragma unroll
+  for (int a = 0; a < 10; ++a)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) U[a][i] = x[3 * int64_t(cn[a]) + i];
+  const double w = V[e] * 0.25;
+  double b[10][3];
+#pragma unroll
+  for (int a = 0; a < 10; ++a)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) b[a][i] = 0.0;
+  for (int q = 0; q < 4; ++q) {
+    double lam[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) lam[a] = a == q ? QA : QB;
+    double gN[10][3];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) gN[a][j] = (4.0 * lam[a] - 1.0) * g[a][j];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const int a = EDGE_A[k], bb = EDGE_B[k];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) gN[4 + k][j] = 4.0 * (lam[bb] * g[a][j] + lam[a] * g[bb][j]);
+    }
+    double H[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        double t = 0.0;
+#pragma unroll
+        for (int a = 0; a < 10; ++a) t += U[a][i] * gN[a][j];
+        H[i][j] = t;
+      }
+    Kin<double> k;
+    kinematics(H, k);
+    const double wJ = w * k.J;
+#pragma unroll
+    for (int a = 0; a < 10; ++a)
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        b[a][i] -= wJ * (k.FiT[i][0] * gN[a][0] + k.FiT[i][1] * gN[a][1] + k.FiT[i][2] * gN[a][2]);
+  }
+  double sacc = 0.0;
+#pragma unroll
+  for (int a = 0; a < 10; ++a) {
+    const uint32_t mk = umask[cn[a]];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      if (!((mk >> i) & 1u)) sacc += b[a][i] * b[a][i] / d[3 * int64_t(cn[a]) + i];
+  }
+  s_out[e] = sacc;
+  const double inv = sacc > 0.0 ? 1.0 / sacc : 0.0;
+  sinv64[e] = inv;
+  sinv32[e] = float(inv);
+}
+
 }  // namespace
+
+double mixed_mu_eff(const Ctx *c) {
+  // the shear modulus of the law's small-strain limit, which scales the
+  // pressure mass in the Schur block: mu (M3), 2 (alpha_p + beta_p) (M5)
+  return c->mat.kind == NLE_MAT_M5 ? 2.0 * (c->mat.a_iso + c->mat.b_iso) : c->mat.mu;
+}
+
+hipError_t mixed_simple_diag(Ctx *c, double *s_out) {
+  const MixedMesh &M = c->mx;
+  if (M.npe != 1 || !M.sinv64) return hipErrorInvalidValue;
+  const int g = int((M.n_e + NT - 1) / NT);
+  hipLaunchKernelGGL(k_mixed_simple, dim3(g), dim3(NT), 0, c->stream, M.n_e, M.n_u, M.conn,
+                     M.G64, M.V64, M.umask, c->ulin64, c->diag64, M.sinv64, M.sinv32,
+                     s_out ? s_out : M.s64);
+  return hipGetLastError();
+}
+
+hipError_t schur_lower_apply(Ctx *c, int prec, bool amg, int schur, const void *b, void *x,
+                             void *t1, void *t2) {
+  const MixedMesh &M = c->mx;
+  const int64_t nu3 = 3 * M.n_u, np = M.n_p, n = nu3 + np;
+  const size_t es = prec == NLE_FP32 ? 4 : 8;
+  hipError_t e;
+  // x_u (the pressure part of x is overwritten below)
+  if (amg)
+    e = amg_apply(c, prec, b, x);
+  else
+    e = pc_apply(c, prec, 1, prec == NLE_FP32 ? static_cast<const void *>(c->dinv32)
+                                              : static_cast<const void *>(c->dinv64),
+                 b, x, n);
+  if (e != hipSuccess) return e;
+  // t2 = J [x_u; 0]: its pressure rows are B x_u
+  e = hipMemcpyAsync(t1, x, size_t(nu3) * es, hipMemcpyDeviceToDevice, c->stream);
+  if (e != hipSuccess) return e;
+  e = vec_fill(c, prec, static_cast<char *>(t1) + size_t(nu3) * es, 0.0, np);
+  if (e != hipSuccess) return e;
+  // the plain tangent (no Krylov epilogue)
+  auto ep = c->ep;
+  c->ep.w = nullptr;
+  c->ep.coef = nullptr;
+  c->ep.red = nullptr;
+  mixed_apply(c, OP_JV, prec, prec == NLE_FP32 ? static_cast<const void *>(c->ulin32)
+                                               : static_cast<const void *>(c->ulin64),
+              t1, t2, nullptr, &e);
+  c->ep = ep;
+  if (e != hipSuccess) return e;
+  const void *sinv;
+  if (schur == 2)
+    sinv = prec == NLE_FP32 ? static_cast<const void *>(M.sinv32)
+                            : static_cast<const void *>(M.sinv64);
+  else  // the pressure rows of the Jacobi data hold mu_eff / (lumped pressure mass)
+    sinv = prec == NLE_FP32 ? static_cast<const void *>(c->dinv32 + nu3)
+                            : static_cast<const void *>(c->dinv64 + nu3);
+  return schur_p(c, prec, static_cast<const char *>(b) + size_t(nu3) * es,
+                 static_cast<const char *>(t2) + size_t(nu3) * es, sinv,
+                 static_cast<char *>(x) + size_t(nu3) * es, np);
+}
 
 int mixed_red_capacity(const Ctx *c) {
   return int((c->mx.n_e + NT - 1) / NT) + int((c->mx.n_u + c->mx.n_p + NT - 1) / NT) + 8;
@@ -468,16 +741,18 @@ nle_status upload_mixed_masks(Ctx *c) {
 }
 
 nle_status build_mixed_mesh(Ctx *c, int64_t nu, const double *X, int64_t ne, const int32_t *conn,
-                            int64_t np, const int32_t *pconn) {
-  // np == 0: second-order displacement elements without a pressure field
+                            int64_t np, const int32_t *pconn, int npe) {
+  // np == 0: second-order displacement elements without a pressure field;
+  // npe: pressure values per element (4 linear, 1 constant)
   if (nu <= 0 || ne <= 0 || np < 0) return fail(c, NLE_E_INVAL, "empty mixed mesh");
+  if (npe != 4 && npe != 1) return fail(c, NLE_E_INVAL, "pressure values per element: 4 or 1");
   if (!X || !conn || (np > 0 && !pconn)) return fail(c, NLE_E_INVAL, "null mesh array");
   if (nu >= (int64_t(1) << 28) || np >= (int64_t(1) << 28) || 10 * ne >= (int64_t(1) << 31))
     return fail(c, NLE_E_UNSUPPORTED, "mixed mesh too large");
   for (int64_t k = 0; k < 10 * ne; ++k)
     if (conn[k] < 0 || conn[k] >= nu) return fail(c, NLE_E_BADMESH, "node index out of range");
   if (np > 0)
-    for (int64_t k = 0; k < 4 * ne; ++k)
+    for (int64_t k = 0; k < npe * ne; ++k)
       if (pconn[k] < 0 || pconn[k] >= np)
         return fail(c, NLE_E_BADMESH, "pressure node index out of range");
   for (int64_t i = 0; i < 3 * nu; ++i)
@@ -517,11 +792,11 @@ nle_status build_mixed_mesh(Ctx *c, int64_t nu, const double *X, int64_t ne, con
     V[e] = det / 6.0;
     V32[e] = float(V[e]);
   }
-  std::vector<int32_t> cs(10 * ne), ps(np > 0 ? 4 * ne : 0);
+  std::vector<int32_t> cs(10 * ne), ps(np > 0 ? npe * ne : 0);
   for (int64_t e = 0; e < ne; ++e) {
     for (int a = 0; a < 10; ++a) cs[size_t(a) * ne + e] = conn[10 * e + a];
     if (np > 0)
-      for (int b = 0; b < 4; ++b) ps[size_t(b) * ne + e] = pconn[4 * e + b];
+      for (int b = 0; b < npe; ++b) ps[size_t(b) * ne + e] = pconn[npe * e + b];
   }
   // node-centred entry lists (entries in increasing element order)
   auto csr = [](int64_t n, const int32_t *cn, int per, int64_t ne_, std::vector<int32_t> *ptr,
@@ -537,9 +812,9 @@ nle_status build_mixed_mesh(Ctx *c, int64_t nu, const double *X, int64_t ne, con
   csr(nu, conn, 10, ne, &uptr, &uent);
   std::vector<double> ml(np, 0.0);
   if (np > 0) {
-    csr(np, pconn, 4, ne, &pptr, &pent);
+    csr(np, pconn, npe, ne, &pptr, &pent);
     for (int64_t e = 0; e < ne; ++e)
-      for (int b = 0; b < 4; ++b) ml[pconn[4 * e + b]] += V[e] / 4.0;
+      for (int b = 0; b < npe; ++b) ml[pconn[npe * e + b]] += V[e] / npe;
   } else {
     pptr.assign(1, 0);
   }
@@ -557,6 +832,7 @@ nle_status build_mixed_mesh(Ctx *c, int64_t nu, const double *X, int64_t ne, con
   M.n_u = nu;
   M.n_p = np;
   M.n_e = ne;
+  M.npe = np > 0 ? npe : 0;
   M.h_conn.assign(conn, conn + 10 * ne);
   hipError_t herr = hipSuccess;
   M.conn = mupload(c, cs, &herr);
@@ -574,6 +850,15 @@ nle_status build_mixed_mesh(Ctx *c, int64_t nu, const double *X, int64_t ne, con
   M.umask = static_cast<uint8_t *>(dalloc(c, size_t(nu)));
   M.cu = dalloc(c, size_t(ne) * 10 * 4 * 8);
   M.cp = dalloc(c, size_t(ne) * 4 * 8);
+  if (np > 0 && npe == 1) {  // SIMPLE diagonal of the constant-pressure pair
+    M.s64 = static_cast<double *>(dalloc(c, size_t(ne) * 8));
+    M.sinv64 = static_cast<double *>(dalloc(c, size_t(ne) * 8));
+    M.sinv32 = static_cast<float *>(dalloc(c, size_t(ne) * 4));
+    for (void *p : {(void *)M.s64, (void *)M.sinv64, (void *)M.sinv32}) {
+      if (!p) herr = hipErrorOutOfMemory;
+      c->mesh_allocs.push_back(p);
+    }
+  }
   double *fext = static_cast<double *>(dalloc(c, size_t(3 * nu) * 8));
   c->fext = fext;
   c->ulin64 = static_cast<double *>(dalloc(c, size_t(n) * 8));

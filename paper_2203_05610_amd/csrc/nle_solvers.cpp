@@ -69,6 +69,7 @@ struct KspOpts {
   int type, orth, pc, restart, max_it, check_every;
   double rtol, atol;
   int cg_launches;
+  int schur = 0;  // displacement / pressure meshes: NLE_SCHUR_* (GMRES)
 };
 
 struct KspResult {
@@ -83,7 +84,7 @@ size_t ksp_bytes(const KspOpts &o, int64_t n, int prec) {
   if (o.type == NLE_KSP_CG) return 4 * v + 4096;
   if (o.type == NLE_KSP_MINRES) return 11 * v + 4096;
   const int m = o.restart > 0 ? std::min(o.restart, o.max_it) : o.max_it;
-  return size_t(m + 3) * v + size_t((m + 1) * m + 4 * m + 8) * 8 +
+  return size_t(m + 3 + (o.schur ? 2 : 0)) * v + size_t((m + 1) * m + 4 * m + 8) * 8 +
          size_t(m + 3) * VGRID_MAX * 8 + size_t(8 + 2 * (m + 1)) * 8 + 8 * 256;
 }
 
@@ -342,6 +343,19 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
   a.red = static_cast<double *>(W.take(size_t(m + 3) * VGRID_MAX * 8));
   a.scal = static_cast<double *>(W.take(size_t(8 + 2 * (m + 1)) * 8));
   a.flag = flag;
+  // the lower block-triangular (Schur) preconditioner of a displacement /
+  // pressure tangent: two more work vectors, and the SIMPLE diagonal of this
+  // linearization when asked for
+  const int schur = (c->mixed && c->mx.n_p > 0) ? o.schur : 0;
+  void *st1 = schur ? W.take(vb) : nullptr;
+  void *st2 = schur ? W.take(vb) : nullptr;
+  if (schur == NLE_SCHUR_LOWER_SIMPLE) NLE_HIP(c, mixed_simple_diag(c));
+  auto precond = [&](const void *in, void *out) -> hipError_t {
+    if (schur) return schur_lower_apply(c, prec, amg, schur, in, out, st1, st2);
+    if (amg) return amg_apply(c, prec, in, out);
+    if (dinv) return pc_apply(c, prec, pcb, dinv, in, out, n);
+    return hipMemcpyAsync(out, in, vb, hipMemcpyDeviceToDevice, c->stream);
+  };
   const int mgs = o.orth == NLE_ORTH_MGS;
   NLE_HIP(c, vec_fill(c, prec, x, 0.0, n));
   NLE_HIP(c, gmres_start(c, a, b, o.rtol, o.atol, 1));
@@ -352,13 +366,7 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
     int queued = 0;
     for (int j = 0; j < m && total + queued < o.max_it; ++j) {
       const void *vj = static_cast<const char *>(a.V) + size_t(j) * vb;
-      hipError_t e = hipSuccess;
-      if (amg)
-        e = amg_apply(c, prec, vj, a.z);
-      else if (dinv)
-        e = pc_apply(c, prec, pcb, dinv, vj, a.z, n);
-      else
-        e = hipMemcpyAsync(a.z, vj, vb, hipMemcpyDeviceToDevice, c->stream);
+      hipError_t e = precond(vj, a.z);
       if (e == hipSuccess)
         elem_apply(c, OP_JV, prec,
                    prec == NLE_FP32 ? (const void *)c->ulin32 : (const void *)c->ulin64, a.z, a.w,
@@ -390,15 +398,15 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
       }
     }
     c->elem_skip = nullptr;
-    if (amg) {
-      // x += M^-1 (V y): form V y in z, then one cycle into w
+    if (amg || schur) {
+      // x += M^-1 (V y): form V y in z, then one application into w
       GmresArgs t = a;
       t.x = a.z;
       t.dinv = nullptr;
       t.pcb = 1;
       NLE_HIP(c, vec_fill(c, prec, a.z, 0.0, n));
       NLE_HIP(c, gmres_update_x(c, t));
-      NLE_HIP(c, amg_apply(c, prec, a.z, a.w));
+      NLE_HIP(c, precond(a.z, a.w));
       NLE_HIP(c, vec_axpy(c, prec, a.w, prec, x, 1.0, nullptr, n));
     } else {
       NLE_HIP(c, gmres_update_x(c, a));
@@ -471,6 +479,8 @@ struct Report {
       r->n_jv = 0;
       r->n_residual = 0;
       r->bfgs_skipped = 0;
+      r->cutbacks = 0;
+      r->reserved = 0;
       r->rnorm0 = 0;
       r->rnorm_final = 0;
       r->t_ms = 0;
@@ -507,7 +517,20 @@ nle_status check_ready(Ctx *c, double *u, const nle_solver_opts *o) {
     return fail(c, NLE_E_INVAL, "bad cg_launches");
   if (o->h0_refresh < 0) return fail(c, NLE_E_INVAL, "bad h0_refresh");
   if (o->jac_lag < 0) return fail(c, NLE_E_INVAL, "bad jac_lag");
-  if (o->reserved != 0) return fail(c, NLE_E_INVAL, "reserved option field must be 0");
+  if (o->schur != NLE_SCHUR_DIAG && o->schur != NLE_SCHUR_LOWER_MASS &&
+      o->schur != NLE_SCHUR_LOWER_SIMPLE)
+    return fail(c, NLE_E_INVAL, "bad schur");
+  if (o->schur != NLE_SCHUR_DIAG) {
+    if (!(c->mixed && c->mx.n_p > 0))
+      return fail(c, NLE_E_UNSUPPORTED, "the Schur forms need a displacement / pressure mesh");
+    if (o->ksp_type != NLE_KSP_GMRES)
+      return fail(c, NLE_E_UNSUPPORTED, "the lower block-triangular preconditioner needs GMRES");
+    if (o->pc != NLE_PC_JACOBI && o->pc != NLE_PC_AMG)
+      return fail(c, NLE_E_UNSUPPORTED, "the Schur forms take pc JACOBI or AMG for the "
+                                        "displacement block");
+    if (o->schur == NLE_SCHUR_LOWER_SIMPLE && c->mx.npe != 1)
+      return fail(c, NLE_E_UNSUPPORTED, "SIMPLE is built for the constant-pressure pair");
+  }
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, NLE_E_HIP, "hipSetDevice failed");
   return NLE_OK;
 }
@@ -592,7 +615,7 @@ nle_status newton(Ctx *c, double *u, const nle_solver_opts &o, nle_report *repor
   const int prec = o.precision == NLE_PREC_MIXED ? NLE_FP32 : NLE_FP64;
   const int64_t n = ndof(c);
   KspOpts ko{o.ksp_type, o.orth, o.pc, o.restart, o.ksp_max_it, std::max(1, o.check_every),
-             o.ksp_rtol, o.ksp_atol, o.cg_launches};
+             o.ksp_rtol, o.ksp_atol, o.cg_launches, o.schur};
   const size_t vb64 = (size_t(n) * 8 + 255) & ~size_t(255);
   const size_t vbp = (size_t(n) * esz(prec) + 255) & ~size_t(255);
   nle_status s = ensure_ws(c, 2 * vb64 + 3 * vbp + ksp_bytes(ko, n, prec));
@@ -709,7 +732,7 @@ nle_status bfgs(Ctx *c, double *u, const nle_solver_opts &o, nle_report *report)
   const int64_t n = ndof(c);
   const int m = std::max(1, o.qn_m);
   KspOpts ko{o.ksp_type, o.orth, o.pc, o.restart, o.ksp_max_it, std::max(1, o.check_every),
-             o.h0_rtol, o.h0_atol, o.cg_launches};
+             o.h0_rtol, o.h0_atol, o.cg_launches, o.schur};
   const size_t vb64 = (size_t(n) * 8 + 255) & ~size_t(255);
   const size_t vbp = (size_t(n) * esz(prec) + 255) & ~size_t(255);
   size_t need = 3 * vb64 + size_t(2 * m + 5) * vbp + 8 * size_t(m + 8) + 4096;

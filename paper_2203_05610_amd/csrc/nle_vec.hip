@@ -854,6 +854,27 @@ hipError_t pc_apply(Ctx *c, int prec, int pcb, const void *d, const void *x, voi
   return hipGetLastError();
 }
 
+// Schur block of the lower block-triangular preconditioner: x_p =
+// -(b_p - t_p) * sinv_p (the Schur approximation -diag(1 / sinv)).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_schur_p(const T *b, const T *t, const T *sinv, T *x,
+                                                int64_t np) {
+  for (int64_t i = int64_t(blockIdx.x) * NT + threadIdx.x; i < np; i += int64_t(gridDim.x) * NT)
+    x[i] = -(b[i] - t[i]) * sinv[i];
+}
+
+hipError_t schur_p(Ctx *c, int prec, const void *b, const void *t, const void *sinv, void *x,
+                   int64_t np) {
+  const int g = vgrid(np);
+  if (prec == NLE_FP32)
+    LAUNCH(k_schur_p<float>, g, static_cast<const float *>(b), static_cast<const float *>(t),
+           static_cast<const float *>(sinv), static_cast<float *>(x), np);
+  else
+    LAUNCH(k_schur_p<double>, g, static_cast<const double *>(b), static_cast<const double *>(t),
+           static_cast<const double *>(sinv), static_cast<double *>(x), np);
+  return hipGetLastError();
+}
+
 hipError_t block_inverse(Ctx *c, int64_t nn) {
   LAUNCH(k_block_inv, vgrid(nn), c->diag64, c->odiag64, c->binv64, c->binv32, nn);
   return hipGetLastError();

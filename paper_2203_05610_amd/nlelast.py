@@ -25,13 +25,14 @@ NLE_DIVERGED_LINEAR, NLE_BFGS_BREAKDOWN = 4, 5
 NLE_E_INVAL, NLE_E_BADMESH, NLE_E_STATE = -1, -2, -3
 NLE_E_OOM, NLE_E_HIP, NLE_E_UNSUPPORTED = -4, -5, -6
 NLE_FP64, NLE_FP32 = 0, 1
-NLE_MAT_M1, NLE_MAT_M2, NLE_MAT_M3, NLE_MAT_M4 = 1, 2, 3, 4
+NLE_MAT_M1, NLE_MAT_M2, NLE_MAT_M3, NLE_MAT_M4, NLE_MAT_M5, NLE_MAT_M6 = 1, 2, 3, 4, 5, 6
 NLE_NK, NLE_INK, NLE_BFGS = 0, 1, 2
 NLE_KSP_GMRES, NLE_KSP_CG, NLE_KSP_MINRES = 0, 1, 2
 NLE_ORTH_MGS, NLE_ORTH_CGS2 = 0, 1
 NLE_PC_NONE, NLE_PC_JACOBI, NLE_PC_BJACOBI3, NLE_PC_AMG = 0, 1, 2, 3
 NLE_H0_PREONLY, NLE_H0_KSP = 0, 1
 NLE_PREC_FP64, NLE_PREC_MIXED = 0, 1
+NLE_SCHUR_DIAG, NLE_SCHUR_LOWER_MASS, NLE_SCHUR_LOWER_SIMPLE = 0, 1, 2
 
 STATUS_NAMES = {
     0: "OK", 1: "DIVERGED_MAXIT", 2: "DIVERGED_NAN", 3: "DIVERGED_INVERTED",
@@ -50,7 +51,8 @@ EXPORTS = [
     "nle_batch_solve", "nle_set_fibres", "nle_set_active_tension", "nle_set_pressure",
     "nle_set_robin", "nle_set_traction_follower", "nle_upload_mesh_mixed", "nle_block_diag", "nle_pc_apply", "nle_batch_autotune",
     "nle_set_inertia", "nle_newmark_predict", "nle_newmark_correct", "nle_amg_levels",
-    "nle_set_robin_damping", "nle_set_step_velocity",
+    "nle_set_robin_damping", "nle_set_step_velocity", "nle_upload_mesh_mixed_p0",
+    "nle_schur_apply", "nle_simple_diag", "nle_set_fibre_frame",
 ]
 
 
@@ -75,7 +77,7 @@ class nle_solver_opts(ctypes.Structure):
             "ew_alpha", "ew_alpha2", "ew_threshold", "ink_ksp_atol", "snes_rtol", "snes_atol",
             "h0_rtol", "h0_atol", "curvature_eps")] + [
         ("h0_refresh", ctypes.c_int32), ("jac_lag", ctypes.c_int32),
-        ("h0_ew", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+        ("h0_ew", ctypes.c_int32), ("schur", ctypes.c_int32)]
 
 
 class nle_report(ctypes.Structure):
@@ -86,7 +88,8 @@ class nle_report(ctypes.Structure):
                 ("rnorm_final", ctypes.c_double), ("t_ms", ctypes.c_double),
                 ("rnorm_hist", ctypes.POINTER(ctypes.c_double)),
                 ("eta_hist", ctypes.POINTER(ctypes.c_double)),
-                ("lit_hist", ctypes.POINTER(ctypes.c_int32))]
+                ("lit_hist", ctypes.POINTER(ctypes.c_int32)),
+                ("cutbacks", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -129,6 +132,10 @@ def lib() -> ctypes.CDLL:
         "nle_residual": (I32, [P, P, P, ctypes.POINTER(D)]),
         "nle_linearize": (I32, [P, P, I32]),
         "nle_jv": (I32, [P, P, P, I32]),
+        "nle_upload_mesh_mixed_p0": (I32, [P, I64, P, I64, P]),
+        "nle_schur_apply": (I32, [P, I32, I32, I32, P, P]),
+        "nle_simple_diag": (I32, [P, P]),
+        "nle_set_fibre_frame": (I32, [P, P, P]),
         "nle_diag": (I32, [P, P]),
         "nle_block_diag": (I32, [P, P]),
         "nle_pc_apply": (I32, [P, I32, I32, P, P]),
@@ -280,6 +287,29 @@ def nle_upload_mesh_mixed(ctx: Context, X, conn, n_pnodes: int, pconn) -> None:
     ctx.n_press = int(n_pnodes)
 
 
+def nle_upload_mesh_mixed_p0(ctx: Context, X, conn) -> None:
+    """Quadratic displacement, one pressure unknown per element (P2-P0)."""
+    X, px = _host(X, np.float64)
+    conn, pc = _host(conn, np.int32)
+    if X.ndim != 2 or X.shape[1] != 3 or conn.shape[1:] != (10,):
+        raise ValueError("X must be (n, 3) and conn (n_e, 10)")
+    ctx.check(lib().nle_upload_mesh_mixed_p0(ctx.handle, X.shape[0], px, conn.shape[0], pc))
+    ctx.n_nodes = X.shape[0]
+    ctx.n_elems = conn.shape[0]
+    ctx.n_press = conn.shape[0]
+
+
+def nle_schur_apply(ctx: Context, pc: int, schur: int, x, y, prec: int = NLE_FP64) -> None:
+    T = ctx.torch.float32 if prec == NLE_FP32 else ctx.torch.float64
+    ctx.check(lib().nle_schur_apply(ctx.handle, int(pc), int(schur), int(prec), ctx.vec(x, T),
+                                    ctx.vec(y, T)))
+
+
+def nle_simple_diag(ctx: Context, s) -> None:
+    """s: float64 device tensor of n_elems entries."""
+    ctx.check(lib().nle_simple_diag(ctx.handle, ctx.vec(s, ctx.torch.float64, n=ctx.n_elems)))
+
+
 def nle_set_material(ctx: Context, kind: int, params) -> None:
     p, pp = _host(params, np.float64)
     ctx.check(lib().nle_set_material(ctx.handle, int(kind), pp, p.size))
@@ -304,6 +334,14 @@ def nle_set_fibres(ctx: Context, fib) -> None:
     if f.shape != (ctx.n_elems, 3):
         raise ValueError(f"expected fibres of shape ({ctx.n_elems}, 3)")
     ctx.check(lib().nle_set_fibres(ctx.handle, pf))
+
+
+def nle_set_fibre_frame(ctx: Context, fib, sheet) -> None:
+    f, pf = _host(fib, np.float64)
+    sh, ps = _host(sheet, np.float64)
+    if f.shape != (ctx.n_elems, 3) or sh.shape != (ctx.n_elems, 3):
+        raise ValueError(f"expected fibres and sheets of shape ({ctx.n_elems}, 3)")
+    ctx.check(lib().nle_set_fibre_frame(ctx.handle, pf, ps))
 
 
 def nle_set_active_tension(ctx: Context, gamma: float) -> None:
@@ -597,6 +635,7 @@ def nle_batch_solve(b: Batch, method: int, opts: nle_solver_opts, u):
                                        ctypes.c_void_p(u.data_ptr()), reps, ctypes.byref(tms)))
     out = [dict(status=r.status, status_name=STATUS_NAMES.get(r.status, str(r.status)),
                 nit=r.nit, lit_total=r.lit_total, n_jv=r.n_jv, n_residual=r.n_residual,
-                cutbacks=r.bfgs_skipped, rnorm0=r.rnorm0, rnorm_final=r.rnorm_final)
+                cutbacks=r.cutbacks, bfgs_skipped=r.bfgs_skipped, rnorm0=r.rnorm0,
+                rnorm_final=r.rnorm_final)
            for r in reps]
     return st, out, tms.value

@@ -64,14 +64,15 @@ def make_opts(method: str, precision: str = "fp64", **over) -> nl.nle_solver_opt
 
 
 def solve_schedule(ctx: nl.Context, u, method: str, opts, scales, hist_cap: int = 4096,
-                   max_cuts: int = 8, start_scale: float = 0.0):
+                   max_cuts: int = 8, start_scale: float = 0.0, progress=None):
     """Solve at each load scale in turn, warm-started from the previous step.
 
     If a step does not converge (an element inverts, NaN, or the iteration
     limit), the state is restored to the last converged step and the load
     increment is halved (at most `max_cuts` times in total); the failed
     attempts stay in the returned reports (their time is part of the solve).
-    Each report carries 'load_scale' and 'accepted'.
+    Each report carries 'load_scale' and 'accepted'; `progress` (optional) is
+    called with each report as it arrives.
     """
     reps = []
     targets = [float(x) for x in scales]
@@ -86,6 +87,8 @@ def solve_schedule(ctx: nl.Context, u, method: str, opts, scales, hist_cap: int 
         rep["load_scale"] = s
         rep["accepted"] = st == nl.NLE_OK
         reps.append(rep)
+        if progress is not None:
+            progress(rep)
         if st == nl.NLE_OK:
             backup.copy_(u)
             s_prev = s
@@ -129,6 +132,15 @@ def setup_cardiac(ctx: nl.Context, mesh, consts: dict, dofs, block_size=None) ->
     nl.nle_set_robin(ctx, mesh.faces["epi"], c["k_perp"], c["k_par"])
     nl.nle_set_load_scale(ctx, 0.0)
     nl.nle_set_active_tension(ctx, 0.0)
+
+
+def setup_guccione(ctx: nl.Context, mesh, consts: dict, law, dofs, block_size=None) -> None:
+    """The heartbeat with the paper's Guccione law (Sec. 4; law M6, law =
+    (C, b_ff, b_ss, b_nn, b_fs, b_fn, b_sn, B)), the mesh's fibre and sheet
+    directions, and the loads and constraints of setup_cardiac."""
+    setup_cardiac(ctx, mesh, consts, dofs, block_size=block_size)
+    nl.nle_set_material(ctx, nl.NLE_MAT_M6, list(law))
+    nl.nle_set_fibre_frame(ctx, mesh.elem_fibre, mesh.elem_sheet)
 
 
 def solve_heartbeat(ctx: nl.Context, u, method: str, opts, schedule, gamma_max: float,
@@ -214,6 +226,18 @@ def setup_twist(ctx: nl.Context, mesh, mu: float, theta: float = 0.0) -> None:
     Dirichlet data come from synthetic.twist_dirichlet via set_twist_angle."""
     nl.nle_upload_mesh_mixed(ctx, mesh.X, mesh.conn, mesh.n_pressure, mesh.pconn)
     nl.nle_set_material(ctx, nl.NLE_MAT_M3, [mu])
+    nl.nle_set_load_scale(ctx, 1.0)
+
+
+TWIST_M5 = (9000.0, 9000.0, 9000.0, 9000.0)  # alpha_p, beta_p, alpha_s, beta_s (Sec. 4)
+
+
+def setup_twist_p0(ctx: nl.Context, mesh, params=TWIST_M5) -> None:
+    """The paper's twist statement (Sec. 4): quadratic displacement with one
+    pressure per element (P2-P0) and the polyconvex law M5 (default: the
+    printed constants, all 9000).  Dirichlet data as for setup_twist."""
+    nl.nle_upload_mesh_mixed_p0(ctx, mesh.X, mesh.conn)
+    nl.nle_set_material(ctx, nl.NLE_MAT_M5, list(params))
     nl.nle_set_load_scale(ctx, 1.0)
 
 

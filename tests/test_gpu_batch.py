@@ -92,8 +92,10 @@ def test_batch_usage_errors():
                          [0, 1, 0], [1.0])
     nl.nle_batch_finalize(B)
     u = torch.zeros(3 * m.n_nodes, dtype=torch.float64, device="cuda")
+    with pytest.raises(nl.NleError):  # batched Krylov is CG
+        nl.nle_batch_solve(B, nl.NLE_BFGS, problems.make_opts("bfgs", ksp="gmres"), u)
     with pytest.raises(nl.NleError):
-        nl.nle_batch_solve(B, nl.NLE_BFGS, problems.make_opts("bfgs"), u)
+        nl.nle_batch_solve(B, 7, problems.make_opts("nk", ksp="cg"), u)
 
 
 def test_batch_autotune_keeps_layout_and_results():
@@ -176,3 +178,56 @@ def test_batch_invariance_bitwise(precision):
         assert torch.equal(u_all[3 * off[k]: 3 * off[k + 1]], u_one), k
         assert reps_all[k]["nit"] == reps_one[0]["nit"]
         assert reps_all[k]["lit_total"] == reps_one[0]["lit_total"]
+
+
+@pytest.mark.parametrize("h0,precision,which", [
+    ("ksp", "mixed", [0, 1, 2, 3, 4]),
+    ("ksp", "fp64", [0, 1, 2, 3, 4]),
+    ("preonly", "fp64", [0, 1, 3]),
+])
+def test_batch_bfgs_matches_oracle_per_instance(h0, precision, which):
+    # batched L-BFGS (m = 10): inexact BFGS (H0 a CG solve to 1e-2) and
+    # BFGS-preonly (H0 the Jacobi inverse) on uneven instances, each against
+    # its own oracle root
+    data = _roots()
+    B = nl.Batch(0)
+    for k in which:
+        m, P, sched, _ = data[k]
+        nx, ny, nz, ratio, tau = INSTANCES[k]
+        problems.add_cook_instance(B, m, MU, ratio * MU, 1.0, sched)
+    nl.nle_batch_finalize(B)
+    off = nl.nle_batch_layout(B)
+    u = torch.zeros(int(3 * off[-1]), dtype=torch.float64, device="cuda")
+    o = problems.make_opts("bfgs", precision, ksp="cg", h0=h0, qn_m=10)
+    tight = precision == "fp64"
+    if tight:
+        o.snes_rtol = 1e-11
+    st, reps, _ = nl.nle_batch_solve(B, nl.NLE_BFGS, o, u)
+    assert st == nl.NLE_OK, [(r["status_name"], r["nit"], r["cutbacks"]) for r in reps]
+    uh = u.cpu().numpy()
+    for j, k in enumerate(which):
+        ustar = data[k][3]
+        ui = uh[3 * off[j]: 3 * off[j + 1]]
+        err = np.linalg.norm(ui - ustar) / np.linalg.norm(ustar)
+        assert err <= (1e-8 if tight else 1e-6), (k, err, reps[j])
+        assert reps[j]["nit"] >= len(data[k][2])
+
+
+def test_batch_bfgs_one_instance_equals_single_solver_root():
+    nx, ny, nz, ratio, tau = INSTANCES[1]
+    m = syn.cook_mesh(nx, ny, nz)
+    sched = syn.cook_load_schedule(tau)
+    o = problems.make_opts("bfgs", "fp64", ksp="cg", h0="ksp", qn_m=10)
+    o.snes_rtol = 1e-11
+    B = nl.Batch(0)
+    problems.add_cook_instance(B, m, MU, ratio * MU, 1.0, sched)
+    nl.nle_batch_finalize(B)
+    u = torch.zeros(3 * m.n_nodes, dtype=torch.float64, device="cuda")
+    st, reps, _ = nl.nle_batch_solve(B, nl.NLE_BFGS, o, u)
+    assert st == nl.NLE_OK
+    ctx = nl.Context(0)
+    problems.setup_cook(ctx, m, MU, ratio * MU, 1.0)
+    v = torch.zeros_like(u)
+    rs = problems.solve_schedule(ctx, v, "bfgs", o, sched)
+    assert problems.schedule_ok(rs, sched)
+    assert torch.allclose(u, v, rtol=0, atol=1e-8 * float(v.abs().max()))

@@ -176,3 +176,109 @@ def test_full_heartbeat_returns_to_rest():
     ustar = _oracle_root(mesh, steps[:10])
     assert relnorm(peak, ustar) <= 1e-6
     assert float(u.abs().max()) <= 1e-6 * float(np.abs(ustar).max())
+
+
+@pytest.mark.parametrize("method,prec,kw", [
+    ("ink", "fp64", {"ksp": "cg", "pc": "amg", "snes_rtol": 1e-10, "ksp_atol": 1e-14}),
+    ("ink", "mixed", {"ksp": "minres"}),
+])
+def test_heartbeat_4x20x64_to_peak_matches_stored_oracle_root(method, prec, kw):
+    # the 4x20x64 shell (30,720 tets), 10 time steps to the activation peak,
+    # against the oracle's root stored by tests/golden/make_golden.py
+    import os
+
+    ustar = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                 "heart4x20x64_peak.npy"))
+    mesh = syn.shell_mesh(4, 20, 64)
+    steps = syn.heartbeat_schedule()[:10]
+    ctx = nl.Context(0)
+    problems.setup_cardiac(ctx, mesh, C, syn.shell_dirichlet(mesh))
+    opts = problems.make_opts(method, prec, **dict(kw))
+    u = torch.zeros(mesh.n_dofs, dtype=torch.float64, device="cuda")
+    reps = problems.solve_heartbeat(ctx, u, method, opts, steps, C["gamma_max"])
+    assert problems.heartbeat_ok(reps, steps), [(r["t"], r["status_name"]) for r in reps]
+    err = relnorm(u.cpu().numpy(), ustar)
+    assert err <= (1e-8 if prec == "fp64" else 1e-6), err
+
+
+# ---- the paper's Guccione law (M6) with the fibre / sheet frame ------------------
+GUC = (0.1, 5.0, 2.0, 2.0, 1.0, 1.0, 1.0, 100.0)  # C, b_ff, b_ss, b_nn, b_fs, b_fn, b_sn, B
+
+
+def _guc(block_size=128, gamma=0.03):
+    mesh = syn.shell_mesh(2, 6, 12)
+    P = fem.guccione_problem(mesh, C, GUC, gamma=gamma)
+    ctx = nl.Context(0)
+    problems.setup_guccione(ctx, mesh, C, GUC, syn.shell_dirichlet(mesh), block_size=block_size)
+    nl.nle_set_active_tension(ctx, gamma)
+    return mesh, P, ctx
+
+
+@pytest.mark.parametrize("be", [64, 512])
+def test_guccione_kernels_parity(be):
+    mesh, P, ctx = _guc(be)
+    u = P.lift(smooth_state(mesh, P.n_dofs, seed=111, amp=0.03))
+    for s in (0.0, 0.7):
+        nl.nle_set_load_scale(ctx, s)
+        r = torch.empty(P.n_dofs, dtype=torch.float64, device="cuda")
+        rn = nl.nle_residual(ctx, _t(u), r)
+        ref = P.residual(u, s)
+        assert relmax(r.cpu().numpy(), ref) < 1e-12
+        assert abs(rn - np.linalg.norm(ref)) <= 1e-12 * np.linalg.norm(ref)
+    s = 0.7
+    nl.nle_linearize(ctx, _t(u), nl.NLE_FP32)
+    K = P.stiffness(u, load_scale=s)
+    v = syn.random_field(P.n_dofs, 1.0, seed=112)
+    y = torch.empty(P.n_dofs, dtype=torch.float64, device="cuda")
+    nl.nle_jv(ctx, _t(v), y, nl.NLE_FP64)
+    assert relmax(y.cpu().numpy(), K @ v) < 1e-12
+    y32 = torch.empty(P.n_dofs, dtype=torch.float32, device="cuda")
+    nl.nle_jv(ctx, _t(v, torch.float32), y32, nl.NLE_FP32)
+    assert_fp32_entrywise(y32.cpu().numpy(), K @ v, row_magnitude(K, v, P, u),
+                          dir_dofs=P.ddofs, v=v)
+    d = torch.empty(P.n_dofs, dtype=torch.float64, device="cuda")
+    nl.nle_diag(ctx, d)
+    assert relmax(d.cpu().numpy(), K.diagonal()) < 1e-12
+    # the potential without the follower pressure (springs, law and activation)
+    ctx2 = nl.Context(0)
+    nl.nle_upload_mesh(ctx2, mesh.X, mesh.conn)
+    nl.nle_set_material(ctx2, nl.NLE_MAT_M6, list(GUC))
+    nl.nle_set_fibre_frame(ctx2, mesh.elem_fibre, mesh.elem_sheet)
+    nl.nle_set_active_tension(ctx2, 0.03)
+    P2 = fem.Problem(mesh.X, mesh.conn, "M6", P.params, np.zeros(P.n_dofs), np.zeros(0, np.int64),
+                     np.zeros(0))
+    e = nl.nle_energy(ctx2, _t(u))
+    assert abs(e - P2.energy(u)) <= 1e-11 * abs(P2.energy(u))
+    # refusals: no sheets, block Jacobi
+    ctx3 = nl.Context(0)
+    nl.nle_upload_mesh(ctx3, mesh.X, mesh.conn)
+    nl.nle_set_material(ctx3, nl.NLE_MAT_M6, list(GUC))
+    nl.nle_set_fibres(ctx3, mesh.elem_fibre)
+    with pytest.raises(nl.NleError) as er:
+        nl.nle_residual(ctx3, _t(u), r)
+    assert er.value.status == nl.NLE_E_STATE
+    with pytest.raises(nl.NleError):
+        nl.nle_set_fibre_frame(ctx3, mesh.elem_fibre, mesh.elem_fibre)  # not orthogonal
+    with pytest.raises(nl.NleError) as er:
+        nl.nle_block_diag(ctx, torch.empty(6 * mesh.n_nodes, dtype=torch.float64, device="cuda"))
+    assert er.value.status == nl.NLE_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("method,prec,kw", [
+    ("ink", "mixed", {"ksp": "gmres", "restart": 1000}),
+    ("nk", "fp64", {"ksp": "gmres", "restart": 1000, "snes_rtol": 1e-10, "ksp_atol": 1e-14}),
+    ("bfgs", "mixed", {"ksp": "gmres", "restart": 1000, "h0": "ksp", "qn_m": 10}),
+])
+def test_guccione_heartbeat_steps_match_oracle(method, prec, kw):
+    mesh = syn.shell_mesh(2, 6, 12)
+    steps = syn.heartbeat_schedule()[:N_STEPS]
+    P = fem.guccione_problem(mesh, C, GUC)
+    ustar = newton.solve_heartbeat(P, steps, C["gamma_max"])[0]
+    ctx = nl.Context(0)
+    problems.setup_guccione(ctx, mesh, C, GUC, syn.shell_dirichlet(mesh), block_size=128)
+    opts = problems.make_opts(method, prec, **dict(kw))
+    u = torch.zeros(mesh.n_dofs, dtype=torch.float64, device="cuda")
+    reps = problems.solve_heartbeat(ctx, u, method, opts, steps, C["gamma_max"])
+    assert problems.heartbeat_ok(reps, steps), [(r["t"], r["status_name"]) for r in reps]
+    err = relnorm(u.cpu().numpy(), ustar)
+    assert err <= (1e-8 if prec == "fp64" else 1e-6), err

@@ -6,9 +6,11 @@ tests/golden/make_golden.py, which runs exact Newton with a complex-step
 tangent and sparse LU to ||r|| <= 1e-13 ||r_0||).
 
 Gates: displacement relative error (2-norm) <= 1e-6 for the mixed-precision
-methods, <= 1e-8 for the FP64 methods with the nonlinear tolerance tightened
-to 1e-11 (so the gate measures the solver, not where the 1e-8 stopping rule
-happens to cut).  Where paths could land on different equilibria at this load
+methods, <= 1e-8 for the FP64 methods, at the schedule's own stopping rule
+||r|| <= 1e-8 ||r_0||.  No tighter rule is used here: at lambda/mu = 5000 the
+FP64 residual's rounding floor lies near 1e-9 of ||r_0|| (the oracle's exact
+Newton stalls at 3e-9, the GPU's at 5e-10), and at the 1e-8 rule the roots
+already agree to ~1e-13.  Where paths could land on different equilibria at this load
 (both residuals converged but u apart), the failure message says so
 ("branch") with both potentials.
 """
@@ -58,18 +60,18 @@ def _check(P, ustar, uh, tol, method):
     return err
 
 
-@pytest.mark.parametrize("method", ["ink_mixed_cg_amg", "ink_fp64_cg_amg", "nk_fp64_cg_amg"])
+@pytest.mark.parametrize("method", ["ink_mixed_cg_amg", "ink_fp64_cg_amg", "nk_fp64_minres_amg"])
 def test_headline_schedule_matches_oracle_root(cook64, method):
     mesh, P, ustar, ctx = cook64
     solver, prec, kw = bench.METHODS[method]
     opts = problems.make_opts(solver, prec, **{"pc": "jacobi", **kw})
     fp64 = prec == "fp64"
-    if fp64:
-        opts.snes_rtol = 1e-11
     u = torch.zeros(P.n_dofs, dtype=torch.float64, device="cuda")
     sched = bench.load_schedule()
     reps = problems.solve_schedule(ctx, u, solver, opts, sched)
-    assert problems.schedule_ok(reps, sched), [(r["load_scale"], r["status_name"]) for r in reps]
+    assert problems.schedule_ok(reps, sched), [(r["load_scale"], r["status_name"], r["nit"],
+                                                r["rnorm_final"] / max(r["rnorm0"], 1e-300))
+                                               for r in reps]
     err = _check(P, ustar, u.cpu().numpy(), 1e-8 if fp64 else 1e-6, method)
     print(f"{method}: rel. error {err:.2e}, attempts "
           f"{[(r['load_scale'], r['status_name'], r['nit']) for r in reps]}")
