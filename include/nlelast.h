@@ -403,6 +403,19 @@ nle_status nle_linearize(nle_ctx *ctx, const double *u_dev, int32_t prec);
  * precision prec (v and y are double* for NLE_FP64, float* for NLE_FP32).
  * NLE_E_STATE without a linearization in that precision. */
 nle_status nle_jv(nle_ctx *ctx, const void *v_dev, void *y_dev, int32_t prec);
+/* Allocation-free Jacobian action, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): y = J(u_lin) v exactly as nle_jv (same kernels, same
+ * result bit for bit), but the partial sums of nodes shared between element
+ * blocks go to a fixed workspace of 64 MiB per device that the library
+ * holds from its load until the process ends, instead of to a buffer of the
+ * context.  It calls no allocator.  P1 meshes only (NLE_E_UNSUPPORTED on a
+ * mixed mesh); NLE_E_STATE without a linearization in prec; NLE_E_INVAL if
+ * the mesh's shared-slot partials (3 values of prec per shared block-node
+ * slot, nle_partition_info entry 5) exceed 64 MiB.  Every call on a device
+ * uses that device's one workspace: calls that overlap in time on one device
+ * (several streams or threads) race and give wrong results; serialise them. */
+nle_status nle_jv_noalloc(nle_ctx *ctx, const void *v_dev, void *y_dev, int32_t prec);
 /* Jacobi data of the current linearization: d = diag J (1 on Dirichlet
  * dofs), double, device. */
 nle_status nle_diag(nle_ctx *ctx, double *d_dev);

@@ -221,6 +221,14 @@ nle_status nle_create(nle_ctx **out, int32_t device, void *stream, const nle_all
     delete c;
     return NLE_E_HIP;
   }
+  // the fixed workspace of nle_jv_noalloc, looked up with the device current
+  if (noalloc_scratch_init(device, &c->noalloc_ws) != hipSuccess) {
+    (void)hipStreamDestroy(c->kstream);
+    (void)hipEventDestroy(c->ev_a);
+    (void)hipEventDestroy(c->ev_b);
+    delete c;
+    return NLE_E_HIP;
+  }
   c->dscal = static_cast<double *>(dalloc(c, 64 * 8));
   c->dflag = static_cast<int32_t *>(dalloc(c, 64 * 4));
   if (!c->dscal || !c->dflag || hipHostMalloc(&c->hpin, 4096) != hipSuccess) {
@@ -928,6 +936,31 @@ nle_status nle_jv(nle_ctx *ctx, const void *v, void *y, int32_t prec) {
   if ((prec == NLE_FP64 && !c->lin64) || (prec == NLE_FP32 && !c->lin32))
     return fail(c, NLE_E_STATE, "nle_jv needs nle_linearize in this precision first");
   return jv(c, v, y, prec);
+}
+
+nle_status nle_jv_noalloc(nle_ctx *ctx, const void *v, void *y, int32_t prec) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  nle_status s = need_mesh(c);
+  if (s != NLE_OK) return s;
+  if (!v || !y) return fail(c, NLE_E_INVAL, "null vector");
+  if (prec != NLE_FP64 && prec != NLE_FP32) return fail(c, NLE_E_INVAL, "bad precision");
+  if ((prec == NLE_FP64 && !c->lin64) || (prec == NLE_FP32 && !c->lin32))
+    return fail(c, NLE_E_STATE, "nle_jv_noalloc needs nle_linearize in this precision first");
+  if (c->mixed)
+    return fail(c, NLE_E_UNSUPPORTED, "nle_jv_noalloc takes P1 meshes (the partial sums of "
+                                      "shared nodes are its workspace)");
+  if (!c->noalloc_ws) return fail(c, NLE_E_STATE, "no fixed workspace on this device");
+  const size_t need = size_t(c->m.n_fx) * 3 * (prec == NLE_FP32 ? 4 : 8);
+  if (need > NOALLOC_SCRATCH_BYTES)
+    return fail(c, NLE_E_INVAL, "nle_jv_noalloc: the mesh's shared-slot partial sums need " +
+                                    std::to_string(need) + " bytes, more than the fixed " +
+                                    std::to_string(NOALLOC_SCRATCH_BYTES) + "-byte workspace");
+  // same kernels as nle_jv, with the partial sums in the fixed workspace
+  void *own = c->partial;
+  c->partial = c->noalloc_ws;
+  const nle_status r = jv(c, v, y, prec);
+  c->partial = own;
+  return r;
 }
 
 nle_status nle_diag(nle_ctx *ctx, double *d) {

@@ -13,10 +13,36 @@
 // reproducible.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "nle_internal.hpp"
 #include "nle_kin.hpp"
 
 namespace nle {
+
+// Fixed device workspace of the allocation-free Jacobian action
+// (nle_jv_noalloc): the shared-slot partial sums live here instead of in the
+// buffer the library allocates at mesh upload.  One copy per device, held
+// until the process ends; in host code the array's name is only a stand-in,
+// so its address is always taken with hipGetSymbolAddress (per device, with
+// that device current) and that pointer is what kernels receive.
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+hipError_t noalloc_scratch_init(int device, void **out) {
+  static std::mutex mu;
+  static void *ptrs[NOALLOC_MAX_DEVICES] = {};
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptrs[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    ptrs[device] = p;
+  }
+  *out = ptrs[device];
+  return hipSuccess;
+}
 
 namespace {
 

@@ -14,6 +14,11 @@ namespace nle {
 constexpr int NT = 256;            // threads per workgroup (four wave64)
 constexpr int VGRID_MAX = 1024;    // workgroups of the streaming vector kernels
 constexpr uint32_t NODE_MASK = 0x0FFFFFFFu;  // node id bits of a block-node word
+// Size of the fixed per-device workspace of nle_jv_noalloc (shared-slot
+// partial sums: 3 values per shared block-node slot), and the devices it
+// is set up for.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
 
 // Device scalar slots of the CG loop (shared by the vector kernels and the
 // element kernels that form the CG direction).
@@ -218,6 +223,7 @@ struct Ctx {
 
   // scratch
   void *partial = nullptr;   // [n_slots][3] doubles (shared-slot partial sums)
+  void *noalloc_ws = nullptr;  // this device's fixed workspace (nle_jv_noalloc)
   double *red = nullptr;     // reduction partials, RED_CAP doubles
   int64_t red_cap = 0;
   double *dscal = nullptr;   // device scalars
@@ -332,6 +338,9 @@ int mixed_red_capacity(const Ctx *c);
 // OP_JV with c->ep.red set, the number of v.(Jv) partials written there.
 int elem_apply(Ctx *c, int op, int prec, const void *u, const void *v, void *out, double *red,
                hipError_t *err);
+// Address of the fixed workspace of the allocation-free Jacobian action on
+// `device` (must be the current device), looked up once per device.
+hipError_t noalloc_scratch_init(int device, void **out);
 int elem_red_capacity(const Ctx *c);
 
 // ---- vector kernels (nle_vec.hip) ------------------------------------------

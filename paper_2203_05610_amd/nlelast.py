@@ -51,7 +51,7 @@ EXPORTS = [
     "nle_batch_solve", "nle_set_fibres", "nle_set_active_tension", "nle_set_pressure",
     "nle_set_robin", "nle_set_traction_follower", "nle_upload_mesh_mixed", "nle_block_diag", "nle_pc_apply", "nle_batch_autotune",
     "nle_set_inertia", "nle_newmark_predict", "nle_newmark_correct", "nle_amg_levels",
-    "nle_set_robin_damping", "nle_set_step_velocity", "nle_upload_mesh_mixed_p0",
+    "nle_set_robin_damping", "nle_set_step_velocity", "nle_jv_noalloc", "nle_upload_mesh_mixed_p0",
     "nle_schur_apply", "nle_simple_diag", "nle_set_fibre_frame",
 ]
 
@@ -132,6 +132,7 @@ def lib() -> ctypes.CDLL:
         "nle_residual": (I32, [P, P, P, ctypes.POINTER(D)]),
         "nle_linearize": (I32, [P, P, I32]),
         "nle_jv": (I32, [P, P, P, I32]),
+        "nle_jv_noalloc": (I32, [P, P, P, I32]),
         "nle_upload_mesh_mixed_p0": (I32, [P, I64, P, I64, P]),
         "nle_schur_apply": (I32, [P, I32, I32, I32, P, P]),
         "nle_simple_diag": (I32, [P, P]),
@@ -437,6 +438,13 @@ def nle_linearize(ctx: Context, u, prec: int = NLE_FP64) -> None:
 def nle_jv(ctx: Context, v, y, prec: int = NLE_FP64) -> None:
     T = ctx.torch.float32 if prec == NLE_FP32 else ctx.torch.float64
     ctx.check(lib().nle_jv(ctx.handle, ctx.vec(v, T), ctx.vec(y, T), int(prec)))
+
+
+def nle_jv_noalloc(ctx: Context, v, y, prec: int = NLE_FP64) -> None:
+    """y = J v through the allocation-free entry point (fixed per-device
+    workspace; same result as nle_jv)."""
+    T = ctx.torch.float32 if prec == NLE_FP32 else ctx.torch.float64
+    ctx.check(lib().nle_jv_noalloc(ctx.handle, ctx.vec(v, T), ctx.vec(y, T), int(prec)))
 
 
 def nle_diag(ctx: Context, d) -> None:
