@@ -370,14 +370,29 @@ TWIST_METHODS = {
     # H0 a MINRES solve to rtol 1e-2, or the preconditioner alone
     "bfgs_ib_fp64": ("bfgs", "fp64", {"ksp": "minres", "h0": "ksp", "qn_m": 10}),
     "bfgs_b_fp64": ("bfgs", "fp64", {"ksp": "minres", "h0": "preonly", "qn_m": 10}),
+    # the lower block-triangular preconditioner (App. B) with the lumped
+    # pressure mass over mu for the Schur complement (schur 1), Jacobi or the
+    # multigrid cycle on the displacement block
+    "ink_mixed_schur_mass": ("ink", "mixed", {"ksp": "gmres", "schur": 1}),
+    "nk_fp64_schur_mass_amg": ("nk", "fp64", {"ksp": "gmres", "schur": 1, "pc": "amg"}),
+    "ink_fp64_schur_mass_amg": ("ink", "fp64", {"ksp": "gmres", "schur": 1, "pc": "amg"}),
+    "ink_mixed_schur_mass_amg": ("ink", "mixed", {"ksp": "gmres", "schur": 1, "pc": "amg"}),
+    # the constant-pressure pair (P2-P0, --twist-p0) also takes the SIMPLE
+    # approximation S = B diag(A)^-1 B^T (schur 2)
+    "nk_fp64_schur_simple": ("nk", "fp64", {"ksp": "gmres", "schur": 2}),
+    "ink_mixed_schur_simple": ("ink", "mixed", {"ksp": "gmres", "schur": 2}),
+    "nk_fp64_schur_simple_amg": ("nk", "fp64", {"ksp": "gmres", "schur": 2, "pc": "amg"}),
+    "ink_fp64_schur_simple_amg": ("ink", "fp64", {"ksp": "gmres", "schur": 2, "pc": "amg"}),
+    "ink_mixed_schur_simple_amg": ("ink", "mixed", {"ksp": "gmres", "schur": 2, "pc": "amg"}),
 }
 
 
-def twist_c3(nl, torch, n: int, methods):
-    """Twist test: unit cube, n^3 cells -> 6 n^3 quadratic tets with linear
-    pressure, mu = 1, top face rotated 10 deg per step to 90 deg (9 steps),
-    MINRES with the block-diagonal preconditioner (Jacobi on u, lumped
-    pressure mass / mu on p).  Setup outside the timed region."""
+def twist_c3(nl, torch, n: int, methods, p0: bool = False):
+    """Twist test: unit cube, n^3 cells -> 6 n^3 quadratic tets, top face
+    rotated 10 deg per step to 90 deg (9 steps).  Default pair: linear
+    pressure, incompressible neo-Hookean, mu = 1; p0: one pressure per
+    element with the polyconvex law and the printed constants (all 9000).
+    Setup outside the timed region."""
     import math
 
     import synthetic as syn
@@ -385,18 +400,28 @@ def twist_c3(nl, torch, n: int, methods):
 
     mesh = syn.twist_p2_mesh(n)
     ctx = nl.Context(0)
-    problems.setup_twist(ctx, mesh, 1.0)
+    if p0:
+        problems.setup_twist_p0(ctx, mesh)
+    else:
+        problems.setup_twist(ctx, mesh, 1.0)
     angles = [math.radians(10 * s) for s in range(1, 10)]
     dirf = lambda th: syn.twist_dirichlet(mesh.X, mesh.sets["bottom"], mesh.sets["top"], th)  # noqa: E731
-    out = {"workload": f"twist {n}^3 cells -> {mesh.n_elems} P2 tets + P1 pressure, "
-                       f"{ctx.n_dofs} unknowns, mu=1, 9 x 10 deg", "methods": {}}
+    pair = ("P0 pressure, polyconvex law, alpha_p=beta_p=alpha_s=beta_s=9000" if p0 else
+            "P1 pressure, incompressible neo-Hookean, mu=1")
+    out = {"workload": f"twist {n}^3 cells -> {mesh.n_elems} P2 tets + {pair}, "
+                       f"{ctx.n_dofs} unknowns, 9 x 10 deg", "methods": {}}
     for m in methods:
         name, prec, kw = TWIST_METHODS[m]
         opts = problems.make_opts(name, prec, **dict(kw))
         x = torch.zeros(ctx.n_dofs, dtype=torch.float64, device="cuda")
         torch.cuda.synchronize()
         t = time.perf_counter()
-        reps = problems.solve_twist(ctx, x, name, opts, angles, dirf)
+        def progress(rep, m=m):
+            print(f"[bench]   twist {m} {math.degrees(rep['theta']):.1f} deg: "
+                  f"{rep['status_name']} nit={rep['nit']} lit={rep['lit_total']}",
+                  file=sys.stderr, flush=True)
+
+        reps = problems.solve_twist(ctx, x, name, opts, angles, dirf, progress=progress)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
         out["methods"][m] = {"seconds": round(dt, 3), "ok": problems.twist_ok(reps, angles),
@@ -613,6 +638,9 @@ def main():
     ap.add_argument("--batch-only", action="store_true", help="only the batched-solve leg")
     ap.add_argument("--twist", type=int, default=24, help="twist cube cells per edge (0 skips)")
     ap.add_argument("--twist-methods", default="nk_fp64,ink_mixed")
+    ap.add_argument("--twist-p0", type=int, default=0,
+                    help="cells per edge of the P2-P0 polyconvex twist leg (0 skips)")
+    ap.add_argument("--twist-p0-methods", default="nk_fp64_schur_simple,ink_mixed_schur_simple")
     ap.add_argument("--cardiac", default="", help="ventricle shell grid n_t,n_s,n_c (e.g. "
                     "8,80,256); empty skips this leg (minutes at full size)")
     ap.add_argument("--cardiac-methods", default="ink_fp64_cg_amg,bfgs_ib_fp64_r20_bj")
@@ -663,6 +691,9 @@ def main():
         res = {"legs_only": True}
         if args.twist > 0:
             res["twist"] = twist_c3(nl, torch, args.twist, args.twist_methods.split(","))
+        if args.twist_p0 > 0:
+            res["twist_p0"] = twist_c3(nl, torch, args.twist_p0,
+                                       args.twist_p0_methods.split(","), p0=True)
         if args.cardiac:
             res["cardiac"] = cardiac_c5(nl, torch, tuple(int(x) for x in args.cardiac.split(",")),
                                         args.cardiac_methods.split(","), args.cardiac_steps)
@@ -765,6 +796,8 @@ def main():
     if args.batch > 0:
         batch = batch_c4(nl, torch, args.batch, args.batch_serial_stride, 1)
     twist = twist_c3(nl, torch, args.twist, args.twist_methods.split(",")) if args.twist > 0 else None
+    twist_p0 = (twist_c3(nl, torch, args.twist_p0, args.twist_p0_methods.split(","), p0=True)
+                if args.twist_p0 > 0 else None)
     cardiac = None
     if args.cardiac:
         cardiac = cardiac_c5(nl, torch, tuple(int(x) for x in args.cardiac.split(",")),
@@ -818,6 +851,7 @@ def main():
         "compare": extra or None,
         "batch": batch,
         "twist": twist,
+        "twist_p0": twist_p0,
         "cardiac": cardiac,
         "follower": follower,
         "p2": p2,

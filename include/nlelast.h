@@ -142,7 +142,12 @@ typedef struct {
   int32_t orth;       /* GMRES orthogonalisation                              */
   int32_t pc;         /* NLE_PC_JACOBI / NLE_PC_BJACOBI3 / NLE_PC_AMG /
                          NLE_PC_NONE (batched solves: Jacobi only)          */
-  int32_t restart;    /* GMRES restart length; <= 0 means ksp_max_it          */
+  int32_t restart;    /* GMRES restart length; <= 0 means ksp_max_it (no
+                         restart).  The basis is allocated as the cycle
+                         grows (segments of max(64, half the vectors so
+                         far), each with its Hessenberg columns), kept by the
+                         context for later solves; a failed growth returns
+                         NLE_E_OOM.  Up front only O(ksp_max_it) scalars.  */
   int32_t ksp_max_it; /* Krylov iteration limit per linear solve              */
   int32_t snes_max_it;/* nonlinear iteration limit                            */
   int32_t ew_version; /* Eisenstat-Walker variant 1 or 2                      */

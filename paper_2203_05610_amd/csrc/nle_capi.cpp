@@ -257,6 +257,7 @@ void nle_destroy(nle_ctx *ctx) {
   if (c->kstream) (void)hipStreamSynchronize(c->kstream);
   drop_graph(c);
   amg_release(c);
+  gmres_pool_release(c);
   for (void *p : c->mesh_allocs) dfree(c, p);
   for (void *p : c->ws_allocs) dfree(c, p);
   dfree(c, c->red);

@@ -264,7 +264,23 @@ struct Ctx {
   std::vector<void *> ws_allocs;
   size_t ws_bytes = 0;
   void *ws = nullptr;
+
+  // GMRES basis pool: segments of basis vectors (vector stride gm_vb), their
+  // Hessenberg columns and partial rows, kept across solves
+  struct GmSeg {
+    void *p;
+    int v0, nv;
+    void *vbase;
+    double *hbase, *rbase;
+  };
+  std::vector<GmSeg> gm_segs;
+  size_t gm_vb = 0;
+  std::vector<void *> gm_hv;
+  std::vector<double *> gm_hr;
 };
+
+// Release the GMRES basis pool (waits for the stream first).
+void gmres_pool_release(Ctx *c);
 
 nle_status fail(Ctx *c, nle_status code, const std::string &msg);
 // Length of the unknown vector: 3 per node, plus one per pressure node.
@@ -451,22 +467,34 @@ hipError_t mr_start_finish(Ctx *c, const MinresArgs &a, double rtol, double atol
 hipError_t mr_iterate(Ctx *c, const MinresArgs &a,
                       hipError_t (*pc_outside)(Ctx *, const MinresArgs &) = nullptr);
 
-// GMRES kernels
+// GMRES kernels.  The basis grows with the iterations: vectors, Hessenberg
+// columns and the partial-sum rows of the multi-dots live in segments that
+// are allocated as the cycle needs them, reached through device tables of
+// pointers (entry i: basis vector i, Hessenberg column i of length i + 2,
+// partial row i) and the host copies of the vector and row pointers.
 struct GmresArgs {
   int prec;
   int64_t n;
-  int m;             // basis capacity (restart)
-  void *V;           // [m+1][n]
+  int m;             // cycle length (restart, or the iteration limit)
+  void **Vp;         // device table [m+1] of basis vectors
+  double **Hp;       // device table [m+1] of Hessenberg columns
+  double **Rp;       // device table [m+1] of partial rows (VGRID_MAX each)
+  void *const *hV;   // host copies of the vector pointers
+  double *const *hR; // host copies of the row pointers
   void *w;           // [n] work
   void *z;           // [n] work (preconditioned)
   void *x;           // [n] solution
   const void *dinv;  // may be null
   int pcb = 1;       // as in CgArgs
-  double *red;       // partials [(m+2) x VGRID_MAX]
-  double *H;         // device Hessenberg [(m+1) x m] column-major, + rotations
+  double *rot;       // cs[m], sn[m], g[m+1], y[m]
+  double *redsq;     // partials of w.w (VGRID_MAX)
   double *scal;
   int32_t *flag;
 };
+// Fill the device tables for segment [v0, v0 + nv) of the basis pool (entries
+// at or beyond `limit` are left alone).
+hipError_t gmres_tables(Ctx *c, const GmresArgs &a, int v0, int nv, int limit, void *vbase,
+                        size_t vb, double *hbase, double *rbase);
 hipError_t gmres_multidot(Ctx *c, const GmresArgs &a, int j);           // h_i = V_i . w, i<=j
 hipError_t gmres_subtract(Ctx *c, const GmresArgs &a, int j, int pass, int want_dots);
 hipError_t gmres_mgs_step(Ctx *c, const GmresArgs &a, int i, int j);    // fused MGS step

@@ -34,6 +34,16 @@ void drop_graph(Ctx *c) {
   c->gkey.clear();
 }
 
+void gmres_pool_release(Ctx *c) {
+  if (c->gm_segs.empty()) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (const Ctx::GmSeg &g : c->gm_segs) dfree(c, g.p);
+  c->gm_segs.clear();
+  c->gm_hv.clear();
+  c->gm_hr.clear();
+  c->gm_vb = 0;
+}
+
 namespace {
 
 constexpr double GOLDEN = 1.6180339887498949;
@@ -83,9 +93,63 @@ size_t ksp_bytes(const KspOpts &o, int64_t n, int prec) {
   const size_t v = (size_t(n) * esz(prec) + 255) & ~size_t(255);
   if (o.type == NLE_KSP_CG) return 4 * v + 4096;
   if (o.type == NLE_KSP_MINRES) return 11 * v + 4096;
-  const int m = o.restart > 0 ? std::min(o.restart, o.max_it) : o.max_it;
-  return size_t(m + 3 + (o.schur ? 2 : 0)) * v + size_t((m + 1) * m + 4 * m + 8) * 8 +
-         size_t(m + 3) * VGRID_MAX * 8 + size_t(8 + 2 * (m + 1)) * 8 + 8 * 256;
+  // GMRES: the basis itself grows in the pool (gmres_reserve); the workspace
+  // holds two work vectors, the pointer tables and the O(m) scalars
+  const size_t m = size_t(o.restart > 0 ? std::min(o.restart, o.max_it) : o.max_it);
+  return size_t(2 + (o.schur ? 2 : 0)) * v + 3 * (m + 1) * 8 + (4 * m + 4) * 8 +
+         size_t(VGRID_MAX) * 8 + (8 + 2 * (m + 1)) * 8 + 8 * 256;
+}
+
+// Basis pool growth: the next segment holds max(64, half the vectors so far)
+// vectors, at most up to the cycle's m + 1.  A segment carries its vectors,
+// the Hessenberg columns of the same indices (column j: j + 2 rows) and one
+// partial row per vector.
+size_t gm_seg_bytes(size_t vb, int v0, int nv) {
+  const size_t hcols = size_t(nv) * size_t(v0 + 2) + size_t(nv) * size_t(nv - 1) / 2;
+  return size_t(nv) * vb + ((hcols * 8 + 255) & ~size_t(255)) + size_t(nv) * VGRID_MAX * 8;
+}
+
+int gm_pool_vectors(const Ctx *c) {
+  return c->gm_segs.empty() ? 0 : c->gm_segs.back().v0 + c->gm_segs.back().nv;
+}
+
+// Make at least `need` (<= m + 1) basis vectors available and their table
+// entries valid; `filled` counts the entries already written for this solve.
+nle_status gmres_reserve(Ctx *c, const GmresArgs &a, size_t vb, int need, int *filled) {
+  if (c->gm_vb != vb) {
+    gmres_pool_release(c);
+    c->gm_vb = vb;
+  }
+  while (gm_pool_vectors(c) < need) {
+    const int have = gm_pool_vectors(c);
+    const int nv = std::min(a.m + 1 - have, std::max(64, have / 2));
+    const size_t bytes = gm_seg_bytes(vb, have, nv);
+    void *p = dalloc(c, bytes);
+    if (!p)
+      return fail(c, NLE_E_OOM, "GMRES basis growth to " + std::to_string(have + nv) +
+                                    " vectors failed (" + std::to_string(bytes >> 20) + " MiB)");
+    Ctx::GmSeg g;
+    g.p = p;
+    g.v0 = have;
+    g.nv = nv;
+    g.vbase = p;
+    g.hbase = reinterpret_cast<double *>(static_cast<char *>(p) + size_t(nv) * vb);
+    const size_t hcols = size_t(nv) * size_t(have + 2) + size_t(nv) * size_t(nv - 1) / 2;
+    g.rbase = reinterpret_cast<double *>(reinterpret_cast<char *>(g.hbase) +
+                                         ((hcols * 8 + 255) & ~size_t(255)));
+    c->gm_segs.push_back(g);
+    for (int i = 0; i < nv; ++i) {
+      c->gm_hv.push_back(static_cast<char *>(p) + size_t(i) * vb);
+      c->gm_hr.push_back(g.rbase + size_t(i) * VGRID_MAX);
+    }
+  }
+  // table entries of the segments not yet written in this solve
+  for (const Ctx::GmSeg &g : c->gm_segs) {
+    if (g.v0 + g.nv <= *filled || g.v0 >= a.m + 1) continue;
+    NLE_HIP(c, gmres_tables(c, a, g.v0, g.nv, a.m + 1, g.vbase, vb, g.hbase, g.rbase));
+  }
+  *filled = std::max(*filled, std::min(gm_pool_vectors(c), a.m + 1));
+  return NLE_OK;
 }
 
 // Run `iteration` (which queues one Krylov iteration on c->stream) until the
@@ -333,16 +397,26 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
   a.prec = prec;
   a.n = n;
   a.m = m;
-  a.V = W.take(size_t(m + 1) * vb);
+  a.Vp = static_cast<void **>(W.take(size_t(m + 1) * 8));
+  a.Hp = static_cast<double **>(W.take(size_t(m + 1) * 8));
+  a.Rp = static_cast<double **>(W.take(size_t(m + 1) * 8));
   a.w = W.take(vb);
   a.z = W.take(vb);
   a.x = x;
   a.dinv = dinv;
   a.pcb = pcb;
-  a.H = static_cast<double *>(W.take(size_t((m + 1) * m + 4 * m + 8) * 8));
-  a.red = static_cast<double *>(W.take(size_t(m + 3) * VGRID_MAX * 8));
+  a.rot = static_cast<double *>(W.take(size_t(4 * m + 4) * 8));
+  a.redsq = static_cast<double *>(W.take(size_t(VGRID_MAX) * 8));
   a.scal = static_cast<double *>(W.take(size_t(8 + 2 * (m + 1)) * 8));
   a.flag = flag;
+  // the first vectors of the basis; the pool grows as the cycle proceeds
+  int filled = 0;
+  {
+    nle_status s = gmres_reserve(c, a, vb, std::min(m + 1, 64), &filled);
+    if (s != NLE_OK) return s;
+  }
+  a.hV = c->gm_hv.data();
+  a.hR = c->gm_hr.data();
   // the lower block-triangular (Schur) preconditioner of a displacement /
   // pressure tangent: two more work vectors, and the SIMPLE diagonal of this
   // linearization when asked for
@@ -365,7 +439,17 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
   while (true) {
     int queued = 0;
     for (int j = 0; j < m && total + queued < o.max_it; ++j) {
-      const void *vj = static_cast<const char *>(a.V) + size_t(j) * vb;
+      if (j + 2 > filled) {
+        // column j writes basis vector j + 1
+        nle_status s = gmres_reserve(c, a, vb, std::min(m + 1, j + 2), &filled);
+        if (s != NLE_OK) {
+          c->elem_skip = nullptr;
+          return s;
+        }
+        a.hV = c->gm_hv.data();
+        a.hR = c->gm_hr.data();
+      }
+      const void *vj = a.hV[j];
       hipError_t e = precond(vj, a.z);
       if (e == hipSuccess)
         elem_apply(c, OP_JV, prec,

@@ -567,44 +567,56 @@ __global__ __launch_bounds__(NT) void k_mr_e(T *x, T *v, const T *y, const T *av
 }
 
 // ------------------------------------------------------------------ GMRES
-// Device layout of GmresArgs::H (doubles, m = capacity):
-//   H[(m+1) * m] column-major Hessenberg, then cs[m], sn[m], g[m+1], y[m].
-// scal: [0] beta (norm of r0), [1] tolerance, [2] 1 / h(j+1, j), [3] current
-// residual estimate; flag: [0] done (1 converged, 3 breakdown), [1] columns
-// in the current cycle.
-__device__ __forceinline__ double *gm_cs(double *H, int m) { return H + (m + 1) * m; }
-__device__ __forceinline__ double *gm_sn(double *H, int m) { return H + (m + 1) * m + m; }
-__device__ __forceinline__ double *gm_g(double *H, int m) { return H + (m + 1) * m + 2 * m; }
-__device__ __forceinline__ double *gm_y(double *H, int m) { return H + (m + 1) * m + 3 * m + 1; }
+// Device data (m = cycle length): Hessenberg column j (rows 0..j+1) at
+// Hp[j]; rot = cs[m], sn[m], g[m+1], y[m]; basis vector i at Vp[i]; partial
+// row i at Rp[i].  scal: [0] beta (norm of r0), [1] tolerance, [2] 1 / h(j+1,
+// j), [3] current residual estimate; flag: [0] done (1 converged, 3
+// breakdown, 4 cycle full), [1] columns in the current cycle.
+__device__ __forceinline__ double *gm_cs(double *rot, int) { return rot; }
+__device__ __forceinline__ double *gm_sn(double *rot, int m) { return rot + m; }
+__device__ __forceinline__ double *gm_g(double *rot, int m) { return rot + 2 * m; }
+__device__ __forceinline__ double *gm_y(double *rot, int m) { return rot + 3 * m + 1; }
+
+// table entries of one pool segment
+__global__ __launch_bounds__(NT) void k_gm_tables(void **Vp, double **Hp, double **Rp, int v0,
+                                                  int nv, int limit, char *vbase, size_t vb,
+                                                  double *hbase, double *rbase) {
+  const int t = blockIdx.x * NT + threadIdx.x;
+  if (t >= nv || v0 + t >= limit) return;
+  Vp[v0 + t] = vbase + size_t(t) * vb;
+  // column v0 + l holds v0 + l + 2 rows
+  Hp[v0 + t] = hbase + (int64_t(t) * (v0 + 2) + int64_t(t) * (t - 1) / 2);
+  Rp[v0 + t] = rbase + int64_t(t) * VGRID_MAX;
+}
 
 // partials of V_i . w for i = blockIdx.y
 template <typename T>
-__global__ __launch_bounds__(NT) void k_gm_dots(const T *V, const T *w, int64_t n, double *red,
-                                                const int32_t *flag) {
+__global__ __launch_bounds__(NT) void k_gm_dots(T *const *Vp, const T *w, int64_t n,
+                                                double *const *Rp, const int32_t *flag) {
   __shared__ T sh[NT / 64];
   if (flag[0] != 0) return;
-  const T *vi = V + int64_t(blockIdx.y) * n;
+  const T *vi = Vp[blockIdx.y];
   T acc = T(0);
   for (int64_t k = int64_t(blockIdx.x) * NT + threadIdx.x; k < n; k += int64_t(gridDim.x) * NT)
     acc += vi[k] * w[k];
   acc = block_sum_all(acc, sh);
-  if (threadIdx.x == 0) red[int64_t(blockIdx.y) * VGRID_MAX + blockIdx.x] = double(acc);
+  if (threadIdx.x == 0) Rp[blockIdx.y][blockIdx.x] = double(acc);
 }
 
-// hc[i] (+)= sum of partials of dot i, one workgroup per i
-__global__ __launch_bounds__(NT) void k_gm_reduce(const double *red, int np, double *hc, int add,
+// hc[i] (+)= sum of partials of dot i (row Rp[i]), one workgroup per i
+__global__ __launch_bounds__(NT) void k_gm_reduce(double *const *Rp, int np, double *hc, int add,
                                                   const int32_t *flag) {
   __shared__ double sh[NT / 64];
   if (flag[0] != 0) return;
-  const double s = sum_partials(red + int64_t(blockIdx.x) * VGRID_MAX, np, sh);
+  const double s = sum_partials(Rp[blockIdx.x], np, sh);
   if (threadIdx.x == 0) hc[blockIdx.x] = add ? hc[blockIdx.x] + s : s;
 }
 
-// w -= sum_{i<=j} h_i V_i, with h the second argument (pass-specific copy);
+// w -= sum_{i<j1} h_i V_i, with h the second argument (pass-specific copy);
 // if want_sq, partials of w.w
 template <typename T>
-__global__ __launch_bounds__(NT) void k_gm_sub(const T *V, T *w, int64_t n, const double *h, int j1,
-                                               double *red_sq, const int32_t *flag) {
+__global__ __launch_bounds__(NT) void k_gm_sub(T *const *Vp, T *w, int64_t n, const double *h,
+                                               int j1, double *red_sq, const int32_t *flag) {
   __shared__ T sh[NT / 64];
   __shared__ double hs[256];
   if (flag[0] != 0) return;
@@ -613,7 +625,7 @@ __global__ __launch_bounds__(NT) void k_gm_sub(const T *V, T *w, int64_t n, cons
   T acc = T(0);
   for (int64_t k = int64_t(blockIdx.x) * NT + threadIdx.x; k < n; k += int64_t(gridDim.x) * NT) {
     double wk = double(w[k]);
-    for (int i = 0; i < j1; ++i) wk -= (i < 256 ? hs[i] : h[i]) * double(V[int64_t(i) * n + k]);
+    for (int i = 0; i < j1; ++i) wk -= (i < 256 ? hs[i] : h[i]) * double(Vp[i][k]);
     const T t = T(wk);
     w[k] = t;
     acc += t * t;
@@ -625,17 +637,18 @@ __global__ __launch_bounds__(NT) void k_gm_sub(const T *V, T *w, int64_t n, cons
 }
 
 // Finish column j: h(j+1,j) = ||w||, Givens rotations, residual test.
-__global__ void k_gm_col(double *H, int m, int j, const double *red_sq, int np, const double *hc1,
-                         const double *hc2, double *scal, int32_t *flag, int max_cols) {
+__global__ void k_gm_col(double *const *Hp, double *rot, int m, int j, const double *red_sq,
+                         int np, const double *hc1, const double *hc2, double *scal,
+                         int32_t *flag, int max_cols) {
   __shared__ double sh[NT / 64];
   if (flag[0] != 0) return;
   const double ww = sum_partials(red_sq, np, sh);
   if (threadIdx.x != 0) return;
-  double *col = H + int64_t(m + 1) * j;
+  double *col = Hp[j];
   for (int i = 0; i <= j; ++i) col[i] = hc1[i] + (hc2 ? hc2[i] : 0.0);
   const double hn = sqrt(ww);
   col[j + 1] = hn;
-  double *cs = gm_cs(H, m), *sn = gm_sn(H, m), *g = gm_g(H, m);
+  double *cs = gm_cs(rot, m), *sn = gm_sn(rot, m), *g = gm_g(rot, m);
   for (int i = 0; i < j; ++i) {
     const double t = cs[i] * col[i] + sn[i] * col[i + 1];
     col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
@@ -675,26 +688,27 @@ __global__ __launch_bounds__(NT) void k_gm_next(const T *w, T *vn, int64_t n, co
     vn[k] = w[k] * s;
 }
 
-// Back substitution H(0:k,0:k) y = g(0:k), k = flag[1].
-__global__ void k_gm_solve(double *H, int m, const int32_t *flag) {
+// Back substitution R(0:k,0:k) y = g(0:k), k = flag[1] (R: the rotated
+// Hessenberg columns).
+__global__ void k_gm_solve(double *const *Hp, double *rot, int m, const int32_t *flag) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const int k = flag[1];
-  double *g = gm_g(H, m), *y = gm_y(H, m);
+  double *g = gm_g(rot, m), *y = gm_y(rot, m);
   for (int i = k - 1; i >= 0; --i) {
     double s = g[i];
-    for (int l = i + 1; l < k; ++l) s -= H[int64_t(m + 1) * l + i] * y[l];
-    const double d = H[int64_t(m + 1) * i + i];
+    for (int l = i + 1; l < k; ++l) s -= Hp[l][i] * y[l];
+    const double d = Hp[i][i];
     y[i] = d != 0.0 ? s / d : 0.0;
   }
 }
 
 // x += M^-1 (sum_i y_i V_i)
 template <typename T, int BS>
-__global__ __launch_bounds__(NT) void k_gm_update(const T *V, T *x, const T *dinv, int64_t n,
-                                                  const double *H, int m, const int32_t *flag) {
+__global__ __launch_bounds__(NT) void k_gm_update(T *const *Vp, T *x, const T *dinv, int64_t n,
+                                                  const double *rot, int m, const int32_t *flag) {
   __shared__ double ys[256];
   const int k = flag[1];
-  const double *y = H + (m + 1) * m + 3 * m + 1;
+  const double *y = rot + 3 * m + 1;
   for (int i = threadIdx.x; i < k && i < 256; i += NT) ys[i] = y[i];
   __syncthreads();
   const int64_t nu = n / BS;
@@ -704,7 +718,7 @@ __global__ __launch_bounds__(NT) void k_gm_update(const T *V, T *x, const T *din
     for (int c = 0; c < BS; ++c) {
       const int64_t q = BS * u + c;
       s[c] = 0.0;
-      for (int i = 0; i < k; ++i) s[c] += (i < 256 ? ys[i] : y[i]) * double(V[int64_t(i) * n + q]);
+      for (int i = 0; i < k; ++i) s[c] += (i < 256 ? ys[i] : y[i]) * double(Vp[i][q]);
     }
     if constexpr (BS == 1) {
       const double d = dinv ? double(dinv[u]) : 1.0;
@@ -724,7 +738,7 @@ __global__ __launch_bounds__(NT) void k_gm_update(const T *V, T *x, const T *din
 // Start of a cycle: V_0 = r0 / ||r0|| given partials of r0.r0; initialise g.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_gm_start(const T *r0, T *V0, int64_t n, const double *red,
-                                                 int np, double *H, int m, double *scal,
+                                                 int np, double *rot, int m, double *scal,
                                                  int32_t *flag, double rtol, double atol,
                                                  int first) {
   __shared__ double sh[NT / 64];
@@ -734,9 +748,8 @@ __global__ __launch_bounds__(NT) void k_gm_start(const T *r0, T *V0, int64_t n, 
     if (first) scal[1] = fmax(rtol * beta, atol);
     scal[0] = beta;
     scal[3] = beta;
-    double *g = gm_g(H, m);
-    for (int i = 0; i <= m; ++i) g[i] = 0.0;
-    g[0] = beta;
+    // g[j + 1] is written by column j before anything reads it
+    gm_g(rot, m)[0] = beta;
     flag[1] = 0;
     flag[0] = !(beta == beta) ? 3 : (beta <= scal[1] ? 1 : 0);
   }
@@ -1063,46 +1076,57 @@ hipError_t mr_iterate(Ctx *c, const MinresArgs &a,
 }
 
 // ------------------------------------------------------------------ GMRES
+hipError_t gmres_tables(Ctx *c, const GmresArgs &a, int v0, int nv, int limit, void *vbase,
+                        size_t vb, double *hbase, double *rbase) {
+  if (nv <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gm_tables, dim3((nv + NT - 1) / NT), dim3(NT), 0, c->stream, a.Vp, a.Hp,
+                     a.Rp, v0, nv, limit, static_cast<char *>(vbase), vb, hbase, rbase);
+  return hipGetLastError();
+}
+
 hipError_t gmres_start(Ctx *c, const GmresArgs &a, const void *r0, double rtol, double atol,
                        int first) {
   const int g = vgrid(a.n);
   hipError_t e;
-  vec_dot_partials(c, a.prec, r0, r0, a.n, a.red, &e);
+  double *red = a.hR[0];
+  vec_dot_partials(c, a.prec, r0, r0, a.n, red, &e);
   if (e != hipSuccess) return e;
   if (a.prec == NLE_FP32)
-    LAUNCH(k_gm_start<float>, g, static_cast<const float *>(r0), static_cast<float *>(a.V), a.n,
-           a.red, g, a.H, a.m, a.scal, a.flag, rtol, atol, first);
+    LAUNCH(k_gm_start<float>, g, static_cast<const float *>(r0), static_cast<float *>(a.hV[0]),
+           a.n, red, g, a.rot, a.m, a.scal, a.flag, rtol, atol, first);
   else
-    LAUNCH(k_gm_start<double>, g, static_cast<const double *>(r0), static_cast<double *>(a.V), a.n,
-           a.red, g, a.H, a.m, a.scal, a.flag, rtol, atol, first);
+    LAUNCH(k_gm_start<double>, g, static_cast<const double *>(r0), static_cast<double *>(a.hV[0]),
+           a.n, red, g, a.rot, a.m, a.scal, a.flag, rtol, atol, first);
   return hipGetLastError();
 }
 
-// h = V_{0..j}^T w into hc (pass 0: scal area A, pass 1: area B)
+// partials of V_i . w, i <= j, into rows 0..j
 hipError_t gmres_multidot(Ctx *c, const GmresArgs &a, int j) {
   const int g = vgrid(a.n);
   if (a.prec == NLE_FP32)
     hipLaunchKernelGGL(k_gm_dots<float>, dim3(g, j + 1), dim3(NT), 0, c->stream,
-                       static_cast<const float *>(a.V), static_cast<const float *>(a.w), a.n, a.red, a.flag);
+                       reinterpret_cast<float *const *>(a.Vp), static_cast<const float *>(a.w),
+                       a.n, a.Rp, a.flag);
   else
     hipLaunchKernelGGL(k_gm_dots<double>, dim3(g, j + 1), dim3(NT), 0, c->stream,
-                       static_cast<const double *>(a.V), static_cast<const double *>(a.w), a.n, a.red, a.flag);
+                       reinterpret_cast<double *const *>(a.Vp), static_cast<const double *>(a.w),
+                       a.n, a.Rp, a.flag);
   return hipGetLastError();
 }
 
-// pass p: reduce the j+1 dots into hc_p, subtract; the last pass also
-// produces partials of w.w (in the partial row j+1 of a.red).
+// pass p: reduce the j+1 dots into hc_p (scal area p), subtract; the last
+// pass also produces partials of w.w.
 hipError_t gmres_subtract(Ctx *c, const GmresArgs &a, int j, int pass, int want_sq) {
   const int g = vgrid(a.n);
   double *hc = a.scal + 8 + pass * (a.m + 1);
-  hipLaunchKernelGGL(k_gm_reduce, dim3(j + 1), dim3(NT), 0, c->stream, a.red, g, hc, 0, a.flag);
-  double *red_sq = want_sq ? a.red + int64_t(a.m + 1) * VGRID_MAX : nullptr;
+  hipLaunchKernelGGL(k_gm_reduce, dim3(j + 1), dim3(NT), 0, c->stream, a.Rp, g, hc, 0, a.flag);
+  double *red_sq = want_sq ? a.redsq : nullptr;
   if (a.prec == NLE_FP32)
-    LAUNCH(k_gm_sub<float>, g, static_cast<const float *>(a.V), static_cast<float *>(a.w), a.n,
-           hc, j + 1, red_sq, a.flag);
+    LAUNCH(k_gm_sub<float>, g, reinterpret_cast<float *const *>(a.Vp), static_cast<float *>(a.w),
+           a.n, hc, j + 1, red_sq, a.flag);
   else
-    LAUNCH(k_gm_sub<double>, g, static_cast<const double *>(a.V), static_cast<double *>(a.w), a.n,
-           hc, j + 1, red_sq, a.flag);
+    LAUNCH(k_gm_sub<double>, g, reinterpret_cast<double *const *>(a.Vp),
+           static_cast<double *>(a.w), a.n, hc, j + 1, red_sq, a.flag);
   return hipGetLastError();
 }
 
@@ -1112,20 +1136,18 @@ hipError_t gmres_mgs_step(Ctx *c, const GmresArgs &a, int i, int j) {
   const int g = vgrid(a.n);
   hipError_t e;
   const int64_t n = a.n;
-  const size_t es = a.prec == NLE_FP32 ? 4 : 8;
-  const void *vi = static_cast<const char *>(a.V) + size_t(i) * n * es;
-  vec_dot_partials(c, a.prec, vi, a.w, n, a.red, &e);
+  vec_dot_partials(c, a.prec, a.hV[i], a.w, n, a.hR[0], &e);
   if (e != hipSuccess) return e;
   double *hc = a.scal + 8;
-  hipLaunchKernelGGL(k_gm_reduce, dim3(1), dim3(NT), 0, c->stream, a.red, g, hc + i, 0, a.flag);
+  hipLaunchKernelGGL(k_gm_reduce, dim3(1), dim3(NT), 0, c->stream, a.Rp, g, hc + i, 0, a.flag);
   const bool last = (i == j);
-  double *red_sq = last ? a.red + int64_t(a.m + 1) * VGRID_MAX : nullptr;
+  double *red_sq = last ? a.redsq : nullptr;
   if (a.prec == NLE_FP32)
-    LAUNCH(k_gm_sub<float>, g, static_cast<const float *>(vi), static_cast<float *>(a.w), n,
-           hc + i, 1, red_sq, a.flag);
+    LAUNCH(k_gm_sub<float>, g, reinterpret_cast<float *const *>(a.Vp) + i,
+           static_cast<float *>(a.w), n, hc + i, 1, red_sq, a.flag);
   else
-    LAUNCH(k_gm_sub<double>, g, static_cast<const double *>(vi), static_cast<double *>(a.w), n,
-           hc + i, 1, red_sq, a.flag);
+    LAUNCH(k_gm_sub<double>, g, reinterpret_cast<double *const *>(a.Vp) + i,
+           static_cast<double *>(a.w), n, hc + i, 1, red_sq, a.flag);
   return hipGetLastError();
 }
 
@@ -1133,10 +1155,9 @@ hipError_t gmres_finish_col(Ctx *c, const GmresArgs &a, int j, int mgs) {
   const int g = vgrid(a.n);
   const double *hc1 = a.scal + 8;
   const double *hc2 = mgs ? nullptr : a.scal + 8 + (a.m + 1);
-  hipLaunchKernelGGL(k_gm_col, dim3(1), dim3(NT), 0, c->stream, a.H, a.m, j,
-                     a.red + int64_t(a.m + 1) * VGRID_MAX, g, hc1, hc2, a.scal, a.flag, a.m);
-  const size_t es = a.prec == NLE_FP32 ? 4 : 8;
-  void *vn = static_cast<char *>(a.V) + size_t(j + 1) * a.n * es;
+  hipLaunchKernelGGL(k_gm_col, dim3(1), dim3(NT), 0, c->stream, a.Hp, a.rot, a.m, j, a.redsq, g,
+                     hc1, hc2, a.scal, a.flag, a.m);
+  void *vn = a.hV[j + 1];
   if (a.prec == NLE_FP32)
     LAUNCH(k_gm_next<float>, g, static_cast<const float *>(a.w), static_cast<float *>(vn), a.n,
            a.scal, a.flag);
@@ -1147,11 +1168,11 @@ hipError_t gmres_finish_col(Ctx *c, const GmresArgs &a, int j, int mgs) {
 }
 
 hipError_t gmres_update_x(Ctx *c, const GmresArgs &a) {
-  hipLaunchKernelGGL(k_gm_solve, dim3(1), dim3(64), 0, c->stream, a.H, a.m, a.flag);
+  hipLaunchKernelGGL(k_gm_solve, dim3(1), dim3(64), 0, c->stream, a.Hp, a.rot, a.m, a.flag);
   const int g = vgrid(a.n);
 #define GM_UPD(T, BS)                                                                          \
-  LAUNCH((k_gm_update<T, BS>), g, static_cast<const T *>(a.V), static_cast<T *>(a.x),           \
-         static_cast<const T *>(a.dinv), a.n, a.H, a.m, a.flag)
+  LAUNCH((k_gm_update<T, BS>), g, reinterpret_cast<T *const *>(a.Vp), static_cast<T *>(a.x),    \
+         static_cast<const T *>(a.dinv), a.n, a.rot, a.m, a.flag)
   if (a.prec == NLE_FP32) {
     if (a.pcb == 3) GM_UPD(float, 3); else GM_UPD(float, 1);
   } else {

@@ -242,11 +242,12 @@ def setup_twist_p0(ctx: nl.Context, mesh, params=TWIST_M5) -> None:
 
 
 def solve_twist(ctx: nl.Context, x, method: str, opts, angles, dirichlet, hist_cap: int = 4096,
-                max_cuts: int = 8, start: float = 0.0):
+                max_cuts: int = 8, start: float = 0.0, progress=None):
     """Rotate the top face through the given angles in turn (warm-started).
     dirichlet(theta) -> (dofs, values).  A failed step is retried from the last
     converged state at the mid angle (at most max_cuts times in total).
-    Reports carry 'theta' and 'accepted'."""
+    Reports carry 'theta' and 'accepted'; progress(rep) is called after each
+    attempt."""
     reps = []
     targets = [float(a) for a in angles]
     backup = x.clone()
@@ -260,6 +261,8 @@ def solve_twist(ctx: nl.Context, x, method: str, opts, angles, dirichlet, hist_c
         st, rep = SOLVERS[method](ctx, x, opts, hist_cap)
         rep.update(theta=th, accepted=st == nl.NLE_OK)
         reps.append(rep)
+        if progress is not None:
+            progress(rep)
         if st == nl.NLE_OK:
             backup.copy_(x)
             prev = th

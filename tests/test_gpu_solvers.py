@@ -324,3 +324,39 @@ def test_cg_three_and_four_launch_forms_are_bitwise_equal(precision, pc):
     with pytest.raises(nl.NleError) as e:
         nl.nle_solve_ink(ctx, torch.zeros(P.n_dofs, dtype=torch.float64, device="cuda"), bad)
     assert e.value.status == nl.NLE_E_INVAL
+
+
+def test_unrestarted_gmres_grows_its_basis():
+    # the basis (with its Hessenberg columns and partial rows) is allocated as
+    # the cycle grows: an iteration limit of two million reserves no basis up
+    # front, and the iterates do not depend on how the pool was grown (fresh,
+    # reused, or after a restarted solve)
+    mesh, P, ctx = _cook(12, 12, 2, 50.0, be=128, tau=2.0)
+    ustar = _root("c12", P, [1.0])
+    runs = {}
+    for orth in ("mgs", "cgs2"):
+        for k in range(2):
+            u = torch.zeros(P.n_dofs, dtype=torch.float64, device="cuda")
+            o = problems.make_opts("nk", ksp="gmres", orth=orth)
+            o.ksp_max_it = 2_000_000
+            st, rep = nl.nle_solve_nk(ctx, u, o)
+            assert st == nl.NLE_OK, rep
+            runs[orth, k] = (u.cpu().numpy(), rep["lit_hist"])
+        assert np.array_equal(runs[orth, 0][0], runs[orth, 1][0])
+        assert runs[orth, 0][1] == runs[orth, 1][1]
+        assert max(runs[orth, 0][1]) > 128, runs[orth, 0][1]  # several segments
+        err = np.linalg.norm(runs[orth, 0][0] - ustar) / np.linalg.norm(ustar)
+        assert err <= 1e-6, (orth, err)
+    # a restarted solve in between, then a fresh context: same iterates
+    u = torch.zeros(P.n_dofs, dtype=torch.float64, device="cuda")
+    st, _ = nl.nle_solve_nk(ctx, u, problems.make_opts("nk", ksp="gmres", restart=30))
+    assert st == nl.NLE_OK
+    _, _, ctx2 = _cook(12, 12, 2, 50.0, be=128, tau=2.0)
+    for c in (ctx, ctx2):
+        u = torch.zeros(P.n_dofs, dtype=torch.float64, device="cuda")
+        o = problems.make_opts("nk", ksp="gmres", orth="mgs")
+        o.ksp_max_it = 2_000_000
+        st, rep = nl.nle_solve_nk(c, u, o)
+        assert st == nl.NLE_OK
+        assert np.array_equal(u.cpu().numpy(), runs["mgs", 0][0])
+        assert rep["lit_hist"] == runs["mgs", 0][1]
