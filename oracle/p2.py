@@ -142,3 +142,32 @@ def cook_p2_problem(mesh2, mu: float = 80.194, lam: float = 400.9, tau: float = 
     f = p2_traction(mesh2.X, mesh2.conn, mesh2.faces["load"], (0.0, tau, 0.0))
     dd = mesh2.dirichlet_dofs("clamp")
     return P2Problem(mesh2.X, mesh2.conn, materials.M1, (mu, lam), f, dd, np.zeros(dd.size))
+
+
+def shell_p2_problem(mesh2, consts: dict, gamma: float = 0.0, law=None) -> P2Problem:
+    """The ventricle shell with quadratic displacements: the cardiac-like law
+    M4 (or, with law = (C, b_ff, b_ss, b_nn, b_fs, b_fn, b_sn, B), Guccione's
+    law M6 with the mesh's sheets), the mesh's per-element fibres, active
+    tension gamma, and the shell's constraints (base plane held in z at its
+    vertices and edge midpoints, three circumferential pins).  No surface
+    loads: the endocardial pressure and epicardial springs act on P1 faces
+    only."""
+    from synthetic import shell_dirichlet
+
+    c = consts
+    if law is None:
+        material = materials.M4
+        params = (c["a"], c["b"], c["af"], c["bf"], c["kappa"], gamma, mesh2.elem_fibre)
+    else:
+        material = materials.M6
+        params = tuple(law) + (gamma, mesh2.elem_fibre, mesh2.elem_sheet)
+    dd = shell_dirichlet(mesh2)
+    return P2Problem(mesh2.X, mesh2.conn, material, params, np.zeros(3 * mesh2.X.shape[0]), dd,
+                     np.zeros(dd.size))
+
+
+def set_active_tension(problem: P2Problem, gamma: float) -> None:
+    """Replace the active tension gamma of an M4 or M6 problem."""
+    p = list(problem.params)
+    p[8 if problem.material == materials.M6 else 5] = gamma
+    problem.params = tuple(p)

@@ -346,7 +346,8 @@ def p2_from_p1(mesh: Mesh) -> Mesh:
     conn[:, 4:] = n1 + inv.reshape(ne, 6)
     sets = {k: np.concatenate([v, v[uniq[:, 0]] & v[uniq[:, 1]]]) for k, v in mesh.sets.items()}
     return Mesh(X=X, conn=conn.astype(np.int32), sets=sets, faces=dict(mesh.faces),
-                elem_fibre=mesh.elem_fibre, grid=mesh.grid, name=mesh.name + "_p2")
+                elem_fibre=mesh.elem_fibre, elem_sheet=mesh.elem_sheet, grid=mesh.grid,
+                name=mesh.name + "_p2")
 
 
 def cook_p2_mesh(nx: int, ny: int, nz: int) -> Mesh:
