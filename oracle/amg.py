@@ -55,6 +55,16 @@ with block size 3 and known coordinates):
 For a symmetric A the cycle is a symmetric operator (the post-smoother is
 the adjoint of the pre-smoother and restriction is the transpose of
 prolongation), so it can precondition CG as well as GMRES.
+
+Smoothed aggregation (setup(..., smooth=True)): the finest level's
+prolongator is the tentative one after one damped Jacobi step,
+P_0 = (I - omega D_0^-1 A_0) P_tent with omega = 4 / (3 rho_0), rho_0 the
+power estimate above; the coarser levels keep their tentative prolongators.
+On a floating body A_0 annihilates the rigid motions, so P_0 still
+reproduces them, and since |1 - omega lambda| <= 1 on the spectrum of
+D^-1 A the smoothing never raises a column's energy.  The coarse graph of
+level 1 is then the aggregates' member adjacency as before (A_1's own
+pattern is wider).
 """
 
 from __future__ import annotations
@@ -166,8 +176,13 @@ class Hierarchy:
         return len(self.A)
 
 
-def setup(K, X: np.ndarray, conn: np.ndarray, fixed: np.ndarray) -> Hierarchy:
-    """The hierarchy of K for the mesh (X, conn) with Dirichlet mask `fixed`."""
+SA_OMEGA = 4.0 / 3.0  # omega rho_0 of the smoothed prolongator
+
+
+def setup(K, X: np.ndarray, conn: np.ndarray, fixed: np.ndarray,
+          smooth: bool = False) -> Hierarchy:
+    """The hierarchy of K for the mesh (X, conn) with Dirichlet mask `fixed`;
+    smooth: smoothed aggregation on the finest level."""
     K = sp.csr_matrix(K)
     n_nodes = X.shape[0]
     H = Hierarchy()
@@ -190,6 +205,10 @@ def setup(K, X: np.ndarray, conn: np.ndarray, fixed: np.ndarray) -> Hierarchy:
             members[agg[v]].append(v)
         rows_of = [[r for v in m for r in vdofs[v]] for m in members]
         P, Bn, kc = tentative(B, rows_of)
+        if smooth and not H.P:
+            # one damped Jacobi step on the tentative columns
+            omega = SA_OMEGA * H.w[-1]
+            P = (P - omega * (sp.diags(1.0 / H.D[-1]) @ (A @ P))).tocsr()
         H.P.append(P)
         H.aggs.append(agg)
         H.kcount.append(kc)

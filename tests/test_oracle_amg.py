@@ -207,3 +207,57 @@ def test_pressure_block_of_the_field_split_is_the_lumped_mass():
         V = abs(np.linalg.det(np.column_stack([x[1] - x[0], x[2] - x[0], x[3] - x[0]]))) / 6.0
         Mc[np.ix_(pconn[e], pconn[e])] += V * (np.ones((4, 4)) + np.eye(4)) / 20.0
     assert np.allclose(Mc.sum(1), ml, rtol=1e-13, atol=0.0)
+
+
+# ---------------------------------------------------- smoothed aggregation
+def test_smoothed_prolongator_reproduces_rigid_motions_on_a_floating_body():
+    # A annihilates the rigid motions, so one Jacobi step leaves them alone:
+    # P_s (coarse coordinates of a rigid motion) = the rigid motion
+    mesh, P, K, fixed = _cook(12, 10, 2, dirichlet=False)
+    Ht = amg.setup(K, mesh.X, mesh.conn, fixed)
+    Hs = amg.setup(K, mesh.X, mesh.conn, fixed, smooth=True)
+    rng = np.random.default_rng(6)
+    t, w = rng.standard_normal(3), rng.standard_normal(3)
+    u = (t[None, :] + np.cross(w[None, :], mesh.X)).reshape(-1)
+    c = Ht.P[0].T @ u  # coordinates in the tentative (orthonormal) basis
+    assert np.linalg.norm(Ht.P[0] @ c - u) <= 1e-10 * np.linalg.norm(u)
+    assert np.linalg.norm(Hs.P[0] @ c - u) <= 1e-9 * np.linalg.norm(u)
+    # and the Galerkin operator annihilates them
+    A1 = Hs.A[1]
+    assert np.linalg.norm(A1 @ c) <= 1e-9 * abs(A1).max() * np.linalg.norm(c)
+    assert abs(A1 - A1.T).max() <= 1e-12 * abs(A1).max()
+
+
+def test_smoothing_lowers_every_prolongator_columns_energy():
+    # |1 - omega lambda| <= 1 on the spectrum of D^-1 A (omega rho = 4/3 with
+    # rho the power estimate, which falls short of the true radius by a few
+    # percent at most), so no column's A-energy rises, and the total drops
+    mesh, P, K, fixed = _cook(10, 8, 2)
+    Ht = amg.setup(K, mesh.X, mesh.conn, fixed)
+    Hs = amg.setup(K, mesh.X, mesh.conn, fixed, smooth=True)
+    Pt, Ps = Ht.P[0], Hs.P[0]
+    et = np.asarray((Pt.multiply(K @ Pt)).sum(axis=0)).ravel()
+    es = np.asarray((Ps.multiply(K @ Ps)).sum(axis=0)).ravel()
+    keep = et > 1e-12 * et.max()
+    assert np.all(es[keep] <= et[keep] * (1.0 + 1e-12))
+    assert es.sum() < 0.7 * et.sum(), (es.sum(), et.sum())
+    # the smoothed columns reach one node ring beyond their aggregates
+    assert Ps.nnz > 1.5 * Pt.nnz
+
+
+def test_smoothed_cycle_is_spd_and_needs_fewer_iterations():
+    mesh, P, K, fixed = _cook(8, 8, 1)
+    Hs = amg.setup(K, mesh.X, mesh.conn, fixed, smooth=True)
+    n = P.n_dofs
+    M = np.column_stack([amg.vcycle(Hs, e) for e in np.eye(n)])
+    assert np.abs(M - M.T).max() <= 1e-12 * np.abs(M).max()
+    assert np.linalg.eigvalsh(0.5 * (M + M.T)).min() > 0.0
+    mesh, P, K, fixed = _cook(16, 16, 2, ratio=500.0)
+    b = -P.residual(np.zeros(P.n_dofs), 1.0)
+    its = []
+    for smooth in (False, True):
+        H = amg.setup(K, mesh.X, mesh.conn, fixed, smooth=smooth)
+        x, it = amg.gmres_amg(K, H, b, 1e-8, max_it=800)
+        assert np.linalg.norm(b - K @ x) <= 1.01e-8 * np.linalg.norm(b)
+        its.append(it)
+    assert its[1] < its[0], its
