@@ -182,7 +182,7 @@ def jv_roofline(nl, torch, reps: int):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("nle_elem.hip", "nle_kin.hpp"):
+    for f in ("nle_elem.hip", "nle_kin.hpp", "nle_laws.hpp"):
         with open(os.path.join(ROOT, "paper_2203_05610_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

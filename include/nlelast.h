@@ -80,7 +80,8 @@ typedef int32_t nle_status;
  *    reference when 2 alpha_p + 4 beta_p = 4 beta_s + 2 alpha_s); small-strain
  *    limit mu = 2 (alpha_p + beta_p), lambda = 4 beta_p. */
 #define NLE_MAT_M5 5
-/* M6 the heartbeat test's Guccione law (Sec. 4), P1 meshes, params
+/* M6 the heartbeat test's Guccione law (Sec. 4), P1 and quadratic
+ * displacement meshes, params
  * (C, b_ff, b_ss, b_nn, b_fs, b_fn, b_sn, B) (the constants are the
  * caller's; the paper refers to Guccione's paper for them):
  *      Psi = C/2 (exp(Q) - 1) + B/2 (J - 1) ln J + gamma sqrt(I4),
@@ -254,6 +255,15 @@ nle_status nle_set_block_size(nle_ctx *ctx, int32_t elems_per_block);
  *   X    [n_nodes][3] reference coordinates (double).
  *   conn [n_elems][4] node indices (int32), positively oriented:
  *        det[X1-X0, X2-X0, X3-X0] > 0.
+ * nodes_per_elem = 10 uploads quadratic displacement elements instead (the
+ * second-order runs of the Sec. 6 tables): conn [n_elems][10] as in
+ * nle_upload_mesh_mixed, no pressure field, laws M1, M2, M4 and M6 at the
+ * four points of the degree-2 rule (per-element fibres and sheets in the
+ * caller's element order), Dirichlet data, active tension, and on 6-node
+ * faces (the vertex triangles passed as for P1 meshes, midpoints found from
+ * the elements) dead traction, follower pressure and springs; follower
+ * traction, body force, inertia and nodal blocks are NLE_E_UNSUPPORTED
+ * there.
  * Validates indices (0 <= i < n_nodes, no repeats within an element) and
  * volumes; on failure returns NLE_E_BADMESH and names the first bad element.
  * Precomputes shape-function gradients and volumes in FP64 (and an FP32
@@ -310,7 +320,8 @@ nle_status nle_set_body_force(nle_ctx *ctx, const double *f);
 /* Load factor s multiplying f_ext and the follower pressure (default 1). */
 nle_status nle_set_load_scale(nle_ctx *ctx, double s);
 /* Unit fibre direction per element for law M4: fib[n_elems][3] (host, user
- * element order, copied); NLE_E_INVAL unless every |f| = 1 to 1e-6. */
+ * element order, copied); NLE_E_INVAL unless every |f| = 1 to 1e-6.  P1 and
+ * quadratic displacement meshes; NLE_E_UNSUPPORTED with a pressure field. */
 nle_status nle_set_fibres(nle_ctx *ctx, const double *fib);
 /* Fibre frame per element for law M6: fib and sheet [n_elems][3] (host,
  * user element order, copied), unit vectors to 1e-6 and orthogonal to 1e-6

@@ -625,15 +625,18 @@ namespace {
 nle_status set_frame(Ctx *c, const double *fib, const double *sheet) {
   nle_status s = need_mesh(c);
   if (s != NLE_OK) return s;
-  if (c->mixed) return fail(c, NLE_E_UNSUPPORTED, "not available on mixed meshes");
+  if (c->mixed && c->mx.n_p > 0)
+    return fail(c, NLE_E_UNSUPPORTED, "fibres belong to meshes without a pressure field");
   if (!fib) return fail(c, NLE_E_INVAL, "null fibre array");
   return guarded(c, [&]() -> nle_status {
-    const int64_t ne = c->m.n_elems;
+    // P1 meshes store per-element data in the block order, quadratic
+    // displacement meshes in the caller's element order
+    const int64_t ne = c->mixed ? c->mx.n_e : c->m.n_elems;
     const int nv = sheet ? 2 : 1;
     std::vector<double> f64(3 * nv * ne);
     std::vector<float> f32(3 * nv * ne);
     for (int64_t k = 0; k < ne; ++k) {
-      const int64_t e = c->m.h_perm[k];
+      const int64_t e = c->mixed ? k : c->m.h_perm[k];
       for (int v = 0; v < nv; ++v) {
         const double *f = (v == 0 ? fib : sheet) + 3 * e;
         const double l2 = f[0] * f[0] + f[1] * f[1] + f[2] * f[2];
@@ -714,7 +717,8 @@ nle_status nle_set_pressure(nle_ctx *ctx, int64_t nf, const int32_t *tri, double
   Ctx *c = reinterpret_cast<Ctx *>(ctx);
   nle_status s = need_mesh(c);
   if (s != NLE_OK) return s;
-  if (c->mixed) return fail(c, NLE_E_UNSUPPORTED, "not available on mixed meshes");
+  if (c->mixed && c->mx.n_p > 0)
+    return fail(c, NLE_E_UNSUPPORTED, "surface loads need a mesh without a pressure field");
   if (!std::isfinite(p)) return fail(c, NLE_E_INVAL, "non-finite pressure");
   return guarded(c, [&]() -> nle_status {
     std::vector<int32_t> t;
@@ -820,7 +824,8 @@ nle_status nle_set_robin_damping(nle_ctx *ctx, double c_perp, double c_par) {
   Ctx *c = reinterpret_cast<Ctx *>(ctx);
   nle_status s = need_mesh(c);
   if (s != NLE_OK) return s;
-  if (c->mixed) return fail(c, NLE_E_UNSUPPORTED, "not available on mixed meshes");
+  if (c->mixed && c->mx.n_p > 0)
+    return fail(c, NLE_E_UNSUPPORTED, "surface loads need a mesh without a pressure field");
   if (!std::isfinite(c_perp) || !std::isfinite(c_par) || c_perp < 0.0 || c_par < 0.0)
     return fail(c, NLE_E_INVAL, "dashpot coefficients must be finite and >= 0");
   drop_graph(c);  // kernel arguments of captured chunks
@@ -870,7 +875,8 @@ nle_status nle_set_robin(nle_ctx *ctx, int64_t nf, const int32_t *tri, double k_
   Ctx *c = reinterpret_cast<Ctx *>(ctx);
   nle_status s = need_mesh(c);
   if (s != NLE_OK) return s;
-  if (c->mixed) return fail(c, NLE_E_UNSUPPORTED, "not available on mixed meshes");
+  if (c->mixed && c->mx.n_p > 0)
+    return fail(c, NLE_E_UNSUPPORTED, "surface loads need a mesh without a pressure field");
   if (!std::isfinite(k_perp) || !std::isfinite(k_par))
     return fail(c, NLE_E_INVAL, "non-finite spring constants");
   return guarded(c, [&]() -> nle_status {

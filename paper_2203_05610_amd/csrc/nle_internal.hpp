@@ -161,9 +161,10 @@ struct Ctx {
     int32_t *node = nullptr;     // [nsn] node ids
     int32_t *ptr = nullptr;      // [nsn+1] incident-face ranges
     int32_t *ent = nullptr;      // incident faces, increasing
-    int32_t *tri = nullptr;      // [npf+ntf+nrf][3]
-    uint32_t *fmask = nullptr;   // [npf+ntf+nrf] Dirichlet bits of the 3 vertices (3 each)
-    double *pgeo64 = nullptr;    // [npf+ntf][9] reference vertex coordinates
+    int32_t fv = 3;              // nodes per face: 3, or 6 on quadratic meshes
+    int32_t *tri = nullptr;      // [npf+ntf+nrf][fv]
+    uint32_t *fmask = nullptr;   // [npf+ntf+nrf] Dirichlet bits of the fv nodes (3 each)
+    double *pgeo64 = nullptr;    // [npf+ntf][3 fv] reference node coordinates
     float *pgeo32 = nullptr;
     double *rgeo64 = nullptr;    // [nrf][4] reference unit normal, area
     float *rgeo32 = nullptr;
@@ -288,8 +289,8 @@ inline int64_t ndof(const Ctx *c) { return 3 * c->m.n_nodes + (c->mixed ? c->mx.
 // The material must suit the mesh (M3 on mixed meshes only), and M4 needs fibres.
 inline nle_status need_fibres(Ctx *c) {
   if (c->mixed && c->mx.n_p == 0) {
-    if (c->mat.kind != NLE_MAT_M1)
-      return fail(c, NLE_E_STATE, "quadratic displacement meshes support law M1");
+    if (c->mat.kind == NLE_MAT_M3 || c->mat.kind == NLE_MAT_M5)
+      return fail(c, NLE_E_STATE, "laws M3 and M5 need a pressure field");
   } else if ((c->mat.kind == NLE_MAT_M3 || c->mat.kind == NLE_MAT_M5) != c->mixed) {
     return fail(c, NLE_E_STATE,
                 "laws M3 and M5 go with a mixed mesh, the other laws with P1 meshes");

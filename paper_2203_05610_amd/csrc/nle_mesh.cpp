@@ -152,6 +152,21 @@ nle_status build_mesh(Ctx *c, int64_t nn, const double *X, int64_t ne, const int
     bn.erase(std::unique(bn.begin(), bn.end()), bn.end());
     const int32_t nl = int32_t(bn.size());
     if (nl > 65535) return fail(c, NLE_E_UNSUPPORTED, "block touches more than 65535 nodes");
+    // slots in decreasing order of their contribution counts (then by node
+    // id): the node sums of one wave then run loops of similar length
+    {
+      for (int32_t l = 0; l < nl; ++l) loc[bn[l]] = l;
+      std::vector<int32_t> nc(nl, 0);
+      for (int64_t k = e0; k < e1; ++k)
+        for (int a = 0; a < 4; ++a) nc[loc[conn[4 * perm[k] + a]]] += 1;
+      std::vector<int32_t> ord(nl);
+      std::iota(ord.begin(), ord.end(), 0);
+      std::stable_sort(ord.begin(), ord.end(),
+                       [&](int32_t x, int32_t y) { return nc[x] > nc[y]; });
+      std::vector<int32_t> sorted(nl);
+      for (int32_t l = 0; l < nl; ++l) sorted[l] = bn[ord[l]];
+      bn.swap(sorted);
+    }
     for (int32_t l = 0; l < nl; ++l) {
       loc[bn[l]] = l;
       touch[bn[l]] += 1;

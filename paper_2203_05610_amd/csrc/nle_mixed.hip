@@ -43,6 +43,7 @@
 
 #include "nle_internal.hpp"
 #include "nle_kin.hpp"
+#include "nle_laws.hpp"
 
 namespace nle {
 
@@ -63,17 +64,187 @@ struct MixArgs {
   T *cu, *cp;
   double mu, lam;
   double ap, bp, cs;  // law M5: alpha_p, beta_p, 4 beta_s + 2 alpha_s
+  MatParams mp;       // laws M2, M4, M6 (no pressure field)
+  const T *fib, *sheet;  // [3][n_e] per-element fibre and sheet (M4, M6)
   double *red;
   int32_t *flag;
   const int32_t *skip;
   int32_t nomask;
 };
 
-// LAW: NLE_MAT_M3 or NLE_MAT_M5 (with a pressure field), NLE_MAT_M1 (none).
-// NPE: pressure values per element, 4 (linear) or 1 (constant).
+// One quadrature point of a compressible law without a pressure field in the
+// common form of nle_laws.hpp:
+//   P  = a F + pT F^-T + h1 (F f) (x) f  [+ F S, law M6]
+//   dP = a dF + (cF L + cFF F:dF) F + (cT L + cM F:dF) F^-T + cX F^-T dF^T F^-T
+//        + h1 (dF f) (x) f + h2 ((F f).(dF f)) (F f) (x) f
+//        [+ dF S + F dS(sym(F^T dF)), law M6],
+// contributions w P grad N_a (residual), w dP grad N_a (action) or the
+// diagonal of the point's tangent for dF = e_i (x) grad N_a.
+template <typename T, int OP, int LAW>
+__device__ __forceinline__ void gen_point(const MixArgs<T> &A, const T H[3][3], const Kin<T> &k,
+                                          const T f[3], const T sh[3], const T gN[10][3],
+                                          const T W[10][3], double w, T cu[10][3],
+                                          double &eacc) {
+  const MatParams &mp = A.mp;
+  FibreKin fk;
+  fk.e4 = 0.0;
+  fk.Ff[0] = fk.Ff[1] = fk.Ff[2] = 0.0;
+  if (has_fibre<LAW>()) fk = fibre_kinematics(H, f);
+  Guc<T> gu;
+  if (LAW == NLE_MAT_M6) guccione(H, f, sh, mp, gu);
+  if (OP == OP_ENERGY) {
+    double psi = energy_density<LAW>(k, H, fk, mp);
+    if (LAW == NLE_MAT_M6) psi += 0.5 * mp.g6[0] * expm1(gu.Q);
+    eacc += w * psi;
+    return;
+  }
+  const Coef cf = coefficients<LAW>(k, H, fk, mp);
+  T Ff[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) Ff[i] = T(fk.Ff[i]);
+  const T tw = T(w);
+  if (OP == OP_RES) {
+    const T ca = T(cf.a), cp = T(cf.pT), ch = T(cf.h1);
+    T P[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        T t = ca * k.F[i][j] + cp * k.FiT[i][j];
+        if (has_fibre<LAW>()) t += ch * Ff[i] * f[j];
+        if (LAW == NLE_MAT_M6)
+          t += k.F[i][0] * gu.S[0][j] + k.F[i][1] * gu.S[1][j] + k.F[i][2] * gu.S[2][j];
+        P[i][j] = tw * t;
+      }
+#pragma unroll
+    for (int a = 0; a < 10; ++a)
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        cu[a][i] += P[i][0] * gN[a][0] + P[i][1] * gN[a][1] + P[i][2] * gN[a][2];
+  } else if (OP == OP_JV) {
+    T dF[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        T s = T(0);
+#pragma unroll
+        for (int a = 0; a < 10; ++a) s += W[a][i] * gN[a][j];
+        dF[i][j] = s;
+      }
+    T L = T(0), FdF = T(0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        L += k.FiT[i][j] * dF[i][j];
+        FdF += k.F[i][j] * dF[i][j];
+      }
+    T M[3][3];  // dF^T F^-T
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        M[r][j] = dF[0][r] * k.FiT[0][j] + dF[1][r] * k.FiT[1][j] + dF[2][r] * k.FiT[2][j];
+    const T sF = T(cf.cF) * L + T(cf.cFF) * FdF, sT = T(cf.cT) * L + T(cf.cM) * FdF;
+    T dFf[3] = {T(0), T(0), T(0)}, s2 = T(0);
+    if (has_fibre<LAW>()) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) dFf[i] = dF[i][0] * f[0] + dF[i][1] * f[1] + dF[i][2] * f[2];
+      s2 = T(cf.h2) * (Ff[0] * dFf[0] + Ff[1] * dFf[1] + Ff[2] * dFf[2]);
+    }
+    T dS[3][3];
+    if (LAW == NLE_MAT_M6) {
+      T dE[3][3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          dE[i][j] = T(0.5) * (k.F[0][i] * dF[0][j] + k.F[1][i] * dF[1][j] + k.F[2][i] * dF[2][j] +
+                               dF[0][i] * k.F[0][j] + dF[1][i] * k.F[1][j] + dF[2][i] * k.F[2][j]);
+      guccione_dS(gu, dE, mp, dS);
+    }
+    T dP[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const T X = k.FiT[i][0] * M[0][j] + k.FiT[i][1] * M[1][j] + k.FiT[i][2] * M[2][j];
+        T t = T(cf.a) * dF[i][j] + sF * k.F[i][j] + sT * k.FiT[i][j] + T(cf.cX) * X;
+        if (has_fibre<LAW>()) t += (T(cf.h1) * dFf[i] + s2 * Ff[i]) * f[j];
+        if (LAW == NLE_MAT_M6)
+          t += dF[i][0] * gu.S[0][j] + dF[i][1] * gu.S[1][j] + dF[i][2] * gu.S[2][j] +
+               k.F[i][0] * dS[0][j] + k.F[i][1] * dS[1][j] + k.F[i][2] * dS[2][j];
+        dP[i][j] = tw * t;
+      }
+#pragma unroll
+    for (int a = 0; a < 10; ++a)
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        cu[a][i] += dP[i][0] * gN[a][0] + dP[i][1] * gN[a][1] + dP[i][2] * gN[a][2];
+  } else if (OP == OP_DIAG) {
+    // dF = e_i (x) g: w = F^-T g, z = F g give
+    // a |g|^2 + (cF + cM) w_i z_i + cFF z_i^2 + (cT + cX) w_i^2 + (h1 + h2 (Ff)_i^2) (g.f)^2
+    // and, for law M6, g.S g + C e^Q (bm : dEb^2 + 2 (bE : dEb)^2) with
+    // dEb = sym(rb (x) gb), rb = R^T F^T e_i, gb = R^T g
+    const T c1 = T(cf.cF + cf.cM), c2 = T(cf.cT + cf.cX);
+    T rb[3][3];
+    if (LAW == NLE_MAT_M6) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+          rb[i][b] = gu.R[0][b] * k.F[i][0] + gu.R[1][b] * k.F[i][1] + gu.R[2][b] * k.F[i][2];
+    }
+#pragma unroll
+    for (int a = 0; a < 10; ++a) {
+      const T gg = gN[a][0] * gN[a][0] + gN[a][1] * gN[a][1] + gN[a][2] * gN[a][2];
+      const T gf = gN[a][0] * f[0] + gN[a][1] * f[1] + gN[a][2] * f[2];
+      T gSg = T(0), gb[3] = {T(0), T(0), T(0)};
+      if (LAW == NLE_MAT_M6) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) gSg += gN[a][i] * gu.S[i][j] * gN[a][j];
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+          gb[b] = gu.R[0][b] * gN[a][0] + gu.R[1][b] * gN[a][1] + gu.R[2][b] * gN[a][2];
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const T wi = k.FiT[i][0] * gN[a][0] + k.FiT[i][1] * gN[a][1] + k.FiT[i][2] * gN[a][2];
+        const T zi = k.F[i][0] * gN[a][0] + k.F[i][1] * gN[a][1] + k.F[i][2] * gN[a][2];
+        T dg = T(cf.a) * gg + c1 * wi * zi + c2 * wi * wi + T(cf.cFF) * zi * zi;
+        if (has_fibre<LAW>()) dg += (T(cf.h1) + T(cf.h2) * Ff[i] * Ff[i]) * gf * gf;
+        if (LAW == NLE_MAT_M6) {
+          const T bm[3][3] = {{T(mp.g6[1]), T(mp.g6[4]), T(mp.g6[5])},
+                              {T(mp.g6[4]), T(mp.g6[2]), T(mp.g6[6])},
+                              {T(mp.g6[5]), T(mp.g6[6]), T(mp.g6[3])}};
+          T q2 = T(0), be = T(0);
+#pragma unroll
+          for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+              const T de = T(0.5) * (rb[i][p] * gb[q] + rb[i][q] * gb[p]);
+              q2 += bm[p][q] * de * de;
+              be += gu.bE[p][q] * de;
+            }
+          dg += gSg + gu.Ce * (q2 + T(2) * be * be);
+        }
+        cu[a][i] += tw * dg;
+      }
+    }
+  }
+}
+
+// LAW: NLE_MAT_M3 or NLE_MAT_M5 (with a pressure field); NLE_MAT_M1, M2, M4
+// or M6 (none).  NPE: pressure values per element, 4 (linear) or 1 (constant).
+// Laws M2, M4 and M6 take the common tangent form of nle_laws.hpp at each
+// point (GEN), evaluated from the state (no per-element cache).
 template <typename T, int OP, int LAW, int NPE>
 __global__ __launch_bounds__(NT) void k_mixed_elem(MixArgs<T> A) {
-  constexpr bool PRES = LAW != NLE_MAT_M1;
+  constexpr bool PRES = LAW == NLE_MAT_M3 || LAW == NLE_MAT_M5;
+  constexpr bool GEN = !PRES && LAW != NLE_MAT_M1;
   __shared__ double sh[NT / 64];
   if (A.skip && A.skip[0] != 0) return;
   const int64_t e = int64_t(blockIdx.x) * NT + threadIdx.x;
@@ -96,6 +267,15 @@ __global__ __launch_bounds__(NT) void k_mixed_elem(MixArgs<T> A) {
 #pragma unroll
     for (int j = 0; j < 3; ++j) g[0][j] = -(g[1][j] + g[2][j] + g[3][j]);
     const double w = double(A.V[e]) * 0.25;
+    T fe[3] = {T(0), T(0), T(0)}, se[3] = {T(0), T(0), T(0)};
+    if (has_fibre<LAW>()) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) fe[j] = A.fib[size_t(j) * ne + e];
+    }
+    if (LAW == NLE_MAT_M6) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) se[j] = A.sheet[size_t(j) * ne + e];
+    }
     T U[10][3], W[10][3], P4[4] = {T(0), T(0), T(0), T(0)}, WP[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
     for (int a = 0; a < 10; ++a) {
@@ -154,6 +334,10 @@ __global__ __launch_bounds__(NT) void k_mixed_elem(MixArgs<T> A) {
       Kin<T> k;
       kinematics(H, k);
       bad |= k.bad;
+      if constexpr (GEN) {
+        gen_point<T, OP, LAW>(A, H, k, fe, se, gN, W, w, cu, eacc);
+        continue;
+      }
       T pq = T(0);
 #pragma unroll
       for (int b = 0; b < NPE; ++b) pq += pb[b] * P4[b];
@@ -389,6 +573,7 @@ struct GatherArgs {
   const T *v;
   T *out;
   const double *fext;
+  const T *fs;  // surface-load contributions (null: none)
   double s, mu;
   double *red;
   const T *ep_w;
@@ -413,6 +598,10 @@ __global__ __launch_bounds__(NT) void k_mixed_gather(GatherArgs<T> A) {
       acc[2] += c[2];
     }
     const uint32_t mk = A.umask[t];
+    if (A.fs) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) acc[i] += A.fs[3 * t + i];
+    }
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const int64_t d = 3 * t + i;
@@ -483,6 +672,9 @@ int launch_mixed(Ctx *c, int op, const T *G, const T *V, const T *x, const T *v,
   A.ap = c->mat.a_iso;   // law M5 keeps alpha_p, beta_p and 4 beta_s + 2 alpha_s here
   A.bp = c->mat.b_iso;
   A.cs = c->mat.a_f;
+  A.mp = c->mat;
+  A.fib = sizeof(T) == 8 ? reinterpret_cast<const T *>(c->fib64) : reinterpret_cast<const T *>(c->fib32);
+  A.sheet = sizeof(T) == 8 ? reinterpret_cast<const T *>(c->sh64) : reinterpret_cast<const T *>(c->sh32);
   A.red = red;
   A.flag = c->dflag;
   A.skip = c->elem_skip;
@@ -494,8 +686,15 @@ int launch_mixed(Ctx *c, int op, const T *G, const T *V, const T *x, const T *v,
   }
   const bool pres = M.n_p > 0;
   const bool m5 = c->mat.kind == NLE_MAT_M5;
+  const int kind = c->mat.kind;
 #define NLE_MIXED_ELEM(OPV)                                                                    \
-  if (!pres)                                                                                   \
+  if (!pres && kind == NLE_MAT_M2)                                                             \
+    hipLaunchKernelGGL((k_mixed_elem<T, OPV, NLE_MAT_M2, 0>), dim3(g1), dim3(NT), 0, c->stream, A); \
+  else if (!pres && kind == NLE_MAT_M4)                                                        \
+    hipLaunchKernelGGL((k_mixed_elem<T, OPV, NLE_MAT_M4, 0>), dim3(g1), dim3(NT), 0, c->stream, A); \
+  else if (!pres && kind == NLE_MAT_M6)                                                        \
+    hipLaunchKernelGGL((k_mixed_elem<T, OPV, NLE_MAT_M6, 0>), dim3(g1), dim3(NT), 0, c->stream, A); \
+  else if (!pres)                                                                              \
     hipLaunchKernelGGL((k_mixed_elem<T, OPV, NLE_MAT_M1, 0>), dim3(g1), dim3(NT), 0, c->stream, A); \
   else if (M.npe == 1 && m5)                                                                   \
     hipLaunchKernelGGL((k_mixed_elem<T, OPV, NLE_MAT_M5, 1>), dim3(g1), dim3(NT), 0, c->stream, A); \
@@ -523,7 +722,15 @@ int launch_mixed(Ctx *c, int op, const T *G, const T *V, const T *x, const T *v,
 #undef NLE_MIXED_ELEM
   *err = hipGetLastError();
   if (*err != hipSuccess) return 0;
+  // surface loads (quadratic heartbeat faces) into the node sums
+  const T *fs = nullptr;
+  if (op == OP_RES || op == OP_JV || op == OP_DIAG) {
+    fs = static_cast<const T *>(
+        surf_apply(c, op, sizeof(T) == 8 ? NLE_FP64 : NLE_FP32, x, v, nullptr, err));
+    if (*err != hipSuccess) return 0;
+  }
   GatherArgs<T> B;
+  B.fs = fs;
   B.nu = M.n_u;
   B.np = M.n_p;
   B.u_ptr = M.u_ptr;

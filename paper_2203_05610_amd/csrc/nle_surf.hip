@@ -23,6 +23,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <unordered_map>
 
 #include "nle_internal.hpp"
 
@@ -220,6 +221,167 @@ __global__ __launch_bounds__(NT) void k_surface(SurfArgs<T> A) {
   }
 }
 
+// Quadratic faces (6 nodes: vertices, then the midpoints of edges (0,1),
+// (1,2), (0,2)) of a second-order mesh: follower pressure and springs (with
+// dashpots).  Node a of a face gains, for the pressure,
+//   pe int N_a (x_xi x x_eta) dxi deta     (residual),
+//   pl int N_a (v_xi x x_eta + x_xi x v_eta) (Jacobian action),
+// over the reference triangle by the 6-point degree-4 rule of Dunavant
+// (exact: the integrand has degree 4), and for the springs
+// sum_b M_ab K w_b with the exact face mass M = 2A/360 [6 -1 -1 0 -4 0; ...]
+// (vertex-vertex 6 / -1, vertex-midpoint 0 on its edges and -4 opposite,
+// midpoint-midpoint 32 / 16).  The pressure adds nothing to the diagonal:
+// (e_i x y)_i = 0.
+__constant__ double D6_L[6][3] = {
+    {0.445948490915965, 0.445948490915965, 0.108103018168070},
+    {0.445948490915965, 0.108103018168070, 0.445948490915965},
+    {0.108103018168070, 0.445948490915965, 0.445948490915965},
+    {0.091576213509771, 0.091576213509771, 0.816847572980459},
+    {0.091576213509771, 0.816847572980459, 0.091576213509771},
+    {0.816847572980459, 0.091576213509771, 0.091576213509771}};
+__constant__ double D6_W[6] = {0.223381589678011, 0.223381589678011, 0.223381589678011,
+                               0.109951743655322, 0.109951743655322, 0.109951743655322};
+__constant__ double M6_REF[6][6] = {{6, -1, -1, 0, -4, 0},   {-1, 6, -1, 0, 0, -4},
+                                    {-1, -1, 6, -4, 0, 0},   {0, 0, -4, 32, 16, 16},
+                                    {-4, 0, 0, 16, 32, 16},  {0, -4, 0, 16, 16, 32}};
+
+// value and (xi, eta) derivatives of the face's shape function a at
+// barycentric (L0, L1, L2), xi = L1, eta = L2
+__device__ __forceinline__ void tri6_shape(int a, const double L[3], double &N, double &dx,
+                                           double &de) {
+  const double dL[3][2] = {{-1.0, -1.0}, {1.0, 0.0}, {0.0, 1.0}};
+  if (a < 3) {
+    N = L[a] * (2.0 * L[a] - 1.0);
+    dx = (4.0 * L[a] - 1.0) * dL[a][0];
+    de = (4.0 * L[a] - 1.0) * dL[a][1];
+  } else {
+    const int p = a == 3 ? 0 : (a == 4 ? 1 : 0), q = a == 3 ? 1 : 2;
+    N = 4.0 * L[p] * L[q];
+    dx = 4.0 * (L[p] * dL[q][0] + L[q] * dL[p][0]);
+    de = 4.0 * (L[p] * dL[q][1] + L[q] * dL[p][1]);
+  }
+}
+
+template <typename T, int OP>
+__global__ __launch_bounds__(NT) void k_surface6(SurfArgs<T> A) {
+  __shared__ double sh[NT / 64];
+  if (A.skip && A.skip[0] != 0) return;
+  const int64_t k = int64_t(blockIdx.x) * NT + threadIdx.x;
+  double e = 0.0;
+  if (k < A.nsn) {
+    const int32_t g = A.node[k];
+    T acc[3] = {T(0), T(0), T(0)};
+    const T pe = OP == OP_JV ? T(A.plin[0]) : T(A.p);
+    for (int q = A.ptr[k]; q < A.ptr[k + 1]; ++q) {
+      const int32_t f = A.ent[q];
+      int32_t n[6];
+#pragma unroll
+      for (int a = 0; a < 6; ++a) n[a] = A.tri[6 * int64_t(f) + a];
+      int me = 0;
+#pragma unroll
+      for (int a = 0; a < 6; ++a)
+        if (n[a] == g) me = a;
+      const uint32_t fm = (OP == OP_JV && !A.nomask) ? A.fmask[f] : 0u;
+      if (f < A.npf) {
+        if (OP != OP_RES && OP != OP_JV) continue;
+        const T *Xf = A.pgeo + 18 * int64_t(f);
+        T x[6][3], w[6][3];
+#pragma unroll
+        for (int a = 0; a < 6; ++a)
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            x[a][i] = Xf[3 * a + i] + A.u[3 * int64_t(n[a]) + i];
+            if (OP == OP_JV) w[a][i] = ((fm >> (3 * a + i)) & 1u) ? T(0) : A.v[3 * int64_t(n[a]) + i];
+          }
+        for (int qp = 0; qp < 6; ++qp) {
+          const double L[3] = {D6_L[qp][0], D6_L[qp][1], D6_L[qp][2]};
+          T xx[3] = {T(0), T(0), T(0)}, xe[3] = {T(0), T(0), T(0)};
+          T vx[3] = {T(0), T(0), T(0)}, ve[3] = {T(0), T(0), T(0)};
+          double Nme = 0.0;
+#pragma unroll
+          for (int a = 0; a < 6; ++a) {
+            double N, dx, de;
+            tri6_shape(a, L, N, dx, de);
+            if (a == me) Nme = N;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+              xx[i] += T(dx) * x[a][i];
+              xe[i] += T(de) * x[a][i];
+              if (OP == OP_JV) {
+                vx[i] += T(dx) * w[a][i];
+                ve[i] += T(de) * w[a][i];
+              }
+            }
+          }
+          // reference area 1/2 times the rule's weight
+          const T s = pe * T(0.5 * D6_W[qp] * Nme);
+          if (OP == OP_RES) {
+            cross_acc(xx, xe, s, acc);
+          } else {
+            cross_acc(vx, xe, s, acc);
+            cross_acc(xx, ve, s, acc);
+          }
+        }
+      } else {
+        const T *R = A.rgeo + 4 * int64_t(f - A.npf - A.ntf);
+        const T N[3] = {R[0], R[1], R[2]};
+        const T area = R[3];
+        const T kpar = T(A.kpar), dk = T(A.kperp - A.kpar);
+        const T kpe = A.damp ? T(A.kpar + A.cv * A.cpar) : kpar;
+        const T dke = A.damp ? T(A.kperp - A.kpar + A.cv * (A.cperp - A.cpar)) : dk;
+        const T m2 = T(2) * area / T(360);
+        if (OP == OP_DIAG) {
+#pragma unroll
+          for (int i = 0; i < 3; ++i) acc[i] += m2 * T(M6_REF[me][me]) * (kpe + dke * N[i] * N[i]);
+        } else if (OP == OP_RES || OP == OP_JV || OP == OP_ENERGY) {
+          const T *wv = OP == OP_JV ? A.v : A.u;
+          const T kw = OP == OP_JV ? kpe : kpar, dw = OP == OP_JV ? dke : dk;
+#pragma unroll
+          for (int b = 0; b < 6; ++b) {
+            const T m = m2 * T(M6_REF[me][b]);
+            const int64_t nb = int64_t(n[b]);
+            T wb[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) wb[i] = ((fm >> (3 * b + i)) & 1u) ? T(0) : wv[3 * nb + i];
+            const T nw = N[0] * wb[0] + N[1] * wb[1] + N[2] * wb[2];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) acc[i] += m * (kw * wb[i] + dw * nw * N[i]);
+            if (OP == OP_RES && A.damp) {
+              T z[3];
+#pragma unroll
+              for (int i = 0; i < 3; ++i)
+                z[i] = T(A.vt[3 * nb + i] + A.cv * (double(A.u[3 * nb + i]) - A.ut[3 * nb + i]));
+              const T nz = N[0] * z[0] + N[1] * z[1] + N[2] * z[2];
+              const T cpar = T(A.cpar), dc = T(A.cperp - A.cpar);
+#pragma unroll
+              for (int i = 0; i < 3; ++i) acc[i] += m * (cpar * z[i] + dc * nz * N[i]);
+            }
+          }
+        }
+      }
+    }
+    if (OP == OP_ENERGY) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) e += 0.5 * double(A.u[3 * int64_t(g) + i]) * double(acc[i]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) A.fs[3 * int64_t(g) + i] = acc[i];
+    }
+  }
+  if (OP == OP_ENERGY) {
+    double v = e;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double r = 0.0;
+      for (int w = 0; w < NT / 64; ++w) r += sh[w];
+      A.red[blockIdx.x] = r;
+    }
+  }
+}
+
 __global__ void k_set_scalar(double *dst, double v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) dst[0] = v;
 }
@@ -258,6 +420,23 @@ void launch_surface(Ctx *c, int op, const T *u, const T *v, T *fs, double *red, 
   A.skip = c->elem_skip;
   A.nomask = (op == OP_JV && c->jv_nomask) ? 1 : 0;
   const int grid = int((S.nsn + NT - 1) / NT);
+  if (S.fv == 6) {
+    switch (op) {
+      case OP_RES:
+        hipLaunchKernelGGL((k_surface6<T, OP_RES>), dim3(grid), dim3(NT), 0, c->stream, A);
+        break;
+      case OP_JV:
+        hipLaunchKernelGGL((k_surface6<T, OP_JV>), dim3(grid), dim3(NT), 0, c->stream, A);
+        break;
+      case OP_DIAG:
+        hipLaunchKernelGGL((k_surface6<T, OP_DIAG>), dim3(grid), dim3(NT), 0, c->stream, A);
+        break;
+      default:
+        hipLaunchKernelGGL((k_surface6<T, OP_ENERGY>), dim3(grid), dim3(NT), 0, c->stream, A);
+        break;
+    }
+    return;
+  }
   switch (op) {
     case OP_RES:
       hipLaunchKernelGGL((k_surface<T, OP_RES>), dim3(grid), dim3(NT), 0, c->stream, A);
@@ -319,9 +498,35 @@ nle_status build_surface(Ctx *c) {
   if (npf + nrf >= (int64_t(1) << 31) / 3) return fail(c, NLE_E_UNSUPPORTED, "too many faces");
   const int64_t nn = c->m.n_nodes;
   const double *X = c->m.h_X.data();
-  std::vector<int32_t> tri(S.h_ptri);
-  tri.insert(tri.end(), S.h_ttri.begin(), S.h_ttri.end());
-  tri.insert(tri.end(), S.h_rtri.begin(), S.h_rtri.end());
+  std::vector<int32_t> tri3(S.h_ptri);
+  tri3.insert(tri3.end(), S.h_ttri.begin(), S.h_ttri.end());
+  tri3.insert(tri3.end(), S.h_rtri.begin(), S.h_rtri.end());
+  // quadratic meshes: each face gains the midpoints of its edges (0,1), (1,2), (0,2)
+  const int fv = c->mixed ? 6 : 3;
+  std::vector<int32_t> tri;
+  if (fv == 3) {
+    tri = tri3;
+  } else {
+    if (ntf > 0) return fail(c, NLE_E_UNSUPPORTED, "follower traction needs a P1 mesh");
+    std::unordered_map<uint64_t, int32_t> mid;
+    const std::vector<int32_t> &cn = c->mx.h_conn;
+    static const int ea[6] = {0, 1, 0, 0, 1, 2}, eb[6] = {1, 2, 2, 3, 3, 3};
+    for (size_t e0 = 0; e0 + 9 < cn.size(); e0 += 10)
+      for (int q = 0; q < 6; ++q) {
+        const uint32_t va = uint32_t(cn[e0 + ea[q]]), vb = uint32_t(cn[e0 + eb[q]]);
+        mid[(uint64_t(std::min(va, vb)) << 32) | std::max(va, vb)] = cn[e0 + 4 + q];
+      }
+    const int pa[3] = {0, 1, 0}, pb[3] = {1, 2, 2};
+    for (size_t f = 0; f < tri3.size() / 3; ++f) {
+      for (int a = 0; a < 3; ++a) tri.push_back(tri3[3 * f + a]);
+      for (int q = 0; q < 3; ++q) {
+        const uint32_t va = uint32_t(tri3[3 * f + pa[q]]), vb = uint32_t(tri3[3 * f + pb[q]]);
+        auto it = mid.find((uint64_t(std::min(va, vb)) << 32) | std::max(va, vb));
+        if (it == mid.end()) return fail(c, NLE_E_INVAL, "face edge is not an element edge");
+        tri.push_back(it->second);
+      }
+    }
+  }
   // incident faces of each node (CSR over nodes, faces in increasing order)
   std::vector<int32_t> cnt(nn + 1, 0);
   for (int32_t v : tri) cnt[v + 1] += 1;
@@ -332,11 +537,11 @@ nle_status build_surface(Ctx *c) {
   std::vector<int64_t> pos(start.begin(), start.end() - 1);
   const int64_t nf = npf + nrf;
   for (int64_t f = 0; f < nf; ++f)
-    for (int a = 0; a < 3; ++a) {
-      const int32_t v = tri[3 * f + a];
+    for (int a = 0; a < fv; ++a) {
+      const int32_t v = tri[fv * f + a];
       // a face listing a node twice would add it twice: rejected
       for (int b = 0; b < a; ++b)
-        if (tri[3 * f + b] == v) return fail(c, NLE_E_BADMESH, "degenerate surface triangle");
+        if (tri[fv * f + b] == v) return fail(c, NLE_E_BADMESH, "degenerate surface triangle");
       all[pos[v]++] = int32_t(f);
     }
   for (int64_t g = 0; g < nn; ++g) {
@@ -345,12 +550,12 @@ nle_status build_surface(Ctx *c) {
     for (int64_t q = start[g]; q < start[g + 1]; ++q) fent.push_back(all[q]);
     fptr.push_back(int32_t(fent.size()));
   }
-  std::vector<double> pg(9 * npf), rg(4 * nrf);
+  std::vector<double> pg(3 * fv * npf), rg(4 * nrf);
   for (int64_t f = 0; f < npf; ++f)
-    for (int a = 0; a < 3; ++a)
-      for (int i = 0; i < 3; ++i) pg[9 * f + 3 * a + i] = X[3 * int64_t(tri[3 * f + a]) + i];
+    for (int a = 0; a < fv; ++a)
+      for (int i = 0; i < 3; ++i) pg[3 * fv * f + 3 * a + i] = X[3 * int64_t(tri[fv * f + a]) + i];
   for (int64_t r = 0; r < nrf; ++r) {
-    const int32_t *t = &tri[3 * (npf + r)];
+    const int32_t *t = &tri[fv * (npf + r)];
     double e1[3], e2[3];
     for (int i = 0; i < 3; ++i) {
       e1[i] = X[3 * int64_t(t[1]) + i] - X[3 * int64_t(t[0]) + i];
@@ -365,6 +570,7 @@ nle_status build_surface(Ctx *c) {
   }
   std::vector<float> pg32(pg.begin(), pg.end()), rg32(rg.begin(), rg.end());
   hipError_t e = hipSuccess;
+  S.fv = fv;
   S.npf = int32_t(npf0);
   S.ntf = int32_t(ntf);
   S.nrf = int32_t(nrf);
@@ -406,11 +612,12 @@ nle_status build_surface(Ctx *c) {
 nle_status upload_surface_masks(Ctx *c) {
   Ctx::Surf &S = c->surf;
   if (S.nsn == 0) return NLE_OK;
-  const int64_t nf = int64_t(S.h_tri.size() / 3);
+  const int fv = S.fv;
+  const int64_t nf = int64_t(S.h_tri.size() / fv);
   std::vector<uint32_t> fm(nf, 0u);
   for (int64_t f = 0; f < nf; ++f)
-    for (int a = 0; a < 3; ++a)
-      fm[f] |= uint32_t(c->h_mask[S.h_tri[3 * f + a]] & 7u) << (3 * a);
+    for (int a = 0; a < fv; ++a)
+      fm[f] |= uint32_t(c->h_mask[S.h_tri[fv * f + a]] & 7u) << (3 * a);
   NLE_HIP(c, hipMemcpyAsync(S.fmask, fm.data(), fm.size() * 4, hipMemcpyHostToDevice, c->stream));
   NLE_HIP(c, hipStreamSynchronize(c->stream));
   return NLE_OK;

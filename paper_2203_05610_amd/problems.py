@@ -143,6 +143,33 @@ def setup_guccione(ctx: nl.Context, mesh, consts: dict, law, dofs, block_size=No
     nl.nle_set_fibre_frame(ctx, mesh.elem_fibre, mesh.elem_sheet)
 
 
+def setup_shell_p2(ctx: nl.Context, mesh2, consts: dict, law=None, loads: bool = False) -> None:
+    """The ventricle shell with quadratic (10-node) displacement elements:
+    law M4 with the consts' constants and the mesh's fibres, or with law =
+    (C, b_ff, b_ss, b_nn, b_fs, b_fn, b_sn, B) Guccione's law M6 with fibres
+    and sheets; base plane held in z (vertices and edge midpoints) plus three
+    pins.  loads: the heartbeat's follower pressure consts['p_max'] on the
+    'endo' faces and springs on the 'epi' faces (6-node faces).  Load scale
+    1, active tension 0."""
+    from synthetic import shell_dirichlet
+
+    c = consts
+    nl.nle_upload_mesh(ctx, mesh2.X, mesh2.conn)
+    if law is None:
+        nl.nle_set_material(ctx, nl.NLE_MAT_M4, [c["a"], c["b"], c["af"], c["bf"], c["kappa"]])
+        nl.nle_set_fibres(ctx, mesh2.elem_fibre)
+    else:
+        nl.nle_set_material(ctx, nl.NLE_MAT_M6, list(law))
+        nl.nle_set_fibre_frame(ctx, mesh2.elem_fibre, mesh2.elem_sheet)
+    dofs = shell_dirichlet(mesh2)
+    nl.nle_set_dirichlet(ctx, dofs, np.zeros(dofs.size))
+    if loads:
+        nl.nle_set_pressure(ctx, mesh2.faces["endo"], c["p_max"])
+        nl.nle_set_robin(ctx, mesh2.faces["epi"], c["k_perp"], c["k_par"])
+    nl.nle_set_load_scale(ctx, 1.0)
+    nl.nle_set_active_tension(ctx, 0.0)
+
+
 def solve_heartbeat(ctx: nl.Context, u, method: str, opts, schedule, gamma_max: float,
                     hist_cap: int = 4096, max_cuts: int = 8, start=(0.0, 0.0)):
     """Quasi-static heartbeat: for each time step (t, shape) set the active

@@ -73,7 +73,7 @@ def test_p2_kernels_parity(grid):
 
 def test_p2_usage_errors():
     mesh, P, ctx = _setup(2, 2, 1, 5.0)
-    nl.nle_set_material(ctx, nl.NLE_MAT_M2, [MU, 5 * MU])
+    nl.nle_set_material(ctx, nl.NLE_MAT_M3, [MU])  # needs a pressure field
     x = torch.zeros(P.n_dofs, dtype=torch.float64, device="cuda")
     with pytest.raises(nl.NleError) as e:
         nl.nle_residual(ctx, x, torch.empty_like(x))
