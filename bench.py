@@ -621,8 +621,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--method", default="ink_mixed_cg_amg", choices=sorted(METHODS))
-    ap.add_argument("--baseline", default="nk_fp64", choices=sorted(METHODS))
-    ap.add_argument("--compare", default="ink_mixed,bfgs_ib_mixed_r20",
+    ap.add_argument("--baseline", default="nk_fp64_minres_amg", choices=sorted(METHODS))
+    ap.add_argument("--compare", default="ink_fp64_cg_amg,ink_mixed,bfgs_ib_mixed_r20",
                     help="comma-separated extra methods, run once each ('' for none)")
     ap.add_argument("--jv-reps", type=int, default=200)
     ap.add_argument("--pc", default="jacobi", choices=["jacobi", "bjacobi3"],
@@ -637,13 +637,14 @@ def main():
                     help="serial FP64 NK baseline on every k-th batch instance (0 skips it)")
     ap.add_argument("--batch-only", action="store_true", help="only the batched-solve leg")
     ap.add_argument("--twist", type=int, default=24, help="twist cube cells per edge (0 skips)")
-    ap.add_argument("--twist-methods", default="nk_fp64,ink_mixed")
-    ap.add_argument("--twist-p0", type=int, default=0,
+    ap.add_argument("--twist-methods", default="nk_fp64,ink_mixed_schur_mass_amg")
+    ap.add_argument("--twist-p0", type=int, default=12,
                     help="cells per edge of the P2-P0 polyconvex twist leg (0 skips)")
-    ap.add_argument("--twist-p0-methods", default="nk_fp64_schur_simple,ink_mixed_schur_simple")
-    ap.add_argument("--cardiac", default="", help="ventricle shell grid n_t,n_s,n_c (e.g. "
-                    "8,80,256); empty skips this leg (minutes at full size)")
-    ap.add_argument("--cardiac-methods", default="ink_fp64_cg_amg,bfgs_ib_fp64_r20_bj")
+    ap.add_argument("--twist-p0-methods",
+                    default="nk_fp64_schur_simple_amg,ink_mixed_schur_simple_amg")
+    ap.add_argument("--cardiac", default="8,80,256", help="ventricle shell grid n_t,n_s,n_c "
+                    "(empty skips this leg)")
+    ap.add_argument("--cardiac-methods", default="ink_fp64_cg_amg")
     ap.add_argument("--cardiac-steps", type=int, default=20)
     ap.add_argument("--follower", default="", help="follower-load Cook grid nx,ny,nz (e.g. "
                     "64,64,4; empty skips)")
