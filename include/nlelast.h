@@ -499,7 +499,11 @@ nle_status nle_simple_diag(nle_ctx *ctx, double *s_dev);
 nle_status nle_energy(nle_ctx *ctx, const double *u_dev, double *pi_host);
 
 /* ---- solvers ------------------------------------------------------------- */
-/* Defaults of App. A for the method (NK, iNK or BFGS); ksp_type CG. */
+/* Tolerances, iteration limits and Eisenstat-Walker constants of App. A for the
+ * method (NK, iNK or BFGS).  The Krylov choice is not App. A's: ksp_type is
+ * CG with point Jacobi and orth CGS2, where App. A runs GMRES with modified
+ * Gram-Schmidt; set ksp_type = NLE_KSP_GMRES and orth = NLE_ORTH_MGS for
+ * that configuration. */
 void nle_default_opts(int32_t method, nle_solver_opts *opts);
 /* Solve r(u) = 0 at the current load scale, starting from u (double,
  * device, overwritten with the result).  If u does not hold the prescribed
@@ -552,13 +556,19 @@ nle_status nle_batch_autotune(nle_batch *b, int32_t prec, double budget_ms, int3
 /* node_offsets[n_inst + 1]: instance i owns nodes [off[i], off[i+1]) of the
  * concatenated vector (dof = 3 * node + component). */
 nle_status nle_batch_layout(const nle_batch *b, int64_t *node_offsets);
-/* Solve every instance over its schedule with NK or iNK (CG + Jacobi inner
- * solves), starting from u (device, concatenated, overwritten).  A load step
- * that diverges is retried from the last converged state with half the
- * increment (at most 8 times per instance).  reports[n_inst] (nullable)
- * receive per-instance outcomes (bfgs_skipped holds the number of cutbacks);
- * *t_ms the wall time of the whole batch on the stream.  Returns NLE_OK when
- * every instance finished its schedule, else the last failing status. */
+/* Solve every instance over its schedule with NK, iNK (CG + point Jacobi
+ * inner solves) or L-BFGS (Sec. 3: inexact BFGS with H0 a CG + Jacobi solve,
+ * or BFGS-preonly with pc NLE_PC_JACOBI or NLE_PC_NONE as H0; qn_m 1..64),
+ * starting from u (device, concatenated, overwritten).  A load step that
+ * diverges is retried from the last converged state with half the increment
+ * (at most 8 times per instance).  reports[n_inst] (nullable) receive
+ * per-instance outcomes: iterations, histories, bfgs_skipped (pairs rejected
+ * by the curvature test) and cutbacks (halved increments); *t_ms the wall
+ * time of the whole batch on the stream.  Returns NLE_OK when every instance
+ * finished its schedule, else the last failing status.  NLE_E_UNSUPPORTED
+ * for another Krylov method or preconditioner, NLE_E_INVAL for a bad method,
+ * precision, BFGS memory or iteration limit, NLE_E_STATE before
+ * nle_batch_finalize. */
 nle_status nle_batch_solve(nle_batch *b, int32_t method, const nle_solver_opts *opts, double *u_dev,
                            nle_report *reports, double *t_ms);
 

@@ -185,32 +185,91 @@ template <typename T, int OP>
 __device__ __forceinline__ void finalize_node(uint32_t g, uint32_t mk, const T acc[3], const T *v,
                                               const T *vz, T bt,
                                               T *out, const double *fext, double s,
-                                              double &nrm, const T *epw, T epc, const T *fs,
-                                              int nomask, const T *icm, const double *iut,
-                                              const T *u) {
+                                              double &nrm, bool dot, const T *epw, T epc,
+                                              const T *fs, int nomask, const T *icm,
+                                              const double *iut, const T *u) {
+  // Every load of the node's three components is issued before the
+  // arithmetic and the stores come last: out may alias the inputs as far as
+  // the compiler knows, so a load after a store would wait for it.
+  const int64_t d0 = 3 * int64_t(g);
+  T a[3], fv[3] = {T(0), T(0), T(0)};
+  if (fs) {
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const int64_t d = 3 * int64_t(g) + i;
-    const bool fixed = (mk >> i) & 1u;
-    const T a = fs ? acc[i] + fs[d] : acc[i];
-    if (OP == OP_RES) {
-      double ra = double(a);
-      if (icm) ra += double(icm[d]) * (double(u[d]) - iut[d]);
-      const double r = fixed ? 0.0 : ra - s * fext[d];
-      out[d] = T(r);
-      nrm += r * r;
-    } else if (OP == OP_JV) {
-      const T vd = vz ? vz[d] + bt * v[d] : v[d];
-      T y = fixed ? (nomask ? T(0) : vd) : (icm ? a + icm[d] * vd : a);
-      if (epw) y -= epc * epw[d];
-      out[d] = y;
-      nrm += double(vd * y);
-    } else if (OP == OP_DIAG) {
-      out[d] = fixed ? T(1) : (icm ? a + icm[d] : a);
-    } else if (OP == OP_ODIAG) {
-      // entry i pairs components (i, i+1 mod 3): xy, yz, zx
-      const bool fx2 = (mk >> ((i + 1) % 3)) & 1u;
-      out[d] = (fixed || fx2) ? T(0) : a;
+    for (int i = 0; i < 3; ++i) fv[i] = fs[d0 + i];
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) a[i] = fs ? acc[i] + fv[i] : acc[i];
+  if (OP == OP_RES) {
+    double fe[3], ci[3] = {0.0, 0.0, 0.0}, uu[3] = {0.0, 0.0, 0.0}, ut[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) fe[i] = fext[d0 + i];
+    if (icm) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        ci[i] = double(icm[d0 + i]);
+        uu[i] = double(u[d0 + i]);
+        ut[i] = iut[d0 + i];
+      }
+    }
+    double r[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      double ra = double(a[i]);
+      if (icm) ra += ci[i] * (uu[i] - ut[i]);
+      r[i] = ((mk >> i) & 1u) ? 0.0 : ra - s * fe[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      out[d0 + i] = T(r[i]);
+      nrm += r[i] * r[i];
+    }
+  } else if (OP == OP_JV) {
+    // the direction is read only at nodes that use it: kept Dirichlet rows
+    // (nomask = 0), inertia and the v.y sum (dot)
+    T vd[3] = {T(0), T(0), T(0)}, cm[3] = {T(0), T(0), T(0)}, ew[3] = {T(0), T(0), T(0)};
+    if (dot || icm || (mk != 0u && !nomask)) {
+      if (vz) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) vd[i] = vz[d0 + i] + bt * v[d0 + i];
+      } else {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) vd[i] = v[d0 + i];
+      }
+    }
+    if (icm) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) cm[i] = icm[d0 + i];
+    }
+    if (epw) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) ew[i] = epw[d0 + i];
+    }
+    T y[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      T t = ((mk >> i) & 1u) ? (nomask ? T(0) : vd[i]) : (icm ? a[i] + cm[i] * vd[i] : a[i]);
+      if (epw) t -= epc * ew[i];
+      y[i] = t;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      out[d0 + i] = y[i];
+      if (dot) nrm += double(vd[i] * y[i]);
+    }
+  } else if (OP == OP_DIAG) {
+    T cm[3] = {T(0), T(0), T(0)};
+    if (icm) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) cm[i] = icm[d0 + i];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) out[d0 + i] = ((mk >> i) & 1u) ? T(1) : (icm ? a[i] + cm[i] : a[i]);
+  } else if (OP == OP_ODIAG) {
+    // entry i pairs components (i, i+1 mod 3): xy, yz, zx
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const bool fx = ((mk >> i) & 1u) || ((mk >> ((i + 1) % 3)) & 1u);
+      out[d0 + i] = fx ? T(0) : a[i];
     }
   }
 }
@@ -320,6 +379,20 @@ __device__ __forceinline__ Coef unpack_coef(const T *lc, uint32_t ne, uint32_t g
   return c;
 }
 
+// cof A (cof A = det A A^-T), row-major
+template <typename T>
+__device__ __forceinline__ void cofactor3(const T A[3][3], T C[3][3]) {
+  C[0][0] = A[1][1] * A[2][2] - A[1][2] * A[2][1];
+  C[0][1] = A[1][2] * A[2][0] - A[1][0] * A[2][2];
+  C[0][2] = A[1][0] * A[2][1] - A[1][1] * A[2][0];
+  C[1][0] = A[0][2] * A[2][1] - A[0][1] * A[2][2];
+  C[1][1] = A[0][0] * A[2][2] - A[0][2] * A[2][0];
+  C[1][2] = A[0][1] * A[2][0] - A[0][0] * A[2][1];
+  C[2][0] = A[0][1] * A[1][2] - A[0][2] * A[1][1];
+  C[2][1] = A[0][2] * A[1][0] - A[0][0] * A[1][2];
+  C[2][2] = A[0][0] * A[1][1] - A[0][1] * A[1][0];
+}
+
 // F = I + H and F^-T = cof(F) / det(F) in the kernel's precision (enough for
 // the tangent; J - 1 and ln J are not needed once the coefficients are cached).
 template <typename T>
@@ -372,15 +445,7 @@ __device__ __forceinline__ void element_forces(const ElemIn<T> &d, const T *uS, 
       for (int a = 1; a < 4; ++a) D[i][a - 1] = xS[i * NL + la[a]] - x0;
     }
     T C[3][3];
-    C[0][0] = D[1][1] * D[2][2] - D[1][2] * D[2][1];
-    C[0][1] = D[1][2] * D[2][0] - D[1][0] * D[2][2];
-    C[0][2] = D[1][0] * D[2][1] - D[1][1] * D[2][0];
-    C[1][0] = D[0][2] * D[2][1] - D[0][1] * D[2][2];
-    C[1][1] = D[0][0] * D[2][2] - D[0][2] * D[2][0];
-    C[1][2] = D[0][1] * D[2][0] - D[0][0] * D[2][1];
-    C[2][0] = D[0][1] * D[1][2] - D[0][2] * D[1][1];
-    C[2][1] = D[0][2] * D[1][0] - D[0][0] * D[1][2];
-    C[2][2] = D[0][0] * D[1][1] - D[0][1] * D[1][0];
+    cofactor3(D, C);
     const T det = D[0][0] * C[0][0] + D[0][1] * C[0][1] + D[0][2] * C[0][2];
     // FP32: the hardware reciprocal (1 ulp) instead of a correctly rounded
     // division sequence; FP64 keeps the division
@@ -666,15 +731,7 @@ __device__ __forceinline__ void element_jv(const ElemIn<T> &d, const T *uS, cons
       }
   }
   T C[3][3];
-  C[0][0] = D[1][1] * D[2][2] - D[1][2] * D[2][1];
-  C[0][1] = D[1][2] * D[2][0] - D[1][0] * D[2][2];
-  C[0][2] = D[1][0] * D[2][1] - D[1][1] * D[2][0];
-  C[1][0] = D[0][2] * D[2][1] - D[0][1] * D[2][2];
-  C[1][1] = D[0][0] * D[2][2] - D[0][2] * D[2][0];
-  C[1][2] = D[0][1] * D[2][0] - D[0][0] * D[2][1];
-  C[2][0] = D[0][1] * D[1][2] - D[0][2] * D[1][1];
-  C[2][1] = D[0][2] * D[1][0] - D[0][0] * D[1][2];
-  C[2][2] = D[0][0] * D[1][1] - D[0][1] * D[1][0];
+  cofactor3(D, C);
   const T det = D[0][0] * C[0][0] + D[0][1] * C[0][1] + D[0][2] * C[0][2];
   // column a-1 of C is c_a: Hh[i][j] = sum_a DU[i][a-1] C[j][a-1]
   T F[3][3], dF[3][3];
@@ -692,15 +749,7 @@ __device__ __forceinline__ void element_jv(const ElemIn<T> &d, const T *uS, cons
       dF[i][j] = DV[i][0] * C[j][0] + DV[i][1] * C[j][1] + DV[i][2] * C[j][2];
     }
   T K[3][3];
-  K[0][0] = F[1][1] * F[2][2] - F[1][2] * F[2][1];
-  K[0][1] = F[1][2] * F[2][0] - F[1][0] * F[2][2];
-  K[0][2] = F[1][0] * F[2][1] - F[1][1] * F[2][0];
-  K[1][0] = F[0][2] * F[2][1] - F[0][1] * F[2][2];
-  K[1][1] = F[0][0] * F[2][2] - F[0][2] * F[2][0];
-  K[1][2] = F[0][1] * F[2][0] - F[0][0] * F[2][1];
-  K[2][0] = F[0][1] * F[1][2] - F[0][2] * F[1][1];
-  K[2][1] = F[0][2] * F[1][0] - F[0][0] * F[1][2];
-  K[2][2] = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+  cofactor3(F, K);
   const T J = F[0][0] * K[0][0] + F[0][1] * K[0][1] + F[0][2] * K[0][2];
   T iJ;
   if (sizeof(T) == 8)
@@ -792,16 +841,95 @@ __device__ __forceinline__ void element_jv(const ElemIn<T> &d, const T *uS, cons
   for (int i = 0; i < 3; ++i) out[0][i] = -(out[1][i] + out[2][i] + out[3][i]);
 }
 
+// Law M1 written on the deformed edge matrix X = D + DU (F = X D^-1).  With
+// C = cof D (column a-1 is det D grad N_a), CX = cof X (column a-1 is
+// det X grad n_a, the spatial gradient), Lh = DV CX^T (det X times the
+// spatial gradient of v) and G = C^T C, the action of the law's tangent (Sec. 2)
+// dP = mu dF + lam (F^-T : dF) F^-T + cX F^-T dF^T F^-T on vertex a is
+//   y_a = V dP grad N_a
+//       = mu / (6 det D) DV G e_a + det D / (6 det X^2) (cX Lh^T + lam tr(Lh) I) CX e_a,
+// since F^-T grad N_a = grad n_a, F^-T dF^T w = (dF F^-1)^T w and dF F^-1 = DV X^-1.
+template <typename T>
+__device__ __forceinline__ void element_jv_m1(const ElemIn<T> &d, const T *uS, const T *vS,
+                                              const T *xS, int NL, const MatParams &mp,
+                                              T out[4][3], const ElemArgs<T> &A, uint32_t ge) {
+  const int la[4] = {lo16(d.lcp.x), hi16(d.lcp.x), lo16(d.lcp.y), hi16(d.lcp.y)};
+  T D[3][3], X[3][3], DV[3][3];
+  {
+    T x0[3], u0[3], v0[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      x0[i] = xS[i * NL + la[0]];
+      u0[i] = uS[i * NL + la[0]];
+      v0[i] = vS[i * NL + la[0]];
+    }
+#pragma unroll
+    for (int a = 1; a < 4; ++a)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const T dx = xS[i * NL + la[a]] - x0[i];
+        D[i][a - 1] = dx;
+        X[i][a - 1] = dx + (uS[i * NL + la[a]] - u0[i]);
+        DV[i][a - 1] = vS[i * NL + la[a]] - v0[i];
+      }
+  }
+  T C[3][3], CX[3][3];
+  cofactor3(D, C);
+  cofactor3(X, CX);
+  const T det = D[0][0] * C[0][0] + D[0][1] * C[0][1] + D[0][2] * C[0][2];
+  const T detx = X[0][0] * CX[0][0] + X[0][1] * CX[0][1] + X[0][2] * CX[0][2];
+  T id, idx;
+  if (sizeof(T) == 8) {
+    id = T(1) / det;
+    idx = T(1) / detx;
+  } else {
+    id = T(__builtin_amdgcn_rcpf(float(det)));
+    idx = T(__builtin_amdgcn_rcpf(float(detx)));
+  }
+  T Lh[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      Lh[i][j] = DV[i][0] * CX[j][0] + DV[i][1] * CX[j][1] + DV[i][2] * CX[j][2];
+  const T s1 = T(mp.mu) * id * T(1.0 / 6.0);
+  const T s2 = det * idx * idx * T(1.0 / 6.0);
+  const T bX = T(A.lcoef[ge]) * s2;
+  const T bT = T(mp.lam) * s2 * (Lh[0][0] + Lh[1][1] + Lh[2][2]);
+  // B = bX Lh^T + bT I and Gs = s1 C^T C (symmetric)
+  T B[3][3], Gs[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) B[i][j] = i == j ? bX * Lh[j][i] + bT : bX * Lh[j][i];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = a; b < 3; ++b) {
+      Gs[a][b] = s1 * (C[0][a] * C[0][b] + C[1][a] * C[1][b] + C[2][a] * C[2][b]);
+      Gs[b][a] = Gs[a][b];
+    }
+#pragma unroll
+  for (int a = 1; a < 4; ++a)
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      out[a][i] = DV[i][0] * Gs[0][a - 1] + DV[i][1] * Gs[1][a - 1] + DV[i][2] * Gs[2][a - 1] +
+                  B[i][0] * CX[0][a - 1] + B[i][1] * CX[1][a - 1] + B[i][2] * CX[2][a - 1];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) out[0][i] = -(out[1][i] + out[2][i] + out[3][i]);
+}
+
 // One shared node of the merge: its partials (contiguous, in block order)
 // summed four loads at a time but added in slot order, then finalized.
 template <typename T, int OP>
 __device__ __forceinline__ void merge_node(const uint32_t *fx_node, const int32_t *fx_ptr,
                                            const T *partial, int64_t k, const T *v, const T *vz,
                                            T bt, T *out, const double *fext, double lscale,
-                                           double &nrm, const T *ep_w, T epc, const T *fs,
+                                           double &nrm, bool dot, const T *ep_w, T epc, const T *fs,
                                            int nomask, const T *icm, const double *iut,
                                            const T *u) {
   T acc[3] = {T(0), T(0), T(0)};
+  const uint32_t w = fx_node[k];
   const int q0 = fx_ptr[k], q1 = fx_ptr[k + 1];
   for (int q = q0; q < q1; q += 4) {
     T pv[4][3];
@@ -817,9 +945,11 @@ __device__ __forceinline__ void merge_node(const uint32_t *fx_node, const int32_
         acc[2] += pv[t][2];
       }
   }
-  const uint32_t w = fx_node[k];
-  finalize_node<T, OP>(w & NODE_MASK, (w >> 28) & 7u, acc, v, vz, bt, out, fext, lscale, nrm,
-                       ep_w, epc, fs, nomask, icm, iut, u);
+  // padding entries (batched mode aligns each instance to whole workgroups)
+  // have an empty slot range and the id 0xFFFFFFFF
+  if (w != 0xFFFFFFFFu)
+    finalize_node<T, OP>(w & NODE_MASK, (w >> 28) & 7u, acc, v, vz, bt, out, fext, lscale, nrm,
+                         dot, ep_w, epc, fs, nomask, icm, iut, u);
 }
 
 // NLC > 0: the block's slot count is at most NLC and its element count at
@@ -953,7 +1083,9 @@ __global__ __launch_bounds__(NTB) void k_elem_block(ElemArgs<T> A) {
   double eacc = 0.0;
   auto run = [&](const ElemIn<T> &d) {
     T out[4][3];
-    if constexpr (OP == OP_JV)
+    if constexpr (OP == OP_JV && MAT == NLE_MAT_M1)
+      element_jv_m1<T>(d, uS, vS, xS, NL, mp, out, A, d.ge);
+    else if constexpr (OP == OP_JV)
       element_jv<T, MAT>(d, uS, vS, xS, NL, mp, out, A, d.ge);
     else
       element_forces<T, OP, MAT>(d, uS, vS, xS, NL, mp, out, bad, eacc, A, d.ge);
@@ -999,7 +1131,8 @@ __global__ __launch_bounds__(NTB) void k_elem_block(ElemArgs<T> A) {
       pp[2] = acc[2];
     } else {
       finalize_node<T, OP>(w & NODE_MASK, (w >> 28) & 7u, acc, A.v, A.vz, bt, A.out, A.fext,
-                           lscale, nrm, A.ep_w, epc, A.fs, A.nomask, A.icm, A.iut, A.u);
+                           lscale, nrm, A.ep_red != nullptr, A.ep_w, epc, A.fs, A.nomask, A.icm,
+                           A.iut, A.u);
     }
   }
   if (OP == OP_RES || (OP == OP_JV && A.ep_red)) {
@@ -1018,13 +1151,11 @@ __global__ __launch_bounds__(NT) void k_elem_merge(MergeArgs<T> A) {
   const double lscale = A.inst_s ? A.inst_s[inst] : A.s;
   const int64_t k = int64_t(wg) * NT + threadIdx.x;
   double nrm = 0.0;
-  // padding entries (batched mode aligns each instance to whole workgroups)
-  // have an empty slot range and the id 0xFFFFFFFF
-  if (k < A.n_sh && A.fx_node[k] != 0xFFFFFFFFu)
+  if (k < A.n_sh)
     merge_node<T, OP>(A.fx_node, A.fx_ptr, A.partial, k, A.v, A.vz,
                       A.vz ? T(A.cg_scal[cgslot::BETA]) : T(0), A.out, A.fext, lscale, nrm,
-                      A.ep_w, A.ep_coef ? T(A.ep_coef[0]) : T(0), A.fs, A.nomask, A.icm, A.iut,
-                      A.u);
+                      A.ep_red != nullptr, A.ep_w, A.ep_coef ? T(A.ep_coef[0]) : T(0), A.fs,
+                      A.nomask, A.icm, A.iut, A.u);
   if (OP == OP_RES || (OP == OP_JV && A.ep_red)) {
     const double s = block_sum<NT>(nrm, rs);
     if (threadIdx.x == 0) (OP == OP_RES ? A.red : A.ep_red)[wg] = s;
