@@ -280,6 +280,7 @@ struct ElemIn {
   uint4 lcp;   // 8 x u16: slot-local vertex ids, then contribution positions
   T f[3];      // fibre direction (laws M4, M6)
   T sh[3];     // sheet direction (law M6)
+  T cx;        // law M1, Jacobian action: the cached tangent coefficient cX
   uint32_t ge; // renumbered element index
 };
 
@@ -289,11 +290,12 @@ __device__ __forceinline__ int hi16(uint32_t w) { return int(w >> 16); }
 // Per-element arrays are component-major ([k][n_e]): with a 32-bit element
 // index and uniform per-component base pointers every load is a scalar base
 // plus one shared 32-bit lane offset.
-template <int MAT, typename T>
+template <int MAT, int OP, typename T>
 __device__ __forceinline__ void load_elem(const ElemArgs<T> &A, uint32_t ge, ElemIn<T> &d) {
   d.lcp = A.lcp[ge];
   const uint32_t ne = uint32_t(A.n_e);
   d.ge = ge;
+  if (OP == OP_JV && MAT == NLE_MAT_M1) d.cx = A.lcoef[ge];
   if (has_fibre<MAT>()) {
 #pragma unroll
     for (int j = 0; j < 3; ++j) d.f[j] = A.fib[size_t(j) * ne + ge];
@@ -852,7 +854,7 @@ __device__ __forceinline__ void element_jv(const ElemIn<T> &d, const T *uS, cons
 template <typename T>
 __device__ __forceinline__ void element_jv_m1(const ElemIn<T> &d, const T *uS, const T *vS,
                                               const T *xS, int NL, const MatParams &mp,
-                                              T out[4][3], const ElemArgs<T> &A, uint32_t ge) {
+                                              T out[4][3]) {
   const int la[4] = {lo16(d.lcp.x), hi16(d.lcp.x), lo16(d.lcp.y), hi16(d.lcp.y)};
   T D[3][3], X[3][3], DV[3][3];
   {
@@ -894,7 +896,7 @@ __device__ __forceinline__ void element_jv_m1(const ElemIn<T> &d, const T *uS, c
       Lh[i][j] = DV[i][0] * CX[j][0] + DV[i][1] * CX[j][1] + DV[i][2] * CX[j][2];
   const T s1 = T(mp.mu) * id * T(1.0 / 6.0);
   const T s2 = det * idx * idx * T(1.0 / 6.0);
-  const T bX = T(A.lcoef[ge]) * s2;
+  const T bX = d.cx * s2;
   const T bT = T(mp.lam) * s2 * (Lh[0][0] + Lh[1][1] + Lh[2][2]);
   // B = bX Lh^T + bT I and Gs = s1 C^T C (symmetric)
   T B[3][3], Gs[3][3];
@@ -996,7 +998,7 @@ __global__ __launch_bounds__(NTB) void k_elem_block(ElemArgs<T> A) {
   // The inputs of this thread's first element are requested before the node
   // gather so all of these loads are in flight together.
   ElemIn<T> ea;
-  if (tid < ne) load_elem<MAT>(A, uint32_t(e0 + tid), ea);
+  if (tid < ne) load_elem<MAT, OP>(A, uint32_t(e0 + tid), ea);
 
   // Phase 1: gather nodal state (and direction) of the block.  The first slot
   // of each thread is requested into registers together with its phase-3
@@ -1084,7 +1086,7 @@ __global__ __launch_bounds__(NTB) void k_elem_block(ElemArgs<T> A) {
   auto run = [&](const ElemIn<T> &d) {
     T out[4][3];
     if constexpr (OP == OP_JV && MAT == NLE_MAT_M1)
-      element_jv_m1<T>(d, uS, vS, xS, NL, mp, out, A, d.ge);
+      element_jv_m1<T>(d, uS, vS, xS, NL, mp, out);
     else if constexpr (OP == OP_JV)
       element_jv<T, MAT>(d, uS, vS, xS, NL, mp, out, A, d.ge);
     else
@@ -1098,7 +1100,7 @@ __global__ __launch_bounds__(NTB) void k_elem_block(ElemArgs<T> A) {
     }
   };
   for (int e = tid; e < ne; e += NTB) {
-    if (e != tid) load_elem<MAT>(A, uint32_t(e0 + e), ea);
+    if (e != tid) load_elem<MAT, OP>(A, uint32_t(e0 + e), ea);
     run(ea);
   }
   if (bad && A.flag) A.flag[inst] = 1;
