@@ -7,7 +7,7 @@ chosen method (mesh upload, partition and material setup are done once,
 outside the timed region; every load step's linearizations are inside).
 Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--method ink_mixed_cg_amg]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--method ink_mixed_cg3_amg]
 """
 
 from __future__ import annotations
@@ -63,6 +63,9 @@ METHODS = {
                                             "pc": "amg", "h0_refresh": 20}),
     # the cycle is symmetric for the symmetric dead-load tangent: CG with it
     "ink_mixed_cg_amg": ("ink", "mixed", {"ksp": "cg", "pc": "amg"}),
+    # the same iterates with the next direction formed inside the Jacobian
+    # action (3 launches per CG iteration besides the cycle)
+    "ink_mixed_cg3_amg": ("ink", "mixed", {"ksp": "cg", "pc": "amg", "cg_launches": 3}),
     "ink_fp64_cg_amg": ("ink", "fp64", {"ksp": "cg", "pc": "amg"}),
     # plain FP64 Newton-Krylov with the same multigrid (the like-for-like
     # baseline: App. A tolerances rtol 1e-6 / atol 1e-10)
@@ -620,7 +623,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--method", default="ink_mixed_cg_amg", choices=sorted(METHODS))
+    ap.add_argument("--method", default="ink_mixed_cg3_amg", choices=sorted(METHODS))
     ap.add_argument("--baseline", default="nk_fp64_minres_amg", choices=sorted(METHODS))
     ap.add_argument("--compare", default="ink_fp64_cg_amg,ink_mixed,bfgs_ib_mixed_r20",
                     help="comma-separated extra methods, run once each ('' for none)")
@@ -637,7 +640,8 @@ def main():
                     help="serial FP64 NK baseline on every k-th batch instance (0 skips it)")
     ap.add_argument("--batch-only", action="store_true", help="only the batched-solve leg")
     ap.add_argument("--twist", type=int, default=24, help="twist cube cells per edge (0 skips)")
-    ap.add_argument("--twist-methods", default="nk_fp64,ink_mixed_schur_mass_amg")
+    ap.add_argument("--twist-methods",
+                    default="nk_fp64,nk_fp64_schur_mass_amg,ink_mixed_schur_mass_amg")
     ap.add_argument("--twist-p0", type=int, default=12,
                     help="cells per edge of the P2-P0 polyconvex twist leg (0 skips)")
     ap.add_argument("--twist-p0-methods",
@@ -840,7 +844,9 @@ def main():
             "preconditioner": {"jacobi": "Jacobi", "bjacobi3": "nodal 3x3 block Jacobi",
                                "amg": "aggregation multigrid, one V(1,1)-cycle"}[
                 METHODS[args.method][2].get("pc", PC["pc"])],
-            "krylov": METHODS[args.method][2].get("ksp", "cg"),
+            "krylov": METHODS[args.method][2].get("ksp", "cg") + (
+                " (next direction formed in the Jacobian action)"
+                if METHODS[args.method][2].get("cg_launches") == 3 else ""),
             "parallelism": "1 GPU",
         },
         "solved": all_ok,

@@ -155,13 +155,14 @@ typedef struct {
   int32_t qn_m;       /* L-BFGS memory (App. A uses 50)                       */
   int32_t h0;         /* NLE_H0_PREONLY / NLE_H0_KSP                          */
   int32_t check_every;/* Krylov iterations queued between host checks        */
-  int32_t cg_launches;/* CG launches per iteration: 4 (a separate direction
-                         kernel; also 0, the default) or 3 (the next
-                         direction and the stopping test are formed inside
-                         the Jacobian action; P1 meshes without surface
-                         loads, else 4).  Same iterates bit for bit; the
-                         copy of r.r that the stagnation test reads lags
-                         one iteration in the 3-launch form              */
+  int32_t cg_launches;/* CG launches per iteration besides a multigrid
+                         cycle: 4 (a separate direction kernel; also 0,
+                         the default) or 3 (the next direction and the
+                         stopping test are formed inside the Jacobian
+                         action; P1 meshes without surface loads, else 4).
+                         Same iterates bit for bit; the copy of r.r that
+                         the stagnation test reads lags one iteration in
+                         the 3-launch form                               */
   double ksp_rtol, ksp_atol;        /* NK: 1e-6, 1e-10                    */
   double ew_rtol0, ew_rtolmax;      /* iNK: 0.1, 0.1                      */
   double ew_rtolmin;                /* lower clip of eta (0: none); mixed

@@ -291,9 +291,11 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
       // three launches per iteration (the next direction and the stopping
       // test formed inside the Jacobian action) on request, where the element
       // kernels support it; four otherwise.  On the 64x64x4 Cook mesh both
-      // take ~20 us per iteration: the fused form saves a launch but adds the
-      // partial sums to the Jacobian action's critical path.
-      const bool fuse = !c->mixed && c->surf.nsn == 0 && o.cg_launches == 3 && !amg;
+      // take ~20 us per iteration with point Jacobi: the fused form saves a
+      // launch but adds the partial sums to the Jacobian action's critical
+      // path.  With the multigrid the cycle runs after the update and
+      // overwrites z and the r.z partials that the next Jacobian action reads.
+      const bool fuse = !c->mixed && c->surf.nsn == 0 && o.cg_launches == 3;
       if (fuse) {
         c->cg.z = a.z;
         c->cg.red = red_b;
@@ -306,11 +308,11 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
         a.np_a = elem_apply(c, OP_JV, prec, ulin, a.p, a.Ap, nullptr, &err);
         if (err != hipSuccess) return err;
         err = cg_update(c, a, fuse);
-        if (err != hipSuccess || fuse) return err;
+        if (err != hipSuccess) return err;
         if (amg) {  // z = M^-1 r by one cycle (the update left z = r), with the r.z partials
           if ((err = amg_apply(c, prec, a.r, a.z, red_b)) != hipSuccess) return err;
         }
-        return cg_direction(c, a);
+        return fuse ? hipSuccess : cg_direction(c, a);
       };
       std::vector<uint64_t> key = {1, uint64_t(prec), uint64_t(n), uint64_t(check),
                                    uint64_t(uintptr_t(x)), uint64_t(uintptr_t(a.r)),

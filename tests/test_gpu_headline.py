@@ -60,7 +60,8 @@ def _check(P, ustar, uh, tol, method):
     return err
 
 
-@pytest.mark.parametrize("method", ["ink_mixed_cg_amg", "ink_fp64_cg_amg", "nk_fp64_minres_amg"])
+@pytest.mark.parametrize("method", ["ink_mixed_cg3_amg", "ink_mixed_cg_amg", "ink_fp64_cg_amg",
+                                    "nk_fp64_minres_amg"])
 def test_headline_schedule_matches_oracle_root(cook64, method):
     mesh, P, ustar, ctx = cook64
     solver, prec, kw = bench.METHODS[method]
