@@ -25,6 +25,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <thread>
 #include <vector>
 
 #include "nle_amg.hpp"
@@ -497,6 +498,59 @@ nle_status build_structure(Ctx *c, Amg *A) {
   return NLE_OK;
 }
 
+// nx.val = P^T l.val P for the coarse operator pattern of nx.  Each coarse
+// vertex's rows are formed by one host thread in the same order whatever the
+// thread count, so the values are the same bit for bit.
+nle_status galerkin(Ctx *c, const Level &l, Level &nx) {
+  nx.val.assign(nx.ci.size(), 0.0);
+  const int64_t nagg = nx.nv;
+  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const int nth = int(std::max<int64_t>(1, std::min<int64_t>(nagg, hw)));
+  std::vector<char> bad(size_t(nth), 0);
+  auto work = [&](int t) {
+    std::vector<int32_t> marker(size_t(nx.n), -1);
+    std::vector<double> tr, acc;
+    for (int64_t a = t; a < nagg; a += nth) {
+      const int64_t R0 = nx.vbeg[a], ka = nx.vbeg[a + 1] - R0;
+      const int32_t p0 = nx.rp[R0], width = nx.rp[R0 + 1] - p0;
+      for (int32_t q = 0; q < width; ++q) marker[nx.ci[p0 + q]] = q;
+      acc.assign(size_t(ka * width), 0.0);
+      tr.resize(width);
+      for (int32_t q = l.rs[R0]; q < l.re[R0]; ++q) {
+        const int32_t r = l.arows[q];
+        std::fill(tr.begin(), tr.end(), 0.0);
+        for (int32_t e2 = l.rp[r]; e2 < l.rp[r + 1]; ++e2) {
+          const int32_t s = l.ci[e2];
+          const double av = l.val[e2];
+          for (int j = 0; j < l.pk[s]; ++j) {
+            const int32_t m = marker[l.poff[s] + j];
+            if (m < 0) {
+              bad[size_t(t)] = 1;
+              return;
+            }
+            tr[m] += av * l.pv[size_t(s) * 6 + j];
+          }
+        }
+        for (int64_t i = 0; i < ka; ++i) {
+          const double p = l.pv[size_t(r) * 6 + i];
+          if (p == 0.0) continue;
+          for (int32_t q2 = 0; q2 < width; ++q2) acc[size_t(i * width + q2)] += p * tr[q2];
+        }
+      }
+      for (int64_t i = 0; i < ka; ++i)
+        std::memcpy(nx.val.data() + nx.rp[R0 + i], acc.data() + i * width, size_t(width) * 8);
+      for (int32_t q = 0; q < width; ++q) marker[nx.ci[p0 + q]] = -1;
+    }
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < nth; ++t) th.emplace_back(work, t);
+  work(0);
+  for (std::thread &x : th) x.join();
+  for (char b : bad)
+    if (b) return fail(c, NLE_E_STATE, "multigrid: Galerkin pattern mismatch");
+  return NLE_OK;
+}
+
 // ---- values of the current linearization ----------------------------------------
 nle_status build_values(Ctx *c, Amg *A) {
   const int64_t n0 = A->L[0].n;
@@ -568,8 +622,11 @@ nle_status build_values(Ctx *c, Amg *A) {
     NLE_HIP(c, hipMemcpyAsync(l1.val.data(), l1.d_v64, l1.ci.size() * 8, hipMemcpyDeviceToHost,
                               c->stream));
     NLE_HIP(c, hipStreamSynchronize(c->stream));
-    // coarser levels on the host
-    std::vector<int32_t> marker;
+    // coarser levels on the host; level 1's Jacobi weight by a power
+    // iteration on the GPU (its operator is there already), queued before
+    // the host forms the coarser Galerkin products and read back after them
+    const std::vector<double> x1 = start_vector(A->L[1].n);
+    bool gpu_power = false;
     for (size_t li = 1; li < A->L.size(); ++li) {
       Level &l = A->L[li];
       l.dinv.assign(l.n, 0.0);
@@ -582,39 +639,33 @@ nle_status build_values(Ctx *c, Amg *A) {
         l.dinv[i] = 1.0 / d;
       }
       if (li + 1 == A->L.size()) break;
-      l.w = 1.0 / host_power(l);
-      Level &nx = A->L[li + 1];
-      nx.val.assign(nx.ci.size(), 0.0);
-      marker.assign(nx.n, -1);
-      std::vector<double> tr, acc;
-      for (int64_t a = 0; a < nx.nv; ++a) {
-        const int64_t R0 = nx.vbeg[a], ka = nx.vbeg[a + 1] - R0;
-        const int32_t p0 = nx.rp[R0], width = nx.rp[R0 + 1] - p0;
-        for (int32_t q = 0; q < width; ++q) marker[nx.ci[p0 + q]] = q;
-        acc.assign(size_t(ka * width), 0.0);
-        tr.resize(width);
-        for (int32_t q = l.rs[R0]; q < l.re[R0]; ++q) {
-          const int32_t r = l.arows[q];
-          std::fill(tr.begin(), tr.end(), 0.0);
-          for (int32_t e2 = l.rp[r]; e2 < l.rp[r + 1]; ++e2) {
-            const int32_t s = l.ci[e2];
-            const double av = l.val[e2];
-            for (int j = 0; j < l.pk[s]; ++j) {
-              const int32_t m = marker[l.poff[s] + j];
-              if (m < 0) return fail(c, NLE_E_STATE, "multigrid: Galerkin pattern mismatch");
-              tr[m] += av * l.pv[size_t(s) * 6 + j];
-            }
-          }
-          for (int64_t i = 0; i < ka; ++i) {
-            const double p = l.pv[size_t(r) * 6 + i];
-            if (p == 0.0) continue;
-            for (int32_t q2 = 0; q2 < width; ++q2) acc[size_t(i * width + q2)] += p * tr[q2];
-          }
+      if (li == 1) {
+        NLE_HIP(c, hipMemcpyAsync(l.d_dinv64, l.dinv.data(), size_t(l.n) * 8,
+                                  hipMemcpyHostToDevice, c->stream));
+        NLE_HIP(c, hipMemcpyAsync(A->d_z, x1.data(), size_t(l.n) * 8, hipMemcpyHostToDevice,
+                                  c->stream));
+        for (int it = 0; it < POWER_ITS; ++it) {
+          NLE_HIP(c, amg_csr_mv(c, A->d_t, A->d_z, l.d_rp, l.d_ci, l.d_v64, l.n));
+          const int np = amg_power_partials(c, A->d_t, l.d_dinv64, A->d_z, A->d_y, l.n, A->d_red, &e);
+          if (e != hipSuccess) return fail(c, NLE_E_HIP, "multigrid: power iteration");
+          NLE_HIP(c, reduce_scalars(c, A->d_red, np, 2, A->d_s));
+          if (it + 1 < POWER_ITS) NLE_HIP(c, amg_power_scale(c, A->d_y, A->d_s, A->d_z, l.n));
         }
-        for (int64_t i = 0; i < ka; ++i)
-          std::memcpy(nx.val.data() + nx.rp[R0 + i], acc.data() + i * width, size_t(width) * 8);
-        for (int32_t q = 0; q < width; ++q) marker[nx.ci[p0 + q]] = -1;
+        gpu_power = true;
+      } else {
+        l.w = 1.0 / host_power(l);
       }
+      const nle_status sg = galerkin(c, l, A->L[li + 1]);
+      if (sg != NLE_OK) return sg;
+    }
+    if (gpu_power) {
+      double s[2];
+      NLE_HIP(c, hipMemcpyAsync(s, A->d_s, 16, hipMemcpyDeviceToHost, c->stream));
+      NLE_HIP(c, hipStreamSynchronize(c->stream));
+      const double lam = std::sqrt(s[0]) / std::sqrt(s[1]);
+      if (!(lam > 0.0) || !std::isfinite(lam))
+        return fail(c, NLE_E_STATE, "multigrid: bad spectral radius estimate");
+      A->L[1].w = 1.0 / lam;
     }
     const Level &lc = A->L.back();
     std::vector<double> D(size_t(lc.n * lc.n), 0.0);

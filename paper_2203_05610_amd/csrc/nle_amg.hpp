@@ -31,6 +31,9 @@ hipError_t amg_probe_vec(Ctx *c, double *z, const double *pv0, const int32_t *pk
                          const int32_t *dcol, int colour, int k, int64_t n);
 hipError_t amg_extract(Ctx *c, const double *y, const double *pv0, const AmgTasks &t, int k,
                        double *val);
+// t = A x for a coarse level's CSR operator (FP64)
+hipError_t amg_csr_mv(Ctx *c, double *t, const double *x, const int32_t *rp, const int32_t *ci,
+                      const double *v, int64_t n);
 // y = dinv * t; partials of y.y at red[0..g) and x.x at red[VGRID_MAX..)
 int amg_power_partials(Ctx *c, const double *t, const double *dinv, const double *x, double *y,
                        int64_t n, double *red, hipError_t *err);

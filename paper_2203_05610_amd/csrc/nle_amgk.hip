@@ -136,6 +136,21 @@ __global__ __launch_bounds__(NT) void k_cheb_step(T *x, T *d, const T *b, const 
   }
 }
 
+// t = A x for a coarse level's operator (the power estimate of its Jacobi
+// weight): one wave per row, fixed-order wave sum.
+__global__ __launch_bounds__(NT) void k_csr_mv(double *t, const double *x, const int32_t *rp,
+                                               const int32_t *ci, const double *v, int64_t n) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w0 = (int64_t(blockIdx.x) * NT + threadIdx.x) >> 6;
+  const int64_t nw = (int64_t(gridDim.x) * NT) >> 6;
+  for (int64_t i = w0; i < n; i += nw) {
+    double s = 0.0;
+    for (int32_t q = rp[i] + lane; q < rp[i + 1]; q += 64) s += v[q] * x[ci[q]];
+    s = wave_total(s);
+    if (lane == 0) t[i] = s;
+  }
+}
+
 // Coarse-level kernels run one wave per row (rows of the coarse operators
 // hold ~100 entries and there are only a few thousand rows: a thread per row
 // would leave most of the chip idle); lanes stride over the row, then a
@@ -249,6 +264,12 @@ hipError_t amg_extract(Ctx *c, const double *y, const double *pv0, const AmgTask
                        double *val) {
   if (t.n == 0) return hipSuccess;
   LAUNCH(k_extract, grid_for(t.n), y, pv0, t, k, val);
+  return hipGetLastError();
+}
+
+hipError_t amg_csr_mv(Ctx *c, double *t, const double *x, const int32_t *rp, const int32_t *ci,
+                      const double *v, int64_t n) {
+  LAUNCH(k_csr_mv, grid_waves(n), t, x, rp, ci, v, n);
   return hipGetLastError();
 }
 
