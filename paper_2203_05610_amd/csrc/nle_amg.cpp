@@ -707,7 +707,7 @@ AmgXfer<void> xfer(const Level &l, const Level &nx, int prec) {
 // level returns in *res where its result is (x, or its residual buffer, which
 // the fused post-smoother writes to).
 hipError_t cycle(Ctx *c, Amg *A, int prec, size_t li, const void *b, void *x,
-                 const void **res, double *red_dot) {
+                 const void **res, double *red_dot, bool first_done = false) {
   const Level &l = A->L[li];
   const bool f32 = prec == NLE_FP32;
   *res = x;
@@ -721,7 +721,8 @@ hipError_t cycle(Ctx *c, Amg *A, int prec, size_t li, const void *b, void *x,
     // finest level: Chebyshev smoothing with the matrix-free Jacobian action
     const void *dinv = f32 ? static_cast<const void *>(c->dinv32) : c->dinv64;
     const void *ulin = f32 ? static_cast<const void *>(c->ulin32) : c->ulin64;
-    if ((e = amg_cheb_first(c, prec, x, A->d_cd, b, dinv, A->cheb_cr[0], l.n)) != hipSuccess)
+    if (!first_done &&
+        (e = amg_cheb_first(c, prec, x, A->d_cd, b, dinv, A->cheb_cr[0], l.n)) != hipSuccess)
       return e;
     for (int j = 1; j < CHEB_DEGREE; ++j) {
       elem_apply(c, OP_JV, prec, ulin, x, A->d_t, nullptr, &e);
@@ -794,9 +795,19 @@ nle_status amg_prepare(Ctx *c) {
   return NLE_OK;
 }
 
-hipError_t amg_apply(Ctx *c, int prec, const void *b, void *x, double *red_dot) {
+bool amg_first_step(Ctx *c, int prec, const void **dinv, void **d, double *inv_theta) {
+  Amg *A = state(c);
+  if (!A || !A->valid || A->L.size() < 2 || (c->mixed && c->mx.n_p > 0)) return false;
+  *dinv = prec == NLE_FP32 ? static_cast<const void *>(c->dinv32) : c->dinv64;
+  *d = A->d_cd;
+  *inv_theta = A->cheb_cr[0];
+  return true;
+}
+
+hipError_t amg_apply(Ctx *c, int prec, const void *b, void *x, double *red_dot, bool first_done) {
   Amg *A = state(c);
   if (!A || !A->valid) return hipErrorNotReady;
+  if (first_done && (A->L.size() < 2 || (c->mixed && c->mx.n_p > 0))) return hipErrorInvalidValue;
   // the smoother's Jacobian actions are the plain tangent: a Krylov loop's
   // epilogue (MINRES: y = J v - coef w with v.y partials) or fused CG
   // direction must not act inside the cycle
@@ -837,7 +848,7 @@ hipError_t amg_apply(Ctx *c, int prec, const void *b, void *x, double *red_dot) 
     vec_dot_partials(c, prec, b, x, A->L[0].n, red_dot, &e);
     return e;
   }
-  return cycle(c, A, prec, 0, b, x, &res, red_dot);  // level 0 works in place: res == x
+  return cycle(c, A, prec, 0, b, x, &res, red_dot, first_done);  // level 0 works in place
 }
 
 int amg_levels(const Ctx *c, int64_t *sizes, int cap) {

@@ -385,8 +385,13 @@ hipError_t vec_recip(Ctx *c, const double *d, double *dinv, int64_t n);
 // amg_invalidate marks the values stale (new linearization); amg_release
 // frees everything (new mesh or Dirichlet set, destroy).
 nle_status amg_prepare(Ctx *c);
-// red_dot (nullable): also write the partials of b . x at red_dot[0 .. vgrid(n))
-hipError_t amg_apply(Ctx *c, int prec, const void *b, void *x, double *red_dot = nullptr);
+// red_dot (nullable): also write the partials of b . x at red_dot[0 .. vgrid(n));
+// first_done: the caller has already taken the finest level's first Chebyshev
+// step, x = d = inv_theta D^-1 b, with the arguments amg_first_step gives
+// (false when the hierarchy has no such step: one level, or a pressure field)
+hipError_t amg_apply(Ctx *c, int prec, const void *b, void *x, double *red_dot = nullptr,
+                     bool first_done = false);
+bool amg_first_step(Ctx *c, int prec, const void **dinv, void **d, double *inv_theta);
 void amg_invalidate(Ctx *c);
 void amg_release(Ctx *c);
 int amg_levels(const Ctx *c, int64_t *sizes, int cap);
@@ -434,6 +439,10 @@ struct CgArgs {
   double *red_b;      // partials of (r.z, r.r), 2 x VGRID_MAX
   double *scal;       // device scalars
   int32_t *flag;      // [0] state (1 converged, 2 breakdown, 3 NaN, 5 limit), [1] its
+  // with the multigrid: the update also takes the cycle's first Chebyshev
+  // step, z = cd = cth D^-1 r (dinv then holds the finest level's D^-1)
+  void *cd = nullptr;
+  double cth = 0.0;
 };
 // finish = false leaves out the final reduction (cg_start_finish), so that a
 // preconditioner applied outside the kernels can replace z, p and the r.z partials

@@ -277,12 +277,16 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
       a.scal = c->dscal;
       a.flag = flag;
       a.np_a = 0;
+      // with the multigrid the update also takes the cycle's first
+      // Chebyshev step (the same arithmetic as the cycle's own kernel)
+      bool first = false;
       if (amg) {
         // the cycle replaces z = p = M^-1 b and the r.z partials
         NLE_HIP(c, cg_start(c, a, b, o.rtol, o.atol, o.max_it, false));
         NLE_HIP(c, amg_apply(c, prec, a.r, a.z, red_b));
         NLE_HIP(c, hipMemcpyAsync(a.p, a.z, vb, hipMemcpyDeviceToDevice, c->stream));
         NLE_HIP(c, cg_start_finish(c, a, o.rtol, o.atol, o.max_it));
+        first = amg_first_step(c, prec, &a.dinv, &a.cd, &a.cth);
       } else {
         NLE_HIP(c, cg_start(c, a, b, o.rtol, o.atol, o.max_it));
       }
@@ -309,8 +313,9 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
         if (err != hipSuccess) return err;
         err = cg_update(c, a, fuse);
         if (err != hipSuccess) return err;
-        if (amg) {  // z = M^-1 r by one cycle (the update left z = r), with the r.z partials
-          if ((err = amg_apply(c, prec, a.r, a.z, red_b)) != hipSuccess) return err;
+        if (amg) {  // z = M^-1 r by one cycle (the update left z = r, or took its first
+                    // step), with the r.z partials
+          if ((err = amg_apply(c, prec, a.r, a.z, red_b, first)) != hipSuccess) return err;
         }
         return fuse ? hipSuccess : cg_direction(c, a);
       };
@@ -322,7 +327,7 @@ nle_status ksp_solve(Ctx *c, const KspOpts &o, int prec, const void *b, void *x,
                                    uint64_t(uintptr_t(c->mx.G32)), uint64_t(uintptr_t(c->mx.cu)),
                                    uint64_t(uintptr_t(c->lc_valid ? c->lc64 : nullptr)),
                                    uint64_t(pcb), uint64_t(fuse), uint64_t(amg),
-                                   amg ? c->amg_gen : 0};
+                                   amg ? c->amg_gen : 0, uint64_t(first)};
       st = run_chunks(c, key, check, o.max_it, flag, iter);
     } else {
       MinresArgs a;

@@ -282,7 +282,7 @@ template <typename T, int BS, bool FUSED>
 __global__ __launch_bounds__(NT) void k_cg_update(T *x, T *r, T *z, T *p, const T *Ap,
                                                   const T *dinv, int64_t n, const double *red_a,
                                                   int np_a, double *red_b, double *scal,
-                                                  int32_t *flag) {
+                                                  int32_t *flag, T *cd, T cth) {
   __shared__ double shd[NT / 64];
   __shared__ T sh[NT / 64];
   if (flag[0] != 0) return;
@@ -317,6 +317,13 @@ __global__ __launch_bounds__(NT) void k_cg_update(T *x, T *r, T *z, T *p, const 
       r[i] = ri[c];
     }
     pc_unit<BS>(dinv, k, nu, ri, zi);
+    if (cd) {  // the multigrid cycle's first Chebyshev step
+#pragma unroll
+      for (int c = 0; c < BS; ++c) {
+        zi[c] = cth * zi[c];
+        cd[BS * k + c] = zi[c];
+      }
+    }
 #pragma unroll
     for (int c = 0; c < BS; ++c) {
       z[BS * k + c] = zi[c];
@@ -981,7 +988,8 @@ hipError_t cg_update(Ctx *c, const CgArgs &a, bool fused) {
 #define CG_UPD(T, BS, F)                                                                       \
   LAUNCH((k_cg_update<T, BS, F>), g, static_cast<T *>(a.x), static_cast<T *>(a.r),              \
          static_cast<T *>(a.z), static_cast<T *>(a.p), static_cast<const T *>(a.Ap),            \
-         static_cast<const T *>(a.dinv), a.n, a.red_a, a.np_a, a.red_b, a.scal, a.flag)
+         static_cast<const T *>(a.dinv), a.n, a.red_a, a.np_a, a.red_b, a.scal, a.flag,         \
+         static_cast<T *>(a.cd), T(a.cth))
 #define CG_UPD2(T, BS)                                                                         \
   if (fused) CG_UPD(T, BS, true); else CG_UPD(T, BS, false)
   if (a.prec == NLE_FP32) {
