@@ -498,6 +498,45 @@ nle_status build_structure(Ctx *c, Amg *A) {
   return NLE_OK;
 }
 
+// Rows of the coarse vertices a = t, t + nth, ... of nx.val = P^T l.val P
+// (*bad = 1 on a pattern mismatch).
+void galerkin_chunk(const Level &l, Level &nx, int t, int nth, char *bad) {
+  const int64_t nagg = nx.nv;
+  std::vector<int32_t> marker(size_t(nx.n), -1);
+  std::vector<double> tr, acc;
+  for (int64_t a = t; a < nagg; a += nth) {
+    const int64_t R0 = nx.vbeg[a], ka = nx.vbeg[a + 1] - R0;
+    const int32_t p0 = nx.rp[R0], width = nx.rp[R0 + 1] - p0;
+    for (int32_t q = 0; q < width; ++q) marker[nx.ci[p0 + q]] = q;
+    acc.assign(size_t(ka * width), 0.0);
+    tr.resize(width);
+    for (int32_t q = l.rs[R0]; q < l.re[R0]; ++q) {
+      const int32_t r = l.arows[q];
+      std::fill(tr.begin(), tr.end(), 0.0);
+      for (int32_t e2 = l.rp[r]; e2 < l.rp[r + 1]; ++e2) {
+        const int32_t s = l.ci[e2];
+        const double av = l.val[e2];
+        for (int j = 0; j < l.pk[s]; ++j) {
+          const int32_t m = marker[l.poff[s] + j];
+          if (m < 0) {
+            *bad = 1;
+            return;
+          }
+          tr[m] += av * l.pv[size_t(s) * 6 + j];
+        }
+      }
+      for (int64_t i = 0; i < ka; ++i) {
+        const double p = l.pv[size_t(r) * 6 + i];
+        if (p == 0.0) continue;
+        for (int32_t q2 = 0; q2 < width; ++q2) acc[size_t(i * width + q2)] += p * tr[q2];
+      }
+    }
+    for (int64_t i = 0; i < ka; ++i)
+      std::memcpy(nx.val.data() + nx.rp[R0 + i], acc.data() + i * width, size_t(width) * 8);
+    for (int32_t q = 0; q < width; ++q) marker[nx.ci[p0 + q]] = -1;
+  }
+}
+
 // nx.val = P^T l.val P for the coarse operator pattern of nx.  Each coarse
 // vertex's rows are formed by one host thread in the same order whatever the
 // thread count, so the values are the same bit for bit.
@@ -506,48 +545,32 @@ nle_status galerkin(Ctx *c, const Level &l, Level &nx) {
   const int64_t nagg = nx.nv;
   const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   const int nth = int(std::max<int64_t>(1, std::min<int64_t>(nagg, hw)));
-  std::vector<char> bad(size_t(nth), 0);
-  auto work = [&](int t) {
-    std::vector<int32_t> marker(size_t(nx.n), -1);
-    std::vector<double> tr, acc;
-    for (int64_t a = t; a < nagg; a += nth) {
-      const int64_t R0 = nx.vbeg[a], ka = nx.vbeg[a + 1] - R0;
-      const int32_t p0 = nx.rp[R0], width = nx.rp[R0 + 1] - p0;
-      for (int32_t q = 0; q < width; ++q) marker[nx.ci[p0 + q]] = q;
-      acc.assign(size_t(ka * width), 0.0);
-      tr.resize(width);
-      for (int32_t q = l.rs[R0]; q < l.re[R0]; ++q) {
-        const int32_t r = l.arows[q];
-        std::fill(tr.begin(), tr.end(), 0.0);
-        for (int32_t e2 = l.rp[r]; e2 < l.rp[r + 1]; ++e2) {
-          const int32_t s = l.ci[e2];
-          const double av = l.val[e2];
-          for (int j = 0; j < l.pk[s]; ++j) {
-            const int32_t m = marker[l.poff[s] + j];
-            if (m < 0) {
-              bad[size_t(t)] = 1;
-              return;
-            }
-            tr[m] += av * l.pv[size_t(s) * 6 + j];
-          }
-        }
-        for (int64_t i = 0; i < ka; ++i) {
-          const double p = l.pv[size_t(r) * 6 + i];
-          if (p == 0.0) continue;
-          for (int32_t q2 = 0; q2 < width; ++q2) acc[size_t(i * width + q2)] += p * tr[q2];
-        }
-      }
-      for (int64_t i = 0; i < ka; ++i)
-        std::memcpy(nx.val.data() + nx.rp[R0 + i], acc.data() + i * width, size_t(width) * 8);
-      for (int32_t q = 0; q < width; ++q) marker[nx.ci[p0 + q]] = -1;
+  std::vector<char> bad(size_t(nth), 0);  // 1: pattern mismatch, 2: host allocation failed
+  auto work = [&](int t) noexcept {
+    try {
+      galerkin_chunk(l, nx, t, nth, &bad[size_t(t)]);
+    } catch (...) {
+      bad[size_t(t)] = 2;
     }
   };
+  // chunk t (coarse vertices a = t mod nth) runs on thread t; chunks whose
+  // thread could not be started run on this one
   std::vector<std::thread> th;
-  for (int t = 1; t < nth; ++t) th.emplace_back(work, t);
+  int started = 1;
+  try {
+    for (int t = 1; t < nth; ++t) {
+      th.emplace_back(work, t);
+      started = t + 1;
+    }
+  } catch (...) {
+  }
   work(0);
+  for (int t = started; t < nth; ++t) work(t);
   for (std::thread &x : th) x.join();
-  for (char b : bad)
-    if (b) return fail(c, NLE_E_STATE, "multigrid: Galerkin pattern mismatch");
+  for (char b : bad) {
+    if (b == 1) return fail(c, NLE_E_STATE, "multigrid: Galerkin pattern mismatch");
+    if (b == 2) return fail(c, NLE_E_OOM, "multigrid: host allocation failed");
+  }
   return NLE_OK;
 }
 
