@@ -281,11 +281,15 @@ def cpu_baseline(n_load_steps: int):
     }
 
 
-def batch_c4(nl, torch, count: int, serial_stride: int, steps: int, autotune: bool = True):
+def batch_c4(nl, torch, count: int, serial_stride: int, steps: int, autotune: bool = True,
+             tail: int = 0, tail_its: int = 0):
     """Batched solves: `count` sampled Cook instances (uneven size, lambda/mu and
     traction; doubling load schedules ending at each tau) solved in one batch
     with mixed iNK, against serial FP64 NK solves of every `serial_stride`-th
-    instance on the same GPU (the serial time is that sample times the stride)."""
+    instance on the same GPU (the serial time is that sample times the stride).
+    tail > 0: the last `tail` unfinished instances, and tail_its > 0: any
+    instance whose batched CG solve takes more than tail_its iterations, are
+    finished alone with CG and the multigrid."""
     import numpy as np
 
     import synthetic as syn
@@ -303,6 +307,7 @@ def batch_c4(nl, torch, count: int, serial_stride: int, steps: int, autotune: bo
     nl.nle_batch_finalize(B)
     off = nl.nle_batch_layout(B)
     block_size = nl.nle_batch_autotune(B, nl.NLE_FP32, budget_ms=400.0) if autotune else 512
+    nl.nle_batch_set_tail(B, tail, tail_its, nl.NLE_PC_AMG)
     u = torch.zeros(int(3 * off[-1]), dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t
@@ -352,7 +357,11 @@ def batch_c4(nl, torch, count: int, serial_stride: int, steps: int, autotune: bo
         "workload": f"{count} Cook instances (n x n x nz, n in 8..48, nz in 1..3, "
                     "lambda/mu log-uniform 10..1e4, tau 2^U(0,5)), seed 0",
         "tets": n_elems, "nodes": int(off[-1]), "setup_s": round(t_setup, 2), "elements_per_block": block_size,
-        "method": "iNK mixed, CG + Jacobi, all instances per launch",
+        "method": "iNK mixed, CG + Jacobi, all instances per launch" + (
+            f"; the last {tail} unfinished instances finished alone with CG + multigrid"
+            if tail > 0 else "") + (
+            f"; instances whose CG solve takes over {tail_its} iterations finished alone with "
+            "CG + multigrid" if tail_its > 0 else ""),
         "seconds": [round(x, 3) for x in times], "solved": f"{min(oks)}/{count}",
         "instances_per_s": round(count / t_batch, 3),
         "serial_fp64_nk": serial,
@@ -636,6 +645,12 @@ def main():
     ap.add_argument("--no-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=256,
                     help="instances of the batched-solve leg (0 skips it)")
+    ap.add_argument("--batch-tail", type=int, default=0,
+                    help="finish the last N unfinished instances of the batch alone with CG + "
+                         "multigrid (0: all in the batch rounds)")
+    ap.add_argument("--batch-tail-its", type=int, default=0,
+                    help="finish alone with CG + multigrid any instance whose batched CG solve "
+                         "takes more than N iterations (0: never)")
     ap.add_argument("--batch-serial-stride", type=int, default=64,
                     help="serial FP64 NK baseline on every k-th batch instance (0 skips it)")
     ap.add_argument("--batch-only", action="store_true", help="only the batched-solve leg")
@@ -689,7 +704,8 @@ def main():
     if args.batch_only:
         print(json.dumps({"batch_only": True,
                           "batch": batch_c4(nl, torch, args.batch, args.batch_serial_stride,
-                                            max(args.steps, 1))}))
+                                            max(args.steps, 1), tail=args.batch_tail,
+                                            tail_its=args.batch_tail_its)}))
         return
 
     if args.legs_only:
@@ -799,7 +815,8 @@ def main():
 
     batch = None
     if args.batch > 0:
-        batch = batch_c4(nl, torch, args.batch, args.batch_serial_stride, 1)
+        batch = batch_c4(nl, torch, args.batch, args.batch_serial_stride, 1, tail=args.batch_tail,
+                         tail_its=args.batch_tail_its)
     twist = twist_c3(nl, torch, args.twist, args.twist_methods.split(",")) if args.twist > 0 else None
     twist_p0 = (twist_c3(nl, torch, args.twist_p0, args.twist_p0_methods.split(","), p0=True)
                 if args.twist_p0 > 0 else None)

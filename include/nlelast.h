@@ -572,6 +572,20 @@ nle_status nle_batch_layout(const nle_batch *b, int64_t *node_offsets);
  * nle_batch_finalize. */
 nle_status nle_batch_solve(nle_batch *b, int32_t method, const nle_solver_opts *opts, double *u_dev,
                            nle_report *reports, double *t_ms);
+/* Instances that leave the batch rounds (the sweeps of Sec. 6 mix easy and
+ * stiff instances, and a round's batched CG lasts as long as its stiffest
+ * solve).  An instance leaves when at most max_tail instances are unfinished,
+ * or (NK and iNK) when its batched CG solve of a round takes more than max_its
+ * iterations; nle_batch_solve then finishes it alone, at once, with the
+ * single-problem solver (a context of its own on the batch's device, stream
+ * and allocator, the batch's method and options with preconditioner pc, e.g.
+ * NLE_PC_AMG), from its last converged state over the rest of its schedule, a
+ * failed increment halved as in the batch rounds within the same budget of
+ * cutbacks.  Its report then counts the iterations of both parts.  Zero (the
+ * default) turns either rule off.  NLE_E_INVAL for a negative count or an
+ * unknown pc; errors of the single-problem calls are returned by
+ * nle_batch_solve with their message. */
+nle_status nle_batch_set_tail(nle_batch *b, int32_t max_tail, int32_t max_its, int32_t pc);
 
 /* Unknowns per level of the multigrid hierarchy built by the last NLE_PC_AMG
  * use (finest first): *n_levels = number of levels (0 if none is built),

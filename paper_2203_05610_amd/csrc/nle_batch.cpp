@@ -51,6 +51,11 @@ struct Batch {
   int32_t *d_blist = nullptr, *d_mlist = nullptr, *d_slist = nullptr;
   double *h_pin = nullptr;  // pinned host staging, 16 n_inst doubles
   int64_t replays = 0;      // replays of captured Krylov chunks (graph launches)
+  // the tail: when at most tail_max instances are unfinished, or (NK, iNK)
+  // when an instance's batched CG solve of a round takes more than tail_its
+  // iterations, it is finished alone with the single-problem solver and
+  // preconditioner tail_pc
+  int32_t tail_max = 0, tail_its = 0, tail_pc = NLE_PC_AMG;
 };
 
 nle_status bfail(Batch *b, nle_status s, const std::string &m) {
@@ -455,6 +460,110 @@ nle_status batch_cg(Batch *b, const BatchCg &cg, int prec, const void *ulin, con
   return NLE_OK;
 }
 
+// Finish instance i alone (the tail of a batch solve): a context of its own on
+// the batch's stream and allocator, the single-problem solver with the batch's
+// method and options but preconditioner tail_pc, from the last converged state
+// (ub) over the current scale and the rest of the schedule, a failed increment
+// halved as in the batch rounds (the same budget of cutbacks).  The result, or
+// the last converged state if the schedule fails, goes to u.
+template <typename St>
+nle_status finish_alone(Batch *b, int32_t i, int method, const nle_solver_opts &o, double *u,
+                        const double *ub, St &I, int max_cuts) {
+  Ctx *c = b->c;
+  const Inst &in = b->inst[size_t(i)];
+  const int64_t nn = int64_t(in.X.size() / 3), ne = int64_t(in.conn.size() / 4);
+  const int64_t d0 = 3 * b->node_off[size_t(i)], nd = 3 * nn;
+  nle_ctx *sub = nullptr;
+  nle_status st = nle_create(&sub, c->device, c->stream, &c->al);
+  if (st != NLE_OK) return bfail(b, st, "tail: context creation failed");
+  struct Guard {
+    Ctx *c;
+    nle_ctx *sub;
+    double *us = nullptr, *usb = nullptr;
+    ~Guard() {
+      if (us) dfree(c, us);
+      if (usb) dfree(c, usb);
+      nle_destroy(sub);
+    }
+  } g{c, sub};
+  auto sfail = [&](nle_status s2) {
+    return bfail(b, s2, std::string("tail: ") + nle_last_error(sub));
+  };
+  if ((st = nle_upload_mesh(sub, nn, in.X.data(), ne, 4, in.conn.data())) != NLE_OK)
+    return sfail(st);
+  const int32_t np = b->kind == NLE_MAT_M2 ? 3 : 2;
+  if ((st = nle_set_material(sub, b->kind, in.params, np)) != NLE_OK) return sfail(st);
+  if ((st = nle_set_dirichlet(sub, int64_t(in.ddofs.size()), in.ddofs.data(), in.dvals.data())) !=
+      NLE_OK)
+    return sfail(st);
+  if (!in.tri.empty() &&
+      (st = nle_set_traction(sub, int64_t(in.tri.size() / 3), in.tri.data(), in.t)) != NLE_OK)
+    return sfail(st);
+  g.us = static_cast<double *>(dalloc(c, size_t(nd) * 8));
+  g.usb = static_cast<double *>(dalloc(c, size_t(nd) * 8));
+  if (!g.us || !g.usb) return bfail(b, NLE_E_OOM, "tail: device allocation failed");
+  BHIP(b, hipMemcpyAsync(g.us, ub + d0, size_t(nd) * 8, hipMemcpyDeviceToDevice, c->stream));
+  BHIP(b, hipMemcpyAsync(g.usb, ub + d0, size_t(nd) * 8, hipMemcpyDeviceToDevice, c->stream));
+  nle_solver_opts oo = o;
+  oo.pc = b->tail_pc;
+  auto solver = method == NLE_NK ? nle_solve_nk : (method == NLE_INK ? nle_solve_ink : nle_solve_bfgs);
+  std::vector<double> tg{I.s_cur};
+  for (size_t k = size_t(I.step); k < in.scales.size(); ++k)
+    if (in.scales[k] > I.s_cur) tg.push_back(in.scales[k]);
+  double s_prev = I.s_prev;
+  int status = NLE_OK;
+  size_t k = 0;
+  while (k < tg.size()) {
+    if ((st = nle_set_load_scale(sub, tg[k])) != NLE_OK) return sfail(st);
+    nle_report rep{};
+    st = solver(sub, g.us, &oo, &rep);
+    if (st < 0) return sfail(st);
+    I.nit += rep.nit;
+    I.lit += rep.lit_total;
+    I.njv += rep.n_jv;
+    I.nres += rep.n_residual;
+    I.skipped += rep.bfgs_skipped;
+    I.rn = rep.rnorm_final;
+    if (st == NLE_OK) {
+      BHIP(b, hipMemcpyAsync(g.usb, g.us, size_t(nd) * 8, hipMemcpyDeviceToDevice, c->stream));
+      s_prev = tg[k];
+      ++k;
+      continue;
+    }
+    BHIP(b, hipMemcpyAsync(g.us, g.usb, size_t(nd) * 8, hipMemcpyDeviceToDevice, c->stream));
+    if (I.cuts >= max_cuts) {
+      status = st;
+      break;
+    }
+    I.cuts += 1;
+    tg.insert(tg.begin() + std::ptrdiff_t(k), 0.5 * (s_prev + tg[k]));
+  }
+  BHIP(b, hipMemcpyAsync(u + d0, g.us, size_t(nd) * 8, hipMemcpyDeviceToDevice, c->stream));
+  BHIP(b, hipStreamSynchronize(c->stream));
+  I.s_prev = s_prev;
+  I.finished = true;
+  I.status = status;
+  return NLE_OK;
+}
+
+// Finish every unfinished instance alone once at most tail_max remain
+// (returns true when it did).
+template <typename St>
+nle_status maybe_tail(Batch *b, int method, const nle_solver_opts &o, double *u, const double *ub,
+                      std::vector<St> &S, int max_cuts, bool *done) {
+  *done = false;
+  int left = 0;
+  for (const St &I : S) left += I.finished ? 0 : 1;
+  if (b->tail_max <= 0 || left == 0 || left > b->tail_max) return NLE_OK;
+  for (size_t i = 0; i < S.size(); ++i)
+    if (!S[i].finished) {
+      const nle_status st = finish_alone(b, int32_t(i), method, o, u, ub, S[i], max_cuts);
+      if (st != NLE_OK) return st;
+    }
+  *done = true;
+  return NLE_OK;
+}
+
 nle_status solve(Batch *b, int method, const nle_solver_opts &o, double *u, nle_report *reports,
                  double *t_ms) {
   Ctx *c = b->c;
@@ -522,6 +631,12 @@ nle_status solve(Batch *b, int method, const nle_solver_opts &o, double *u, nle_
     bool any = false;
     for (int32_t i = 0; i < n; ++i) any |= !S[i].finished;
     if (!any) break;
+    {
+      bool tail = false;
+      st = maybe_tail(b, method, o, u, ub, S, max_cuts, &tail);
+      if (st != NLE_OK) return st;
+      if (tail) break;
+    }
     // ---- residuals of all unfinished instances ---------------------------
     for (int32_t i = 0; i < n; ++i) {
       hs[i] = S[i].s_cur;
@@ -651,6 +766,15 @@ nle_status solve(Batch *b, int method, const nle_solver_opts &o, double *u, nle_
           S[i].lit += its[i];
           S[i].njv += its[i];
         }
+      // instances whose solve took more than tail_its iterations leave the
+      // rounds (the rest of this round skips them) and are finished alone
+      if (b->tail_its > 0)
+        for (int32_t i = 0; i < n; ++i)
+          if (S[i].newton && its[i] > b->tail_its) {
+            S[i].newton = false;
+            st = finish_alone(b, i, method, o, u, ub, S[i], max_cuts);
+            if (st != NLE_OK) return st;
+          }
     }
     // ---- iNK: ||r + J du|| per instance ------------------------------------------
     if (inexact) {
@@ -824,6 +948,12 @@ nle_status solve_bfgs(Batch *b, const nle_solver_opts &o, double *u, nle_report 
     bool any = false;
     for (int32_t i = 0; i < n; ++i) any |= !S[i].finished;
     if (!any) break;
+    {
+      bool tail = false;
+      st = maybe_tail(b, NLE_BFGS, o, u, ub, S, max_cuts, &tail);
+      if (st != NLE_OK) return st;
+      if (tail) break;
+    }
     // ---- residuals (the gradients g) of all unfinished instances -------------
     for (int32_t i = 0; i < n; ++i) {
       hs[i] = S[i].s_cur;
@@ -1216,6 +1346,18 @@ nle_status nle_batch_layout(const nle_batch *h, int64_t *node_offsets) {
   if (!h || !node_offsets) return NLE_E_INVAL;
   if (!h->b.finalized) return NLE_E_STATE;
   std::copy(h->b.node_off.begin(), h->b.node_off.end(), node_offsets);
+  return NLE_OK;
+}
+
+nle_status nle_batch_set_tail(nle_batch *h, int32_t max_tail, int32_t max_its, int32_t pc) {
+  if (!h) return NLE_E_INVAL;
+  Batch *b = &h->b;
+  if (max_tail < 0 || max_its < 0) return bfail(b, NLE_E_INVAL, "max_tail and max_its must be >= 0");
+  if (pc != NLE_PC_NONE && pc != NLE_PC_JACOBI && pc != NLE_PC_BJACOBI3 && pc != NLE_PC_AMG)
+    return bfail(b, NLE_E_INVAL, "bad tail preconditioner");
+  b->tail_max = max_tail;
+  b->tail_its = max_its;
+  b->tail_pc = pc;
   return NLE_OK;
 }
 

@@ -52,7 +52,7 @@ EXPORTS = [
     "nle_set_robin", "nle_set_traction_follower", "nle_upload_mesh_mixed", "nle_block_diag", "nle_pc_apply", "nle_batch_autotune",
     "nle_set_inertia", "nle_newmark_predict", "nle_newmark_correct", "nle_amg_levels",
     "nle_set_robin_damping", "nle_set_step_velocity", "nle_jv_noalloc", "nle_upload_mesh_mixed_p0",
-    "nle_schur_apply", "nle_simple_diag", "nle_set_fibre_frame",
+    "nle_schur_apply", "nle_simple_diag", "nle_set_fibre_frame", "nle_batch_set_tail",
 ]
 
 
@@ -153,6 +153,7 @@ def lib() -> ctypes.CDLL:
                                 ctypes.POINTER(I32)]),
         "nle_batch_finalize": (I32, [P]),
         "nle_batch_autotune": (I32, [P, I32, D, P]),
+        "nle_batch_set_tail": (I32, [P, I32, I32, I32]),
         "nle_batch_layout": (I32, [P, ctypes.POINTER(I64)]),
         "nle_batch_solve": (I32, [P, I32, ctypes.POINTER(nle_solver_opts), P,
                                   ctypes.POINTER(nle_report), ctypes.POINTER(D)]),
@@ -623,6 +624,13 @@ def nle_batch_autotune(b: Batch, prec: int = NLE_FP32, budget_ms: float = 200.0)
     out = ctypes.c_int32()
     b.check(lib().nle_batch_autotune(b.handle, int(prec), float(budget_ms), ctypes.byref(out)))
     return out.value
+
+
+def nle_batch_set_tail(b: Batch, max_tail: int, max_its: int = 0, pc: int = NLE_PC_AMG) -> None:
+    """Finish alone, with preconditioner pc, the last max_tail unfinished
+    instances and (NK, iNK) any instance whose batched CG solve takes more
+    than max_its iterations in a round (0 turns either rule off)."""
+    b.check(lib().nle_batch_set_tail(b.handle, int(max_tail), int(max_its), int(pc)))
 
 
 def nle_batch_layout(b: Batch):

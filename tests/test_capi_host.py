@@ -91,3 +91,4 @@ def test_newer_calls_reject_null_arguments_without_a_device():
     assert L.nle_set_robin_damping(None, 1.0, 1.0) == nl.NLE_E_INVAL
     assert L.nle_set_step_velocity(None, 1.0, None) == nl.NLE_E_INVAL
     assert L.nle_newmark_predict(None, 0.1, 0.25, 0.5, None, None, None, None, None) == nl.NLE_E_INVAL
+    assert L.nle_batch_set_tail(None, 4, 0, nl.NLE_PC_AMG) == nl.NLE_E_INVAL

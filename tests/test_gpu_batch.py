@@ -150,6 +150,71 @@ def test_batch_recipe_sample_matches_stored_oracle_roots():
     assert max(errs) <= 1e-6, list(zip(ids, errs))
 
 
+@pytest.mark.parametrize("tail,max_its", [(len(INSTANCES), 0), (2, 0), (0, 50)])
+def test_batch_tail_finishes_instances_alone_with_the_multigrid(tail, max_its):
+    # once at most `tail` instances are unfinished, or once an instance's
+    # batched CG solve takes more than max_its iterations, it is finished alone
+    # with the single-problem solver and the multigrid (all five from the
+    # start; the last two after batch rounds with point Jacobi; the stiff ones
+    # after their first round); every instance still lands on its oracle root,
+    # and its report counts both parts
+    data = _roots()
+    B = nl.Batch(0)
+    for (m, P, sched, _), (nx, ny, nz, ratio, tau) in zip(data, INSTANCES):
+        problems.add_cook_instance(B, m, MU, ratio * MU, 1.0, sched)
+    nl.nle_batch_finalize(B)
+    nl.nle_batch_set_tail(B, tail, max_its, nl.NLE_PC_AMG)
+    off = nl.nle_batch_layout(B)
+    u = torch.zeros(int(3 * off[-1]), dtype=torch.float64, device="cuda")
+    st, reps, tms = nl.nle_batch_solve(B, nl.NLE_INK, problems.make_opts("ink", "mixed", ksp="cg"), u)
+    assert st == nl.NLE_OK, reps
+    assert tms > 0
+    uh = u.cpu().numpy()
+    for i, (m, P, sched, ustar) in enumerate(data):
+        ui = uh[3 * off[i]: 3 * off[i + 1]]
+        err = np.linalg.norm(ui - ustar) / np.linalg.norm(ustar)
+        assert err <= 1e-6, (i, err, reps[i])
+        assert reps[i]["nit"] >= len(sched)
+        assert reps[i]["lit_total"] > 0
+
+
+def test_batch_tail_recipe_sample_matches_stored_oracle_roots():
+    # the 16-instance sample of the batch recipe with its last four instances
+    # finished alone with the multigrid, against the stored oracle roots
+    import os
+
+    gold = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                "batch16_roots.npz"))
+    recipe = syn.batch_recipe(256)
+    ids = list(range(0, 256, 16))
+    B = nl.Batch(0)
+    for i in ids:
+        r = recipe[i]
+        m = syn.cook_mesh(r["nx"], r["ny"], r["nz"])
+        problems.add_cook_instance(B, m, r["mu"], r["lam"], 1.0, syn.cook_load_schedule(r["tau"]))
+    nl.nle_batch_finalize(B)
+    nl.nle_batch_set_tail(B, 4, 0, nl.NLE_PC_AMG)
+    off = nl.nle_batch_layout(B)
+    u = torch.zeros(int(3 * off[-1]), dtype=torch.float64, device="cuda")
+    st, reps, _ = nl.nle_batch_solve(B, nl.NLE_INK, problems.make_opts("ink", "mixed", ksp="cg"), u)
+    assert st == nl.NLE_OK, [(r["status"], r["nit"]) for r in reps]
+    uh = u.cpu().numpy()
+    errs = [float(np.linalg.norm(uh[3 * off[k]: 3 * off[k + 1]] - gold[f"i{i}"]) /
+                  np.linalg.norm(gold[f"i{i}"])) for k, i in enumerate(ids)]
+    assert max(errs) <= 1e-6, list(zip(ids, errs))
+
+
+def test_batch_tail_usage_errors():
+    B = nl.Batch(0)
+    with pytest.raises(nl.NleError):
+        nl.nle_batch_set_tail(B, -1, 0, nl.NLE_PC_AMG)
+    with pytest.raises(nl.NleError):
+        nl.nle_batch_set_tail(B, 0, -5, nl.NLE_PC_AMG)
+    with pytest.raises(nl.NleError):
+        nl.nle_batch_set_tail(B, 2, 0, 9)
+    nl.nle_batch_set_tail(B, 0, 0, nl.NLE_PC_JACOBI)  # off
+
+
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
 def test_batch_invariance_bitwise(precision):
     # an instance solved inside a batch of uneven neighbours gives bit for bit
