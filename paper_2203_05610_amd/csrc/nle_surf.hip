@@ -1,11 +1,12 @@
 // Surface loads of the heartbeat test (Sec. 4): a follower pressure on the
 // endocardium and elastic Robin springs on the epicardium.
 //
-// One thread per face node sums the contributions of its incident faces in
-// increasing face order and writes the node's three values to a dense
-// per-dof buffer (zero off the face nodes); the element kernels add that
-// buffer when they finalize each node.  No atomics: the result is bitwise
-// reproducible.
+// Each face node sums the contributions of its incident faces (P1 faces: eight
+// lanes per node, each taking every eighth face, summed by a fixed butterfly;
+// 6-node faces: one thread per node, in increasing face order) and writes the
+// node's three values to a dense per-dof buffer (zero off the face nodes); the
+// element kernels add that buffer when they finalize each node.  No atomics:
+// the result is bitwise reproducible.
 //
 // Pressure p (times the load scale) on a flat triangle with current vertices
 // x0, x1, x2 (outward from the body): each vertex gets p (x1-x0) x (x2-x0) / 6
@@ -60,145 +61,164 @@ __device__ __forceinline__ void cross_acc(const T a[3], const T b[3], T s, T acc
   acc[2] += s * (a[0] * b[1] - a[1] * b[0]);
 }
 
+// Contributions of face f to node g (a vertex of f), added to acc.
 template <typename T, int OP>
-__global__ __launch_bounds__(NT) void k_surface(SurfArgs<T> A) {
-  __shared__ double sh[NT / 64];
-  if (A.skip && A.skip[0] != 0) return;
-  const int64_t k = int64_t(blockIdx.x) * NT + threadIdx.x;
-  double e = 0.0;
-  if (k < A.nsn) {
-    const int32_t g = A.node[k];
-    T acc[3] = {T(0), T(0), T(0)};
-    const T pe = OP == OP_JV ? T(A.plin[0]) : T(A.p);
-    for (int q = A.ptr[k]; q < A.ptr[k + 1]; ++q) {
-      const int32_t f = A.ent[q];
-      const int32_t n[3] = {A.tri[3 * f], A.tri[3 * f + 1], A.tri[3 * f + 2]};
-      if (f < A.npf + A.ntf) {
-        const bool trac = f >= A.npf;
-        if (OP == OP_RES || OP == OP_JV || (trac && (OP == OP_DIAG || OP == OP_ODIAG))) {
-          const T *Xf = A.pgeo + 9 * int64_t(f);
-          T x[3][3];
+__device__ __forceinline__ void surface_face(const SurfArgs<T> &A, int32_t g, int32_t f, T pe,
+                                             T acc[3]) {
+  const int32_t n[3] = {A.tri[3 * f], A.tri[3 * f + 1], A.tri[3 * f + 2]};
+  if (f < A.npf + A.ntf) {
+    const bool trac = f >= A.npf;
+    if (OP == OP_RES || OP == OP_JV || (trac && (OP == OP_DIAG || OP == OP_ODIAG))) {
+      const T *Xf = A.pgeo + 9 * int64_t(f);
+      T x[3][3];
 #pragma unroll
-          for (int a = 0; a < 3; ++a)
+      for (int a = 0; a < 3; ++a)
 #pragma unroll
-            for (int i = 0; i < 3; ++i) x[a][i] = Xf[3 * a + i] + A.u[3 * int64_t(n[a]) + i];
-          T e1[3], e2[3];
+        for (int i = 0; i < 3; ++i) x[a][i] = Xf[3 * a + i] + A.u[3 * int64_t(n[a]) + i];
+      T e1[3], e2[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        e1[i] = x[1][i] - x[0][i];
+        e2[i] = x[2][i] - x[0][i];
+      }
+      const T s = pe / T(6);
+      if (trac) {
+        T a2[3] = {T(0), T(0), T(0)};
+        cross_acc(e1, e2, T(1), a2);
+        const T l = sqrt(a2[0] * a2[0] + a2[1] * a2[1] + a2[2] * a2[2]);
+        const T tv[3] = {T(A.tf[0]), T(A.tf[1]), T(A.tf[2])};
+        // the Jacobian action and the (lazily formed) nodal blocks use the
+        // load scale of the linearization
+        const T sc = ((OP == OP_JV || OP == OP_ODIAG) ? T(A.plin[1]) : T(A.s)) / T(6);
+        if (OP == OP_RES) {
+#pragma unroll
+          for (int i = 0; i < 3; ++i) acc[i] -= sc * l * tv[i];
+        } else if (OP == OP_JV) {
+          const uint32_t fm = A.nomask ? 0u : A.fmask[f];
+          T d1[3], d2[3];
 #pragma unroll
           for (int i = 0; i < 3; ++i) {
-            e1[i] = x[1][i] - x[0][i];
-            e2[i] = x[2][i] - x[0][i];
+            const T v0 = ((fm >> i) & 1u) ? T(0) : A.v[3 * int64_t(n[0]) + i];
+            const T v1 = ((fm >> (3 + i)) & 1u) ? T(0) : A.v[3 * int64_t(n[1]) + i];
+            const T v2 = ((fm >> (6 + i)) & 1u) ? T(0) : A.v[3 * int64_t(n[2]) + i];
+            d1[i] = v1 - v0;
+            d2[i] = v2 - v0;
           }
-          const T s = pe / T(6);
-          if (trac) {
-            T a2[3] = {T(0), T(0), T(0)};
-            cross_acc(e1, e2, T(1), a2);
-            const T l = sqrt(a2[0] * a2[0] + a2[1] * a2[1] + a2[2] * a2[2]);
-            const T tv[3] = {T(A.tf[0]), T(A.tf[1]), T(A.tf[2])};
-            // the Jacobian action and the (lazily formed) nodal blocks use the
-            // load scale of the linearization
-            const T sc = ((OP == OP_JV || OP == OP_ODIAG) ? T(A.plin[1]) : T(A.s)) / T(6);
-            if (OP == OP_RES) {
+          T da[3] = {T(0), T(0), T(0)};
+          cross_acc(d1, e2, T(1), da);
+          cross_acc(e1, d2, T(1), da);
+          const T dl = (a2[0] * da[0] + a2[1] * da[1] + a2[2] * da[2]) / l;
 #pragma unroll
-              for (int i = 0; i < 3; ++i) acc[i] -= sc * l * tv[i];
-            } else if (OP == OP_JV) {
-              const uint32_t fm = A.nomask ? 0u : A.fmask[f];
-              T d1[3], d2[3];
+          for (int i = 0; i < 3; ++i) acc[i] -= sc * dl * tv[i];
+        } else {
+          // this node's own block: -s/6 t (x) dl/dx_a
+          const int a = n[0] == g ? 0 : (n[1] == g ? 1 : 2);
+          const T nh[3] = {a2[0] / l, a2[1] / l, a2[2] / l};
+          T w[3];
 #pragma unroll
-              for (int i = 0; i < 3; ++i) {
-                const T v0 = ((fm >> i) & 1u) ? T(0) : A.v[3 * int64_t(n[0]) + i];
-                const T v1 = ((fm >> (3 + i)) & 1u) ? T(0) : A.v[3 * int64_t(n[1]) + i];
-                const T v2 = ((fm >> (6 + i)) & 1u) ? T(0) : A.v[3 * int64_t(n[2]) + i];
-                d1[i] = v1 - v0;
-                d2[i] = v2 - v0;
-              }
-              T da[3] = {T(0), T(0), T(0)};
-              cross_acc(d1, e2, T(1), da);
-              cross_acc(e1, d2, T(1), da);
-              const T dl = (a2[0] * da[0] + a2[1] * da[1] + a2[2] * da[2]) / l;
+          for (int i = 0; i < 3; ++i) w[i] = a == 0 ? e1[i] - e2[i] : (a == 1 ? e2[i] : T(0));
+          T ga[3] = {T(0), T(0), T(0)};
+          if (a == 2)
+            cross_acc(nh, e1, T(1), ga);
+          else
+            cross_acc(w, nh, T(1), ga);
 #pragma unroll
-              for (int i = 0; i < 3; ++i) acc[i] -= sc * dl * tv[i];
-            } else {
-              // this node's own block: -s/6 t (x) dl/dx_a
-              const int a = n[0] == g ? 0 : (n[1] == g ? 1 : 2);
-              const T nh[3] = {a2[0] / l, a2[1] / l, a2[2] / l};
-              T w[3];
-#pragma unroll
-              for (int i = 0; i < 3; ++i) w[i] = a == 0 ? e1[i] - e2[i] : (a == 1 ? e2[i] : T(0));
-              T ga[3] = {T(0), T(0), T(0)};
-              if (a == 2)
-                cross_acc(nh, e1, T(1), ga);
-              else
-                cross_acc(w, nh, T(1), ga);
-#pragma unroll
-              for (int i = 0; i < 3; ++i) {
-                if (OP == OP_DIAG)
-                  acc[i] -= sc * tv[i] * ga[i];
-                else
-                  acc[i] -= T(0.5) * sc * (tv[i] * ga[(i + 1) % 3] + ga[i] * tv[(i + 1) % 3]);
-              }
-            }
-          } else if (OP == OP_RES) {
-            cross_acc(e1, e2, s, acc);
-          } else if (OP == OP_JV) {
-            // the tangent has identity rows and columns on Dirichlet dofs:
-            // v's prescribed components do not enter the coupling
-            const uint32_t fm = A.nomask ? 0u : A.fmask[f];
-            T d1[3], d2[3];
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-              const T v0 = ((fm >> i) & 1u) ? T(0) : A.v[3 * int64_t(n[0]) + i];
-              const T v1 = ((fm >> (3 + i)) & 1u) ? T(0) : A.v[3 * int64_t(n[1]) + i];
-              const T v2 = ((fm >> (6 + i)) & 1u) ? T(0) : A.v[3 * int64_t(n[2]) + i];
-              d1[i] = v1 - v0;
-              d2[i] = v2 - v0;
-            }
-            cross_acc(d1, e2, s, acc);
-            cross_acc(e1, d2, s, acc);
+          for (int i = 0; i < 3; ++i) {
+            if (OP == OP_DIAG)
+              acc[i] -= sc * tv[i] * ga[i];
+            else
+              acc[i] -= T(0.5) * sc * (tv[i] * ga[(i + 1) % 3] + ga[i] * tv[(i + 1) % 3]);
           }
         }
-      } else {
-        const T *R = A.rgeo + 4 * int64_t(f - A.npf - A.ntf);
-        const T N[3] = {R[0], R[1], R[2]};
-        const T area = R[3];
-        const T kpar = T(A.kpar), dk = T(A.kperp - A.kpar);
-        // the dashpots' force C (vt + cv (u - ut)) adds cv C to the tangent
-        const T kpe = A.damp ? T(A.kpar + A.cv * A.cpar) : kpar;
-        const T dke = A.damp ? T(A.kperp - A.kpar + A.cv * (A.cperp - A.cpar)) : dk;
-        if (OP == OP_DIAG) {
+      } else if (OP == OP_RES) {
+        cross_acc(e1, e2, s, acc);
+      } else if (OP == OP_JV) {
+        // the tangent has identity rows and columns on Dirichlet dofs:
+        // v's prescribed components do not enter the coupling
+        const uint32_t fm = A.nomask ? 0u : A.fmask[f];
+        T d1[3], d2[3];
 #pragma unroll
-          for (int i = 0; i < 3; ++i) acc[i] += area / T(6) * (kpe + dke * N[i] * N[i]);
-        } else if (OP == OP_ODIAG) {
+        for (int i = 0; i < 3; ++i) {
+          const T v0 = ((fm >> i) & 1u) ? T(0) : A.v[3 * int64_t(n[0]) + i];
+          const T v1 = ((fm >> (3 + i)) & 1u) ? T(0) : A.v[3 * int64_t(n[1]) + i];
+          const T v2 = ((fm >> (6 + i)) & 1u) ? T(0) : A.v[3 * int64_t(n[2]) + i];
+          d1[i] = v1 - v0;
+          d2[i] = v2 - v0;
+        }
+        cross_acc(d1, e2, s, acc);
+        cross_acc(e1, d2, s, acc);
+      }
+    }
+  } else {
+    const T *R = A.rgeo + 4 * int64_t(f - A.npf - A.ntf);
+    const T N[3] = {R[0], R[1], R[2]};
+    const T area = R[3];
+    const T kpar = T(A.kpar), dk = T(A.kperp - A.kpar);
+    // the dashpots' force C (vt + cv (u - ut)) adds cv C to the tangent
+    const T kpe = A.damp ? T(A.kpar + A.cv * A.cpar) : kpar;
+    const T dke = A.damp ? T(A.kperp - A.kpar + A.cv * (A.cperp - A.cpar)) : dk;
+    if (OP == OP_DIAG) {
 #pragma unroll
-          for (int i = 0; i < 3; ++i) acc[i] += area / T(6) * dke * N[i] * N[(i + 1) % 3];
-        } else {
-          const T *w = OP == OP_JV ? A.v : A.u;
-          const uint32_t fm = (OP == OP_JV && !A.nomask) ? A.fmask[f] : 0u;
-          const T kw = OP == OP_JV ? kpe : kpar, dw = OP == OP_JV ? dke : dk;
+      for (int i = 0; i < 3; ++i) acc[i] += area / T(6) * (kpe + dke * N[i] * N[i]);
+    } else if (OP == OP_ODIAG) {
 #pragma unroll
-          for (int b = 0; b < 3; ++b) {
-            const T m = area / T(12) * (n[b] == g ? T(2) : T(1));
-            const int64_t nb = int64_t(n[b]);
-            T wb[3];
+      for (int i = 0; i < 3; ++i) acc[i] += area / T(6) * dke * N[i] * N[(i + 1) % 3];
+    } else {
+      const T *w = OP == OP_JV ? A.v : A.u;
+      const uint32_t fm = (OP == OP_JV && !A.nomask) ? A.fmask[f] : 0u;
+      const T kw = OP == OP_JV ? kpe : kpar, dw = OP == OP_JV ? dke : dk;
 #pragma unroll
-            for (int i = 0; i < 3; ++i)
-              wb[i] = ((fm >> (3 * b + i)) & 1u) ? T(0) : w[3 * nb + i];
-            const T nw = N[0] * wb[0] + N[1] * wb[1] + N[2] * wb[2];
+      for (int b = 0; b < 3; ++b) {
+        const T m = area / T(12) * (n[b] == g ? T(2) : T(1));
+        const int64_t nb = int64_t(n[b]);
+        T wb[3];
 #pragma unroll
-            for (int i = 0; i < 3; ++i) acc[i] += m * (kw * wb[i] + dw * nw * N[i]);
-            if (OP == OP_RES && A.damp) {
-              T z[3];
+        for (int i = 0; i < 3; ++i)
+          wb[i] = ((fm >> (3 * b + i)) & 1u) ? T(0) : w[3 * nb + i];
+        const T nw = N[0] * wb[0] + N[1] * wb[1] + N[2] * wb[2];
 #pragma unroll
-              for (int i = 0; i < 3; ++i)
-                z[i] = T(A.vt[3 * nb + i] + A.cv * (double(A.u[3 * nb + i]) - A.ut[3 * nb + i]));
-              const T nz = N[0] * z[0] + N[1] * z[1] + N[2] * z[2];
-              const T cpar = T(A.cpar), dc = T(A.cperp - A.cpar);
+        for (int i = 0; i < 3; ++i) acc[i] += m * (kw * wb[i] + dw * nw * N[i]);
+        if (OP == OP_RES && A.damp) {
+          T z[3];
 #pragma unroll
-              for (int i = 0; i < 3; ++i) acc[i] += m * (cpar * z[i] + dc * nz * N[i]);
-            }
-          }
+          for (int i = 0; i < 3; ++i)
+            z[i] = T(A.vt[3 * nb + i] + A.cv * (double(A.u[3 * nb + i]) - A.ut[3 * nb + i]));
+          const T nz = N[0] * z[0] + N[1] * z[1] + N[2] * z[2];
+          const T cpar = T(A.cpar), dc = T(A.cperp - A.cpar);
+#pragma unroll
+          for (int i = 0; i < 3; ++i) acc[i] += m * (cpar * z[i] + dc * nz * N[i]);
         }
       }
     }
+  }
+}
+
+// SL lanes per face node: lane j of a node takes its incident faces j, j + SL,
+// ... (in increasing face order) and the node's lanes, which are consecutive
+// and aligned in a wave, are summed by a fixed butterfly.  SL = 8 keeps a face
+// node's ~6 dependent face loads in flight together; the energy (one partial
+// per workgroup of nodes) runs with SL = 1.
+template <typename T, int OP, int SL>
+__global__ __launch_bounds__(NT) void k_surface(SurfArgs<T> A) {
+  __shared__ double sh[NT / 64];
+  if (A.skip && A.skip[0] != 0) return;
+  const int64_t t = int64_t(blockIdx.x) * NT + threadIdx.x;
+  const int64_t k = t / SL;
+  const int sub = int(t % SL);
+  double e = 0.0;
+  T acc[3] = {T(0), T(0), T(0)};
+  int32_t g = 0;
+  if (k < A.nsn) {
+    g = A.node[k];
+    const T pe = OP == OP_JV ? T(A.plin[0]) : T(A.p);
+    for (int q = A.ptr[k] + sub; q < A.ptr[k + 1]; q += SL)
+      surface_face<T, OP>(A, g, A.ent[q], pe, acc);
+  }
+#pragma unroll
+  for (int o = SL / 2; o > 0; o >>= 1)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) acc[i] += __shfl_xor(acc[i], o);
+  if (k < A.nsn && sub == 0) {
     if (OP == OP_ENERGY) {
 #pragma unroll
       for (int i = 0; i < 3; ++i) e += 0.5 * double(A.u[3 * int64_t(g) + i]) * double(acc[i]);
@@ -437,21 +457,23 @@ void launch_surface(Ctx *c, int op, const T *u, const T *v, T *fs, double *red, 
     }
     return;
   }
+  constexpr int SL = 8;
+  const int grid8 = int((SL * S.nsn + NT - 1) / NT);
   switch (op) {
     case OP_RES:
-      hipLaunchKernelGGL((k_surface<T, OP_RES>), dim3(grid), dim3(NT), 0, c->stream, A);
+      hipLaunchKernelGGL((k_surface<T, OP_RES, SL>), dim3(grid8), dim3(NT), 0, c->stream, A);
       break;
     case OP_JV:
-      hipLaunchKernelGGL((k_surface<T, OP_JV>), dim3(grid), dim3(NT), 0, c->stream, A);
+      hipLaunchKernelGGL((k_surface<T, OP_JV, SL>), dim3(grid8), dim3(NT), 0, c->stream, A);
       break;
     case OP_DIAG:
-      hipLaunchKernelGGL((k_surface<T, OP_DIAG>), dim3(grid), dim3(NT), 0, c->stream, A);
+      hipLaunchKernelGGL((k_surface<T, OP_DIAG, SL>), dim3(grid8), dim3(NT), 0, c->stream, A);
       break;
     case OP_ODIAG:
-      hipLaunchKernelGGL((k_surface<T, OP_ODIAG>), dim3(grid), dim3(NT), 0, c->stream, A);
+      hipLaunchKernelGGL((k_surface<T, OP_ODIAG, SL>), dim3(grid8), dim3(NT), 0, c->stream, A);
       break;
     default:
-      hipLaunchKernelGGL((k_surface<T, OP_ENERGY>), dim3(grid), dim3(NT), 0, c->stream, A);
+      hipLaunchKernelGGL((k_surface<T, OP_ENERGY, 1>), dim3(grid), dim3(NT), 0, c->stream, A);
       break;
   }
 }
