@@ -178,6 +178,28 @@ def test_batch_tail_finishes_instances_alone_with_the_multigrid(tail, max_its):
         assert reps[i]["lit_total"] > 0
 
 
+def test_batch_bfgs_tail_finishes_instances_alone():
+    # batched inexact BFGS (mixed, m = 10): the last two unfinished instances
+    # are finished alone by the single-problem BFGS solver with the multigrid
+    # in its H0 solve; every instance still lands on its oracle root
+    data = _roots()
+    B = nl.Batch(0)
+    for (m, P, sched, _), (nx, ny, nz, ratio, tau) in zip(data, INSTANCES):
+        problems.add_cook_instance(B, m, MU, ratio * MU, 1.0, sched)
+    nl.nle_batch_finalize(B)
+    nl.nle_batch_set_tail(B, 2, 0, nl.NLE_PC_AMG)
+    off = nl.nle_batch_layout(B)
+    u = torch.zeros(int(3 * off[-1]), dtype=torch.float64, device="cuda")
+    o = problems.make_opts("bfgs", "mixed", ksp="cg", h0="ksp", qn_m=10)
+    st, reps, _ = nl.nle_batch_solve(B, nl.NLE_BFGS, o, u)
+    assert st == nl.NLE_OK, [(r["status_name"], r["nit"], r["cutbacks"]) for r in reps]
+    uh = u.cpu().numpy()
+    for i, (m, P, sched, ustar) in enumerate(data):
+        ui = uh[3 * off[i]: 3 * off[i + 1]]
+        err = np.linalg.norm(ui - ustar) / np.linalg.norm(ustar)
+        assert err <= 1e-6, (i, err, reps[i])
+
+
 def test_batch_tail_recipe_sample_matches_stored_oracle_roots():
     # the 16-instance sample of the batch recipe with its last four instances
     # finished alone with the multigrid, against the stored oracle roots
