@@ -201,6 +201,39 @@ def test_heartbeat_4x20x64_to_peak_matches_stored_oracle_root(method, prec, kw):
     assert err <= (1e-8 if prec == "fp64" else 1e-6), err
 
 
+@pytest.mark.parametrize("method,prec,kw", [
+    ("ink", "fp64", {"ksp": "cg", "pc": "amg", "snes_rtol": 1e-10, "ksp_atol": 1e-14}),
+    ("ink", "mixed", {"ksp": "cg", "pc": "amg"}),
+    ("nk", "fp64", {"ksp": "minres", "pc": "amg", "snes_rtol": 1e-10, "ksp_atol": 1e-14}),
+])
+def test_heartbeat_strong_pressure_symmetric_krylov_reaches_oracle_root(method, prec, kw):
+    # 50 times the endocardial pressure and twice the activation, 10 steps to
+    # the peak: the follower pressure's nonsymmetric part grows with p (at the
+    # oracle's root ||K - K^T||_F / ||K||_F is about 4e-6, 40 times that of
+    # the nominal load), and the shell's largest displacement triples.  CG and
+    # MINRES, which assume a symmetric tangent, still bring every Newton step
+    # to the FP64 rule, and the solution is the oracle's exact-Newton root.
+    import scipy.sparse.linalg as sla
+
+    c = dict(C)
+    c["p_max"] = 50.0 * C["p_max"]
+    c["gamma_max"] = 2.0 * C["gamma_max"]
+    mesh = syn.shell_mesh(2, 6, 12)
+    steps = syn.heartbeat_schedule()[:10]
+    P = fem.cardiac_problem(mesh, c)
+    ustar = newton.solve_heartbeat(P, steps, c["gamma_max"])[0]
+    K = P.stiffness(ustar, load_scale=steps[-1][1])
+    assert sla.norm(K - K.T) > 1e-6 * sla.norm(K)
+    ctx = nl.Context(0)
+    problems.setup_cardiac(ctx, mesh, c, syn.shell_dirichlet(mesh), block_size=128)
+    opts = problems.make_opts(method, prec, **dict(kw))
+    u = torch.zeros(mesh.n_dofs, dtype=torch.float64, device="cuda")
+    reps = problems.solve_heartbeat(ctx, u, method, opts, steps, c["gamma_max"])
+    assert problems.heartbeat_ok(reps, steps), [(r["t"], r["status_name"]) for r in reps]
+    err = relnorm(u.cpu().numpy(), ustar)
+    assert err <= (1e-8 if prec == "fp64" else 1e-6), err
+
+
 # ---- the paper's Guccione law (M6) with the fibre / sheet frame ------------------
 GUC = (0.1, 5.0, 2.0, 2.0, 1.0, 1.0, 1.0, 100.0)  # C, b_ff, b_ss, b_nn, b_fs, b_fn, b_sn, B
 
