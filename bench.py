@@ -27,6 +27,9 @@ sys.path.insert(0, ROOT)
 MU = 80.194
 RATIO = 5000.0
 GRID = (64, 64, 4)
+# elements per block of the timed mesh: 98,304 tets in 256 blocks of 384, one
+# per compute unit (512 leaves 192 blocks, fewer than the chip's 256 CUs)
+HEAD_BLOCK = 384
 XL_GRID = (256, 256, 16)
 HBM_PEAK_GBS = 8000.0
 JV_KERNEL = "nle_jv FP32 (k_elem_block<float,JV> + k_elem_merge<float,JV>)"
@@ -637,6 +640,8 @@ def main():
     ap.add_argument("--compare", default="ink_fp64_cg_amg,ink_mixed,bfgs_ib_mixed_r20",
                     help="comma-separated extra methods, run once each ('' for none)")
     ap.add_argument("--jv-reps", type=int, default=200)
+    ap.add_argument("--block-size", type=int, default=HEAD_BLOCK,
+                    help="elements per block of the timed Cook mesh")
     ap.add_argument("--pc", default="jacobi", choices=["jacobi", "bjacobi3"],
                     help="preconditioner of the Cook methods that name none (point or nodal "
                          "3x3 block Jacobi)")
@@ -731,7 +736,7 @@ def main():
     t_setup = time.perf_counter()
     mesh = syn.cook_mesh(*GRID)
     ctx = nl.Context(0)
-    problems.setup_cook(ctx, mesh, MU, RATIO * MU, 1.0)
+    problems.setup_cook(ctx, mesh, MU, RATIO * MU, 1.0, block_size=args.block_size)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
     u = torch.zeros(3 * mesh.n_nodes, dtype=torch.float64, device="cuda")
@@ -864,6 +869,7 @@ def main():
             "krylov": METHODS[args.method][2].get("ksp", "cg") + (
                 " (next direction formed in the Jacobian action)"
                 if METHODS[args.method][2].get("cg_launches") == 3 else ""),
+            "elements_per_block": args.block_size,
             "parallelism": "1 GPU",
         },
         "solved": all_ok,

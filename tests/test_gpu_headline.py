@@ -42,7 +42,7 @@ def cook64():
     ustar = np.load(GOLDEN)
     assert ustar.shape == (P.n_dofs,)
     ctx = nl.Context(0)
-    problems.setup_cook(ctx, mesh, MU, bench.RATIO * MU, 1.0)
+    problems.setup_cook(ctx, mesh, MU, bench.RATIO * MU, 1.0, block_size=bench.HEAD_BLOCK)
     yield mesh, P, ustar, ctx
     ctx.close()
 
