@@ -1148,12 +1148,7 @@ __global__ __launch_bounds__(NTB) void k_elem_block(ElemArgs<T> A) {
   }
 }
 
-// NPT = 2 (single problems with more shared nodes than the chip holds merge
-// threads at once): each thread takes nodes k and k + NT of its workgroup's
-// 2 NT, and the first four partials of both are requested before either is
-// summed or stored, so one wave of workgroups covers the nodes.  Each node's
-// sum keeps the order of merge_node.
-template <typename T, int OP, int NPT>
+template <typename T, int OP>
 __global__ __launch_bounds__(NT) void k_elem_merge(MergeArgs<T> A) {
   __shared__ double rs[NT / 64];
   if (A.skip && A.skip[0] != 0) return;
@@ -1161,78 +1156,13 @@ __global__ __launch_bounds__(NT) void k_elem_merge(MergeArgs<T> A) {
   const int inst = A.mwg_inst ? A.mwg_inst[wg] : 0;
   if (A.inst_done && A.inst_done[inst]) return;
   const double lscale = A.inst_s ? A.inst_s[inst] : A.s;
+  const int64_t k = int64_t(wg) * NT + threadIdx.x;
   double nrm = 0.0;
-  const T bt = A.vz ? T(A.cg_scal[cgslot::BETA]) : T(0);
-  const T epc = A.ep_coef ? T(A.ep_coef[0]) : T(0);
-  if constexpr (NPT == 1) {
-    const int64_t k = int64_t(wg) * NT + threadIdx.x;
-    if (k < A.n_sh)
-      merge_node<T, OP>(A.fx_node, A.fx_ptr, A.partial, k, A.v, A.vz, bt, A.out, A.fext, lscale,
-                        nrm, A.ep_red != nullptr, A.ep_w, epc, A.fs, A.nomask, A.icm, A.iut,
-                        A.u);
-  } else {
-    uint32_t w[NPT];
-    int q0[NPT], q1[NPT];
-#pragma unroll
-    for (int j = 0; j < NPT; ++j) {
-      const int64_t k = int64_t(wg) * (NPT * NT) + j * NT + threadIdx.x;
-      w[j] = 0xFFFFFFFFu;
-      q0[j] = q1[j] = 0;
-      if (k < A.n_sh) {
-        w[j] = A.fx_node[k];
-        q0[j] = A.fx_ptr[k];
-        q1[j] = A.fx_ptr[k + 1];
-      }
-    }
-    // the first four partials of each node, read unconditionally at indexes
-    // clamped into the node's range (or to entry 0, which exists since
-    // n_sh > 0), so the loads issue without branches; entries past the
-    // range are not added
-    T acc[NPT][3], pv[NPT][4][3];
-#pragma unroll
-    for (int j = 0; j < NPT; ++j) {
-      const int last = q1[j] > q0[j] ? q1[j] - 1 : 0;
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int64_t qq = 3 * int64_t(min(q0[j] + t, last));
-#pragma unroll
-        for (int i = 0; i < 3; ++i) pv[j][t][i] = A.partial[qq + i];
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < NPT; ++j) {
-      acc[j][0] = acc[j][1] = acc[j][2] = T(0);
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
-        if (q0[j] + t < q1[j]) {
-          acc[j][0] += pv[j][t][0];
-          acc[j][1] += pv[j][t][1];
-          acc[j][2] += pv[j][t][2];
-        }
-      for (int q = q0[j] + 4; q < q1[j]; q += 4) {
-        T pq[4][3];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int64_t qq = 3 * int64_t(min(q + t, q1[j] - 1));
-#pragma unroll
-          for (int i = 0; i < 3; ++i) pq[t][i] = A.partial[qq + i];
-        }
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-          if (q + t < q1[j]) {
-            acc[j][0] += pq[t][0];
-            acc[j][1] += pq[t][1];
-            acc[j][2] += pq[t][2];
-          }
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < NPT; ++j)
-      if (w[j] != 0xFFFFFFFFu)
-        finalize_node<T, OP>(w[j] & NODE_MASK, (w[j] >> 28) & 7u, acc[j], A.v, A.vz, bt, A.out,
-                             A.fext, lscale, nrm, A.ep_red != nullptr, A.ep_w, epc, A.fs,
-                             A.nomask, A.icm, A.iut, A.u);
-  }
+  if (k < A.n_sh)
+    merge_node<T, OP>(A.fx_node, A.fx_ptr, A.partial, k, A.v, A.vz,
+                      A.vz ? T(A.cg_scal[cgslot::BETA]) : T(0), A.out, A.fext, lscale, nrm,
+                      A.ep_red != nullptr, A.ep_w, A.ep_coef ? T(A.ep_coef[0]) : T(0), A.fs,
+                      A.nomask, A.icm, A.iut, A.u);
   if (OP == OP_RES || (OP == OP_JV && A.ep_red)) {
     const double s = block_sum<NT>(nrm, rs);
     if (threadIdx.x == 0) (OP == OP_RES ? A.red : A.ep_red)[wg] = s;
@@ -1379,11 +1309,7 @@ int launch(Ctx *c, int op, const T *xr, const T *u, const T *v, T *out, double *
   if (*err != hipSuccess) return 0;
   if (op == OP_ENERGY) return M.nblk;
   int nred = (op == OP_RES || (op == OP_JV && c->ep.red)) ? M.nblk : 0;
-  // two shared nodes per merge thread for the Jacobian action of a single
-  // problem with more shared nodes than 8 workgroups of NT per CU hold
-  const bool two = op == OP_JV && !c->mwg_list && !M.mwg_inst && M.n_shared > int64_t(8) * NT * 256;
-  const int g2 = c->mwg_list ? c->n_mlist
-                             : int((M.n_shared + (two ? 2 : 1) * NT - 1) / ((two ? 2 : 1) * NT));
+  const int g2 = c->mwg_list ? c->n_mlist : int((M.n_shared + NT - 1) / NT);
   if (M.n_shared > 0 && g2 > 0) {
     MergeArgs<T> B;
     B.fx_node = M.fx_node;
@@ -1412,22 +1338,19 @@ int launch(Ctx *c, int op, const T *xr, const T *u, const T *v, T *out, double *
     B.iut = A.iut;
     switch (op) {
       case OP_RES:
-        hipLaunchKernelGGL((k_elem_merge<T, OP_RES, 1>), dim3(g2), dim3(NT), 0, c->stream, B);
+        hipLaunchKernelGGL((k_elem_merge<T, OP_RES>), dim3(g2), dim3(NT), 0, c->stream, B);
         nred += g2;
         break;
       case OP_JV:
-        if (two)
-          hipLaunchKernelGGL((k_elem_merge<T, OP_JV, 2>), dim3(g2), dim3(NT), 0, c->stream, B);
-        else
-          hipLaunchKernelGGL((k_elem_merge<T, OP_JV, 1>), dim3(g2), dim3(NT), 0, c->stream, B);
+        hipLaunchKernelGGL((k_elem_merge<T, OP_JV>), dim3(g2), dim3(NT), 0, c->stream, B);
         if (c->ep.red) nred += g2;
         break;
       case OP_ODIAG:
         if constexpr (sizeof(T) == 8)
-          hipLaunchKernelGGL((k_elem_merge<T, OP_ODIAG, 1>), dim3(g2), dim3(NT), 0, c->stream, B);
+          hipLaunchKernelGGL((k_elem_merge<T, OP_ODIAG>), dim3(g2), dim3(NT), 0, c->stream, B);
         break;
       default:
-        hipLaunchKernelGGL((k_elem_merge<T, OP_DIAG, 1>), dim3(g2), dim3(NT), 0, c->stream, B);
+        hipLaunchKernelGGL((k_elem_merge<T, OP_DIAG>), dim3(g2), dim3(NT), 0, c->stream, B);
         break;
     }
     *err = hipGetLastError();
