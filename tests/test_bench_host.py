@@ -33,3 +33,14 @@ def test_method_tables_build_options(table):
         if o.pc == nl.NLE_PC_AMG and table == "TWIST_METHODS":  # field split: GMRES only
             assert o.ksp_type == nl.NLE_KSP_GMRES, name
     assert "ink_mixed_cg_amg" in bench.METHODS
+
+
+def test_timed_mesh_block_size_gives_one_block_per_compute_unit():
+    # the timed Cook mesh is cut into element blocks of bench.HEAD_BLOCK: 256
+    # equal blocks, one per compute unit of the MI355X
+    import synthetic as syn
+
+    m = syn.cook_mesh(*bench.GRID, with_faces=False)
+    n_e = len(m.conn)
+    assert n_e % bench.HEAD_BLOCK == 0
+    assert n_e // bench.HEAD_BLOCK == 256
